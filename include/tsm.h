@@ -1,0 +1,166 @@
+/*
+ * tsm.h -- C ABI of the two-scale micro-batch library (libtsm.so, gfx950).
+ *
+ * Method (arXiv 2103.17040):
+ *   - one micro problem per macro degree of freedom, posed on a shared
+ *     reference cell Z = [-1,1]^2 and fed the nodal macro value u_i
+ *     (Section 3.3, micro system at the support point of the macro basis
+ *     function);
+ *   - micro integrals pulled back to Z with K = (D zeta)^{-1} and
+ *     J = det D zeta (Section 3.1, equations grad_map and det_map): the
+ *     stiffness weight is K K^T J per quadrature point and the boundary
+ *     weight is |cof(F) nu| (change of variables, Section 3.1);
+ *   - Q1 elements on the macro mesh B_H and on the reference mesh K_h
+ *     (Section 3.1, spaces U_H and V_h), 2x2 Gauss per cell, 2-point Gauss
+ *     per boundary edge;
+ *   - macro/micro coupling through the Robin exchange kappa (p u - v) on the
+ *     micro boundary and its mean as the macro source (Section 2.1, model
+ *     system; the macro source carries the sign source_sign, -1 being the
+ *     paper's sink);
+ *   - every system solved by preconditioned conjugate gradients (Section 3.3).
+ *
+ * Time-dependent system stepped by implicit Euler with step dt:
+ *   u_t - D Lap u = source_sign * mean_{dY_x} kappa (p u - v)  in [0,1]^2, u = 0 on the boundary
+ *   v_t - d Lap_y v = 0 in Y_x,   d grad v . n = kappa (p u - v) on dY_x
+ * Deformation family: zeta_x(y) = R_theta (y + a (sin(pi y1) y2, sin(pi y2) y1) / 4).
+ * Each step is solved exactly: v_i = v0_i + u_i w_i with the time-invariant
+ * response w_i = kappa p S_i^{-1} b_i, one micro solve per instance, one
+ * macro solve.
+ *
+ * Conventions
+ *   - Instance i is macro node i, lexicographic with x1 fastest:
+ *     i = k2 (N_M+1) + k1, n_inst = (N_M+1)^2.
+ *   - Micro vectors are ragged: instance i owns entries
+ *     [offsets[i], offsets[i+1]) with offsets[i+1]-offsets[i] = (N_i+1)^2 and
+ *     node j = j2 (N_i+1) + j1 at reference point (-1 + 2 j1/N_i, -1 + 2 j2/N_i).
+ *   - "device pointer" arguments are HIP device memory owned by the caller;
+ *     inputs are copied, outputs are written with stream-ordered copies on
+ *     the context's stream.  "host pointer" arguments are ordinary memory.
+ *   - All calls return a tsm_status; on failure tsm_last_error() gives a
+ *     message.  Calls on one context are not thread-safe.
+ */
+#ifndef TSM_H
+#define TSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TSM_OK = 0,
+    TSM_EINVAL = -1,   /* invalid argument or parameter */
+    TSM_EGEOM = -2,    /* det D zeta <= 0 at some quadrature point */
+    TSM_ENOCONV = -3,  /* some solve missed its tolerance (state still advanced) */
+    TSM_EHIP = -4,     /* HIP runtime error */
+    TSM_ENOMEM = -5,   /* device allocation failed or size limit exceeded */
+    TSM_ESTATE = -6    /* call order violated (e.g. step before set_deformation) */
+} tsm_status;
+
+enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
+
+/* flags */
+#define TSM_FLAG_NO_GRAPH   (1ull << 0)  /* launch kernels directly instead of a captured hipGraph */
+#define TSM_FLAG_STENCIL_STREAM (1ull << 1) /* force the streamed-stencil micro kernels */
+
+typedef struct {
+    int32_t macro_cells;     /* N_M >= 2: macro Q1 cells per side on [0,1]^2 */
+    double D;                /* macro diffusion, > 0 */
+    double d;                /* micro diffusion, > 0 */
+    double kappa;            /* Robin transfer rate, >= 0 */
+    double p;                /* partition coefficient, > 0 */
+    double dt;               /* time step, > 0 */
+    int32_t source_sign;     /* -1 (paper's sink) or +1 */
+    int32_t precision;       /* TSM_FP64 or TSM_FP32_REFINE */
+    double rtol;             /* micro step solves: ||b - S x||_2 <= rtol ||b||_2 */
+    double inner_rtol;       /* FP32 inner solves (refinement mode) */
+    double setup_rtol;       /* response solves w_i at setup */
+    int32_t max_iter;        /* PCG iterations per solve (per inner solve) */
+    int32_t max_refine;      /* FP64 refinement sweeps (refinement mode) */
+    int32_t checkpoint_every;/* adjoint checkpoint spacing in steps, >= 1 */
+    uint64_t flags;          /* TSM_FLAG_* */
+} tsm_params;
+
+typedef struct {
+    int64_t n_inst;
+    int64_t n_micro_dofs;        /* sum_i (N_i+1)^2 */
+    int64_t steps_taken;         /* since set_state */
+    int32_t iters_min, iters_max;/* PCG iterations of the last step (inner total in refine mode) */
+    double iters_mean;
+    int32_t sweeps_max;          /* refinement sweeps of the last step */
+    int32_t unconverged;         /* instances that missed rtol in the last step */
+    int32_t macro_sweeps;        /* tensor-preconditioned macro sweeps per solve */
+    double macro_contraction;    /* bound on the macro sweep contraction factor */
+    double setup_ms;             /* last set_deformation */
+    double step_ms;              /* last tsm_step call, wall on the stream */
+} tsm_stats;
+
+typedef struct tsm_ctx tsm_ctx;
+
+/* Fill *p with the defaults: kappa = p = 1, D = 1, d = 0.5, dt = 0.01,
+ * source_sign = -1, FP64, rtol 1e-12, inner_rtol 1e-5, setup_rtol 1e-14,
+ * max_iter 1000, max_refine 12, checkpoint_every 10, flags 0. */
+void tsm_default_params(tsm_params* p);
+
+/* Create a context on the current HIP device.  stream is a hipStream_t
+ * (NULL: the null stream).  The context owns every device buffer it
+ * allocates.  EINVAL on bad parameters. */
+tsm_status tsm_create(const tsm_params* p, void* stream, tsm_ctx** out);
+
+/* Reference mesh of every instance: micro_cells[i] = N_i in 2..64 cells per
+ * side of K_h (host pointer, n_inst entries, n_inst == (N_M+1)^2).
+ * Allocates the ragged buffers.  Invalidates any deformation and state. */
+tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_t n_inst);
+
+/* Ragged layout: offsets_out[0..n_inst] (host pointer, n_inst+1 entries). */
+tsm_status tsm_get_offsets(const tsm_ctx* c, int64_t* offsets_out);
+
+/* Deformation amplitudes a_i and rotation angles theta_i (device pointers,
+ * n_inst doubles each; theta may be NULL = 0).  Checks that every value is
+ * finite (EINVAL) and det D zeta > 0 at every quadrature point (EGEOM), then
+ * runs setup: assembles each S_i = M_i/dt + d A_i + kappa B_i, solves the
+ * responses w_i and builds the macro solver.  The rotation leaves K K^T J and
+ * |cof(F) nu| unchanged, so it does not enter the arithmetic. */
+tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta, int64_t n_inst);
+
+/* State (device pointers): u has n_inst entries (macro-boundary entries
+ * are forced to 0), v is ragged or NULL (= 0).  Resets steps_taken. */
+tsm_status tsm_set_state(tsm_ctx* c, const double* u, const double* v);
+
+/* Advance n_steps >= 0 implicit-Euler steps on the context's stream, then
+ * synchronise it.  ENOCONV if any solve missed its tolerance (the state is
+ * still advanced with the last iterate; see tsm_get_stats). */
+tsm_status tsm_step(tsm_ctx* c, int32_t n_steps);
+
+/* Outputs (device pointers, written on the context's stream, then synchronised):
+ * macro field u (n_inst), mean Robin fluxes F_i of the last step (n_inst),
+ * micro field v (ragged). */
+tsm_status tsm_get_macro(const tsm_ctx* c, double* u_out);
+tsm_status tsm_get_fluxes(const tsm_ctx* c, double* F_out);
+tsm_status tsm_get_micro(const tsm_ctx* c, double* v_out);
+
+/* Setup quantities (device pointers, n_inst each or NULL to skip): response
+ * functional beta_i = kappa p - (kappa/|dY_i|) b_i^T w_i, boundary length
+ * |dY_i| = 1^T b_i; and the ragged response w (NULL to skip). */
+tsm_status tsm_get_setup(const tsm_ctx* c, double* beta_out, double* len_out, double* w_out);
+
+/* y = S x for every instance with the assembled FP64 operator
+ * (device pointers, ragged). */
+tsm_status tsm_apply_operator(tsm_ctx* c, const double* x, double* y);
+
+/* Gradient of J = u(T)^T M_H u(T) (the integral of u_h(T)^2) after n_steps
+ * steps from the current state with respect to the amplitudes a_i:
+ * forward with checkpoints every checkpoint_every steps, then the discrete
+ * adjoint backwards.  J_out is a host pointer, dJda_out a device pointer
+ * (n_inst).  The current state is left unchanged. */
+tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda_out);
+
+tsm_status tsm_get_stats(const tsm_ctx* c, tsm_stats* s);
+const char* tsm_last_error(const tsm_ctx* c);
+void tsm_destroy(tsm_ctx* c);   /* NULL-safe */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSM_H */

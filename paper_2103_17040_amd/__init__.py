@@ -1,0 +1,114 @@
+"""Two-scale micro-batch FEM (arXiv 2103.17040) on MI355X.
+
+``tsm``            ctypes binding of libtsm.so (same names as include/tsm.h)
+``TwoScaleBatch``  owner of one library context plus torch-allocated device
+                   buffers for its inputs and outputs
+"""
+from __future__ import annotations
+
+__all__ = ["TwoScaleBatch"]
+
+
+class TwoScaleBatch:
+    """One batch of micro problems (one per macro node) and the macro field.
+
+    All arithmetic happens in libtsm; this class only moves arguments.
+    Inputs may be numpy arrays or torch tensors; outputs are torch CUDA
+    tensors (float64)."""
+
+    def __init__(self, macro_cells, micro_cells, a, theta=None, *, D=1.0, d=0.5, kappa=1.0, p=1.0,
+                 dt=0.01, sigma=-1, precision="fp64", rtol=1e-12, inner_rtol=1e-5, setup_rtol=1e-14,
+                 max_iter=1000, max_refine=12, checkpoint_every=10, flags=0, device="cuda:0"):
+        import numpy as np
+        import torch
+        global tsm
+        from . import tsm
+        self.torch = torch
+        self.device = torch.device(device)
+        prm = tsm.tsm_default_params()
+        prm.macro_cells = int(macro_cells)
+        prm.D, prm.d, prm.kappa, prm.p, prm.dt = float(D), float(d), float(kappa), float(p), float(dt)
+        prm.source_sign = int(sigma)
+        prm.precision = {"fp64": tsm.TSM_FP64, "fp32_refine": tsm.TSM_FP32_REFINE}[precision]
+        prm.rtol, prm.inner_rtol, prm.setup_rtol = float(rtol), float(inner_rtol), float(setup_rtol)
+        prm.max_iter, prm.max_refine, prm.checkpoint_every = int(max_iter), int(max_refine), int(checkpoint_every)
+        prm.flags = int(flags)
+        self.params = prm
+        self.n_inst = (int(macro_cells) + 1) ** 2
+        with torch.cuda.device(self.device):
+            self.ctx = tsm.tsm_create(prm, None)
+        try:
+            tsm.tsm_set_reference_mesh(self.ctx, np.asarray(micro_cells, dtype=np.int32))
+            self.offsets = tsm.tsm_get_offsets(self.ctx, self.n_inst)
+            self.n_micro = int(self.offsets[-1])
+            self.set_deformation(a, theta)
+        except Exception:
+            self.close()
+            raise
+
+    def _dev(self, x):
+        if x is None:
+            return None
+        t = self.torch.as_tensor(x, dtype=self.torch.float64, device=self.device).contiguous()
+        return t
+
+    def _empty(self, n):
+        return self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+
+    def set_deformation(self, a, theta=None):
+        self._a = self._dev(a)
+        self._theta = self._dev(theta)
+        tsm.tsm_set_deformation(self.ctx, self._a, self._theta, self.n_inst)
+
+    def set_state(self, u, v=None):
+        tu, tv = self._dev(u), self._dev(v)
+        tsm.tsm_set_state(self.ctx, tu, tv)
+
+    def step(self, n_steps=1, allow_noconv=False):
+        return tsm.tsm_step(self.ctx, n_steps, allow_noconv)
+
+    def macro(self):
+        out = self._empty(self.n_inst)
+        tsm.tsm_get_macro(self.ctx, out)
+        return out
+
+    def fluxes(self):
+        out = self._empty(self.n_inst)
+        tsm.tsm_get_fluxes(self.ctx, out)
+        return out
+
+    def micro(self):
+        out = self._empty(self.n_micro)
+        tsm.tsm_get_micro(self.ctx, out)
+        return out
+
+    def setup(self):
+        beta, ln, w = self._empty(self.n_inst), self._empty(self.n_inst), self._empty(self.n_micro)
+        tsm.tsm_get_setup(self.ctx, beta, ln, w)
+        return beta, ln, w
+
+    def apply(self, x):
+        tx = self._dev(x)
+        y = self._empty(self.n_micro)
+        tsm.tsm_apply_operator(self.ctx, tx, y)
+        return y
+
+    def gradient(self, n_steps):
+        g = self._empty(self.n_inst)
+        J = tsm.tsm_gradient(self.ctx, n_steps, g)
+        return J, g
+
+    def stats(self):
+        return tsm.tsm_get_stats(self.ctx)
+
+    def close(self):
+        from . import tsm
+        if getattr(self, "ctx", None):
+            tsm.tsm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,632 @@
+// Host runtime of libtsm: validation, device buffers, setup, the per-step
+// launch sequence (captured once in a hipGraph and replayed), outputs.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tsm_internal.h"
+
+using namespace tsm;
+
+namespace {
+
+// Micro kernel classes: SLOTS nodes per lane with 256 lanes per workgroup.
+const int kSlotClasses[] = {1, 2, 3, 5, 9, 17};
+
+int slots_for(int n) {
+    for (int s : kSlotClasses)
+        if (s * kMicroThreads >= n) return s;
+    return -1;
+}
+
+struct Group {
+    int first;      // first task in the order array
+    int count;
+    int slots;
+    int mode;       // 0 FP64 resident, 1 FP64 streamed, 2 refine resident, 3 refine streamed
+    int max_level;
+};
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return hipSuccess;
+    return hipMalloc((void**)p, count * sizeof(T));
+}
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace
+
+struct tsm_ctx {
+    tsm_params prm{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    int NM = 0, n_macro_int = 0;
+    int64_t n_inst = 0, total = 0;
+    std::vector<int32_t> level_h;
+    std::vector<int64_t> off_h;
+    std::vector<int32_t> order_h;
+    std::vector<Group> groups;
+
+    // per instance
+    int32_t *level = nullptr, *order = nullptr, *iters = nullptr, *sweeps = nullptr, *counters = nullptr;
+    int64_t* offsets = nullptr;
+    double *amp = nullptr, *beta = nullptr, *len = nullptr, *jmin = nullptr, *bx = nullptr,
+           *alpha = nullptr, *F = nullptr, *u = nullptr;
+    // ragged
+    double *S64 = nullptr, *M64 = nullptr, *b = nullptr, *w = nullptr, *v0 = nullptr;
+    float* S32 = nullptr;
+    // tables
+    int32_t* tab_off = nullptr;
+    double *tab_y = nullptr, *tab_s = nullptr, *tab_c = nullptr;
+    // macro solver
+    double *rhs = nullptr, *R = nullptr, *T1 = nullptr, *T2 = nullptr, *Q = nullptr, *lam = nullptr;
+    int macro_sweeps = 2;
+    double rho = 0.0;
+
+    bool have_mesh = false, have_geom = false, have_state = false;
+    hipGraphExec_t graph = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int64_t steps_taken = 0;
+    double setup_ms = 0.0, step_ms = 0.0;
+
+    tsm_status fail(tsm_status s, const std::string& m) {
+        err = m;
+        return s;
+    }
+    void free_mesh() {
+        dfree(level); dfree(order); dfree(iters); dfree(sweeps); dfree(offsets);
+        dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
+        dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32);
+        dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
+        drop_graph();
+        have_mesh = have_geom = have_state = false;
+    }
+    void free_macro() { dfree(rhs); dfree(R); dfree(T1); dfree(T2); dfree(Q); dfree(lam); }
+    void drop_graph() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+    }
+    MacroArgs macro_args() const {
+        MacroArgs m;
+        const double H = 1.0 / NM;
+        m.NM = NM;
+        m.n = NM - 1;
+        m.mass_c = H * H / (36.0 * prm.dt);
+        m.lap_c = prm.D / 3.0;
+        m.sig_h2 = prm.source_sign * H * H;
+        m.kappa = prm.kappa;
+        m.p = prm.p;
+        m.beta = beta;
+        m.len = len;
+        return m;
+    }
+};
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return c->fail(TSM_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define HIPALLOC(p, n)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = dalloc(&(p), (n));                                                 \
+        if (e_ != hipSuccess) {                                                            \
+            (void)hipGetLastError();                                                       \
+            return c->fail(TSM_ENOMEM, std::string("allocation of ") + #p + " failed: " + hipGetErrorString(e_)); \
+        }                                                                                  \
+    } while (0)
+
+namespace {
+
+// One batched micro solve over every group.
+tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
+    for (const Group& g : c->groups) {
+        MicroArgs a = base;
+        a.n_tasks = g.count;
+        a.order = c->order + g.first;
+        int mode = g.mode;
+        if (setup) mode = (g.slots <= 5 && !(c->prm.flags & TSM_FLAG_STENCIL_STREAM)) ? 0 : 1;
+        const int NP = g.max_level + 1;
+        const size_t n_pad = (size_t)NP * NP + 2 * (size_t)(NP + 1);
+        const size_t lds = n_pad * (sizeof(double) + sizeof(float));
+        HIPCHK(launch_micro(a, g.slots, mode, g.count, lds, c->stream));
+    }
+    return TSM_OK;
+}
+
+MicroArgs micro_base(tsm_ctx* c) {
+    MicroArgs a{};
+    a.level = c->level;
+    a.offsets = c->offsets;
+    a.S64 = c->S64;
+    a.S32 = c->S32;
+    a.M64 = c->M64;
+    a.b = c->b;
+    a.w = c->w;
+    a.bx_out = c->bx;
+    a.iters_out = c->iters;
+    a.sweeps_out = c->sweeps;
+    a.nonconv = c->counters;
+    a.inv_dt = 1.0 / c->prm.dt;
+    a.rtol = c->prm.rtol;
+    a.inner_rtol = c->prm.inner_rtol;
+    a.max_iter = c->prm.max_iter;
+    a.max_refine = c->prm.max_refine;
+    a.queue = nullptr;
+    return a;
+}
+
+// Macro solve of A_M u = rhs in place (u holds the initial guess).
+tsm_status enqueue_macro_solve(tsm_ctx* c, double* u) {
+    const MacroArgs m = c->macro_args();
+    const int n = m.n;
+    for (int s = 0; s < c->macro_sweeps; ++s) {
+        HIPCHK(launch_macro_residual(m, u, c->rhs, c->R, c->stream));
+        HIPCHK(launch_gemm(n, c->Q, c->R, c->T1, 0, nullptr, nullptr, c->NM, c->stream));
+        HIPCHK(launch_gemm(n, c->T1, c->Q, c->T2, 1, c->lam, nullptr, c->NM, c->stream));
+        HIPCHK(launch_gemm(n, c->Q, c->T2, c->T1, 0, nullptr, nullptr, c->NM, c->stream));
+        HIPCHK(launch_gemm(n, c->T1, c->Q, nullptr, 2, nullptr, u, c->NM, c->stream));
+    }
+    return TSM_OK;
+}
+
+// One forward step: micro solves (state v = v0 + u w in place), macro solve, fluxes.
+tsm_status enqueue_step(tsm_ctx* c) {
+    MicroArgs a = micro_base(c);
+    a.X0 = c->v0;
+    a.coef = c->u;
+    a.rhs_vec = nullptr;
+    a.zero_init = 0;
+    a.X_out = c->v0;
+    tsm_status st = enqueue_micro(c, a, false);
+    if (st != TSM_OK) return st;
+    const MacroArgs m = c->macro_args();
+    HIPCHK(launch_macro_rhs_forward(m, c->u, c->bx, c->rhs, c->alpha, c->stream));
+    st = enqueue_macro_solve(c, c->u);
+    if (st != TSM_OK) return st;
+    HIPCHK(launch_macro_finalize(m, c->u, c->alpha, c->F, c->stream));
+    return TSM_OK;
+}
+
+tsm_status build_graph(tsm_ctx* c) {
+    c->drop_graph();
+    if (c->prm.flags & TSM_FLAG_NO_GRAPH) return TSM_OK;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    tsm_status st = enqueue_step(c);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (st != TSM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    HIPCHK(e);
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    return TSM_OK;
+}
+
+bool finite_all(const std::vector<double>& v) {
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tsm_default_params(tsm_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->macro_cells = 8;
+    p->D = 1.0;
+    p->d = 0.5;
+    p->kappa = 1.0;
+    p->p = 1.0;
+    p->dt = 0.01;
+    p->source_sign = -1;
+    p->precision = TSM_FP64;
+    p->rtol = 1e-12;
+    p->inner_rtol = 1e-5;
+    p->setup_rtol = 1e-14;
+    p->max_iter = 1000;
+    p->max_refine = 12;
+    p->checkpoint_every = 10;
+    p->flags = 0;
+}
+
+tsm_status tsm_create(const tsm_params* p, void* stream, tsm_ctx** out) {
+    if (!out) return TSM_EINVAL;
+    *out = nullptr;
+    if (!p) return TSM_EINVAL;
+    const bool ok = p->macro_cells >= 2 && p->macro_cells <= 1024 && p->D > 0 && p->d > 0 && p->kappa >= 0 &&
+                    p->p > 0 && p->dt > 0 && (p->source_sign == 1 || p->source_sign == -1) &&
+                    (p->precision == TSM_FP64 || p->precision == TSM_FP32_REFINE) && p->rtol > 0 &&
+                    p->inner_rtol > 0 && p->inner_rtol < 1 && p->setup_rtol > 0 && p->max_iter >= 1 &&
+                    p->max_refine >= 1 && p->checkpoint_every >= 1 && std::isfinite(p->D) &&
+                    std::isfinite(p->d) && std::isfinite(p->kappa) && std::isfinite(p->p) && std::isfinite(p->dt);
+    if (!ok) return TSM_EINVAL;
+    tsm_ctx* c = new tsm_ctx();
+    c->prm = *p;
+    c->NM = p->macro_cells;
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return TSM_EHIP;
+        }
+        c->own_stream = true;
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        dalloc(&c->counters, 4) != hipSuccess) {
+        tsm_destroy(c);
+        return TSM_EHIP;
+    }
+    *out = c;
+    return TSM_OK;
+}
+
+tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_t n_inst) {
+    if (!c) return TSM_EINVAL;
+    if (!micro_cells) return c->fail(TSM_EINVAL, "micro_cells is NULL");
+    const int64_t expect = (int64_t)(c->NM + 1) * (c->NM + 1);
+    if (n_inst != expect)
+        return c->fail(TSM_EINVAL, "n_inst must equal (macro_cells+1)^2 = " + std::to_string(expect));
+    for (int64_t i = 0; i < n_inst; ++i)
+        if (micro_cells[i] < kMinLevel || micro_cells[i] > kMaxLevel)
+            return c->fail(TSM_EINVAL, "micro_cells[" + std::to_string(i) + "] = " + std::to_string(micro_cells[i]) +
+                                           " outside 2..64");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->free_mesh();
+    c->free_macro();
+    c->n_inst = n_inst;
+    c->level_h.assign(micro_cells, micro_cells + n_inst);
+    c->off_h.assign(n_inst + 1, 0);
+    for (int64_t i = 0; i < n_inst; ++i) c->off_h[i + 1] = c->off_h[i] + (int64_t)(micro_cells[i] + 1) * (micro_cells[i] + 1);
+    c->total = c->off_h[n_inst];
+
+    // task order: descending mesh size (largest first), stable in instance index
+    c->order_h.resize(n_inst);
+    for (int64_t i = 0; i < n_inst; ++i) c->order_h[i] = (int32_t)i;
+    std::stable_sort(c->order_h.begin(), c->order_h.end(),
+                     [&](int32_t x, int32_t y) { return c->level_h[x] > c->level_h[y]; });
+    c->groups.clear();
+    const bool refine = c->prm.precision == TSM_FP32_REFINE;
+    const bool stream_all = (c->prm.flags & TSM_FLAG_STENCIL_STREAM) != 0;
+    for (int64_t t = 0; t < n_inst; ++t) {
+        const int lvl = c->level_h[c->order_h[t]];
+        const int sl = slots_for((lvl + 1) * (lvl + 1));
+        if (c->groups.empty() || c->groups.back().slots != sl) {
+            Group g;
+            g.first = (int)t;
+            g.count = 0;
+            g.slots = sl;
+            const bool resident = !stream_all && (refine ? sl <= 9 : sl <= 5);
+            g.mode = (refine ? 2 : 0) + (resident ? 0 : 1);
+            g.max_level = lvl;
+            c->groups.push_back(g);
+        }
+        c->groups.back().count++;
+    }
+
+    // level tables
+    std::vector<int32_t> toff(kMaxLevel + 1, 0);
+    std::vector<double> ty, ts, tc;
+    std::vector<bool> present(kMaxLevel + 1, false);
+    for (int32_t l : c->level_h) present[l] = true;
+    const double g0 = 0.5 - 0.5 / std::sqrt(3.0), g1 = 0.5 + 0.5 / std::sqrt(3.0);
+    for (int N = kMinLevel; N <= kMaxLevel; ++N) {
+        if (!present[N]) continue;
+        toff[N] = (int32_t)ty.size();
+        const double h = 2.0 / N;
+        for (int t = 0; t < 2 * N + 2; ++t) {
+            double y;
+            if (t < 2 * N) y = -1.0 + ((t / 2) + ((t % 2) ? g1 : g0)) * h;
+            else y = (t == 2 * N) ? -1.0 : 1.0;
+            ty.push_back(y);
+            ts.push_back(0.25 * std::sin(M_PI * y));
+            tc.push_back(0.25 * M_PI * std::cos(M_PI * y));
+        }
+    }
+
+    const int64_t ni = n_inst, tot = c->total;
+    HIPALLOC(c->level, ni); HIPALLOC(c->order, ni); HIPALLOC(c->iters, ni); HIPALLOC(c->sweeps, ni);
+    HIPALLOC(c->offsets, ni + 1);
+    HIPALLOC(c->amp, ni); HIPALLOC(c->beta, ni); HIPALLOC(c->len, ni); HIPALLOC(c->jmin, ni);
+    HIPALLOC(c->bx, ni); HIPALLOC(c->alpha, ni); HIPALLOC(c->F, ni); HIPALLOC(c->u, ni);
+    HIPALLOC(c->S64, kStencil * tot); HIPALLOC(c->M64, kStencil * tot); HIPALLOC(c->S32, kStencil * tot);
+    HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot);
+    HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
+    HIPALLOC(c->tab_c, tc.size());
+    HIPCHK(hipMemcpy(c->level, c->level_h.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->order, c->order_h.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->offsets, c->off_h.data(), (ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->tab_off, toff.data(), toff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->tab_y, ty.data(), ty.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->tab_s, ts.data(), ts.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->tab_c, tc.data(), tc.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(c->u, 0, ni * sizeof(double)));
+    HIPCHK(hipMemset(c->F, 0, ni * sizeof(double)));
+    HIPCHK(hipMemset(c->v0, 0, tot * sizeof(double)));
+
+    const int n = c->NM - 1;
+    HIPALLOC(c->rhs, (size_t)n * n); HIPALLOC(c->R, (size_t)n * n); HIPALLOC(c->T1, (size_t)n * n);
+    HIPALLOC(c->T2, (size_t)n * n); HIPALLOC(c->Q, (size_t)n * n); HIPALLOC(c->lam, (size_t)n * n);
+    c->have_mesh = true;
+    return TSM_OK;
+}
+
+tsm_status tsm_get_offsets(const tsm_ctx* c, int64_t* out) {
+    if (!c || !out) return TSM_EINVAL;
+    if (!c->have_mesh) return TSM_ESTATE;
+    std::memcpy(out, c->off_h.data(), (c->n_inst + 1) * sizeof(int64_t));
+    return TSM_OK;
+}
+
+tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta, int64_t n_inst) {
+    if (!c) return TSM_EINVAL;
+    if (!c->have_mesh) return c->fail(TSM_ESTATE, "set_reference_mesh first");
+    if (!a) return c->fail(TSM_EINVAL, "a is NULL");
+    if (n_inst != c->n_inst) return c->fail(TSM_EINVAL, "n_inst does not match the reference mesh");
+    const auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(hipDeviceSynchronize());   // caller's producers of a, theta
+    std::vector<double> ah(n_inst), th(n_inst, 0.0);
+    HIPCHK(hipMemcpy(ah.data(), a, n_inst * sizeof(double), hipMemcpyDeviceToHost));
+    if (theta) HIPCHK(hipMemcpy(th.data(), theta, n_inst * sizeof(double), hipMemcpyDeviceToHost));
+    if (!finite_all(ah) || !finite_all(th)) return c->fail(TSM_EINVAL, "non-finite deformation parameter");
+    c->have_geom = false;
+    c->have_state = false;
+    c->drop_graph();
+    HIPCHK(hipMemcpyAsync(c->amp, a, n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+
+    AssembleArgs as;
+    as.n_inst = (int)n_inst;
+    as.level = c->level;
+    as.offsets = c->offsets;
+    as.amp = c->amp;
+    as.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
+    as.d = c->prm.d;
+    as.kappa = c->prm.kappa;
+    as.inv_dt = 1.0 / c->prm.dt;
+    as.S64 = c->S64; as.S32 = c->S32; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
+    HIPCHK(launch_assemble(as, c->stream));
+    std::vector<double> jm(n_inst);
+    HIPCHK(hipMemcpyAsync(jm.data(), c->jmin, n_inst * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n_inst; ++i)
+        if (!(jm[i] > 0.0)) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "det D zeta = %.3e <= 0 at a quadrature point of instance %lld (a = %.6g)",
+                          jm[i], (long long)i, ah[i]);
+            return c->fail(TSM_EGEOM, buf);
+        }
+
+    // responses w_i = kappa p S_i^{-1} b_i (FP64, zero initial guess)
+    HIPCHK(hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->stream));
+    MicroArgs ma = micro_base(c);
+    ma.X0 = nullptr;
+    ma.coef = nullptr;
+    ma.rhs_vec = c->b;
+    ma.rhs_scale = c->prm.kappa * c->prm.p;
+    ma.zero_init = 1;
+    ma.X_out = c->w;
+    ma.rtol = c->prm.setup_rtol;
+    ma.max_iter = std::max(c->prm.max_iter, 50000);   // setup must converge whatever the step budget
+    tsm_status st = enqueue_micro(c, ma, true);
+    if (st != TSM_OK) return st;
+    HIPCHK(launch_beta((int)n_inst, c->prm.kappa, c->prm.p, c->len, c->bx, c->beta, c->stream));
+    std::vector<double> bh(n_inst);
+    int32_t nc = 0;
+    HIPCHK(hipMemcpyAsync(bh.data(), c->beta, n_inst * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&nc, c->counters, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (nc > 0) return c->fail(TSM_ENOCONV, std::to_string(nc) + " response solves missed setup_rtol");
+
+    // macro solver: reference beta, eigenvalues, sine basis, sweep count
+    const int NM = c->NM, n = NM - 1;
+    const double H = 1.0 / NM;
+    double bmin = 1e300, bmax = -1e300;
+    for (int k2 = 1; k2 < NM; ++k2)
+        for (int k1 = 1; k1 < NM; ++k1) {
+            const double v = bh[(size_t)k2 * (NM + 1) + k1];
+            bmin = std::min(bmin, v);
+            bmax = std::max(bmax, v);
+        }
+    const double bref = 0.5 * (bmin + bmax);
+    std::vector<double> mk(n), kk(n), Qh((size_t)n * n), lh((size_t)n * n);
+    for (int k = 0; k < n; ++k) {
+        const double th_k = M_PI * (k + 1) * H;
+        mk[k] = H / 6.0 * (4.0 + 2.0 * std::cos(th_k));
+        kk[k] = (2.0 - 2.0 * std::cos(th_k)) / H;
+    }
+    double lmin = 1e300;
+    const double sg = c->prm.source_sign;
+    for (int l2 = 0; l2 < n; ++l2)
+        for (int l1 = 0; l1 < n; ++l1) {
+            const double v = mk[l1] * mk[l2] / c->prm.dt + c->prm.D * (kk[l1] * mk[l2] + mk[l1] * kk[l2]) -
+                             sg * bref * H * H;
+            lh[(size_t)l2 * n + l1] = v;
+            lmin = std::min(lmin, std::fabs(v));
+        }
+    const double qs = std::sqrt(2.0 / (n + 1));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Qh[(size_t)i * n + j] = qs * std::sin(M_PI * (double)(i + 1) * (j + 1) / (n + 1));
+    c->rho = H * H * 0.5 * (bmax - bmin) / lmin;
+    if (!(c->rho < 0.5))
+        return c->fail(TSM_EINVAL, "macro sweep contraction bound " + std::to_string(c->rho) +
+                                       " >= 0.5: response functionals too heterogeneous for the tensor solver");
+    int sweeps = 2;
+    if (c->rho > 0) sweeps = std::max(2, (int)std::ceil(std::log(1e-17) / std::log(c->rho)));
+    c->macro_sweeps = std::min(sweeps, 64);
+    HIPCHK(hipMemcpy(c->Q, Qh.data(), Qh.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->lam, lh.data(), lh.size() * sizeof(double), hipMemcpyHostToDevice));
+
+    c->have_geom = true;
+    tsm_status gs = build_graph(c);
+    if (gs != TSM_OK) return gs;
+    c->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return TSM_OK;
+}
+
+tsm_status tsm_set_state(tsm_ctx* c, const double* u, const double* v) {
+    if (!c) return TSM_EINVAL;
+    if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation first");
+    if (!u) return c->fail(TSM_EINVAL, "u is NULL");
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<double> uh(c->n_inst);
+    HIPCHK(hipMemcpy(uh.data(), u, c->n_inst * sizeof(double), hipMemcpyDeviceToHost));
+    if (!finite_all(uh)) return c->fail(TSM_EINVAL, "non-finite macro state");
+    const int W = c->NM + 1;
+    for (int k2 = 0; k2 < W; ++k2)
+        for (int k1 = 0; k1 < W; ++k1)
+            if (k1 == 0 || k2 == 0 || k1 == c->NM || k2 == c->NM) uh[(size_t)k2 * W + k1] = 0.0;
+    HIPCHK(hipMemcpy(c->u, uh.data(), c->n_inst * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(launch_state_split((int)c->n_inst, c->offsets, c->u, v, c->w, c->v0, c->stream));
+    HIPCHK(hipMemsetAsync(c->F, 0, c->n_inst * sizeof(double), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->steps_taken = 0;
+    c->have_state = true;
+    return TSM_OK;
+}
+
+tsm_status tsm_step(tsm_ctx* c, int32_t n_steps) {
+    if (!c) return TSM_EINVAL;
+    if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
+    if (n_steps < 0) return c->fail(TSM_EINVAL, "n_steps < 0");
+    HIPCHK(hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->stream));
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    for (int s = 0; s < n_steps; ++s) {
+        if (c->graph) {
+            HIPCHK(hipGraphLaunch(c->graph, c->stream));
+        } else {
+            tsm_status st = enqueue_step(c);
+            if (st != TSM_OK) return st;
+        }
+    }
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    int32_t nc = 0;
+    HIPCHK(hipMemcpyAsync(&nc, c->counters, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->step_ms = ms;
+    c->steps_taken += n_steps;
+    if (nc > 0) return c->fail(TSM_ENOCONV, std::to_string(nc) + " micro solves missed rtol");
+    return TSM_OK;
+}
+
+tsm_status tsm_get_macro(const tsm_ctx* cc, double* out) {
+    tsm_ctx* c = const_cast<tsm_ctx*>(cc);
+    if (!c || !out) return TSM_EINVAL;
+    if (!c->have_state) return c->fail(TSM_ESTATE, "no state");
+    HIPCHK(hipDeviceSynchronize());   // the caller's pending work on the output buffer
+    HIPCHK(hipMemcpyAsync(out, c->u, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TSM_OK;
+}
+
+tsm_status tsm_get_fluxes(const tsm_ctx* cc, double* out) {
+    tsm_ctx* c = const_cast<tsm_ctx*>(cc);
+    if (!c || !out) return TSM_EINVAL;
+    if (!c->have_state) return c->fail(TSM_ESTATE, "no state");
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpyAsync(out, c->F, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TSM_OK;
+}
+
+tsm_status tsm_get_micro(const tsm_ctx* cc, double* out) {
+    tsm_ctx* c = const_cast<tsm_ctx*>(cc);
+    if (!c || !out) return TSM_EINVAL;
+    if (!c->have_state) return c->fail(TSM_ESTATE, "no state");
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(launch_state_join((int)c->n_inst, c->offsets, c->u, c->v0, c->w, out, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TSM_OK;
+}
+
+tsm_status tsm_get_setup(const tsm_ctx* cc, double* beta_out, double* len_out, double* w_out) {
+    tsm_ctx* c = const_cast<tsm_ctx*>(cc);
+    if (!c) return TSM_EINVAL;
+    if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation first");
+    HIPCHK(hipDeviceSynchronize());
+    if (beta_out) HIPCHK(hipMemcpyAsync(beta_out, c->beta, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (len_out) HIPCHK(hipMemcpyAsync(len_out, c->len, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (w_out) HIPCHK(hipMemcpyAsync(w_out, c->w, c->total * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TSM_OK;
+}
+
+tsm_status tsm_apply_operator(tsm_ctx* c, const double* x, double* y) {
+    if (!c || !x || !y) return TSM_EINVAL;
+    if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation first");
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(launch_apply((int)c->n_inst, c->level, c->offsets, c->S64, x, y, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TSM_OK;
+}
+
+tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda_out) {
+    if (!c) return TSM_EINVAL;
+    (void)n_steps; (void)J_out; (void)dJda_out;
+    return c->fail(TSM_EINVAL, "gradient: not available in this build");
+}
+
+tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
+    tsm_ctx* c = const_cast<tsm_ctx*>(cc);
+    if (!c || !s) return TSM_EINVAL;
+    std::memset(s, 0, sizeof(*s));
+    s->n_inst = c->n_inst;
+    s->n_micro_dofs = c->total;
+    s->steps_taken = c->steps_taken;
+    s->macro_sweeps = c->macro_sweeps;
+    s->macro_contraction = c->rho;
+    s->setup_ms = c->setup_ms;
+    s->step_ms = c->step_ms;
+    if (c->have_geom && c->n_inst > 0) {
+        std::vector<int32_t> it(c->n_inst), sw(c->n_inst);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipMemcpy(it.data(), c->iters, c->n_inst * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(sw.data(), c->sweeps, c->n_inst * sizeof(int32_t), hipMemcpyDeviceToHost));
+        int32_t nc = 0;
+        HIPCHK(hipMemcpy(&nc, c->counters, sizeof(int32_t), hipMemcpyDeviceToHost));
+        s->iters_min = *std::min_element(it.begin(), it.end());
+        s->iters_max = *std::max_element(it.begin(), it.end());
+        double sum = 0;
+        for (int32_t v : it) sum += v;
+        s->iters_mean = sum / c->n_inst;
+        s->sweeps_max = *std::max_element(sw.begin(), sw.end());
+        s->unconverged = nc;
+    }
+    return TSM_OK;
+}
+
+const char* tsm_last_error(const tsm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void tsm_destroy(tsm_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    c->free_mesh();
+    c->free_macro();
+    dfree(c->counters);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+// Setup kernel: the pulled-back Q1 operator of every micro instance.
+//
+// For node j of instance i the kernel integrates, over the (at most four)
+// cells around j with the 2x2 Gauss rule, the row of
+//     S_i = M_i/dt + d A_i + kappa B_i,   M_i = int eta eta J,
+//     A_i = int grad eta . (K K^T J) grad eta
+// (discrete weak form on the reference cell, paper Section 3.1) and over the
+// (at most two) boundary edges at j, with the 2-point rule, the row of
+//     B_i = int_dZ eta eta |cof(F) nu|      (boundary change of variables).
+// Each node gathers its own row -- no atomics, fixed summation order.
+// K K^T J and |cof F nu| are evaluated at each point from the amplitude a_i
+// and the per-level sin/cos tables (the paper caches J and K K^T J per
+// quadrature point; here they cost a few flops, so nothing is cached).
+#include "device_common.h"
+
+namespace tsm {
+
+namespace {
+
+__global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A) {
+    __shared__ double red_s[2][1][kMicroThreads / kWave];
+    __shared__ double mins[kMicroThreads / kWave];
+    BlockReducer<kMicroThreads / kWave, 1, double> red(red_s);
+
+    const int inst = blockIdx.x;
+    const int N = A.level[inst];
+    const int NP = N + 1;
+    const int n = NP * NP;
+    const int64_t off = A.offsets[inst];
+    const double a = A.amp[inst];
+    const double h = 2.0 / N;
+    const double wq = 0.25 * h * h;      // 2x2 Gauss weight on an h x h cell
+    const double wb = 0.5 * h;           // 2-point Gauss weight on an edge of length h
+    const int tb = A.tab.off[N];
+    const double* ys = A.tab.y + tb;
+    const double* ss = A.tab.s + tb;
+    const double* cs = A.tab.c + tb;
+    const int tm = 2 * N, tp = 2 * N + 1;  // table entries at y = -1, y = +1
+
+    double len_part = 0.0;
+    double jmin = 1e300;
+    for (int j = threadIdx.x; j < n; j += kMicroThreads) {
+        const int j1 = j % NP, j2 = j / NP;
+        double S[kStencil], M[kStencil];
+#pragma unroll
+        for (int k = 0; k < kStencil; ++k) { S[k] = 0.0; M[k] = 0.0; }
+        double bj = 0.0;
+        // ---- cells around node j
+        for (int dc2 = -1; dc2 <= 0; ++dc2) {
+            const int c2 = j2 + dc2;
+            if (c2 < 0 || c2 >= N) continue;
+            const int l2 = j2 - c2;
+            for (int dc1 = -1; dc1 <= 0; ++dc1) {
+                const int c1 = j1 + dc1;
+                if (c1 < 0 || c1 >= N) continue;
+                const int l1 = j1 - c1;
+                for (int g2 = 0; g2 < 2; ++g2) {
+                    const int t2 = 2 * c2 + g2;
+                    for (int g1 = 0; g1 < 2; ++g1) {
+                        const int t1 = 2 * c1 + g1;
+                        const Pull P = pullback_at(a, ys[t1], ys[t2], ss[t1], cs[t1], ss[t2], cs[t2]);
+                        jmin = fmin(jmin, P.J);
+                        // basis of local node (l1,l2) and its reference gradient
+                        const double f1 = lin(l1, g1), f2 = lin(l2, g2);
+                        const double phl = f1 * f2;
+                        const double gl1 = (l1 ? 1.0 : -1.0) * f2 / h;
+                        const double gl2 = f1 * (l2 ? 1.0 : -1.0) / h;
+                        const double Cg1 = P.C11 * gl1 + P.C12 * gl2;
+                        const double Cg2 = P.C12 * gl1 + P.C22 * gl2;
+#pragma unroll
+                        for (int m2 = 0; m2 < 2; ++m2) {
+#pragma unroll
+                            for (int m1 = 0; m1 < 2; ++m1) {
+                                const double e1 = lin(m1, g1), e2 = lin(m2, g2);
+                                const double phm = e1 * e2;
+                                const double gm1 = (m1 ? 1.0 : -1.0) * e2 / h;
+                                const double gm2 = e1 * (m2 ? 1.0 : -1.0) / h;
+                                const int k = (m2 - l2 + 1) * 3 + (m1 - l1 + 1);
+                                const double mass = wq * P.J * phl * phm;
+                                const double stiff = wq * (Cg1 * gm1 + Cg2 * gm2);
+                                M[k] += mass;
+                                S[k] += A.d * stiff + A.inv_dt * mass;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // ---- boundary edges at node j: weight |F tau|
+        // bottom / top edges run along y1 (tangent (1,0)): |M e1| = sqrt(M11^2 + M21^2)
+        for (int side = 0; side < 2; ++side) {
+            if (j2 != (side ? N : 0)) continue;
+            const int tf = side ? tp : tm;
+            const double yf = ys[tf];
+            for (int e = j1 - 1; e <= j1; ++e) {
+                if (e < 0 || e >= N) continue;
+                const int l1 = j1 - e;
+                for (int g = 0; g < 2; ++g) {
+                    const int t1 = 2 * e + g;
+                    const double M11 = 1.0 + a * cs[t1] * yf;
+                    const double M21 = a * ss[tf];
+                    const double om = sqrt(M11 * M11 + M21 * M21);
+                    for (int m1 = 0; m1 < 2; ++m1) {
+                        const double v = wb * om * lin(l1, g) * lin(m1, g);
+                        S[3 + (m1 - l1 + 1)] += A.kappa * v;
+                        bj += v;
+                    }
+                }
+            }
+        }
+        // left / right edges run along y2 (tangent (0,1)): |M e2| = sqrt(M12^2 + M22^2)
+        for (int side = 0; side < 2; ++side) {
+            if (j1 != (side ? N : 0)) continue;
+            const int tf = side ? tp : tm;
+            const double yf = ys[tf];
+            for (int e = j2 - 1; e <= j2; ++e) {
+                if (e < 0 || e >= N) continue;
+                const int l2 = j2 - e;
+                for (int g = 0; g < 2; ++g) {
+                    const int t2 = 2 * e + g;
+                    const double M12 = a * ss[tf];
+                    const double M22 = 1.0 + a * cs[t2] * yf;
+                    const double om = sqrt(M12 * M12 + M22 * M22);
+                    for (int m2 = 0; m2 < 2; ++m2) {
+                        const double v = wb * om * lin(l2, g) * lin(m2, g);
+                        S[(m2 - l2 + 1) * 3 + 1] += A.kappa * v;
+                        bj += v;
+                    }
+                }
+            }
+        }
+        double* Sd = A.S64 + kStencil * off;
+        float* Sf = A.S32 + kStencil * off;
+        double* Md = A.M64 + kStencil * off;
+#pragma unroll
+        for (int k = 0; k < kStencil; ++k) {
+            Sd[(int64_t)k * n + j] = S[k];
+            Sf[(int64_t)k * n + j] = (float)S[k];
+            Md[(int64_t)k * n + j] = M[k];
+        }
+        A.b[off + j] = bj;
+        len_part += bj;
+    }
+    double v[1] = {len_part};
+    red.sum(v);
+    double m = jmin;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) mins[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mm = mins[0];
+        for (int w = 1; w < kMicroThreads / kWave; ++w) mm = fmin(mm, mins[w]);
+        A.len[inst] = v[0];
+        A.jmin[inst] = mm;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s) {
+    if (a.n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(assemble_kernel, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace tsm

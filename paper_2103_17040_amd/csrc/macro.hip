@@ -1,0 +1,186 @@
+// Macro coupling solve and per-instance bookkeeping.
+//
+// After the micro solves, the step leaves one SPD system on the interior
+// macro nodes (Schur complement of the coupled implicit-Euler step):
+//     A_M u = M_H u^n / dt + sign L alpha,
+//     A_M   = M_H / dt + D K_H - sign L diag(beta),
+// with the Q1 mass and stiffness of the uniform macro mesh (9-point stencils
+// (H^2/36)[1 4 1; 4 16 4; 1 4 1] and (1/3)[-1 -1 -1; -1 8 -1; -1 -1 -1]) and
+// the nodal coupling weight L_kk = H^2 of interior nodes.
+//
+// Solver: A_M = A_0 - sign L diag(beta - beta_ref) where A_0 (beta_ref in
+// place of beta) is a tensor product of 1D tridiagonal Toeplitz matrices,
+// diagonalised by the orthonormal sine basis Q: A_0^{-1} = Q Q Lambda^{-1} Q Q
+// (applied to the interior grid as two-sided products, i.e. four n x n
+// GEMMs).  The sweep u <- u + A_0^{-1} (rhs - A_M u) contracts the error by
+// rho <= max |L_kk (beta_k - beta_ref)| / min |Lambda|, which is tiny because
+// every micro response is a discretisation of the same continuum cell
+// problem; the host picks the sweep count from rho at setup.
+#include "device_common.h"
+
+namespace tsm {
+
+namespace {
+
+__device__ __forceinline__ double mass9(const double* u, int k, int W) {
+    return 16.0 * u[k] + 4.0 * (u[k - 1] + u[k + 1] + u[k - W] + u[k + W])
+         + (u[k - W - 1] + u[k - W + 1] + u[k + W - 1] + u[k + W + 1]);
+}
+__device__ __forceinline__ double lap9(const double* u, int k, int W) {
+    return 8.0 * u[k] - (u[k - 1] + u[k + 1] + u[k - W] + u[k + W]
+                         + u[k - W - 1] + u[k - W + 1] + u[k + W - 1] + u[k + W + 1]);
+}
+
+// rhs on interior nodes (n x n grid, row = k2-1): M_H u^n / dt + sign L alpha,
+// alpha_k = -(kappa / |dY_k|) b_k^T v0_k.  alpha is stored for all nodes.
+__global__ void rhs_forward_kernel(MacroArgs m, const double* u, const double* bx,
+                                   double* rhs, double* alpha) {
+    const int W = m.NM + 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < W * W) alpha[idx] = -m.kappa / m.len[idx] * bx[idx];
+    if (idx >= m.n * m.n) return;
+    const int i1 = idx % m.n, i2 = idx / m.n;
+    const int k = (i2 + 1) * W + (i1 + 1);
+    const double al = -m.kappa / m.len[k] * bx[k];
+    rhs[idx] = m.mass_c * mass9(u, k, W) + m.sig_h2 * al;
+}
+
+// adjoint rhs: M_H mu^{n+2}/dt + kappa p (b^T lam0) (+ 2 M_H u^N on the last step)
+__global__ void rhs_adjoint_kernel(MacroArgs m, const double* mu_next, const double* blam,
+                                   const double* u_final, int add_terminal, double mass_h2, double* rhs) {
+    const int W = m.NM + 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m.n * m.n) return;
+    const int i1 = idx % m.n, i2 = idx / m.n;
+    const int k = (i2 + 1) * W + (i1 + 1);
+    double v = m.mass_c * mass9(mu_next, k, W) + m.kappa * m.p * blam[k];
+    if (add_terminal) v += 2.0 * mass_h2 * mass9(u_final, k, W);
+    rhs[idx] = v;
+}
+
+// R = rhs - A_M u on interior nodes (u is the full grid, zero on the boundary)
+__global__ void residual_kernel(MacroArgs m, const double* u, const double* rhs, double* R) {
+    const int W = m.NM + 1;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m.n * m.n) return;
+    const int i1 = idx % m.n, i2 = idx / m.n;
+    const int k = (i2 + 1) * W + (i1 + 1);
+    const double Au = m.mass_c * mass9(u, k, W) + m.lap_c * lap9(u, k, W) - m.sig_h2 * m.beta[k] * u[k];
+    R[idx] = rhs[idx] - Au;
+}
+
+// C = A B for n x n row-major FP64 matrices, 16x16 output tile per workgroup.
+constexpr int TG = 16;
+__global__ __launch_bounds__(TG * TG) void gemm_kernel(int n, const double* A, const double* B, double* C,
+                                                      int epi, const double* lam, double* u, int NM) {
+    __shared__ double As[TG][TG + 1];
+    __shared__ double Bs[TG][TG + 1];
+    const int tx = threadIdx.x % TG, ty = threadIdx.x / TG;
+    const int row = blockIdx.y * TG + ty, col = blockIdx.x * TG + tx;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < n; k0 += TG) {
+        const int ka = k0 + tx, kb = k0 + ty;
+        As[ty][tx] = (row < n && ka < n) ? A[(int64_t)row * n + ka] : 0.0;
+        Bs[ty][tx] = (kb < n && col < n) ? B[(int64_t)kb * n + col] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TG; ++kk) acc += As[ty][kk] * Bs[kk][tx];
+        __syncthreads();
+    }
+    if (row >= n || col >= n) return;
+    const int64_t o = (int64_t)row * n + col;
+    if (epi == 0) {
+        C[o] = acc;
+    } else if (epi == 1) {
+        C[o] = acc / lam[o];
+    } else {
+        const int W = NM + 1;
+        u[(row + 1) * W + (col + 1)] += acc;
+    }
+}
+
+__global__ void finalize_kernel(MacroArgs m, const double* u, const double* alpha, double* F) {
+    const int W = m.NM + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < W * W) F[k] = m.beta[k] * u[k] + alpha[k];
+}
+
+__global__ void beta_kernel(int n, double kappa, double p, const double* len, const double* bx, double* beta) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) beta[i] = kappa * p - kappa / len[i] * bx[i];
+}
+
+// v0 = v - u_i w and v = v0 + u_i w over the ragged vector (one workgroup per instance)
+__global__ void state_split_kernel(const int64_t* offsets, const double* u, const double* v,
+                                   const double* w, double* v0) {
+    const int i = blockIdx.x;
+    const int64_t b = offsets[i], e = offsets[i + 1];
+    const double ui = u[i];
+    for (int64_t j = b + threadIdx.x; j < e; j += blockDim.x) v0[j] = (v ? v[j] : 0.0) - ui * w[j];
+}
+__global__ void state_join_kernel(const int64_t* offsets, const double* u, const double* v0,
+                                  const double* w, double* v) {
+    const int i = blockIdx.x;
+    const int64_t b = offsets[i], e = offsets[i + 1];
+    const double ui = u[i];
+    for (int64_t j = b + threadIdx.x; j < e; j += blockDim.x) v[j] = v0[j] + ui * w[j];
+}
+
+inline int blocks(int n, int t) { return (n + t - 1) / t; }
+
+}  // namespace
+
+hipError_t launch_macro_rhs_forward(const MacroArgs& m, const double* u, const double* bx,
+                                    double* rhs, double* alpha, hipStream_t s) {
+    const int tot = (m.NM + 1) * (m.NM + 1);
+    hipLaunchKernelGGL(rhs_forward_kernel, dim3(blocks(tot, 256)), dim3(256), 0, s, m, u, bx, rhs, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_rhs_adjoint(const MacroArgs& m, const double* mu_next, const double* blam,
+                                    const double* u_final, int add_terminal, double* rhs, hipStream_t s) {
+    // M_H = (H^2/36) mass9; m.mass_c = H^2/(36 dt) so H^2/36 = m.mass_c * dt is passed explicitly
+    const double H = 1.0 / m.NM;
+    const double mass_h2 = H * H / 36.0;
+    hipLaunchKernelGGL(rhs_adjoint_kernel, dim3(blocks(m.n * m.n, 256)), dim3(256), 0, s, m, mu_next, blam,
+                       u_final, add_terminal, mass_h2, rhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_residual(const MacroArgs& m, const double* u, const double* rhs, double* R, hipStream_t s) {
+    hipLaunchKernelGGL(residual_kernel, dim3(blocks(m.n * m.n, 256)), dim3(256), 0, s, m, u, rhs, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(int n, const double* A, const double* B, double* C, int epilogue,
+                       const double* lam, double* u, int NM, hipStream_t s) {
+    const dim3 grid(blocks(n, TG), blocks(n, TG));
+    hipLaunchKernelGGL(gemm_kernel, grid, dim3(TG * TG), 0, s, n, A, B, C, epilogue, lam, u, NM);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_finalize(const MacroArgs& m, const double* u, const double* alpha, double* F, hipStream_t s) {
+    const int tot = (m.NM + 1) * (m.NM + 1);
+    hipLaunchKernelGGL(finalize_kernel, dim3(blocks(tot, 256)), dim3(256), 0, s, m, u, alpha, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_beta(int n_inst, double kappa, double p, const double* len, const double* bx,
+                       double* beta, hipStream_t s) {
+    hipLaunchKernelGGL(beta_kernel, dim3(blocks(n_inst, 256)), dim3(256), 0, s, n_inst, kappa, p, len, bx, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_split(int n_inst, const int64_t* offsets, const double* u, const double* v,
+                              const double* w, double* v0, hipStream_t s) {
+    hipLaunchKernelGGL(state_split_kernel, dim3(n_inst), dim3(256), 0, s, offsets, u, v, w, v0);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_join(int n_inst, const int64_t* offsets, const double* u, const double* v0,
+                             const double* w, double* v, hipStream_t s) {
+    hipLaunchKernelGGL(state_join_kernel, dim3(n_inst), dim3(256), 0, s, offsets, u, v0, w, v);
+    return hipGetLastError();
+}
+
+}  // namespace tsm

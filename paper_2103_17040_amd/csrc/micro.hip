@@ -1,0 +1,435 @@
+// Batched micro solves: Jacobi-preconditioned conjugate gradients on every
+// instance's S_i = M_i/dt + d A_i + kappa B_i (paper Section 3.3: every system
+// solved by CG, the micro systems distributed over the processors).
+//
+// Layout and mapping (one workgroup of 256 lanes per instance):
+//   - lane t owns nodes j = t + 256 s for s < SLOTS; its x, r, diag^{-1}
+//     stay in registers for the whole solve;
+//   - the search direction lives in LDS with N+2 zero entries on both sides,
+//     so the 9-point neighbour reads of the boundary rows stay in bounds and
+//     read zeros where the stencil coefficient is zero anyway;
+//   - the stencil row (9 coefficients, coefficient-major in HBM so that a
+//     wavefront reads it coalesced) is either held in registers across all
+//     iterations (resident forms) or re-read every iteration (streamed forms,
+//     for meshes whose rows do not fit in registers);
+//   - dot products: butterfly wavefront sums, then one LDS exchange per call
+//     (ping-pong buffer, one barrier per reduction), identical on all lanes,
+//     so every lane takes the same convergence decision.
+//
+// Precision forms:
+//   FP64      PCG in FP64 until ||b - S x||_2 <= rtol ||b||_2.
+//   REFINE    FP64 residual r = b - S x (FP64 stencil), FP32 PCG on
+//             S d = r / ||r|| to inner_rtol with the FP32 stencil, x += ||r|| d,
+//             repeated until the FP64 residual meets rtol.
+#include "device_common.h"
+
+namespace tsm {
+
+namespace {
+
+constexpr int NT = kMicroThreads;
+constexpr int NW = NT / kWave;
+
+struct Geo {
+    int n, NP, PAD;
+    int64_t off;
+    int dj[kStencil];
+};
+
+__device__ __forceinline__ Geo instance_geo(const MicroArgs& A, int inst) {
+    Geo g;
+    const int N = A.level[inst];
+    g.NP = N + 1;
+    g.n = g.NP * g.NP;
+    g.PAD = g.NP + 1;
+    g.off = A.offsets[inst];
+#pragma unroll
+    for (int k = 0; k < kStencil; ++k) g.dj[k] = (k / 3 - 1) * g.NP + (k % 3 - 1);
+    return g;
+}
+
+// x0 into registers and LDS; right-hand side b.
+template <int SLOTS>
+__device__ __forceinline__ void load_initial(const MicroArgs& A, int inst, const Geo& g,
+                                             double* xs, double (&x)[SLOTS], double (&b)[SLOTS]) {
+    const int tid = threadIdx.x;
+    for (int t = tid; t < g.PAD; t += NT) {
+        xs[t] = 0.0;
+        xs[g.PAD + g.n + t] = 0.0;
+    }
+    const double cf = (A.coef != nullptr) ? A.coef[inst] : 0.0;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int j = tid + s * NT;
+        double v = 0.0;
+        if (j < g.n && !A.zero_init) v = A.X0[g.off + j] + cf * A.w[g.off + j];
+        x[s] = v;
+        if (j < g.n) xs[g.PAD + j] = v;
+    }
+    __syncthreads();
+    const double* __restrict__ Mm = A.M64 + kStencil * g.off;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int j = tid + s * NT;
+        double v = 0.0;
+        if (j < g.n) {
+            if (A.rhs_vec != nullptr) {
+                v = A.rhs_scale * A.rhs_vec[g.off + j];
+            } else {
+                double m = 0.0;
+#pragma unroll
+                for (int k = 0; k < kStencil; ++k) m += Mm[(int64_t)k * g.n + j] * xs[g.PAD + j + g.dj[k]];
+                v = m * A.inv_dt;
+            }
+        }
+        b[s] = v;
+    }
+}
+
+template <int SLOTS>
+__device__ __forceinline__ void write_result(const MicroArgs& A, int inst, const Geo& g,
+                                             const double (&x)[SLOTS], int iters, int sweeps, bool conv,
+                                             BlockReducer<NW, 1, double>& red1) {
+    const int tid = threadIdx.x;
+    double bx[1] = {0.0};
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int j = tid + s * NT;
+        if (j < g.n) {
+            A.X_out[g.off + j] = x[s];
+            bx[0] += A.b[g.off + j] * x[s];
+        }
+    }
+    red1.sum(bx);
+    if (tid == 0) {
+        A.bx_out[inst] = bx[0];
+        if (A.iters_out) A.iters_out[inst] = iters;
+        if (A.sweeps_out) A.sweeps_out[inst] = sweeps;
+        if (!conv) atomicAdd(A.nonconv, 1);
+    }
+}
+
+// ---------------------------------------------------------------- FP64 PCG
+template <int SLOTS, bool RES>
+__device__ void solve_fp64(const MicroArgs& A, int inst, double* xs,
+                           BlockReducer<NW, 1, double>& red1, BlockReducer<NW, 3, double>& red3) {
+    const Geo g = instance_geo(A, inst);
+    const int tid = threadIdx.x;
+    const double* __restrict__ S = A.S64 + kStencil * g.off;
+    double x[SLOTS], b[SLOTS], r[SLOTS], dinv[SLOTS], p[SLOTS];
+    double Sr[RES ? SLOTS : 1][kStencil];
+    load_initial<SLOTS>(A, inst, g, xs, x, b);
+
+    double acc[3] = {0.0, 0.0, 0.0};   // ||b||^2, ||r||^2, r.z
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int j = tid + s * NT;
+        r[s] = 0.0; dinv[s] = 0.0;
+        if (j < g.n) {
+            double sx = 0.0;
+#pragma unroll
+            for (int k = 0; k < kStencil; ++k) {
+                const double c = S[(int64_t)k * g.n + j];
+                if constexpr (RES) Sr[s][k] = c;
+                sx += c * xs[g.PAD + j + g.dj[k]];
+            }
+            r[s] = b[s] - sx;
+            dinv[s] = 1.0 / S[4 * (int64_t)g.n + j];
+            acc[0] += b[s] * b[s];
+            acc[1] += r[s] * r[s];
+            acc[2] += r[s] * dinv[s] * r[s];
+        } else if constexpr (RES) {
+#pragma unroll
+            for (int k = 0; k < kStencil; ++k) Sr[s][k] = 0.0;
+        }
+        p[s] = dinv[s] * r[s];
+    }
+    red3.sum(acc);
+    const double tol2 = A.rtol * A.rtol * acc[0];
+    double rr = acc[1], rz = acc[2];
+    bool conv = rr <= tol2;
+    int it = 0;
+    while (!conv && it < A.max_iter) {
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int j = tid + s * NT;
+            if (j < g.n) xs[g.PAD + j] = p[s];
+        }
+        __syncthreads();
+        double q[SLOTS];
+        double pq[1] = {0.0};
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int j = tid + s * NT;
+            double t = 0.0;
+            if (j < g.n) {
+#pragma unroll
+                for (int k = 0; k < kStencil; ++k) {
+                    const double c = RES ? Sr[s][k] : S[(int64_t)k * g.n + j];
+                    t += c * xs[g.PAD + j + g.dj[k]];
+                }
+            }
+            q[s] = t;
+            pq[0] += p[s] * t;
+        }
+        red1.sum(pq);
+        const double alpha = rz / pq[0];
+        double a2[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            x[s] += alpha * p[s];
+            r[s] -= alpha * q[s];
+            a2[0] += r[s] * dinv[s] * r[s];
+            a2[1] += r[s] * r[s];
+        }
+        red3.sum(a2);
+        ++it;
+        rr = a2[1];
+        if (rr <= tol2) { conv = true; break; }
+        const double beta = a2[0] / rz;
+        rz = a2[0];
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) p[s] = dinv[s] * r[s] + beta * p[s];
+    }
+    write_result<SLOTS>(A, inst, g, x, it, 1, conv, red1);
+}
+
+// ------------------------------------------- FP32 PCG inside FP64 refinement
+template <int SLOTS, bool RES>
+__device__ void solve_refine(const MicroArgs& A, int inst, double* xs, float* ps,
+                             BlockReducer<NW, 1, double>& red1, BlockReducer<NW, 3, double>& red3,
+                             BlockReducer<NW, 1, float>& rf1, BlockReducer<NW, 2, float>& rf2) {
+    const Geo g = instance_geo(A, inst);
+    const int tid = threadIdx.x;
+    const double* __restrict__ S = A.S64 + kStencil * g.off;
+    const float* __restrict__ Sf = A.S32 + kStencil * g.off;
+    double x[SLOTS], b[SLOTS];
+    float dinv[SLOTS];
+    float Sr[RES ? SLOTS : 1][kStencil];
+    for (int t = tid; t < g.PAD; t += NT) {
+        ps[t] = 0.0f;
+        ps[g.PAD + g.n + t] = 0.0f;
+    }
+    load_initial<SLOTS>(A, inst, g, xs, x, b);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int j = tid + s * NT;
+        dinv[s] = 0.0f;
+        if (j < g.n) {
+            if constexpr (RES) {
+#pragma unroll
+                for (int k = 0; k < kStencil; ++k) Sr[s][k] = Sf[(int64_t)k * g.n + j];
+            }
+            dinv[s] = 1.0f / Sf[4 * (int64_t)g.n + j];
+        } else if constexpr (RES) {
+#pragma unroll
+            for (int k = 0; k < kStencil; ++k) Sr[s][k] = 0.0f;
+        }
+    }
+    double bn2 = 0.0;
+    int sweeps = 0, iters = 0;
+    bool conv = false;
+    for (;;) {
+        if (sweeps > 0) {
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const int j = tid + s * NT;
+                if (j < g.n) xs[g.PAD + j] = x[s];
+            }
+            __syncthreads();
+        }
+        // FP64 residual
+        double r64[SLOTS];
+        double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int j = tid + s * NT;
+            double t = 0.0;
+            if (j < g.n) {
+                double sx = 0.0;
+#pragma unroll
+                for (int k = 0; k < kStencil; ++k) sx += S[(int64_t)k * g.n + j] * xs[g.PAD + j + g.dj[k]];
+                t = b[s] - sx;
+            }
+            r64[s] = t;
+            acc[0] += b[s] * b[s];
+            acc[1] += t * t;
+        }
+        red3.sum(acc);
+        if (sweeps == 0) bn2 = acc[0];
+        ++sweeps;
+        if (acc[1] <= A.rtol * A.rtol * bn2) { conv = true; break; }
+        if (sweeps > A.max_refine) break;
+        // inner FP32 solve of S d = r / ||r||, zero initial guess
+        const double rn = sqrt(acc[1]);
+        const double isc = 1.0 / rn;
+        float r[SLOTS], d[SLOTS], p[SLOTS];
+        float f2[2] = {0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            r[s] = (float)(r64[s] * isc);
+            d[s] = 0.0f;
+            p[s] = dinv[s] * r[s];
+            f2[0] += r[s] * p[s];
+            f2[1] += r[s] * r[s];
+        }
+        rf2.sum(f2);
+        float rz = f2[0];
+        const float itol2 = (float)(A.inner_rtol * A.inner_rtol) * f2[1];
+        int it = 0;
+        for (;;) {
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const int j = tid + s * NT;
+                if (j < g.n) ps[g.PAD + j] = p[s];
+            }
+            __syncthreads();
+            float q[SLOTS];
+            float pq[1] = {0.0f};
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                const int j = tid + s * NT;
+                float t = 0.0f;
+                if (j < g.n) {
+#pragma unroll
+                    for (int k = 0; k < kStencil; ++k) {
+                        const float c = RES ? Sr[s][k] : Sf[(int64_t)k * g.n + j];
+                        t += c * ps[g.PAD + j + g.dj[k]];
+                    }
+                }
+                q[s] = t;
+                pq[0] += p[s] * t;
+            }
+            rf1.sum(pq);
+            const float alpha = rz / pq[0];
+            float a2[2] = {0.0f, 0.0f};
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+                d[s] += alpha * p[s];
+                r[s] -= alpha * q[s];
+                a2[0] += r[s] * dinv[s] * r[s];
+                a2[1] += r[s] * r[s];
+            }
+            rf2.sum(a2);
+            ++it;
+            if (a2[1] <= itol2 || it >= A.max_iter) break;
+            const float beta = a2[0] / rz;
+            rz = a2[0];
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) p[s] = dinv[s] * r[s] + beta * p[s];
+        }
+        iters += it;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) x[s] += rn * (double)d[s];
+    }
+    write_result<SLOTS>(A, inst, g, x, iters, sweeps, conv, red1);
+}
+
+// MODE: 0 FP64 resident stencil, 1 FP64 streamed, 2 refine resident, 3 refine streamed
+template <int SLOTS, int MODE>
+__global__ __launch_bounds__(NT) void micro_kernel(MicroArgs A, int max_n_pad) {
+    extern __shared__ double lds[];
+    __shared__ double r1[2][1][NW];
+    __shared__ double r3[2][3][NW];
+    __shared__ float f1[2][1][NW];
+    __shared__ float f2[2][2][NW];
+    __shared__ int task_s;
+    BlockReducer<NW, 1, double> red1(r1);
+    BlockReducer<NW, 3, double> red3(r3);
+    BlockReducer<NW, 1, float> rf1(f1);
+    BlockReducer<NW, 2, float> rf2(f2);
+    double* xs = lds;
+    float* ps = reinterpret_cast<float*>(lds + max_n_pad);
+
+    int task = blockIdx.x;
+    for (;;) {
+        if (A.queue != nullptr) {
+            if (threadIdx.x == 0) task_s = atomicAdd(A.queue, 1);
+            __syncthreads();
+            task = task_s;
+            __syncthreads();
+        }
+        if (task >= A.n_tasks) break;
+        const int inst = A.order[task];
+        if constexpr (MODE == 0) solve_fp64<SLOTS, true>(A, inst, xs, red1, red3);
+        if constexpr (MODE == 1) solve_fp64<SLOTS, false>(A, inst, xs, red1, red3);
+        if constexpr (MODE == 2) solve_refine<SLOTS, true>(A, inst, xs, ps, red1, red3, rf1, rf2);
+        if constexpr (MODE == 3) solve_refine<SLOTS, false>(A, inst, xs, ps, red1, red3, rf1, rf2);
+        if (A.queue == nullptr) break;
+    }
+}
+
+template <int SLOTS, int MODE>
+hipError_t launch_one(const MicroArgs& a, int grid, size_t lds, hipStream_t s) {
+    const int max_n_pad = (int)(lds / (sizeof(double) + sizeof(float)));
+    hipLaunchKernelGGL((micro_kernel<SLOTS, MODE>), dim3(grid), dim3(NT), lds, s, a, max_n_pad);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_mode(const MicroArgs& a, int slots, int grid, size_t lds, hipStream_t s) {
+    switch (slots) {
+        case 1: return launch_one<1, MODE>(a, grid, lds, s);
+        case 2: return launch_one<2, MODE>(a, grid, lds, s);
+        case 3: return launch_one<3, MODE>(a, grid, lds, s);
+        case 5: return launch_one<5, MODE>(a, grid, lds, s);
+        case 9: return launch_one<9, MODE>(a, grid, lds, s);
+        case 17:
+            if constexpr (MODE == 1 || MODE == 3) return launch_one<17, MODE>(a, grid, lds, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// y = S x for every instance (FP64 stencil), one workgroup per instance.
+__global__ __launch_bounds__(NT) void apply_kernel(const int32_t* level, const int64_t* offsets,
+                                                   const double* S64, const double* x, double* y) {
+    const int inst = blockIdx.x;
+    const int NP = level[inst] + 1;
+    const int n = NP * NP;
+    const int64_t off = offsets[inst];
+    const double* S = S64 + kStencil * off;
+    for (int j = threadIdx.x; j < n; j += NT) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < kStencil; ++k) {
+            const int jj = j + (k / 3 - 1) * NP + (k % 3 - 1);
+            const double c = S[(int64_t)k * n + j];
+            if (jj >= 0 && jj < n) t += c * x[off + jj];
+        }
+        y[off + j] = t;
+    }
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_t lds, hipStream_t s) {
+    if (a.n_tasks <= 0 || grid <= 0) return hipSuccess;
+    switch (mode) {
+        case 0: return launch_mode<0>(a, slots, grid, lds, s);
+        case 1: return launch_mode<1>(a, slots, grid, lds, s);
+        case 2: return launch_mode<2>(a, slots, grid, lds, s);
+        case 3: return launch_mode<3>(a, slots, grid, lds, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_apply(int n_inst, const int32_t* level, const int64_t* offsets,
+                        const double* S64, const double* x, double* y, hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(apply_kernel, dim3(n_inst), dim3(NT), 0, s, level, offsets, S64, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace tsm

@@ -1,0 +1,111 @@
+// Internal declarations shared by the HIP sources of libtsm (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "tsm.h"
+
+namespace tsm {
+
+constexpr int kMicroThreads = 256;        // lanes per micro workgroup (4 waves)
+constexpr int kWave = 64;
+constexpr int kMaxLevel = 64;             // largest micro mesh N (cells per side)
+constexpr int kMinLevel = 2;
+constexpr int kStencil = 9;               // 9-point Q1 stencil, k = (dj2+1)*3 + (dj1+1)
+
+// Per-level quadrature tables: for level N, entries [tab_off[N], tab_off[N] + 2N + 2).
+// Entry t < 2N is the Gauss abscissa y_t = -1 + (t/2 + g_{t%2}) h of cell t/2;
+// entries 2N and 2N+1 are the edges y = -1 and y = +1.
+// s_t = sin(pi y_t)/4 and c_t = pi cos(pi y_t)/4, so the displacement
+// gradient is G = [[c(y1) y2, s(y1)], [s(y2), c(y2) y1]].
+struct Tables {
+    const int32_t* off;   // [kMaxLevel + 1]
+    const double* y;
+    const double* s;
+    const double* c;
+};
+
+struct AssembleArgs {
+    int n_inst;
+    const int32_t* level;
+    const int64_t* offsets;
+    const double* amp;
+    Tables tab;
+    double d, kappa, inv_dt;
+    double* S64;          // [9 * total] : instance block at 9*off, coefficient-major [k][n]
+    float* S32;
+    double* M64;
+    double* b;            // boundary load B 1 (ragged)
+    double* len;          // [n_inst] 1^T b
+    double* jmin;         // [n_inst] minimum det over all quadrature points
+};
+
+// One batched micro solve: for every task t, instance i = order[t] solves
+//   S_i x = rhs_i,   rhs_i = rhs_scale * rhs_vec_i       (rhs_vec != null)
+//                    rhs_i = M_i x0_i / dt                (otherwise)
+// from the initial guess x0_i = X0_i + coef_i * w_i (zero if zero_init).
+// Writes x to X_out and b_i^T x to bx_out[i].
+struct MicroArgs {
+    int n_tasks;
+    const int32_t* order;
+    const int32_t* level;
+    const int64_t* offsets;
+    const double* S64;
+    const float* S32;
+    const double* M64;
+    const double* b;
+    const double* X0;
+    const double* w;
+    const double* coef;
+    const double* rhs_vec;
+    double rhs_scale;
+    int zero_init;
+    double* X_out;
+    double* bx_out;
+    int32_t* iters_out;
+    int32_t* sweeps_out;
+    int32_t* nonconv;     // device counter, incremented by instances that miss rtol
+    double inv_dt;
+    double rtol, inner_rtol;
+    int max_iter, max_refine;
+    int32_t* queue;       // persistent work counter (null: task = blockIdx.x)
+};
+
+struct MacroArgs {
+    int NM;               // macro cells per side
+    int n;                // interior nodes per side = NM - 1
+    double mass_c;        // H^2 / (36 dt)
+    double lap_c;         // D / 3
+    double sig_h2;        // source_sign * H^2 (nodal weight L_kk of interior nodes times sign)
+    double kappa, p;
+    const double* beta;   // [n_inst]
+    const double* len;    // [n_inst]
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s);
+hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t launch_apply(int n_inst, const int32_t* level, const int64_t* offsets,
+                        const double* S64, const double* x, double* y, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int n, hipStream_t s);
+
+// macro kernels
+hipError_t launch_macro_rhs_forward(const MacroArgs& m, const double* u, const double* bx,
+                                    double* rhs, double* alpha, hipStream_t s);
+hipError_t launch_macro_rhs_adjoint(const MacroArgs& m, const double* mu_next, const double* blam,
+                                    const double* u_final, int add_terminal, double* rhs, hipStream_t s);
+hipError_t launch_macro_residual(const MacroArgs& m, const double* u, const double* rhs, double* R, hipStream_t s);
+// C = A * B (n x n row-major); epilogue 0: C stored; 1: C ./= lam; 2: u[interior] += C
+hipError_t launch_gemm(int n, const double* A, const double* B, double* C, int epilogue,
+                       const double* lam, double* u, int NM, hipStream_t s);
+hipError_t launch_macro_finalize(const MacroArgs& m, const double* u, const double* alpha,
+                                 double* F, hipStream_t s);
+hipError_t launch_beta(int n_inst, double kappa, double p, const double* len, const double* bx,
+                       double* beta, hipStream_t s);
+hipError_t launch_state_split(int n_inst, const int64_t* offsets, const double* u, const double* v,
+                              const double* w, double* v0, hipStream_t s);
+hipError_t launch_state_join(int n_inst, const int64_t* offsets, const double* u, const double* v0,
+                             const double* w, double* v, hipStream_t s);
+
+}  // namespace tsm

@@ -1,0 +1,181 @@
+"""ctypes binding of libtsm.so: the C ABI of include/tsm.h with the same
+names.  Argument marshalling only: every step of the path runs in the HIP
+library.  Device pointers are passed as integers (e.g. ``tensor.data_ptr()``
+of a torch CUDA tensor); PyTorch is only a convenient owner of device memory.
+
+If the shared library is missing the import of this module fails loudly:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtsm.so")
+
+TSM_OK, TSM_EINVAL, TSM_EGEOM, TSM_ENOCONV, TSM_EHIP, TSM_ENOMEM, TSM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+TSM_FP64, TSM_FP32_REFINE = 0, 1
+TSM_FLAG_NO_GRAPH = 1 << 0
+TSM_FLAG_STENCIL_STREAM = 1 << 1
+
+STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV",
+                -4: "TSM_EHIP", -5: "TSM_ENOMEM", -6: "TSM_ESTATE"}
+
+EXPORTED = ["tsm_default_params", "tsm_create", "tsm_set_reference_mesh", "tsm_get_offsets",
+            "tsm_set_deformation", "tsm_set_state", "tsm_step", "tsm_get_macro", "tsm_get_fluxes",
+            "tsm_get_micro", "tsm_get_setup", "tsm_apply_operator", "tsm_gradient", "tsm_get_stats",
+            "tsm_last_error", "tsm_destroy"]
+
+
+class tsm_params(ctypes.Structure):
+    _fields_ = [("macro_cells", ctypes.c_int32), ("D", ctypes.c_double), ("d", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("p", ctypes.c_double), ("dt", ctypes.c_double),
+                ("source_sign", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("setup_rtol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("checkpoint_every", ctypes.c_int32), ("flags", ctypes.c_uint64)]
+
+
+class tsm_stats(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int64), ("n_micro_dofs", ctypes.c_int64), ("steps_taken", ctypes.c_int64),
+                ("iters_min", ctypes.c_int32), ("iters_max", ctypes.c_int32), ("iters_mean", ctypes.c_double),
+                ("sweeps_max", ctypes.c_int32), ("unconverged", ctypes.c_int32),
+                ("macro_sweeps", ctypes.c_int32), ("macro_contraction", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("step_ms", ctypes.c_double)]
+
+
+class TsmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_17040_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, VP = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    sig = {
+        "tsm_default_params": (None, [ctypes.POINTER(tsm_params)]),
+        "tsm_create": (I32, [ctypes.POINTER(tsm_params), VP, ctypes.POINTER(P)]),
+        "tsm_set_reference_mesh": (I32, [P, ctypes.POINTER(I32), I64]),
+        "tsm_get_offsets": (I32, [P, ctypes.POINTER(I64)]),
+        "tsm_set_deformation": (I32, [P, VP, VP, I64]),
+        "tsm_set_state": (I32, [P, VP, VP]),
+        "tsm_step": (I32, [P, I32]),
+        "tsm_get_macro": (I32, [P, VP]),
+        "tsm_get_fluxes": (I32, [P, VP]),
+        "tsm_get_micro": (I32, [P, VP]),
+        "tsm_get_setup": (I32, [P, VP, VP, VP]),
+        "tsm_apply_operator": (I32, [P, VP, VP]),
+        "tsm_gradient": (I32, [P, I32, ctypes.POINTER(D), VP]),
+        "tsm_get_stats": (I32, [P, ctypes.POINTER(tsm_stats)]),
+        "tsm_last_error": (ctypes.c_char_p, [P]),
+        "tsm_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(ctx, status):
+    if status != TSM_OK:
+        msg = _lib.tsm_last_error(ctx).decode() if ctx else ""
+        raise TsmError(status, msg)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def tsm_default_params() -> tsm_params:
+    p = tsm_params()
+    _lib.tsm_default_params(ctypes.byref(p))
+    return p
+
+
+def tsm_create(params: tsm_params, stream=None):
+    out = ctypes.c_void_p()
+    st = _lib.tsm_create(ctypes.byref(params), stream, ctypes.byref(out))
+    if st != TSM_OK:
+        raise TsmError(st, "tsm_create rejected the parameters")
+    return out.value
+
+
+def tsm_set_reference_mesh(ctx, micro_cells) -> None:
+    mc = np.ascontiguousarray(micro_cells, dtype=np.int32)
+    _check(ctx, _lib.tsm_set_reference_mesh(ctx, mc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), mc.size))
+
+
+def tsm_get_offsets(ctx, n_inst: int) -> np.ndarray:
+    out = np.zeros(n_inst + 1, dtype=np.int64)
+    _check(ctx, _lib.tsm_get_offsets(ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return out
+
+
+def tsm_set_deformation(ctx, a, theta, n_inst: int) -> None:
+    _check(ctx, _lib.tsm_set_deformation(ctx, _ptr(a), _ptr(theta), n_inst))
+
+
+def tsm_set_state(ctx, u, v) -> None:
+    _check(ctx, _lib.tsm_set_state(ctx, _ptr(u), _ptr(v)))
+
+
+def tsm_step(ctx, n_steps: int, allow_noconv: bool = False) -> int:
+    st = _lib.tsm_step(ctx, int(n_steps))
+    if st == TSM_ENOCONV and allow_noconv:
+        return st
+    _check(ctx, st)
+    return st
+
+
+def tsm_get_macro(ctx, u_out) -> None:
+    _check(ctx, _lib.tsm_get_macro(ctx, _ptr(u_out)))
+
+
+def tsm_get_fluxes(ctx, F_out) -> None:
+    _check(ctx, _lib.tsm_get_fluxes(ctx, _ptr(F_out)))
+
+
+def tsm_get_micro(ctx, v_out) -> None:
+    _check(ctx, _lib.tsm_get_micro(ctx, _ptr(v_out)))
+
+
+def tsm_get_setup(ctx, beta_out=None, len_out=None, w_out=None) -> None:
+    _check(ctx, _lib.tsm_get_setup(ctx, _ptr(beta_out), _ptr(len_out), _ptr(w_out)))
+
+
+def tsm_apply_operator(ctx, x, y) -> None:
+    _check(ctx, _lib.tsm_apply_operator(ctx, _ptr(x), _ptr(y)))
+
+
+def tsm_gradient(ctx, n_steps: int, dJda_out) -> float:
+    J = ctypes.c_double()
+    _check(ctx, _lib.tsm_gradient(ctx, int(n_steps), ctypes.byref(J), _ptr(dJda_out)))
+    return J.value
+
+
+def tsm_get_stats(ctx) -> dict:
+    s = tsm_stats()
+    _check(ctx, _lib.tsm_get_stats(ctx, ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in tsm_stats._fields_}
+
+
+def tsm_last_error(ctx) -> str:
+    return _lib.tsm_last_error(ctx).decode()
+
+
+def tsm_destroy(ctx) -> None:
+    _lib.tsm_destroy(ctx)

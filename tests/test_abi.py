@@ -1,0 +1,63 @@
+"""The C ABI library loads without a GPU and exports every entry point the
+header declares; parameter validation runs on the host."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsm.h")
+LIB = os.path.join(ROOT, "paper_2103_17040_amd", "libtsm.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsm_[a-z_]+)\s*\(", src)))
+
+
+def _exported():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    return sorted({line.split()[-1] for line in out.splitlines() if " T " in line and line.split()[-1].startswith("tsm_")})
+
+
+@pytest.fixture(scope="module")
+def lib_built():
+    if not os.path.exists(LIB):
+        pytest.fail("libtsm.so is not built: run `python -m paper_2103_17040_amd.build`")
+    return LIB
+
+
+def test_every_declared_symbol_is_exported(lib_built):
+    decl = _declared()
+    assert len(decl) >= 15
+    assert decl == _exported()
+
+
+def test_binding_names_match_header(lib_built):
+    from paper_2103_17040_amd import tsm
+    assert sorted(tsm.EXPORTED) == _declared()
+
+
+def test_params_struct_layout_and_validation(lib_built):
+    from paper_2103_17040_amd import tsm
+    p = tsm.tsm_default_params()
+    assert p.macro_cells == 8 and p.kappa == 1.0 and p.source_sign == -1 and p.rtol == 1e-12
+    bad = []
+    for field, value in (("D", 0.0), ("dt", -1.0), ("source_sign", 0), ("precision", 7), ("macro_cells", 1),
+                         ("inner_rtol", 1.5), ("p", float("nan"))):
+        q = tsm.tsm_default_params()
+        setattr(q, field, value)
+        bad.append(q)
+    for q in bad:
+        with pytest.raises(tsm.TsmError) as e:
+            tsm.tsm_create(q, None)
+        assert e.value.status == tsm.TSM_EINVAL
+
+
+def test_null_safety(lib_built):
+    from paper_2103_17040_amd import tsm
+    tsm._lib.tsm_destroy(None)
+    assert tsm._lib.tsm_last_error(None) == b"null context"

@@ -1,0 +1,161 @@
+"""GPU path against the FP64 oracle, element by element, on seeded inputs
+(small sizes that still span several workgroup slots and a ragged tail)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import banner, gpu_for, oracle_for, rel, run_both, workload_case
+
+pytestmark = pytest.mark.gpu
+
+# Tolerances: relative discrete l2 over each whole output vector.
+TOL_FP64 = 1e-10        # FP64 path (micro rtol 1e-12)
+TOL_REFINE = 1e-8       # FP32 PCG inside FP64 refinement (rtol 1e-10)
+
+
+def _ragged(NM, levels_set, seed):
+    rng = np.random.default_rng(seed)
+    n = (NM + 1) ** 2
+    lv = rng.choice(np.asarray(levels_set), n).astype(np.int32)
+    a = rng.uniform(-0.3, 0.3, n)
+    th = rng.uniform(0.0, np.pi / 8, n)
+    return lv, a, th
+
+
+def test_operator_parity_every_level_class():
+    """K1: S_i x from the GPU's assembled operator vs the oracle's sparse S_i."""
+    NM = 4
+    lv, a, th = _ragged(NM, [2, 3, 5, 8, 15, 16, 17, 22, 27, 33, 47, 48, 64], 11)
+    banner(f"operator parity levels {sorted(set(lv.tolist()))}")
+    ts = oracle_for(NM, lv, a, th, dt=0.005)
+    g = gpu_for(NM, lv, a, th, dt=0.005)
+    try:
+        x = np.random.default_rng(3).standard_normal(g.n_micro)
+        y = g.apply(x).cpu().numpy()
+    finally:
+        g.close()
+    for i, I in enumerate(ts.inst):
+        sl = slice(ts.offsets[i], ts.offsets[i + 1])
+        assert rel(y[sl], I.S @ x[sl]) <= 1e-14, (i, I.N)
+
+
+def test_setup_parity():
+    NM = 4
+    lv, a, th = _ragged(NM, [2, 7, 16, 32, 64], 12)
+    ts = oracle_for(NM, lv, a, th, dt=0.005)
+    g = gpu_for(NM, lv, a, th, dt=0.005)
+    try:
+        beta, ln, w = (t.cpu().numpy() for t in g.setup())
+    finally:
+        g.close()
+    assert rel(ln, ts.len) <= 1e-14
+    assert rel(beta, ts.beta) <= 1e-12
+    assert rel(w, np.concatenate([I.w for I in ts.inst])) <= 1e-11
+
+
+def test_small_fp64_workload_parity():
+    """81 instances of 16x16, analytic amplitudes, 10 steps of dt = 0.01."""
+    w, a, th, lv, u0, v0, phys = workload_case("small_fp64")
+    ref, out, _ = run_both(w.macro_cells, lv, a, th, w.dt, w.steps, u0, v0, rtol=1e-12, **phys)
+    assert rel(out["u"], ref["u"]) <= TOL_FP64
+    assert rel(out["F"], ref["F"]) <= TOL_FP64
+    assert rel(out["v"], ref["v"]) <= TOL_FP64
+    assert out["stats"]["unconverged"] == 0
+
+
+def test_small_workload_refine_parity():
+    w, a, th, lv, u0, v0, phys = workload_case("small_fp64")
+    ref, out, _ = run_both(w.macro_cells, lv, a, th, w.dt, w.steps, u0, v0, precision="fp32_refine",
+                           rtol=1e-10, **phys)
+    for k in ("u", "F", "v"):
+        assert rel(out[k], ref[k]) <= TOL_REFINE, k
+    assert out["stats"]["sweeps_max"] >= 2
+
+
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, TOL_FP64), ("fp32_refine", 1e-10, TOL_REFINE)])
+@pytest.mark.parametrize("NM,levels", [(2, [2, 3]), (5, [4, 16, 33, 64]), (6, [16, 32, 64])])
+def test_ragged_batch_parity(NM, levels, precision, rtol, tol):
+    lv, a, th = _ragged(NM, levels, 20 + NM)
+    rng = np.random.default_rng(5)
+    u0 = W.initial_macro(NM) * (1.0 + 0.3 * rng.standard_normal((NM + 1) ** 2))
+    u0[W.macro_boundary_mask(NM)] = 0.0
+    v0 = rng.uniform(0.0, 1.0, int(W.offsets(lv)[-1]))
+    ref, out, _ = run_both(NM, lv, a, th, 0.005, 4, u0, v0, precision=precision, rtol=rtol)
+    for k in ("u", "F", "v"):
+        assert rel(out[k], ref[k]) <= tol, k
+
+
+def test_sign_plus_one_and_kappa_zero():
+    NM = 4
+    lv, a, th = _ragged(NM, [8, 16], 31)
+    u0 = W.initial_macro(NM)
+    v0 = np.zeros(int(W.offsets(lv)[-1]))
+    for phys in (dict(sigma=1), dict(kappa=0.0), dict(D=0.3, d=2.0, kappa=3.0, p=0.5)):
+        ref, out, _ = run_both(NM, lv, a, th, 0.01, 3, u0, v0, **phys)
+        assert rel(out["u"], ref["u"]) <= TOL_FP64
+        assert rel(out["v"], ref["v"]) <= TOL_FP64 or np.abs(ref["v"]).max() == 0
+
+
+def test_forms_agree_bitwise():
+    """Graph replay, direct launches and the streamed-stencil kernels compute
+    the same sums in the same order: outputs are bitwise identical, and two
+    runs are bitwise identical (deterministic: no atomics in any sum)."""
+    from paper_2103_17040_amd import tsm
+    w, a, th, lv, u0, v0, phys = workload_case("small_fp64")
+    outs = []
+    for flags in (0, 0, tsm.TSM_FLAG_NO_GRAPH, tsm.TSM_FLAG_STENCIL_STREAM):
+        banner(f"forms flags={flags}")
+        g = gpu_for(w.macro_cells, lv, a, th, w.dt, flags=flags, **phys)
+        try:
+            g.set_state(u0, v0)
+            g.step(5)
+            outs.append((g.macro().cpu().numpy(), g.micro().cpu().numpy(), g.fluxes().cpu().numpy()))
+        finally:
+            g.close()
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x, y)
+
+
+def test_boundary_instances_stay_zero():
+    w, a, th, lv, u0, v0, phys = workload_case("small_fp64")
+    g = gpu_for(w.macro_cells, lv, a, th, w.dt, **phys)
+    try:
+        g.set_state(u0, v0)
+        g.step(3)
+        u = g.macro().cpu().numpy()
+        v = g.micro().cpu().numpy()
+    finally:
+        g.close()
+    bnd = W.macro_boundary_mask(w.macro_cells)
+    off = W.offsets(lv)
+    assert np.abs(u[bnd]).max() == 0.0
+    for i in np.flatnonzero(bnd):
+        assert np.abs(v[off[i]:off[i + 1]]).max() == 0.0
+
+
+def test_error_paths():
+    from paper_2103_17040_amd import tsm
+    NM = 2
+    lv = np.full(9, 8, np.int32)
+    with pytest.raises(tsm.TsmError) as e:
+        gpu_for(NM, lv, np.full(9, 1.5))
+    assert e.value.status == tsm.TSM_EGEOM
+    bad = np.zeros(9); bad[3] = np.nan
+    with pytest.raises(tsm.TsmError) as e:
+        gpu_for(NM, lv, bad)
+    assert e.value.status == tsm.TSM_EINVAL
+    with pytest.raises(tsm.TsmError) as e:
+        gpu_for(NM, np.full(9, 65, np.int32), np.zeros(9))
+    assert e.value.status == tsm.TSM_EINVAL
+    g = gpu_for(NM, lv, np.full(9, 0.2), max_iter=2)
+    try:
+        with pytest.raises(tsm.TsmError) as e:
+            g.step(1)
+        assert e.value.status == tsm.TSM_ESTATE
+        g.set_state(W.initial_macro(NM), np.random.default_rng(0).uniform(0, 1, g.n_micro))
+        st = g.step(1, allow_noconv=True)
+        assert st == tsm.TSM_ENOCONV
+        assert g.stats()["unconverged"] > 0
+    finally:
+        g.close()
