@@ -1,0 +1,204 @@
+"""Benchmark of the two-scale micro batch on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one implicit-Euler time step of the whole hot path: every micro
+solve of the batch (FP32 PCG inside FP64 refinement, or plain FP64), the
+Robin flux averages, the macro coupling solve and the state update, replayed
+as one captured hipGraph.  Inputs are synthetic and seeded (module
+workloads); they are resident in HBM before the timed region starts.
+
+Prints one JSON line.  `value` is micro DoF-updates/s of the FP32+refinement
+form (sum over instances of (N_i+1)^2 per step); the plain FP64 form on the
+same workload and tolerance is timed beside it, the dominant kernel's
+duration is measured with HIP events on the library's stream for the
+roofline, and the FP64 oracle is timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+# FP64 FMA and non-packed FP32 FMA issue at 64 lanes per clock per CU on
+# gfx950: 256 CUs * 2.4 GHz * 64 FMA * 2 flop = 78.6 TFLOP/s for either type
+# (packed FP32, which would double FP32, is not used).
+PEAK_ALU_TFLOPS = 78.6
+
+# Algorithmic work per micro DoF-update of the micro kernel.
+# Flops: per PCG iteration 9-point stencil (9 FMA), p.q, x/d update, r update,
+# z = D^{-1} r, r.z, r.r, p update = 15 FMA + 1 MUL = 31 flops; per FP64
+# residual sweep 9 FMA + 1 SUB + 1 FMA (norm) + 1 FMA (x += ||r|| d) = 23 flops;
+# per solve M x0/dt, b^T x, x0 = X0 + u w = 23 flops.
+FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 23.0, 23.0
+# Bytes that the instance-resident kernel must move per DoF per step: the
+# FP64 mass stencil (9 x 8), the FP64 operator stencil per FP64 residual
+# sweep (9 x 8), the FP32 operator stencil once (9 x 4; FP64 form: the FP64
+# stencil once), and the state: read v0 and w, write v0, read b (4 x 8).
+B_MASS, B_S64, B_S32, B_STATE = 72.0, 72.0, 36.0, 32.0
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_form(w, a, th, lv, precision, steps, warmup, rtol):
+    import torch
+    from paper_2103_17040_amd import TwoScaleBatch, tsm
+    g = TwoScaleBatch(w.macro_cells, lv, a, th, D=w.D, d=w.d, kappa=w.kappa, p=w.p, dt=w.dt,
+                      sigma=w.sigma, precision=precision, rtol=rtol)
+    try:
+        setup_ms = g.stats()["setup_ms"]
+        u0 = W.initial_macro(w.macro_cells)
+        g.set_state(u0, None)
+        g.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st = g.stats()
+        # roofline pass: same steps, direct launches bracketed by HIP events
+        g.set_flags(tsm.TSM_FLAG_TIMING)
+        g.step(steps)
+        tst = g.stats()
+        g.set_flags(0)
+        return {"t": t, "setup_ms": setup_ms, "stats": st, "timing": tst, "n_dofs": g.n_micro}
+    finally:
+        g.close()
+
+
+def cpu_baseline(w, a, th, lv, seconds_hint=15.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    a macro mesh of S cells per side (so (S+1)^2 instances) with the
+    workload's micro mesh, dt and first (S+1)^2 amplitudes, stepped K times.
+    BLAS/LAPACK threads are limited to one; the oracle itself is serial."""
+    from threadpoolctl import threadpool_limits
+    from oracle import twoscale
+    S = 7
+    ninst = (S + 1) ** 2
+    lvl = np.resize(lv, ninst)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ts = twoscale.TwoScale(twoscale.Params(S, w.dt, w.D, w.d, w.kappa, w.p, w.sigma), lvl,
+                               a[:ninst], None if th is None else th[:ninst])
+        t_setup = time.perf_counter() - t0
+        u = W.initial_macro(S)
+        v = np.zeros(int(ts.offsets[-1]))
+        K = 0
+        t0 = time.perf_counter()
+        while True:
+            u, v, _ = ts.step(u, v)
+            K += 1
+            if time.perf_counter() - t0 > seconds_hint or K >= 200:
+                break
+        t = time.perf_counter() - t0
+    dofs = int(ts.offsets[-1])
+    return {"value": dofs * K / t, "unit": "micro DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{ninst} instances ({S}x{S} macro cells) of the workload's micro meshes, "
+                      f"{K} implicit-Euler steps, banded-Cholesky micro solves factored once "
+                      f"(setup {t_setup:.1f} s excluded, as for the GPU value)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large_mixed", choices=sorted(W.WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the batch shards by instance "
+              "with one allgather of per-instance scalars per step, which is not built here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w, a, th, lv = W.make(args.workload, args.seed)
+    refine = w.precision == "fp32_refine"
+    _log(f"workload {w.name}: {w.n_inst} instances, levels {sorted(set(lv.tolist()))}, "
+         f"{int(W.offsets(lv)[-1])} micro DoFs, precision {w.precision}, rtol {w.rtol}")
+
+    main_form = run_form(w, a, th, lv, w.precision, args.steps, args.warmup, w.rtol)
+    _log(f"main form done: {main_form['t']:.3f} s for {args.steps} steps; stats {main_form['stats']}")
+    fp64 = None
+    if refine and not args.no_fp64:
+        fp64 = run_form(w, a, th, lv, "fp64", args.steps, args.warmup, w.rtol)
+        _log(f"fp64 form done: {fp64['t']:.3f} s; stats {fp64['stats']}")
+
+    n_dofs = main_form["n_dofs"]
+    K = args.steps
+    value = n_dofs * K / main_form["t"]
+
+    # roofline of the dominant kernel (the micro solve), per launch
+    tst = main_form["timing"]
+    launches = tst["timed_steps"] * tst["micro_launches"]
+    micro_ms_per_launch = tst["micro_ms"] / max(launches, 1)
+    st = main_form["stats"]
+    iters = st["iters_mean"]
+    sweeps = st["sweeps_max"] if refine else 0
+    dofs_per_launch = n_dofs / max(tst["micro_launches"], 1)
+    flops = dofs_per_launch * (FLOP_ITER * iters + FLOP_SWEEP * sweeps + FLOP_SOLVE)
+    if refine:
+        nbytes = dofs_per_launch * (B_MASS + B_S64 * sweeps + B_S32 + B_STATE)
+    else:
+        nbytes = dofs_per_launch * (B_MASS + B_S64 + B_STATE)
+    t_launch = micro_ms_per_launch * 1e-3
+    alu = flops / t_launch / 1e12
+    hbm = nbytes / t_launch / 1e9
+    if alu / PEAK_ALU_TFLOPS >= hbm / PEAK_HBM_GBS:
+        roof = {"bound": "alu", "achieved": alu, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": alu / PEAK_ALU_TFLOPS, "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": hbm / PEAK_HBM_GBS, "traffic": None}
+    roof.update({"kernel": "micro_kernel", "launch_ms": micro_ms_per_launch,
+                 "hbm_model_GBs": hbm, "alu_model_TFLOPs": alu})
+
+    out = {
+        "metric": "micro DoF-updates/s (batched FP32+refine vs plain FP64) at 1e-8 rel; adjoint/fwd",
+        "value": value,
+        "unit": "micro DoF-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": main_form["t"] / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if refine else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "instances": w.n_inst, "micro_levels": sorted(set(lv.tolist())),
+                   "micro_dofs": n_dofs, "dt": w.dt, "rtol": w.rtol, "precision": w.precision,
+                   "seed": args.seed},
+        "iters_mean": iters, "iters_max": st["iters_max"], "sweeps_max": st["sweeps_max"],
+        "setup_ms": main_form["setup_ms"],
+        "macro_ms_per_step": tst["macro_ms"] / max(tst["timed_steps"], 1),
+        "roofline": roof,
+    }
+    if fp64 is not None:
+        v64 = n_dofs * K / fp64["t"]
+        out["fp64_value"] = v64
+        out["fp32_refine_speedup_vs_fp64"] = value / v64
+        out["fp64_iters_mean"] = fp64["stats"]["iters_mean"]
+    if not args.no_cpu_baseline:
+        _log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(w, a, th, lv)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

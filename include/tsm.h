@@ -63,6 +63,10 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
 /* flags */
 #define TSM_FLAG_NO_GRAPH   (1ull << 0)  /* launch kernels directly instead of a captured hipGraph */
 #define TSM_FLAG_STENCIL_STREAM (1ull << 1) /* force the streamed-stencil micro kernels */
+#define TSM_FLAG_GENERIC    (1ull << 3)  /* solve every mesh size with the one-instance-per-workgroup
+                                            kernels (no packed kernels for 16/32/64 cells) */
+#define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
+                                            HIP events on the context's stream (see tsm_stats) */
 
 typedef struct {
     int32_t macro_cells;     /* N_M >= 2: macro Q1 cells per side on [0,1]^2 */
@@ -93,7 +97,11 @@ typedef struct {
     int32_t macro_sweeps;        /* tensor-preconditioned macro sweeps per solve */
     double macro_contraction;    /* bound on the macro sweep contraction factor */
     double setup_ms;             /* last set_deformation */
-    double step_ms;              /* last tsm_step call, wall on the stream */
+    double step_ms;              /* last tsm_step call, between events on the stream */
+    double micro_ms;             /* TSM_FLAG_TIMING: micro-solve phase, summed over the last tsm_step */
+    double macro_ms;             /* TSM_FLAG_TIMING: macro solve + fluxes, summed likewise */
+    int32_t timed_steps;         /* steps covered by micro_ms / macro_ms */
+    int32_t micro_launches;      /* micro kernel launches per step (one per mesh-size class) */
 } tsm_stats;
 
 typedef struct tsm_ctx tsm_ctx;
@@ -155,6 +163,10 @@ tsm_status tsm_apply_operator(tsm_ctx* c, const double* x, double* y);
  * adjoint backwards.  J_out is a host pointer, dJda_out a device pointer
  * (n_inst).  The current state is left unchanged. */
 tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda_out);
+
+/* Replace the launch flags (TSM_FLAG_*) of a context; rebuilds the step
+ * graph if set_deformation has run.  Results do not depend on the flags. */
+tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags);
 
 tsm_status tsm_get_stats(const tsm_ctx* c, tsm_stats* s);
 const char* tsm_last_error(const tsm_ctx* c);

@@ -98,6 +98,9 @@ class TwoScaleBatch:
         J = tsm.tsm_gradient(self.ctx, n_steps, g)
         return J, g
 
+    def set_flags(self, flags):
+        tsm.tsm_set_flags(self.ctx, flags)
+
     def stats(self):
         return tsm.tsm_get_stats(self.ctx)
 

@@ -1,6 +1,7 @@
 // Host runtime of libtsm: validation, device buffers, setup, the per-step
 // launch sequence (captured once in a hipGraph and replayed), outputs.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -56,7 +57,10 @@ struct tsm_ctx {
     std::vector<int32_t> level_h;
     std::vector<int64_t> off_h;
     std::vector<int32_t> order_h;
-    std::vector<Group> groups;
+    std::vector<Group> groups;        // generic kernels: one launch per slot class
+    int n_packs = 0;                  // packed kernels: one launch per mesh size
+    std::vector<std::array<int, 3>> pack_groups;   // (level, first pack, pack count)
+    int32_t *pk_first = nullptr, *pk_count = nullptr;
 
     // per instance
     int32_t *level = nullptr, *order = nullptr, *iters = nullptr, *sweeps = nullptr, *counters = nullptr;
@@ -78,7 +82,9 @@ struct tsm_ctx {
     hipGraphExec_t graph = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int64_t steps_taken = 0;
-    double setup_ms = 0.0, step_ms = 0.0;
+    double setup_ms = 0.0, step_ms = 0.0, micro_ms = 0.0, macro_ms = 0.0;
+    int timed_steps = 0;
+    std::vector<hipEvent_t> tev;   // TSM_FLAG_TIMING: 3 events per step
 
     tsm_status fail(tsm_status s, const std::string& m) {
         err = m;
@@ -89,6 +95,7 @@ struct tsm_ctx {
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32);
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
+        dfree(pk_first); dfree(pk_count);
         drop_graph();
         have_mesh = have_geom = have_state = false;
     }
@@ -130,8 +137,17 @@ struct tsm_ctx {
 
 namespace {
 
-// One batched micro solve over every group.
+// One batched micro solve: the packed launch (16/32/64 cells) and one
+// generic launch per remaining slot class.  setup: FP64 whatever the precision.
 tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
+    const bool refine = c->prm.precision == TSM_FP32_REFINE && !setup;
+    for (const auto& pg : c->pack_groups) {
+        PackList pl{pg[2], c->pk_first + pg[1], c->pk_count + pg[1]};
+        MicroArgs a = base;
+        a.n_tasks = (int)c->n_inst;
+        a.order = c->order;
+        HIPCHK(launch_packed(a, pl, pg[0], refine ? 2 : 1, pg[2], c->stream));
+    }
     for (const Group& g : c->groups) {
         MicroArgs a = base;
         a.n_tasks = g.count;
@@ -143,6 +159,65 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
         const size_t lds = n_pad * (sizeof(double) + sizeof(float));
         HIPCHK(launch_micro(a, g.slots, mode, g.count, lds, c->stream));
     }
+    return TSM_OK;
+}
+
+// Task order, packs and generic groups for the current mesh and flags.
+tsm_status plan_tasks(tsm_ctx* c) {
+    const int64_t n_inst = c->n_inst;
+    const bool use_packs = !(c->prm.flags & TSM_FLAG_GENERIC);
+    auto packable = [&](int32_t i) { return use_packs && packed_capacity(c->level_h[i]) > 0; };
+    c->order_h.resize(n_inst);
+    for (int64_t i = 0; i < n_inst; ++i) c->order_h[i] = (int32_t)i;
+    // packable instances first, then by descending mesh size (largest first), stable
+    std::stable_sort(c->order_h.begin(), c->order_h.end(), [&](int32_t x, int32_t y) {
+        const bool px = packable(x), py = packable(y);
+        if (px != py) return px;
+        return c->level_h[x] > c->level_h[y];
+    });
+    std::vector<int32_t> pf, pc;
+    int64_t t = 0;
+    c->pack_groups.clear();
+    while (t < n_inst && packable(c->order_h[t])) {
+        const int lvl = c->level_h[c->order_h[t]];
+        const int cap = packed_capacity(lvl);
+        int cnt = 0;
+        while (t + cnt < n_inst && cnt < cap && packable(c->order_h[t + cnt]) && c->level_h[c->order_h[t + cnt]] == lvl)
+            ++cnt;
+        if (c->pack_groups.empty() || c->pack_groups.back()[0] != lvl)
+            c->pack_groups.push_back({lvl, (int)pf.size(), 0});
+        c->pack_groups.back()[2]++;
+        pf.push_back((int32_t)t);
+        pc.push_back(cnt);
+        t += cnt;
+    }
+    c->n_packs = (int)pf.size();
+    c->groups.clear();
+    const bool refine = c->prm.precision == TSM_FP32_REFINE;
+    const bool stream_all = (c->prm.flags & TSM_FLAG_STENCIL_STREAM) != 0;
+    for (; t < n_inst; ++t) {
+        const int lvl = c->level_h[c->order_h[t]];
+        const int sl = slots_for((lvl + 1) * (lvl + 1));
+        if (c->groups.empty() || c->groups.back().slots != sl) {
+            Group g;
+            g.first = (int)t;
+            g.count = 0;
+            g.slots = sl;
+            const bool resident = !stream_all && (refine ? sl <= 9 : sl <= 5);
+            g.mode = (refine ? 2 : 0) + (resident ? 0 : 1);
+            g.max_level = lvl;
+            c->groups.push_back(g);
+        }
+        c->groups.back().count++;
+    }
+    dfree(c->pk_first); dfree(c->pk_count);
+    if (c->n_packs > 0) {
+        HIPALLOC(c->pk_first, c->n_packs); HIPALLOC(c->pk_count, c->n_packs);
+        HIPCHK(hipMemcpy(c->pk_first, pf.data(), pf.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->pk_count, pc.data(), pc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    if (!c->order) HIPALLOC(c->order, n_inst);
+    HIPCHK(hipMemcpy(c->order, c->order_h.data(), n_inst * sizeof(int32_t), hipMemcpyHostToDevice));
     return TSM_OK;
 }
 
@@ -183,7 +258,9 @@ tsm_status enqueue_macro_solve(tsm_ctx* c, double* u) {
 }
 
 // One forward step: micro solves (state v = v0 + u w in place), macro solve, fluxes.
-tsm_status enqueue_step(tsm_ctx* c) {
+// ev (optional, 3 events) brackets the micro and macro phases.
+tsm_status enqueue_step(tsm_ctx* c, const hipEvent_t* ev = nullptr) {
+    if (ev) HIPCHK(hipEventRecord(ev[0], c->stream));
     MicroArgs a = micro_base(c);
     a.X0 = c->v0;
     a.coef = c->u;
@@ -192,17 +269,19 @@ tsm_status enqueue_step(tsm_ctx* c) {
     a.X_out = c->v0;
     tsm_status st = enqueue_micro(c, a, false);
     if (st != TSM_OK) return st;
+    if (ev) HIPCHK(hipEventRecord(ev[1], c->stream));
     const MacroArgs m = c->macro_args();
     HIPCHK(launch_macro_rhs_forward(m, c->u, c->bx, c->rhs, c->alpha, c->stream));
     st = enqueue_macro_solve(c, c->u);
     if (st != TSM_OK) return st;
     HIPCHK(launch_macro_finalize(m, c->u, c->alpha, c->F, c->stream));
+    if (ev) HIPCHK(hipEventRecord(ev[2], c->stream));
     return TSM_OK;
 }
 
 tsm_status build_graph(tsm_ctx* c) {
     c->drop_graph();
-    if (c->prm.flags & TSM_FLAG_NO_GRAPH) return TSM_OK;
+    if (c->prm.flags & (TSM_FLAG_NO_GRAPH | TSM_FLAG_TIMING)) return TSM_OK;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     tsm_status st = enqueue_step(c);
     hipGraph_t g = nullptr;
@@ -299,30 +378,6 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     for (int64_t i = 0; i < n_inst; ++i) c->off_h[i + 1] = c->off_h[i] + (int64_t)(micro_cells[i] + 1) * (micro_cells[i] + 1);
     c->total = c->off_h[n_inst];
 
-    // task order: descending mesh size (largest first), stable in instance index
-    c->order_h.resize(n_inst);
-    for (int64_t i = 0; i < n_inst; ++i) c->order_h[i] = (int32_t)i;
-    std::stable_sort(c->order_h.begin(), c->order_h.end(),
-                     [&](int32_t x, int32_t y) { return c->level_h[x] > c->level_h[y]; });
-    c->groups.clear();
-    const bool refine = c->prm.precision == TSM_FP32_REFINE;
-    const bool stream_all = (c->prm.flags & TSM_FLAG_STENCIL_STREAM) != 0;
-    for (int64_t t = 0; t < n_inst; ++t) {
-        const int lvl = c->level_h[c->order_h[t]];
-        const int sl = slots_for((lvl + 1) * (lvl + 1));
-        if (c->groups.empty() || c->groups.back().slots != sl) {
-            Group g;
-            g.first = (int)t;
-            g.count = 0;
-            g.slots = sl;
-            const bool resident = !stream_all && (refine ? sl <= 9 : sl <= 5);
-            g.mode = (refine ? 2 : 0) + (resident ? 0 : 1);
-            g.max_level = lvl;
-            c->groups.push_back(g);
-        }
-        c->groups.back().count++;
-    }
-
     // level tables
     std::vector<int32_t> toff(kMaxLevel + 1, 0);
     std::vector<double> ty, ts, tc;
@@ -344,7 +399,7 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     }
 
     const int64_t ni = n_inst, tot = c->total;
-    HIPALLOC(c->level, ni); HIPALLOC(c->order, ni); HIPALLOC(c->iters, ni); HIPALLOC(c->sweeps, ni);
+    HIPALLOC(c->level, ni); HIPALLOC(c->iters, ni); HIPALLOC(c->sweeps, ni);
     HIPALLOC(c->offsets, ni + 1);
     HIPALLOC(c->amp, ni); HIPALLOC(c->beta, ni); HIPALLOC(c->len, ni); HIPALLOC(c->jmin, ni);
     HIPALLOC(c->bx, ni); HIPALLOC(c->alpha, ni); HIPALLOC(c->F, ni); HIPALLOC(c->u, ni);
@@ -353,7 +408,6 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());
     HIPCHK(hipMemcpy(c->level, c->level_h.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->order, c->order_h.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->offsets, c->off_h.data(), (ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->tab_off, toff.data(), toff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->tab_y, ty.data(), ty.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -363,6 +417,10 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPCHK(hipMemset(c->F, 0, ni * sizeof(double)));
     HIPCHK(hipMemset(c->v0, 0, tot * sizeof(double)));
 
+    {
+        tsm_status ps = plan_tasks(c);
+        if (ps != TSM_OK) return ps;
+    }
     const int n = c->NM - 1;
     HIPALLOC(c->rhs, (size_t)n * n); HIPALLOC(c->R, (size_t)n * n); HIPALLOC(c->T1, (size_t)n * n);
     HIPALLOC(c->T2, (size_t)n * n); HIPALLOC(c->Q, (size_t)n * n); HIPALLOC(c->lam, (size_t)n * n);
@@ -507,13 +565,21 @@ tsm_status tsm_step(tsm_ctx* c, int32_t n_steps) {
     if (!c) return TSM_EINVAL;
     if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
     if (n_steps < 0) return c->fail(TSM_EINVAL, "n_steps < 0");
+    const bool timing = (c->prm.flags & TSM_FLAG_TIMING) != 0;
+    if (timing) {
+        while ((int)c->tev.size() < 3 * n_steps) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            c->tev.push_back(e);
+        }
+    }
     HIPCHK(hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->stream));
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     for (int s = 0; s < n_steps; ++s) {
         if (c->graph) {
             HIPCHK(hipGraphLaunch(c->graph, c->stream));
         } else {
-            tsm_status st = enqueue_step(c);
+            tsm_status st = enqueue_step(c, timing ? &c->tev[3 * s] : nullptr);
             if (st != TSM_OK) return st;
         }
     }
@@ -524,6 +590,18 @@ tsm_status tsm_step(tsm_ctx* c, int32_t n_steps) {
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->step_ms = ms;
+    c->micro_ms = c->macro_ms = 0.0;
+    c->timed_steps = 0;
+    if (timing) {
+        for (int s = 0; s < n_steps; ++s) {
+            float a = 0.0f, b = 0.0f;
+            HIPCHK(hipEventElapsedTime(&a, c->tev[3 * s], c->tev[3 * s + 1]));
+            HIPCHK(hipEventElapsedTime(&b, c->tev[3 * s + 1], c->tev[3 * s + 2]));
+            c->micro_ms += a;
+            c->macro_ms += b;
+        }
+        c->timed_steps = n_steps;
+    }
     c->steps_taken += n_steps;
     if (nc > 0) return c->fail(TSM_ENOCONV, std::to_string(nc) + " micro solves missed rtol");
     return TSM_OK;
@@ -586,6 +664,19 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
     return c->fail(TSM_EINVAL, "gradient: not available in this build");
 }
 
+tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
+    if (!c) return TSM_EINVAL;
+    const bool replan = ((flags ^ c->prm.flags) & (TSM_FLAG_STENCIL_STREAM | TSM_FLAG_GENERIC)) != 0;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->prm.flags = flags;
+    if (replan && c->have_mesh) {
+        tsm_status st = plan_tasks(c);
+        if (st != TSM_OK) return st;
+    }
+    if (c->have_geom) return build_graph(c);
+    return TSM_OK;
+}
+
 tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
     tsm_ctx* c = const_cast<tsm_ctx*>(cc);
     if (!c || !s) return TSM_EINVAL;
@@ -597,6 +688,10 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
     s->macro_contraction = c->rho;
     s->setup_ms = c->setup_ms;
     s->step_ms = c->step_ms;
+    s->micro_ms = c->micro_ms;
+    s->macro_ms = c->macro_ms;
+    s->timed_steps = c->timed_steps;
+    s->micro_launches = (int32_t)(c->groups.size() + c->pack_groups.size());
     if (c->have_geom && c->n_inst > 0) {
         std::vector<int32_t> it(c->n_inst), sw(c->n_inst);
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -625,6 +720,7 @@ void tsm_destroy(tsm_ctx* c) {
     dfree(c->counters);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

@@ -8,7 +8,8 @@
 
 namespace tsm {
 
-constexpr int kMicroThreads = 256;        // lanes per micro workgroup (4 waves)
+constexpr int kMicroThreads = 256;        // lanes per micro workgroup (4 waves), generic kernels
+constexpr int kPackThreads = 1024;        // lanes per packed workgroup (16 waves)
 constexpr int kWave = 64;
 constexpr int kMaxLevel = 64;             // largest micro mesh N (cells per side)
 constexpr int kMinLevel = 2;
@@ -72,6 +73,13 @@ struct MicroArgs {
     int32_t* queue;       // persistent work counter (null: task = blockIdx.x)
 };
 
+// Packs of instances of one mesh size solved by one 1024-lane workgroup.
+struct PackList {
+    int n_packs;
+    const int32_t* first;   // first task (index into MicroArgs::order)
+    const int32_t* count;   // instances in the pack
+};
+
 struct MacroArgs {
     int NM;               // macro cells per side
     int n;                // interior nodes per side = NM - 1
@@ -86,6 +94,10 @@ struct MacroArgs {
 // launchers (return hipError_t of the launch)
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s);
 hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_t lds_bytes, hipStream_t s);
+// packs of one mesh size (16, 32 or 64); mode 1 FP64, 2 refinement
+hipError_t launch_packed(const MicroArgs& a, const PackList& p, int level, int mode, int grid, hipStream_t s);
+int packed_capacity(int level);          // instances per pack (0: no packed kernel for this size)
+size_t packed_lds_bytes(int level);      // dynamic LDS of one pack
 hipError_t launch_apply(int n_inst, const int32_t* level, const int64_t* offsets,
                         const double* S64, const double* x, double* y, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int n, hipStream_t s);

@@ -19,13 +19,15 @@ TSM_OK, TSM_EINVAL, TSM_EGEOM, TSM_ENOCONV, TSM_EHIP, TSM_ENOMEM, TSM_ESTATE = 0
 TSM_FP64, TSM_FP32_REFINE = 0, 1
 TSM_FLAG_NO_GRAPH = 1 << 0
 TSM_FLAG_STENCIL_STREAM = 1 << 1
+TSM_FLAG_TIMING = 1 << 2
+TSM_FLAG_GENERIC = 1 << 3
 
 STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV",
                 -4: "TSM_EHIP", -5: "TSM_ENOMEM", -6: "TSM_ESTATE"}
 
 EXPORTED = ["tsm_default_params", "tsm_create", "tsm_set_reference_mesh", "tsm_get_offsets",
             "tsm_set_deformation", "tsm_set_state", "tsm_step", "tsm_get_macro", "tsm_get_fluxes",
-            "tsm_get_micro", "tsm_get_setup", "tsm_apply_operator", "tsm_gradient", "tsm_get_stats",
+            "tsm_get_micro", "tsm_get_setup", "tsm_apply_operator", "tsm_gradient", "tsm_set_flags", "tsm_get_stats",
             "tsm_last_error", "tsm_destroy"]
 
 
@@ -43,7 +45,9 @@ class tsm_stats(ctypes.Structure):
                 ("iters_min", ctypes.c_int32), ("iters_max", ctypes.c_int32), ("iters_mean", ctypes.c_double),
                 ("sweeps_max", ctypes.c_int32), ("unconverged", ctypes.c_int32),
                 ("macro_sweeps", ctypes.c_int32), ("macro_contraction", ctypes.c_double),
-                ("setup_ms", ctypes.c_double), ("step_ms", ctypes.c_double)]
+                ("setup_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
+                ("micro_ms", ctypes.c_double), ("macro_ms", ctypes.c_double),
+                ("timed_steps", ctypes.c_int32), ("micro_launches", ctypes.c_int32)]
 
 
 class TsmError(RuntimeError):
@@ -72,6 +76,7 @@ def _load():
         "tsm_get_setup": (I32, [P, VP, VP, VP]),
         "tsm_apply_operator": (I32, [P, VP, VP]),
         "tsm_gradient": (I32, [P, I32, ctypes.POINTER(D), VP]),
+        "tsm_set_flags": (I32, [P, ctypes.c_uint64]),
         "tsm_get_stats": (I32, [P, ctypes.POINTER(tsm_stats)]),
         "tsm_last_error": (ctypes.c_char_p, [P]),
         "tsm_destroy": (None, [P]),
@@ -165,6 +170,10 @@ def tsm_gradient(ctx, n_steps: int, dJda_out) -> float:
     J = ctypes.c_double()
     _check(ctx, _lib.tsm_gradient(ctx, int(n_steps), ctypes.byref(J), _ptr(dJda_out)))
     return J.value
+
+
+def tsm_set_flags(ctx, flags: int) -> None:
+    _check(ctx, _lib.tsm_set_flags(ctx, int(flags)))
 
 
 def tsm_get_stats(ctx) -> dict:

@@ -97,24 +97,42 @@ def test_sign_plus_one_and_kappa_zero():
 
 
 def test_forms_agree_bitwise():
-    """Graph replay, direct launches and the streamed-stencil kernels compute
-    the same sums in the same order: outputs are bitwise identical, and two
-    runs are bitwise identical (deterministic: no atomics in any sum)."""
+    """Graph replay, direct launches, the timing form and the streamed-stencil
+    switch compute the same sums in the same order: outputs are bitwise
+    identical, and two runs are bitwise identical (no atomics in any sum)."""
     from paper_2103_17040_amd import tsm
-    w, a, th, lv, u0, v0, phys = workload_case("small_fp64")
+    lv, a, th = _ragged(5, [8, 16, 32, 64], 41)
+    u0 = W.initial_macro(5)
+    v0 = np.zeros(int(W.offsets(lv)[-1]))
     outs = []
-    for flags in (0, 0, tsm.TSM_FLAG_NO_GRAPH, tsm.TSM_FLAG_STENCIL_STREAM):
-        banner(f"forms flags={flags}")
-        g = gpu_for(w.macro_cells, lv, a, th, w.dt, flags=flags, **phys)
-        try:
-            g.set_state(u0, v0)
-            g.step(5)
-            outs.append((g.macro().cpu().numpy(), g.micro().cpu().numpy(), g.fluxes().cpu().numpy()))
-        finally:
-            g.close()
+    for prec in ("fp64", "fp32_refine"):
+        for flags in (0, 0, tsm.TSM_FLAG_NO_GRAPH, tsm.TSM_FLAG_STENCIL_STREAM, tsm.TSM_FLAG_TIMING):
+            banner(f"forms {prec} flags={flags}")
+            g = gpu_for(5, lv, a, th, 0.005, precision=prec, rtol=1e-10, flags=flags)
+            try:
+                g.set_state(u0, v0)
+                g.step(4)
+                outs.append((prec, g.macro().cpu().numpy(), g.micro().cpu().numpy(), g.fluxes().cpu().numpy()))
+            finally:
+                g.close()
     for o in outs[1:]:
-        for x, y in zip(outs[0], o):
+        ref = next(x for x in outs if x[0] == o[0])
+        for x, y in zip(ref[1:], o[1:]):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, TOL_FP64), ("fp32_refine", 1e-10, TOL_REFINE)])
+def test_generic_kernels_parity(precision, rtol, tol):
+    """The one-instance-per-workgroup kernels (forced for every mesh size)
+    against the oracle, on the sizes that otherwise go to the packed kernels."""
+    from paper_2103_17040_amd import tsm
+    lv, a, th = _ragged(4, [16, 32, 64], 43)
+    u0 = W.initial_macro(4)
+    v0 = np.random.default_rng(2).uniform(0, 1, int(W.offsets(lv)[-1]))
+    ref, out, _ = run_both(4, lv, a, th, 0.005, 3, u0, v0, precision=precision, rtol=rtol,
+                           gpu_kw={"flags": tsm.TSM_FLAG_GENERIC})
+    for k in ("u", "F", "v"):
+        assert rel(out[k], ref[k]) <= tol, k
 
 
 def test_boundary_instances_stay_zero():
