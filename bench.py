@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calib-bytes", type=int, default=0,
+                    help="first run a plain device copy of this many bytes (3 times), the reference "
+                         "for scaling HBM counters (FETCH_SIZE, WRITE_SIZE) in profiles")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the batch shards by instance "
@@ -127,6 +130,14 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_bytes > 0:
+        src = torch.ones(args.calib_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        _log(f"calibration copy: {args.calib_bytes} bytes read + written, 3 times")
+        del src, dst
     w, a, th, lv = W.make(args.workload, args.seed)
     refine = w.precision == "fp32_refine"
     _log(f"workload {w.name}: {w.n_inst} instances, levels {sorted(set(lv.tolist()))}, "

@@ -69,7 +69,7 @@ struct tsm_ctx {
            *alpha = nullptr, *F = nullptr, *u = nullptr;
     // ragged
     double *S64 = nullptr, *M64 = nullptr, *b = nullptr, *w = nullptr, *v0 = nullptr;
-    float* S32 = nullptr;
+    float *S32 = nullptr, *Slo = nullptr;
     // tables
     int32_t* tab_off = nullptr;
     double *tab_y = nullptr, *tab_s = nullptr, *tab_c = nullptr;
@@ -93,7 +93,7 @@ struct tsm_ctx {
     void free_mesh() {
         dfree(level); dfree(order); dfree(iters); dfree(sweeps); dfree(offsets);
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
-        dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32);
+        dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32); dfree(Slo);
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count);
         drop_graph();
@@ -227,6 +227,7 @@ MicroArgs micro_base(tsm_ctx* c) {
     a.offsets = c->offsets;
     a.S64 = c->S64;
     a.S32 = c->S32;
+    a.Slo = c->Slo;
     a.M64 = c->M64;
     a.b = c->b;
     a.w = c->w;
@@ -404,6 +405,7 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPALLOC(c->amp, ni); HIPALLOC(c->beta, ni); HIPALLOC(c->len, ni); HIPALLOC(c->jmin, ni);
     HIPALLOC(c->bx, ni); HIPALLOC(c->alpha, ni); HIPALLOC(c->F, ni); HIPALLOC(c->u, ni);
     HIPALLOC(c->S64, kStencil * tot); HIPALLOC(c->M64, kStencil * tot); HIPALLOC(c->S32, kStencil * tot);
+    HIPALLOC(c->Slo, kStencil * tot);
     HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot);
     HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());
@@ -460,7 +462,7 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
     as.d = c->prm.d;
     as.kappa = c->prm.kappa;
     as.inv_dt = 1.0 / c->prm.dt;
-    as.S64 = c->S64; as.S32 = c->S32; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
+    as.S64 = c->S64; as.S32 = c->S32; as.Slo = c->Slo; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
     HIPCHK(launch_assemble(as, c->stream));
     std::vector<double> jm(n_inst);
     HIPCHK(hipMemcpyAsync(jm.data(), c->jmin, n_inst * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -131,11 +131,14 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
         }
         double* Sd = A.S64 + kStencil * off;
         float* Sf = A.S32 + kStencil * off;
+        float* Sl = A.Slo + kStencil * off;
         double* Md = A.M64 + kStencil * off;
 #pragma unroll
         for (int k = 0; k < kStencil; ++k) {
             Sd[(int64_t)k * n + j] = S[k];
-            Sf[(int64_t)k * n + j] = (float)S[k];
+            const float hi = (float)S[k];
+            Sf[(int64_t)k * n + j] = hi;
+            Sl[(int64_t)k * n + j] = (float)(S[k] - (double)hi);
             Md[(int64_t)k * n + j] = M[k];
         }
         A.b[off + j] = bj;

@@ -16,13 +16,41 @@ __device__ __forceinline__ double gauss_x(int g) { return g ? kGX1 : kGX0; }
 // 1D linear basis on [0,1]: local node l at abscissa g
 __device__ __forceinline__ double lin(int l, int g) { return l ? gauss_x(g) : 1.0 - gauss_x(g); }
 
-// Butterfly reduction: every lane ends with the same bitwise value
-// (each stage adds two operands in either order, and IEEE addition commutes).
+// Wavefront sum with DPP lane permutations (no LDS traffic):
+//   quad_perm [1,0,3,2], quad_perm [2,3,0,1]  -> every lane holds its quad sum
+//   row_half_mirror, row_mirror               -> every lane holds its 16-lane row sum
+// then the four row sums are read as scalars and added in a fixed order.
+// Every lane returns the same bits: each step adds two operands whose order
+// differs between partner lanes only, and IEEE addition commutes.
+// All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ float lane_read(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);   // row_half_mirror
+    v += dpp<0x140>(v);   // row_mirror
+    return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
 // Sum of NV values over a workgroup of NW waves.  red is a [2][NV][NW] LDS

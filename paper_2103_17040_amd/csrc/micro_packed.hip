@@ -138,67 +138,109 @@ __device__ __forceinline__ void zero_halo(T* g, const Lane& z) {
     }
 }
 
-// Stencil source: registers (S[i][k]) or global memory (wave-uniform base,
-// coefficient-major [k][n]).
+// Stencil sources.  A source gives, for row i of the lane's strip and
+// coefficient k, a raw value (load) and the coefficient (value):
+//   RegStencil     FP32 stencil resident in registers
+//   GlobalStencil  stencil in global memory, coefficient-major [k][n]
+//   SplitStencil   FP64 operator as resident FP32 part + streamed FP32 low
+//                  part: S32 + Slo spans at most 48 significant bits, so the
+//                  FP64 sum is exact and equals S to about 2^-48 relative.
 template <class L, typename TS>
 struct RegStencil {
     static constexpr bool kGlobal = false;
+    using raw_t = TS;
     const TS (&S)[L::R][kStencil];
-    __device__ __forceinline__ TS at(const Lane&, int i, int k) const { return S[i][k]; }
+    __device__ __forceinline__ TS load(const Lane&, int i, int k) const { return S[i][k]; }
+    __device__ __forceinline__ TS value(int, int, TS raw) const { return raw; }
 };
-// The base pointer is passed through an empty asm at every use site so the
-// compiler cannot hoist the (loop-invariant) coefficient loads out of the
-// solver loops and keep them live across them.
+
+// The base pointer of a streamed stencil passes through an empty asm at
+// every use, so the compiler cannot hoist the loop-invariant coefficient
+// loads out of the solver loops and keep them live across them.
 template <typename T>
 __device__ __forceinline__ const T* opaque(const T* p) {
     asm volatile("" : "+s"(p));
     return p;
 }
 
+// wave-uniform base + zero-extended 32-bit byte offset (scalar-base
+// addressing); rows past the mesh read the last mesh row, in bounds, and
+// their results are discarded
+template <class L, typename T>
+__device__ __forceinline__ T stencil_load(const T* base, const Lane& z, int i, int k) {
+    const int row = min(z.r0 + i, L::NP - 1);
+    const uint32_t byte = (uint32_t)(k * L::n + row * L::NP + z.col) * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte);
+}
+
 template <class L, typename TS>
 struct GlobalStencil {
     static constexpr bool kGlobal = true;
+    using raw_t = TS;
     const TS* __restrict__ base;
-    __device__ __forceinline__ TS at(const Lane& z, int i, int k) const {
-        // uniform base + zero-extended 32-bit byte offset: scalar-base addressing
-        const uint32_t byte = (uint32_t)(k * L::n + node_of<L>(z, i)) * (uint32_t)sizeof(TS);
-        return *reinterpret_cast<const TS*>(reinterpret_cast<const char*>(base) + byte);
-    }
+    __device__ __forceinline__ TS load(const Lane& z, int i, int k) const { return stencil_load<L>(base, z, i, k); }
+    __device__ __forceinline__ TS value(int, int, TS raw) const { return raw; }
+    __device__ __forceinline__ TS at(const Lane& z, int i, int k) const { return load(z, i, k); }
+};
+
+template <class L>
+struct SplitStencil {
+    static constexpr bool kGlobal = true;
+    using raw_t = float;
+    const float (&S)[L::R][kStencil];
+    const float* __restrict__ base;   // Slo
+    __device__ __forceinline__ float load(const Lane& z, int i, int k) const { return stencil_load<L>(base, z, i, k); }
+    __device__ __forceinline__ double value(int i, int k, float raw) const { return (double)S[i][k] + (double)raw; }
 };
 
 // y_i = sum_k S_ik g(row r0+i + dr, col + dc) in k order 0..8, one product
-// at a time; own-column values come from mine[].  Active lanes only.
-template <class L, typename TA, typename TG, class ST>
+// at a time; own-column values come from mine[].  Streamed coefficients are
+// loaded B rows at a time, all loads of a batch in flight before the first
+// use (scheduling barriers keep the batches apart without draining memory).
+// Rows past the mesh give 0.  Active lanes only.
+template <class L, int B, typename TA, typename TG, class ST>
 __device__ __forceinline__ void strip_apply(const ST& S0, const TG* g, const Lane& z,
                                             const TG (&mine)[L::R], TA (&y)[L::R]) {
     ST S = S0;
     if constexpr (ST::kGlobal) S.base = opaque(S.base);
     constexpr int W2 = L::W2;
     const int base = (z.r0 + 1) * W2 + (z.col + 1);
-    TG l0 = g[base - W2 - 1], r0 = g[base - W2 + 1];
-    TG l1 = g[base - 1], r1 = g[base + 1];
-    const TG up = g[base - W2];
+    TG lf[L::R + 2], rt[L::R + 2];
 #pragma unroll
-    for (int i = 0; i < L::R; ++i) {
-        asm volatile("" ::: "memory");   // one row of loads in flight (register budget)
-        const TG l2 = g[base + (i + 1) * W2 - 1];
-        const TG r2 = g[base + (i + 1) * W2 + 1];
-        const TG cm = (i == 0) ? up : mine[i - 1];
-        const TG cp = (i == L::R - 1) ? g[base + L::R * W2] : mine[i + 1];
-        TA t = TA(0);
-        if (z.r0 + i < L::NP) {
-            t += TA(S.at(z, i, 0)) * TA(l0);
-            t += TA(S.at(z, i, 1)) * TA(cm);
-            t += TA(S.at(z, i, 2)) * TA(r0);
-            t += TA(S.at(z, i, 3)) * TA(l1);
-            t += TA(S.at(z, i, 4)) * TA(mine[i]);
-            t += TA(S.at(z, i, 5)) * TA(r1);
-            t += TA(S.at(z, i, 6)) * TA(l2);
-            t += TA(S.at(z, i, 7)) * TA(cp);
-            t += TA(S.at(z, i, 8)) * TA(r2);
+    for (int i = 0; i < L::R + 2; ++i) {
+        lf[i] = g[base + (i - 1) * W2 - 1];
+        rt[i] = g[base + (i - 1) * W2 + 1];
+    }
+    const TG up = g[base - W2];
+    const TG dn = g[base + L::R * W2];
+#pragma unroll
+    for (int i0 = 0; i0 < L::R; i0 += B) {
+        typename ST::raw_t c[B][kStencil];
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int k = 0; k < kStencil; ++k)
+                if (i0 + b < L::R) c[b][k] = S.load(z, i0 + b, k);
+        if constexpr (ST::kGlobal) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = i0 + b;
+            if (i >= L::R) break;
+            const TG cm = (i == 0) ? up : mine[i - 1];
+            const TG cp = (i == L::R - 1) ? dn : mine[i + 1];
+            TA t = TA(0);
+            t += TA(S.value(i, 0, c[b][0])) * TA(lf[i]);
+            t += TA(S.value(i, 1, c[b][1])) * TA(cm);
+            t += TA(S.value(i, 2, c[b][2])) * TA(rt[i]);
+            t += TA(S.value(i, 3, c[b][3])) * TA(lf[i + 1]);
+            t += TA(S.value(i, 4, c[b][4])) * TA(mine[i]);
+            t += TA(S.value(i, 5, c[b][5])) * TA(rt[i + 1]);
+            t += TA(S.value(i, 6, c[b][6])) * TA(lf[i + 2]);
+            t += TA(S.value(i, 7, c[b][7])) * TA(cp);
+            t += TA(S.value(i, 8, c[b][8])) * TA(rt[i + 2]);
+            y[i] = (z.r0 + i < L::NP) ? t : TA(0);
         }
-        y[i] = t;
-        l0 = l1; l1 = l2; r0 = r1; r1 = r2;
+        if constexpr (ST::kGlobal) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -249,11 +291,11 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
         for (int i = 0; i < L::R; ++i)
             b[i] = row_ok<L>(z, i) ? A.rhs_scale * A.rhs_vec[z.off + node_of<L>(z, i)] : 0.0;
     } else if (z.act) {
-        strip_apply<L>(GlobalStencil<L, double>{A.M64 + kStencil * z.off}, xg, z, x, b);
+        strip_apply<L, 3>(GlobalStencil<L, double>{A.M64 + kStencil * z.off}, xg, z, x, b);
 #pragma unroll
         for (int i = 0; i < L::R; ++i) b[i] *= A.inv_dt;
     }
-    if (z.act) strip_apply<L>(GlobalStencil<L, double>{A.S64 + kStencil * z.off}, xg, z, x, sx);
+    if (z.act) strip_apply<L, 3>(GlobalStencil<L, double>{A.S64 + kStencil * z.off}, xg, z, x, sx);
     bb = 0.0;
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
@@ -305,7 +347,7 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
         double q[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) q[i] = 0.0;
-        if (z.act) strip_apply<L>(S, xg, z, p, q);
+        if (z.act) strip_apply<L, 2>(S, xg, z, p, q);
         double pq[1] = {0.0};
 #pragma unroll
         for (int i = 0; i < L::R; ++i) pq[0] += p[i] * q[i];
@@ -344,27 +386,33 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
     const Lane z = lane_of<L>(A, first, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     float* pg = reinterpret_cast<float*>(xg);
-    const GlobalStencil<L, double> S64{A.S64 + kStencil * z.off};
     double x[L::R], r64[L::R];
     double bb;
     pack_start<L>(A, z, xg, x, r64, bb);
     float S[L::R][kStencil], dinv[L::R];
     {
-        const GlobalStencil<L, float> Sf{A.S32 + kStencil * z.off};
+        // branch-free: every row's loads in flight at once (rows past the
+        // mesh read in bounds and are zeroed)
+        const float* Sf = A.S32 + kStencil * z.off;
+#pragma unroll
+        for (int i = 0; i < L::R; ++i)
+#pragma unroll
+            for (int k = 0; k < kStencil; ++k) S[i][k] = stencil_load<L>(Sf, z, i, k);
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
+            const bool ok = row_ok<L>(z, i);
 #pragma unroll
-            for (int k = 0; k < kStencil; ++k) S[i][k] = row_ok<L>(z, i) ? Sf.at(z, i, k) : 0.0f;
-            dinv[i] = row_ok<L>(z, i) ? 1.0f / S[i][4] : 0.0f;
+            for (int k = 0; k < kStencil; ++k) S[i][k] = ok ? S[i][k] : 0.0f;
+            dinv[i] = ok ? 1.0f / S[i][4] : 0.0f;
         }
     }
     const RegStencil<L, float> SR{S};
+    const SplitStencil<L> S64{S, A.Slo + kStencil * z.off};
     double acc[3] = {bb, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < L::R; ++i) acc[2] += r64[i] * r64[i];
     red3.sum(acc, z.w0, L::WPI);
     __shared__ double otol_s[L::IPP];
-    __shared__ float itol_s[L::IPP];
     const double tol2 = A.rtol * A.rtol * acc[0];
     if (z.live && z.lt == 0) otol_s[z.sub] = tol2;
     double rr = acc[2];
@@ -378,70 +426,71 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
         return any;
     };
     while (outer_any() && sweeps <= A.max_refine) {
-        // inner FP32 solve of S d = r / ||r|| (converged instances sit out)
+        // Inner FP32 solve of S d = r / ||r|| by the Chronopoulos-Gear form of
+        // PCG: s = S p is carried by a recurrence, so each iteration needs one
+        // operator application (w = S u, u = D^{-1} r) and ONE fused reduction
+        // of (r,u), (w,u), (r,r); two barriers per iteration.  The normalised
+        // residual starts at ||r|| = 1, so the inner stopping test is
+        // (r,r) <= inner_rtol^2 for every instance; outer-converged instances
+        // enter with r = 0 and sit out.
         const bool me = !conv;
         const double rn = sqrt(rr);
         const double isc = me ? 1.0 / rn : 0.0;
-        float r[L::R], d[L::R], p[L::R];
-        float f3[3] = {0.0f, 0.0f, 0.0f};
+        float r[L::R], d[L::R], p[L::R], sv[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
             r[i] = (float)(r64[i] * isc);
             d[i] = 0.0f;
-            p[i] = dinv[i] * r[i];
-            f3[1] += r[i] * p[i];
-            f3[2] += r[i] * r[i];
+            p[i] = 0.0f;
+            sv[i] = 0.0f;
         }
-        rf3.sum(f3, z.w0, L::WPI);
-        const float itol2 = (float)(A.inner_rtol * A.inner_rtol) * f3[2];
-        if (z.live && z.lt == 0) itol_s[z.sub] = me ? itol2 : 3.0e38f;
-        float rz = f3[1];
+        const float itol2 = (float)(A.inner_rtol * A.inner_rtol);
+        float gam_prev = 1.0f, alpha_prev = 1.0f;
         bool iconv = !me;
-        __syncthreads();
-        auto inner_any = [&]() {
-            bool a = false;
-            for (int s = 0; s < L::IPP && s < cnt; ++s) a |= rf3.last_of(s, L::WPI) > itol_s[s];
-            return a;
-        };
-        bool go = inner_any();
         int k = 0;
-        while (go && k < A.max_iter) {
-            const bool act = !iconv;
-#pragma unroll
-            for (int i = 0; i < L::R; ++i)
-                if (row_ok<L>(z, i)) pg[cell_of<L>(z, i)] = p[i];
-            __syncthreads();
-            float q[L::R];
-#pragma unroll
-            for (int i = 0; i < L::R; ++i) q[i] = 0.0f;
-            if (z.act) strip_apply<L>(SR, pg, z, p, q);
-            float pq[1] = {0.0f};
-#pragma unroll
-            for (int i = 0; i < L::R; ++i) pq[0] += p[i] * q[i];
-            rf1.sum(pq, z.w0, L::WPI);
-            const float alpha = act ? rz / pq[0] : 0.0f;
-            float a3[3] = {0.0f, 0.0f, 0.0f};
+        for (;;) {
+            float u[L::R], w[L::R];
 #pragma unroll
             for (int i = 0; i < L::R; ++i) {
-                d[i] += alpha * p[i];
-                r[i] -= alpha * q[i];
-                a3[1] += r[i] * dinv[i] * r[i];
-                a3[2] += r[i] * r[i];
+                u[i] = dinv[i] * r[i];
+                w[i] = 0.0f;
+                if (row_ok<L>(z, i)) pg[cell_of<L>(z, i)] = u[i];
             }
-            rf3.sum(a3, z.w0, L::WPI);
-            ++k;
-            if (act) {
-                ++iters;
-                if (a3[2] <= itol2) {
-                    iconv = true;
-                } else {
-                    const float beta = a3[1] / rz;
-                    rz = a3[1];
+            __syncthreads();
+            if (z.act) strip_apply<L, L::R>(SR, pg, z, u, w);
+            float g3[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-                    for (int i = 0; i < L::R; ++i) p[i] = dinv[i] * r[i] + beta * p[i];
-                }
+            for (int i = 0; i < L::R; ++i) {
+                g3[0] += r[i] * u[i];
+                g3[1] += w[i] * u[i];
+                g3[2] += r[i] * r[i];
             }
-            go = inner_any();
+            rf3.sum(g3, z.w0, L::WPI);
+            if (!iconv && g3[2] <= itol2) iconv = true;
+            bool go;
+            if constexpr (L::IPP == 1) {
+                go = !iconv;
+            } else {
+                go = false;
+                for (int q = 0; q < L::IPP && q < cnt; ++q) go |= rf3.last_of(q, L::WPI) > itol2;
+            }
+            if (!go || k >= A.max_iter) break;
+            if (!iconv) {
+                const float beta = (k == 0) ? 0.0f : g3[0] * __builtin_amdgcn_rcpf(gam_prev);
+                const float den = (k == 0) ? g3[1] : g3[1] - beta * g3[0] * __builtin_amdgcn_rcpf(alpha_prev);
+                const float alpha = g3[0] * __builtin_amdgcn_rcpf(den);
+#pragma unroll
+                for (int i = 0; i < L::R; ++i) {
+                    p[i] = u[i] + beta * p[i];
+                    sv[i] = w[i] + beta * sv[i];
+                    d[i] += alpha * p[i];
+                    r[i] -= alpha * sv[i];
+                }
+                gam_prev = g3[0];
+                alpha_prev = alpha;
+                ++iters;
+            }
+            ++k;
         }
         // x += ||r|| d;  r64 -= ||r|| S d  (FP64 stencil, d exact in FP64)
         const double sc = me ? rn : 0.0;
@@ -454,7 +503,7 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
         double sd[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) sd[i] = 0.0;
-        if (z.act) strip_apply<L>(S64, pg, z, d, sd);
+        if (z.act) strip_apply<L, 3>(S64, pg, z, d, sd);
         double a1[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {

@@ -35,7 +35,8 @@ struct AssembleArgs {
     Tables tab;
     double d, kappa, inv_dt;
     double* S64;          // [9 * total] : instance block at 9*off, coefficient-major [k][n]
-    float* S32;
+    float* S32;           // S rounded to FP32
+    float* Slo;           // S - S32 rounded to FP32: S32 + Slo equals S to about 2^-48 relative
     double* M64;
     double* b;            // boundary load B 1 (ragged)
     double* len;          // [n_inst] 1^T b
@@ -54,6 +55,7 @@ struct MicroArgs {
     const int64_t* offsets;
     const double* S64;
     const float* S32;
+    const float* Slo;
     const double* M64;
     const double* b;
     const double* X0;
