@@ -102,6 +102,8 @@ typedef struct {
     double macro_ms;             /* TSM_FLAG_TIMING: macro solve + fluxes, summed likewise */
     int32_t timed_steps;         /* steps covered by micro_ms / macro_ms */
     int32_t micro_launches;      /* micro kernel launches per step (one per mesh-size class) */
+    double grad_forward_ms;      /* last tsm_gradient: forward with checkpoints */
+    double grad_backward_ms;     /* last tsm_gradient: segment recompute + adjoint + gradient */
 } tsm_stats;
 
 typedef struct tsm_ctx tsm_ctx;

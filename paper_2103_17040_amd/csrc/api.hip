@@ -78,6 +78,12 @@ struct tsm_ctx {
     int macro_sweeps = 2;
     double rho = 0.0;
 
+    // adjoint: amplitude-derivative operators and work vectors (first tsm_gradient)
+    double *dS64 = nullptr, *dM64 = nullptr, *db = nullptr, *dlen = nullptr, *jmin_d = nullptr;
+    double *lam0 = nullptr, *mu = nullptr, *coef = nullptr, *grad = nullptr, *Jd = nullptr;
+    bool have_deriv = false;
+    double grad_fwd_ms = 0.0, grad_bwd_ms = 0.0;
+
     bool have_mesh = false, have_geom = false, have_state = false;
     hipGraphExec_t graph = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -96,6 +102,9 @@ struct tsm_ctx {
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32); dfree(Slo);
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count);
+        dfree(dS64); dfree(dM64); dfree(db); dfree(dlen); dfree(jmin_d);
+        dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
+        have_deriv = false;
         drop_graph();
         have_mesh = have_geom = have_state = false;
     }
@@ -450,6 +459,7 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
     if (!finite_all(ah) || !finite_all(th)) return c->fail(TSM_EINVAL, "non-finite deformation parameter");
     c->have_geom = false;
     c->have_state = false;
+    c->have_deriv = false;
     c->drop_graph();
     HIPCHK(hipMemcpyAsync(c->amp, a, n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
 
@@ -662,8 +672,147 @@ tsm_status tsm_apply_operator(tsm_ctx* c, const double* x, double* y) {
 
 tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda_out) {
     if (!c) return TSM_EINVAL;
-    (void)n_steps; (void)J_out; (void)dJda_out;
-    return c->fail(TSM_EINVAL, "gradient: not available in this build");
+    if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
+    if (n_steps < 1) return c->fail(TSM_EINVAL, "n_steps < 1");
+    if (!J_out || !dJda_out) return c->fail(TSM_EINVAL, "J_out and dJda_out are required");
+    const int64_t ni = c->n_inst, tot = c->total;
+    const int N = n_steps, K = c->prm.checkpoint_every;
+    const int nseg = (N + K - 1) / K;
+    HIPCHK(hipDeviceSynchronize());
+    // --- amplitude-derivative operators, once per deformation
+    if (!c->have_deriv) {
+        if (!c->dS64) {
+            HIPALLOC(c->dS64, kStencil * tot); HIPALLOC(c->dM64, kStencil * tot); HIPALLOC(c->db, tot);
+            HIPALLOC(c->dlen, ni); HIPALLOC(c->jmin_d, ni);
+            HIPALLOC(c->lam0, tot); HIPALLOC(c->mu, ni); HIPALLOC(c->coef, ni); HIPALLOC(c->grad, ni);
+            HIPALLOC(c->Jd, 1);
+        }
+        AssembleArgs as{};
+        as.n_inst = (int)ni;
+        as.level = c->level;
+        as.offsets = c->offsets;
+        as.amp = c->amp;
+        as.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
+        as.d = c->prm.d;
+        as.kappa = c->prm.kappa;
+        as.inv_dt = 1.0 / c->prm.dt;
+        as.S64 = c->dS64; as.M64 = c->dM64; as.b = c->db; as.len = c->dlen; as.jmin = c->jmin_d;
+        HIPCHK(launch_assemble_da(as, c->stream));
+        c->have_deriv = true;
+    }
+    // --- work buffers of this call
+    double *U = nullptr, *ck_u = nullptr, *ck_v = nullptr, *V = nullptr, *save_u = nullptr, *save_v = nullptr,
+           *save_F = nullptr;
+    auto release = [&]() { dfree(U); dfree(ck_u); dfree(ck_v); dfree(V); dfree(save_u); dfree(save_v); dfree(save_F); };
+    if (dalloc(&U, (size_t)(N + 1) * ni) != hipSuccess || dalloc(&ck_u, (size_t)nseg * ni) != hipSuccess ||
+        dalloc(&ck_v, (size_t)nseg * tot) != hipSuccess || dalloc(&V, (size_t)(K + 1) * tot) != hipSuccess ||
+        dalloc(&save_u, ni) != hipSuccess || dalloc(&save_v, tot) != hipSuccess || dalloc(&save_F, ni) != hipSuccess) {
+        (void)hipGetLastError();
+        release();
+        return c->fail(TSM_ENOMEM, "gradient work buffers");
+    }
+    tsm_status st = TSM_OK;
+    auto run = [&]() -> tsm_status {
+        hipStream_t s = c->stream;
+        HIPCHK(hipMemcpyAsync(save_u, c->u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(save_v, c->v0, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(save_F, c->F, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), s));
+        HIPCHK(hipEventRecord(c->ev0, s));
+        // forward with checkpoints; u of every step kept (n_inst doubles per step)
+        HIPCHK(hipMemcpyAsync(U, c->u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+        for (int n = 0; n < N; ++n) {
+            if (n % K == 0) {
+                HIPCHK(hipMemcpyAsync(ck_u + (size_t)(n / K) * ni, c->u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(ck_v + (size_t)(n / K) * tot, c->v0, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+            }
+            if (c->graph) {
+                HIPCHK(hipGraphLaunch(c->graph, s));
+            } else {
+                tsm_status e = enqueue_step(c);
+                if (e != TSM_OK) return e;
+            }
+            HIPCHK(hipMemcpyAsync(U + (size_t)(n + 1) * ni, c->u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        const MacroArgs m = c->macro_args();
+        HIPCHK(launch_observable(m, U + (size_t)N * ni, c->Jd, s));
+        HIPCHK(hipEventRecord(c->ev1, s));
+        // backward: lambda^{N+1} = 0, mu^{N+1} = 0
+        HIPCHK(hipMemsetAsync(c->lam0, 0, tot * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(c->coef, 0, ni * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(c->mu, 0, ni * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(c->grad, 0, ni * sizeof(double), s));
+        for (int sg = nseg - 1; sg >= 0; --sg) {
+            const int a = sg * K, e = std::min(a + K, N);
+            // recompute the segment's states v^a .. v^e (same kernels: bitwise equal)
+            HIPCHK(hipMemcpyAsync(c->u, ck_u + (size_t)sg * ni, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(c->v0, ck_v + (size_t)sg * tot, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+            HIPCHK(launch_state_join((int)ni, c->offsets, c->u, c->v0, c->w, V, s));
+            for (int n = a + 1; n <= e; ++n) {
+                if (c->graph) {
+                    HIPCHK(hipGraphLaunch(c->graph, s));
+                } else {
+                    tsm_status e2 = enqueue_step(c);
+                    if (e2 != TSM_OK) return e2;
+                }
+                HIPCHK(launch_state_join((int)ni, c->offsets, c->u, c->v0, c->w, V + (size_t)(n - a) * tot, s));
+            }
+            for (int mstep = e; mstep > a; --mstep) {
+                // micro adjoint solves: lam0^m = S^{-1} M (lam0^{m+1} + coef^{m+1} w) / dt
+                MicroArgs ma = micro_base(c);
+                ma.X0 = c->lam0;
+                ma.coef = c->coef;
+                ma.rhs_vec = nullptr;
+                ma.zero_init = 0;
+                ma.X_out = c->lam0;
+                tsm_status e3 = enqueue_micro(c, ma, false);
+                if (e3 != TSM_OK) return e3;
+                // macro adjoint: A_M mu^m = M_H mu^{m+1}/dt + kappa p (b^T lam0^m) (+ 2 M_H u^N)
+                HIPCHK(launch_macro_rhs_adjoint(m, c->mu, c->bx, U + (size_t)N * ni, mstep == N ? 1 : 0, c->rhs, s));
+                e3 = enqueue_macro_solve(c, c->mu);
+                if (e3 != TSM_OK) return e3;
+                HIPCHK(launch_adjoint_coef(m, c->mu, c->coef, s));
+                GradArgs ga;
+                ga.n_inst = (int)ni;
+                ga.NM = c->NM;
+                ga.level = c->level;
+                ga.offsets = c->offsets;
+                ga.dS = c->dS64; ga.dM = c->dM64; ga.db = c->db; ga.dlen = c->dlen; ga.b = c->b; ga.len = c->len;
+                ga.lam0 = c->lam0; ga.coef = c->coef; ga.w = c->w;
+                ga.v_now = V + (size_t)(mstep - a) * tot;
+                ga.v_prev = V + (size_t)(mstep - a - 1) * tot;
+                ga.u_now = U + (size_t)mstep * ni;
+                ga.mu = c->mu;
+                ga.kappa = c->prm.kappa; ga.p = c->prm.p; ga.sign = c->prm.source_sign; ga.inv_dt = 1.0 / c->prm.dt;
+                ga.g = c->grad;
+                HIPCHK(launch_gradient_step(ga, s));
+            }
+        }
+        hipEvent_t e_end;
+        HIPCHK(hipEventCreate(&e_end));
+        HIPCHK(hipEventRecord(e_end, s));
+        HIPCHK(hipMemcpyAsync(dJda_out, c->grad, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(J_out, c->Jd, sizeof(double), hipMemcpyDeviceToHost, s));
+        // restore the state
+        HIPCHK(hipMemcpyAsync(c->u, save_u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->v0, save_v, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->F, save_F, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+        int32_t nc = 0;
+        HIPCHK(hipMemcpyAsync(&nc, c->counters, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        float f1 = 0.0f, f2 = 0.0f;
+        HIPCHK(hipEventElapsedTime(&f1, c->ev0, c->ev1));
+        HIPCHK(hipEventElapsedTime(&f2, c->ev1, e_end));
+        (void)hipEventDestroy(e_end);
+        c->grad_fwd_ms = f1;
+        c->grad_bwd_ms = f2;
+        if (nc > 0) return c->fail(TSM_ENOCONV, std::to_string(nc) + " solves missed rtol during the gradient");
+        return TSM_OK;
+    };
+    st = run();
+    (void)hipStreamSynchronize(c->stream);
+    release();
+    return st;
 }
 
 tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
@@ -694,6 +843,8 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
     s->macro_ms = c->macro_ms;
     s->timed_steps = c->timed_steps;
     s->micro_launches = (int32_t)(c->groups.size() + c->pack_groups.size());
+    s->grad_forward_ms = c->grad_fwd_ms;
+    s->grad_backward_ms = c->grad_bwd_ms;
     if (c->have_geom && c->n_inst > 0) {
         std::vector<int32_t> it(c->n_inst), sw(c->n_inst);
         HIPCHK(hipStreamSynchronize(c->stream));

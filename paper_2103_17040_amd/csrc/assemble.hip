@@ -17,6 +17,10 @@ namespace tsm {
 
 namespace {
 
+// DERIV: assemble the amplitude derivatives dS/da, dM/da and db/da instead
+// (F = I + a G: dJ = G11 M22 + M11 G22 - G12 M21 - M12 G21,
+//  dC = d[adj(M) adj(M)^T]/da / J - C dJ / J,  d|M tau| = (M tau).(G tau) / |M tau|).
+template <bool DERIV>
 __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A) {
     __shared__ double red_s[2][1][kMicroThreads / kWave];
     __shared__ double mins[kMicroThreads / kWave];
@@ -58,8 +62,9 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     const int t2 = 2 * c2 + g2;
                     for (int g1 = 0; g1 < 2; ++g1) {
                         const int t1 = 2 * c1 + g1;
-                        const Pull P = pullback_at(a, ys[t1], ys[t2], ss[t1], cs[t1], ss[t2], cs[t2]);
+                        Pull P = pullback_at(a, ys[t1], ys[t2], ss[t1], cs[t1], ss[t2], cs[t2]);
                         jmin = fmin(jmin, P.J);
+                        if constexpr (DERIV) P = pullback_da_at(a, ys[t1], ys[t2], ss[t1], cs[t1], ss[t2], cs[t2]);
                         // basis of local node (l1,l2) and its reference gradient
                         const double f1 = lin(l1, g1), f2 = lin(l2, g2);
                         const double phl = f1 * f2;
@@ -99,7 +104,8 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     const int t1 = 2 * e + g;
                     const double M11 = 1.0 + a * cs[t1] * yf;
                     const double M21 = a * ss[tf];
-                    const double om = sqrt(M11 * M11 + M21 * M21);
+                    double om = sqrt(M11 * M11 + M21 * M21);
+                    if constexpr (DERIV) om = (M11 * cs[t1] * yf + M21 * ss[tf]) / om;
                     for (int m1 = 0; m1 < 2; ++m1) {
                         const double v = wb * om * lin(l1, g) * lin(m1, g);
                         S[3 + (m1 - l1 + 1)] += A.kappa * v;
@@ -120,7 +126,8 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     const int t2 = 2 * e + g;
                     const double M12 = a * ss[tf];
                     const double M22 = 1.0 + a * cs[t2] * yf;
-                    const double om = sqrt(M12 * M12 + M22 * M22);
+                    double om = sqrt(M12 * M12 + M22 * M22);
+                    if constexpr (DERIV) om = (M12 * ss[tf] + M22 * cs[t2] * yf) / om;
                     for (int m2 = 0; m2 < 2; ++m2) {
                         const double v = wb * om * lin(l2, g) * lin(m2, g);
                         S[(m2 - l2 + 1) * 3 + 1] += A.kappa * v;
@@ -130,16 +137,16 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
             }
         }
         double* Sd = A.S64 + kStencil * off;
-        float* Sf = A.S32 + kStencil * off;
-        float* Sl = A.Slo + kStencil * off;
         double* Md = A.M64 + kStencil * off;
 #pragma unroll
         for (int k = 0; k < kStencil; ++k) {
             Sd[(int64_t)k * n + j] = S[k];
-            const float hi = (float)S[k];
-            Sf[(int64_t)k * n + j] = hi;
-            Sl[(int64_t)k * n + j] = (float)(S[k] - (double)hi);
             Md[(int64_t)k * n + j] = M[k];
+            if constexpr (!DERIV) {
+                const float hi = (float)S[k];
+                A.S32[kStencil * off + (int64_t)k * n + j] = hi;
+                A.Slo[kStencil * off + (int64_t)k * n + j] = (float)(S[k] - (double)hi);
+            }
         }
         A.b[off + j] = bj;
         len_part += bj;
@@ -163,7 +170,13 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
 
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s) {
     if (a.n_inst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(assemble_kernel, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
+    hipLaunchKernelGGL(assemble_kernel<false>, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_da(const AssembleArgs& a, hipStream_t s) {
+    if (a.n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(assemble_kernel<true>, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -104,4 +104,23 @@ __device__ __forceinline__ Pull pullback_at(double a, double y1, double y2,
     return g;
 }
 
+// a-derivatives of J and C at one reference point (M = I + a G, dM/da = G)
+__device__ __forceinline__ Pull pullback_da_at(double a, double y1, double y2,
+                                               double s1, double c1, double s2, double c2) {
+    const double G11 = c1 * y2, G12 = s1, G21 = s2, G22 = c2 * y1;
+    const double M11 = 1.0 + a * G11, M12 = a * G12, M21 = a * G21, M22 = 1.0 + a * G22;
+    const double J = M11 * M22 - M12 * M21;
+    const double iJ = 1.0 / J;
+    const double dJ = G11 * M22 + M11 * G22 - G12 * M21 - M12 * G21;
+    const double C11 = (M22 * M22 + M12 * M12) * iJ;
+    const double C12 = -(M22 * M21 + M12 * M11) * iJ;
+    const double C22 = (M21 * M21 + M11 * M11) * iJ;
+    Pull d;
+    d.J = dJ;
+    d.C11 = 2.0 * (M22 * G22 + M12 * G12) * iJ - C11 * dJ * iJ;
+    d.C12 = -(G22 * M21 + M22 * G21 + G12 * M11 + M12 * G11) * iJ - C12 * dJ * iJ;
+    d.C22 = 2.0 * (M21 * G21 + M11 * G11) * iJ - C22 * dJ * iJ;
+    return d;
+}
+
 }  // namespace tsm

@@ -126,6 +126,30 @@ __global__ void state_join_kernel(const int64_t* offsets, const double* u, const
     for (int64_t j = b + threadIdx.x; j < e; j += blockDim.x) v[j] = v0[j] + ui * w[j];
 }
 
+// J = u^T M_H u (the integral of u_h^2), one workgroup, fixed summation order
+__global__ __launch_bounds__(1024) void observable_kernel(MacroArgs m, const double* u, double* J) {
+    __shared__ double red_s[2][1][1024 / kWave];
+    BlockReducer<1024 / kWave, 1, double> red(red_s);
+    const int W = m.NM + 1;
+    const double mass_h2 = 1.0 / (36.0 * m.NM * m.NM);
+    double v[1] = {0.0};
+    for (int idx = threadIdx.x; idx < m.n * m.n; idx += 1024) {
+        const int k = (idx / m.n + 1) * W + (idx % m.n + 1);
+        v[0] += u[k] * mass_h2 * mass9(u, k, W);
+    }
+    red.sum(v);
+    if (threadIdx.x == 0) *J = v[0];
+}
+
+// adjoint coupling coefficient: lambda_i = lambda0_i + coef_i w_i with
+// coef_i = -sign L_ii mu_i / (p |dY_i|)   (L_ii = H^2 inside, mu = 0 on the boundary)
+__global__ void adjoint_coef_kernel(MacroArgs m, const double* mu, double* coef) {
+    const int W = m.NM + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= W * W) return;
+    coef[k] = -m.sig_h2 * mu[k] / (m.p * m.len[k]);
+}
+
 inline int blocks(int n, int t) { return (n + t - 1) / t; }
 
 }  // namespace
@@ -156,6 +180,17 @@ hipError_t launch_gemm(int n, const double* A, const double* B, double* C, int e
                        const double* lam, double* u, int NM, hipStream_t s) {
     const dim3 grid(blocks(n, TG), blocks(n, TG));
     hipLaunchKernelGGL(gemm_kernel, grid, dim3(TG * TG), 0, s, n, A, B, C, epilogue, lam, u, NM);
+    return hipGetLastError();
+}
+
+hipError_t launch_observable(const MacroArgs& m, const double* u, double* J, hipStream_t s) {
+    hipLaunchKernelGGL(observable_kernel, dim3(1), dim3(1024), 0, s, m, u, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_coef(const MacroArgs& m, const double* mu, double* coef, hipStream_t s) {
+    const int tot = (m.NM + 1) * (m.NM + 1);
+    hipLaunchKernelGGL(adjoint_coef_kernel, dim3(blocks(tot, 256)), dim3(256), 0, s, m, mu, coef);
     return hipGetLastError();
 }
 

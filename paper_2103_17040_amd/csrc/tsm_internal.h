@@ -95,6 +95,8 @@ struct MacroArgs {
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s);
+// same gather with the amplitude derivatives: S64 <- dS/da, M64 <- dM/da, b <- db/da, len <- 1^T db
+hipError_t launch_assemble_da(const AssembleArgs& a, hipStream_t s);
 hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_t lds_bytes, hipStream_t s);
 // packs of one mesh size (16, 32 or 64); mode 1 FP64, 2 refinement
 hipError_t launch_packed(const MicroArgs& a, const PackList& p, int level, int mode, int grid, hipStream_t s);
@@ -113,6 +115,25 @@ hipError_t launch_macro_residual(const MacroArgs& m, const double* u, const doub
 // C = A * B (n x n row-major); epilogue 0: C stored; 1: C ./= lam; 2: u[interior] += C
 hipError_t launch_gemm(int n, const double* A, const double* B, double* C, int epilogue,
                        const double* lam, double* u, int NM, hipStream_t s);
+hipError_t launch_observable(const MacroArgs& m, const double* u, double* J, hipStream_t s);
+hipError_t launch_adjoint_coef(const MacroArgs& m, const double* mu, double* coef, hipStream_t s);
+
+// Gradient contribution of one adjoint step m (one workgroup per instance):
+//   g_i -= lam_i^T (dS_i v_i^m - kappa p u_i^m db_i - dM_i v_i^{m-1} / dt)
+//          - sign mu_i L_ii dF_i,   dF_i = -kappa (db_i^T v_i^m / |dY_i| - (b_i^T v_i^m) d|dY_i| / |dY_i|^2)
+// with lam_i = lam0_i + coef_i w_i.
+struct GradArgs {
+    int n_inst, NM;
+    const int32_t* level;
+    const int64_t* offsets;
+    const double *dS, *dM, *db, *dlen, *b, *len;
+    const double *lam0, *coef, *w;
+    const double *v_now, *v_prev, *u_now, *mu;
+    double kappa, p, sign, inv_dt;
+    double* g;
+};
+hipError_t launch_gradient_step(const GradArgs& a, hipStream_t s);
+
 hipError_t launch_macro_finalize(const MacroArgs& m, const double* u, const double* alpha,
                                  double* F, hipStream_t s);
 hipError_t launch_beta(int n_inst, double kappa, double p, const double* len, const double* bx,
