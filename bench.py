@@ -52,11 +52,12 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_form(w, a, th, lv, precision, steps, warmup, rtol):
+def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0):
     import torch
     from paper_2103_17040_amd import TwoScaleBatch, tsm
     g = TwoScaleBatch(w.macro_cells, lv, a, th, D=w.D, d=w.d, kappa=w.kappa, p=w.p, dt=w.dt,
-                      sigma=w.sigma, precision=precision, rtol=rtol)
+                      sigma=w.sigma, precision=precision, rtol=rtol,
+                      checkpoint_every=max(w.checkpoint_every, 1))
     try:
         setup_ms = g.stats()["setup_ms"]
         u0 = W.initial_macro(w.macro_cells)
@@ -73,7 +74,21 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol):
         g.step(steps)
         tst = g.stats()
         g.set_flags(0)
-        return {"t": t, "setup_ms": setup_ms, "stats": st, "timing": tst, "n_dofs": g.n_micro}
+        adj = None
+        if adjoint_steps > 0:
+            # gradient of int u(T)^2 from the initial state: checkpointed
+            # forward, then segment recompute + adjoint + gradient
+            g.set_state(u0, None)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            J, dJ = g.gradient(adjoint_steps)
+            torch.cuda.synchronize()
+            tg = time.perf_counter() - t0
+            gs = g.stats()
+            adj = {"steps": adjoint_steps, "checkpoint_every": max(w.checkpoint_every, 1),
+                   "J": J, "grad_norm": float(dJ.norm()), "wall_s": tg,
+                   "forward_ms": gs["grad_forward_ms"], "backward_ms": gs["grad_backward_ms"]}
+        return {"t": t, "setup_ms": setup_ms, "stats": st, "timing": tst, "n_dofs": g.n_micro, "adjoint": adj}
     finally:
         g.close()
 
@@ -119,6 +134,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=40,
+                    help="steps of the gradient leg (0: skip); checkpoint spacing from the workload")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run a plain device copy of this many bytes (3 times), the reference "
                          "for scaling HBM counters (FETCH_SIZE, WRITE_SIZE) in profiles")
@@ -143,7 +160,7 @@ def main():
     _log(f"workload {w.name}: {w.n_inst} instances, levels {sorted(set(lv.tolist()))}, "
          f"{int(W.offsets(lv)[-1])} micro DoFs, precision {w.precision}, rtol {w.rtol}")
 
-    main_form = run_form(w, a, th, lv, w.precision, args.steps, args.warmup, w.rtol)
+    main_form = run_form(w, a, th, lv, w.precision, args.steps, args.warmup, w.rtol, args.adjoint_steps)
     _log(f"main form done: {main_form['t']:.3f} s for {args.steps} steps; stats {main_form['stats']}")
     fp64 = None
     if refine and not args.no_fp64:
@@ -205,6 +222,14 @@ def main():
         out["fp64_value"] = v64
         out["fp32_refine_speedup_vs_fp64"] = value / v64
         out["fp64_iters_mean"] = fp64["stats"]["iters_mean"]
+    adj = main_form["adjoint"]
+    if adj is not None:
+        plain_fwd_ms = main_form["t"] / K * 1e3 * adj["steps"]
+        adj["plain_forward_ms"] = plain_fwd_ms
+        adj["backward_over_forward"] = adj["backward_ms"] / adj["forward_ms"]
+        adj["total_over_plain_forward"] = (adj["forward_ms"] + adj["backward_ms"]) / plain_fwd_ms
+        out["adjoint"] = adj
+        out["adjoint_over_forward"] = adj["backward_over_forward"]
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, a, th, lv)
