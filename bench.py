@@ -41,11 +41,41 @@ PEAK_ALU_TFLOPS = 78.6
 # residual sweep 9 FMA + 1 SUB + 1 FMA (norm) + 1 FMA (x += ||r|| d) = 23 flops;
 # per solve M x0/dt, b^T x, x0 = X0 + u w = 23 flops.
 FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 23.0, 23.0
-# Bytes that the instance-resident kernel must move per DoF per step: the
-# FP64 mass stencil (9 x 8), the FP64 operator stencil per FP64 residual
-# sweep (9 x 8), the FP32 operator stencil once (9 x 4; FP64 form: the FP64
-# stencil once), and the state: read v0 and w, write v0, read b (4 x 8).
-B_MASS, B_S64, B_S32, B_STATE = 72.0, 72.0, 36.0, 32.0
+# Bytes the instance-resident micro kernel must move per DoF per step
+# (algorithmic: the vectors of the iterations stay on chip).
+#   both forms: x0 = v0 + u w (read v0, w: 16), b = M x0/dt (FP64 mass
+#               stencil, 72), r = b - S x0 (FP64 stencil, 72), write x and
+#               read b for the flux average (16)
+#   refine:     the FP32 stencil once (36) and, per residual update after an
+#               inner solve, the FP32 low part of the stencil (36)
+#   FP64:       the FP64 stencil once per PCG iteration (72)
+B_START, B_MASS, B_S64, B_S32, B_SLO, B_END = 16.0, 72.0, 72.0, 36.0, 36.0, 16.0
+KERNEL_SOURCES = ("micro_packed.hip", "device_common.h", "tsm_internal.h")
+COUNTERS = os.path.join(ROOT, "profiles", "micro_kernel_counters.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2103_17040_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, form):
+    """Counter-measured HBM bytes per launch of the micro kernel (scaled
+    FETCH_SIZE + WRITE_SIZE) from the committed profile, or None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(COUNTERS) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    ent = rec.get("launches", {}).get(f"{workload}/{form}")
+    return None if ent is None else ent["fetch_bytes"] + ent["write_bytes"]
 
 
 def _log(msg):
@@ -181,20 +211,23 @@ def main():
     dofs_per_launch = n_dofs / max(tst["micro_launches"], 1)
     flops = dofs_per_launch * (FLOP_ITER * iters + FLOP_SWEEP * sweeps + FLOP_SOLVE)
     if refine:
-        nbytes = dofs_per_launch * (B_MASS + B_S64 * sweeps + B_S32 + B_STATE)
+        nbytes = dofs_per_launch * (B_START + B_MASS + B_S64 + B_S32 + B_SLO * max(sweeps - 1, 0) + B_END)
     else:
-        nbytes = dofs_per_launch * (B_MASS + B_S64 + B_STATE)
+        nbytes = dofs_per_launch * (B_START + B_MASS + B_S64 + B_S64 * iters + B_END)
     t_launch = micro_ms_per_launch * 1e-3
     alu = flops / t_launch / 1e12
     hbm = nbytes / t_launch / 1e9
+    traffic = measured_traffic(w.name, w.precision)
     if alu / PEAK_ALU_TFLOPS >= hbm / PEAK_HBM_GBS:
         roof = {"bound": "alu", "achieved": alu, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": alu / PEAK_ALU_TFLOPS, "traffic": None}
+                "frac": alu / PEAK_ALU_TFLOPS, "traffic": traffic}
     else:
         roof = {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": hbm / PEAK_HBM_GBS, "traffic": None}
-    roof.update({"kernel": "micro_kernel", "launch_ms": micro_ms_per_launch,
-                 "hbm_model_GBs": hbm, "alu_model_TFLOPs": alu})
+                "frac": hbm / PEAK_HBM_GBS, "traffic": traffic}
+    roof.update({"kernel": "packed_kernel (micro PCG)", "launch_ms": micro_ms_per_launch,
+                 "algorithmic_bytes_per_launch": nbytes, "algorithmic_flops_per_launch": flops,
+                 "hbm_model_GBs": hbm, "alu_model_TFLOPs": alu,
+                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"})
 
     out = {
         "metric": "micro DoF-updates/s (batched FP32+refine vs plain FP64) at 1e-8 rel; adjoint/fwd",
