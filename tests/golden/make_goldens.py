@@ -1,0 +1,89 @@
+"""Write the oracle's expected outputs for the full-size parity tests.
+
+    python tests/golden/make_goldens.py [batched_fp64 uneven_mixed adjoint_fp64]
+
+Calls only the FP64 oracle and the seeded input generators (seed 0).  Each
+file stores a compact, sampled set of outputs (compressed .npz, no pickles):
+macro fields at a few steps, all fluxes of the first and last step, the micro
+field of a few sampled instances at the end, the response functionals, and
+for the adjoint workload J and dJ/da.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+from oracle import adjoint, twoscale  # noqa: E402
+
+SAMPLE_STEPS = (1, 2, 10)
+
+
+def sampled_instances(w, lv, count=12, seed=0):
+    """Interior instances spread over the batch, covering every mesh size."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 4242]))
+    interior = np.flatnonzero(~W.macro_boundary_mask(w.macro_cells))
+    picks = []
+    for lvl in sorted(set(lv.tolist())):
+        cand = interior[lv[interior] == lvl]
+        picks += list(rng.choice(cand, size=min(len(cand), max(2, count // len(set(lv.tolist())))), replace=False))
+    return np.array(sorted(set(int(i) for i in picks)), dtype=np.int64)
+
+
+def forward_golden(name):
+    w, a, th, lv = W.make(name, 0)
+    prm = twoscale.Params(w.macro_cells, w.dt, w.D, w.d, w.kappa, w.p, w.sigma)
+    t0 = time.time()
+    ts = twoscale.TwoScale(prm, lv, a, th)
+    print(f"{name}: setup {time.time() - t0:.1f} s", flush=True)
+    u = W.initial_macro(w.macro_cells)
+    v = np.zeros(int(ts.offsets[-1]))
+    steps = sorted(set(SAMPLE_STEPS + (w.steps,)))
+    us, F1 = {}, None
+    t0 = time.time()
+    for n in range(1, w.steps + 1):
+        u, v, F = ts.step(u, v)
+        if n == 1:
+            F1 = F
+        if n in steps:
+            us[n] = u.copy()
+    print(f"{name}: {w.steps} steps {time.time() - t0:.1f} s", flush=True)
+    inst = sampled_instances(w, lv)
+    vs = [v[ts.offsets[i]:ts.offsets[i + 1]] for i in inst]
+    out = {
+        "steps": np.array(steps, dtype=np.int64),
+        "u": np.stack([us[n] for n in steps]),
+        "F_first": F1, "F_last": F,
+        "inst": inst,
+        "v_len": np.array([len(x) for x in vs], dtype=np.int64),
+        "v_last": np.concatenate(vs),
+        "beta": ts.beta, "len": ts.len,
+        "J": np.array(ts.observable(u)),
+    }
+    np.savez_compressed(os.path.join(HERE, f"{name}_seed0.npz"), **out)
+
+
+def adjoint_golden(name="adjoint_fp64"):
+    w, a, th, lv = W.make(name, 0)
+    prm = twoscale.Params(w.macro_cells, w.dt, w.D, w.d, w.kappa, w.p, w.sigma)
+    t0 = time.time()
+    ts = twoscale.TwoScale(prm, lv, a, th)
+    u0 = W.initial_macro(w.macro_cells)
+    v0 = np.zeros(int(ts.offsets[-1]))
+    J, g = adjoint.gradient(ts, u0, v0, w.steps)
+    print(f"{name}: gradient {time.time() - t0:.1f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, f"{name}_seed0.npz"), J=np.array(J), g=g)
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or ["batched_fp64", "uneven_mixed", "adjoint_fp64"]
+    for nm in names:
+        if nm == "adjoint_fp64":
+            adjoint_golden(nm)
+        else:
+            forward_golden(nm)

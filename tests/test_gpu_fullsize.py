@@ -1,0 +1,164 @@
+"""Parity at the full workload sizes.
+
+* 4225 x 32^2 FP64 (100 steps), 4225 uneven 16/32/64 FP32+refinement (100
+  steps) and the 1089 x 32^2 gradient (50 steps) against the oracle's outputs
+  stored by tests/golden/make_goldens.py (sampled micro fields, all macro
+  fields at several steps, all fluxes, the response functionals).
+* 16641 x 64^2 (70.3M DoFs), where the oracle cannot run in seconds: one
+  step from a seeded state, checked through relations that hold at any size
+  -- the micro step equation, the flux definition and the conservation
+  identity on sampled instances with oracle-assembled matrices, the macro
+  equation on every row with the oracle's macro matrices -- plus per-instance
+  setup parity on sampled instances and the constant-amplitude rank-one
+  reduction on the whole batch.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import banner, gpu_for, rel
+from oracle import fem, twoscale
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    return np.load(os.path.join(GOLD, f"{name}_seed0.npz"), allow_pickle=False)
+
+
+def _run_forward(name, precision, rtol):
+    w, a, th, lv = W.make(name, 0)
+    ref = _golden(name)
+    banner(f"full-size {name} {precision} rtol={rtol}")
+    g = gpu_for(w.macro_cells, lv, a, th, w.dt, precision=precision, rtol=rtol,
+                D=w.D, d=w.d, kappa=w.kappa, p=w.p, sigma=w.sigma)
+    try:
+        beta, ln, _ = (t.cpu().numpy() for t in g.setup())
+        g.set_state(W.initial_macro(w.macro_cells), None)
+        us, F_first, done = {}, None, 0
+        for n in ref["steps"]:
+            g.step(int(n) - done)
+            done = int(n)
+            us[int(n)] = g.macro().cpu().numpy()
+            if done == 1:
+                F_first = g.fluxes().cpu().numpy()
+        F_last = g.fluxes().cpu().numpy()
+        v = g.micro().cpu().numpy()
+    finally:
+        g.close()
+    off = W.offsets(lv)
+    v_s = np.concatenate([v[off[i]:off[i + 1]] for i in ref["inst"]])
+    return ref, dict(beta=beta, len=ln, u=np.stack([us[int(n)] for n in ref["steps"]]),
+                     F_first=F_first, F_last=F_last, v_last=v_s)
+
+
+def test_batched_fp64_full_size():
+    ref, out = _run_forward("batched_fp64", "fp64", 1e-12)
+    assert rel(out["len"], ref["len"]) <= 1e-14
+    assert rel(out["beta"], ref["beta"]) <= 1e-12
+    for k in ("u", "F_first", "F_last", "v_last"):
+        assert rel(out[k], ref[k]) <= 1e-10, k
+
+
+def test_uneven_mixed_refine_full_size():
+    ref, out = _run_forward("uneven_mixed", "fp32_refine", 1e-10)
+    assert rel(out["beta"], ref["beta"]) <= 1e-12
+    for k in ("u", "F_first", "F_last", "v_last"):
+        assert rel(out[k], ref[k]) <= 1e-8, k
+
+
+def test_adjoint_workload_full_size():
+    w, a, th, lv = W.make("adjoint_fp64", 0)
+    ref = _golden("adjoint_fp64")
+    banner("full-size adjoint_fp64 gradient")
+    g = gpu_for(w.macro_cells, lv, a, th, w.dt, rtol=1e-12, checkpoint_every=w.checkpoint_every,
+                D=w.D, d=w.d, kappa=w.kappa, p=w.p, sigma=w.sigma)
+    try:
+        g.set_state(W.initial_macro(w.macro_cells), None)
+        J, dJ = g.gradient(w.steps)
+        dJ = dJ.cpu().numpy()
+    finally:
+        g.close()
+    banner(f"J rel err {abs(J - float(ref['J'])) / abs(float(ref['J'])):.2e}, dJ/da rel err {rel(dJ, ref['g']):.2e}")
+    assert abs(J - float(ref["J"])) <= 1e-10 * abs(float(ref["J"]))
+    assert rel(dJ, ref["g"]) <= 1e-6
+
+
+# ---------------------------------------------------------------- 16641 x 64^2
+def _large_sample(w, count=6, seed=3):
+    rng = np.random.default_rng(seed)
+    interior = np.flatnonzero(~W.macro_boundary_mask(w.macro_cells))
+    return np.sort(rng.choice(interior, size=count, replace=False))
+
+
+def test_large_mixed_one_step_relations():
+    w, a, th, lv = W.make("large_mixed", 0)
+    NM = w.macro_cells
+    u0, v0 = W.random_state(lv, NM, seed=1)
+    banner("full-size large_mixed one step, refine rtol 1e-8")
+    g = gpu_for(NM, lv, a, th, w.dt, precision="fp32_refine", rtol=w.rtol,
+                D=w.D, d=w.d, kappa=w.kappa, p=w.p, sigma=w.sigma)
+    try:
+        beta, ln, wv = (t.cpu().numpy() for t in g.setup())
+        g.set_state(u0, v0)
+        g.step(1)
+        u1 = g.macro().cpu().numpy()
+        F1 = g.fluxes().cpu().numpy()
+        v1 = g.micro().cpu().numpy()
+    finally:
+        g.close()
+    off = W.offsets(lv)
+    prm = twoscale.Params(NM, w.dt, w.D, w.d, w.kappa, w.p, w.sigma)
+    kp = w.kappa * w.p
+    for i in _large_sample(w):
+        I = twoscale.Instance(lv[i], a[i], th[i], prm)
+        sl = slice(off[i], off[i + 1])
+        # setup parity, one instance at a time
+        assert rel(wv[sl], I.w) <= 1e-11
+        assert abs(beta[i] - I.beta) <= 1e-12 * abs(I.beta)
+        assert abs(ln[i] - I.len) <= 1e-14 * I.len
+        # micro step equation  S v1 - kappa p u1 b = M v0 / dt
+        rhs = I.M @ v0[sl] / w.dt
+        res = I.S @ v1[sl] - kp * u1[i] * I.b - rhs
+        assert np.linalg.norm(res) <= 2e-8 * np.linalg.norm(rhs), i
+        # flux definition and conservation
+        Fi = kp * u1[i] - w.kappa / I.len * float(I.b @ v1[sl])
+        assert abs(F1[i] - Fi) <= 1e-12 * max(abs(Fi), 1e-300) + 1e-15
+        cons = np.ones(I.n) @ (I.M @ (v1[sl] - v0[sl])) / w.dt
+        assert abs(cons - I.len * F1[i]) <= 1e-7 * abs(cons)
+    # macro equation on every interior row: (M_H/dt + D K_H) u1 - sigma L F1 = M_H u0 / dt
+    MH, KH, L = fem.macro_matrices(NM)
+    inner = ~fem.macro_boundary(NM)
+    r = ((MH / w.dt + w.D * KH) @ u1 - w.sigma * L * F1 - MH @ u0 / w.dt)[inner]
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm((MH @ u0 / w.dt)[inner])
+    assert np.abs(u1[~inner]).max() == 0.0
+
+
+def test_large_mixed_constant_amplitude_rank_one():
+    """a = const, v0 = 0, u0 = I_h(sin sin): u^n = rho_n u0 and
+    v_i^n = u0_i V^n on the whole 16641 x 64^2 batch."""
+    w = W.WORKLOADS["large_mixed"]
+    NM = w.macro_cells
+    n = (NM + 1) ** 2
+    lv = np.full(n, 64, np.int32)
+    u0 = W.initial_macro(NM)
+    banner("full-size rank-one reduction 16641 x 64^2")
+    g = gpu_for(NM, lv, np.full(n, 0.17), None, w.dt, precision="fp32_refine", rtol=1e-10)
+    try:
+        g.set_state(u0, None)
+        g.step(3)
+        u = g.macro().cpu().numpy()
+        v = g.micro().cpu().numpy()
+    finally:
+        g.close()
+    inner = ~W.macro_boundary_mask(NM)
+    ratio = u[inner] / u0[inner]
+    assert np.std(ratio) <= 1e-9 * abs(np.mean(ratio))
+    off = W.offsets(lv)
+    picks = np.flatnonzero(inner)[[0, 5000, 12000]]
+    Vs = [v[off[i]:off[i + 1]] / u0[i] for i in picks]
+    for V in Vs[1:]:
+        assert rel(V, Vs[0]) <= 1e-8
