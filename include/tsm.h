@@ -37,7 +37,8 @@
  *     inputs are copied, outputs are written with stream-ordered copies on
  *     the context's stream.  "host pointer" arguments are ordinary memory.
  *   - All calls return a tsm_status; on failure tsm_last_error() gives a
- *     message.  Calls on one context are not thread-safe.
+ *     message (tsm_last_error(NULL): the calling thread's last tsm_create
+ *     failure).  Calls on one context are not thread-safe.
  */
 #ifndef TSM_H
 #define TSM_H
@@ -65,6 +66,9 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
 #define TSM_FLAG_STENCIL_STREAM (1ull << 1) /* force the streamed-stencil micro kernels */
 #define TSM_FLAG_GENERIC    (1ull << 3)  /* solve every mesh size with the one-instance-per-workgroup
                                             kernels (no packed kernels for 16/32/64 cells) */
+#define TSM_FLAG_PERSISTENT (1ull << 4)  /* all packed mesh sizes in ONE persistent launch with a
+                                            work queue (largest meshes first), instead of one
+                                            launch per mesh size */
 #define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
                                             HIP events on the context's stream (see tsm_stats) */
 
@@ -167,8 +171,19 @@ tsm_status tsm_apply_operator(tsm_ctx* c, const double* x, double* y);
 tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda_out);
 
 /* Replace the launch flags (TSM_FLAG_*) of a context; rebuilds the step
- * graph if set_deformation has run.  Results do not depend on the flags. */
+ * graph if set_deformation has run.  Results are bitwise identical under
+ * every flag except TSM_FLAG_GENERIC, whose different summation order
+ * changes them within the solver tolerance. */
 tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags);
+
+/* Autotuner: time the launch plans {one launch per mesh size, one persistent
+ * launch for all sizes, the one-instance-per-workgroup kernels} for
+ * `steps` steps each (after one warm-up step) from the current state,
+ * restore the state after each, and keep the fastest plan.  The timings
+ * (ms per step, -1 where a plan does not apply) go to ms_out[3] (host,
+ * may be NULL) and the chosen TSM_FLAG_* bits to *flags_out (host, may be
+ * NULL).  Needs set_state first. */
+tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* flags_out);
 
 tsm_status tsm_get_stats(const tsm_ctx* c, tsm_stats* s);
 const char* tsm_last_error(const tsm_ctx* c);

@@ -34,11 +34,13 @@ class TwoScaleBatch:
         prm.max_iter, prm.max_refine, prm.checkpoint_every = int(max_iter), int(max_refine), int(checkpoint_every)
         prm.flags = int(flags)
         self.params = prm
+        self._flags = int(flags)
         self.n_inst = (int(macro_cells) + 1) ** 2
         with torch.cuda.device(self.device):
             self.ctx = tsm.tsm_create(prm, None)
         try:
-            tsm.tsm_set_reference_mesh(self.ctx, np.asarray(micro_cells, dtype=np.int32))
+            self._levels = np.asarray(micro_cells, dtype=np.int32)
+            tsm.tsm_set_reference_mesh(self.ctx, self._levels)
             self.offsets = tsm.tsm_get_offsets(self.ctx, self.n_inst)
             self.n_micro = int(self.offsets[-1])
             self.set_deformation(a, theta)
@@ -100,6 +102,40 @@ class TwoScaleBatch:
 
     def set_flags(self, flags):
         tsm.tsm_set_flags(self.ctx, flags)
+        self._flags = int(flags)
+
+    def autotune(self, steps=2, cache=None):
+        """Pick the fastest launch plan on the current state (which is left
+        unchanged).  With `cache` (a JSON path), a plan measured before for
+        the same device, precision and mesh-size histogram is reused."""
+        import json
+        import os
+        import numpy as np
+        key = None
+        if cache is not None:
+            levels, counts = np.unique(np.asarray(self._levels), return_counts=True)
+            key = "|".join([self.torch.cuda.get_device_name(self.device), str(self.params.precision),
+                            str(self.params.macro_cells),
+                            ",".join(f"{l}x{c}" for l, c in zip(levels.tolist(), counts.tolist()))])
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    rec = json.load(fh)
+                if key in rec:
+                    plan_bits = tsm.TSM_FLAG_PERSISTENT | tsm.TSM_FLAG_GENERIC
+                    self.set_flags((self._flags & ~plan_bits) | int(rec[key]["flags"]))
+                    return rec[key]
+        ms, flags = tsm.tsm_autotune(self.ctx, steps)
+        self._flags = (self._flags & ~(tsm.TSM_FLAG_PERSISTENT | tsm.TSM_FLAG_GENERIC | tsm.TSM_FLAG_TIMING)) | flags
+        res = {"flags": flags, "ms_per_step": {"per_size": ms[0], "persistent": ms[1], "generic": ms[2]}}
+        if cache is not None:
+            rec = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    rec = json.load(fh)
+            rec[key] = res
+            with open(cache, "w") as fh:
+                json.dump(rec, fh, indent=1)
+        return res
 
     def stats(self):
         return tsm.tsm_get_stats(self.ctx)

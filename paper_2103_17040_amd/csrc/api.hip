@@ -60,7 +60,9 @@ struct tsm_ctx {
     std::vector<Group> groups;        // generic kernels: one launch per slot class
     int n_packs = 0;                  // packed kernels: one launch per mesh size
     std::vector<std::array<int, 3>> pack_groups;   // (level, first pack, pack count)
-    int32_t *pk_first = nullptr, *pk_count = nullptr;
+    int32_t *pk_first = nullptr, *pk_count = nullptr, *pk_level = nullptr, *queue = nullptr;
+    size_t pack_lds_max = 0;
+    int n_cu = 0;
 
     // per instance
     int32_t *level = nullptr, *order = nullptr, *iters = nullptr, *sweeps = nullptr, *counters = nullptr;
@@ -101,7 +103,7 @@ struct tsm_ctx {
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32); dfree(Slo);
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
-        dfree(pk_first); dfree(pk_count);
+        dfree(pk_first); dfree(pk_count); dfree(pk_level);
         dfree(dS64); dfree(dM64); dfree(db); dfree(dlen); dfree(jmin_d);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
         have_deriv = false;
@@ -150,12 +152,25 @@ namespace {
 // generic launch per remaining slot class.  setup: FP64 whatever the precision.
 tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
     const bool refine = c->prm.precision == TSM_FP32_REFINE && !setup;
-    for (const auto& pg : c->pack_groups) {
-        PackList pl{pg[2], c->pk_first + pg[1], c->pk_count + pg[1]};
+    if ((c->prm.flags & TSM_FLAG_PERSISTENT) && c->n_packs > 0) {
+        // one persistent launch over every pack; the queue is reset by a
+        // kernel so the sequence can be captured in a graph
+        PackList pl{c->n_packs, c->pk_first, c->pk_count};
         MicroArgs a = base;
         a.n_tasks = (int)c->n_inst;
         a.order = c->order;
-        HIPCHK(launch_packed(a, pl, pg[0], refine ? 2 : 1, pg[2], c->stream));
+        a.queue = c->queue;
+        HIPCHK(launch_fill_i32(c->queue, 0, 1, c->stream));
+        HIPCHK(launch_packed_mixed(a, pl, c->pk_level, refine ? 2 : 1, std::min(c->n_packs, c->n_cu),
+                                   c->pack_lds_max, c->stream));
+    } else {
+        for (const auto& pg : c->pack_groups) {
+            PackList pl{pg[2], c->pk_first + pg[1], c->pk_count + pg[1]};
+            MicroArgs a = base;
+            a.n_tasks = (int)c->n_inst;
+            a.order = c->order;
+            HIPCHK(launch_packed(a, pl, pg[0], refine ? 2 : 1, pg[2], c->stream));
+        }
     }
     for (const Group& g : c->groups) {
         MicroArgs a = base;
@@ -184,9 +199,10 @@ tsm_status plan_tasks(tsm_ctx* c) {
         if (px != py) return px;
         return c->level_h[x] > c->level_h[y];
     });
-    std::vector<int32_t> pf, pc;
+    std::vector<int32_t> pf, pc, pv;
     int64_t t = 0;
     c->pack_groups.clear();
+    c->pack_lds_max = 0;
     while (t < n_inst && packable(c->order_h[t])) {
         const int lvl = c->level_h[c->order_h[t]];
         const int cap = packed_capacity(lvl);
@@ -198,6 +214,8 @@ tsm_status plan_tasks(tsm_ctx* c) {
         c->pack_groups.back()[2]++;
         pf.push_back((int32_t)t);
         pc.push_back(cnt);
+        pv.push_back(lvl);
+        c->pack_lds_max = std::max(c->pack_lds_max, packed_lds_bytes(lvl));
         t += cnt;
     }
     c->n_packs = (int)pf.size();
@@ -219,9 +237,10 @@ tsm_status plan_tasks(tsm_ctx* c) {
         }
         c->groups.back().count++;
     }
-    dfree(c->pk_first); dfree(c->pk_count);
+    dfree(c->pk_first); dfree(c->pk_count); dfree(c->pk_level);
     if (c->n_packs > 0) {
-        HIPALLOC(c->pk_first, c->n_packs); HIPALLOC(c->pk_count, c->n_packs);
+        HIPALLOC(c->pk_first, c->n_packs); HIPALLOC(c->pk_count, c->n_packs); HIPALLOC(c->pk_level, c->n_packs);
+        HIPCHK(hipMemcpy(c->pk_level, pv.data(), pv.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(c->pk_first, pf.data(), pf.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(c->pk_count, pc.data(), pc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
@@ -337,34 +356,52 @@ void tsm_default_params(tsm_params* p) {
     p->flags = 0;
 }
 
+namespace {
+thread_local std::string g_create_error = "no error";   // tsm_last_error(NULL)
+
+tsm_status create_failed(tsm_ctx* c, tsm_status st, const std::string& msg) {
+    g_create_error = msg;
+    if (c) tsm_destroy(c);
+    return st;
+}
+}  // namespace
+
 tsm_status tsm_create(const tsm_params* p, void* stream, tsm_ctx** out) {
-    if (!out) return TSM_EINVAL;
+    if (!out) return create_failed(nullptr, TSM_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!p) return TSM_EINVAL;
+    if (!p) return create_failed(nullptr, TSM_EINVAL, "params is NULL");
     const bool ok = p->macro_cells >= 2 && p->macro_cells <= 1024 && p->D > 0 && p->d > 0 && p->kappa >= 0 &&
                     p->p > 0 && p->dt > 0 && (p->source_sign == 1 || p->source_sign == -1) &&
                     (p->precision == TSM_FP64 || p->precision == TSM_FP32_REFINE) && p->rtol > 0 &&
                     p->inner_rtol > 0 && p->inner_rtol < 1 && p->setup_rtol > 0 && p->max_iter >= 1 &&
                     p->max_refine >= 1 && p->checkpoint_every >= 1 && std::isfinite(p->D) &&
                     std::isfinite(p->d) && std::isfinite(p->kappa) && std::isfinite(p->p) && std::isfinite(p->dt);
-    if (!ok) return TSM_EINVAL;
+    if (!ok) return create_failed(nullptr, TSM_EINVAL, "parameter out of range");
     tsm_ctx* c = new tsm_ctx();
     c->prm = *p;
     c->NM = p->macro_cells;
     if (stream) {
         c->stream = (hipStream_t)stream;
     } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        const hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
             delete c;
-            return TSM_EHIP;
+            return create_failed(nullptr, TSM_EHIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
         }
         c->own_stream = true;
     }
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-        dalloc(&c->counters, 4) != hipSuccess) {
-        tsm_destroy(c);
-        return TSM_EHIP;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return create_failed(c, TSM_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || c->n_cu <= 0)
+        return create_failed(c, TSM_EHIP, std::string("compute unit count: ") + hipGetErrorString(e));
+    if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess ||
+        (e = dalloc(&c->counters, 4)) != hipSuccess || (e = dalloc(&c->queue, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return create_failed(c, TSM_EHIP, std::string("context resources: ") + hipGetErrorString(e));
     }
+    g_create_error = "no error";
     *out = c;
     return TSM_OK;
 }
@@ -818,6 +855,8 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
 tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
     if (!c) return TSM_EINVAL;
     const bool replan = ((flags ^ c->prm.flags) & (TSM_FLAG_STENCIL_STREAM | TSM_FLAG_GENERIC)) != 0;
+    if (flags & ~(TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_TIMING | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT))
+        return c->fail(TSM_EINVAL, "unknown flag bits");
     HIPCHK(hipStreamSynchronize(c->stream));
     c->prm.flags = flags;
     if (replan && c->have_mesh) {
@@ -826,6 +865,57 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
     }
     if (c->have_geom) return build_graph(c);
     return TSM_OK;
+}
+
+tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* flags_out) {
+    if (!c) return TSM_EINVAL;
+    if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
+    if (steps < 1) return c->fail(TSM_EINVAL, "steps < 1");
+    const int64_t ni = c->n_inst, tot = c->total;
+    // plans are timed with the whole-step events (TSM_FLAG_TIMING would turn the graph off)
+    const uint64_t timing = c->prm.flags & TSM_FLAG_TIMING;
+    const uint64_t keep = c->prm.flags & ~(TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT | TSM_FLAG_TIMING);
+    const uint64_t plans[3] = {0, TSM_FLAG_PERSISTENT, TSM_FLAG_GENERIC};
+    double ms[3] = {-1.0, -1.0, -1.0};
+    double *su = nullptr, *sv = nullptr, *sF = nullptr;
+    if (dalloc(&su, ni) != hipSuccess || dalloc(&sv, tot) != hipSuccess || dalloc(&sF, ni) != hipSuccess) {
+        (void)hipGetLastError();
+        dfree(su); dfree(sv); dfree(sF);
+        return c->fail(TSM_ENOMEM, "autotune state copy");
+    }
+    auto copy = [&](double* du, double* dv, double* dF, const double* u, const double* v, const double* F) {
+        return hipMemcpyAsync(du, u, ni * sizeof(double), hipMemcpyDeviceToDevice, c->stream) == hipSuccess &&
+               hipMemcpyAsync(dv, v, tot * sizeof(double), hipMemcpyDeviceToDevice, c->stream) == hipSuccess &&
+               hipMemcpyAsync(dF, F, ni * sizeof(double), hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
+    };
+    tsm_status st = TSM_OK;
+    const int64_t taken = c->steps_taken;
+    if (!copy(su, sv, sF, c->u, c->v0, c->F)) st = c->fail(TSM_EHIP, "autotune: state copy");
+    int best = -1;
+    for (int k = 0; k < 3 && st == TSM_OK; ++k) {
+        if (plans[k] == TSM_FLAG_PERSISTENT && c->n_packs == 0) continue;   // same as plan 0
+        if (plans[k] == TSM_FLAG_GENERIC && c->n_packs == 0) continue;      // already generic
+        st = tsm_set_flags(c, keep | plans[k]);
+        if (st != TSM_OK) break;
+        tsm_status s1 = tsm_step(c, 1);                  // warm-up (and code load)
+        if (s1 != TSM_OK && s1 != TSM_ENOCONV) { st = s1; break; }
+        s1 = tsm_step(c, steps);
+        if (s1 != TSM_OK && s1 != TSM_ENOCONV) { st = s1; break; }
+        ms[k] = c->step_ms / steps;
+        if (best < 0 || ms[k] < ms[best]) best = k;
+        if (!copy(c->u, c->v0, c->F, su, sv, sF)) st = c->fail(TSM_EHIP, "autotune: state restore");
+    }
+    if (st == TSM_OK) {
+        if (best < 0) best = 0;
+        st = tsm_set_flags(c, keep | timing | plans[best]);
+        (void)hipStreamSynchronize(c->stream);
+        c->steps_taken = taken;
+        if (ms_out) std::memcpy(ms_out, ms, sizeof(ms));
+        if (flags_out) *flags_out = plans[best];
+    }
+    (void)hipStreamSynchronize(c->stream);
+    dfree(su); dfree(sv); dfree(sF);
+    return st;
 }
 
 tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
@@ -863,7 +953,7 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
     return TSM_OK;
 }
 
-const char* tsm_last_error(const tsm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* tsm_last_error(const tsm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 void tsm_destroy(tsm_ctx* c) {
     if (!c) return;
@@ -871,6 +961,7 @@ void tsm_destroy(tsm_ctx* c) {
     c->free_mesh();
     c->free_macro();
     dfree(c->counters);
+    dfree(c->queue);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);

@@ -549,6 +549,41 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
     }
 }
 
+// All mesh sizes in ONE persistent launch: every workgroup pops packs from a
+// work queue (packs in largest-first order) until the queue is empty; the
+// register allocation is the largest of the three size paths.
+template <int MODE>
+__global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList P, const int32_t* pack_level) {
+    extern __shared__ double lds[];
+    __shared__ double r1[2][1][NWP];
+    __shared__ double r3[2][3][NWP];
+    __shared__ float f1[2][1][NWP];
+    __shared__ float f3[2][3][NWP];
+    __shared__ int task_s;
+    PackRed<1, double> red1(r1);
+    PackRed<3, double> red3(r3);
+    PackRed<1, float> rf1(f1);
+    PackRed<3, float> rf3(f3);
+    for (;;) {
+        if (threadIdx.x == 0) task_s = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int task = task_s;
+        __syncthreads();
+        if (task >= P.n_packs) break;
+        const int lvl = pack_level[task], first = P.first[task], cnt = P.count[task];
+        if constexpr (MODE == 2) {
+            if (lvl == 64) pack_refine<L64>(A, first, cnt, lds, red1, red3, rf1, rf3);
+            else if (lvl == 32) pack_refine<L32>(A, first, cnt, lds, red1, red3, rf1, rf3);
+            else pack_refine<L16>(A, first, cnt, lds, red1, red3, rf1, rf3);
+        } else {
+            if (lvl == 64) pack_fp64<L64>(A, first, cnt, lds, red1, red3);
+            else if (lvl == 32) pack_fp64<L32>(A, first, cnt, lds, red1, red3);
+            else pack_fp64<L16>(A, first, cnt, lds, red1, red3);
+        }
+        __syncthreads();
+    }
+}
+
 template <class L>
 hipError_t launch_level(const MicroArgs& a, const PackList& p, int mode, int grid, hipStream_t s) {
     const size_t lds = sizeof(double) * L::GRID * L::IPP;
@@ -575,6 +610,15 @@ size_t packed_lds_bytes(int level) {
         case 64: return sizeof(double) * L64::GRID * L64::IPP;
         default: return 0;
     }
+}
+
+hipError_t launch_packed_mixed(const MicroArgs& a, const PackList& p, const int32_t* pack_level, int mode,
+                               int grid, size_t lds, hipStream_t s) {
+    if (p.n_packs <= 0 || grid <= 0 || a.queue == nullptr) return hipSuccess;
+    if (mode == 2) hipLaunchKernelGGL(packed_mixed_kernel<2>, dim3(grid), dim3(NTP), lds, s, a, p, pack_level);
+    else if (mode == 1) hipLaunchKernelGGL(packed_mixed_kernel<1>, dim3(grid), dim3(NTP), lds, s, a, p, pack_level);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_packed(const MicroArgs& a, const PackList& p, int level, int mode, int grid, hipStream_t s) {

@@ -100,6 +100,9 @@ hipError_t launch_assemble_da(const AssembleArgs& a, hipStream_t s);
 hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_t lds_bytes, hipStream_t s);
 // packs of one mesh size (16, 32 or 64); mode 1 FP64, 2 refinement
 hipError_t launch_packed(const MicroArgs& a, const PackList& p, int level, int mode, int grid, hipStream_t s);
+// every pack of every size in one persistent launch (work queue a.queue, reset to 0 beforehand)
+hipError_t launch_packed_mixed(const MicroArgs& a, const PackList& p, const int32_t* pack_level, int mode,
+                               int grid, size_t lds, hipStream_t s);
 int packed_capacity(int level);          // instances per pack (0: no packed kernel for this size)
 size_t packed_lds_bytes(int level);      // dynamic LDS of one pack
 hipError_t launch_apply(int n_inst, const int32_t* level, const int64_t* offsets,

@@ -12,6 +12,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch ships its own HIP runtime.  Loading torch first makes libtsm bind to
+# that same runtime (same soname); a second copy loaded from the ROCm tree
+# would not see the device once torch's copy owns it.
+import torch  # noqa: F401
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtsm.so")
 
@@ -21,13 +25,14 @@ TSM_FLAG_NO_GRAPH = 1 << 0
 TSM_FLAG_STENCIL_STREAM = 1 << 1
 TSM_FLAG_TIMING = 1 << 2
 TSM_FLAG_GENERIC = 1 << 3
+TSM_FLAG_PERSISTENT = 1 << 4
 
 STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV",
                 -4: "TSM_EHIP", -5: "TSM_ENOMEM", -6: "TSM_ESTATE"}
 
 EXPORTED = ["tsm_default_params", "tsm_create", "tsm_set_reference_mesh", "tsm_get_offsets",
             "tsm_set_deformation", "tsm_set_state", "tsm_step", "tsm_get_macro", "tsm_get_fluxes",
-            "tsm_get_micro", "tsm_get_setup", "tsm_apply_operator", "tsm_gradient", "tsm_set_flags", "tsm_get_stats",
+            "tsm_get_micro", "tsm_get_setup", "tsm_apply_operator", "tsm_gradient", "tsm_set_flags", "tsm_autotune", "tsm_get_stats",
             "tsm_last_error", "tsm_destroy"]
 
 
@@ -78,6 +83,7 @@ def _load():
         "tsm_apply_operator": (I32, [P, VP, VP]),
         "tsm_gradient": (I32, [P, I32, ctypes.POINTER(D), VP]),
         "tsm_set_flags": (I32, [P, ctypes.c_uint64]),
+        "tsm_autotune": (I32, [P, I32, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_uint64)]),
         "tsm_get_stats": (I32, [P, ctypes.POINTER(tsm_stats)]),
         "tsm_last_error": (ctypes.c_char_p, [P]),
         "tsm_destroy": (None, [P]),
@@ -116,7 +122,7 @@ def tsm_create(params: tsm_params, stream=None):
     out = ctypes.c_void_p()
     st = _lib.tsm_create(ctypes.byref(params), stream, ctypes.byref(out))
     if st != TSM_OK:
-        raise TsmError(st, "tsm_create rejected the parameters")
+        raise TsmError(st, "tsm_create: " + _lib.tsm_last_error(None).decode())
     return out.value
 
 
@@ -175,6 +181,14 @@ def tsm_gradient(ctx, n_steps: int, dJda_out) -> float:
 
 def tsm_set_flags(ctx, flags: int) -> None:
     _check(ctx, _lib.tsm_set_flags(ctx, int(flags)))
+
+
+def tsm_autotune(ctx, steps: int):
+    """Returns (ms per step of each plan [per-size, persistent, generic], chosen flags)."""
+    ms = (ctypes.c_double * 3)()
+    fl = ctypes.c_uint64()
+    _check(ctx, _lib.tsm_autotune(ctx, int(steps), ms, ctypes.byref(fl)))
+    return list(ms), fl.value
 
 
 def tsm_get_stats(ctx) -> dict:

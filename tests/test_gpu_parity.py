@@ -97,16 +97,20 @@ def test_sign_plus_one_and_kappa_zero():
 
 
 def test_forms_agree_bitwise():
-    """Graph replay, direct launches, the timing form and the streamed-stencil
-    switch compute the same sums in the same order: outputs are bitwise
-    identical, and two runs are bitwise identical (no atomics in any sum)."""
+    """Graph replay, direct launches, the timing form, the streamed-stencil
+    switch and the single persistent launch over all mesh sizes compute the
+    same sums in the same order: outputs are bitwise identical, and two runs
+    are bitwise identical (no atomics in any sum; the persistent launch's
+    queue only decides which workgroup takes a pack)."""
     from paper_2103_17040_amd import tsm
     lv, a, th = _ragged(5, [8, 16, 32, 64], 41)
     u0 = W.initial_macro(5)
     v0 = np.zeros(int(W.offsets(lv)[-1]))
     outs = []
     for prec in ("fp64", "fp32_refine"):
-        for flags in (0, 0, tsm.TSM_FLAG_NO_GRAPH, tsm.TSM_FLAG_STENCIL_STREAM, tsm.TSM_FLAG_TIMING):
+        for flags in (0, 0, tsm.TSM_FLAG_NO_GRAPH, tsm.TSM_FLAG_STENCIL_STREAM, tsm.TSM_FLAG_TIMING,
+                      tsm.TSM_FLAG_PERSISTENT, tsm.TSM_FLAG_PERSISTENT | tsm.TSM_FLAG_NO_GRAPH,
+                      tsm.TSM_FLAG_PERSISTENT | tsm.TSM_FLAG_STENCIL_STREAM):
             banner(f"forms {prec} flags={flags}")
             g = gpu_for(5, lv, a, th, 0.005, precision=prec, rtol=1e-10, flags=flags)
             try:
