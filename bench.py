@@ -38,18 +38,34 @@ PEAK_ALU_TFLOPS = 78.6
 # Algorithmic work per micro DoF-update of the micro kernel.
 # Flops: per PCG iteration 9-point stencil (9 FMA), p.q, x/d update, r update,
 # z = D^{-1} r, r.z, r.r, p update = 15 FMA + 1 MUL = 31 flops; per FP64
-# residual sweep 9 FMA + 1 SUB + 1 FMA (norm) + 1 FMA (x += ||r|| d) = 23 flops;
-# per solve M x0/dt, b^T x, x0 = X0 + u w = 23 flops.
-FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 23.0, 23.0
+# residual update of the refinement S d with S = S32 + Slo (9 ADD + 9 FMA),
+# r -= ||r|| S d, r.r, x += ||r|| d = 33 flops; per solve x0 = X0 + u w,
+# K x0, M x0 (9 FMA each), ||b||^2 and ||r||^2 = 43 flops.
+FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 33.0, 43.0
 # Bytes the instance-resident micro kernel must move per DoF per step
-# (algorithmic: the vectors of the iterations stay on chip).
-#   both forms: x0 = v0 + u w (read v0, w: 16), b = M x0/dt (FP64 mass
-#               stencil, 72), r = b - S x0 (FP64 stencil, 72), write x and
-#               read b for the flux average (16)
-#   refine:     the FP32 stencil once (36) and, per residual update after an
-#               inner solve, the FP32 low part of the stencil (36)
-#   FP64:       the FP64 stencil once per PCG iteration (72)
-B_START, B_MASS, B_S64, B_S32, B_SLO, B_END = 16.0, 72.0, 72.0, 36.0, 36.0, 16.0
+# (algorithmic: the vectors of the iterations stay on chip; operators are read
+# from their symmetric upper-half planes, 5 coefficients per node):
+#   both forms: x0 = v0 + u w (read v0, w: 16), r = -K x0 (FP64 K, 40),
+#               ||b|| = ||M x0||/dt (FP32 M, 20), write x and read b for the
+#               flux average (16)
+#   refine:     the FP32 stencil once (20) and, per residual update after an
+#               inner solve, the FP32 low part of the stencil (20)
+#   FP64:       the FP64 stencil once per PCG iteration (40) and its centre
+#               plane once for diag^{-1} (8)
+B_START, B_K, B_M32, B_END = 16.0, 40.0, 20.0, 16.0
+B_S64, B_DIAG, B_S32, B_SLO = 40.0, 8.0, 20.0, 20.0
+
+
+def streaming_bytes(refine, iters, sweeps):
+    """Bytes per DoF-update of a PCG that streams its vectors through HBM
+    every iteration (10 words per iteration for a two-pass fused PCG, the FP64
+    residual sweeps at 6 words, 3 state words): the reference bandwidth model
+    the resident kernel is compared with."""
+    if refine:
+        return iters * 10 * 4 + max(sweeps - 1, 1) * 6 * 8 + 3 * 8
+    return iters * 10 * 8 + 3 * 8
+
+
 KERNEL_SOURCES = ("micro_packed.hip", "device_common.h", "tsm_internal.h")
 COUNTERS = os.path.join(ROOT, "profiles", "micro_kernel_counters.json")
 
@@ -82,7 +98,7 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0):
+def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, autotune=True):
     import torch
     from paper_2103_17040_amd import TwoScaleBatch, tsm
     g = TwoScaleBatch(w.macro_cells, lv, a, th, D=w.D, d=w.d, kappa=w.kappa, p=w.p, dt=w.dt,
@@ -93,6 +109,9 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0):
         u0 = W.initial_macro(w.macro_cells)
         g.set_state(u0, None)
         g.step(warmup)
+        # launch plan: per-size launches, one persistent launch, or the
+        # one-instance-per-workgroup kernels, timed on this state (restored)
+        plan = g.autotune(steps=3) if autotune else {"flags": 0, "ms_per_step": None}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g.step(steps)
@@ -100,10 +119,10 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0):
         t = time.perf_counter() - t0
         st = g.stats()
         # roofline pass: same steps, direct launches bracketed by HIP events
-        g.set_flags(tsm.TSM_FLAG_TIMING)
+        g.set_flags(tsm.TSM_FLAG_TIMING | plan["flags"])
         g.step(steps)
         tst = g.stats()
-        g.set_flags(0)
+        g.set_flags(plan["flags"])
         adj = None
         if adjoint_steps > 0:
             # gradient of int u(T)^2 from the initial state: checkpointed
@@ -118,7 +137,10 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0):
             adj = {"steps": adjoint_steps, "checkpoint_every": max(w.checkpoint_every, 1),
                    "J": J, "grad_norm": float(dJ.norm()), "wall_s": tg,
                    "forward_ms": gs["grad_forward_ms"], "backward_ms": gs["grad_backward_ms"]}
-        return {"t": t, "setup_ms": setup_ms, "stats": st, "timing": tst, "n_dofs": g.n_micro, "adjoint": adj}
+        names = {0: "per_size", tsm.TSM_FLAG_PERSISTENT: "persistent", tsm.TSM_FLAG_GENERIC: "generic"}
+        plan = {"plan": names.get(plan["flags"], str(plan["flags"])), "ms_per_step": plan["ms_per_step"]}
+        return {"t": t, "setup_ms": setup_ms, "stats": st, "timing": tst, "n_dofs": g.n_micro, "adjoint": adj,
+                "plan": plan}
     finally:
         g.close()
 
@@ -207,13 +229,13 @@ def main():
     micro_ms_per_launch = tst["micro_ms"] / max(launches, 1)
     st = main_form["stats"]
     iters = st["iters_mean"]
-    sweeps = st["sweeps_max"] if refine else 0
+    sweeps = st["sweeps_mean"] if refine else 0
     dofs_per_launch = n_dofs / max(tst["micro_launches"], 1)
     flops = dofs_per_launch * (FLOP_ITER * iters + FLOP_SWEEP * sweeps + FLOP_SOLVE)
     if refine:
-        nbytes = dofs_per_launch * (B_START + B_MASS + B_S64 + B_S32 + B_SLO * max(sweeps - 1, 0) + B_END)
+        nbytes = dofs_per_launch * (B_START + B_K + B_M32 + B_S32 + B_SLO * max(sweeps - 1, 0) + B_END)
     else:
-        nbytes = dofs_per_launch * (B_START + B_MASS + B_S64 + B_S64 * iters + B_END)
+        nbytes = dofs_per_launch * (B_START + B_K + B_M32 + B_DIAG + B_S64 * iters + B_END)
     t_launch = micro_ms_per_launch * 1e-3
     alu = flops / t_launch / 1e12
     hbm = nbytes / t_launch / 1e9
@@ -224,7 +246,11 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": hbm / PEAK_HBM_GBS, "traffic": traffic}
-    roof.update({"kernel": "packed_kernel (micro PCG)", "launch_ms": micro_ms_per_launch,
+    kname = {"per_size": "packed_kernel (micro PCG)", "persistent": "packed_mixed_kernel (micro PCG)",
+             "generic": "micro_kernel (micro PCG)"}[main_form["plan"]["plan"]]
+    stream_gbs = dofs_per_launch * streaming_bytes(refine, iters, sweeps) / t_launch / 1e9
+    roof.update({"kernel": kname, "launch_ms": micro_ms_per_launch,
+                 "streaming_pcg_model_GBs": stream_gbs, "streaming_pcg_model_frac": stream_gbs / PEAK_HBM_GBS,
                  "algorithmic_bytes_per_launch": nbytes, "algorithmic_flops_per_launch": flops,
                  "hbm_model_GBs": hbm, "alu_model_TFLOPs": alu,
                  "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"})
@@ -246,8 +272,10 @@ def main():
                    "micro_dofs": n_dofs, "dt": w.dt, "rtol": w.rtol, "precision": w.precision,
                    "seed": args.seed},
         "iters_mean": iters, "iters_max": st["iters_max"], "sweeps_max": st["sweeps_max"],
+        "sweeps_mean": st["sweeps_mean"],
         "setup_ms": main_form["setup_ms"],
         "macro_ms_per_step": tst["macro_ms"] / max(tst["timed_steps"], 1),
+        "launch_plan": main_form["plan"],
         "roofline": roof,
     }
     if fp64 is not None:

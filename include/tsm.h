@@ -82,7 +82,10 @@ typedef struct {
     int32_t source_sign;     /* -1 (paper's sink) or +1 */
     int32_t precision;       /* TSM_FP64 or TSM_FP32_REFINE */
     double rtol;             /* micro step solves: ||b - S x||_2 <= rtol ||b||_2 */
-    double inner_rtol;       /* FP32 inner solves (refinement mode) */
+    double inner_rtol;       /* FP32 inner solves (refinement mode): the loosest
+                                relative tolerance of one inner solve; each one
+                                is solved to half of what the FP64 residual test
+                                still needs, but no tighter than 2^-20 */
     double setup_rtol;       /* response solves w_i at setup */
     int32_t max_iter;        /* PCG iterations per solve (per inner solve) */
     int32_t max_refine;      /* FP64 refinement sweeps (refinement mode) */
@@ -108,12 +111,14 @@ typedef struct {
     int32_t micro_launches;      /* micro kernel launches per step (one per mesh-size class) */
     double grad_forward_ms;      /* last tsm_gradient: forward with checkpoints */
     double grad_backward_ms;     /* last tsm_gradient: segment recompute + adjoint + gradient */
+    double sweeps_mean;          /* refinement sweeps of the last step, mean over instances
+                                    (1 + the inner solves of an instance) */
 } tsm_stats;
 
 typedef struct tsm_ctx tsm_ctx;
 
 /* Fill *p with the defaults: kappa = p = 1, D = 1, d = 0.5, dt = 0.01,
- * source_sign = -1, FP64, rtol 1e-12, inner_rtol 1e-5, setup_rtol 1e-14,
+ * source_sign = -1, FP64, rtol 1e-12, inner_rtol 1e-2, setup_rtol 1e-14,
  * max_iter 1000, max_refine 12, checkpoint_every 10, flags 0. */
 void tsm_default_params(tsm_params* p);
 

@@ -66,12 +66,16 @@ struct tsm_ctx {
 
     // per instance
     int32_t *level = nullptr, *order = nullptr, *iters = nullptr, *sweeps = nullptr, *counters = nullptr;
+    int64_t* order_off = nullptr;   // offsets[order[t]]
     int64_t* offsets = nullptr;
     double *amp = nullptr, *beta = nullptr, *len = nullptr, *jmin = nullptr, *bx = nullptr,
            *alpha = nullptr, *F = nullptr, *u = nullptr;
     // ragged
     double *S64 = nullptr, *M64 = nullptr, *b = nullptr, *w = nullptr, *v0 = nullptr;
     float *S32 = nullptr, *Slo = nullptr;
+    // symmetric upper-half planes [kSym][n] of S, K = S - M/dt, M (FP32), S split in FP32
+    double *Ss64 = nullptr, *Ks64 = nullptr;
+    float *Ms32 = nullptr, *Ss32 = nullptr, *Sslo = nullptr;
     // tables
     int32_t* tab_off = nullptr;
     double *tab_y = nullptr, *tab_s = nullptr, *tab_c = nullptr;
@@ -99,7 +103,8 @@ struct tsm_ctx {
         return s;
     }
     void free_mesh() {
-        dfree(level); dfree(order); dfree(iters); dfree(sweeps); dfree(offsets);
+        dfree(level); dfree(order); dfree(order_off); dfree(iters); dfree(sweeps); dfree(offsets);
+        dfree(Ss64); dfree(Ks64); dfree(Ms32); dfree(Ss32); dfree(Sslo);
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32); dfree(Slo);
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
@@ -159,6 +164,7 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
         MicroArgs a = base;
         a.n_tasks = (int)c->n_inst;
         a.order = c->order;
+        a.order_off = c->order_off;
         a.queue = c->queue;
         HIPCHK(launch_fill_i32(c->queue, 0, 1, c->stream));
         HIPCHK(launch_packed_mixed(a, pl, c->pk_level, refine ? 2 : 1, std::min(c->n_packs, c->n_cu),
@@ -169,6 +175,7 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
             MicroArgs a = base;
             a.n_tasks = (int)c->n_inst;
             a.order = c->order;
+            a.order_off = c->order_off;
             HIPCHK(launch_packed(a, pl, pg[0], refine ? 2 : 1, pg[2], c->stream));
         }
     }
@@ -245,7 +252,11 @@ tsm_status plan_tasks(tsm_ctx* c) {
         HIPCHK(hipMemcpy(c->pk_count, pc.data(), pc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
     if (!c->order) HIPALLOC(c->order, n_inst);
+    if (!c->order_off) HIPALLOC(c->order_off, n_inst);
+    std::vector<int64_t> oo(n_inst);
+    for (int64_t i = 0; i < n_inst; ++i) oo[i] = c->off_h[c->order_h[i]];
     HIPCHK(hipMemcpy(c->order, c->order_h.data(), n_inst * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->order_off, oo.data(), n_inst * sizeof(int64_t), hipMemcpyHostToDevice));
     return TSM_OK;
 }
 
@@ -257,6 +268,11 @@ MicroArgs micro_base(tsm_ctx* c) {
     a.S32 = c->S32;
     a.Slo = c->Slo;
     a.M64 = c->M64;
+    a.Ss64 = c->Ss64;
+    a.Ks64 = c->Ks64;
+    a.Ms32 = c->Ms32;
+    a.Ss32 = c->Ss32;
+    a.Sslo = c->Sslo;
     a.b = c->b;
     a.w = c->w;
     a.bx_out = c->bx;
@@ -348,7 +364,7 @@ void tsm_default_params(tsm_params* p) {
     p->source_sign = -1;
     p->precision = TSM_FP64;
     p->rtol = 1e-12;
-    p->inner_rtol = 1e-5;
+    p->inner_rtol = 1e-2;
     p->setup_rtol = 1e-14;
     p->max_iter = 1000;
     p->max_refine = 12;
@@ -452,6 +468,8 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPALLOC(c->bx, ni); HIPALLOC(c->alpha, ni); HIPALLOC(c->F, ni); HIPALLOC(c->u, ni);
     HIPALLOC(c->S64, kStencil * tot); HIPALLOC(c->M64, kStencil * tot); HIPALLOC(c->S32, kStencil * tot);
     HIPALLOC(c->Slo, kStencil * tot);
+    HIPALLOC(c->Ss64, kSym * tot); HIPALLOC(c->Ks64, kSym * tot); HIPALLOC(c->Ms32, kSym * tot);
+    HIPALLOC(c->Ss32, kSym * tot); HIPALLOC(c->Sslo, kSym * tot);
     HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot);
     HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());
@@ -510,6 +528,7 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
     as.kappa = c->prm.kappa;
     as.inv_dt = 1.0 / c->prm.dt;
     as.S64 = c->S64; as.S32 = c->S32; as.Slo = c->Slo; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
+    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ms32 = c->Ms32; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
     HIPCHK(launch_assemble(as, c->stream));
     std::vector<double> jm(n_inst);
     HIPCHK(hipMemcpyAsync(jm.data(), c->jmin, n_inst * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -932,7 +951,8 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
     s->micro_ms = c->micro_ms;
     s->macro_ms = c->macro_ms;
     s->timed_steps = c->timed_steps;
-    s->micro_launches = (int32_t)(c->groups.size() + c->pack_groups.size());
+    const size_t packed = ((c->prm.flags & TSM_FLAG_PERSISTENT) && !c->pack_groups.empty()) ? 1 : c->pack_groups.size();
+    s->micro_launches = (int32_t)(c->groups.size() + packed);
     s->grad_forward_ms = c->grad_fwd_ms;
     s->grad_backward_ms = c->grad_bwd_ms;
     if (c->have_geom && c->n_inst > 0) {
@@ -948,6 +968,9 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
         for (int32_t v : it) sum += v;
         s->iters_mean = sum / c->n_inst;
         s->sweeps_max = *std::max_element(sw.begin(), sw.end());
+        double ssum = 0;
+        for (int32_t v : sw) ssum += v;
+        s->sweeps_mean = ssum / c->n_inst;
         s->unconverged = nc;
     }
     return TSM_OK;

@@ -8,6 +8,9 @@
 // (at most two) boundary edges at j, with the 2-point rule, the row of
 //     B_i = int_dZ eta eta |cof(F) nu|      (boundary change of variables).
 // Each node gathers its own row -- no atomics, fixed summation order.
+// Besides the full rows (generic kernels, adjoint) it stores the upper half
+// of S, of K = d A + kappa B and of M (FP32) as symmetric planes for the
+// packed kernels.
 // K K^T J and |cof F nu| are evaluated at each point from the amplitude a_i
 // and the per-level sin/cos tables (the paper caches J and K K^T J per
 // quadrature point; here they cost a few flops, so nothing is cached).
@@ -45,9 +48,9 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
     double jmin = 1e300;
     for (int j = threadIdx.x; j < n; j += kMicroThreads) {
         const int j1 = j % NP, j2 = j / NP;
-        double S[kStencil], M[kStencil];
+        double S[kStencil], M[kStencil], K[kStencil];
 #pragma unroll
-        for (int k = 0; k < kStencil; ++k) { S[k] = 0.0; M[k] = 0.0; }
+        for (int k = 0; k < kStencil; ++k) { S[k] = 0.0; M[k] = 0.0; K[k] = 0.0; }
         double bj = 0.0;
         // ---- cells around node j
         for (int dc2 = -1; dc2 <= 0; ++dc2) {
@@ -85,6 +88,7 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                                 const double stiff = wq * (Cg1 * gm1 + Cg2 * gm2);
                                 M[k] += mass;
                                 S[k] += A.d * stiff + A.inv_dt * mass;
+                                K[k] += A.d * stiff;
                             }
                         }
                     }
@@ -109,6 +113,7 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     for (int m1 = 0; m1 < 2; ++m1) {
                         const double v = wb * om * lin(l1, g) * lin(m1, g);
                         S[3 + (m1 - l1 + 1)] += A.kappa * v;
+                        K[3 + (m1 - l1 + 1)] += A.kappa * v;
                         bj += v;
                     }
                 }
@@ -131,6 +136,7 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     for (int m2 = 0; m2 < 2; ++m2) {
                         const double v = wb * om * lin(l2, g) * lin(m2, g);
                         S[(m2 - l2 + 1) * 3 + 1] += A.kappa * v;
+                        K[(m2 - l2 + 1) * 3 + 1] += A.kappa * v;
                         bj += v;
                     }
                 }
@@ -146,6 +152,19 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                 const float hi = (float)S[k];
                 A.S32[kStencil * off + (int64_t)k * n + j] = hi;
                 A.Slo[kStencil * off + (int64_t)k * n + j] = (float)(S[k] - (double)hi);
+            }
+        }
+        if constexpr (!DERIV) {
+#pragma unroll
+            for (int q = 0; q < kSym; ++q) {
+                const int k = 4 + q;
+                const int64_t e = kSym * off + (int64_t)q * n + j;
+                const float hi = (float)S[k];
+                A.Ss64[e] = S[k];
+                A.Ks64[e] = K[k];
+                A.Ms32[e] = (float)M[k];
+                A.Ss32[e] = hi;
+                A.Sslo[e] = (float)(S[k] - (double)hi);
             }
         }
         A.b[off + j] = bj;

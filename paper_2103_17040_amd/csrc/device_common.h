@@ -23,15 +23,16 @@ __device__ __forceinline__ double lin(int l, int g) { return l ? gauss_x(g) : 1.
 // Every lane returns the same bits: each step adds two operands whose order
 // differs between partner lanes only, and IEEE addition commutes.
 // All 64 lanes must be active.
-template <int CTRL>
+// DPP move of v under control CTRL; rows outside ROWMASK read 0.
+template <int CTRL, int ROWMASK = 0xF>
 __device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
 }
-template <int CTRL>
+template <int CTRL, int ROWMASK = 0xF>
 __device__ __forceinline__ double dpp(double v) {
     const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWMASK, 0xF, false);
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 __device__ __forceinline__ float lane_read(float v, int l) {
@@ -51,6 +52,35 @@ __device__ __forceinline__ T wave_sum(T v) {
     v += dpp<0x141>(v);   // row_half_mirror
     v += dpp<0x140>(v);   // row_mirror
     return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+}
+
+// Wavefront sum that ends in lane 63 only (other lanes hold partial sums):
+// the four in-row steps above, then row_bcast:15 adds the sum of each row
+// into the next row (row 3 gets r3 + r2) and row_bcast:31 adds lane 31
+// (r1 + r0) into rows 2 and 3, so lane 63 holds (r3 + r2) + (r1 + r0).  Two
+// DPP steps and no lane reads in place of the four lane reads and three adds
+// of wave_sum.
+template <typename T>
+__device__ __forceinline__ T wave_total_last(T v) {
+    v += dpp<0xB1>(v);
+    v += dpp<0x4E>(v);
+    v += dpp<0x141>(v);
+    v += dpp<0x140>(v);
+    v += dpp<0x142>(v);   // row_bcast:15
+    v += dpp<0x143>(v);   // row_bcast:31
+    return v;
+}
+
+// Sum over aligned groups of G lanes (G = 1, 2, 4, 8 or 16) within each
+// 16-lane row; every lane of a group ends with the same bits.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1..16 lanes");
+    if constexpr (G > 1) v += dpp<0xB1>(v);
+    if constexpr (G > 2) v += dpp<0x4E>(v);
+    if constexpr (G > 4) v += dpp<0x141>(v);
+    if constexpr (G > 8) v += dpp<0x140>(v);
+    return v;
 }
 
 // Sum of NV values over a workgroup of NW waves.  red is a [2][NV][NW] LDS

@@ -19,7 +19,8 @@
 // Precision forms:
 //   FP64      PCG in FP64 until ||b - S x||_2 <= rtol ||b||_2.
 //   REFINE    FP64 residual r = b - S x (FP64 stencil), FP32 PCG on
-//             S d = r / ||r|| to inner_rtol with the FP32 stencil, x += ||r|| d,
+//             S d = r / ||r|| to its own tolerance (inner_tol2) with the FP32
+//             stencil, x += ||r|| d,
 //             repeated until the FP64 residual meets rtol.
 #include "device_common.h"
 
@@ -275,7 +276,7 @@ __device__ void solve_refine(const MicroArgs& A, int inst, double* xs, float* ps
         }
         rf2.sum(f2);
         float rz = f2[0];
-        const float itol2 = (float)(A.inner_rtol * A.inner_rtol) * f2[1];
+        const float itol2 = inner_tol2(A.rtol * A.rtol * bn2, acc[1], A.inner_rtol) * f2[1];
         int it = 0;
         for (;;) {
 #pragma unroll

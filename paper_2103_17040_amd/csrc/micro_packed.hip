@@ -12,20 +12,30 @@
 // Vectors live in an LDS grid with a zero halo (rows past the mesh included),
 // so boundary rows need no bounds checks.
 //
+// Operators are read from their symmetric upper-half planes (kSym): 5 stored
+// coefficients per node instead of 9, so each streamed operator costs 40
+// (FP64) or 20 (FP32) bytes per node; the lower coefficients are loaded from
+// the neighbours' planes (same cache lines as the neighbours' own loads).
+//
 // Register budget (1024 lanes: 128 VGPRs per lane) decides the data flow:
 //   FP64 form     x, r, p, q in FP64 registers, diag^{-1} in FP32 (the
 //                 preconditioner need not be exact), FP64 stencil re-read
 //                 from global memory every iteration.
 //   REFINE form   FP32 stencil and diag^{-1} resident in registers for the
 //                 whole solve; FP32 PCG on S d = r/||r||; the FP64 residual
-//                 is formed once from b = M x0/dt and S x0, then updated as
-//                 r <- r - ||r|| S d with the FP64 stencil (read once per
-//                 sweep), x <- x + ||r|| d, until ||r|| <= rtol ||b||.
+//                 is formed once as r = -K x0 (K = S - M/dt, the right-hand
+//                 side M x0/dt enters only through its norm), then updated
+//                 as r <- r - ||r|| S d with the FP64 stencil (FP32 part in
+//                 registers plus the streamed FP32 low part), x <- x + ||r|| d,
+//                 until ||r|| <= rtol ||b||.
 //
 // Lockstep: all instances of a pack pass the same barriers; an instance
 // that has met its tolerance freezes while the others go on.  Dot products:
-// wavefront butterfly, one LDS exchange per reduction (ping-pong buffer,
-// one barrier), per-instance sums in a fixed order.
+// a DPP wavefront sum ending in lane 63, one LDS exchange (ping-pong buffer,
+// one barrier), a DPP sum over the waves of each instance; fixed order, so
+// every wave of an instance holds the same bits.
+#include <cmath>
+
 #include "device_common.h"
 
 namespace tsm {
@@ -44,44 +54,69 @@ struct Lvl {
     static constexpr int IPP = NTP / TPI_;                  // instances per pack
     static constexpr int GRID = H2 * W2;                    // LDS cells per instance
     static constexpr int n = NP * NP;
+    // DPP group of the second reduction level: the waves of one instance
+    static constexpr int G = IPP == 1 ? 16 : WPI;
     static_assert(NS * NP <= TPI, "strips do not fit the lanes of an instance");
     static_assert(TPI % kWave == 0, "an instance owns whole waves");
+    static_assert(IPP * WPI <= NWP && WPI <= G, "instances must fit one 16-lane DPP row");
 };
 using L16 = Lvl<16, 64, 6>;
 using L32 = Lvl<32, 256, 5>;
 using L64 = Lvl<64, 896, 5>;
 
+// Per-instance sums of NV values (NV <= 4).  Level 1: every wave reduces its
+// lanes into lane 63 (wave_total_last), which writes the NV totals to LDS.
+// Level 2, after the one barrier: lane l < IPP*WPI reads wave l's totals and
+// a DPP sum over groups of G lanes gives every lane of a group its
+// instance's totals; each wave takes them from lane w0 (its first wave).
+// `tail` keeps, per lane of row 0, the group total of value NV-1 for the
+// convergence vote (any_above).  All lanes must call.
 template <int NV, typename T>
 struct PackRed {
-    T (*buf)[NV][NWP];
+    T (*buf)[NWP][4];
     int phase = 0;
-    __device__ PackRed(T (*b)[NV][NWP]) : buf(b) {}
-    // Per-instance sums (instance = waves [w0, w0+wpi)).  All lanes call.
-    __device__ __forceinline__ void sum(T (&v)[NV], int w0, int wpi) {
+    T tail = T(0);
+    __device__ PackRed(T (*b)[NWP][4]) : buf(b) {}
+    template <class L>
+    __device__ __forceinline__ void sum(T (&v)[NV], int w0) {
+        static_assert(NV <= 4, "at most 4 values");
         const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-        if (lane == 0) {
+        for (int i = 0; i < NV; ++i) v[i] = wave_total_last(v[i]);
+        if (lane == kWave - 1) {
 #pragma unroll
-            for (int i = 0; i < NV; ++i) buf[phase][i][wid] = v[i];
+            for (int i = 0; i < NV; ++i) buf[phase][wid][i] = v[i];
         }
         __syncthreads();
+        const bool has = lane < L::IPP * L::WPI;
+        const T* slot = buf[phase][lane & (NWP - 1)];   // in bounds for every lane
+        T t[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) t[i] = slot[i];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) t[i] = has ? t[i] : T(0);
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            T s = buf[phase][i][w0];
-            for (int w = 1; w < wpi; ++w) s += buf[phase][i][w0 + w];
-            v[i] = s;
+            t[i] = group_sum<L::G>(t[i]);
+            v[i] = lane_read(t[i], w0);
         }
+        tail = t[NV - 1];
         phase ^= 1;
     }
-    // value NV-1 of instance k from the last sum
-    __device__ __forceinline__ T last_of(int k, int wpi) const {
-        const int ph = phase ^ 1;
-        T s = buf[ph][NV - 1][k * wpi];
-        for (int w = 1; w < wpi; ++w) s += buf[ph][NV - 1][k * wpi + w];
-        return s;
-    }
+    // Some instance's value NV-1 (of the last sum) exceeds its threshold
+    // (thr: per lane, see lane_threshold).  Uniform over the workgroup.
+    __device__ __forceinline__ bool any_above(T thr) const { return __ballot(tail > thr) != 0; }
 };
+
+// Per-lane threshold for any_above: the group leaders (lane q*WPI of
+// instance q of the pack) hold instance q's threshold, all others +inf.
+template <class L, typename T>
+__device__ __forceinline__ T lane_threshold(const T* thr_s, int cnt) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int q = lane / L::WPI;
+    const bool lead = lane % L::WPI == 0 && q < L::IPP && q < cnt;
+    return lead ? thr_s[lead ? q : 0] : T(INFINITY);
+}
 
 struct Lane {
     int sub, lt, col, r0, inst, w0;     // w0: first wave of the instance (0 for spare lanes)
@@ -96,15 +131,17 @@ __device__ __forceinline__ Lane lane_of(const MicroArgs& A, int first, int cnt) 
     z.lt = threadIdx.x - z.sub * L::TPI;
     z.w0 = (z.sub < L::IPP ? z.sub : 0) * L::WPI;
     z.live = z.sub < L::IPP && z.sub < cnt;
-    // every wave belongs to one instance: instance and offset are wave-uniform
-    int inst = z.live ? A.order[first + z.sub] : 0;
+    // every wave belongs to one instance: instance and offset are wave-uniform;
+    // the offset comes from the task's own slot, not through the instance
+    const int t = first + (z.live ? z.sub : 0);
+    int inst = z.live ? A.order[t] : 0;
+    const int64_t off = z.live ? A.order_off[t] : 0;
     inst = __builtin_amdgcn_readfirstlane(inst);
     z.inst = inst;
     z.col = z.lt % L::NP;
     const int strip = z.lt / L::NP;
     z.r0 = strip * L::R;
     z.act = z.live && strip < L::NS;
-    const int64_t off = z.live ? A.offsets[inst] : 0;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)off & 0xffffffffu));
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)off >> 32));
     z.off = (int64_t)(((uint64_t)hi << 32) | lo);
@@ -138,10 +175,69 @@ __device__ __forceinline__ void zero_halo(T* g, const Lane& z) {
     }
 }
 
+// Write the lane's strip values to the grid.  Rows past the mesh carry 0 in
+// every vector the kernels write, so they land on the zero halo unchanged.
+template <class L, typename T>
+__device__ __forceinline__ void strip_store(T* g, const Lane& z, const T (&v)[L::R]) {
+    if (z.act) {
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) g[cell_of<L>(z, i)] = v[i];
+    }
+}
+
+// The base pointer of a streamed stencil passes through an empty asm at
+// every use, so the compiler cannot hoist the loop-invariant coefficient
+// loads out of the solver loops and keep them live across them.
+template <typename T>
+__device__ __forceinline__ const T* opaque(const T* p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Load from global memory at base + byte.  The address-space cast keeps it a
+// global load after opaque() has hidden where the pointer came from (a flat
+// load would also count against the LDS wait counter).
+template <typename T>
+__device__ __forceinline__ T global_at(const T* base, uint32_t byte) {
+    using gchar = const __attribute__((address_space(1))) char;
+    using gT = const __attribute__((address_space(1))) T;
+    return *reinterpret_cast<gT*>((gchar*)base + byte);
+}
+
+// Coefficient k of the 9-point row of the lane's strip row i from the
+// upper-half planes at base (instance block, [kSym][n]): wave-uniform base
+// plus a zero-extended 32-bit byte offset.  Rows past the mesh read the last
+// mesh row (results discarded).  The lower couplings index a neighbour node;
+// every such index stays inside the instance's five planes (at worst it
+// falls NP+1 entries into the previous plane).  Wrapped reads at the left
+// and right edges hit coefficients that are structurally zero (E and NE of
+// the last column, NW of the first column, N of the top row), so only the
+// bottom mesh row needs a mask.
+template <class L, typename T>
+__device__ __forceinline__ T sym_load(const T* base, const Lane& z, int i, int k) {
+    const int row = min(z.r0 + i, L::NP - 1);
+    const int node = row * L::NP + z.col;
+    int e;
+    switch (k) {
+        case 0: e = 4 * L::n + node - L::NP - 1; break;    // SW = NE of j-NP-1
+        case 1: e = 3 * L::n + node - L::NP; break;        // S  = N  of j-NP
+        case 2: e = 2 * L::n + node - L::NP + 1; break;    // SE = NW of j-NP+1
+        case 3: e = 1 * L::n + node - 1; break;            // W  = E  of j-1
+        default: e = (k - 4) * L::n + node; break;         // own C, E, NW, N, NE
+    }
+    const T v = global_at(base, (uint32_t)e * (uint32_t)sizeof(T));
+    if (i == 0 && k <= 3) {
+        // strip row 0 may be mesh row 0: no southern neighbours, and node 0 has no W
+        const bool ok = (k == 3) ? (z.r0 > 0 || z.col > 0) : (z.r0 > 0);
+        return ok ? v : T(0);
+    }
+    return v;
+}
+
 // Stencil sources.  A source gives, for row i of the lane's strip and
 // coefficient k, a raw value (load) and the coefficient (value):
 //   RegStencil     FP32 stencil resident in registers
-//   GlobalStencil  stencil in global memory, coefficient-major [k][n]
+//   SymStencil     symmetric planes in global memory, streamed
 //   SplitStencil   FP64 operator as resident FP32 part + streamed FP32 low
 //                  part: S32 + Slo spans at most 48 significant bits, so the
 //                  FP64 sum is exact and equals S to about 2^-48 relative.
@@ -154,33 +250,13 @@ struct RegStencil {
     __device__ __forceinline__ TS value(int, int, TS raw) const { return raw; }
 };
 
-// The base pointer of a streamed stencil passes through an empty asm at
-// every use, so the compiler cannot hoist the loop-invariant coefficient
-// loads out of the solver loops and keep them live across them.
-template <typename T>
-__device__ __forceinline__ const T* opaque(const T* p) {
-    asm volatile("" : "+s"(p));
-    return p;
-}
-
-// wave-uniform base + zero-extended 32-bit byte offset (scalar-base
-// addressing); rows past the mesh read the last mesh row, in bounds, and
-// their results are discarded
-template <class L, typename T>
-__device__ __forceinline__ T stencil_load(const T* base, const Lane& z, int i, int k) {
-    const int row = min(z.r0 + i, L::NP - 1);
-    const uint32_t byte = (uint32_t)(k * L::n + row * L::NP + z.col) * (uint32_t)sizeof(T);
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte);
-}
-
 template <class L, typename TS>
-struct GlobalStencil {
+struct SymStencil {
     static constexpr bool kGlobal = true;
     using raw_t = TS;
     const TS* __restrict__ base;
-    __device__ __forceinline__ TS load(const Lane& z, int i, int k) const { return stencil_load<L>(base, z, i, k); }
+    __device__ __forceinline__ TS load(const Lane& z, int i, int k) const { return sym_load<L>(base, z, i, k); }
     __device__ __forceinline__ TS value(int, int, TS raw) const { return raw; }
-    __device__ __forceinline__ TS at(const Lane& z, int i, int k) const { return load(z, i, k); }
 };
 
 template <class L>
@@ -188,16 +264,17 @@ struct SplitStencil {
     static constexpr bool kGlobal = true;
     using raw_t = float;
     const float (&S)[L::R][kStencil];
-    const float* __restrict__ base;   // Slo
-    __device__ __forceinline__ float load(const Lane& z, int i, int k) const { return stencil_load<L>(base, z, i, k); }
+    const float* __restrict__ base;   // low parts, symmetric planes
+    __device__ __forceinline__ float load(const Lane& z, int i, int k) const { return sym_load<L>(base, z, i, k); }
     __device__ __forceinline__ double value(int i, int k, float raw) const { return (double)S[i][k] + (double)raw; }
 };
 
 // y_i = sum_k S_ik g(row r0+i + dr, col + dc) in k order 0..8, one product
 // at a time; own-column values come from mine[].  Streamed coefficients are
 // loaded B rows at a time, all loads of a batch in flight before the first
-// use (scheduling barriers keep the batches apart without draining memory).
-// Rows past the mesh give 0.  Active lanes only.
+// use (scheduling barriers keep the batches apart without draining memory);
+// coefficient 1 (S) of row i > 0 is coefficient 7 (N) of row i-1, already
+// loaded.  Rows past the mesh give 0.  Active lanes only.
 template <class L, int B, typename TA, typename TG, class ST>
 __device__ __forceinline__ void strip_apply(const ST& S0, const TG* g, const Lane& z,
                                             const TG (&mine)[L::R], TA (&y)[L::R]) {
@@ -213,14 +290,18 @@ __device__ __forceinline__ void strip_apply(const ST& S0, const TG* g, const Lan
     }
     const TG up = g[base - W2];
     const TG dn = g[base + L::R * W2];
+    typename ST::raw_t carry7 = typename ST::raw_t(0);
 #pragma unroll
     for (int i0 = 0; i0 < L::R; i0 += B) {
         typename ST::raw_t c[B][kStencil];
 #pragma unroll
         for (int b = 0; b < B; ++b)
 #pragma unroll
-            for (int k = 0; k < kStencil; ++k)
-                if (i0 + b < L::R) c[b][k] = S.load(z, i0 + b, k);
+            for (int k = 0; k < kStencil; ++k) {
+                if (i0 + b >= L::R) continue;
+                if (k == 1 && i0 + b > 0) c[b][1] = (b > 0) ? c[b - 1][7] : carry7;
+                else c[b][k] = S.load(z, i0 + b, k);
+            }
         if constexpr (ST::kGlobal) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -228,8 +309,7 @@ __device__ __forceinline__ void strip_apply(const ST& S0, const TG* g, const Lan
             if (i >= L::R) break;
             const TG cm = (i == 0) ? up : mine[i - 1];
             const TG cp = (i == L::R - 1) ? dn : mine[i + 1];
-            TA t = TA(0);
-            t += TA(S.value(i, 0, c[b][0])) * TA(lf[i]);
+            TA t = TA(S.value(i, 0, c[b][0])) * TA(lf[i]);
             t += TA(S.value(i, 1, c[b][1])) * TA(cm);
             t += TA(S.value(i, 2, c[b][2])) * TA(rt[i]);
             t += TA(S.value(i, 3, c[b][3])) * TA(lf[i + 1]);
@@ -239,6 +319,7 @@ __device__ __forceinline__ void strip_apply(const ST& S0, const TG* g, const Lan
             t += TA(S.value(i, 7, c[b][7])) * TA(cp);
             t += TA(S.value(i, 8, c[b][8])) * TA(rt[i + 2]);
             y[i] = (z.r0 + i < L::NP) ? t : TA(0);
+            carry7 = c[b][7];
         }
         if constexpr (ST::kGlobal) __builtin_amdgcn_sched_barrier(0);
     }
@@ -256,7 +337,7 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
             bx[0] += A.b[z.off + j] * x[i];
         }
     }
-    red1.sum(bx, z.w0, L::WPI);
+    red1.sum<L>(bx, z.w0);
     if (z.live && z.lt == 0) {
         A.bx_out[z.inst] = bx[0];
         if (A.iters_out) A.iters_out[z.inst] = iters;
@@ -265,8 +346,12 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
     }
 }
 
-// x0 into registers and the (double) grid; b = M x0/dt or the given
-// right-hand side; r = b - S x0 with the FP64 stencil; bb = partial ||b||^2.
+// x0 into registers and the (double) grid, then the FP64 residual and the
+// partial ||b||^2:
+//   given right-hand side:  b = rhs_scale rhs,  r = b - S x0
+//   time step:              b = M x0 / dt,      r = b - S x0 = -K x0
+// (K = S - M/dt is stored on its own, so the residual carries no
+// cancellation; M, in FP32, only sizes ||b||).
 template <class L>
 __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, double* xg, double (&x)[L::R],
                                            double (&r)[L::R], double& bb) {
@@ -280,27 +365,34 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
             v = A.X0[z.off + j] + cf * A.w[z.off + j];
         }
         x[i] = v;
-        if (row_ok<L>(z, i)) xg[cell_of<L>(z, i)] = v;
     }
+    strip_store<L>(xg, z, x);
     __syncthreads();
     double b[L::R], sx[L::R];
 #pragma unroll
     for (int i = 0; i < L::R; ++i) { b[i] = 0.0; sx[i] = 0.0; }
+    bb = 0.0;
     if (A.rhs_vec != nullptr) {
 #pragma unroll
         for (int i = 0; i < L::R; ++i)
             b[i] = row_ok<L>(z, i) ? A.rhs_scale * A.rhs_vec[z.off + node_of<L>(z, i)] : 0.0;
-    } else if (z.act) {
-        strip_apply<L, 3>(GlobalStencil<L, double>{A.M64 + kStencil * z.off}, xg, z, x, b);
+        if (z.act) strip_apply<L, 3>(SymStencil<L, double>{A.Ss64 + kSym * z.off}, xg, z, x, sx);
 #pragma unroll
-        for (int i = 0; i < L::R; ++i) b[i] *= A.inv_dt;
-    }
-    if (z.act) strip_apply<L, 3>(GlobalStencil<L, double>{A.S64 + kStencil * z.off}, xg, z, x, sx);
-    bb = 0.0;
+        for (int i = 0; i < L::R; ++i) {
+            r[i] = b[i] - sx[i];
+            bb += b[i] * b[i];
+        }
+    } else {
+        if (z.act) {
+            strip_apply<L, 3>(SymStencil<L, double>{A.Ks64 + kSym * z.off}, xg, z, x, sx);
+            strip_apply<L, 5>(SymStencil<L, float>{A.Ms32 + kSym * z.off}, xg, z, x, b);
+        }
 #pragma unroll
-    for (int i = 0; i < L::R; ++i) {
-        r[i] = row_ok<L>(z, i) ? b[i] - sx[i] : 0.0;
-        bb += row_ok<L>(z, i) ? b[i] * b[i] : 0.0;
+        for (int i = 0; i < L::R; ++i) {
+            r[i] = -sx[i];
+            const double bi = b[i] * A.inv_dt;
+            bb += bi * bi;
+        }
     }
 }
 
@@ -310,7 +402,7 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
                           PackRed<3, double>& red3) {
     const Lane z = lane_of<L>(A, first, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
-    const GlobalStencil<L, double> S{A.S64 + kStencil * z.off};
+    const SymStencil<L, double> S{A.Ss64 + kSym * z.off};
     double x[L::R], r[L::R], p[L::R];
     float dinv[L::R];
     double bb;
@@ -318,12 +410,12 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
     double acc[3] = {bb, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
-        dinv[i] = row_ok<L>(z, i) ? (float)(1.0 / S.at(z, i, 4)) : 0.0f;
+        dinv[i] = row_ok<L>(z, i) ? (float)(1.0 / S.load(z, i, 4)) : 0.0f;
         p[i] = (double)dinv[i] * r[i];
         acc[1] += r[i] * p[i];
         acc[2] += r[i] * r[i];
     }
-    red3.sum(acc, z.w0, L::WPI);
+    red3.sum<L>(acc, z.w0);
     __shared__ double tol_s[L::IPP];
     const double tol2 = A.rtol * A.rtol * acc[0];
     if (z.live && z.lt == 0) tol_s[z.sub] = tol2;
@@ -331,18 +423,12 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
     bool conv = acc[2] <= tol2;
     int it = 0;
     __syncthreads();
-    auto any_active = [&]() {
-        bool any = false;
-        for (int s = 0; s < L::IPP && s < cnt; ++s) any |= red3.last_of(s, L::WPI) > tol_s[s];
-        return any;
-    };
-    bool go = any_active();
+    const double thr = lane_threshold<L>(tol_s, cnt);
+    bool go = red3.any_above(thr);
     int k = 0;
     while (go && k < A.max_iter) {
         const bool me = !conv;
-#pragma unroll
-        for (int i = 0; i < L::R; ++i)
-            if (row_ok<L>(z, i)) xg[cell_of<L>(z, i)] = p[i];
+        strip_store<L>(xg, z, p);
         __syncthreads();
         double q[L::R];
 #pragma unroll
@@ -351,7 +437,7 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
         double pq[1] = {0.0};
 #pragma unroll
         for (int i = 0; i < L::R; ++i) pq[0] += p[i] * q[i];
-        red1.sum(pq, z.w0, L::WPI);
+        red1.sum<L>(pq, z.w0);
         const double alpha = me ? rz / pq[0] : 0.0;
         double a3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -361,7 +447,7 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
             a3[1] += r[i] * (double)dinv[i] * r[i];
             a3[2] += r[i] * r[i];
         }
-        red3.sum(a3, z.w0, L::WPI);
+        red3.sum<L>(a3, z.w0);
         ++k;
         if (me) {
             ++it;
@@ -374,7 +460,7 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
                 for (int i = 0; i < L::R; ++i) p[i] = (double)dinv[i] * r[i] + beta * p[i];
             }
         }
-        go = any_active();
+        go = red3.any_above(thr);
     }
     pack_store<L>(A, z, x, it, 1, conv, red1);
 }
@@ -382,7 +468,7 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
 // --------------------------------------------------------------- REFINE
 template <class L>
 __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds, PackRed<1, double>& red1,
-                            PackRed<3, double>& red3, PackRed<1, float>& rf1, PackRed<3, float>& rf3) {
+                            PackRed<3, double>& red3, PackRed<3, float>& rf3) {
     const Lane z = lane_of<L>(A, first, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     float* pg = reinterpret_cast<float*>(xg);
@@ -392,27 +478,26 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
     float S[L::R][kStencil], dinv[L::R];
     {
         // branch-free: every row's loads in flight at once (rows past the
-        // mesh read in bounds and are zeroed)
-        const float* Sf = A.S32 + kStencil * z.off;
+        // mesh read the last mesh row in bounds; their products are
+        // discarded and their diag^{-1} is 0); coefficient 1 of row i > 0
+        // is coefficient 7 of row i-1
+        const float* Sf = A.Ss32 + kSym * z.off;
 #pragma unroll
         for (int i = 0; i < L::R; ++i)
 #pragma unroll
-            for (int k = 0; k < kStencil; ++k) S[i][k] = stencil_load<L>(Sf, z, i, k);
+            for (int k = 0; k < kStencil; ++k)
+                S[i][k] = (k == 1 && i > 0) ? S[i - 1][7] : sym_load<L>(Sf, z, i, k);
 #pragma unroll
-        for (int i = 0; i < L::R; ++i) {
-            const bool ok = row_ok<L>(z, i);
-#pragma unroll
-            for (int k = 0; k < kStencil; ++k) S[i][k] = ok ? S[i][k] : 0.0f;
-            dinv[i] = ok ? 1.0f / S[i][4] : 0.0f;
-        }
+        for (int i = 0; i < L::R; ++i) dinv[i] = row_ok<L>(z, i) ? 1.0f / S[i][4] : 0.0f;
     }
     const RegStencil<L, float> SR{S};
-    const SplitStencil<L> S64{S, A.Slo + kStencil * z.off};
+    const SplitStencil<L> S64{S, A.Sslo + kSym * z.off};
     double acc[3] = {bb, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < L::R; ++i) acc[2] += r64[i] * r64[i];
-    red3.sum(acc, z.w0, L::WPI);
+    red3.sum<L>(acc, z.w0);
     __shared__ double otol_s[L::IPP];
+    __shared__ float itol_s[L::IPP];
     const double tol2 = A.rtol * A.rtol * acc[0];
     if (z.live && z.lt == 0) otol_s[z.sub] = tol2;
     double rr = acc[2];
@@ -420,19 +505,15 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
     int sweeps = 1, iters = 0;
     zero_halo<L, float>(pg, z);     // the float view of the grid from here on
     __syncthreads();
-    auto outer_any = [&]() {
-        bool any = false;
-        for (int s = 0; s < L::IPP && s < cnt; ++s) any |= red3.last_of(s, L::WPI) > otol_s[s];
-        return any;
-    };
-    while (outer_any() && sweeps <= A.max_refine) {
+    const double othr = lane_threshold<L>(otol_s, cnt);
+    while (red3.any_above(othr) && sweeps <= A.max_refine) {
         // Inner FP32 solve of S d = r / ||r|| by the Chronopoulos-Gear form of
         // PCG: s = S p is carried by a recurrence, so each iteration needs one
         // operator application (w = S u, u = D^{-1} r) and ONE fused reduction
         // of (r,u), (w,u), (r,r); two barriers per iteration.  The normalised
         // residual starts at ||r|| = 1, so the inner stopping test is
-        // (r,r) <= inner_rtol^2 for every instance; outer-converged instances
-        // enter with r = 0 and sit out.
+        // (r,r) <= itol2, each instance's own inner tolerance (inner_tol2);
+        // outer-converged instances enter with r = 0 and sit out.
         const bool me = !conv;
         const double rn = sqrt(rr);
         const double isc = me ? 1.0 / rn : 0.0;
@@ -444,7 +525,10 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
             p[i] = 0.0f;
             sv[i] = 0.0f;
         }
-        const float itol2 = (float)(A.inner_rtol * A.inner_rtol);
+        const float itol2 = me ? inner_tol2(tol2, rr, A.inner_rtol) : 0.0f;
+        if (z.live && z.lt == 0) itol_s[z.sub] = itol2;
+        __syncthreads();
+        const float ithr = lane_threshold<L>(itol_s, cnt);
         float gam_prev = 1.0f, alpha_prev = 1.0f;
         bool iconv = !me;
         int k = 0;
@@ -454,8 +538,8 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
             for (int i = 0; i < L::R; ++i) {
                 u[i] = dinv[i] * r[i];
                 w[i] = 0.0f;
-                if (row_ok<L>(z, i)) pg[cell_of<L>(z, i)] = u[i];
             }
+            strip_store<L>(pg, z, u);
             __syncthreads();
             if (z.act) strip_apply<L, L::R>(SR, pg, z, u, w);
             float g3[3] = {0.0f, 0.0f, 0.0f};
@@ -465,16 +549,9 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
                 g3[1] += w[i] * u[i];
                 g3[2] += r[i] * r[i];
             }
-            rf3.sum(g3, z.w0, L::WPI);
+            rf3.sum<L>(g3, z.w0);
             if (!iconv && g3[2] <= itol2) iconv = true;
-            bool go;
-            if constexpr (L::IPP == 1) {
-                go = !iconv;
-            } else {
-                go = false;
-                for (int q = 0; q < L::IPP && q < cnt; ++q) go |= rf3.last_of(q, L::WPI) > itol2;
-            }
-            if (!go || k >= A.max_iter) break;
+            if (!rf3.any_above(ithr) || k >= A.max_iter) break;
             if (!iconv) {
                 const float beta = (k == 0) ? 0.0f : g3[0] * __builtin_amdgcn_rcpf(gam_prev);
                 const float den = (k == 0) ? g3[1] : g3[1] - beta * g3[0] * __builtin_amdgcn_rcpf(alpha_prev);
@@ -495,10 +572,8 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
         // x += ||r|| d;  r64 -= ||r|| S d  (FP64 stencil, d exact in FP64)
         const double sc = me ? rn : 0.0;
 #pragma unroll
-        for (int i = 0; i < L::R; ++i) {
-            x[i] += sc * (double)d[i];
-            if (row_ok<L>(z, i)) pg[cell_of<L>(z, i)] = d[i];
-        }
+        for (int i = 0; i < L::R; ++i) x[i] += sc * (double)d[i];
+        strip_store<L>(pg, z, d);
         __syncthreads();
         double sd[L::R];
 #pragma unroll
@@ -510,7 +585,7 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
             r64[i] -= sc * sd[i];
             a1[2] += r64[i] * r64[i];
         }
-        red3.sum(a1, z.w0, L::WPI);
+        red3.sum<L>(a1, z.w0);
         ++sweeps;
         rr = a1[2];
         if (!conv && rr <= tol2) conv = true;
@@ -518,31 +593,34 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
     pack_store<L>(A, z, x, iters, sweeps, conv, red1);
 }
 
+// Reduction buffers of one packed workgroup.
+struct PackShared {
+    double r1[2][NWP][4];
+    double r3[2][NWP][4];
+    float f3[2][NWP][4];
+    int task;
+};
+
 // MODE: 1 FP64, 2 refine.  One instantiation per mesh size (LV), so each
 // gets its own register allocation.
 template <int MODE, class L>
 __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
     extern __shared__ double lds[];
-    __shared__ double r1[2][1][NWP];
-    __shared__ double r3[2][3][NWP];
-    __shared__ float f1[2][1][NWP];
-    __shared__ float f3[2][3][NWP];
-    __shared__ int task_s;
-    PackRed<1, double> red1(r1);
-    PackRed<3, double> red3(r3);
-    PackRed<1, float> rf1(f1);
-    PackRed<3, float> rf3(f3);
+    __shared__ PackShared sh;
+    PackRed<1, double> red1(sh.r1);
+    PackRed<3, double> red3(sh.r3);
+    PackRed<3, float> rf3(sh.f3);
     int task = blockIdx.x;
     for (;;) {
         if (A.queue != nullptr) {
-            if (threadIdx.x == 0) task_s = atomicAdd(A.queue, 1);
+            if (threadIdx.x == 0) sh.task = atomicAdd(A.queue, 1);
             __syncthreads();
-            task = task_s;
+            task = sh.task;
             __syncthreads();
         }
         if (task >= P.n_packs) break;
         const int first = P.first[task], cnt = P.count[task];
-        if constexpr (MODE == 2) pack_refine<L>(A, first, cnt, lds, red1, red3, rf1, rf3);
+        if constexpr (MODE == 2) pack_refine<L>(A, first, cnt, lds, red1, red3, rf3);
         else pack_fp64<L>(A, first, cnt, lds, red1, red3);
         if (A.queue == nullptr) break;
         __syncthreads();
@@ -555,26 +633,21 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
 template <int MODE>
 __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList P, const int32_t* pack_level) {
     extern __shared__ double lds[];
-    __shared__ double r1[2][1][NWP];
-    __shared__ double r3[2][3][NWP];
-    __shared__ float f1[2][1][NWP];
-    __shared__ float f3[2][3][NWP];
-    __shared__ int task_s;
-    PackRed<1, double> red1(r1);
-    PackRed<3, double> red3(r3);
-    PackRed<1, float> rf1(f1);
-    PackRed<3, float> rf3(f3);
+    __shared__ PackShared sh;
+    PackRed<1, double> red1(sh.r1);
+    PackRed<3, double> red3(sh.r3);
+    PackRed<3, float> rf3(sh.f3);
     for (;;) {
-        if (threadIdx.x == 0) task_s = atomicAdd(A.queue, 1);
+        if (threadIdx.x == 0) sh.task = atomicAdd(A.queue, 1);
         __syncthreads();
-        const int task = task_s;
+        const int task = sh.task;
         __syncthreads();
         if (task >= P.n_packs) break;
         const int lvl = pack_level[task], first = P.first[task], cnt = P.count[task];
         if constexpr (MODE == 2) {
-            if (lvl == 64) pack_refine<L64>(A, first, cnt, lds, red1, red3, rf1, rf3);
-            else if (lvl == 32) pack_refine<L32>(A, first, cnt, lds, red1, red3, rf1, rf3);
-            else pack_refine<L16>(A, first, cnt, lds, red1, red3, rf1, rf3);
+            if (lvl == 64) pack_refine<L64>(A, first, cnt, lds, red1, red3, rf3);
+            else if (lvl == 32) pack_refine<L32>(A, first, cnt, lds, red1, red3, rf3);
+            else pack_refine<L16>(A, first, cnt, lds, red1, red3, rf3);
         } else {
             if (lvl == 64) pack_fp64<L64>(A, first, cnt, lds, red1, red3);
             else if (lvl == 32) pack_fp64<L32>(A, first, cnt, lds, red1, red3);

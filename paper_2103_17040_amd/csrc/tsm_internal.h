@@ -14,6 +14,29 @@ constexpr int kWave = 64;
 constexpr int kMaxLevel = 64;             // largest micro mesh N (cells per side)
 constexpr int kMinLevel = 2;
 constexpr int kStencil = 9;               // 9-point Q1 stencil, k = (dj2+1)*3 + (dj1+1)
+// The operators are symmetric, so the packed kernels read only the upper half
+// of each row, k = 4..8 (centre, E, NW, N, NE), stored as planes p = k - 4;
+// the lower coefficients of node j are upper ones of its neighbours:
+//   k=3 (W) = E of j-1,   k=1 (S) = N of j-NP,
+//   k=0 (SW) = NE of j-NP-1,   k=2 (SE) = NW of j-NP+1.
+constexpr int kSym = 5;
+// Tightest relative tolerance asked of an FP32 inner solve (2^-20, about
+// eight FP32 ulps): below it the FP32 correction is no more accurate.
+constexpr double kInnerFloor = 9.5367431640625e-07;
+
+// Squared relative tolerance of one FP32 inner solve in the refinement: half
+// of what the outer test still needs (tol2 = rtol^2 ||b||^2 against the
+// current squared FP64 residual rr), no tighter than kInnerFloor and no
+// looser than cap.  A correction solved this far usually ends the
+// refinement; a looser one would cost another FP64 residual pass, a tighter
+// one iterations that the outer test does not need.
+__host__ __device__ inline float inner_tol2(double tol2, double rr, double cap) {
+    double t = 0.25 * tol2 / rr;
+    const double lo = kInnerFloor * kInnerFloor, hi = cap * cap;
+    t = t < lo ? lo : t;
+    t = t > hi ? hi : t;
+    return (float)t;
+}
 
 // Per-level quadrature tables: for level N, entries [tab_off[N], tab_off[N] + 2N + 2).
 // Entry t < 2N is the Gauss abscissa y_t = -1 + (t/2 + g_{t%2}) h of cell t/2;
@@ -38,6 +61,12 @@ struct AssembleArgs {
     float* S32;           // S rounded to FP32
     float* Slo;           // S - S32 rounded to FP32: S32 + Slo equals S to about 2^-48 relative
     double* M64;
+    // upper-half planes [kSym][n] at kSym*off (symmetric storage, see kSym)
+    double* Ss64;         // S
+    double* Ks64;         // K = d A + kappa B = S - M/dt, accumulated on its own
+    float* Ms32;          // M rounded to FP32 (norms only)
+    float* Ss32;          // S rounded to FP32
+    float* Sslo;          // S - Ss32 rounded to FP32
     double* b;            // boundary load B 1 (ragged)
     double* len;          // [n_inst] 1^T b
     double* jmin;         // [n_inst] minimum det over all quadrature points
@@ -51,12 +80,18 @@ struct AssembleArgs {
 struct MicroArgs {
     int n_tasks;
     const int32_t* order;
+    const int64_t* order_off;   // offsets[order[t]] (packed kernels)
     const int32_t* level;
     const int64_t* offsets;
     const double* S64;
     const float* S32;
     const float* Slo;
     const double* M64;
+    const double* Ss64;   // symmetric upper-half planes (packed kernels)
+    const double* Ks64;
+    const float* Ms32;
+    const float* Ss32;
+    const float* Sslo;
     const double* b;
     const double* X0;
     const double* w;

@@ -53,7 +53,8 @@ class tsm_stats(ctypes.Structure):
                 ("setup_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
                 ("micro_ms", ctypes.c_double), ("macro_ms", ctypes.c_double),
                 ("timed_steps", ctypes.c_int32), ("micro_launches", ctypes.c_int32),
-                ("grad_forward_ms", ctypes.c_double), ("grad_backward_ms", ctypes.c_double)]
+                ("grad_forward_ms", ctypes.c_double), ("grad_backward_ms", ctypes.c_double),
+                ("sweeps_mean", ctypes.c_double)]
 
 
 class TsmError(RuntimeError):

@@ -55,9 +55,38 @@ def test_params_struct_layout_and_validation(lib_built):
         with pytest.raises(tsm.TsmError) as e:
             tsm.tsm_create(q, None)
         assert e.value.status == tsm.TSM_EINVAL
+        # the reason of a rejected create is kept per thread under the NULL context
+        assert tsm._lib.tsm_last_error(None) == b"parameter out of range"
+        assert "parameter out of range" in str(e.value)
 
 
 def test_null_safety(lib_built):
     from paper_2103_17040_amd import tsm
     tsm._lib.tsm_destroy(None)
-    assert tsm._lib.tsm_last_error(None) == b"null context"
+    assert isinstance(tsm._lib.tsm_last_error(None), bytes)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes structs have the size and field offsets that a C compiler
+    gives the header's structs."""
+    from paper_2103_17040_amd import tsm
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tsm.h"', 'int main(void) {']
+    for cname, py in (("tsm_params", tsm.tsm_params), ("tsm_stats", tsm.tsm_stats)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    want = {}
+    for ln in out:
+        if ln:
+            c, f, v = ln.split()
+            want[(c, f)] = int(v)
+    for cname, py in (("tsm_params", tsm.tsm_params), ("tsm_stats", tsm.tsm_stats)):
+        assert ctypes.sizeof(py) == want[(cname, "size")], cname
+        for f, _ in py._fields_:
+            assert getattr(py, f).offset == want[(cname, f)], (cname, f)
