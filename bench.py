@@ -246,7 +246,10 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": hbm / PEAK_HBM_GBS, "traffic": traffic}
-    kname = {"per_size": "packed_kernel (micro PCG)", "persistent": "packed_mixed_kernel (micro PCG)",
+    n_sizes = len(set(lv.tolist()))
+    kname = {"per_size": "packed_kernel (micro PCG)",
+             "persistent": "packed_kernel, persistent (micro PCG)" if n_sizes == 1
+             else "packed_mixed_kernel (micro PCG)",
              "generic": "micro_kernel (micro PCG)"}[main_form["plan"]["plan"]]
     stream_gbs = dofs_per_launch * streaming_bytes(refine, iters, sweeps) / t_launch / 1e9
     roof.update({"kernel": kname, "launch_ms": micro_ms_per_launch,

@@ -66,9 +66,10 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
 #define TSM_FLAG_STENCIL_STREAM (1ull << 1) /* force the streamed-stencil micro kernels */
 #define TSM_FLAG_GENERIC    (1ull << 3)  /* solve every mesh size with the one-instance-per-workgroup
                                             kernels (no packed kernels for 16/32/64 cells) */
-#define TSM_FLAG_PERSISTENT (1ull << 4)  /* all packed mesh sizes in ONE persistent launch with a
-                                            work queue (largest meshes first), instead of one
-                                            launch per mesh size */
+#define TSM_FLAG_PERSISTENT (1ull << 4)  /* all packed mesh sizes in ONE persistent launch (one
+                                            workgroup per compute unit) with a work queue
+                                            (largest meshes first), instead of one launch per
+                                            mesh size with one workgroup per pack */
 #define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
                                             HIP events on the context's stream (see tsm_stats) */
 

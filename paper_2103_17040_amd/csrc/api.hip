@@ -167,8 +167,11 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
         a.order_off = c->order_off;
         a.queue = c->queue;
         HIPCHK(launch_fill_i32(c->queue, 0, 1, c->stream));
-        HIPCHK(launch_packed_mixed(a, pl, c->pk_level, refine ? 2 : 1, std::min(c->n_packs, c->n_cu),
-                                   c->pack_lds_max, c->stream));
+        const int grid = std::min(c->n_packs, c->n_cu);
+        if (c->pack_groups.size() == 1)   // one mesh size: its own kernel, same queue
+            HIPCHK(launch_packed(a, pl, c->pack_groups[0][0], refine ? 2 : 1, grid, c->stream));
+        else
+            HIPCHK(launch_packed_mixed(a, pl, c->pk_level, refine ? 2 : 1, grid, c->pack_lds_max, c->stream));
     } else {
         for (const auto& pg : c->pack_groups) {
             PackList pl{pg[2], c->pk_first + pg[1], c->pk_count + pg[1]};

@@ -23,10 +23,12 @@ __device__ __forceinline__ double lin(int l, int g) { return l ? gauss_x(g) : 1.
 // Every lane returns the same bits: each step adds two operands whose order
 // differs between partner lanes only, and IEEE addition commutes.
 // All 64 lanes must be active.
-// DPP move of v under control CTRL; rows outside ROWMASK read 0.
+// DPP move of v under control CTRL; lanes without a source lane (and rows
+// outside ROWMASK) read 0 (bound_ctrl), which lets v + dpp(v) become one
+// v_add_f32 with a DPP operand.
 template <int CTRL, int ROWMASK = 0xF>
 __device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, true));
 }
 template <int CTRL, int ROWMASK = 0xF>
 __device__ __forceinline__ double dpp(double v) {

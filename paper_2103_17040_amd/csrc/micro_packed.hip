@@ -468,7 +468,7 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
 // --------------------------------------------------------------- REFINE
 template <class L>
 __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds, PackRed<1, double>& red1,
-                            PackRed<3, double>& red3, PackRed<3, float>& rf3) {
+                            PackRed<3, double>& red3, PackRed<2, float>& rf2) {
     const Lane z = lane_of<L>(A, first, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     float* pg = reinterpret_cast<float*>(xg);
@@ -510,10 +510,11 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
         // Inner FP32 solve of S d = r / ||r|| by the Chronopoulos-Gear form of
         // PCG: s = S p is carried by a recurrence, so each iteration needs one
         // operator application (w = S u, u = D^{-1} r) and ONE fused reduction
-        // of (r,u), (w,u), (r,r); two barriers per iteration.  The normalised
-        // residual starts at ||r|| = 1, so the inner stopping test is
-        // (r,r) <= itol2, each instance's own inner tolerance (inner_tol2);
-        // outer-converged instances enter with r = 0 and sit out.
+        // of (w,u) and (r,u); two barriers per iteration.  The inner test is
+        // on the preconditioned norm: (r,u) <= itol2 (r0,u0), with each
+        // instance's own itol2 (inner_tol2); outer-converged instances enter
+        // with r = 0 and sit out.  Frozen instances take alpha = beta = 0,
+        // which leaves d and r unchanged, so the update needs no branch.
         const bool me = !conv;
         const double rn = sqrt(rr);
         const double isc = me ? 1.0 / rn : 0.0;
@@ -529,41 +530,46 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
         if (z.live && z.lt == 0) itol_s[z.sub] = itol2;
         __syncthreads();
         const float ithr = lane_threshold<L>(itol_s, cnt);
+        float vthr = ithr, gam0 = 0.0f;
         float gam_prev = 1.0f, alpha_prev = 1.0f;
         bool iconv = !me;
         int k = 0;
         for (;;) {
             float u[L::R], w[L::R];
 #pragma unroll
-            for (int i = 0; i < L::R; ++i) {
-                u[i] = dinv[i] * r[i];
-                w[i] = 0.0f;
-            }
+            for (int i = 0; i < L::R; ++i) u[i] = dinv[i] * r[i];
             strip_store<L>(pg, z, u);
             __syncthreads();
-            if (z.act) strip_apply<L, L::R>(SR, pg, z, u, w);
-            float g3[3] = {0.0f, 0.0f, 0.0f};
+            // every lane applies (no branch): the reads of inactive and spare
+            // lanes stay inside the LDS block, rows past the mesh give 0, and
+            // spare waves never enter a sum
+            strip_apply<L, L::R>(SR, pg, z, u, w);
+            float g2[2] = {0.0f, 0.0f};     // (w,u), (r,u)
 #pragma unroll
             for (int i = 0; i < L::R; ++i) {
-                g3[0] += r[i] * u[i];
-                g3[1] += w[i] * u[i];
-                g3[2] += r[i] * r[i];
+                g2[0] += w[i] * u[i];
+                g2[1] += r[i] * u[i];
             }
-            rf3.sum<L>(g3, z.w0);
-            if (!iconv && g3[2] <= itol2) iconv = true;
-            if (!rf3.any_above(ithr) || k >= A.max_iter) break;
-            if (!iconv) {
-                const float beta = (k == 0) ? 0.0f : g3[0] * __builtin_amdgcn_rcpf(gam_prev);
-                const float den = (k == 0) ? g3[1] : g3[1] - beta * g3[0] * __builtin_amdgcn_rcpf(alpha_prev);
-                const float alpha = g3[0] * __builtin_amdgcn_rcpf(den);
+            rf2.sum<L>(g2, z.w0);
+            if (k == 0) {
+                gam0 = g2[1];
+                vthr = (ithr < INFINITY) ? ithr * rf2.tail : ithr;
+            }
+            if (!iconv && g2[1] <= itol2 * gam0) iconv = true;
+            if (!rf2.any_above(vthr) || k >= A.max_iter) break;
+            const float gam = g2[1];
+            const float beta = (k == 0 || iconv) ? 0.0f : gam * __builtin_amdgcn_rcpf(gam_prev);
+            const float den = (k == 0) ? g2[0] : g2[0] - beta * gam * __builtin_amdgcn_rcpf(alpha_prev);
+            const float alpha = iconv ? 0.0f : gam * __builtin_amdgcn_rcpf(den);
 #pragma unroll
-                for (int i = 0; i < L::R; ++i) {
-                    p[i] = u[i] + beta * p[i];
-                    sv[i] = w[i] + beta * sv[i];
-                    d[i] += alpha * p[i];
-                    r[i] -= alpha * sv[i];
-                }
-                gam_prev = g3[0];
+            for (int i = 0; i < L::R; ++i) {
+                p[i] = u[i] + beta * p[i];
+                sv[i] = w[i] + beta * sv[i];
+                d[i] += alpha * p[i];
+                r[i] -= alpha * sv[i];
+            }
+            if (!iconv) {
+                gam_prev = gam;
                 alpha_prev = alpha;
                 ++iters;
             }
@@ -609,7 +615,7 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
     __shared__ PackShared sh;
     PackRed<1, double> red1(sh.r1);
     PackRed<3, double> red3(sh.r3);
-    PackRed<3, float> rf3(sh.f3);
+    PackRed<2, float> rf2(sh.f3);
     int task = blockIdx.x;
     for (;;) {
         if (A.queue != nullptr) {
@@ -620,7 +626,7 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
         }
         if (task >= P.n_packs) break;
         const int first = P.first[task], cnt = P.count[task];
-        if constexpr (MODE == 2) pack_refine<L>(A, first, cnt, lds, red1, red3, rf3);
+        if constexpr (MODE == 2) pack_refine<L>(A, first, cnt, lds, red1, red3, rf2);
         else pack_fp64<L>(A, first, cnt, lds, red1, red3);
         if (A.queue == nullptr) break;
         __syncthreads();
@@ -636,7 +642,7 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
     __shared__ PackShared sh;
     PackRed<1, double> red1(sh.r1);
     PackRed<3, double> red3(sh.r3);
-    PackRed<3, float> rf3(sh.f3);
+    PackRed<2, float> rf2(sh.f3);
     for (;;) {
         if (threadIdx.x == 0) sh.task = atomicAdd(A.queue, 1);
         __syncthreads();
@@ -645,9 +651,9 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
         if (task >= P.n_packs) break;
         const int lvl = pack_level[task], first = P.first[task], cnt = P.count[task];
         if constexpr (MODE == 2) {
-            if (lvl == 64) pack_refine<L64>(A, first, cnt, lds, red1, red3, rf3);
-            else if (lvl == 32) pack_refine<L32>(A, first, cnt, lds, red1, red3, rf3);
-            else pack_refine<L16>(A, first, cnt, lds, red1, red3, rf3);
+            if (lvl == 64) pack_refine<L64>(A, first, cnt, lds, red1, red3, rf2);
+            else if (lvl == 32) pack_refine<L32>(A, first, cnt, lds, red1, red3, rf2);
+            else pack_refine<L16>(A, first, cnt, lds, red1, red3, rf2);
         } else {
             if (lvl == 64) pack_fp64<L64>(A, first, cnt, lds, red1, red3);
             else if (lvl == 32) pack_fp64<L32>(A, first, cnt, lds, red1, red3);
