@@ -98,7 +98,10 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, autotune=True):
+PLAN_FLAGS = {"per_size": 0, "persistent": 1 << 4, "generic": 1 << 3}
+
+
+def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan="auto"):
     import torch
     from paper_2103_17040_amd import TwoScaleBatch, tsm
     g = TwoScaleBatch(w.macro_cells, lv, a, th, D=w.D, d=w.d, kappa=w.kappa, p=w.p, dt=w.dt,
@@ -111,7 +114,11 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, auto
         g.step(warmup)
         # launch plan: per-size launches, one persistent launch, or the
         # one-instance-per-workgroup kernels, timed on this state (restored)
-        plan = g.autotune(steps=3) if autotune else {"flags": 0, "ms_per_step": None}
+        if plan == "auto":
+            plan = g.autotune(steps=3)
+        else:
+            g.set_flags(PLAN_FLAGS[plan])
+            plan = {"flags": PLAN_FLAGS[plan], "ms_per_step": None}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g.step(steps)
@@ -186,6 +193,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--plan", default="auto", choices=["auto"] + sorted(PLAN_FLAGS),
+                    help="launch plan of the micro solves (auto: the autotuner picks on the live state)")
     ap.add_argument("--adjoint-steps", type=int, default=40,
                     help="steps of the gradient leg (0: skip); checkpoint spacing from the workload")
     ap.add_argument("--calib-bytes", type=int, default=0,
@@ -212,11 +221,11 @@ def main():
     _log(f"workload {w.name}: {w.n_inst} instances, levels {sorted(set(lv.tolist()))}, "
          f"{int(W.offsets(lv)[-1])} micro DoFs, precision {w.precision}, rtol {w.rtol}")
 
-    main_form = run_form(w, a, th, lv, w.precision, args.steps, args.warmup, w.rtol, args.adjoint_steps)
+    main_form = run_form(w, a, th, lv, w.precision, args.steps, args.warmup, w.rtol, args.adjoint_steps, args.plan)
     _log(f"main form done: {main_form['t']:.3f} s for {args.steps} steps; stats {main_form['stats']}")
     fp64 = None
     if refine and not args.no_fp64:
-        fp64 = run_form(w, a, th, lv, "fp64", args.steps, args.warmup, w.rtol)
+        fp64 = run_form(w, a, th, lv, "fp64", args.steps, args.warmup, w.rtol, plan=args.plan)
         _log(f"fp64 form done: {fp64['t']:.3f} s; stats {fp64['stats']}")
 
     n_dofs = main_form["n_dofs"]

@@ -54,6 +54,27 @@ def test_persistent_matches_per_size_many_packs(prec):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("level", [16, 32, 64])
+def test_persistent_single_size(level):
+    """One packed mesh size: the persistent plan runs that size's own kernel
+    with the work queue (more packs than compute units for 16 and 32)."""
+    from paper_2103_17040_amd import tsm
+    NM = {16: 80, 32: 40, 64: 18}[level]
+    n = (NM + 1) ** 2
+    rng = np.random.default_rng(level)
+    lv = np.full(n, level, np.int32)
+    a = rng.uniform(-0.3, 0.3, n)
+    th = rng.uniform(0.0, 2.0 * np.pi, n)
+    u0 = W.initial_macro(NM)
+    v0 = np.random.default_rng(4).uniform(0, 1, int(W.offsets(lv)[-1]))
+    banner(f"persistent single size {level}, NM={NM}")
+    for prec, rtol in (("fp64", 1e-12), ("fp32_refine", 1e-10)):
+        ref = _run(NM, lv, a, th, prec, 0, 3, u0, v0, rtol)
+        out = _run(NM, lv, a, th, prec, tsm.TSM_FLAG_PERSISTENT, 3, u0, v0, rtol)
+        for x, y in zip(ref, out):
+            assert np.array_equal(x, y), prec
+
+
 def test_persistent_with_generic_sizes():
     """Mesh sizes outside the packed kernels (odd sizes) still go to the
     one-instance-per-workgroup kernel next to the persistent launch."""
