@@ -13,6 +13,9 @@ form (sum over instances of (N_i+1)^2 per step); the plain FP64 form on the
 same workload and tolerance is timed beside it, the dominant kernel's
 duration is measured with HIP events on the library's stream for the
 roofline, and the FP64 oracle is timed on a bounded sample on the host.
+Side legs on the same workload: the gradient (checkpointed forward +
+adjoint), and the paper's alternating macro/micro coupling timed against the
+exact coupling step.
 """
 from __future__ import annotations
 
@@ -101,7 +104,7 @@ def _log(msg):
 PLAN_FLAGS = {"per_size": 0, "persistent": 1 << 4, "generic": 1 << 3}
 
 
-def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan="auto"):
+def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan="auto", fp_steps=0):
     import torch
     from paper_2103_17040_amd import TwoScaleBatch, tsm
     g = TwoScaleBatch(w.macro_cells, lv, a, th, D=w.D, d=w.d, kappa=w.kappa, p=w.p, dt=w.dt,
@@ -130,6 +133,23 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan
         g.step(steps)
         tst = g.stats()
         g.set_flags(plan["flags"])
+        fp = None
+        if fp_steps > 0:
+            # the paper's alternating coupling on the same workload: every
+            # iteration is a full batch of micro solves
+            g.set_flags(plan["flags"] | tsm.TSM_FLAG_FIXED_POINT)
+            g.set_state(u0, None)
+            g.step(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            iters = []
+            for _ in range(fp_steps):
+                g.step(1)
+                iters.append(g.stats()["fp_iters_last"])
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - t0
+            g.set_flags(plan["flags"])
+            fp = {"steps": fp_steps, "ms_per_step": tf / fp_steps * 1e3, "iterations": iters}
         adj = None
         if adjoint_steps > 0:
             # gradient of int u(T)^2 from the initial state: checkpointed
@@ -147,7 +167,7 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan
         names = {0: "per_size", tsm.TSM_FLAG_PERSISTENT: "persistent", tsm.TSM_FLAG_GENERIC: "generic"}
         plan = {"plan": names.get(plan["flags"], str(plan["flags"])), "ms_per_step": plan["ms_per_step"]}
         return {"t": t, "setup_ms": setup_ms, "stats": st, "timing": tst, "n_dofs": g.n_micro, "adjoint": adj,
-                "plan": plan}
+                "plan": plan, "fixed_point": fp}
     finally:
         g.close()
 
@@ -195,6 +215,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--plan", default="auto", choices=["auto"] + sorted(PLAN_FLAGS),
                     help="launch plan of the micro solves (auto: the autotuner picks on the live state)")
+    ap.add_argument("--fp-steps", type=int, default=3,
+                    help="steps of the alternating-coupling leg (0: skip), timed against the exact step")
     ap.add_argument("--adjoint-steps", type=int, default=40,
                     help="steps of the gradient leg (0: skip); checkpoint spacing from the workload")
     ap.add_argument("--calib-bytes", type=int, default=0,
@@ -221,7 +243,8 @@ def main():
     _log(f"workload {w.name}: {w.n_inst} instances, levels {sorted(set(lv.tolist()))}, "
          f"{int(W.offsets(lv)[-1])} micro DoFs, precision {w.precision}, rtol {w.rtol}")
 
-    main_form = run_form(w, a, th, lv, w.precision, args.steps, args.warmup, w.rtol, args.adjoint_steps, args.plan)
+    main_form = run_form(w, a, th, lv, w.precision, args.steps, args.warmup, w.rtol, args.adjoint_steps, args.plan,
+                         args.fp_steps)
     _log(f"main form done: {main_form['t']:.3f} s for {args.steps} steps; stats {main_form['stats']}")
     fp64 = None
     if refine and not args.no_fp64:
@@ -303,6 +326,10 @@ def main():
         adj["total_over_plain_forward"] = (adj["forward_ms"] + adj["backward_ms"]) / plain_fwd_ms
         out["adjoint"] = adj
         out["adjoint_over_forward"] = adj["backward_over_forward"]
+    fpl = main_form["fixed_point"]
+    if fpl is not None:
+        fpl["over_exact_step"] = fpl["ms_per_step"] / out["ms_per_step"]
+        out["fixed_point_coupling"] = fpl
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, a, th, lv)

@@ -72,6 +72,16 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
                                             mesh size with one workgroup per pack */
 #define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
                                             HIP events on the context's stream (see tsm_stats) */
+#define TSM_FLAG_FIXED_POINT (1ull << 5) /* tsm_step couples macro and micro solves by the paper's
+                                            alternating iteration (Section 3.3): macro solve with
+                                            the micro data lagged, then every micro solve with the
+                                            new macro values, until the residual sum (macro
+                                            residual norm + mean micro residual norm) changes by
+                                            less than fp_rtol times its first value.  Converges to
+                                            the same step as the default exact (Schur) coupling;
+                                            each iteration costs a full batch of micro solves.
+                                            Launched directly (one host sync per iteration);
+                                            tsm_gradient always uses the exact coupling. */
 
 typedef struct {
     int32_t macro_cells;     /* N_M >= 2: macro Q1 cells per side on [0,1]^2 */
@@ -86,12 +96,15 @@ typedef struct {
     double inner_rtol;       /* FP32 inner solves (refinement mode): the loosest
                                 relative tolerance of one inner solve; each one
                                 is solved to half of what the FP64 residual test
-                                still needs, but no tighter than 2^-20 */
+                                still needs, but no tighter than 2^-18 */
     double setup_rtol;       /* response solves w_i at setup */
     int32_t max_iter;        /* PCG iterations per solve (per inner solve) */
     int32_t max_refine;      /* FP64 refinement sweeps (refinement mode) */
     int32_t checkpoint_every;/* adjoint checkpoint spacing in steps, >= 1 */
     uint64_t flags;          /* TSM_FLAG_* */
+    double fp_rtol;          /* TSM_FLAG_FIXED_POINT: stop when the residual sum changes by
+                                less than fp_rtol x its first value, > 0 */
+    int32_t fp_max_iter;     /* TSM_FLAG_FIXED_POINT: iterations per step, >= 2 */
 } tsm_params;
 
 typedef struct {
@@ -114,13 +127,16 @@ typedef struct {
     double grad_backward_ms;     /* last tsm_gradient: segment recompute + adjoint + gradient */
     double sweeps_mean;          /* refinement sweeps of the last step, mean over instances
                                     (1 + the inner solves of an instance) */
+    int32_t fp_iters_last;       /* TSM_FLAG_FIXED_POINT: coupling iterations of the last step */
+    int32_t fp_iters_max;        /* ... and the most over the steps of the last tsm_step call */
 } tsm_stats;
 
 typedef struct tsm_ctx tsm_ctx;
 
 /* Fill *p with the defaults: kappa = p = 1, D = 1, d = 0.5, dt = 0.01,
  * source_sign = -1, FP64, rtol 1e-12, inner_rtol 1e-2, setup_rtol 1e-14,
- * max_iter 1000, max_refine 12, checkpoint_every 10, flags 0. */
+ * max_iter 1000, max_refine 12, checkpoint_every 10, flags 0, fp_rtol 1e-10,
+ * fp_max_iter 50. */
 void tsm_default_params(tsm_params* p);
 
 /* Create a context on the current HIP device.  stream is a hipStream_t

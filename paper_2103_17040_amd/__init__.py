@@ -18,7 +18,8 @@ class TwoScaleBatch:
 
     def __init__(self, macro_cells, micro_cells, a, theta=None, *, D=1.0, d=0.5, kappa=1.0, p=1.0,
                  dt=0.01, sigma=-1, precision="fp64", rtol=1e-12, inner_rtol=1e-2, setup_rtol=1e-14,
-                 max_iter=1000, max_refine=12, checkpoint_every=10, flags=0, device="cuda:0"):
+                 max_iter=1000, max_refine=12, checkpoint_every=10, flags=0, coupling="schur",
+                 fp_rtol=1e-10, fp_max_iter=50, device="cuda:0"):
         import numpy as np
         import torch
         global tsm
@@ -32,9 +33,10 @@ class TwoScaleBatch:
         prm.precision = {"fp64": tsm.TSM_FP64, "fp32_refine": tsm.TSM_FP32_REFINE}[precision]
         prm.rtol, prm.inner_rtol, prm.setup_rtol = float(rtol), float(inner_rtol), float(setup_rtol)
         prm.max_iter, prm.max_refine, prm.checkpoint_every = int(max_iter), int(max_refine), int(checkpoint_every)
-        prm.flags = int(flags)
+        prm.flags = int(flags) | {"schur": 0, "fixed_point": tsm.TSM_FLAG_FIXED_POINT}[coupling]
+        prm.fp_rtol, prm.fp_max_iter = float(fp_rtol), int(fp_max_iter)
         self.params = prm
-        self._flags = int(flags)
+        self._flags = int(prm.flags)
         self.n_inst = (int(macro_cells) + 1) ** 2
         with torch.cuda.device(self.device):
             self.ctx = tsm.tsm_create(prm, None)

@@ -83,6 +83,12 @@ struct tsm_ctx {
     double *rhs = nullptr, *R = nullptr, *T1 = nullptr, *T2 = nullptr, *Q = nullptr, *lam = nullptr;
     int macro_sweeps = 2;
     double rho = 0.0;
+    // alternating (fixed-point) coupling: macro operator with beta = kappa p
+    // (eigenvalues lam_fp), full micro state vf, rhs M v^n, previous macro
+    // state, per-instance residual norms, the residual sum (2 values)
+    double *lam_fp = nullptr, *beta_fp = nullptr, *vf = nullptr, *rvec = nullptr, *u_prev = nullptr,
+           *resn = nullptr, *fpm = nullptr;
+    int fp_iters_last = 0, fp_iters_max = 0;
 
     // adjoint: amplitude-derivative operators and work vectors (first tsm_gradient)
     double *dS64 = nullptr, *dM64 = nullptr, *db = nullptr, *dlen = nullptr, *jmin_d = nullptr;
@@ -115,7 +121,10 @@ struct tsm_ctx {
         drop_graph();
         have_mesh = have_geom = have_state = false;
     }
-    void free_macro() { dfree(rhs); dfree(R); dfree(T1); dfree(T2); dfree(Q); dfree(lam); }
+    void free_macro() {
+        dfree(rhs); dfree(R); dfree(T1); dfree(T2); dfree(Q); dfree(lam);
+        dfree(lam_fp); dfree(beta_fp); dfree(vf); dfree(rvec); dfree(u_prev); dfree(resn); dfree(fpm);
+    }
     void drop_graph() {
         if (graph) (void)hipGraphExecDestroy(graph);
         graph = nullptr;
@@ -292,17 +301,22 @@ MicroArgs micro_base(tsm_ctx* c) {
 }
 
 // Macro solve of A_M u = rhs in place (u holds the initial guess).
-tsm_status enqueue_macro_solve(tsm_ctx* c, double* u) {
-    const MacroArgs m = c->macro_args();
+// Sweeps u <- u + A0^{-1} (rhs - A_M u) of the macro solve; A_M from m (its
+// beta), A0^{-1} by the sine basis and the eigenvalues lam.
+tsm_status enqueue_macro_solve(tsm_ctx* c, double* u, const MacroArgs& m, const double* lam, int sweeps) {
     const int n = m.n;
-    for (int s = 0; s < c->macro_sweeps; ++s) {
+    for (int s = 0; s < sweeps; ++s) {
         HIPCHK(launch_macro_residual(m, u, c->rhs, c->R, c->stream));
         HIPCHK(launch_gemm(n, c->Q, c->R, c->T1, 0, nullptr, nullptr, c->NM, c->stream));
-        HIPCHK(launch_gemm(n, c->T1, c->Q, c->T2, 1, c->lam, nullptr, c->NM, c->stream));
+        HIPCHK(launch_gemm(n, c->T1, c->Q, c->T2, 1, lam, nullptr, c->NM, c->stream));
         HIPCHK(launch_gemm(n, c->Q, c->T2, c->T1, 0, nullptr, nullptr, c->NM, c->stream));
         HIPCHK(launch_gemm(n, c->T1, c->Q, nullptr, 2, nullptr, u, c->NM, c->stream));
     }
     return TSM_OK;
+}
+
+tsm_status enqueue_macro_solve(tsm_ctx* c, double* u) {
+    return enqueue_macro_solve(c, u, c->macro_args(), c->lam, c->macro_sweeps);
 }
 
 // One forward step: micro solves (state v = v0 + u w in place), macro solve, fluxes.
@@ -327,9 +341,70 @@ tsm_status enqueue_step(tsm_ctx* c, const hipEvent_t* ev = nullptr) {
     return TSM_OK;
 }
 
+// One step of the paper's alternating coupling (Section 3.3): the macro
+// solve with the micro data lagged (A_fp u = M_H u^n/dt + sign L alpha(v^k),
+// A_fp = M_H/dt + D K_H - sign kappa p L, solved exactly by the sine basis),
+// then every micro solve with the new macro values
+// (S_i v_i = M_i v_i^n/dt + kappa p u_i b_i, previous iterate as the guess),
+// until the residual sum (macro residual norm + mean micro residual norm)
+// changes by less than fp_rtol times its first value.  The test runs on the
+// host: one synchronisation per iteration.
+tsm_status step_fixed_point(tsm_ctx* c) {
+    const int64_t ni = c->n_inst, tot = c->total;
+    if (!c->vf) {
+        HIPALLOC(c->vf, tot); HIPALLOC(c->rvec, tot); HIPALLOC(c->u_prev, ni);
+        HIPALLOC(c->resn, ni); HIPALLOC(c->fpm, 2);
+    }
+    hipStream_t s = c->stream;
+    MacroArgs m = c->macro_args();
+    m.beta = c->beta_fp;
+    const int nR = m.n * m.n;
+    HIPCHK(launch_state_join((int)ni, c->offsets, c->u, c->v0, c->w, c->vf, s));          // v^n
+    HIPCHK(launch_apply((int)ni, c->level, c->offsets, c->M64, c->vf, c->rvec, s));       // M v^n
+    HIPCHK(hipMemcpyAsync(c->u_prev, c->u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_bdot((int)ni, c->offsets, c->b, c->vf, c->bx, s));
+    double first = 0.0, prev = 0.0;
+    int it = 0;
+    while (it < c->prm.fp_max_iter) {
+        ++it;
+        HIPCHK(launch_macro_rhs_forward(m, c->u_prev, c->bx, c->rhs, c->alpha, s));
+        tsm_status st = enqueue_macro_solve(c, c->u, m, c->lam_fp, 2);
+        if (st != TSM_OK) return st;
+        MicroArgs a = micro_base(c);
+        a.X0 = c->vf;
+        a.coef = nullptr;
+        a.zero_init = 0;
+        a.rhs_vec = c->rvec;
+        a.rhs_scale = 1.0 / c->prm.dt;
+        a.rhs_bcoef = c->u;
+        a.rhs_bscale = c->prm.kappa * c->prm.p;
+        a.X_out = c->vf;
+        a.res_out = c->resn;
+        st = enqueue_micro(c, a, false);
+        if (st != TSM_OK) return st;
+        // residual sum of (u^{k+1}, v^{k+1}); alpha is left for the fluxes
+        HIPCHK(launch_macro_rhs_forward(m, c->u_prev, c->bx, c->rhs, c->alpha, s));
+        HIPCHK(launch_macro_residual(m, c->u, c->rhs, c->R, s));
+        HIPCHK(launch_coupling_residual(nR, c->R, (int)ni, c->resn, c->fpm, s));
+        double h[2];
+        HIPCHK(hipMemcpyAsync(h, c->fpm, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double res = h[0] + h[1];
+        if (!std::isfinite(res)) return c->fail(TSM_ENOCONV, "fixed-point coupling: residual sum is not finite");
+        if (it == 1) first = res;
+        else if (std::fabs(res - prev) <= c->prm.fp_rtol * first) break;
+        prev = res;
+    }
+    HIPCHK(launch_macro_finalize(m, c->u, c->alpha, c->F, s));                         // F = kappa p u + alpha
+    HIPCHK(launch_state_split((int)ni, c->offsets, c->u, c->vf, c->w, c->v0, s));       // back to (v0, u)
+    c->fp_iters_last = it;
+    c->fp_iters_max = std::max(c->fp_iters_max, it);
+    return TSM_OK;
+}
+
 tsm_status build_graph(tsm_ctx* c) {
     c->drop_graph();
-    if (c->prm.flags & (TSM_FLAG_NO_GRAPH | TSM_FLAG_TIMING)) return TSM_OK;
+    if (c->prm.flags & (TSM_FLAG_NO_GRAPH | TSM_FLAG_TIMING | TSM_FLAG_FIXED_POINT)) return TSM_OK;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     tsm_status st = enqueue_step(c);
     hipGraph_t g = nullptr;
@@ -373,6 +448,8 @@ void tsm_default_params(tsm_params* p) {
     p->max_refine = 12;
     p->checkpoint_every = 10;
     p->flags = 0;
+    p->fp_rtol = 1e-10;
+    p->fp_max_iter = 50;
 }
 
 namespace {
@@ -393,7 +470,7 @@ tsm_status tsm_create(const tsm_params* p, void* stream, tsm_ctx** out) {
                     p->p > 0 && p->dt > 0 && (p->source_sign == 1 || p->source_sign == -1) &&
                     (p->precision == TSM_FP64 || p->precision == TSM_FP32_REFINE) && p->rtol > 0 &&
                     p->inner_rtol > 0 && p->inner_rtol < 1 && p->setup_rtol > 0 && p->max_iter >= 1 &&
-                    p->max_refine >= 1 && p->checkpoint_every >= 1 && std::isfinite(p->D) &&
+                    p->max_refine >= 1 && p->checkpoint_every >= 1 && p->fp_rtol > 0 && p->fp_max_iter >= 2 && std::isfinite(p->D) &&
                     std::isfinite(p->d) && std::isfinite(p->kappa) && std::isfinite(p->p) && std::isfinite(p->dt);
     if (!ok) return create_failed(nullptr, TSM_EINVAL, "parameter out of range");
     tsm_ctx* c = new tsm_ctx();
@@ -493,6 +570,7 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     const int n = c->NM - 1;
     HIPALLOC(c->rhs, (size_t)n * n); HIPALLOC(c->R, (size_t)n * n); HIPALLOC(c->T1, (size_t)n * n);
     HIPALLOC(c->T2, (size_t)n * n); HIPALLOC(c->Q, (size_t)n * n); HIPALLOC(c->lam, (size_t)n * n);
+    HIPALLOC(c->lam_fp, (size_t)n * n);
     c->have_mesh = true;
     return TSM_OK;
 }
@@ -558,6 +636,12 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
     tsm_status st = enqueue_micro(c, ma, true);
     if (st != TSM_OK) return st;
     HIPCHK(launch_beta((int)n_inst, c->prm.kappa, c->prm.p, c->len, c->bx, c->beta, c->stream));
+    {
+        std::vector<double> kp_h(n_inst, c->prm.kappa * c->prm.p);
+        if (!c->beta_fp) HIPALLOC(c->beta_fp, n_inst);
+        HIPCHK(hipMemcpyAsync(c->beta_fp, kp_h.data(), n_inst * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
     std::vector<double> bh(n_inst);
     int32_t nc = 0;
     HIPCHK(hipMemcpyAsync(bh.data(), c->beta, n_inst * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -584,11 +668,14 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
     }
     double lmin = 1e300;
     const double sg = c->prm.source_sign;
+    const double kp = c->prm.kappa * c->prm.p;
+    std::vector<double> lf((size_t)n * n);
     for (int l2 = 0; l2 < n; ++l2)
         for (int l1 = 0; l1 < n; ++l1) {
-            const double v = mk[l1] * mk[l2] / c->prm.dt + c->prm.D * (kk[l1] * mk[l2] + mk[l1] * kk[l2]) -
-                             sg * bref * H * H;
+            const double a0 = mk[l1] * mk[l2] / c->prm.dt + c->prm.D * (kk[l1] * mk[l2] + mk[l1] * kk[l2]);
+            const double v = a0 - sg * bref * H * H;
             lh[(size_t)l2 * n + l1] = v;
+            lf[(size_t)l2 * n + l1] = a0 - sg * kp * H * H;   // lagged coupling: beta = kappa p, exact
             lmin = std::min(lmin, std::fabs(v));
         }
     const double qs = std::sqrt(2.0 / (n + 1));
@@ -603,6 +690,7 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
     c->macro_sweeps = std::min(sweeps, 64);
     HIPCHK(hipMemcpy(c->Q, Qh.data(), Qh.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->lam, lh.data(), lh.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->lam_fp, lf.data(), lf.size() * sizeof(double), hipMemcpyHostToDevice));
 
     c->have_geom = true;
     tsm_status gs = build_graph(c);
@@ -636,7 +724,8 @@ tsm_status tsm_step(tsm_ctx* c, int32_t n_steps) {
     if (!c) return TSM_EINVAL;
     if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
     if (n_steps < 0) return c->fail(TSM_EINVAL, "n_steps < 0");
-    const bool timing = (c->prm.flags & TSM_FLAG_TIMING) != 0;
+    // per-phase events bracket the exact step only (the alternating step times as a whole)
+    const bool timing = (c->prm.flags & TSM_FLAG_TIMING) && !(c->prm.flags & TSM_FLAG_FIXED_POINT);
     if (timing) {
         while ((int)c->tev.size() < 3 * n_steps) {
             hipEvent_t e;
@@ -646,8 +735,13 @@ tsm_status tsm_step(tsm_ctx* c, int32_t n_steps) {
     }
     HIPCHK(hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->stream));
     HIPCHK(hipEventRecord(c->ev0, c->stream));
+    const bool fixed_point = (c->prm.flags & TSM_FLAG_FIXED_POINT) != 0;
+    if (fixed_point) c->fp_iters_max = 0;
     for (int s = 0; s < n_steps; ++s) {
-        if (c->graph) {
+        if (fixed_point) {
+            tsm_status st = step_fixed_point(c);
+            if (st != TSM_OK) return st;
+        } else if (c->graph) {
             HIPCHK(hipGraphLaunch(c->graph, c->stream));
         } else {
             tsm_status st = enqueue_step(c, timing ? &c->tev[3 * s] : nullptr);
@@ -877,7 +971,8 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
 tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
     if (!c) return TSM_EINVAL;
     const bool replan = ((flags ^ c->prm.flags) & (TSM_FLAG_STENCIL_STREAM | TSM_FLAG_GENERIC)) != 0;
-    if (flags & ~(TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_TIMING | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT))
+    if (flags & ~(TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_TIMING | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT |
+                  TSM_FLAG_FIXED_POINT))
         return c->fail(TSM_EINVAL, "unknown flag bits");
     HIPCHK(hipStreamSynchronize(c->stream));
     c->prm.flags = flags;
@@ -956,6 +1051,8 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
     s->timed_steps = c->timed_steps;
     const size_t packed = ((c->prm.flags & TSM_FLAG_PERSISTENT) && !c->pack_groups.empty()) ? 1 : c->pack_groups.size();
     s->micro_launches = (int32_t)(c->groups.size() + packed);
+    s->fp_iters_last = c->fp_iters_last;
+    s->fp_iters_max = c->fp_iters_max;
     s->grad_forward_ms = c->grad_fwd_ms;
     s->grad_backward_ms = c->grad_bwd_ms;
     if (c->have_geom && c->n_inst > 0) {

@@ -150,6 +150,22 @@ __global__ void adjoint_coef_kernel(MacroArgs m, const double* mu, double* coef)
     coef[k] = -m.sig_h2 * mu[k] / (m.p * m.len[k]);
 }
 
+// Residual sum of the alternating coupling (paper Section 3.3: the macro and
+// micro solves alternate until the sum of the residuals settles).
+__global__ __launch_bounds__(1024) void coupling_residual_kernel(int nR, const double* R, int n_inst,
+                                                                 const double* res, double* out) {
+    __shared__ double red_s[2][2][1024 / kWave];
+    BlockReducer<1024 / kWave, 2, double> red(red_s);
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < nR; i += 1024) v[0] += R[i] * R[i];
+    for (int i = threadIdx.x; i < n_inst; i += 1024) v[1] += res[i];
+    red.sum(v);
+    if (threadIdx.x == 0) {
+        out[0] = sqrt(v[0]);
+        out[1] = v[1] / n_inst;
+    }
+}
+
 inline int blocks(int n, int t) { return (n + t - 1) / t; }
 
 }  // namespace
@@ -185,6 +201,13 @@ hipError_t launch_gemm(int n, const double* A, const double* B, double* C, int e
 
 hipError_t launch_observable(const MacroArgs& m, const double* u, double* J, hipStream_t s) {
     hipLaunchKernelGGL(observable_kernel, dim3(1), dim3(1024), 0, s, m, u, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_coupling_residual(int nR, const double* R, int n_inst, const double* res, double* out,
+                                    hipStream_t s) {
+    if (n_inst <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(coupling_residual_kernel, dim3(1), dim3(1024), 0, s, nR, R, n_inst, res, out);
     return hipGetLastError();
 }
 

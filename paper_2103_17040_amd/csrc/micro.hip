@@ -69,6 +69,7 @@ __device__ __forceinline__ void load_initial(const MicroArgs& A, int inst, const
     }
     __syncthreads();
     const double* __restrict__ Mm = A.M64 + kStencil * g.off;
+    const double bc = (A.rhs_vec != nullptr && A.rhs_bcoef != nullptr) ? A.rhs_bscale * A.rhs_bcoef[inst] : 0.0;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int j = tid + s * NT;
@@ -76,6 +77,7 @@ __device__ __forceinline__ void load_initial(const MicroArgs& A, int inst, const
         if (j < g.n) {
             if (A.rhs_vec != nullptr) {
                 v = A.rhs_scale * A.rhs_vec[g.off + j];
+                if (A.rhs_bcoef != nullptr) v += bc * A.b[g.off + j];
             } else {
                 double m = 0.0;
 #pragma unroll
@@ -90,7 +92,7 @@ __device__ __forceinline__ void load_initial(const MicroArgs& A, int inst, const
 template <int SLOTS>
 __device__ __forceinline__ void write_result(const MicroArgs& A, int inst, const Geo& g,
                                              const double (&x)[SLOTS], int iters, int sweeps, bool conv,
-                                             BlockReducer<NW, 1, double>& red1) {
+                                             double rr, BlockReducer<NW, 1, double>& red1) {
     const int tid = threadIdx.x;
     double bx[1] = {0.0};
 #pragma unroll
@@ -106,6 +108,7 @@ __device__ __forceinline__ void write_result(const MicroArgs& A, int inst, const
         A.bx_out[inst] = bx[0];
         if (A.iters_out) A.iters_out[inst] = iters;
         if (A.sweeps_out) A.sweeps_out[inst] = sweeps;
+        if (A.res_out) A.res_out[inst] = sqrt(rr);
         if (!conv) atomicAdd(A.nonconv, 1);
     }
 }
@@ -192,7 +195,7 @@ __device__ void solve_fp64(const MicroArgs& A, int inst, double* xs,
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) p[s] = dinv[s] * r[s] + beta * p[s];
     }
-    write_result<SLOTS>(A, inst, g, x, it, 1, conv, red1);
+    write_result<SLOTS>(A, inst, g, x, it, 1, conv, rr, red1);
 }
 
 // ------------------------------------------- FP32 PCG inside FP64 refinement
@@ -227,7 +230,7 @@ __device__ void solve_refine(const MicroArgs& A, int inst, double* xs, float* ps
             for (int k = 0; k < kStencil; ++k) Sr[s][k] = 0.0f;
         }
     }
-    double bn2 = 0.0;
+    double bn2 = 0.0, rr_last = 0.0;
     int sweeps = 0, iters = 0;
     bool conv = false;
     for (;;) {
@@ -259,6 +262,7 @@ __device__ void solve_refine(const MicroArgs& A, int inst, double* xs, float* ps
         red3.sum(acc);
         if (sweeps == 0) bn2 = acc[0];
         ++sweeps;
+        rr_last = acc[1];
         if (acc[1] <= A.rtol * A.rtol * bn2) { conv = true; break; }
         if (sweeps > A.max_refine) break;
         // inner FP32 solve of S d = r / ||r||, zero initial guess
@@ -323,7 +327,7 @@ __device__ void solve_refine(const MicroArgs& A, int inst, double* xs, float* ps
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) x[s] += rn * (double)d[s];
     }
-    write_result<SLOTS>(A, inst, g, x, iters, sweeps, conv, red1);
+    write_result<SLOTS>(A, inst, g, x, iters, sweeps, conv, rr_last, red1);
 }
 
 // MODE: 0 FP64 resident stencil, 1 FP64 streamed, 2 refine resident, 3 refine streamed
@@ -402,6 +406,19 @@ __global__ __launch_bounds__(NT) void apply_kernel(const int32_t* level, const i
     }
 }
 
+// out_i = b_i^T x_i (one workgroup per instance, fixed summation order)
+__global__ __launch_bounds__(NT) void bdot_kernel(const int64_t* offsets, const double* b, const double* x,
+                                                  double* out) {
+    __shared__ double red_s[2][1][NW];
+    BlockReducer<NW, 1, double> red(red_s);
+    const int inst = blockIdx.x;
+    const int64_t off = offsets[inst], n = offsets[inst + 1] - off;
+    double v[1] = {0.0};
+    for (int64_t j = threadIdx.x; j < n; j += NT) v[0] += b[off + j] * x[off + j];
+    red.sum(v);
+    if (threadIdx.x == 0) out[inst] = v[0];
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -424,6 +441,13 @@ hipError_t launch_apply(int n_inst, const int32_t* level, const int64_t* offsets
                         const double* S64, const double* x, double* y, hipStream_t s) {
     if (n_inst <= 0) return hipSuccess;
     hipLaunchKernelGGL(apply_kernel, dim3(n_inst), dim3(NT), 0, s, level, offsets, S64, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_bdot(int n_inst, const int64_t* offsets, const double* b, const double* x, double* out,
+                       hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bdot_kernel, dim3(n_inst), dim3(NT), 0, s, offsets, b, x, out);
     return hipGetLastError();
 }
 

@@ -327,7 +327,7 @@ __device__ __forceinline__ void strip_apply(const ST& S0, const TG* g, const Lan
 
 template <class L>
 __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, const double (&x)[L::R],
-                                           int iters, int sweeps, bool conv, PackRed<1, double>& red1) {
+                                           int iters, int sweeps, bool conv, double rr, PackRed<1, double>& red1) {
     double bx[1] = {0.0};
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
@@ -342,13 +342,14 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
         A.bx_out[z.inst] = bx[0];
         if (A.iters_out) A.iters_out[z.inst] = iters;
         if (A.sweeps_out) A.sweeps_out[z.inst] = sweeps;
+        if (A.res_out) A.res_out[z.inst] = sqrt(rr);
         if (!conv) atomicAdd(A.nonconv, 1);
     }
 }
 
 // x0 into registers and the (double) grid, then the FP64 residual and the
 // partial ||b||^2:
-//   given right-hand side:  b = rhs_scale rhs,  r = b - S x0
+//   given right-hand side:  b = rhs_scale rhs [+ rhs_bscale c_i b_i],  r = b - S x0
 //   time step:              b = M x0 / dt,      r = b - S x0 = -K x0
 // (K = S - M/dt is stored on its own, so the residual carries no
 // cancellation; M, in FP32, only sizes ||b||).
@@ -376,6 +377,12 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
 #pragma unroll
         for (int i = 0; i < L::R; ++i)
             b[i] = row_ok<L>(z, i) ? A.rhs_scale * A.rhs_vec[z.off + node_of<L>(z, i)] : 0.0;
+        if (A.rhs_bcoef != nullptr) {
+            const double bc = z.live ? A.rhs_bscale * A.rhs_bcoef[z.inst] : 0.0;
+#pragma unroll
+            for (int i = 0; i < L::R; ++i)
+                if (row_ok<L>(z, i)) b[i] += bc * A.b[z.off + node_of<L>(z, i)];
+        }
         if (z.act) strip_apply<L, 3>(SymStencil<L, double>{A.Ss64 + kSym * z.off}, xg, z, x, sx);
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
@@ -419,7 +426,7 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
     __shared__ double tol_s[L::IPP];
     const double tol2 = A.rtol * A.rtol * acc[0];
     if (z.live && z.lt == 0) tol_s[z.sub] = tol2;
-    double rz = acc[1];
+    double rz = acc[1], rr = acc[2];
     bool conv = acc[2] <= tol2;
     int it = 0;
     __syncthreads();
@@ -448,6 +455,7 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
             a3[2] += r[i] * r[i];
         }
         red3.sum<L>(a3, z.w0);
+        rr = a3[2];
         ++k;
         if (me) {
             ++it;
@@ -462,7 +470,7 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
         }
         go = red3.any_above(thr);
     }
-    pack_store<L>(A, z, x, it, 1, conv, red1);
+    pack_store<L>(A, z, x, it, 1, conv, rr, red1);
 }
 
 // --------------------------------------------------------------- REFINE
@@ -596,7 +604,7 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
         rr = a1[2];
         if (!conv && rr <= tol2) conv = true;
     }
-    pack_store<L>(A, z, x, iters, sweeps, conv, red1);
+    pack_store<L>(A, z, x, iters, sweeps, conv, rr, red1);
 }
 
 // Reduction buffers of one packed workgroup.

@@ -76,7 +76,7 @@ struct AssembleArgs {
 };
 
 // One batched micro solve: for every task t, instance i = order[t] solves
-//   S_i x = rhs_i,   rhs_i = rhs_scale * rhs_vec_i       (rhs_vec != null)
+//   S_i x = rhs_i,   rhs_i = rhs_scale * rhs_vec_i [+ rhs_bscale * rhs_bcoef_i * b_i]   (rhs_vec != null)
 //                    rhs_i = M_i x0_i / dt                (otherwise)
 // from the initial guess x0_i = X0_i + coef_i * w_i (zero if zero_init).
 // Writes x to X_out and b_i^T x to bx_out[i].
@@ -101,6 +101,9 @@ struct MicroArgs {
     const double* coef;
     const double* rhs_vec;
     double rhs_scale;
+    const double* rhs_bcoef;   // with rhs_vec: rhs_i += rhs_bscale * rhs_bcoef[i] * b_i (may be null)
+    double rhs_bscale;
+    double* res_out;           // optional: final FP64 residual norm ||rhs - S x||_2 per instance
     int zero_init;
     double* X_out;
     double* bx_out;
@@ -146,6 +149,13 @@ size_t packed_lds_bytes(int level);      // dynamic LDS of one pack
 hipError_t launch_apply(int n_inst, const int32_t* level, const int64_t* offsets,
                         const double* S64, const double* x, double* y, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int n, hipStream_t s);
+// out_i = b_i^T x_i for every instance
+hipError_t launch_bdot(int n_inst, const int64_t* offsets, const double* b, const double* x, double* out,
+                       hipStream_t s);
+// residual sum of the alternating coupling: out[0] = ||R||_2 (nR interior macro rows),
+// out[1] = mean over instances of res (per-instance micro residual norms)
+hipError_t launch_coupling_residual(int nR, const double* R, int n_inst, const double* res, double* out,
+                                    hipStream_t s);
 
 // macro kernels
 hipError_t launch_macro_rhs_forward(const MacroArgs& m, const double* u, const double* bx,

@@ -26,6 +26,7 @@ TSM_FLAG_STENCIL_STREAM = 1 << 1
 TSM_FLAG_TIMING = 1 << 2
 TSM_FLAG_GENERIC = 1 << 3
 TSM_FLAG_PERSISTENT = 1 << 4
+TSM_FLAG_FIXED_POINT = 1 << 5
 
 STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV",
                 -4: "TSM_EHIP", -5: "TSM_ENOMEM", -6: "TSM_ESTATE"}
@@ -42,7 +43,8 @@ class tsm_params(ctypes.Structure):
                 ("source_sign", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("setup_rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("max_refine", ctypes.c_int32),
-                ("checkpoint_every", ctypes.c_int32), ("flags", ctypes.c_uint64)]
+                ("checkpoint_every", ctypes.c_int32), ("flags", ctypes.c_uint64),
+                ("fp_rtol", ctypes.c_double), ("fp_max_iter", ctypes.c_int32)]
 
 
 class tsm_stats(ctypes.Structure):
@@ -54,7 +56,8 @@ class tsm_stats(ctypes.Structure):
                 ("micro_ms", ctypes.c_double), ("macro_ms", ctypes.c_double),
                 ("timed_steps", ctypes.c_int32), ("micro_launches", ctypes.c_int32),
                 ("grad_forward_ms", ctypes.c_double), ("grad_backward_ms", ctypes.c_double),
-                ("sweeps_mean", ctypes.c_double)]
+                ("sweeps_mean", ctypes.c_double),
+                ("fp_iters_last", ctypes.c_int32), ("fp_iters_max", ctypes.c_int32)]
 
 
 class TsmError(RuntimeError):

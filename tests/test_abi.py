@@ -47,7 +47,7 @@ def test_params_struct_layout_and_validation(lib_built):
     assert p.macro_cells == 8 and p.kappa == 1.0 and p.source_sign == -1 and p.rtol == 1e-12
     bad = []
     for field, value in (("D", 0.0), ("dt", -1.0), ("source_sign", 0), ("precision", 7), ("macro_cells", 1),
-                         ("inner_rtol", 1.5), ("p", float("nan"))):
+                         ("inner_rtol", 1.5), ("p", float("nan")), ("fp_rtol", 0.0), ("fp_max_iter", 1)):
         q = tsm.tsm_default_params()
         setattr(q, field, value)
         bad.append(q)
