@@ -79,6 +79,23 @@ def boundary_weight(y1, y2, tau, a, theta=0.0):
     return np.sqrt(np.sum(Ft * Ft, axis=-1))
 
 
+def pullback_from_jacobian(F):
+    """(J, C = K K^T J) from given Jacobians F = D zeta, shape (..., 2, 2):
+    the same change of variables for a map known only through its Jacobian
+    at the quadrature points."""
+    F = np.asarray(F, dtype=np.float64)
+    J = np.linalg.det(F)
+    K = np.linalg.inv(F)
+    C = np.einsum("...ij,...kj->...ik", K, K) * J[..., None, None]
+    return J, C
+
+
+def boundary_weight_from_jacobian(F, tau):
+    """|F tau| for given Jacobians F (..., 2, 2) and a reference unit tangent."""
+    Ft = np.asarray(F, dtype=np.float64) @ np.asarray(tau, dtype=np.float64)
+    return np.sqrt(np.sum(Ft * Ft, axis=-1))
+
+
 # ---------------------------------------------------------------------------
 # a-derivatives (used by the discrete adjoint).  With M = I + a G and
 # F = R M:  dF/da = R G;  dJ/da = J tr(F^{-1} dF/da);

@@ -118,12 +118,17 @@ def boundary_edges(N):
 def assemble_boundary(N, weight_fn):
     """B_jk = sum over boundary edges and 2 Gauss points of
     (h/2) * w(y) * eta_j eta_k, with w = weight_fn(y1, y2, tau)."""
+    return assemble_boundary_weights(N, [weight_fn(y1, y2, tau) for _, _, y1, y2, tau in boundary_edges(N)])
+
+
+def assemble_boundary_weights(N, weights):
+    """B from the surface weights at the boundary Gauss points, one (N, 2)
+    array per side in the order of boundary_edges (bottom, top, left, right)."""
     h = 2.0 / N
     n = (N + 1) ** 2
     rows, cols, vals = [], [], []
     basis = np.stack([1.0 - GAUSS_X, GAUSS_X], axis=1)     # (g, local)
-    for na, nb, y1, y2, tau in boundary_edges(N):
-        w = weight_fn(y1, y2, tau)                           # (N, 2)
+    for (na, nb, _, _, _), w in zip(boundary_edges(N), weights):
         Be = np.einsum("g,eg,gl,gm->elm", GAUSS_W * h, w, basis, basis)
         loc = np.stack([na, nb], axis=1)
         rows.append(np.repeat(loc, 2, axis=1).ravel())
@@ -142,6 +147,28 @@ def micro_matrices(N, a, theta=0.0):
     M, A = assemble_cells(N, -1.0, h, J, C)
     B = assemble_boundary(N, lambda s1, s2, tau: geo.boundary_weight(s1, s2, tau, a, theta))
     return M, A, B
+
+
+def quadrature_points(N):
+    """Reference coordinates of the points where a map's Jacobian is needed:
+    cells (N*N, 4) in cell order c2*N + c1 and point order g2*2 + g1, and
+    boundary (4, N, 2) per side (bottom, top, left, right), edge, point."""
+    h = 2.0 / N
+    _, y1, y2, _, _, _ = _quad_points(N, -1.0, h)
+    b1 = np.stack([e[2] for e in boundary_edges(N)])
+    b2 = np.stack([e[3] for e in boundary_edges(N)])
+    return (y1, y2), (b1, b2)
+
+
+def micro_matrices_from_jacobians(N, Fc, Fb):
+    """(M, A, B) of one instance whose map is known only through its
+    Jacobians: Fc (N*N, 4, 2, 2) at the cell Gauss points and Fb (4, N, 2, 2, 2)
+    at the boundary Gauss points (layout of quadrature_points)."""
+    h = 2.0 / N
+    J, C = geo.pullback_from_jacobian(Fc)
+    M, A = assemble_cells(N, -1.0, h, J, C)
+    W = [geo.boundary_weight_from_jacobian(Fb[k], tau) for k, (_, _, _, _, tau) in enumerate(boundary_edges(N))]
+    return M, A, assemble_boundary_weights(N, W)
 
 
 def micro_matrices_da(N, a, theta=0.0):

@@ -80,9 +80,15 @@ class BandedSPD:
 class Instance:
     """One micro system: time-invariant matrices and the affine response."""
 
-    def __init__(self, N, a, theta, prm: Params):
-        self.N, self.a, self.theta = int(N), float(a), float(theta)
-        self.M, self.A, self.B = fem.micro_matrices(self.N, self.a, self.theta)
+    def __init__(self, N, a, theta, prm: Params, jacobians=None):
+        self.N = int(N)
+        if jacobians is None:
+            self.a, self.theta = float(a), float(theta)
+            self.M, self.A, self.B = fem.micro_matrices(self.N, self.a, self.theta)
+        else:
+            # a general map, given by its Jacobians at the quadrature points
+            self.a = self.theta = None
+            self.M, self.A, self.B = fem.micro_matrices_from_jacobians(self.N, *jacobians)
         self.S = (self.M / prm.dt + prm.d * self.A + prm.kappa * self.B).tocsr()
         self.b = np.asarray(self.B.sum(axis=1)).ravel()
         self.len = float(self.b.sum())
@@ -98,14 +104,21 @@ class Instance:
 class TwoScale:
     """The full batch: one Instance per macro node plus the macro operator."""
 
-    def __init__(self, prm: Params, levels, a, theta=None):
+    def __init__(self, prm: Params, levels, a, theta=None, jacobians=None):
+        """jacobians: None (the deformation family with amplitudes a, angles
+        theta) or one (Fc, Fb) pair per instance (fem.micro_matrices_from_jacobians)."""
         self.prm = prm
         n_inst = (prm.macro_cells + 1) ** 2
         levels = np.asarray(levels)
-        a = np.asarray(a, dtype=np.float64)
-        theta = np.zeros(n_inst) if theta is None else np.asarray(theta, dtype=np.float64)
-        assert levels.shape == a.shape == theta.shape == (n_inst,)
-        self.inst = [Instance(levels[i], a[i], theta[i], prm) for i in range(n_inst)]
+        assert levels.shape == (n_inst,)
+        if jacobians is None:
+            a = np.asarray(a, dtype=np.float64)
+            theta = np.zeros(n_inst) if theta is None else np.asarray(theta, dtype=np.float64)
+            assert a.shape == theta.shape == (n_inst,)
+            self.inst = [Instance(levels[i], a[i], theta[i], prm) for i in range(n_inst)]
+        else:
+            assert len(jacobians) == n_inst
+            self.inst = [Instance(levels[i], None, None, prm, jacobians[i]) for i in range(n_inst)]
         self.offsets = np.concatenate([[0], np.cumsum([I.n for I in self.inst])]).astype(np.int64)
         self.MH, self.KH, self.L = fem.macro_matrices(prm.macro_cells)
         self.bnd = fem.macro_boundary(prm.macro_cells)

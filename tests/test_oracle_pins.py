@@ -402,3 +402,61 @@ def test_paper_tables_rate_formula_after_unswapping_last_rows():
     r = t["macro"]
     q = observed_rates([float(x[0]) for x in r], [float(x[3]) for x in r])
     assert q[-1] < 0
+
+
+# ------------------------------------------------------------ general maps
+def test_jacobian_tables_reproduce_the_analytic_instance():
+    """Tables of the family's own Jacobian (the workloads generator, its own
+    layout) give the analytic instance's matrices: ties the table path, and
+    the table layout, to the pinned analytic path."""
+    from oracle import fem
+    for N, a, th in ((4, 0.3, 0.0), (7, -0.25, 1.1)):
+        per, _, _ = W.jacobian_tables(np.array([N]), W.sinusoidal_map_jacobian, [(a, th)])
+        Mt, At, Bt = fem.micro_matrices_from_jacobians(N, *per[0])
+        M, A, B = fem.micro_matrices(N, a, th)
+        for X, Y in ((Mt, M), (At, A), (Bt, B)):
+            assert abs(X - Y).max() <= 1e-14 * abs(Y).max()
+
+
+def test_jacobian_tables_affine_map_closed_forms():
+    """A constant Jacobian F (an affine map): area 4 det F, perimeter
+    4(|F e1| + |F e2|), and the energy of the physically linear function
+    v = g . zeta(y) is |g|^2 * area (Q1 reproduces it exactly)."""
+    from oracle import fem
+    F = np.array([[1.2, 0.3], [-0.1, 0.9]])
+    g = np.array([0.7, -1.3])
+    for N in (3, 8):
+        per, _, _ = W.jacobian_tables(np.array([N]), lambda y1, y2: np.broadcast_to(F, np.shape(y1) + (2, 2)).copy(), [()])
+        M, A, B = fem.micro_matrices_from_jacobians(N, *per[0])
+        one = np.ones((N + 1) ** 2)
+        area = 4.0 * np.linalg.det(F)
+        assert abs(one @ M @ one - area) <= 1e-13 * area
+        perim = 4.0 * (np.linalg.norm(F[:, 0]) + np.linalg.norm(F[:, 1]))
+        assert abs(one @ B @ one - perim) <= 1e-13 * perim
+        h = 2.0 / N
+        j = np.arange((N + 1) ** 2)
+        y1, y2 = -1.0 + (j % (N + 1)) * h, -1.0 + (j // (N + 1)) * h
+        z = F @ np.stack([y1, y2])
+        v = g @ z
+        assert abs(v @ A @ v - g @ g * area) <= 1e-12 * g @ g * area
+
+
+def test_polynomial_test_map_is_a_valid_deformation():
+    """The general-map test family: Jacobian vs central differences of the
+    map, det > 0 on the tables, and it really leaves the sinusoidal family
+    (the cell's area changes)."""
+    from oracle import fem
+    c, d, th = 0.2, -0.25, 0.7
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    zeta = lambda y1, y2: R @ np.array([y1 + c * y1 * y2, y2 + d * y1 * y1 * y2])
+    for y in ((0.3, -0.6), (-0.9, 0.8)):
+        e = 1e-6
+        Ffd = np.stack([(zeta(y[0] + e, y[1]) - zeta(y[0] - e, y[1])) / (2 * e),
+                        (zeta(y[0], y[1] + e) - zeta(y[0], y[1] - e)) / (2 * e)], axis=1)
+        assert np.allclose(W.polynomial_map_jacobian(y[0], y[1], c, d, th), Ffd, atol=1e-8)
+    per, _, _ = W.jacobian_tables(np.array([6]), W.polynomial_map_jacobian, [(c, d, th)])
+    assert np.linalg.det(per[0][0]).min() > 0.3
+    M, _, _ = fem.micro_matrices_from_jacobians(6, *per[0])
+    one = np.ones(49)
+    # area of zeta(Z) = int (1 + c y2)(1 + d y1^2) - 2 c d y1^2 y2 = 4 (1 + d/3)
+    assert abs(one @ M @ one - 4.0 * (1.0 + d / 3.0)) <= 1e-13 * 4.0   # Gauss is exact here

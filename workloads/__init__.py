@@ -173,3 +173,84 @@ def make(name: str, seed: int = 0):
     """(workload, a, theta, levels) for a named workload."""
     w = WORKLOADS[name]
     return w, amplitudes(w, seed), thetas(w, seed), levels(w, seed)
+
+
+# ---------------------------------------------------------------------------
+# Maps given by their Jacobians (general-geometry input).  A user with any
+# map zeta supplies D zeta at the points the interface lists: per instance,
+# the 2x2 Gauss points of every reference cell (cells c2*N + c1, points
+# g2*2 + g1) and the 2 Gauss points of every boundary edge (sides bottom,
+# top, left, right; edges in increasing coordinate).  The generator below
+# evaluates the derivative of a seeded test map there; it is input data.
+# ---------------------------------------------------------------------------
+_GAUSS01 = (0.5 - 0.5 / math.sqrt(3.0), 0.5 + 0.5 / math.sqrt(3.0))
+
+
+def table_points(N: int):
+    """Reference coordinates of the Jacobian table of one instance with N
+    cells per side: cells (N*N, 4) and boundary (4, N, 2) arrays of (y1, y2)."""
+    h = 2.0 / N
+    g = np.array(_GAUSS01)
+    c = np.arange(N)
+    # cells: c2 slow, c1 fast; points: g2 slow, g1 fast
+    y1 = (-1.0 + (c[None, :, None, None] + g[None, None, None, :]) * h) * np.ones((N, 1, 2, 1))
+    y2 = (-1.0 + (c[:, None, None, None] + g[None, None, :, None]) * h) * np.ones((1, N, 1, 2))
+    cell = (y1.reshape(N * N, 4), y2.reshape(N * N, 4))
+    s = -1.0 + (c[:, None] + g[None, :]) * h              # (edge, point) along a side
+    one = np.ones_like(s)
+    b1 = np.stack([s, s, -one, one])
+    b2 = np.stack([-one, one, s, s])
+    return cell, (b1, b2)
+
+
+def polynomial_map_jacobian(y1, y2, c, d, theta):
+    """D zeta of the test map zeta(y) = R_theta (y1 + c y1 y2, y2 + d y1^2 y2),
+    a map outside the sinusoidal family (the cell changes shape and size).
+    det D zeta > 0 for |c|, |d| <= 0.25 on [-1,1]^2."""
+    y1 = np.asarray(y1, dtype=np.float64)
+    y2 = np.asarray(y2, dtype=np.float64)
+    M = np.empty(y1.shape + (2, 2))
+    M[..., 0, 0] = 1.0 + c * y2
+    M[..., 0, 1] = c * y1
+    M[..., 1, 0] = 2.0 * d * y1 * y2
+    M[..., 1, 1] = 1.0 + d * y1 * y1
+    R = np.array([[math.cos(theta), -math.sin(theta)], [math.sin(theta), math.cos(theta)]])
+    return np.einsum("ij,...jk->...ik", R, M)
+
+
+def sinusoidal_map_jacobian(y1, y2, a, theta):
+    """D zeta of the workloads' family zeta(y) = R_theta (y + a phi(y)),
+    phi = (sin(pi y1) y2, sin(pi y2) y1)/4 (for checking the table layout)."""
+    y1 = np.asarray(y1, dtype=np.float64)
+    y2 = np.asarray(y2, dtype=np.float64)
+    M = np.empty(y1.shape + (2, 2))
+    M[..., 0, 0] = 1.0 + a * 0.25 * math.pi * np.cos(math.pi * y1) * y2
+    M[..., 0, 1] = a * 0.25 * np.sin(math.pi * y1)
+    M[..., 1, 0] = a * 0.25 * np.sin(math.pi * y2)
+    M[..., 1, 1] = 1.0 + a * 0.25 * math.pi * np.cos(math.pi * y2) * y1
+    R = np.array([[math.cos(theta), -math.sin(theta)], [math.sin(theta), math.cos(theta)]])
+    return np.einsum("ij,...jk->...ik", R, M)
+
+
+def jacobian_tables(levels_: np.ndarray, jac_fn, params):
+    """Tables of D zeta for every instance: jac_fn(y1, y2, *params[i]).
+    Returns (per-instance list of (Fc (N*N,4,2,2), Fb (4,N,2,2,2)),
+    flat cell table, flat boundary table) in the interface's layout."""
+    per, flat_c, flat_b = [], [], []
+    for i, N in enumerate(np.asarray(levels_).tolist()):
+        (c1, c2), (b1, b2) = table_points(int(N))
+        Fc = jac_fn(c1, c2, *params[i])
+        Fb = jac_fn(b1, b2, *params[i])
+        per.append((Fc, Fb))
+        flat_c.append(Fc.ravel())
+        flat_b.append(Fb.ravel())
+    return per, np.concatenate(flat_c), np.concatenate(flat_b)
+
+
+def polynomial_map_params(n_inst: int, seed: int = 0, strength: float = 0.25):
+    """Seeded (c, d, theta) per instance for polynomial_map_jacobian."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 777]))
+    c = rng.uniform(-strength, strength, n_inst)
+    d = rng.uniform(-strength, strength, n_inst)
+    th = rng.uniform(0.0, 2.0 * math.pi, n_inst)
+    return list(zip(c.tolist(), d.tolist(), th.tolist()))
