@@ -13,9 +13,10 @@ form (sum over instances of (N_i+1)^2 per step); the plain FP64 form on the
 same workload and tolerance is timed beside it, the dominant kernel's
 duration is measured with HIP events on the library's stream for the
 roofline, and the FP64 oracle is timed on a bounded sample on the host.
-Side legs on the same workload: the gradient (checkpointed forward +
-adjoint), and the paper's alternating macro/micro coupling timed against the
-exact coupling step.
+Side legs: the gradient (checkpointed forward + adjoint) and the paper's
+alternating macro/micro coupling timed against the exact coupling step, on
+the same workload; a general map given by Jacobian tables on the uneven
+4225-instance batch.
 """
 from __future__ import annotations
 
@@ -172,6 +173,39 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan
         g.close()
 
 
+def general_map_leg(steps, precision="fp32_refine", rtol=1e-10):
+    """A map outside the sinusoidal family, given by its Jacobian tables, on
+    the uneven 4225-instance batch (16/32/64 cells): setup from the tables
+    against setup from amplitudes on the same meshes, and the step time."""
+    import torch
+    from paper_2103_17040_amd import TwoScaleBatch
+    w, a, th, lv = W.make("uneven_mixed", 0)
+    per, Fc, Fb = W.jacobian_tables(lv, W.polynomial_map_jacobian, W.polynomial_map_params(len(lv), seed=2))
+    del per
+    u0 = W.initial_macro(w.macro_cells)
+    kw = dict(D=w.D, d=w.d, kappa=w.kappa, p=w.p, dt=w.dt, sigma=w.sigma, precision=precision, rtol=rtol)
+    g = TwoScaleBatch(w.macro_cells, lv, a, th, **kw)
+    setup_analytic = g.stats()["setup_ms"]
+    g.close()
+    g = TwoScaleBatch(w.macro_cells, lv, jacobians=(Fc, Fb), **kw)
+    try:
+        setup_tables = g.stats()["setup_ms"]
+        g.set_state(u0, None)
+        g.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        st = g.stats()
+    finally:
+        g.close()
+    return {"workload": f"{len(lv)} instances, 16/32/64 cells (uneven batch), polynomial map from Jacobian tables",
+            "table_bytes": 8 * (Fc.size + Fb.size), "setup_ms_tables": setup_tables,
+            "setup_ms_analytic": setup_analytic, "steps": steps, "ms_per_step": t * 1e3,
+            "micro_dofs": int(W.offsets(lv)[-1]), "iters_mean": st["iters_mean"], "precision": precision}
+
+
 def cpu_baseline(w, a, th, lv, seconds_hint=15.0):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
     a macro mesh of S cells per side (so (S+1)^2 instances) with the
@@ -215,6 +249,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--plan", default="auto", choices=["auto"] + sorted(PLAN_FLAGS),
                     help="launch plan of the micro solves (auto: the autotuner picks on the live state)")
+    ap.add_argument("--gm-steps", type=int, default=5,
+                    help="steps of the general-map leg (Jacobian tables, uneven batch; 0: skip)")
     ap.add_argument("--fp-steps", type=int, default=3,
                     help="steps of the alternating-coupling leg (0: skip), timed against the exact step")
     ap.add_argument("--adjoint-steps", type=int, default=40,
@@ -330,6 +366,9 @@ def main():
     if fpl is not None:
         fpl["over_exact_step"] = fpl["ms_per_step"] / out["ms_per_step"]
         out["fixed_point_coupling"] = fpl
+    if args.gm_steps > 0:
+        _log("general-map leg ...")
+        out["general_map"] = general_map_leg(args.gm_steps)
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, a, th, lv)

@@ -160,6 +160,26 @@ tsm_status tsm_get_offsets(const tsm_ctx* c, int64_t* offsets_out);
  * |cof(F) nu| unchanged, so it does not enter the arithmetic. */
 tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta, int64_t n_inst);
 
+/* General maps (Section 3.1: the map zeta enters the discrete problem only
+ * through its Jacobian at the quadrature points, whence the paper's cache of
+ * J and K K^T J per point).  Fcell and Fbnd (device pointers, row-major 2x2
+ * Jacobians F = D zeta, entries F11 F12 F21 F22) give D zeta of every
+ * instance at the reference points y = -1 + (cell + g) h, h = 2/N,
+ * g in {1/2 - 1/(2 sqrt 3), 1/2 + 1/(2 sqrt 3)}:
+ *   Fcell: per instance (in instance order) its N^2 cells in order
+ *          c2*N + c1, each with 4 points in order g2*2 + g1 (g1 along y1):
+ *          16 N_i^2 values, n_cell = sum over instances;
+ *   Fbnd:  per instance its 4 sides (y2 = -1, y2 = +1, y1 = -1, y1 = +1),
+ *          each with N edges in increasing coordinate and 2 points:
+ *          32 N_i values, n_bnd = sum over instances.
+ * J = det F, K K^T J = adj(F) adj(F)^T / J and |cof(F) nu| = |F tau| are
+ * formed per point.  EINVAL on wrong sizes or NULL, EGEOM if det F <= 0 or an
+ * entry is not finite at some point; otherwise the same setup as
+ * tsm_set_deformation.  The tables are read during the call only.
+ * tsm_gradient (derivatives with respect to amplitudes) is not available
+ * for a geometry given this way (ESTATE). */
+tsm_status tsm_set_jacobians(tsm_ctx* c, const double* Fcell, int64_t n_cell, const double* Fbnd, int64_t n_bnd);
+
 /* State (device pointers): u has n_inst entries (macro-boundary entries
  * are forced to 0), v is ragged or NULL (= 0).  Resets steps_taken. */
 tsm_status tsm_set_state(tsm_ctx* c, const double* u, const double* v);

@@ -16,7 +16,7 @@ class TwoScaleBatch:
     Inputs may be numpy arrays or torch tensors; outputs are torch CUDA
     tensors (float64)."""
 
-    def __init__(self, macro_cells, micro_cells, a, theta=None, *, D=1.0, d=0.5, kappa=1.0, p=1.0,
+    def __init__(self, macro_cells, micro_cells, a=None, theta=None, *, jacobians=None, D=1.0, d=0.5, kappa=1.0, p=1.0,
                  dt=0.01, sigma=-1, precision="fp64", rtol=1e-12, inner_rtol=1e-2, setup_rtol=1e-14,
                  max_iter=1000, max_refine=12, checkpoint_every=10, flags=0, coupling="schur",
                  fp_rtol=1e-10, fp_max_iter=50, device="cuda:0"):
@@ -45,7 +45,10 @@ class TwoScaleBatch:
             tsm.tsm_set_reference_mesh(self.ctx, self._levels)
             self.offsets = tsm.tsm_get_offsets(self.ctx, self.n_inst)
             self.n_micro = int(self.offsets[-1])
-            self.set_deformation(a, theta)
+            if jacobians is not None:
+                self.set_jacobians(*jacobians)
+            else:
+                self.set_deformation(a, theta)
         except Exception:
             self.close()
             raise
@@ -63,6 +66,13 @@ class TwoScaleBatch:
         self._a = self._dev(a)
         self._theta = self._dev(theta)
         tsm.tsm_set_deformation(self.ctx, self._a, self._theta, self.n_inst)
+
+    def set_jacobians(self, Fcell, Fbnd):
+        """Geometry of a general map from its Jacobians at the quadrature
+        points (layout of tsm_set_jacobians in include/tsm.h)."""
+        self._Fc, self._Fb = self._dev(Fcell), self._dev(Fbnd)
+        tsm.tsm_set_jacobians(self.ctx, self._Fc, self._Fc.numel(), self._Fb, self._Fb.numel())
+        self._Fc = self._Fb = None   # read during the call only
 
     def set_state(self, u, v=None):
         tu, tv = self._dev(u), self._dev(v)

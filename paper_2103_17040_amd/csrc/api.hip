@@ -67,6 +67,8 @@ struct tsm_ctx {
     // per instance
     int32_t *level = nullptr, *order = nullptr, *iters = nullptr, *sweeps = nullptr, *counters = nullptr;
     int64_t* order_off = nullptr;   // offsets[order[t]]
+    int64_t *cell_off = nullptr, *bnd_off = nullptr;   // Jacobian tables per instance
+    bool geom_tables = false;       // geometry from tsm_set_jacobians (no amplitude gradient)
     int64_t* offsets = nullptr;
     double *amp = nullptr, *beta = nullptr, *len = nullptr, *jmin = nullptr, *bx = nullptr,
            *alpha = nullptr, *F = nullptr, *u = nullptr;
@@ -110,6 +112,8 @@ struct tsm_ctx {
     }
     void free_mesh() {
         dfree(level); dfree(order); dfree(order_off); dfree(iters); dfree(sweeps); dfree(offsets);
+        dfree(cell_off); dfree(bnd_off);
+        geom_tables = false;
         dfree(Ss64); dfree(Ks64); dfree(Ms32); dfree(Ss32); dfree(Sslo);
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32); dfree(Slo);
@@ -582,43 +586,23 @@ tsm_status tsm_get_offsets(const tsm_ctx* c, int64_t* out) {
     return TSM_OK;
 }
 
-tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta, int64_t n_inst) {
-    if (!c) return TSM_EINVAL;
-    if (!c->have_mesh) return c->fail(TSM_ESTATE, "set_reference_mesh first");
-    if (!a) return c->fail(TSM_EINVAL, "a is NULL");
-    if (n_inst != c->n_inst) return c->fail(TSM_EINVAL, "n_inst does not match the reference mesh");
-    const auto t0 = std::chrono::steady_clock::now();
-    HIPCHK(hipDeviceSynchronize());   // caller's producers of a, theta
-    std::vector<double> ah(n_inst), th(n_inst, 0.0);
-    HIPCHK(hipMemcpy(ah.data(), a, n_inst * sizeof(double), hipMemcpyDeviceToHost));
-    if (theta) HIPCHK(hipMemcpy(th.data(), theta, n_inst * sizeof(double), hipMemcpyDeviceToHost));
-    if (!finite_all(ah) || !finite_all(th)) return c->fail(TSM_EINVAL, "non-finite deformation parameter");
-    c->have_geom = false;
-    c->have_state = false;
-    c->have_deriv = false;
-    c->drop_graph();
-    HIPCHK(hipMemcpyAsync(c->amp, a, n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+extern "C++" {
+namespace {
 
-    AssembleArgs as;
-    as.n_inst = (int)n_inst;
-    as.level = c->level;
-    as.offsets = c->offsets;
-    as.amp = c->amp;
-    as.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
-    as.d = c->prm.d;
-    as.kappa = c->prm.kappa;
-    as.inv_dt = 1.0 / c->prm.dt;
-    as.S64 = c->S64; as.S32 = c->S32; as.Slo = c->Slo; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
-    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ms32 = c->Ms32; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
-    HIPCHK(launch_assemble(as, c->stream));
+// Everything after the assembly, shared by both geometry inputs: the det
+// check, the responses w_i, beta, the macro solver and the step graph.
+// what(i) describes instance i for the geometry error message.
+template <class What>
+tsm_status finish_setup(tsm_ctx* c, std::chrono::steady_clock::time_point t0, What what) {
+    const int64_t n_inst = c->n_inst;
     std::vector<double> jm(n_inst);
     HIPCHK(hipMemcpyAsync(jm.data(), c->jmin, n_inst * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     for (int64_t i = 0; i < n_inst; ++i)
         if (!(jm[i] > 0.0)) {
             char buf[160];
-            std::snprintf(buf, sizeof buf, "det D zeta = %.3e <= 0 at a quadrature point of instance %lld (a = %.6g)",
-                          jm[i], (long long)i, ah[i]);
+            std::snprintf(buf, sizeof buf, "det D zeta = %.3e <= 0 at a quadrature point of instance %lld (%s)",
+                          jm[i], (long long)i, what(i).c_str());
             return c->fail(TSM_EGEOM, buf);
         }
 
@@ -697,6 +681,92 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
     if (gs != TSM_OK) return gs;
     c->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return TSM_OK;
+}
+
+}  // namespace
+}  // extern "C++"
+
+tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta, int64_t n_inst) {
+    if (!c) return TSM_EINVAL;
+    if (!c->have_mesh) return c->fail(TSM_ESTATE, "set_reference_mesh first");
+    if (!a) return c->fail(TSM_EINVAL, "a is NULL");
+    if (n_inst != c->n_inst) return c->fail(TSM_EINVAL, "n_inst does not match the reference mesh");
+    const auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(hipDeviceSynchronize());   // caller's producers of a, theta
+    std::vector<double> ah(n_inst), th(n_inst, 0.0);
+    HIPCHK(hipMemcpy(ah.data(), a, n_inst * sizeof(double), hipMemcpyDeviceToHost));
+    if (theta) HIPCHK(hipMemcpy(th.data(), theta, n_inst * sizeof(double), hipMemcpyDeviceToHost));
+    if (!finite_all(ah) || !finite_all(th)) return c->fail(TSM_EINVAL, "non-finite deformation parameter");
+    c->have_geom = false;
+    c->have_state = false;
+    c->have_deriv = false;
+    c->geom_tables = false;
+    c->drop_graph();
+    HIPCHK(hipMemcpyAsync(c->amp, a, n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+
+    AssembleArgs as;
+    as.n_inst = (int)n_inst;
+    as.level = c->level;
+    as.offsets = c->offsets;
+    as.amp = c->amp;
+    as.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
+    as.d = c->prm.d;
+    as.kappa = c->prm.kappa;
+    as.inv_dt = 1.0 / c->prm.dt;
+    as.S64 = c->S64; as.S32 = c->S32; as.Slo = c->Slo; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
+    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ms32 = c->Ms32; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
+    HIPCHK(launch_assemble(as, c->stream));
+    return finish_setup(c, t0, [&](int64_t i) {
+        char b[48];
+        std::snprintf(b, sizeof b, "a = %.6g", ah[i]);
+        return std::string(b);
+    });
+}
+
+tsm_status tsm_set_jacobians(tsm_ctx* c, const double* Fcell, int64_t n_cell, const double* Fbnd, int64_t n_bnd) {
+    if (!c) return TSM_EINVAL;
+    if (!c->have_mesh) return c->fail(TSM_ESTATE, "set_reference_mesh first");
+    if (!Fcell || !Fbnd) return c->fail(TSM_EINVAL, "Jacobian table is NULL");
+    const int64_t n_inst = c->n_inst;
+    std::vector<int64_t> co(n_inst), bo(n_inst);
+    int64_t nc = 0, nb = 0;
+    for (int64_t i = 0; i < n_inst; ++i) {
+        const int64_t N = c->level_h[i];
+        co[i] = nc;
+        bo[i] = nb;
+        nc += 16 * N * N;
+        nb += 32 * N;
+    }
+    if (n_cell != nc || n_bnd != nb)
+        return c->fail(TSM_EINVAL, "Jacobian tables must hold 16 sum N_i^2 = " + std::to_string(nc) +
+                                       " and 32 sum N_i = " + std::to_string(nb) + " values");
+    const auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(hipDeviceSynchronize());   // caller's producers of the tables
+    c->have_geom = false;
+    c->have_state = false;
+    c->have_deriv = false;
+    c->drop_graph();
+    if (!c->cell_off) HIPALLOC(c->cell_off, n_inst);
+    if (!c->bnd_off) HIPALLOC(c->bnd_off, n_inst);
+    HIPCHK(hipMemcpy(c->cell_off, co.data(), n_inst * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->bnd_off, bo.data(), n_inst * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemsetAsync(c->amp, 0, n_inst * sizeof(double), c->stream));
+
+    AssembleArgs as{};
+    as.n_inst = (int)n_inst;
+    as.level = c->level;
+    as.offsets = c->offsets;
+    as.amp = c->amp;
+    as.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
+    as.d = c->prm.d;
+    as.kappa = c->prm.kappa;
+    as.inv_dt = 1.0 / c->prm.dt;
+    as.S64 = c->S64; as.S32 = c->S32; as.Slo = c->Slo; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
+    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ms32 = c->Ms32; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
+    as.Fcell = Fcell; as.Fbnd = Fbnd; as.cell_off = c->cell_off; as.bnd_off = c->bnd_off;
+    HIPCHK(launch_assemble_tables(as, c->stream));
+    c->geom_tables = true;
+    return finish_setup(c, t0, [](int64_t) { return std::string("Jacobian tables; -1: non-finite entry"); });
 }
 
 tsm_status tsm_set_state(tsm_ctx* c, const double* u, const double* v) {
@@ -828,6 +898,9 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
     if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
     if (n_steps < 1) return c->fail(TSM_EINVAL, "n_steps < 1");
     if (!J_out || !dJda_out) return c->fail(TSM_EINVAL, "J_out and dJda_out are required");
+    if (c->geom_tables)
+        return c->fail(TSM_ESTATE, "tsm_gradient differentiates with respect to the deformation amplitudes; "
+                                   "the geometry came from Jacobian tables");
     const int64_t ni = c->n_inst, tot = c->total;
     const int N = n_steps, K = c->prm.checkpoint_every;
     const int nseg = (N + K - 1) / K;

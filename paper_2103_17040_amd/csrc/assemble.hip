@@ -20,11 +20,16 @@ namespace tsm {
 
 namespace {
 
-// DERIV: assemble the amplitude derivatives dS/da, dM/da and db/da instead
-// (F = I + a G: dJ = G11 M22 + M11 G22 - G12 M21 - M12 G21,
-//  dC = d[adj(M) adj(M)^T]/da / J - C dJ / J,  d|M tau| = (M tau).(G tau) / |M tau|).
-template <bool DERIV>
+// MODE 0: the sinusoidal family from the amplitude a_i.
+// MODE 1: the amplitude derivatives dS/da, dM/da and db/da instead
+//   (F = I + a G: dJ = G11 M22 + M11 G22 - G12 M21 - M12 G21,
+//    dC = d[adj(M) adj(M)^T]/da / J - C dJ / J,  d|M tau| = (M tau).(G tau) / |M tau|).
+// MODE 2: a general map given by its Jacobian F at every quadrature point
+//   (the paper caches J and K K^T J per quadrature point; here the caller
+//   supplies F and the same formulas give J, C and |F tau|).
+template <int MODE>
 __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A) {
+    constexpr bool DERIV = MODE == 1, TAB = MODE == 2;
     __shared__ double red_s[2][1][kMicroThreads / kWave];
     __shared__ double mins[kMicroThreads / kWave];
     BlockReducer<kMicroThreads / kWave, 1, double> red(red_s);
@@ -43,6 +48,9 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
     const double* ss = A.tab.s + tb;
     const double* cs = A.tab.c + tb;
     const int tm = 2 * N, tp = 2 * N + 1;  // table entries at y = -1, y = +1
+    const double* Fc = TAB ? A.Fcell + A.cell_off[inst] : nullptr;
+    const double* Fb = TAB ? A.Fbnd + A.bnd_off[inst] : nullptr;
+    bool bad = false;                      // TAB: a non-finite Jacobian entry
 
     double len_part = 0.0;
     double jmin = 1e300;
@@ -65,7 +73,14 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     const int t2 = 2 * c2 + g2;
                     for (int g1 = 0; g1 < 2; ++g1) {
                         const int t1 = 2 * c1 + g1;
-                        Pull P = pullback_at(a, ys[t1], ys[t2], ss[t1], cs[t1], ss[t2], cs[t2]);
+                        Pull P;
+                        if constexpr (TAB) {
+                            const double* F = Fc + 4 * ((int64_t)(c2 * N + c1) * 4 + g2 * 2 + g1);
+                            P = pull_from(F[0], F[1], F[2], F[3]);
+                            bad |= !isfinite(P.J) || !isfinite(P.C11) || !isfinite(P.C12) || !isfinite(P.C22);
+                        } else {
+                            P = pullback_at(a, ys[t1], ys[t2], ss[t1], cs[t1], ss[t2], cs[t2]);
+                        }
                         jmin = fmin(jmin, P.J);
                         if constexpr (DERIV) P = pullback_da_at(a, ys[t1], ys[t2], ss[t1], cs[t1], ss[t2], cs[t2]);
                         // basis of local node (l1,l2) and its reference gradient
@@ -106,9 +121,17 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                 const int l1 = j1 - e;
                 for (int g = 0; g < 2; ++g) {
                     const int t1 = 2 * e + g;
-                    const double M11 = 1.0 + a * cs[t1] * yf;
-                    const double M21 = a * ss[tf];
+                    double M11, M21;
+                    if constexpr (TAB) {
+                        const double* F = Fb + 4 * ((int64_t)(side * N + e) * 2 + g);
+                        M11 = F[0];
+                        M21 = F[2];
+                    } else {
+                        M11 = 1.0 + a * cs[t1] * yf;
+                        M21 = a * ss[tf];
+                    }
                     double om = sqrt(M11 * M11 + M21 * M21);
+                    if constexpr (TAB) bad |= !isfinite(om);
                     if constexpr (DERIV) om = (M11 * cs[t1] * yf + M21 * ss[tf]) / om;
                     for (int m1 = 0; m1 < 2; ++m1) {
                         const double v = wb * om * lin(l1, g) * lin(m1, g);
@@ -129,9 +152,17 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                 const int l2 = j2 - e;
                 for (int g = 0; g < 2; ++g) {
                     const int t2 = 2 * e + g;
-                    const double M12 = a * ss[tf];
-                    const double M22 = 1.0 + a * cs[t2] * yf;
+                    double M12, M22;
+                    if constexpr (TAB) {
+                        const double* F = Fb + 4 * ((int64_t)((2 + side) * N + e) * 2 + g);
+                        M12 = F[1];
+                        M22 = F[3];
+                    } else {
+                        M12 = a * ss[tf];
+                        M22 = 1.0 + a * cs[t2] * yf;
+                    }
                     double om = sqrt(M12 * M12 + M22 * M22);
+                    if constexpr (TAB) bad |= !isfinite(om);
                     if constexpr (DERIV) om = (M12 * ss[tf] + M22 * cs[t2] * yf) / om;
                     for (int m2 = 0; m2 < 2; ++m2) {
                         const double v = wb * om * lin(l2, g) * lin(m2, g);
@@ -172,7 +203,7 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
     }
     double v[1] = {len_part};
     red.sum(v);
-    double m = jmin;
+    double m = bad ? -1.0 : jmin;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, kWave));
     if ((threadIdx.x & (kWave - 1)) == 0) mins[threadIdx.x / kWave] = m;
@@ -189,13 +220,21 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
 
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s) {
     if (a.n_inst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(assemble_kernel<false>, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
+    hipLaunchKernelGGL(assemble_kernel<0>, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_tables(const AssembleArgs& a, hipStream_t s) {
+    if (a.n_inst <= 0) return hipSuccess;
+    if (a.Fcell == nullptr || a.Fbnd == nullptr || a.cell_off == nullptr || a.bnd_off == nullptr)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(assemble_kernel<2>, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_assemble_da(const AssembleArgs& a, hipStream_t s) {
     if (a.n_inst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(assemble_kernel<true>, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
+    hipLaunchKernelGGL(assemble_kernel<1>, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -120,6 +120,18 @@ struct Pull {
     double J, C11, C12, C22;
 };
 
+// J = det M and C = adj(M) adj(M)^T / J (= K K^T J with K = M^{-1}) for a
+// Jacobian M; any rotation in front of M drops out of both.
+__device__ __forceinline__ Pull pull_from(double M11, double M12, double M21, double M22) {
+    Pull g;
+    g.J = M11 * M22 - M12 * M21;
+    const double iJ = 1.0 / g.J;
+    g.C11 = (M22 * M22 + M12 * M12) * iJ;
+    g.C12 = -(M22 * M21 + M12 * M11) * iJ;
+    g.C22 = (M21 * M21 + M11 * M11) * iJ;
+    return g;
+}
+
 __device__ __forceinline__ Pull pullback_at(double a, double y1, double y2,
                                             double s1, double c1, double s2, double c2) {
     const double M11 = 1.0 + a * c1 * y2;

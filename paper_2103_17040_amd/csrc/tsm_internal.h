@@ -72,7 +72,15 @@ struct AssembleArgs {
     float* Sslo;          // S - Ss32 rounded to FP32
     double* b;            // boundary load B 1 (ragged)
     double* len;          // [n_inst] 1^T b
-    double* jmin;         // [n_inst] minimum det over all quadrature points
+    double* jmin;         // [n_inst] minimum det over all quadrature points (-1: non-finite Jacobian)
+    // general maps (launch_assemble_tables): D zeta at the quadrature points,
+    // per instance at cell_off[i] (cells c2*N+c1, points g2*2+g1, 4 entries
+    // F11 F12 F21 F22) and bnd_off[i] (sides bottom, top, left, right; edges;
+    // 2 points; 4 entries)
+    const double* Fcell;
+    const double* Fbnd;
+    const int64_t* cell_off;
+    const int64_t* bnd_off;
 };
 
 // One batched micro solve: for every task t, instance i = order[t] solves
@@ -138,6 +146,8 @@ struct MacroArgs {
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s);
 // same gather with the amplitude derivatives: S64 <- dS/da, M64 <- dM/da, b <- db/da, len <- 1^T db
 hipError_t launch_assemble_da(const AssembleArgs& a, hipStream_t s);
+// same gather for maps given by their Jacobian tables (a.Fcell, a.Fbnd)
+hipError_t launch_assemble_tables(const AssembleArgs& a, hipStream_t s);
 hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_t lds_bytes, hipStream_t s);
 // packs of one mesh size (16, 32 or 64); mode 1 FP64, 2 refinement
 hipError_t launch_packed(const MicroArgs& a, const PackList& p, int level, int mode, int grid, hipStream_t s);

@@ -32,7 +32,7 @@ STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV
                 -4: "TSM_EHIP", -5: "TSM_ENOMEM", -6: "TSM_ESTATE"}
 
 EXPORTED = ["tsm_default_params", "tsm_create", "tsm_set_reference_mesh", "tsm_get_offsets",
-            "tsm_set_deformation", "tsm_set_state", "tsm_step", "tsm_get_macro", "tsm_get_fluxes",
+            "tsm_set_deformation", "tsm_set_jacobians", "tsm_set_state", "tsm_step", "tsm_get_macro", "tsm_get_fluxes",
             "tsm_get_micro", "tsm_get_setup", "tsm_apply_operator", "tsm_gradient", "tsm_set_flags", "tsm_autotune", "tsm_get_stats",
             "tsm_last_error", "tsm_destroy"]
 
@@ -78,6 +78,7 @@ def _load():
         "tsm_set_reference_mesh": (I32, [P, ctypes.POINTER(I32), I64]),
         "tsm_get_offsets": (I32, [P, ctypes.POINTER(I64)]),
         "tsm_set_deformation": (I32, [P, VP, VP, I64]),
+        "tsm_set_jacobians": (I32, [P, VP, I64, VP, I64]),
         "tsm_set_state": (I32, [P, VP, VP]),
         "tsm_step": (I32, [P, I32]),
         "tsm_get_macro": (I32, [P, VP]),
@@ -143,6 +144,10 @@ def tsm_get_offsets(ctx, n_inst: int) -> np.ndarray:
 
 def tsm_set_deformation(ctx, a, theta, n_inst: int) -> None:
     _check(ctx, _lib.tsm_set_deformation(ctx, _ptr(a), _ptr(theta), n_inst))
+
+
+def tsm_set_jacobians(ctx, Fcell, n_cell: int, Fbnd, n_bnd: int) -> None:
+    _check(ctx, _lib.tsm_set_jacobians(ctx, _ptr(Fcell), int(n_cell), _ptr(Fbnd), int(n_bnd)))
 
 
 def tsm_set_state(ctx, u, v) -> None:
