@@ -60,6 +60,25 @@ B_START, B_K, B_M32, B_END = 16.0, 40.0, 20.0, 16.0
 B_S64, B_DIAG, B_S32, B_SLO = 40.0, 8.0, 20.0, 20.0
 
 
+PACKED_LEVELS = (16, 32, 64)
+GENERIC_SLOTS = (1, 2, 3, 5, 9, 17)      # nodes per lane of the generic kernel (256 lanes)
+
+
+def micro_bytes_per_dof(N, plan, refine, iters, sweeps):
+    """Algorithmic HBM bytes per DoF-update of the micro kernel that solves an
+    N x N instance under the launch plan (packed kernels: symmetric planes as
+    above; generic kernel: full 9-coefficient rows, FP64 M for b, its stencil
+    held in registers when the instance fits, else streamed)."""
+    if plan != "generic" and N in PACKED_LEVELS:
+        if refine:
+            return B_START + B_K + B_M32 + B_S32 + B_SLO * max(sweeps - 1, 0) + B_END
+        return B_START + B_K + B_M32 + B_DIAG + B_S64 * iters + B_END
+    slots = next(s for s in GENERIC_SLOTS if s * 256 >= (N + 1) ** 2)
+    if refine:   # FP32 stencil once (resident) or per inner iteration; FP64 rows per residual
+        return 16 + 72 + 72 * sweeps + (36 if slots <= 9 else 36 * iters) + 16
+    return 16 + 72 + 72 + (0 if slots <= 5 else 72 * iters) + 16
+
+
 def streaming_bytes(refine, iters, sweeps):
     """Bytes per DoF-update of a PCG that streams its vectors through HBM
     every iteration (10 words per iteration for a two-pass fused PCG, the FP64
@@ -300,10 +319,10 @@ def main():
     sweeps = st["sweeps_mean"] if refine else 0
     dofs_per_launch = n_dofs / max(tst["micro_launches"], 1)
     flops = dofs_per_launch * (FLOP_ITER * iters + FLOP_SWEEP * sweeps + FLOP_SOLVE)
-    if refine:
-        nbytes = dofs_per_launch * (B_START + B_K + B_M32 + B_S32 + B_SLO * max(sweeps - 1, 0) + B_END)
-    else:
-        nbytes = dofs_per_launch * (B_START + B_K + B_M32 + B_DIAG + B_S64 * iters + B_END)
+    plan_name = main_form["plan"]["plan"]
+    step_bytes = sum((N + 1) ** 2 * micro_bytes_per_dof(int(N), plan_name, refine, iters, sweeps)
+                     for N in lv.tolist())
+    nbytes = step_bytes / max(tst["micro_launches"], 1)
     t_launch = micro_ms_per_launch * 1e-3
     alu = flops / t_launch / 1e12
     hbm = nbytes / t_launch / 1e9

@@ -325,6 +325,55 @@ __device__ __forceinline__ void strip_apply(const ST& S0, const TG* g, const Lan
     }
 }
 
+// As strip_apply, but the neighbour columns are read from LDS row by row (six
+// reads per row instead of 2R+4 values held through the whole apply), which
+// leaves registers for a larger batch of streamed coefficients: fewer
+// dependent memory round trips in the start and residual phases.
+template <class L, int B, typename TA, typename TG, class ST>
+__device__ __forceinline__ void strip_apply_lean(const ST& S0, const TG* g, const Lane& z,
+                                                 const TG (&mine)[L::R], TA (&y)[L::R]) {
+    ST S = S0;
+    if constexpr (ST::kGlobal) S.base = opaque(S.base);
+    constexpr int W2 = L::W2;
+    const int base = (z.r0 + 1) * W2 + (z.col + 1);
+    typename ST::raw_t carry7 = typename ST::raw_t(0);
+#pragma unroll
+    for (int i0 = 0; i0 < L::R; i0 += B) {
+        typename ST::raw_t c[B][kStencil];
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int k = 0; k < kStencil; ++k) {
+                if (i0 + b >= L::R) continue;
+                if (k == 1 && i0 + b > 0) c[b][1] = (b > 0) ? c[b - 1][7] : carry7;
+                else c[b][k] = S.load(z, i0 + b, k);
+            }
+        if constexpr (ST::kGlobal) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = i0 + b;
+            if (i >= L::R) break;
+            const int rb = base + (i - 1) * W2;
+            const TG l0 = g[rb - 1], l1 = g[rb + W2 - 1], l2 = g[rb + 2 * W2 - 1];
+            const TG q0 = g[rb + 1], q1 = g[rb + W2 + 1], q2 = g[rb + 2 * W2 + 1];
+            const TG cm = (i == 0) ? g[base - W2] : mine[i - 1];
+            const TG cp = (i == L::R - 1) ? g[base + L::R * W2] : mine[i + 1];
+            TA t = TA(S.value(i, 0, c[b][0])) * TA(l0);
+            t += TA(S.value(i, 1, c[b][1])) * TA(cm);
+            t += TA(S.value(i, 2, c[b][2])) * TA(q0);
+            t += TA(S.value(i, 3, c[b][3])) * TA(l1);
+            t += TA(S.value(i, 4, c[b][4])) * TA(mine[i]);
+            t += TA(S.value(i, 5, c[b][5])) * TA(q1);
+            t += TA(S.value(i, 6, c[b][6])) * TA(l2);
+            t += TA(S.value(i, 7, c[b][7])) * TA(cp);
+            t += TA(S.value(i, 8, c[b][8])) * TA(q2);
+            y[i] = (z.r0 + i < L::NP) ? t : TA(0);
+            carry7 = c[b][7];
+        }
+        if constexpr (ST::kGlobal) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 template <class L>
 __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, const double (&x)[L::R],
                                            int iters, int sweeps, bool conv, double rr, PackRed<1, double>& red1) {
@@ -383,7 +432,7 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
             for (int i = 0; i < L::R; ++i)
                 if (row_ok<L>(z, i)) b[i] += bc * A.b[z.off + node_of<L>(z, i)];
         }
-        if (z.act) strip_apply<L, 3>(SymStencil<L, double>{A.Ss64 + kSym * z.off}, xg, z, x, sx);
+        if (z.act) strip_apply_lean<L, L::R>(SymStencil<L, double>{A.Ss64 + kSym * z.off}, xg, z, x, sx);
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
             r[i] = b[i] - sx[i];
@@ -391,8 +440,8 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
         }
     } else {
         if (z.act) {
-            strip_apply<L, 3>(SymStencil<L, double>{A.Ks64 + kSym * z.off}, xg, z, x, sx);
-            strip_apply<L, 5>(SymStencil<L, float>{A.Ms32 + kSym * z.off}, xg, z, x, b);
+            strip_apply_lean<L, L::R>(SymStencil<L, double>{A.Ks64 + kSym * z.off}, xg, z, x, sx);
+            strip_apply_lean<L, L::R>(SymStencil<L, float>{A.Ms32 + kSym * z.off}, xg, z, x, b);
         }
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
@@ -592,7 +641,7 @@ __device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds,
         double sd[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) sd[i] = 0.0;
-        if (z.act) strip_apply<L, 3>(S64, pg, z, d, sd);
+        if (z.act) strip_apply_lean<L, L::R>(S64, pg, z, d, sd);
         double a1[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
