@@ -61,6 +61,8 @@ struct tsm_ctx {
     int n_packs = 0;                  // packed kernels: one launch per mesh size
     std::vector<std::array<int, 3>> pack_groups;   // (level, first pack, pack count)
     int32_t *pk_first = nullptr, *pk_count = nullptr, *pk_level = nullptr, *queue = nullptr;
+    int32_t* pk_slot_inst = nullptr;
+    int64_t* pk_slot_off = nullptr;
     size_t pack_lds_max = 0;
     int n_cu = 0;
 
@@ -118,7 +120,7 @@ struct tsm_ctx {
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32); dfree(Slo);
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
-        dfree(pk_first); dfree(pk_count); dfree(pk_level);
+        dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
         dfree(dS64); dfree(dM64); dfree(db); dfree(dlen); dfree(jmin_d);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
         have_deriv = false;
@@ -173,7 +175,7 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
     if ((c->prm.flags & TSM_FLAG_PERSISTENT) && c->n_packs > 0) {
         // one persistent launch over every pack; the queue is reset by a
         // kernel so the sequence can be captured in a graph
-        PackList pl{c->n_packs, c->pk_first, c->pk_count};
+        PackList pl{c->n_packs, c->pk_first, c->pk_count, c->pk_slot_inst, c->pk_slot_off};
         MicroArgs a = base;
         a.n_tasks = (int)c->n_inst;
         a.order = c->order;
@@ -187,7 +189,8 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
             HIPCHK(launch_packed_mixed(a, pl, c->pk_level, refine ? 2 : 1, grid, c->pack_lds_max, c->stream));
     } else {
         for (const auto& pg : c->pack_groups) {
-            PackList pl{pg[2], c->pk_first + pg[1], c->pk_count + pg[1]};
+            PackList pl{pg[2], c->pk_first + pg[1], c->pk_count + pg[1], c->pk_slot_inst + (int64_t)pg[1] * kPackSlots,
+                        c->pk_slot_off + (int64_t)pg[1] * kPackSlots};
             MicroArgs a = base;
             a.n_tasks = (int)c->n_inst;
             a.order = c->order;
@@ -260,9 +263,21 @@ tsm_status plan_tasks(tsm_ctx* c) {
         }
         c->groups.back().count++;
     }
-    dfree(c->pk_first); dfree(c->pk_count); dfree(c->pk_level);
+    dfree(c->pk_first); dfree(c->pk_count); dfree(c->pk_level); dfree(c->pk_slot_inst); dfree(c->pk_slot_off);
     if (c->n_packs > 0) {
         HIPALLOC(c->pk_first, c->n_packs); HIPALLOC(c->pk_count, c->n_packs); HIPALLOC(c->pk_level, c->n_packs);
+        const int64_t ns = (int64_t)c->n_packs * kPackSlots;
+        std::vector<int32_t> si(ns, 0);
+        std::vector<int64_t> so(ns, 0);
+        for (int k = 0; k < c->n_packs; ++k)
+            for (int q = 0; q < pc[k]; ++q) {
+                const int32_t inst = c->order_h[pf[k] + q];
+                si[(int64_t)k * kPackSlots + q] = inst;
+                so[(int64_t)k * kPackSlots + q] = c->off_h[inst];
+            }
+        HIPALLOC(c->pk_slot_inst, ns); HIPALLOC(c->pk_slot_off, ns);
+        HIPCHK(hipMemcpy(c->pk_slot_inst, si.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->pk_slot_off, so.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(c->pk_level, pv.data(), pv.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(c->pk_first, pf.data(), pf.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(c->pk_count, pc.data(), pc.size() * sizeof(int32_t), hipMemcpyHostToDevice));

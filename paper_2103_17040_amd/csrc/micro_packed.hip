@@ -59,6 +59,7 @@ struct Lvl {
     static_assert(NS * NP <= TPI, "strips do not fit the lanes of an instance");
     static_assert(TPI % kWave == 0, "an instance owns whole waves");
     static_assert(IPP * WPI <= NWP && WPI <= G, "instances must fit one 16-lane DPP row");
+    static_assert(IPP <= kPackSlots, "pack slots");
 };
 using L16 = Lvl<16, 64, 6>;
 using L32 = Lvl<32, 256, 5>;
@@ -125,17 +126,17 @@ struct Lane {
 };
 
 template <class L>
-__device__ __forceinline__ Lane lane_of(const MicroArgs& A, int first, int cnt) {
+__device__ __forceinline__ Lane lane_of(const PackList& P, int task, int cnt) {
     Lane z;
     z.sub = threadIdx.x / L::TPI;
     z.lt = threadIdx.x - z.sub * L::TPI;
     z.w0 = (z.sub < L::IPP ? z.sub : 0) * L::WPI;
     z.live = z.sub < L::IPP && z.sub < cnt;
-    // every wave belongs to one instance: instance and offset are wave-uniform;
-    // the offset comes from the task's own slot, not through the instance
-    const int t = first + (z.live ? z.sub : 0);
-    int inst = z.live ? A.order[t] : 0;
-    const int64_t off = z.live ? A.order_off[t] : 0;
+    // every wave belongs to one instance: instance and offset are wave-uniform
+    // and come from the pack's slot directly
+    const int t = task * kPackSlots + (z.live ? z.sub : 0);
+    int inst = z.live ? P.slot_inst[t] : 0;
+    const int64_t off = z.live ? P.slot_off[t] : 0;
     inst = __builtin_amdgcn_readfirstlane(inst);
     z.inst = inst;
     z.col = z.lt % L::NP;
@@ -454,9 +455,9 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
 
 // ------------------------------------------------------------------ FP64
 template <class L>
-__device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, PackRed<1, double>& red1,
+__device__ void pack_fp64(const MicroArgs& A, const PackList& P, int task, int cnt, double* lds, PackRed<1, double>& red1,
                           PackRed<3, double>& red3) {
-    const Lane z = lane_of<L>(A, first, cnt);
+    const Lane z = lane_of<L>(P, task, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     const SymStencil<L, double> S{A.Ss64 + kSym * z.off};
     double x[L::R], r[L::R], p[L::R];
@@ -524,9 +525,9 @@ __device__ void pack_fp64(const MicroArgs& A, int first, int cnt, double* lds, P
 
 // --------------------------------------------------------------- REFINE
 template <class L>
-__device__ void pack_refine(const MicroArgs& A, int first, int cnt, double* lds, PackRed<1, double>& red1,
+__device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int cnt, double* lds, PackRed<1, double>& red1,
                             PackRed<3, double>& red3, PackRed<2, float>& rf2) {
-    const Lane z = lane_of<L>(A, first, cnt);
+    const Lane z = lane_of<L>(P, task, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     float* pg = reinterpret_cast<float*>(xg);
     double x[L::R], r64[L::R];
@@ -682,9 +683,9 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
             __syncthreads();
         }
         if (task >= P.n_packs) break;
-        const int first = P.first[task], cnt = P.count[task];
-        if constexpr (MODE == 2) pack_refine<L>(A, first, cnt, lds, red1, red3, rf2);
-        else pack_fp64<L>(A, first, cnt, lds, red1, red3);
+        const int cnt = P.count[task];
+        if constexpr (MODE == 2) pack_refine<L>(A, P, task, cnt, lds, red1, red3, rf2);
+        else pack_fp64<L>(A, P, task, cnt, lds, red1, red3);
         if (A.queue == nullptr) break;
         __syncthreads();
     }
@@ -706,15 +707,15 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
         const int task = sh.task;
         __syncthreads();
         if (task >= P.n_packs) break;
-        const int lvl = pack_level[task], first = P.first[task], cnt = P.count[task];
+        const int lvl = pack_level[task], cnt = P.count[task];
         if constexpr (MODE == 2) {
-            if (lvl == 64) pack_refine<L64>(A, first, cnt, lds, red1, red3, rf2);
-            else if (lvl == 32) pack_refine<L32>(A, first, cnt, lds, red1, red3, rf2);
-            else pack_refine<L16>(A, first, cnt, lds, red1, red3, rf2);
+            if (lvl == 64) pack_refine<L64>(A, P, task, cnt, lds, red1, red3, rf2);
+            else if (lvl == 32) pack_refine<L32>(A, P, task, cnt, lds, red1, red3, rf2);
+            else pack_refine<L16>(A, P, task, cnt, lds, red1, red3, rf2);
         } else {
-            if (lvl == 64) pack_fp64<L64>(A, first, cnt, lds, red1, red3);
-            else if (lvl == 32) pack_fp64<L32>(A, first, cnt, lds, red1, red3);
-            else pack_fp64<L16>(A, first, cnt, lds, red1, red3);
+            if (lvl == 64) pack_fp64<L64>(A, P, task, cnt, lds, red1, red3);
+            else if (lvl == 32) pack_fp64<L32>(A, P, task, cnt, lds, red1, red3);
+            else pack_fp64<L16>(A, P, task, cnt, lds, red1, red3);
         }
         __syncthreads();
     }

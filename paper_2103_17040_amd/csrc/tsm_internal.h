@@ -125,10 +125,16 @@ struct MicroArgs {
 };
 
 // Packs of instances of one mesh size solved by one 1024-lane workgroup.
+constexpr int kPackSlots = 16;             // slot stride of a pack (the most instances a pack holds)
+
 struct PackList {
     int n_packs;
     const int32_t* first;   // first task (index into MicroArgs::order)
     const int32_t* count;   // instances in the pack
+    // per pack slot (pack * kPackSlots + sub): the instance and its offset,
+    // so a workgroup finds its instances in one dependent load
+    const int32_t* slot_inst;
+    const int64_t* slot_off;
 };
 
 struct MacroArgs {
