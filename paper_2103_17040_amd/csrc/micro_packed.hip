@@ -403,7 +403,10 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
 //   time step:              b = M x0 / dt,      r = b - S x0 = -K x0
 // (K = S - M/dt is stored on its own, so the residual carries no
 // cancellation; M, in FP32, only sizes ||b||).
-template <class L>
+// NORM_LATER: the time-step form leaves ||b||^2 to the caller (bb = 0), which
+// forms b = M x0/dt = S x0 + r from its register stencil instead of reading
+// M (the refinement solve; x0 stays in the double grid).
+template <class L, bool NORM_LATER = false>
 __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, double* xg, double (&x)[L::R],
                                            double (&r)[L::R], double& bb) {
     zero_halo<L, double>(xg, z);
@@ -442,13 +445,14 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
     } else {
         if (z.act) {
             strip_apply_lean<L, L::R>(SymStencil<L, double>{A.Ks64 + kSym * z.off}, xg, z, x, sx);
-            strip_apply_lean<L, L::R>(SymStencil<L, float>{A.Ms32 + kSym * z.off}, xg, z, x, b);
+            if constexpr (!NORM_LATER)
+                strip_apply_lean<L, L::R>(SymStencil<L, float>{A.Ms32 + kSym * z.off}, xg, z, x, b);
         }
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
             r[i] = -sx[i];
             const double bi = b[i] * A.inv_dt;
-            bb += bi * bi;
+            if constexpr (!NORM_LATER) bb += bi * bi;
         }
     }
 }
@@ -532,7 +536,7 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
     float* pg = reinterpret_cast<float*>(xg);
     double x[L::R], r64[L::R];
     double bb;
-    pack_start<L>(A, z, xg, x, r64, bb);
+    pack_start<L, true>(A, z, xg, x, r64, bb);
     float S[L::R][kStencil], dinv[L::R];
     {
         // branch-free: every row's loads in flight at once (rows past the
@@ -550,6 +554,19 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
     }
     const RegStencil<L, float> SR{S};
     const SplitStencil<L> S64{S, A.Sslo + kSym * z.off};
+    if (A.rhs_vec == nullptr) {
+        // ||b|| of the time step from b = S x0 + r (S in FP32: the norm only
+        // sizes the tolerance, ~1e-7 relative is plenty); x0 is in the grid
+        double sb[L::R];
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) sb[i] = 0.0;
+        if (z.act) strip_apply<L, L::R>(SR, xg, z, x, sb);
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) {
+            const double bi = sb[i] + r64[i];
+            bb += row_ok<L>(z, i) ? bi * bi : 0.0;
+        }
+    }
     double acc[3] = {bb, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < L::R; ++i) acc[2] += r64[i] * r64[i];
