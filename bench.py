@@ -45,17 +45,18 @@ PEAK_ALU_TFLOPS = 78.6
 # residual update of the refinement S d with S = S32 + Slo (9 ADD + 9 FMA),
 # r -= ||r|| S d, r.r, x += ||r|| d = 33 flops; per solve x0 = X0 + u w,
 # K x0, M x0 (9 FMA each), ||b||^2 and ||r||^2 = 43 flops.
-FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 33.0, 43.0
+FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 33.0, 43.0   # (refine: S x0 replaces M x0 in the solve term)
 # Bytes the instance-resident micro kernel must move per DoF per step
 # (algorithmic: the vectors of the iterations stay on chip; operators are read
 # from their symmetric upper-half planes, 5 coefficients per node):
 #   both forms: x0 = v0 + u w (read v0, w: 16), r = -K x0 (FP64 K, 40),
-#               ||b|| = ||M x0||/dt (FP32 M, 20), write x and read b for the
-#               flux average (16)
-#   refine:     the FP32 stencil once (20) and, per residual update after an
-#               inner solve, the FP32 low part of the stencil (20)
-#   FP64:       the FP64 stencil once per PCG iteration (40) and its centre
-#               plane once for diag^{-1} (8)
+#               write x and read b for the flux average (16)
+#   refine:     the FP32 stencil once (20; it also gives ||b|| = ||S x0 + r||)
+#               and the FP32 low part of the stencil for the residual update
+#               after the first inner solve (20); later updates are within
+#               2^12 of the tolerance and use the FP32 stencil alone
+#   FP64:       ||b|| = ||M x0||/dt (FP32 M, 20), the FP64 stencil once per
+#               PCG iteration (40) and its centre plane once for diag^{-1} (8)
 B_START, B_K, B_M32, B_END = 16.0, 40.0, 20.0, 16.0
 B_S64, B_DIAG, B_S32, B_SLO = 40.0, 8.0, 20.0, 20.0
 
@@ -71,7 +72,7 @@ def micro_bytes_per_dof(N, plan, refine, iters, sweeps):
     held in registers when the instance fits, else streamed)."""
     if plan != "generic" and N in PACKED_LEVELS:
         if refine:
-            return B_START + B_K + B_M32 + B_S32 + B_SLO * max(sweeps - 1, 0) + B_END
+            return B_START + B_K + B_S32 + B_SLO * min(max(sweeps - 1, 0), 1) + B_END
         return B_START + B_K + B_M32 + B_DIAG + B_S64 * iters + B_END
     slots = next(s for s in GENERIC_SLOTS if s * 256 >= (N + 1) ** 2)
     if refine:   # FP32 stencil once (resident) or per inner iteration; FP64 rows per residual

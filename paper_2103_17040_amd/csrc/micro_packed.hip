@@ -659,7 +659,15 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
         double sd[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) sd[i] = 0.0;
-        if (z.act) strip_apply_lean<L, L::R>(S64, pg, z, d, sd);
+        // Once the residual is within 2^12 of the tolerance, the FP32 stencil
+        // alone is exact enough for the update: its rounding error is about
+        // 2^-24 of the update (which is about the residual), i.e. below 2^-12
+        // of the tolerance, and the low part need not be read.
+        const bool lo = rr > 16777216.0 * tol2;
+        if (z.act) {
+            if (lo) strip_apply_lean<L, L::R>(S64, pg, z, d, sd);
+            else strip_apply<L, L::R>(SR, pg, z, d, sd);
+        }
         double a1[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
