@@ -460,7 +460,7 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
 // ------------------------------------------------------------------ FP64
 template <class L>
 __device__ void pack_fp64(const MicroArgs& A, const PackList& P, int task, int cnt, double* lds, PackRed<1, double>& red1,
-                          PackRed<3, double>& red3) {
+                          PackRed<2, double>& red2, PackRed<3, double>& red3) {
     const Lane z = lane_of<L>(P, task, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     const SymStencil<L, double> S{A.Ss64 + kSym * z.off};
@@ -500,29 +500,29 @@ __device__ void pack_fp64(const MicroArgs& A, const PackList& P, int task, int c
         for (int i = 0; i < L::R; ++i) pq[0] += p[i] * q[i];
         red1.sum<L>(pq, z.w0);
         const double alpha = me ? rz / pq[0] : 0.0;
-        double a3[3] = {0.0, 0.0, 0.0};
+        double a2[2] = {0.0, 0.0};     // (r, D^-1 r), (r, r)
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
             x[i] += alpha * p[i];
             r[i] -= alpha * q[i];
-            a3[1] += r[i] * (double)dinv[i] * r[i];
-            a3[2] += r[i] * r[i];
+            a2[0] += r[i] * (double)dinv[i] * r[i];
+            a2[1] += r[i] * r[i];
         }
-        red3.sum<L>(a3, z.w0);
-        rr = a3[2];
+        red2.sum<L>(a2, z.w0);
+        rr = a2[1];
         ++k;
         if (me) {
             ++it;
-            if (a3[2] <= tol2) {
+            if (a2[1] <= tol2) {
                 conv = true;
             } else {
-                const double beta = a3[1] / rz;
-                rz = a3[1];
+                const double beta = a2[0] / rz;
+                rz = a2[0];
 #pragma unroll
                 for (int i = 0; i < L::R; ++i) p[i] = (double)dinv[i] * r[i] + beta * p[i];
             }
         }
-        go = red3.any_above(thr);
+        go = red2.any_above(thr);
     }
     pack_store<L>(A, z, x, it, 1, conv, rr, red1);
 }
@@ -581,7 +581,8 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
     zero_halo<L, float>(pg, z);     // the float view of the grid from here on
     __syncthreads();
     const double othr = lane_threshold<L>(otol_s, cnt);
-    while (red3.any_above(othr) && sweeps <= A.max_refine) {
+    bool ogo = red3.any_above(othr);
+    while (ogo && sweeps <= A.max_refine) {
         // Inner FP32 solve of S d = r / ||r|| by the Chronopoulos-Gear form of
         // PCG: s = S p is carried by a recurrence, so each iteration needs one
         // operator application (w = S u, u = D^{-1} r) and ONE fused reduction
@@ -668,15 +669,16 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
             if (lo) strip_apply_lean<L, L::R>(S64, pg, z, d, sd);
             else strip_apply<L, L::R>(SR, pg, z, d, sd);
         }
-        double a1[3] = {0.0, 0.0, 0.0};
+        double a1[1] = {0.0};
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
             r64[i] -= sc * sd[i];
-            a1[2] += r64[i] * r64[i];
+            a1[0] += r64[i] * r64[i];
         }
-        red3.sum<L>(a1, z.w0);
+        red1.sum<L>(a1, z.w0);
+        ogo = red1.any_above(othr);
         ++sweeps;
-        rr = a1[2];
+        rr = a1[0];
         if (!conv && rr <= tol2) conv = true;
     }
     pack_store<L>(A, z, x, iters, sweeps, conv, rr, red1);
@@ -685,6 +687,7 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
 // Reduction buffers of one packed workgroup.
 struct PackShared {
     double r1[2][NWP][4];
+    double r2[2][NWP][4];
     double r3[2][NWP][4];
     float f3[2][NWP][4];
     int task;
@@ -697,6 +700,7 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
     extern __shared__ double lds[];
     __shared__ PackShared sh;
     PackRed<1, double> red1(sh.r1);
+    PackRed<2, double> red2(sh.r2);
     PackRed<3, double> red3(sh.r3);
     PackRed<2, float> rf2(sh.f3);
     int task = blockIdx.x;
@@ -710,7 +714,7 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
         if (task >= P.n_packs) break;
         const int cnt = P.count[task];
         if constexpr (MODE == 2) pack_refine<L>(A, P, task, cnt, lds, red1, red3, rf2);
-        else pack_fp64<L>(A, P, task, cnt, lds, red1, red3);
+        else pack_fp64<L>(A, P, task, cnt, lds, red1, red2, red3);
         if (A.queue == nullptr) break;
         __syncthreads();
     }
@@ -724,6 +728,7 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
     extern __shared__ double lds[];
     __shared__ PackShared sh;
     PackRed<1, double> red1(sh.r1);
+    PackRed<2, double> red2(sh.r2);
     PackRed<3, double> red3(sh.r3);
     PackRed<2, float> rf2(sh.f3);
     for (;;) {
@@ -738,9 +743,9 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
             else if (lvl == 32) pack_refine<L32>(A, P, task, cnt, lds, red1, red3, rf2);
             else pack_refine<L16>(A, P, task, cnt, lds, red1, red3, rf2);
         } else {
-            if (lvl == 64) pack_fp64<L64>(A, P, task, cnt, lds, red1, red3);
-            else if (lvl == 32) pack_fp64<L32>(A, P, task, cnt, lds, red1, red3);
-            else pack_fp64<L16>(A, P, task, cnt, lds, red1, red3);
+            if (lvl == 64) pack_fp64<L64>(A, P, task, cnt, lds, red1, red2, red3);
+            else if (lvl == 32) pack_fp64<L32>(A, P, task, cnt, lds, red1, red2, red3);
+            else pack_fp64<L16>(A, P, task, cnt, lds, red1, red2, red3);
         }
         __syncthreads();
     }
