@@ -66,12 +66,18 @@ PACKED_LEVELS = (16, 32, 64)
 GENERIC_SLOTS = (1, 2, 3, 5, 9, 17)      # nodes per lane of the generic kernel (256 lanes)
 
 
-def micro_bytes_per_dof(N, plan, refine, iters, sweeps):
+def packed_under(N, flags):
+    """Whether the launch plan `flags` solves N x N instances with a packed kernel."""
+    per_size = {16: 1 << 6, 32: 1 << 7, 64: 1 << 8}
+    return N in PACKED_LEVELS and not (flags & (1 << 3)) and not (flags & per_size[N])
+
+
+def micro_bytes_per_dof(N, flags, refine, iters, sweeps):
     """Algorithmic HBM bytes per DoF-update of the micro kernel that solves an
-    N x N instance under the launch plan (packed kernels: symmetric planes as
-    above; generic kernel: full 9-coefficient rows, FP64 M for b, its stencil
-    held in registers when the instance fits, else streamed)."""
-    if plan != "generic" and N in PACKED_LEVELS:
+    N x N instance under the launch plan `flags` (packed kernels: symmetric
+    planes as above; generic kernel: full 9-coefficient rows, FP64 M for b,
+    its stencil held in registers when the instance fits, else streamed)."""
+    if packed_under(N, flags):
         if refine:
             return B_START + B_K + B_S32 + B_SLO * min(max(sweeps - 1, 0), 1) + B_END
         return B_START + B_K + B_M32 + B_DIAG + B_S64 * iters + B_END
@@ -123,7 +129,8 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-PLAN_FLAGS = {"per_size": 0, "persistent": 1 << 4, "generic": 1 << 3}
+PLAN_FLAGS = {"per_size": 0, "persistent": 1 << 4, "generic": 1 << 3,
+              "persistent+generic16": (1 << 4) | (1 << 6)}
 
 
 def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan="auto", fp_steps=0):
@@ -186,8 +193,7 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan
             adj = {"steps": adjoint_steps, "checkpoint_every": max(w.checkpoint_every, 1),
                    "J": J, "grad_norm": float(dJ.norm()), "wall_s": tg,
                    "forward_ms": gs["grad_forward_ms"], "backward_ms": gs["grad_backward_ms"]}
-        names = {0: "per_size", tsm.TSM_FLAG_PERSISTENT: "persistent", tsm.TSM_FLAG_GENERIC: "generic"}
-        plan = {"plan": names.get(plan["flags"], str(plan["flags"])), "ms_per_step": plan["ms_per_step"]}
+        plan = {"plan": tsm.plan_name(plan["flags"]), "flags": plan["flags"], "ms_per_step": plan["ms_per_step"]}
         return {"t": t, "setup_ms": setup_ms, "stats": st, "timing": tst, "n_dofs": g.n_micro, "adjoint": adj,
                 "plan": plan, "fixed_point": fp}
     finally:
@@ -381,19 +387,23 @@ def main():
     sweeps = st["sweeps_mean"] if refine else 0
     dofs_per_launch = n_dofs / max(tst["micro_launches"], 1)
     flops = dofs_per_launch * (FLOP_ITER * iters + FLOP_SWEEP * sweeps + FLOP_SOLVE)
-    plan_name = main_form["plan"]["plan"]
-    step_bytes = sum((N + 1) ** 2 * micro_bytes_per_dof(int(N), plan_name, refine, iters, sweeps)
+    plan_flags = main_form["plan"]["flags"]
+    step_bytes = sum((N + 1) ** 2 * micro_bytes_per_dof(int(N), plan_flags, refine, iters, sweeps)
                      for N in lv.tolist())
     nbytes = step_bytes / max(tst["micro_launches"], 1)
     t_launch = micro_ms_per_launch * 1e-3
     alu = flops / t_launch / 1e12
     hbm = nbytes / t_launch / 1e9
     traffic = measured_traffic(w.name, w.precision)
-    n_sizes = len(set(lv.tolist()))
-    kname = {"per_size": "packed_kernel (micro PCG)",
-             "persistent": "packed_kernel, persistent (micro PCG)" if n_sizes == 1
-             else "packed_mixed_kernel (micro PCG)",
-             "generic": "micro_kernel (micro PCG)"}[main_form["plan"]["plan"]]
+    n_packed = len({N for N in lv.tolist() if packed_under(int(N), plan_flags)})
+    if n_packed == 0:
+        kname = "micro_kernel (micro PCG)"
+    elif plan_flags & (1 << 4):
+        kname = ("packed_kernel, persistent" if n_packed == 1 else "packed_mixed_kernel") + " (micro PCG)"
+    else:
+        kname = "packed_kernel (micro PCG)"
+    if 0 < n_packed and any(not packed_under(int(N), plan_flags) for N in set(lv.tolist())):
+        kname += " + micro_kernel"
     # achieved: the algorithmic bytes of one DoF-update as the survey's
     # measurement plan counts them (a PCG that streams its vectors through
     # HBM every iteration) times the DoF-updates of one launch, over the

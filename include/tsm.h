@@ -66,6 +66,9 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
 #define TSM_FLAG_STENCIL_STREAM (1ull << 1) /* force the streamed-stencil micro kernels */
 #define TSM_FLAG_GENERIC    (1ull << 3)  /* solve every mesh size with the one-instance-per-workgroup
                                             kernels (no packed kernels for 16/32/64 cells) */
+#define TSM_FLAG_GENERIC_16 (1ull << 6)  /* ... only the 16-cell meshes (likewise 32, 64): the */
+#define TSM_FLAG_GENERIC_32 (1ull << 7)  /* best kernel differs per mesh size and precision    */
+#define TSM_FLAG_GENERIC_64 (1ull << 8)
 #define TSM_FLAG_PERSISTENT (1ull << 4)  /* all packed mesh sizes in ONE persistent launch (one
                                             workgroup per compute unit) with a work queue
                                             (largest meshes first), instead of one launch per
@@ -220,11 +223,14 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags);
 
 /* Autotuner: time the launch plans {one launch per mesh size, one persistent
  * launch for all sizes, the one-instance-per-workgroup kernels} for
- * `steps` steps each (after one warm-up step) from the current state,
- * restore the state after each, and keep the fastest plan.  The timings
- * (ms per step, -1 where a plan does not apply) go to ms_out[3] (host,
- * may be NULL) and the chosen TSM_FLAG_* bits to *flags_out (host, may be
- * NULL).  Needs set_state first. */
+ * `steps` steps each (after one warm-up step) from the current state, then,
+ * from the faster packed plan, move one packed mesh size at a time to the
+ * one-instance-per-workgroup kernel (TSM_FLAG_GENERIC_16/32/64) while that
+ * is faster; restore the state after every trial and keep the fastest plan.
+ * ms_out[4] (host, may be NULL): ms per step of the per-size, persistent and
+ * generic plans (-1 where a plan does not apply) and of the chosen plan;
+ * *flags_out (host, may be NULL): the chosen TSM_FLAG_* plan bits.  Needs
+ * set_state first. */
 tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* flags_out);
 
 tsm_status tsm_get_stats(const tsm_ctx* c, tsm_stats* s);

@@ -133,12 +133,12 @@ class TwoScaleBatch:
                 with open(cache) as fh:
                     rec = json.load(fh)
                 if key in rec:
-                    plan_bits = tsm.TSM_FLAG_PERSISTENT | tsm.TSM_FLAG_GENERIC
-                    self.set_flags((self._flags & ~plan_bits) | int(rec[key]["flags"]))
+                    self.set_flags((self._flags & ~tsm.PLAN_BITS) | int(rec[key]["flags"]))
                     return rec[key]
         ms, flags = tsm.tsm_autotune(self.ctx, steps)
-        self._flags = (self._flags & ~(tsm.TSM_FLAG_PERSISTENT | tsm.TSM_FLAG_GENERIC | tsm.TSM_FLAG_TIMING)) | flags
-        res = {"flags": flags, "ms_per_step": {"per_size": ms[0], "persistent": ms[1], "generic": ms[2]}}
+        self._flags = (self._flags & ~tsm.PLAN_BITS) | flags
+        res = {"flags": flags, "plan": tsm.plan_name(flags),
+               "ms_per_step": {"per_size": ms[0], "persistent": ms[1], "generic": ms[2], "chosen": ms[3]}}
         if cache is not None:
             rec = {}
             if os.path.exists(cache):

@@ -215,8 +215,16 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
 // Task order, packs and generic groups for the current mesh and flags.
 tsm_status plan_tasks(tsm_ctx* c) {
     const int64_t n_inst = c->n_inst;
-    const bool use_packs = !(c->prm.flags & TSM_FLAG_GENERIC);
-    auto packable = [&](int32_t i) { return use_packs && packed_capacity(c->level_h[i]) > 0; };
+    const uint64_t fl = c->prm.flags;
+    const bool use_packs = !(fl & TSM_FLAG_GENERIC);
+    auto size_ok = [&](int lvl) {
+        return !((lvl == 16 && (fl & TSM_FLAG_GENERIC_16)) || (lvl == 32 && (fl & TSM_FLAG_GENERIC_32)) ||
+                 (lvl == 64 && (fl & TSM_FLAG_GENERIC_64)));
+    };
+    auto packable = [&](int32_t i) {
+        const int lvl = c->level_h[i];
+        return use_packs && packed_capacity(lvl) > 0 && size_ok(lvl);
+    };
     c->order_h.resize(n_inst);
     for (int64_t i = 0; i < n_inst; ++i) c->order_h[i] = (int32_t)i;
     // packable instances first, then by descending mesh size (largest first), stable
@@ -1058,9 +1066,10 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
 
 tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
     if (!c) return TSM_EINVAL;
-    const bool replan = ((flags ^ c->prm.flags) & (TSM_FLAG_STENCIL_STREAM | TSM_FLAG_GENERIC)) != 0;
+    const bool replan = ((flags ^ c->prm.flags) & (TSM_FLAG_STENCIL_STREAM | TSM_FLAG_GENERIC | TSM_FLAG_GENERIC_16 |
+                                                    TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64)) != 0;
     if (flags & ~(TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_TIMING | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT |
-                  TSM_FLAG_FIXED_POINT))
+                  TSM_FLAG_FIXED_POINT | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64))
         return c->fail(TSM_EINVAL, "unknown flag bits");
     HIPCHK(hipStreamSynchronize(c->stream));
     c->prm.flags = flags;
@@ -1078,10 +1087,11 @@ tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* fla
     if (steps < 1) return c->fail(TSM_EINVAL, "steps < 1");
     const int64_t ni = c->n_inst, tot = c->total;
     // plans are timed with the whole-step events (TSM_FLAG_TIMING would turn the graph off)
+    const uint64_t plan_bits = TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 |
+                               TSM_FLAG_GENERIC_64;
     const uint64_t timing = c->prm.flags & TSM_FLAG_TIMING;
-    const uint64_t keep = c->prm.flags & ~(TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT | TSM_FLAG_TIMING);
-    const uint64_t plans[3] = {0, TSM_FLAG_PERSISTENT, TSM_FLAG_GENERIC};
-    double ms[3] = {-1.0, -1.0, -1.0};
+    const uint64_t keep = c->prm.flags & ~(plan_bits | TSM_FLAG_TIMING);
+    double ms[4] = {-1.0, -1.0, -1.0, -1.0};
     double *su = nullptr, *sv = nullptr, *sF = nullptr;
     if (dalloc(&su, ni) != hipSuccess || dalloc(&sv, tot) != hipSuccess || dalloc(&sF, ni) != hipSuccess) {
         (void)hipGetLastError();
@@ -1096,27 +1106,56 @@ tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* fla
     tsm_status st = TSM_OK;
     const int64_t taken = c->steps_taken;
     if (!copy(su, sv, sF, c->u, c->v0, c->F)) st = c->fail(TSM_EHIP, "autotune: state copy");
-    int best = -1;
-    for (int k = 0; k < 3 && st == TSM_OK; ++k) {
-        if (plans[k] == TSM_FLAG_PERSISTENT && c->n_packs == 0) continue;   // same as plan 0
-        if (plans[k] == TSM_FLAG_GENERIC && c->n_packs == 0) continue;      // already generic
-        st = tsm_set_flags(c, keep | plans[k]);
-        if (st != TSM_OK) break;
+    // time one plan from the saved state, then restore it
+    auto trial = [&](uint64_t plan, double& out) {
+        if (st != TSM_OK) return;
+        st = tsm_set_flags(c, keep | plan);
+        if (st != TSM_OK) return;
         tsm_status s1 = tsm_step(c, 1);                  // warm-up (and code load)
-        if (s1 != TSM_OK && s1 != TSM_ENOCONV) { st = s1; break; }
-        s1 = tsm_step(c, steps);
-        if (s1 != TSM_OK && s1 != TSM_ENOCONV) { st = s1; break; }
-        ms[k] = c->step_ms / steps;
-        if (best < 0 || ms[k] < ms[best]) best = k;
+        if (s1 == TSM_OK || s1 == TSM_ENOCONV) s1 = tsm_step(c, steps);
+        if (s1 != TSM_OK && s1 != TSM_ENOCONV) { st = s1; return; }
+        out = c->step_ms / steps;
         if (!copy(c->u, c->v0, c->F, su, sv, sF)) st = c->fail(TSM_EHIP, "autotune: state restore");
+    };
+    // the packed mesh sizes present
+    bool present[3] = {false, false, false};
+    for (int32_t l : c->level_h) {
+        if (l == 16) present[0] = true;
+        if (l == 32) present[1] = true;
+        if (l == 64) present[2] = true;
     }
+    const bool packs = present[0] || present[1] || present[2];
+    // stage 1: whole plans
+    trial(0, ms[0]);
+    if (packs) {
+        trial(TSM_FLAG_PERSISTENT, ms[1]);
+        trial(TSM_FLAG_GENERIC, ms[2]);
+    }
+    uint64_t best = 0;
+    double best_ms = ms[0];
+    if (ms[1] >= 0 && ms[1] < best_ms) { best = TSM_FLAG_PERSISTENT; best_ms = ms[1]; }
+    // stage 2: from the better packed plan, move one mesh size at a time to
+    // the generic kernel while that helps
+    const uint64_t size_bit[3] = {TSM_FLAG_GENERIC_16, TSM_FLAG_GENERIC_32, TSM_FLAG_GENERIC_64};
+    int packed_sizes = (int)present[0] + (int)present[1] + (int)present[2];
+    for (int k = 0; k < 3 && st == TSM_OK && packed_sizes > 1; ++k) {
+        if (!present[k]) continue;
+        double t = -1.0;
+        trial(best | size_bit[k], t);
+        if (t >= 0 && t < best_ms) {
+            best |= size_bit[k];
+            best_ms = t;
+            --packed_sizes;
+        }
+    }
+    if (ms[2] >= 0 && ms[2] < best_ms) { best = TSM_FLAG_GENERIC; best_ms = ms[2]; }
+    ms[3] = best_ms;
     if (st == TSM_OK) {
-        if (best < 0) best = 0;
-        st = tsm_set_flags(c, keep | timing | plans[best]);
+        st = tsm_set_flags(c, keep | timing | best);
         (void)hipStreamSynchronize(c->stream);
         c->steps_taken = taken;
         if (ms_out) std::memcpy(ms_out, ms, sizeof(ms));
-        if (flags_out) *flags_out = plans[best];
+        if (flags_out) *flags_out = best;
     }
     (void)hipStreamSynchronize(c->stream);
     dfree(su); dfree(sv); dfree(sF);

@@ -27,6 +27,9 @@ TSM_FLAG_TIMING = 1 << 2
 TSM_FLAG_GENERIC = 1 << 3
 TSM_FLAG_PERSISTENT = 1 << 4
 TSM_FLAG_FIXED_POINT = 1 << 5
+TSM_FLAG_GENERIC_16 = 1 << 6
+TSM_FLAG_GENERIC_32 = 1 << 7
+TSM_FLAG_GENERIC_64 = 1 << 8
 
 STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV",
                 -4: "TSM_EHIP", -5: "TSM_ENOMEM", -6: "TSM_ESTATE"}
@@ -192,9 +195,24 @@ def tsm_set_flags(ctx, flags: int) -> None:
     _check(ctx, _lib.tsm_set_flags(ctx, int(flags)))
 
 
+PLAN_BITS = (TSM_FLAG_PERSISTENT | TSM_FLAG_GENERIC | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32
+             | TSM_FLAG_GENERIC_64)
+
+
+def plan_name(flags: int) -> str:
+    """Readable name of the launch-plan bits of a flag word."""
+    if flags & TSM_FLAG_GENERIC:
+        return "generic"
+    name = "persistent" if flags & TSM_FLAG_PERSISTENT else "per_size"
+    for bit, lvl in ((TSM_FLAG_GENERIC_16, 16), (TSM_FLAG_GENERIC_32, 32), (TSM_FLAG_GENERIC_64, 64)):
+        if flags & bit:
+            name += f"+generic{lvl}"
+    return name
+
+
 def tsm_autotune(ctx, steps: int):
-    """Returns (ms per step of each plan [per-size, persistent, generic], chosen flags)."""
-    ms = (ctypes.c_double * 3)()
+    """Returns (ms per step [per-size, persistent, generic, chosen], chosen plan flags)."""
+    ms = (ctypes.c_double * 4)()
     fl = ctypes.c_uint64()
     _check(ctx, _lib.tsm_autotune(ctx, int(steps), ms, ctypes.byref(fl)))
     return list(ms), fl.value

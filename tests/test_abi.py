@@ -90,3 +90,15 @@ def test_struct_layouts_match_header(tmp_path):
         assert ctypes.sizeof(py) == want[(cname, "size")], cname
         for f, _ in py._fields_:
             assert getattr(py, f).offset == want[(cname, f)], (cname, f)
+
+
+def test_binding_constants_match_header():
+    """Every TSM_ flag, status and precision the header defines has the same
+    value in the binding."""
+    from paper_2103_17040_amd import tsm
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defs = re.findall(r"#define\s+(TSM_[A-Z0-9_]+)\s+\(?\s*(\d+)(?:ull)?\s*(?:<<\s*(\d+))?\s*\)?", src)
+    assert len(defs) >= 9, defs
+    for name, base, shift in defs:
+        value = int(base) << int(shift or 0)
+        assert getattr(tsm, name) == value, name
