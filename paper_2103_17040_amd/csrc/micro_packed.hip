@@ -1,10 +1,13 @@
 // Packed micro solves for the common mesh sizes (16, 32 and 64 cells per
 // side): Jacobi-preconditioned CG (paper Section 3.3: CG on every micro
 // system, the systems distributed over the processors), laid out for a
-// 1024-lane workgroup that solves a pack of instances of one size in
-// lockstep:
-//     64x64: 1 instance on 14 waves,  32x32: 4 instances on 4 waves each,
-//     16x16: 16 instances on 1 wave each.
+// 768-lane workgroup (12 waves, 3 per SIMD: 168 VGPRs per lane) that
+// solves a pack of instances of one size in lockstep:
+//     64x64: 1 instance on 12 waves (strips of 6 rows),
+//     32x32: 3 instances on 4 waves each,  16x16: 12 instances on 1 wave each.
+// (1024 lanes would give 4 waves per SIMD but only 128 VGPRs, and 64x64 would
+// take 14 waves in strips of 5 rows: the busiest SIMD then carries 4 waves x
+// 5 rows against 3 x 6 here, and the solver state spills.)
 // Within an instance, lane l owns column l % (N+1) and a strip of R
 // consecutive rows.  Each iteration it reads only the left/right neighbour
 // columns and the two rows past its strip from LDS (2R+6 reads for R nodes,
@@ -17,7 +20,7 @@
 // (FP64) or 20 (FP32) bytes per node; the lower coefficients are loaded from
 // the neighbours' planes (same cache lines as the neighbours' own loads).
 //
-// Register budget (1024 lanes: 128 VGPRs per lane) decides the data flow:
+// Register budget (768 lanes: 168 VGPRs per lane) decides the data flow:
 //   FP64 form     x, r, p, q in FP64 registers, diag^{-1} in FP32 (the
 //                 preconditioner need not be exact), FP64 stencil re-read
 //                 from global memory every iteration.
@@ -43,7 +46,7 @@ namespace tsm {
 namespace {
 
 constexpr int NTP = kPackThreads;
-constexpr int NWP = NTP / kWave;
+constexpr int NWP = 16;                    // reduction slots: at most 16 waves
 
 template <int N_, int TPI_, int R_>
 struct Lvl {
@@ -63,7 +66,7 @@ struct Lvl {
 };
 using L16 = Lvl<16, 64, 6>;
 using L32 = Lvl<32, 256, 5>;
-using L64 = Lvl<64, 896, 5>;
+using L64 = Lvl<64, 768, 6>;
 
 // Per-instance sums of NV values (NV <= 4).  Level 1: every wave reduces its
 // lanes into lane 63 (wave_total_last), which writes the NV totals to LDS.

@@ -9,7 +9,7 @@
 namespace tsm {
 
 constexpr int kMicroThreads = 256;        // lanes per micro workgroup (4 waves), generic kernels
-constexpr int kPackThreads = 1024;        // lanes per packed workgroup (16 waves)
+constexpr int kPackThreads = 768;         // lanes per packed workgroup (12 waves)
 constexpr int kWave = 64;
 constexpr int kMaxLevel = 64;             // largest micro mesh N (cells per side)
 constexpr int kMinLevel = 2;
@@ -124,7 +124,7 @@ struct MicroArgs {
     int32_t* queue;       // persistent work counter (null: task = blockIdx.x)
 };
 
-// Packs of instances of one mesh size solved by one 1024-lane workgroup.
+// Packs of instances of one mesh size solved by one kPackThreads-lane workgroup.
 constexpr int kPackSlots = 16;             // slot stride of a pack (the most instances a pack holds)
 
 struct PackList {
