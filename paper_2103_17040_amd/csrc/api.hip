@@ -575,8 +575,15 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPALLOC(c->bx, ni); HIPALLOC(c->alpha, ni); HIPALLOC(c->F, ni); HIPALLOC(c->u, ni);
     HIPALLOC(c->S64, kStencil * tot); HIPALLOC(c->M64, kStencil * tot); HIPALLOC(c->S32, kStencil * tot);
     HIPALLOC(c->Slo, kStencil * tot);
-    HIPALLOC(c->Ss64, kSym * tot); HIPALLOC(c->Ks64, kSym * tot); HIPALLOC(c->Ms32, kSym * tot);
-    HIPALLOC(c->Ss32, kSym * tot); HIPALLOC(c->Sslo, kSym * tot);
+    // symmetric planes: kPlanePad zeroed entries past the last instance
+    // (the packed kernels read past an instance's block for strip rows past
+    // its mesh and discard the products)
+    const int64_t np = kSym * tot + kPlanePad;
+    HIPALLOC(c->Ss64, np); HIPALLOC(c->Ks64, np); HIPALLOC(c->Ms32, np);
+    HIPALLOC(c->Ss32, np); HIPALLOC(c->Sslo, np);
+    HIPCHK(hipMemset(c->Ss64, 0, np * sizeof(double))); HIPCHK(hipMemset(c->Ks64, 0, np * sizeof(double)));
+    HIPCHK(hipMemset(c->Ms32, 0, np * sizeof(float))); HIPCHK(hipMemset(c->Ss32, 0, np * sizeof(float)));
+    HIPCHK(hipMemset(c->Sslo, 0, np * sizeof(float)));
     HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot);
     HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());

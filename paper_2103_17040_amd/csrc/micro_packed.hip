@@ -47,6 +47,7 @@ namespace {
 
 constexpr int NTP = kPackThreads;
 constexpr int NWP = 16;                    // reduction slots: at most 16 waves
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 template <int N_, int TPI_, int R_>
 struct Lvl {
@@ -67,6 +68,13 @@ struct Lvl {
 using L16 = Lvl<16, 64, 6>;
 using L32 = Lvl<32, 256, 5>;
 using L64 = Lvl<64, 768, 6>;
+
+// Workgroup barrier for LDS traffic only.  __syncthreads() is also a memory
+// fence, which makes every wave wait for all of its global loads, the
+// asynchronous global->LDS plane copies included; this barrier waits only for
+// the wave's own LDS operations, so a plane copy stays in flight across it.
+// Every use orders LDS accesses alone.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Per-instance sums of NV values (NV <= 4).  Level 1: every wave reduces its
 // lanes into lane 63 (wave_total_last), which writes the NV totals to LDS.
@@ -91,7 +99,7 @@ struct PackRed {
 #pragma unroll
             for (int i = 0; i < NV; ++i) buf[phase][wid][i] = v[i];
         }
-        __syncthreads();
+        lds_barrier();
         const bool has = lane < L::IPP * L::WPI;
         const T* slot = buf[phase][lane & (NWP - 1)];   // in bounds for every lane
         T t[NV];
@@ -131,8 +139,13 @@ struct Lane {
 template <class L>
 __device__ __forceinline__ Lane lane_of(const PackList& P, int task, int cnt) {
     Lane z;
-    z.sub = threadIdx.x / L::TPI;
-    z.lt = threadIdx.x - z.sub * L::TPI;
+    // the lane geometry is recomputed for every pack: hidden from the
+    // compiler, so that it is not hoisted out of the work-queue loop and
+    // held (or spilled) across every solve
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    z.sub = tid / L::TPI;
+    z.lt = tid - z.sub * L::TPI;
     z.w0 = (z.sub < L::IPP ? z.sub : 0) * L::WPI;
     z.live = z.sub < L::IPP && z.sub < cnt;
     // every wave belongs to one instance: instance and offset are wave-uniform
@@ -198,38 +211,15 @@ __device__ __forceinline__ const T* opaque(const T* p) {
     return p;
 }
 
-// Load from global memory at base + byte.  The address-space cast keeps it a
-// global load after opaque() has hidden where the pointer came from (a flat
-// load would also count against the LDS wait counter).
-template <typename T>
-__device__ __forceinline__ T global_at(const T* base, uint32_t byte) {
-    using gchar = const __attribute__((address_space(1))) char;
-    using gT = const __attribute__((address_space(1))) T;
-    return *reinterpret_cast<gT*>((gchar*)base + byte);
-}
-
-// Coefficient k of the 9-point row of the lane's strip row i from the
-// upper-half planes at base (instance block, [kSym][n]): wave-uniform base
-// plus a zero-extended 32-bit byte offset.  Rows past the mesh read the last
-// mesh row (results discarded).  The lower couplings index a neighbour node;
-// every such index stays inside the instance's five planes (at worst it
-// falls NP+1 entries into the previous plane).  Wrapped reads at the left
-// and right edges hit coefficients that are structurally zero (E and NE of
-// the last column, NW of the first column, N of the top row), so only the
-// bottom mesh row needs a mask.
+// Coefficient k of the 9-point row of the lane's strip row i is read from the
+// upper-half planes of the instance ([kSym][n]).  The lower couplings index a
+// neighbour node; for mesh row 0 such an index falls at most NP+1 entries
+// into the previous plane (never before the block).  Wrapped reads at the
+// left and right edges hit coefficients that are structurally zero (E and NE
+// of the last column, NW of the first column, N of the top row), so only the
+// bottom mesh row needs a mask (sym_mask).
 template <class L, typename T>
-__device__ __forceinline__ T sym_load(const T* base, const Lane& z, int i, int k) {
-    const int row = min(z.r0 + i, L::NP - 1);
-    const int node = row * L::NP + z.col;
-    int e;
-    switch (k) {
-        case 0: e = 4 * L::n + node - L::NP - 1; break;    // SW = NE of j-NP-1
-        case 1: e = 3 * L::n + node - L::NP; break;        // S  = N  of j-NP
-        case 2: e = 2 * L::n + node - L::NP + 1; break;    // SE = NW of j-NP+1
-        case 3: e = 1 * L::n + node - 1; break;            // W  = E  of j-1
-        default: e = (k - 4) * L::n + node; break;         // own C, E, NW, N, NE
-    }
-    const T v = global_at(base, (uint32_t)e * (uint32_t)sizeof(T));
+__device__ __forceinline__ T sym_mask(const Lane& z, int i, int k, T v) {
     if (i == 0 && k <= 3) {
         // strip row 0 may be mesh row 0: no southern neighbours, and node 0 has no W
         const bool ok = (k == 3) ? (z.r0 > 0 || z.col > 0) : (z.r0 > 0);
@@ -238,13 +228,68 @@ __device__ __forceinline__ T sym_load(const T* base, const Lane& z, int i, int k
     return v;
 }
 
+
+// The same coefficients from a copy of the instance's planes in LDS, read
+// from two per-lane base addresses (planes 0-1 from the lane's node in strip
+// row 0, planes 2-4 from one plane further) plus compile-time offsets, all
+// non-negative and below 64 KiB (the instruction's offset field): no
+// per-coefficient address arithmetic.  Strip rows past the mesh read up to
+// 2(N+1) floats past the instance's planes (the buffer is padded for the last
+// one); their products are discarded.
+template <class L>
+struct LdsPlanes {
+    const float* lo;
+    const float* hi;
+    __device__ __forceinline__ LdsPlanes(const float* planes, const Lane& z) {
+        const int j0 = z.r0 * L::NP + z.col;
+        lo = planes + j0;
+        hi = planes + L::n + j0;
+    }
+    __device__ __forceinline__ float at(const Lane& z, int i, int k) const {
+        int p, d;
+        switch (k) {
+            case 0: p = 4; d = -L::NP - 1; break;    // SW = NE of j-NP-1
+            case 1: p = 3; d = -L::NP; break;        // S  = N  of j-NP
+            case 2: p = 2; d = -L::NP + 1; break;    // SE = NW of j-NP+1
+            case 3: p = 1; d = -1; break;            // W  = E  of j-1
+            default: p = k - 4; d = 0; break;        // own C, E, NW, N, NE
+        }
+        const float v = p < 2 ? lo[p * L::n + i * L::NP + d] : hi[(p - 1) * L::n + i * L::NP + d];
+        return sym_mask<L>(z, i, k, v);
+    }
+    static_assert((3 * L::n + L::R * L::NP) * 4 < 65536, "offsets fit the instruction");
+};
+
+// Asynchronous copy of one instance's symmetric FP32 planes (kSym * n floats
+// at src, global) into LDS at dst, issued by the waves of the instance (lt:
+// lane within the instance): each instruction moves 64 consecutive floats,
+// lane l's to dst + 64c + l, without passing through registers.
+template <class L>
+__device__ __forceinline__ void planes_copy_start(const float* src, float* dst, int lt) {
+    using gptr = __attribute__((address_space(1))) void*;
+    using lptr = __attribute__((address_space(3))) void*;
+    constexpr int total = kSym * L::n;
+    const int lane = lt & (kWave - 1);
+    for (int c = lt / kWave; c * kWave < total; c += L::WPI) {
+        const int e = c * kWave + lane;
+        if (e < total) __builtin_amdgcn_global_load_lds((gptr)(src + e), (lptr)(dst + c * kWave), 4, 0, 0);
+    }
+}
+
+// Every wave waits for its own copies, then for the others'.
+__device__ __forceinline__ void planes_copy_wait() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
 // Stencil sources.  A source gives, for row i of the lane's strip and
 // coefficient k, a raw value (load) and the coefficient (value):
 //   RegStencil     FP32 stencil resident in registers
 //   SymStencil     symmetric planes in global memory, streamed
-//   SplitStencil   FP64 operator as resident FP32 part + streamed FP32 low
-//                  part: S32 + Slo spans at most 48 significant bits, so the
-//                  FP64 sum is exact and equals S to about 2^-48 relative.
+//   SplitStencil   FP64 operator as resident FP32 part + FP32 low part read
+//                  from an LDS copy of its planes: S32 + Slo spans at most 48
+//                  significant bits, so the FP64 sum is exact and equals S to
+//                  about 2^-48 relative.
 template <class L, typename TS>
 struct RegStencil {
     static constexpr bool kGlobal = false;
@@ -254,22 +299,50 @@ struct RegStencil {
     __device__ __forceinline__ TS value(int, int, TS raw) const { return raw; }
 };
 
+// Streamed planes are addressed with one VGPR per lane: each load is plane
+// k's base (wave-uniform, SGPRs) + the byte offset of the lane's node in
+// strip row 0 (VGPR) + a compile-time offset for the row and the neighbour
+// (the instruction's immediate), so a whole batch of loads is in flight with
+// no address registers of its own.  Strip rows past the mesh read past the
+// instance's block (the planes carry kPlanePad zeroed entries at the end);
+// their products are discarded.
 template <class L, typename TS>
 struct SymStencil {
     static constexpr bool kGlobal = true;
     using raw_t = TS;
-    const TS* __restrict__ base;
-    __device__ __forceinline__ TS load(const Lane& z, int i, int k) const { return sym_load<L>(base, z, i, k); }
+    const TS* __restrict__ base;   // instance block: kSym planes of n
+    const TS* pb[kSym] = {};       // plane bases, set by prepare()
+    uint32_t vofs = 0;
+    __device__ __forceinline__ SymStencil(const TS* b) : base(b) {}
+    __device__ __forceinline__ void prepare(const Lane& z) {
+#pragma unroll
+        for (int p = 0; p < kSym; ++p) pb[p] = opaque(base + p * L::n);
+        vofs = (uint32_t)((z.r0 * L::NP + z.col) * (int)sizeof(TS));
+    }
+    __device__ __forceinline__ TS load(const Lane& z, int i, int k) const {
+        int p, d;
+        switch (k) {
+            case 0: p = 4; d = -L::NP - 1; break;    // SW = NE of j-NP-1
+            case 1: p = 3; d = -L::NP; break;        // S  = N  of j-NP
+            case 2: p = 2; d = -L::NP + 1; break;    // SE = NW of j-NP+1
+            case 3: p = 1; d = -1; break;            // W  = E  of j-1
+            default: p = k - 4; d = 0; break;        // own C, E, NW, N, NE
+        }
+        using gchar = const __attribute__((address_space(1))) char;
+        using gT = const __attribute__((address_space(1))) TS;
+        const TS v = *reinterpret_cast<gT*>((gchar*)pb[p] + vofs + (i * L::NP + d) * (int)sizeof(TS));
+        return sym_mask<L>(z, i, k, v);
+    }
     __device__ __forceinline__ TS value(int, int, TS raw) const { return raw; }
 };
 
 template <class L>
 struct SplitStencil {
-    static constexpr bool kGlobal = true;
+    static constexpr bool kGlobal = false;
     using raw_t = float;
     const float (&S)[L::R][kStencil];
-    const float* __restrict__ base;   // low parts, symmetric planes
-    __device__ __forceinline__ float load(const Lane& z, int i, int k) const { return sym_load<L>(base, z, i, k); }
+    LdsPlanes<L> planes;              // low parts, symmetric planes, copied to LDS
+    __device__ __forceinline__ float load(const Lane& z, int i, int k) const { return planes.at(z, i, k); }
     __device__ __forceinline__ double value(int i, int k, float raw) const { return (double)S[i][k] + (double)raw; }
 };
 
@@ -283,7 +356,7 @@ template <class L, int B, typename TA, typename TG, class ST>
 __device__ __forceinline__ void strip_apply(const ST& S0, const TG* g, const Lane& z,
                                             const TG (&mine)[L::R], TA (&y)[L::R]) {
     ST S = S0;
-    if constexpr (ST::kGlobal) S.base = opaque(S.base);
+    if constexpr (ST::kGlobal) S.prepare(z);
     constexpr int W2 = L::W2;
     const int base = (z.r0 + 1) * W2 + (z.col + 1);
     TG lf[L::R + 2], rt[L::R + 2];
@@ -337,7 +410,7 @@ template <class L, int B, typename TA, typename TG, class ST>
 __device__ __forceinline__ void strip_apply_lean(const ST& S0, const TG* g, const Lane& z,
                                                  const TG (&mine)[L::R], TA (&y)[L::R]) {
     ST S = S0;
-    if constexpr (ST::kGlobal) S.base = opaque(S.base);
+    if constexpr (ST::kGlobal) S.prepare(z);
     constexpr int W2 = L::W2;
     const int base = (z.r0 + 1) * W2 + (z.col + 1);
     typename ST::raw_t carry7 = typename ST::raw_t(0);
@@ -409,9 +482,13 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
 // NORM_LATER: the time-step form leaves ||b||^2 to the caller (bb = 0), which
 // forms b = M x0/dt = S x0 + r from its register stencil instead of reading
 // M (the refinement solve; x0 stays in the double grid).
+// copy_src/copy_dst (non-null): start the asynchronous copy of the instance's
+// FP32 planes into LDS once x0 is in the grid, so that it overlaps the
+// operator application; the caller waits for it (planes_copy_wait).
 template <class L, bool NORM_LATER = false>
 __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, double* xg, double (&x)[L::R],
-                                           double (&r)[L::R], double& bb) {
+                                           double (&r)[L::R], double& bb, const float* copy_src = nullptr,
+                                           float* copy_dst = nullptr) {
     zero_halo<L, double>(xg, z);
     const double cf = (z.live && A.coef != nullptr) ? A.coef[z.inst] : 0.0;
 #pragma unroll
@@ -425,6 +502,7 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
     }
     strip_store<L>(xg, z, x);
     __syncthreads();
+    if (copy_src != nullptr && z.live) planes_copy_start<L>(copy_src, copy_dst, z.lt);
     double b[L::R], sx[L::R];
 #pragma unroll
     for (int i = 0; i < L::R; ++i) { b[i] = 0.0; sx[i] = 0.0; }
@@ -472,9 +550,11 @@ __device__ void pack_fp64(const MicroArgs& A, const PackList& P, int task, int c
     double bb;
     pack_start<L>(A, z, xg, x, r, bb);
     double acc[3] = {bb, 0.0, 0.0};
+    SymStencil<L, double> Sd = S;
+    Sd.prepare(z);
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
-        dinv[i] = row_ok<L>(z, i) ? (float)(1.0 / S.load(z, i, 4)) : 0.0f;
+        dinv[i] = row_ok<L>(z, i) ? (float)(1.0 / Sd.load(z, i, 4)) : 0.0f;
         p[i] = (double)dinv[i] * r[i];
         acc[1] += r[i] * p[i];
         acc[2] += r[i] * r[i];
@@ -531,32 +611,41 @@ __device__ void pack_fp64(const MicroArgs& A, const PackList& P, int task, int c
 }
 
 // --------------------------------------------------------------- REFINE
+// planes: LDS for the FP32 planes of the pack's instances (IPP * kSym * n
+// floats).  It holds S32 while the register stencil is loaded, then the low
+// parts Slo, copied while the first inner solve runs, for the FP64 residual
+// updates.  Between the start of a copy and its wait, barriers are
+// lds_barrier() (LDS ordering only) so that the copy stays in flight.
 template <class L>
-__device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int cnt, double* lds, PackRed<1, double>& red1,
-                            PackRed<3, double>& red3, PackRed<2, float>& rf2) {
+__device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int cnt, double* lds, float* planes,
+                            PackRed<1, double>& red1, PackRed<3, double>& red3, PackRed<2, float>& rf2) {
     const Lane z = lane_of<L>(P, task, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     float* pg = reinterpret_cast<float*>(xg);
+    // spare instances of a partial pack read instance 0's planes (results discarded)
+    float* pl = planes + (z.live ? z.sub : 0) * (kSym * L::n);
     double x[L::R], r64[L::R];
     double bb;
-    pack_start<L, true>(A, z, xg, x, r64, bb);
+    pack_start<L, true>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, pl);
     float S[L::R][kStencil], dinv[L::R];
+    planes_copy_wait();
+    const LdsPlanes<L> plv(pl, z);
     {
-        // branch-free: every row's loads in flight at once (rows past the
-        // mesh read the last mesh row in bounds; their products are
-        // discarded and their diag^{-1} is 0); coefficient 1 of row i > 0
-        // is coefficient 7 of row i-1
-        const float* Sf = A.Ss32 + kSym * z.off;
+        // coefficient 1 of row i > 0 is coefficient 7 of row i-1; rows past
+        // the mesh give products that are discarded and diag^{-1} = 0
 #pragma unroll
         for (int i = 0; i < L::R; ++i)
 #pragma unroll
             for (int k = 0; k < kStencil; ++k)
-                S[i][k] = (k == 1 && i > 0) ? S[i - 1][7] : sym_load<L>(Sf, z, i, k);
+                S[i][k] = (k == 1 && i > 0) ? S[i - 1][7] : plv.at(z, i, k);
 #pragma unroll
         for (int i = 0; i < L::R; ++i) dinv[i] = row_ok<L>(z, i) ? 1.0f / S[i][4] : 0.0f;
     }
+    // every wave has its stencil: the planes buffer takes the low parts next
+    lds_barrier();
+    if (z.live) planes_copy_start<L>(A.Sslo + kSym * z.off, pl, z.lt);
     const RegStencil<L, float> SR{S};
-    const SplitStencil<L> S64{S, A.Sslo + kSym * z.off};
+    const SplitStencil<L> S64{S, plv};
     if (A.rhs_vec == nullptr) {
         // ||b|| of the time step from b = S x0 + r (S in FP32: the norm only
         // sizes the tolerance, ~1e-7 relative is plenty); x0 is in the grid
@@ -582,7 +671,7 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
     bool conv = rr <= tol2;
     int sweeps = 1, iters = 0;
     zero_halo<L, float>(pg, z);     // the float view of the grid from here on
-    __syncthreads();
+    lds_barrier();
     const double othr = lane_threshold<L>(otol_s, cnt);
     bool ogo = red3.any_above(othr);
     while (ogo && sweeps <= A.max_refine) {
@@ -607,7 +696,7 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
         }
         const float itol2 = me ? inner_tol2(tol2, rr, A.inner_rtol) : 0.0f;
         if (z.live && z.lt == 0) itol_s[z.sub] = itol2;
-        __syncthreads();
+        lds_barrier();
         const float ithr = lane_threshold<L>(itol_s, cnt);
         float vthr = ithr, gam0 = 0.0f;
         float gam_prev = 1.0f, alpha_prev = 1.0f;
@@ -618,7 +707,7 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
 #pragma unroll
             for (int i = 0; i < L::R; ++i) u[i] = dinv[i] * r[i];
             strip_store<L>(pg, z, u);
-            __syncthreads();
+            lds_barrier();
             // every lane applies (no branch): the reads of inactive and spare
             // lanes stay inside the LDS block, rows past the mesh give 0, and
             // spare waves never enter a sum
@@ -659,7 +748,7 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
 #pragma unroll
         for (int i = 0; i < L::R; ++i) x[i] += sc * (double)d[i];
         strip_store<L>(pg, z, d);
-        __syncthreads();
+        planes_copy_wait();     // the low parts are in LDS from here on
         double sd[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) sd[i] = 0.0;
@@ -684,8 +773,16 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
         rr = a1[0];
         if (!conv && rr <= tol2) conv = true;
     }
+    // the copy must end before the next pack's copy reuses the buffer (a pack
+    // that needs no sweep never waited for it)
+    planes_copy_wait();
     pack_store<L>(A, z, x, iters, sweeps, conv, rr, red1);
 }
+
+// FP32 planes buffer of the refinement (one pack's instances), in LDS, with
+// room for the reads past the last instance's planes (LdsPlanes).
+constexpr int kPlaneFloats =
+    cmax(cmax(L16::IPP * kSym * L16::n, L32::IPP * kSym * L32::n), L64::IPP * kSym * L64::n) + 2 * (kMaxLevel + 1);
 
 // Reduction buffers of one packed workgroup.
 struct PackShared {
@@ -716,8 +813,12 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
         }
         if (task >= P.n_packs) break;
         const int cnt = P.count[task];
-        if constexpr (MODE == 2) pack_refine<L>(A, P, task, cnt, lds, red1, red3, rf2);
-        else pack_fp64<L>(A, P, task, cnt, lds, red1, red2, red3);
+        if constexpr (MODE == 2) {
+            __shared__ float planes[kSym * L::n * L::IPP + 2 * L::NP];
+            pack_refine<L>(A, P, task, cnt, lds, planes, red1, red3, rf2);
+        } else {
+            pack_fp64<L>(A, P, task, cnt, lds, red1, red2, red3);
+        }
         if (A.queue == nullptr) break;
         __syncthreads();
     }
@@ -742,9 +843,10 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
         if (task >= P.n_packs) break;
         const int lvl = pack_level[task], cnt = P.count[task];
         if constexpr (MODE == 2) {
-            if (lvl == 64) pack_refine<L64>(A, P, task, cnt, lds, red1, red3, rf2);
-            else if (lvl == 32) pack_refine<L32>(A, P, task, cnt, lds, red1, red3, rf2);
-            else pack_refine<L16>(A, P, task, cnt, lds, red1, red3, rf2);
+            __shared__ float planes[kPlaneFloats];
+            if (lvl == 64) pack_refine<L64>(A, P, task, cnt, lds, planes, red1, red3, rf2);
+            else if (lvl == 32) pack_refine<L32>(A, P, task, cnt, lds, planes, red1, red3, rf2);
+            else pack_refine<L16>(A, P, task, cnt, lds, planes, red1, red3, rf2);
         } else {
             if (lvl == 64) pack_fp64<L64>(A, P, task, cnt, lds, red1, red2, red3);
             else if (lvl == 32) pack_fp64<L32>(A, P, task, cnt, lds, red1, red2, red3);
