@@ -581,9 +581,12 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     const int64_t np = kSym * tot + kPlanePad;
     HIPALLOC(c->Ss64, np); HIPALLOC(c->Ks64, np); HIPALLOC(c->Ms32, np);
     HIPALLOC(c->Ss32, np); HIPALLOC(c->Sslo, np);
-    HIPCHK(hipMemset(c->Ss64, 0, np * sizeof(double))); HIPCHK(hipMemset(c->Ks64, 0, np * sizeof(double)));
-    HIPCHK(hipMemset(c->Ms32, 0, np * sizeof(float))); HIPCHK(hipMemset(c->Ss32, 0, np * sizeof(float)));
-    HIPCHK(hipMemset(c->Sslo, 0, np * sizeof(float)));
+    const int64_t pe = kSym * tot;     // the assembly writes every entry before it
+    HIPCHK(hipMemset(c->Ss64 + pe, 0, kPlanePad * sizeof(double)));
+    HIPCHK(hipMemset(c->Ks64 + pe, 0, kPlanePad * sizeof(double)));
+    HIPCHK(hipMemset(c->Ms32 + pe, 0, kPlanePad * sizeof(float)));
+    HIPCHK(hipMemset(c->Ss32 + pe, 0, kPlanePad * sizeof(float)));
+    HIPCHK(hipMemset(c->Sslo + pe, 0, kPlanePad * sizeof(float)));
     HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot);
     HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());
