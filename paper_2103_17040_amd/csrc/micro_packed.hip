@@ -58,6 +58,9 @@ struct Lvl {
     static constexpr int IPP = NTP / TPI_;                  // instances per pack
     static constexpr int GRID = H2 * W2;                    // LDS cells per instance
     static constexpr int n = NP * NP;
+    // LDS stride of one instance's copied FP32 planes (planes_copy_start):
+    // kSym*n floats shifted by up to 3, rounded up to whole 16-byte words
+    static constexpr int PS = (kSym * NP * NP + 8 + 3) / 4 * 4;
     // DPP group of the second reduction level: the waves of one instance
     static constexpr int G = IPP == 1 ? 16 : WPI;
     static_assert(NS * NP <= TPI, "strips do not fit the lanes of an instance");
@@ -136,8 +139,13 @@ struct Lane {
     int64_t off;
 };
 
+// A pack's metadata, copied into LDS ahead of its solve (meta_copy_start):
+// slot instances [0, 16), slot offsets as int64 [16, 48), instance count 48,
+// mesh size 49.
+constexpr int kMetaInst = 0, kMetaOff = 16, kMetaCount = 48, kMetaLevel = 49, kMetaWords = 64;
+
 template <class L>
-__device__ __forceinline__ Lane lane_of(const PackList& P, int task, int cnt) {
+__device__ __forceinline__ Lane lane_of(const int32_t* meta, int cnt) {
     Lane z;
     // the lane geometry is recomputed for every pack: hidden from the
     // compiler, so that it is not hoisted out of the work-queue loop and
@@ -149,12 +157,11 @@ __device__ __forceinline__ Lane lane_of(const PackList& P, int task, int cnt) {
     z.w0 = (z.sub < L::IPP ? z.sub : 0) * L::WPI;
     z.live = z.sub < L::IPP && z.sub < cnt;
     // every wave belongs to one instance: instance and offset are wave-uniform
-    // and come from the pack's slot directly
-    const int t = task * kPackSlots + (z.live ? z.sub : 0);
-    int inst = z.live ? P.slot_inst[t] : 0;
-    const int64_t off = z.live ? P.slot_off[t] : 0;
-    inst = __builtin_amdgcn_readfirstlane(inst);
-    z.inst = inst;
+    // and come from the pack's slot in the LDS copy of its metadata
+    const int t = z.live ? z.sub : 0;
+    const int inst = z.live ? meta[kMetaInst + t] : 0;
+    const int64_t off = z.live ? *reinterpret_cast<const int64_t*>(meta + kMetaOff + 2 * t) : 0;
+    z.inst = __builtin_amdgcn_readfirstlane(inst);
     z.col = z.lt % L::NP;
     const int strip = z.lt / L::NP;
     z.r0 = strip * L::R;
@@ -261,18 +268,24 @@ struct LdsPlanes {
 };
 
 // Asynchronous copy of one instance's symmetric FP32 planes (kSym * n floats
-// at src, global) into LDS at dst, issued by the waves of the instance (lt:
-// lane within the instance): each instruction moves 64 consecutive floats,
-// lane l's to dst + 64c + l, without passing through registers.
+// at src, global) into LDS, issued by the waves of the instance (lt: lane
+// within the instance), without passing through registers.  Each instruction
+// moves 16 bytes per lane, 1 KiB per wave, from a 16-byte aligned address:
+// the copy starts `shift` = (src / 4) mod 4 floats before src, so element e
+// of the block lands at region + shift + e (region: 16-byte aligned, L::PS
+// floats).  It ends at most 3 floats past the block (inside the planes'
+// zeroed pad after the last instance).
 template <class L>
-__device__ __forceinline__ void planes_copy_start(const float* src, float* dst, int lt) {
+__device__ __forceinline__ void planes_copy_start(const float* src, float* region, int lt, int shift) {
     using gptr = __attribute__((address_space(1))) void*;
     using lptr = __attribute__((address_space(3))) void*;
-    constexpr int total = kSym * L::n;
+    constexpr int chunk = kWave * 4;
+    const float* g = src - shift;
+    const int total = shift + kSym * L::n;
     const int lane = lt & (kWave - 1);
-    for (int c = lt / kWave; c * kWave < total; c += L::WPI) {
-        const int e = c * kWave + lane;
-        if (e < total) __builtin_amdgcn_global_load_lds((gptr)(src + e), (lptr)(dst + c * kWave), 4, 0, 0);
+    for (int c = lt / kWave; c * chunk < total; c += L::WPI) {
+        const int e = c * chunk + 4 * lane;
+        if (e < total) __builtin_amdgcn_global_load_lds((gptr)(g + e), (lptr)(region + c * chunk), 16, 0, 0);
     }
 }
 
@@ -280,6 +293,21 @@ __device__ __forceinline__ void planes_copy_start(const float* src, float* dst, 
 __device__ __forceinline__ void planes_copy_wait() {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
+}
+
+// Asynchronous copy of pack `task`'s metadata into LDS (kMetaWords words at
+// dst), one instruction of the first wave: lane l copies word l.  pack_level
+// may be null (one mesh size); unused words repeat the count.
+__device__ __forceinline__ void meta_copy_start(const PackList& P, const int32_t* pack_level, int task,
+                                                int32_t* dst) {
+    using gptr = __attribute__((address_space(1))) void*;
+    using lptr = __attribute__((address_space(3))) void*;
+    const int l = threadIdx.x & (kWave - 1);
+    const int32_t* src = P.count + task;
+    if (l < kMetaOff) src = P.slot_inst + task * kPackSlots + l;
+    else if (l < kMetaCount) src = reinterpret_cast<const int32_t*>(P.slot_off + task * kPackSlots) + (l - kMetaOff);
+    else if (l == kMetaLevel && pack_level != nullptr) src = pack_level + task;
+    __builtin_amdgcn_global_load_lds((gptr)src, (lptr)dst, 4, 0, 0);
 }
 
 // Stencil sources.  A source gives, for row i of the lane's strip and
@@ -483,12 +511,13 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
 // forms b = M x0/dt = S x0 + r from its register stencil instead of reading
 // M (the refinement solve; x0 stays in the double grid).
 // copy_src/copy_dst (non-null): start the asynchronous copy of the instance's
-// FP32 planes into LDS once x0 is in the grid, so that it overlaps the
-// operator application; the caller waits for it (planes_copy_wait).
+// FP32 planes into LDS (planes_copy_start) once x0 is in the grid, so that it
+// overlaps the operator application; the caller waits for it
+// (planes_copy_wait).
 template <class L, bool NORM_LATER = false>
 __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, double* xg, double (&x)[L::R],
                                            double (&r)[L::R], double& bb, const float* copy_src = nullptr,
-                                           float* copy_dst = nullptr) {
+                                           float* copy_dst = nullptr, int copy_shift = 0) {
     zero_halo<L, double>(xg, z);
     const double cf = (z.live && A.coef != nullptr) ? A.coef[z.inst] : 0.0;
 #pragma unroll
@@ -502,7 +531,7 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
     }
     strip_store<L>(xg, z, x);
     __syncthreads();
-    if (copy_src != nullptr && z.live) planes_copy_start<L>(copy_src, copy_dst, z.lt);
+    if (copy_src != nullptr && z.live) planes_copy_start<L>(copy_src, copy_dst, z.lt, copy_shift);
     double b[L::R], sx[L::R];
 #pragma unroll
     for (int i = 0; i < L::R; ++i) { b[i] = 0.0; sx[i] = 0.0; }
@@ -539,16 +568,19 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
 }
 
 // ------------------------------------------------------------------ FP64
-template <class L>
-__device__ void pack_fp64(const MicroArgs& A, const PackList& P, int task, int cnt, double* lds, PackRed<1, double>& red1,
-                          PackRed<2, double>& red2, PackRed<3, double>& red3) {
-    const Lane z = lane_of<L>(P, task, cnt);
+// meta: this pack's metadata in LDS; prefetch(): starts the copy of the next
+// pack's metadata (all waves call it once, early in the solve).
+template <class L, class Prefetch>
+__device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, PackRed<1, double>& red1,
+                          PackRed<2, double>& red2, PackRed<3, double>& red3, Prefetch prefetch) {
+    const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     const SymStencil<L, double> S{A.Ss64 + kSym * z.off};
     double x[L::R], r[L::R], p[L::R];
     float dinv[L::R];
     double bb;
     pack_start<L>(A, z, xg, x, r, bb);
+    prefetch();
     double acc[3] = {bb, 0.0, 0.0};
     SymStencil<L, double> Sd = S;
     Sd.prepare(z);
@@ -616,17 +648,21 @@ __device__ void pack_fp64(const MicroArgs& A, const PackList& P, int task, int c
 // parts Slo, copied while the first inner solve runs, for the FP64 residual
 // updates.  Between the start of a copy and its wait, barriers are
 // lds_barrier() (LDS ordering only) so that the copy stays in flight.
-template <class L>
-__device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int cnt, double* lds, float* planes,
-                            PackRed<1, double>& red1, PackRed<3, double>& red3, PackRed<2, float>& rf2) {
-    const Lane z = lane_of<L>(P, task, cnt);
+template <class L, class Prefetch>
+__device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, float* planes,
+                            PackRed<1, double>& red1, PackRed<3, double>& red3, PackRed<2, float>& rf2,
+                            Prefetch prefetch) {
+    const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     float* pg = reinterpret_cast<float*>(xg);
-    // spare instances of a partial pack read instance 0's planes (results discarded)
-    float* pl = planes + (z.live ? z.sub : 0) * (kSym * L::n);
+    // spare instances of a partial pack read instance 0's planes (results
+    // discarded); pl: element 0 of the instance's copied planes
+    float* region = planes + (z.live ? z.sub : 0) * L::PS;
+    const int shift = (int)((kSym * z.off) & 3);
+    const float* pl = region + shift;
     double x[L::R], r64[L::R];
     double bb;
-    pack_start<L, true>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, pl);
+    pack_start<L, true>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift);
     float S[L::R][kStencil], dinv[L::R];
     planes_copy_wait();
     const LdsPlanes<L> plv(pl, z);
@@ -643,7 +679,8 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
     }
     // every wave has its stencil: the planes buffer takes the low parts next
     lds_barrier();
-    if (z.live) planes_copy_start<L>(A.Sslo + kSym * z.off, pl, z.lt);
+    if (z.live) planes_copy_start<L>(A.Sslo + kSym * z.off, region, z.lt, shift);
+    prefetch();
     const RegStencil<L, float> SR{S};
     const SplitStencil<L> S64{S, plv};
     if (A.rhs_vec == nullptr) {
@@ -782,16 +819,58 @@ __device__ void pack_refine(const MicroArgs& A, const PackList& P, int task, int
 // FP32 planes buffer of the refinement (one pack's instances), in LDS, with
 // room for the reads past the last instance's planes (LdsPlanes).
 constexpr int kPlaneFloats =
-    cmax(cmax(L16::IPP * kSym * L16::n, L32::IPP * kSym * L32::n), L64::IPP * kSym * L64::n) + 2 * (kMaxLevel + 1);
+    cmax(cmax(L16::IPP * L16::PS, L32::IPP * L32::PS), L64::IPP * L64::PS) + 2 * (kMaxLevel + 1);
 
-// Reduction buffers of one packed workgroup.
+// Reduction buffers and pack metadata of one packed workgroup.
 struct PackShared {
     double r1[2][NWP][4];
     double r2[2][NWP][4];
     double r3[2][NWP][4];
     float f3[2][NWP][4];
+    int32_t meta[2][kMetaWords];   // this pack's and the next one's
     int task;
 };
+
+// The work loop of a packed workgroup.  With a queue, packs are popped one
+// ahead: while pack t is solved, the first wave pops the next pack and copies
+// its metadata into the other half of sh.meta (the solve calls prefetch()
+// once it has its own data in flight), so that the next solve starts from
+// LDS instead of three dependent global round trips.  Without a queue the
+// workgroup solves pack blockIdx.x.  solve(meta, cnt, level, prefetch).
+template <class Solve>
+__device__ __forceinline__ void pack_loop(const MicroArgs& A, const PackList& P, const int32_t* pack_level,
+                                          PackShared& sh, Solve solve) {
+    int task;
+    if (A.queue != nullptr) {
+        if (threadIdx.x == 0) sh.task = atomicAdd(A.queue, 1);
+        __syncthreads();
+        task = sh.task;
+    } else {
+        task = blockIdx.x;
+    }
+    if (task < P.n_packs && threadIdx.x < kWave) meta_copy_start(P, pack_level, task, sh.meta[0]);
+    planes_copy_wait();
+    int buf = 0;
+    while (task < P.n_packs) {
+        int nxt = P.n_packs;
+        if (A.queue != nullptr && threadIdx.x == 0) nxt = atomicAdd(A.queue, 1);
+        const int32_t* meta = sh.meta[buf];
+        int32_t* meta_next = sh.meta[buf ^ 1];
+        auto prefetch = [&]() {
+            if (A.queue != nullptr && threadIdx.x < kWave) {
+                const int n = __builtin_amdgcn_readfirstlane(nxt);
+                if (threadIdx.x == 0) sh.task = n;
+                if (n < P.n_packs) meta_copy_start(P, pack_level, n, meta_next);
+            }
+        };
+        solve(meta, meta[kMetaCount], meta[kMetaLevel], prefetch);
+        if (A.queue == nullptr) break;
+        planes_copy_wait();     // the next pack's metadata has landed
+        task = sh.task;
+        buf ^= 1;
+        __syncthreads();        // every wave has read sh.task before it is rewritten
+    }
+}
 
 // MODE: 1 FP64, 2 refine.  One instantiation per mesh size (LV), so each
 // gets its own register allocation.
@@ -803,24 +882,15 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
     PackRed<2, double> red2(sh.r2);
     PackRed<3, double> red3(sh.r3);
     PackRed<2, float> rf2(sh.f3);
-    int task = blockIdx.x;
-    for (;;) {
-        if (A.queue != nullptr) {
-            if (threadIdx.x == 0) sh.task = atomicAdd(A.queue, 1);
-            __syncthreads();
-            task = sh.task;
-            __syncthreads();
-        }
-        if (task >= P.n_packs) break;
-        const int cnt = P.count[task];
-        if constexpr (MODE == 2) {
-            __shared__ float planes[kSym * L::n * L::IPP + 2 * L::NP];
-            pack_refine<L>(A, P, task, cnt, lds, planes, red1, red3, rf2);
-        } else {
-            pack_fp64<L>(A, P, task, cnt, lds, red1, red2, red3);
-        }
-        if (A.queue == nullptr) break;
-        __syncthreads();
+    if constexpr (MODE == 2) {
+        __shared__ __attribute__((aligned(16))) float planes[L::PS * L::IPP + 2 * L::NP];
+        pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
+            pack_refine<L>(A, meta, cnt, lds, planes, red1, red3, rf2, prefetch);
+        });
+    } else {
+        pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
+            pack_fp64<L>(A, meta, cnt, lds, red1, red2, red3, prefetch);
+        });
     }
 }
 
@@ -835,24 +905,19 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
     PackRed<2, double> red2(sh.r2);
     PackRed<3, double> red3(sh.r3);
     PackRed<2, float> rf2(sh.f3);
-    for (;;) {
-        if (threadIdx.x == 0) sh.task = atomicAdd(A.queue, 1);
-        __syncthreads();
-        const int task = sh.task;
-        __syncthreads();
-        if (task >= P.n_packs) break;
-        const int lvl = pack_level[task], cnt = P.count[task];
-        if constexpr (MODE == 2) {
-            __shared__ float planes[kPlaneFloats];
-            if (lvl == 64) pack_refine<L64>(A, P, task, cnt, lds, planes, red1, red3, rf2);
-            else if (lvl == 32) pack_refine<L32>(A, P, task, cnt, lds, planes, red1, red3, rf2);
-            else pack_refine<L16>(A, P, task, cnt, lds, planes, red1, red3, rf2);
-        } else {
-            if (lvl == 64) pack_fp64<L64>(A, P, task, cnt, lds, red1, red2, red3);
-            else if (lvl == 32) pack_fp64<L32>(A, P, task, cnt, lds, red1, red2, red3);
-            else pack_fp64<L16>(A, P, task, cnt, lds, red1, red2, red3);
-        }
-        __syncthreads();
+    if constexpr (MODE == 2) {
+        __shared__ __attribute__((aligned(16))) float planes[kPlaneFloats];
+        pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
+            if (lvl == 64) pack_refine<L64>(A, meta, cnt, lds, planes, red1, red3, rf2, prefetch);
+            else if (lvl == 32) pack_refine<L32>(A, meta, cnt, lds, planes, red1, red3, rf2, prefetch);
+            else pack_refine<L16>(A, meta, cnt, lds, planes, red1, red3, rf2, prefetch);
+        });
+    } else {
+        pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
+            if (lvl == 64) pack_fp64<L64>(A, meta, cnt, lds, red1, red2, red3, prefetch);
+            else if (lvl == 32) pack_fp64<L32>(A, meta, cnt, lds, red1, red2, red3, prefetch);
+            else pack_fp64<L16>(A, meta, cnt, lds, red1, red2, red3, prefetch);
+        });
     }
 }
 
