@@ -64,6 +64,7 @@ struct tsm_ctx {
     int32_t* pk_slot_inst = nullptr;
     int64_t* pk_slot_off = nullptr;
     size_t pack_lds_max = 0;
+    int64_t n_packed_tasks = 0;
     int n_cu = 0;
 
     // per instance
@@ -172,11 +173,14 @@ namespace {
 // generic launch per remaining slot class.  setup: FP64 whatever the precision.
 tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
     const bool refine = c->prm.precision == TSM_FP32_REFINE && !setup;
+    // the packed kernels leave b^T x to one boundary pass over their instances
+    MicroArgs pbase = base;
+    pbase.bx_out = nullptr;
     if ((c->prm.flags & TSM_FLAG_PERSISTENT) && c->n_packs > 0) {
         // one persistent launch over every pack; the queue is reset by a
         // kernel so the sequence can be captured in a graph
         PackList pl{c->n_packs, c->pk_first, c->pk_count, c->pk_slot_inst, c->pk_slot_off};
-        MicroArgs a = base;
+        MicroArgs a = pbase;
         a.n_tasks = (int)c->n_inst;
         a.order = c->order;
         a.order_off = c->order_off;
@@ -191,13 +195,16 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
         for (const auto& pg : c->pack_groups) {
             PackList pl{pg[2], c->pk_first + pg[1], c->pk_count + pg[1], c->pk_slot_inst + (int64_t)pg[1] * kPackSlots,
                         c->pk_slot_off + (int64_t)pg[1] * kPackSlots};
-            MicroArgs a = base;
+            MicroArgs a = pbase;
             a.n_tasks = (int)c->n_inst;
             a.order = c->order;
             a.order_off = c->order_off;
             HIPCHK(launch_packed(a, pl, pg[0], refine ? 2 : 1, pg[2], c->stream));
         }
     }
+    if (c->n_packs > 0 && base.bx_out != nullptr)
+        HIPCHK(launch_bdot_boundary((int)c->n_packed_tasks, c->order, c->level, c->offsets, c->b, base.X_out,
+                                    base.bx_out, c->stream));
     for (const Group& g : c->groups) {
         MicroArgs a = base;
         a.n_tasks = g.count;
@@ -253,6 +260,7 @@ tsm_status plan_tasks(tsm_ctx* c) {
         t += cnt;
     }
     c->n_packs = (int)pf.size();
+    c->n_packed_tasks = t;     // the packed instances are order[0, t)
     c->groups.clear();
     const bool refine = c->prm.precision == TSM_FP32_REFINE;
     const bool stream_all = (c->prm.flags & TSM_FLAG_STENCIL_STREAM) != 0;

@@ -419,6 +419,34 @@ __global__ __launch_bounds__(NT) void bdot_kernel(const int64_t* offsets, const 
     if (threadIdx.x == 0) out[inst] = v[0];
 }
 
+// b_i^T x_i over the boundary nodes only (b is the boundary load B 1, zero at
+// every interior node): one wave per task, 4N nodes per N x N instance.
+constexpr int kBdotWaves = 4;
+__global__ __launch_bounds__(kBdotWaves * kWave) void bdot_boundary_kernel(int n_tasks, const int32_t* order,
+                                                                           const int32_t* level,
+                                                                           const int64_t* offsets, const double* b,
+                                                                           const double* x, double* out) {
+    const int t = blockIdx.x * kBdotWaves + (int)(threadIdx.x / kWave);
+    if (t >= n_tasks) return;                // whole waves leave together
+    const int lane = threadIdx.x & (kWave - 1);
+    const int inst = order[t];
+    const int N = level[inst], NP = N + 1;
+    const int64_t off = offsets[inst];
+    double v = 0.0;
+    for (int k = lane; k < 4 * N; k += kWave) {
+        // bottom row (NP nodes), top row (NP), then the interior rows' first
+        // and last columns (N-1 each)
+        int j;
+        if (k < NP) j = k;
+        else if (k < 2 * NP) j = N * NP + (k - NP);
+        else if (k < 2 * NP + N - 1) j = (k - 2 * NP + 1) * NP;
+        else j = (k - 2 * NP - N + 2) * NP + N;
+        v += b[off + j] * x[off + j];
+    }
+    v = wave_total_last(v);
+    if (lane == kWave - 1) out[inst] = v;
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -448,6 +476,14 @@ hipError_t launch_bdot(int n_inst, const int64_t* offsets, const double* b, cons
                        hipStream_t s) {
     if (n_inst <= 0) return hipSuccess;
     hipLaunchKernelGGL(bdot_kernel, dim3(n_inst), dim3(NT), 0, s, offsets, b, x, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bdot_boundary(int n_tasks, const int32_t* order, const int32_t* level, const int64_t* offsets,
+                                const double* b, const double* x, double* out, hipStream_t s) {
+    if (n_tasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bdot_boundary_kernel, dim3((n_tasks + kBdotWaves - 1) / kBdotWaves), dim3(kBdotWaves * kWave),
+                       0, s, n_tasks, order, level, offsets, b, x, out);
     return hipGetLastError();
 }
 

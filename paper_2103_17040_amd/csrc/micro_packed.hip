@@ -479,21 +479,25 @@ __device__ __forceinline__ void strip_apply_lean(const ST& S0, const TG* g, cons
     }
 }
 
+// x to X_out and the per-instance results.  b^T x (the flux) only when
+// A.bx_out is set: the step leaves it to a boundary-only pass after the
+// launch (b vanishes in the interior), which spares the b loads and a
+// reduction at the end of every solve.
 template <class L>
 __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, const double (&x)[L::R],
                                            int iters, int sweeps, bool conv, double rr, PackRed<1, double>& red1) {
-    double bx[1] = {0.0};
 #pragma unroll
-    for (int i = 0; i < L::R; ++i) {
-        if (row_ok<L>(z, i)) {
-            const int j = node_of<L>(z, i);
-            A.X_out[z.off + j] = x[i];
-            bx[0] += A.b[z.off + j] * x[i];
-        }
+    for (int i = 0; i < L::R; ++i)
+        if (row_ok<L>(z, i)) A.X_out[z.off + node_of<L>(z, i)] = x[i];
+    double bx[1] = {0.0};
+    if (A.bx_out != nullptr) {
+#pragma unroll
+        for (int i = 0; i < L::R; ++i)
+            if (row_ok<L>(z, i)) bx[0] += A.b[z.off + node_of<L>(z, i)] * x[i];
+        red1.sum<L>(bx, z.w0);
     }
-    red1.sum<L>(bx, z.w0);
     if (z.live && z.lt == 0) {
-        A.bx_out[z.inst] = bx[0];
+        if (A.bx_out != nullptr) A.bx_out[z.inst] = bx[0];
         if (A.iters_out) A.iters_out[z.inst] = iters;
         if (A.sweeps_out) A.sweeps_out[z.inst] = sweeps;
         if (A.res_out) A.res_out[z.inst] = sqrt(rr);

@@ -117,7 +117,7 @@ struct MicroArgs {
     double* res_out;           // optional: final FP64 residual norm ||rhs - S x||_2 per instance
     int zero_init;
     double* X_out;
-    double* bx_out;
+    double* bx_out;       // b_i^T x_i per instance (packed kernels: null, a separate boundary pass)
     int32_t* iters_out;
     int32_t* sweeps_out;
     int32_t* nonconv;     // device counter, incremented by instances that miss rtol
@@ -171,6 +171,10 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int n, hipStream_t s);
 // out_i = b_i^T x_i for every instance
 hipError_t launch_bdot(int n_inst, const int64_t* offsets, const double* b, const double* x, double* out,
                        hipStream_t s);
+// out[order[t]] = b^T x over the boundary nodes of instance order[t], t < n_tasks
+// (b vanishes at interior nodes)
+hipError_t launch_bdot_boundary(int n_tasks, const int32_t* order, const int32_t* level, const int64_t* offsets,
+                                const double* b, const double* x, double* out, hipStream_t s);
 // residual sum of the alternating coupling: out[0] = ||R||_2 (nR interior macro rows),
 // out[1] = mean over instances of res (per-instance micro residual norms)
 hipError_t launch_coupling_residual(int nR, const double* R, int n_inst, const double* res, double* out,
