@@ -743,21 +743,25 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
         float gam_prev = 1.0f, alpha_prev = 1.0f;
         bool iconv = !me;
         int k = 0;
-        for (;;) {
-            float u[L::R], w[L::R];
+        // One iteration, from the direction pair (pi, si) to (po, so): u and
+        // w are formed in po and so, which then become the new p and s.  Two
+        // iterations per loop trip with the pairs swapped, so the new p and s
+        // are never copied back into the old registers.  True: stop.
+        auto iterate = [&](const float (&pi)[L::R], const float (&si)[L::R], float (&po)[L::R],
+                           float (&so)[L::R]) -> bool {
 #pragma unroll
-            for (int i = 0; i < L::R; ++i) u[i] = dinv[i] * r[i];
-            strip_store<L>(pg, z, u);
+            for (int i = 0; i < L::R; ++i) po[i] = dinv[i] * r[i];     // u
+            strip_store<L>(pg, z, po);
             lds_barrier();
             // every lane applies (no branch): the reads of inactive and spare
             // lanes stay inside the LDS block, rows past the mesh give 0, and
             // spare waves never enter a sum
-            strip_apply<L, L::R>(SR, pg, z, u, w);
+            strip_apply<L, L::R>(SR, pg, z, po, so);                    // w = S u
             float g2[2] = {0.0f, 0.0f};     // (w,u), (r,u)
 #pragma unroll
             for (int i = 0; i < L::R; ++i) {
-                g2[0] += w[i] * u[i];
-                g2[1] += r[i] * u[i];
+                g2[0] += so[i] * po[i];
+                g2[1] += r[i] * po[i];
             }
             rf2.sum<L>(g2, z.w0);
             if (k == 0) {
@@ -765,17 +769,17 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
                 vthr = (ithr < INFINITY) ? ithr * rf2.tail : ithr;
             }
             if (!iconv && g2[1] <= itol2 * gam0) iconv = true;
-            if (!rf2.any_above(vthr) || k >= A.max_iter) break;
+            if (!rf2.any_above(vthr) || k >= A.max_iter) return true;
             const float gam = g2[1];
             const float beta = (k == 0 || iconv) ? 0.0f : gam * __builtin_amdgcn_rcpf(gam_prev);
             const float den = (k == 0) ? g2[0] : g2[0] - beta * gam * __builtin_amdgcn_rcpf(alpha_prev);
             const float alpha = iconv ? 0.0f : gam * __builtin_amdgcn_rcpf(den);
 #pragma unroll
             for (int i = 0; i < L::R; ++i) {
-                p[i] = u[i] + beta * p[i];
-                sv[i] = w[i] + beta * sv[i];
-                d[i] += alpha * p[i];
-                r[i] -= alpha * sv[i];
+                po[i] = po[i] + beta * pi[i];     // p = u + beta p
+                so[i] = so[i] + beta * si[i];     // s = w + beta s
+                d[i] += alpha * po[i];
+                r[i] -= alpha * so[i];
             }
             if (!iconv) {
                 gam_prev = gam;
@@ -783,6 +787,12 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
                 ++iters;
             }
             ++k;
+            return false;
+        };
+        float p2[L::R], sv2[L::R];
+        for (;;) {
+            if (iterate(p, sv, p2, sv2)) break;
+            if (iterate(p2, sv2, p, sv)) break;
         }
         // x += ||r|| d;  r64 -= ||r|| S d  (FP64 stencil, d exact in FP64)
         const double sc = me ? rn : 0.0;
