@@ -95,10 +95,8 @@ struct tsm_ctx {
            *resn = nullptr, *fpm = nullptr;
     int fp_iters_last = 0, fp_iters_max = 0;
 
-    // adjoint: amplitude-derivative operators and work vectors (first tsm_gradient)
-    double *dS64 = nullptr, *dM64 = nullptr, *db = nullptr, *dlen = nullptr, *jmin_d = nullptr;
+    // adjoint work vectors (first tsm_gradient)
     double *lam0 = nullptr, *mu = nullptr, *coef = nullptr, *grad = nullptr, *Jd = nullptr;
-    bool have_deriv = false;
     double grad_fwd_ms = 0.0, grad_bwd_ms = 0.0;
 
     bool have_mesh = false, have_geom = false, have_state = false;
@@ -122,9 +120,7 @@ struct tsm_ctx {
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32); dfree(Slo);
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
-        dfree(dS64); dfree(dM64); dfree(db); dfree(dlen); dfree(jmin_d);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
-        have_deriv = false;
         drop_graph();
         have_mesh = have_geom = have_state = false;
     }
@@ -740,7 +736,6 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
     if (!finite_all(ah) || !finite_all(th)) return c->fail(TSM_EINVAL, "non-finite deformation parameter");
     c->have_geom = false;
     c->have_state = false;
-    c->have_deriv = false;
     c->geom_tables = false;
     c->drop_graph();
     HIPCHK(hipMemcpyAsync(c->amp, a, n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -785,7 +780,6 @@ tsm_status tsm_set_jacobians(tsm_ctx* c, const double* Fcell, int64_t n_cell, co
     HIPCHK(hipDeviceSynchronize());   // caller's producers of the tables
     c->have_geom = false;
     c->have_state = false;
-    c->have_deriv = false;
     c->drop_graph();
     if (!c->cell_off) HIPALLOC(c->cell_off, n_inst);
     if (!c->bnd_off) HIPALLOC(c->bnd_off, n_inst);
@@ -946,26 +940,10 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
     const int N = n_steps, K = c->prm.checkpoint_every;
     const int nseg = (N + K - 1) / K;
     HIPCHK(hipDeviceSynchronize());
-    // --- amplitude-derivative operators, once per deformation
-    if (!c->have_deriv) {
-        if (!c->dS64) {
-            HIPALLOC(c->dS64, kStencil * tot); HIPALLOC(c->dM64, kStencil * tot); HIPALLOC(c->db, tot);
-            HIPALLOC(c->dlen, ni); HIPALLOC(c->jmin_d, ni);
-            HIPALLOC(c->lam0, tot); HIPALLOC(c->mu, ni); HIPALLOC(c->coef, ni); HIPALLOC(c->grad, ni);
-            HIPALLOC(c->Jd, 1);
-        }
-        AssembleArgs as{};
-        as.n_inst = (int)ni;
-        as.level = c->level;
-        as.offsets = c->offsets;
-        as.amp = c->amp;
-        as.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
-        as.d = c->prm.d;
-        as.kappa = c->prm.kappa;
-        as.inv_dt = 1.0 / c->prm.dt;
-        as.S64 = c->dS64; as.M64 = c->dM64; as.b = c->db; as.len = c->dlen; as.jmin = c->jmin_d;
-        HIPCHK(launch_assemble_da(as, c->stream));
-        c->have_deriv = true;
+    // --- adjoint state (the derivative forms are evaluated matrix-free)
+    if (!c->lam0) {
+        HIPALLOC(c->lam0, tot); HIPALLOC(c->mu, ni); HIPALLOC(c->coef, ni); HIPALLOC(c->grad, ni);
+        HIPALLOC(c->Jd, 1);
     }
     // --- work buffers of this call
     double *U = nullptr, *ck_u = nullptr, *ck_v = nullptr, *V = nullptr, *save_u = nullptr, *save_v = nullptr,
@@ -1044,7 +1022,10 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
                 ga.NM = c->NM;
                 ga.level = c->level;
                 ga.offsets = c->offsets;
-                ga.dS = c->dS64; ga.dM = c->dM64; ga.db = c->db; ga.dlen = c->dlen; ga.b = c->b; ga.len = c->len;
+                ga.amp = c->amp;
+                ga.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
+                ga.len = c->len;
+                ga.d = c->prm.d;
                 ga.lam0 = c->lam0; ga.coef = c->coef; ga.w = c->w;
                 ga.v_now = V + (size_t)(mstep - a) * tot;
                 ga.v_prev = V + (size_t)(mstep - a - 1) * tot;

@@ -8,7 +8,7 @@
 // (at most two) boundary edges at j, with the 2-point rule, the row of
 //     B_i = int_dZ eta eta |cof(F) nu|      (boundary change of variables).
 // Each node gathers its own row -- no atomics, fixed summation order.
-// Besides the full rows (generic kernels, adjoint) it stores the upper half
+// Besides the full rows (generic kernels) it stores the upper half
 // of S, of K = d A + kappa B and of M (FP32) as symmetric planes for the
 // packed kernels.
 // K K^T J and |cof F nu| are evaluated at each point from the amplitude a_i
@@ -21,15 +21,12 @@ namespace tsm {
 namespace {
 
 // MODE 0: the sinusoidal family from the amplitude a_i.
-// MODE 1: the amplitude derivatives dS/da, dM/da and db/da instead
-//   (F = I + a G: dJ = G11 M22 + M11 G22 - G12 M21 - M12 G21,
-//    dC = d[adj(M) adj(M)^T]/da / J - C dJ / J,  d|M tau| = (M tau).(G tau) / |M tau|).
 // MODE 2: a general map given by its Jacobian F at every quadrature point
 //   (the paper caches J and K K^T J per quadrature point; here the caller
 //   supplies F and the same formulas give J, C and |F tau|).
 template <int MODE>
 __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A) {
-    constexpr bool DERIV = MODE == 1, TAB = MODE == 2;
+    constexpr bool TAB = MODE == 2;
     __shared__ double red_s[2][1][kMicroThreads / kWave];
     __shared__ double mins[kMicroThreads / kWave];
     BlockReducer<kMicroThreads / kWave, 1, double> red(red_s);
@@ -82,7 +79,6 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                             P = pullback_at(a, ys[t1], ys[t2], ss[t1], cs[t1], ss[t2], cs[t2]);
                         }
                         jmin = fmin(jmin, P.J);
-                        if constexpr (DERIV) P = pullback_da_at(a, ys[t1], ys[t2], ss[t1], cs[t1], ss[t2], cs[t2]);
                         // basis of local node (l1,l2) and its reference gradient
                         const double f1 = lin(l1, g1), f2 = lin(l2, g2);
                         const double phl = f1 * f2;
@@ -132,7 +128,6 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     }
                     double om = sqrt(M11 * M11 + M21 * M21);
                     if constexpr (TAB) bad |= !isfinite(om);
-                    if constexpr (DERIV) om = (M11 * cs[t1] * yf + M21 * ss[tf]) / om;
                     for (int m1 = 0; m1 < 2; ++m1) {
                         const double v = wb * om * lin(l1, g) * lin(m1, g);
                         S[3 + (m1 - l1 + 1)] += A.kappa * v;
@@ -163,7 +158,6 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     }
                     double om = sqrt(M12 * M12 + M22 * M22);
                     if constexpr (TAB) bad |= !isfinite(om);
-                    if constexpr (DERIV) om = (M12 * ss[tf] + M22 * cs[t2] * yf) / om;
                     for (int m2 = 0; m2 < 2; ++m2) {
                         const double v = wb * om * lin(l2, g) * lin(m2, g);
                         S[(m2 - l2 + 1) * 3 + 1] += A.kappa * v;
@@ -179,24 +173,20 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
         for (int k = 0; k < kStencil; ++k) {
             Sd[(int64_t)k * n + j] = S[k];
             Md[(int64_t)k * n + j] = M[k];
-            if constexpr (!DERIV) {
-                const float hi = (float)S[k];
-                A.S32[kStencil * off + (int64_t)k * n + j] = hi;
-                A.Slo[kStencil * off + (int64_t)k * n + j] = (float)(S[k] - (double)hi);
-            }
+            const float hi = (float)S[k];
+            A.S32[kStencil * off + (int64_t)k * n + j] = hi;
+            A.Slo[kStencil * off + (int64_t)k * n + j] = (float)(S[k] - (double)hi);
         }
-        if constexpr (!DERIV) {
 #pragma unroll
-            for (int q = 0; q < kSym; ++q) {
-                const int k = 4 + q;
-                const int64_t e = kSym * off + (int64_t)q * n + j;
-                const float hi = (float)S[k];
-                A.Ss64[e] = S[k];
-                A.Ks64[e] = K[k];
-                A.Ms32[e] = (float)M[k];
-                A.Ss32[e] = hi;
-                A.Sslo[e] = (float)(S[k] - (double)hi);
-            }
+        for (int q = 0; q < kSym; ++q) {
+            const int k = 4 + q;
+            const int64_t e = kSym * off + (int64_t)q * n + j;
+            const float hi = (float)S[k];
+            A.Ss64[e] = S[k];
+            A.Ks64[e] = K[k];
+            A.Ms32[e] = (float)M[k];
+            A.Ss32[e] = hi;
+            A.Sslo[e] = (float)(S[k] - (double)hi);
         }
         A.b[off + j] = bj;
         len_part += bj;
@@ -229,12 +219,6 @@ hipError_t launch_assemble_tables(const AssembleArgs& a, hipStream_t s) {
     if (a.Fcell == nullptr || a.Fbnd == nullptr || a.cell_off == nullptr || a.bnd_off == nullptr)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(assemble_kernel<2>, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_assemble_da(const AssembleArgs& a, hipStream_t s) {
-    if (a.n_inst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(assemble_kernel<1>, dim3(a.n_inst), dim3(kMicroThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -153,8 +153,6 @@ struct MacroArgs {
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s);
-// same gather with the amplitude derivatives: S64 <- dS/da, M64 <- dM/da, b <- db/da, len <- 1^T db
-hipError_t launch_assemble_da(const AssembleArgs& a, hipStream_t s);
 // same gather for maps given by their Jacobian tables (a.Fcell, a.Fbnd)
 hipError_t launch_assemble_tables(const AssembleArgs& a, hipStream_t s);
 hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_t lds_bytes, hipStream_t s);
@@ -195,15 +193,18 @@ hipError_t launch_adjoint_coef(const MacroArgs& m, const double* mu, double* coe
 // Gradient contribution of one adjoint step m (one workgroup per instance):
 //   g_i -= lam_i^T (dS_i v_i^m - kappa p u_i^m db_i - dM_i v_i^{m-1} / dt)
 //          - sign mu_i L_ii dF_i,   dF_i = -kappa (db_i^T v_i^m / |dY_i| - (b_i^T v_i^m) d|dY_i| / |dY_i|^2)
-// with lam_i = lam0_i + coef_i w_i.
+// with lam_i = lam0_i + coef_i w_i; the derivative forms are evaluated
+// matrix-free from the amplitudes and the quadrature tables.
 struct GradArgs {
     int n_inst, NM;
     const int32_t* level;
     const int64_t* offsets;
-    const double *dS, *dM, *db, *dlen, *b, *len;
+    const double* amp;
+    Tables tab;
+    const double* len;
     const double *lam0, *coef, *w;
     const double *v_now, *v_prev, *u_now, *mu;
-    double kappa, p, sign, inv_dt;
+    double d, kappa, p, sign, inv_dt;
     double* g;
 };
 hipError_t launch_gradient_step(const GradArgs& a, hipStream_t s);
