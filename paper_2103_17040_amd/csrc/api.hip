@@ -77,6 +77,7 @@ struct tsm_ctx {
            *alpha = nullptr, *F = nullptr, *u = nullptr;
     // ragged
     double *S64 = nullptr, *M64 = nullptr, *b = nullptr, *w = nullptr, *v0 = nullptr;
+    double* Mw = nullptr;          // M_i w_i (packed step solves start from v0)
     float *S32 = nullptr, *Slo = nullptr;
     // symmetric upper-half planes [kSym][n] of S, K = S - M/dt, M (FP32), S split in FP32
     double *Ss64 = nullptr, *Ks64 = nullptr;
@@ -117,7 +118,7 @@ struct tsm_ctx {
         geom_tables = false;
         dfree(Ss64); dfree(Ks64); dfree(Ms32); dfree(Ss32); dfree(Sslo);
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
-        dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(v0); dfree(S32); dfree(Slo);
+        dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(Mw); dfree(v0); dfree(S32); dfree(Slo);
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
@@ -357,6 +358,7 @@ tsm_status enqueue_step(tsm_ctx* c, const hipEvent_t* ev = nullptr) {
     MicroArgs a = micro_base(c);
     a.X0 = c->v0;
     a.coef = c->u;
+    a.Mw = c->Mw;
     a.rhs_vec = nullptr;
     a.zero_init = 0;
     a.X_out = c->v0;
@@ -591,7 +593,7 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPCHK(hipMemset(c->Ms32 + pe, 0, kPlanePad * sizeof(float)));
     HIPCHK(hipMemset(c->Ss32 + pe, 0, kPlanePad * sizeof(float)));
     HIPCHK(hipMemset(c->Sslo + pe, 0, kPlanePad * sizeof(float)));
-    HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot);
+    HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot); HIPALLOC(c->Mw, tot);
     HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());
     HIPCHK(hipMemcpy(c->level, c->level_h.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -656,6 +658,10 @@ tsm_status finish_setup(tsm_ctx* c, std::chrono::steady_clock::time_point t0, Wh
     ma.max_iter = std::max(c->prm.max_iter, 50000);   // setup must converge whatever the step budget
     tsm_status st = enqueue_micro(c, ma, true);
     if (st != TSM_OK) return st;
+    // M w, so that the packed step solves can start from v0 alone (the
+    // homogeneous part changes by O(dt) per step; v = v0 + u w does not
+    // settle while u does)
+    HIPCHK(launch_apply((int)n_inst, c->level, c->offsets, c->M64, c->w, c->Mw, c->stream));
     HIPCHK(launch_beta((int)n_inst, c->prm.kappa, c->prm.p, c->len, c->bx, c->beta, c->stream));
     {
         std::vector<double> kp_h(n_inst, c->prm.kappa * c->prm.p);
@@ -1007,6 +1013,7 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
                 MicroArgs ma = micro_base(c);
                 ma.X0 = c->lam0;
                 ma.coef = c->coef;
+                ma.Mw = c->Mw;
                 ma.rhs_vec = nullptr;
                 ma.zero_init = 0;
                 ma.X_out = c->lam0;

@@ -509,6 +509,8 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
 // partial ||b||^2:
 //   given right-hand side:  b = rhs_scale rhs [+ rhs_bscale c_i b_i],  r = b - S x0
 //   time step:              b = M x0 / dt,      r = b - S x0 = -K x0
+//   time step with Mw:      the iterate starts from y0 = X0 (x0 = y0 + coef w)
+//                           and r = b - S y0 = -K y0 + coef M w / dt
 // (K = S - M/dt is stored on its own, so the residual carries no
 // cancellation; M, in FP32, only sizes ||b||).
 // NORM_LATER: the time-step form leaves ||b||^2 to the caller (bb = 0), which
@@ -524,14 +526,24 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
                                            float* copy_dst = nullptr, int copy_shift = 0) {
     zero_halo<L, double>(xg, z);
     const double cf = (z.live && A.coef != nullptr) ? A.coef[z.inst] : 0.0;
+    // time step with M w: start from X0 alone; the right-hand side keeps
+    // coef w through cm[i] = coef (M w)_j / dt
+    const bool use_mw = A.rhs_vec == nullptr && A.Mw != nullptr && !A.zero_init;
+    double cm[L::R];
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
-        double v = 0.0;
+        double v = 0.0, m = 0.0;
         if (row_ok<L>(z, i) && !A.zero_init) {
             const int j = node_of<L>(z, i);
-            v = A.X0[z.off + j] + cf * A.w[z.off + j];
+            if (use_mw) {
+                v = A.X0[z.off + j];
+                m = cf * A.inv_dt * A.Mw[z.off + j];
+            } else {
+                v = A.X0[z.off + j] + cf * A.w[z.off + j];
+            }
         }
         x[i] = v;
+        cm[i] = m;
     }
     strip_store<L>(xg, z, x);
     __syncthreads();
@@ -564,8 +576,8 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
         }
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
-            r[i] = -sx[i];
-            const double bi = b[i] * A.inv_dt;
+            r[i] = cm[i] - sx[i];
+            const double bi = b[i] * A.inv_dt + cm[i];
             if constexpr (!NORM_LATER) bb += bi * bi;
         }
     }

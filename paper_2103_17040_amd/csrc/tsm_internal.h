@@ -89,7 +89,8 @@ struct AssembleArgs {
 // One batched micro solve: for every task t, instance i = order[t] solves
 //   S_i x = rhs_i,   rhs_i = rhs_scale * rhs_vec_i [+ rhs_bscale * rhs_bcoef_i * b_i]   (rhs_vec != null)
 //                    rhs_i = M_i x0_i / dt                (otherwise)
-// from the initial guess x0_i = X0_i + coef_i * w_i (zero if zero_init).
+// from the initial guess x0_i = X0_i + coef_i * w_i (zero if zero_init; X0_i
+// alone with Mw, see there).
 // Writes x to X_out and b_i^T x to bx_out[i].
 struct MicroArgs {
     int n_tasks;
@@ -112,6 +113,10 @@ struct MicroArgs {
     const double* coef;
     const double* rhs_vec;
     double rhs_scale;
+    // M_i w_i per node (packed kernels, time-step form, may be null): with it
+    // the iteration starts from X0 instead of X0 + coef w; the right-hand side
+    // is unchanged, M (X0 + coef w)/dt, so r = -K X0 + coef Mw / dt
+    const double* Mw;
     const double* rhs_bcoef;   // with rhs_vec: rhs_i += rhs_bscale * rhs_bcoef[i] * b_i (may be null)
     double rhs_bscale;
     double* res_out;           // optional: final FP64 residual norm ||rhs - S x||_2 per instance
