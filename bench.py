@@ -51,14 +51,15 @@ FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 33.0, 43.0   # (refine: S x0 replaces 
 # (algorithmic: the vectors of the iterations stay on chip; operators are read
 # from their symmetric upper-half planes, 5 coefficients per node):
 #   both forms: x0 = v0 + u w (read v0, w: 16), r = -K x0 (FP64 K, 40),
-#               write x and read b for the flux average (16)
+#               write x (8); b^T x for the flux average is a separate pass
+#               over the 4N boundary nodes (b and x: 16 B each, below 1 B
+#               per node of the mesh)
 #   refine:     the FP32 stencil once (20; it also gives ||b|| = ||S x0 + r||)
-#               and the FP32 low part of the stencil for the residual update
-#               after the first inner solve (20); later updates are within
-#               2^12 of the tolerance and use the FP32 stencil alone
+#               and the FP32 low part of the stencil, copied to LDS once per
+#               solve for the FP64 residual updates (20)
 #   FP64:       ||b|| = ||M x0||/dt (FP32 M, 20), the FP64 stencil once per
 #               PCG iteration (40) and its centre plane once for diag^{-1} (8)
-B_START, B_K, B_M32, B_END = 16.0, 40.0, 20.0, 16.0
+B_START, B_K, B_M32, B_END = 16.0, 40.0, 20.0, 8.0
 B_S64, B_DIAG, B_S32, B_SLO = 40.0, 8.0, 20.0, 20.0
 
 
@@ -78,9 +79,10 @@ def micro_bytes_per_dof(N, flags, refine, iters, sweeps):
     planes as above; generic kernel: full 9-coefficient rows, FP64 M for b,
     its stencil held in registers when the instance fits, else streamed)."""
     if packed_under(N, flags):
+        bdot = 16.0 * 4 * N / (N + 1) ** 2      # the boundary pass for b^T x
         if refine:
-            return B_START + B_K + B_S32 + B_SLO * min(max(sweeps - 1, 0), 1) + B_END
-        return B_START + B_K + B_M32 + B_DIAG + B_S64 * iters + B_END
+            return B_START + B_K + B_S32 + B_SLO + B_END + bdot
+        return B_START + B_K + B_M32 + B_DIAG + B_S64 * iters + B_END + bdot
     slots = next(s for s in GENERIC_SLOTS if s * 256 >= (N + 1) ** 2)
     if refine:   # FP32 stencil once (resident) or per inner iteration; FP64 rows per residual
         return 16 + 72 + 72 * sweeps + (36 if slots <= 9 else 36 * iters) + 16
