@@ -591,18 +591,26 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
                           PackRed<2, double>& red2, PackRed<3, double>& red3, Prefetch prefetch) {
     const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
-    const SymStencil<L, double> S{A.Ss64 + kSym * z.off};
     double x[L::R], r[L::R], p[L::R];
     float dinv[L::R];
     double bb;
     pack_start<L>(A, z, xg, x, r, bb);
     prefetch();
+    // the FP64 stencil of the lane's rows, resident in registers for the solve
+    double Sr[L::R][kStencil];
+    {
+        SymStencil<L, double> Sg{A.Ss64 + kSym * z.off};
+        Sg.prepare(z);
+#pragma unroll
+        for (int i = 0; i < L::R; ++i)
+#pragma unroll
+            for (int k = 0; k < kStencil; ++k) Sr[i][k] = (k == 1 && i > 0) ? Sr[i - 1][7] : Sg.load(z, i, k);
+    }
+    const RegStencil<L, double> S{Sr};
     double acc[3] = {bb, 0.0, 0.0};
-    SymStencil<L, double> Sd = S;
-    Sd.prepare(z);
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
-        dinv[i] = row_ok<L>(z, i) ? (float)(1.0 / Sd.load(z, i, 4)) : 0.0f;
+        dinv[i] = row_ok<L>(z, i) ? (float)(1.0 / Sr[i][4]) : 0.0f;
         p[i] = (double)dinv[i] * r[i];
         acc[1] += r[i] * p[i];
         acc[2] += r[i] * r[i];
@@ -625,7 +633,7 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
         double q[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) q[i] = 0.0;
-        if (z.act) strip_apply<L, 2>(S, xg, z, p, q);
+        if (z.act) strip_apply_lean<L, 1>(S, xg, z, p, q);
         double pq[1] = {0.0};
 #pragma unroll
         for (int i = 0; i < L::R; ++i) pq[0] += p[i] * q[i];
