@@ -586,9 +586,13 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
 // ------------------------------------------------------------------ FP64
 // meta: this pack's metadata in LDS; prefetch(): starts the copy of the next
 // pack's metadata (all waves call it once, early in the solve).
+// xs: LDS for the iterate, kFp64Rows slots per lane ([row][lane]): x is only
+// read and written once per iteration, so it waits there instead of holding
+// registers that the resident stencil needs.
 template <class L, class Prefetch>
-__device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, PackRed<1, double>& red1,
-                          PackRed<2, double>& red2, PackRed<3, double>& red3, Prefetch prefetch) {
+__device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, double* xs,
+                          PackRed<1, double>& red1, PackRed<2, double>& red2, PackRed<3, double>& red3,
+                          Prefetch prefetch) {
     const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     double x[L::R], r[L::R], p[L::R];
@@ -596,6 +600,8 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
     double bb;
     pack_start<L>(A, z, xg, x, r, bb);
     prefetch();
+#pragma unroll
+    for (int i = 0; i < L::R; ++i) xs[i * NTP + threadIdx.x] = x[i];
     // the FP64 stencil of the lane's rows, resident in registers for the solve
     double Sr[L::R][kStencil];
     {
@@ -642,7 +648,7 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
         double a2[2] = {0.0, 0.0};     // (r, D^-1 r), (r, r)
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
-            x[i] += alpha * p[i];
+            xs[i * NTP + threadIdx.x] += alpha * p[i];
             r[i] -= alpha * q[i];
             a2[0] += r[i] * (double)dinv[i] * r[i];
             a2[1] += r[i] * r[i];
@@ -663,6 +669,8 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
         }
         go = red2.any_above(thr);
     }
+#pragma unroll
+    for (int i = 0; i < L::R; ++i) x[i] = xs[i * NTP + threadIdx.x];
     pack_store<L>(A, z, x, it, 1, conv, rr, red1);
 }
 
@@ -850,6 +858,9 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
     pack_store<L>(A, z, x, iters, sweeps, conv, rr, red1);
 }
 
+// Iterate slots of the FP64 solves (xs of pack_fp64): the most rows per lane.
+constexpr int kFp64Rows = cmax(cmax(L16::R, L32::R), L64::R);
+
 // FP32 planes buffer of the refinement (one pack's instances), in LDS, with
 // room for the reads past the last instance's planes (LdsPlanes).
 constexpr int kPlaneFloats =
@@ -922,8 +933,9 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
             pack_refine<L>(A, meta, cnt, lds, planes, red1, red3, rf2, prefetch);
         });
     } else {
+        __shared__ double xs[L::R * NTP];
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_fp64<L>(A, meta, cnt, lds, red1, red2, red3, prefetch);
+            pack_fp64<L>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch);
         });
     }
 }
@@ -947,10 +959,11 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
             else pack_refine<L16>(A, meta, cnt, lds, planes, red1, red3, rf2, prefetch);
         });
     } else {
+        __shared__ double xs[kFp64Rows * NTP];
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
-            if (lvl == 64) pack_fp64<L64>(A, meta, cnt, lds, red1, red2, red3, prefetch);
-            else if (lvl == 32) pack_fp64<L32>(A, meta, cnt, lds, red1, red2, red3, prefetch);
-            else pack_fp64<L16>(A, meta, cnt, lds, red1, red2, red3, prefetch);
+            if (lvl == 64) pack_fp64<L64>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch);
+            else if (lvl == 32) pack_fp64<L32>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch);
+            else pack_fp64<L16>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch);
         });
     }
 }
