@@ -57,10 +57,10 @@ FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 33.0, 43.0   # (refine: S x0 replaces 
 #   refine:     the FP32 stencil once (20; it also gives ||b|| = ||S x0 + r||)
 #               and the FP32 low part of the stencil, copied to LDS once per
 #               solve for the FP64 residual updates (20)
-#   FP64:       ||b|| = ||M x0||/dt (FP32 M, 20), the FP64 stencil once per
-#               PCG iteration (40) and its centre plane once for diag^{-1} (8)
-B_START, B_K, B_M32, B_END = 16.0, 40.0, 20.0, 8.0
-B_S64, B_DIAG, B_S32, B_SLO = 40.0, 8.0, 20.0, 20.0
+#   FP64:       the FP64 stencil once, into registers for the whole solve
+#               (40; it also gives ||b|| = ||S x0 + r|| and diag^{-1})
+B_START, B_K, B_END = 16.0, 40.0, 8.0
+B_S64, B_S32, B_SLO = 40.0, 20.0, 20.0
 
 
 PACKED_LEVELS = (16, 32, 64)
@@ -82,7 +82,7 @@ def micro_bytes_per_dof(N, flags, refine, iters, sweeps):
         bdot = 16.0 * 4 * N / (N + 1) ** 2      # the boundary pass for b^T x
         if refine:
             return B_START + B_K + B_S32 + B_SLO + B_END + bdot
-        return B_START + B_K + B_M32 + B_DIAG + B_S64 * iters + B_END + bdot
+        return B_START + B_K + B_S64 + B_END + bdot
     slots = next(s for s in GENERIC_SLOTS if s * 256 >= (N + 1) ** 2)
     if refine:   # FP32 stencil once (resident) or per inner iteration; FP64 rows per residual
         return 16 + 72 + 72 * sweeps + (36 if slots <= 9 else 36 * iters) + 16

@@ -81,7 +81,7 @@ struct tsm_ctx {
     float *S32 = nullptr, *Slo = nullptr;
     // symmetric upper-half planes [kSym][n] of S, K = S - M/dt, M (FP32), S split in FP32
     double *Ss64 = nullptr, *Ks64 = nullptr;
-    float *Ms32 = nullptr, *Ss32 = nullptr, *Sslo = nullptr;
+    float *Ss32 = nullptr, *Sslo = nullptr;
     // tables
     int32_t* tab_off = nullptr;
     double *tab_y = nullptr, *tab_s = nullptr, *tab_c = nullptr;
@@ -116,7 +116,7 @@ struct tsm_ctx {
         dfree(level); dfree(order); dfree(order_off); dfree(iters); dfree(sweeps); dfree(offsets);
         dfree(cell_off); dfree(bnd_off);
         geom_tables = false;
-        dfree(Ss64); dfree(Ks64); dfree(Ms32); dfree(Ss32); dfree(Sslo);
+        dfree(Ss64); dfree(Ks64); dfree(Ss32); dfree(Sslo);
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(Mw); dfree(v0); dfree(S32); dfree(Slo);
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
@@ -314,7 +314,6 @@ MicroArgs micro_base(tsm_ctx* c) {
     a.M64 = c->M64;
     a.Ss64 = c->Ss64;
     a.Ks64 = c->Ks64;
-    a.Ms32 = c->Ms32;
     a.Ss32 = c->Ss32;
     a.Sslo = c->Sslo;
     a.b = c->b;
@@ -585,12 +584,11 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     // (the packed kernels read past an instance's block for strip rows past
     // its mesh and discard the products)
     const int64_t np = kSym * tot + kPlanePad;
-    HIPALLOC(c->Ss64, np); HIPALLOC(c->Ks64, np); HIPALLOC(c->Ms32, np);
+    HIPALLOC(c->Ss64, np); HIPALLOC(c->Ks64, np);
     HIPALLOC(c->Ss32, np); HIPALLOC(c->Sslo, np);
     const int64_t pe = kSym * tot;     // the assembly writes every entry before it
     HIPCHK(hipMemset(c->Ss64 + pe, 0, kPlanePad * sizeof(double)));
     HIPCHK(hipMemset(c->Ks64 + pe, 0, kPlanePad * sizeof(double)));
-    HIPCHK(hipMemset(c->Ms32 + pe, 0, kPlanePad * sizeof(float)));
     HIPCHK(hipMemset(c->Ss32 + pe, 0, kPlanePad * sizeof(float)));
     HIPCHK(hipMemset(c->Sslo + pe, 0, kPlanePad * sizeof(float)));
     HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot); HIPALLOC(c->Mw, tot);
@@ -756,7 +754,7 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
     as.kappa = c->prm.kappa;
     as.inv_dt = 1.0 / c->prm.dt;
     as.S64 = c->S64; as.S32 = c->S32; as.Slo = c->Slo; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
-    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ms32 = c->Ms32; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
+    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
     HIPCHK(launch_assemble(as, c->stream));
     return finish_setup(c, t0, [&](int64_t i) {
         char b[48];
@@ -803,7 +801,7 @@ tsm_status tsm_set_jacobians(tsm_ctx* c, const double* Fcell, int64_t n_cell, co
     as.kappa = c->prm.kappa;
     as.inv_dt = 1.0 / c->prm.dt;
     as.S64 = c->S64; as.S32 = c->S32; as.Slo = c->Slo; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
-    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ms32 = c->Ms32; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
+    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
     as.Fcell = Fcell; as.Fbnd = Fbnd; as.cell_off = c->cell_off; as.bnd_off = c->bnd_off;
     HIPCHK(launch_assemble_tables(as, c->stream));
     c->geom_tables = true;

@@ -184,7 +184,6 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
             const float hi = (float)S[k];
             A.Ss64[e] = S[k];
             A.Ks64[e] = K[k];
-            A.Ms32[e] = (float)M[k];
             A.Ss32[e] = hi;
             A.Sslo[e] = (float)(S[k] - (double)hi);
         }

@@ -505,22 +505,21 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
     }
 }
 
-// x0 into registers and the (double) grid, then the FP64 residual and the
-// partial ||b||^2:
-//   given right-hand side:  b = rhs_scale rhs [+ rhs_bscale c_i b_i],  r = b - S x0
+// x0 into registers and the (double) grid, then the FP64 residual:
+//   given right-hand side:  b = rhs_scale rhs [+ rhs_bscale c_i b_i],  r = b - S x0,
+//                           and the partial ||b||^2 in bb
 //   time step:              b = M x0 / dt,      r = b - S x0 = -K x0
 //   time step with Mw:      the iterate starts from y0 = X0 (x0 = y0 + coef w)
 //                           and r = b - S y0 = -K y0 + coef M w / dt
 // (K = S - M/dt is stored on its own, so the residual carries no
-// cancellation; M, in FP32, only sizes ||b||).
-// NORM_LATER: the time-step form leaves ||b||^2 to the caller (bb = 0), which
-// forms b = M x0/dt = S x0 + r from its register stencil instead of reading
-// M (the refinement solve; x0 stays in the double grid).
+// cancellation).  The time-step forms leave ||b||^2 to the caller (bb = 0),
+// which forms b = S y0 + r from its register stencil (y0 stays in the
+// double grid) instead of reading M.
 // copy_src/copy_dst (non-null): start the asynchronous copy of the instance's
 // FP32 planes into LDS (planes_copy_start) once x0 is in the grid, so that it
 // overlaps the operator application; the caller waits for it
 // (planes_copy_wait).
-template <class L, bool NORM_LATER = false>
+template <class L>
 __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, double* xg, double (&x)[L::R],
                                            double (&r)[L::R], double& bb, const float* copy_src = nullptr,
                                            float* copy_dst = nullptr, int copy_shift = 0) {
@@ -569,17 +568,9 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
             bb += b[i] * b[i];
         }
     } else {
-        if (z.act) {
-            strip_apply_lean<L, L::R>(SymStencil<L, double>{A.Ks64 + kSym * z.off}, xg, z, x, sx);
-            if constexpr (!NORM_LATER)
-                strip_apply_lean<L, L::R>(SymStencil<L, float>{A.Ms32 + kSym * z.off}, xg, z, x, b);
-        }
+        if (z.act) strip_apply_lean<L, L::R>(SymStencil<L, double>{A.Ks64 + kSym * z.off}, xg, z, x, sx);
 #pragma unroll
-        for (int i = 0; i < L::R; ++i) {
-            r[i] = cm[i] - sx[i];
-            const double bi = b[i] * A.inv_dt + cm[i];
-            if constexpr (!NORM_LATER) bb += bi * bi;
-        }
+        for (int i = 0; i < L::R; ++i) r[i] = cm[i] - sx[i];
     }
 }
 
@@ -613,6 +604,19 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
             for (int k = 0; k < kStencil; ++k) Sr[i][k] = (k == 1 && i > 0) ? Sr[i - 1][7] : Sg.load(z, i, k);
     }
     const RegStencil<L, double> S{Sr};
+    if (A.rhs_vec == nullptr) {
+        // ||b|| of the time step from b = S x0 + r with the resident stencil
+        // (x0 is still in the grid): no pass over M
+        double sb[L::R];
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) sb[i] = 0.0;
+        if (z.act) strip_apply_lean<L, 1>(S, xg, z, x, sb);
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) {
+            const double bi = sb[i] + r[i];
+            bb += row_ok<L>(z, i) ? bi * bi : 0.0;
+        }
+    }
     double acc[3] = {bb, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
@@ -694,7 +698,7 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
     const float* pl = region + shift;
     double x[L::R], r64[L::R];
     double bb;
-    pack_start<L, true>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift);
+    pack_start<L>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift);
     float S[L::R][kStencil], dinv[L::R];
     planes_copy_wait();
     const LdsPlanes<L> plv(pl, z);

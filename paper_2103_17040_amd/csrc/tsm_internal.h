@@ -70,7 +70,6 @@ struct AssembleArgs {
     // upper-half planes [kSym][n] at kSym*off (symmetric storage, see kSym)
     double* Ss64;         // S
     double* Ks64;         // K = d A + kappa B = S - M/dt, accumulated on its own
-    float* Ms32;          // M rounded to FP32 (norms only)
     float* Ss32;          // S rounded to FP32
     float* Sslo;          // S - Ss32 rounded to FP32
     double* b;            // boundary load B 1 (ragged)
@@ -104,7 +103,6 @@ struct MicroArgs {
     const double* M64;
     const double* Ss64;   // symmetric upper-half planes (packed kernels)
     const double* Ks64;
-    const float* Ms32;
     const float* Ss32;
     const float* Sslo;
     const double* b;
