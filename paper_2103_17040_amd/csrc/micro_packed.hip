@@ -16,20 +16,22 @@
 // so boundary rows need no bounds checks.
 //
 // Operators are read from their symmetric upper-half planes (kSym): 5 stored
-// coefficients per node instead of 9, so each streamed operator costs 40
-// (FP64) or 20 (FP32) bytes per node; the lower coefficients are loaded from
-// the neighbours' planes (same cache lines as the neighbours' own loads).
+// coefficients per node instead of 9, so each operator read costs 40 (FP64)
+// or 20 (FP32) bytes per node; the lower coefficients are loaded from the
+// neighbours' planes (same cache lines as the neighbours' own loads).  Every
+// operator is read once per solve: the start residual from K, the solver's
+// stencil into registers (FP32 planes through an asynchronous LDS copy).
 //
 // Register budget (768 lanes: 168 VGPRs per lane) decides the data flow:
-//   FP64 form     x, r, p, q in FP64 registers, diag^{-1} in FP32 (the
-//                 preconditioner need not be exact), FP64 stencil re-read
-//                 from global memory every iteration.
+//   FP64 form     the FP64 stencil rows resident in registers for the whole
+//                 solve, r, p, q in FP64 registers, x in LDS, diag^{-1} in
+//                 FP32 (the preconditioner need not be exact).
 //   REFINE form   FP32 stencil and diag^{-1} resident in registers for the
 //                 whole solve; FP32 PCG on S d = r/||r||; the FP64 residual
 //                 is formed once as r = -K x0 (K = S - M/dt, the right-hand
 //                 side M x0/dt enters only through its norm), then updated
 //                 as r <- r - ||r|| S d with the FP64 stencil (FP32 part in
-//                 registers plus the streamed FP32 low part), x <- x + ||r|| d,
+//                 registers plus the FP32 low part from LDS), x <- x + ||r|| d,
 //                 until ||r|| <= rtol ||b||.
 //
 // Lockstep: all instances of a pack pass the same barriers; an instance
@@ -209,9 +211,9 @@ __device__ __forceinline__ void strip_store(T* g, const Lane& z, const T (&v)[L:
     }
 }
 
-// The base pointer of a streamed stencil passes through an empty asm at
-// every use, so the compiler cannot hoist the loop-invariant coefficient
-// loads out of the solver loops and keep them live across them.
+// The plane bases of a streamed stencil pass through an empty asm at every
+// application (SymStencil::prepare), so the compiler cannot hoist the
+// coefficient loads out of the work loop and keep them live across solves.
 template <typename T>
 __device__ __forceinline__ const T* opaque(const T* p) {
     asm volatile("" : "+s"(p));
@@ -312,8 +314,8 @@ __device__ __forceinline__ void meta_copy_start(const PackList& P, const int32_t
 
 // Stencil sources.  A source gives, for row i of the lane's strip and
 // coefficient k, a raw value (load) and the coefficient (value):
-//   RegStencil     FP32 stencil resident in registers
-//   SymStencil     symmetric planes in global memory, streamed
+//   RegStencil     stencil resident in registers (FP32, or FP64)
+//   SymStencil     symmetric planes in global memory, read per application
 //   SplitStencil   FP64 operator as resident FP32 part + FP32 low part read
 //                  from an LDS copy of its planes: S32 + Slo spans at most 48
 //                  significant bits, so the FP64 sum is exact and equals S to
