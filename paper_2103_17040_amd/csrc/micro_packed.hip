@@ -688,7 +688,7 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
 // lds_barrier() (LDS ordering only) so that the copy stays in flight.
 template <class L, class Prefetch>
 __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, float* planes,
-                            PackRed<1, double>& red1, PackRed<3, double>& red3, PackRed<2, float>& rf2,
+                            PackRed<1, double>& red1, PackRed<2, double>& red2, PackRed<2, float>& rf2,
                             Prefetch prefetch) {
     const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
@@ -734,21 +734,21 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
             bb += row_ok<L>(z, i) ? bi * bi : 0.0;
         }
     }
-    double acc[3] = {bb, 0.0, 0.0};
+    double acc[2] = {bb, 0.0};     // ||b||^2, ||r||^2
 #pragma unroll
-    for (int i = 0; i < L::R; ++i) acc[2] += r64[i] * r64[i];
-    red3.sum<L>(acc, z.w0);
+    for (int i = 0; i < L::R; ++i) acc[1] += r64[i] * r64[i];
+    red2.sum<L>(acc, z.w0);
     __shared__ double otol_s[L::IPP];
     __shared__ float itol_s[L::IPP];
     const double tol2 = A.rtol * A.rtol * acc[0];
     if (z.live && z.lt == 0) otol_s[z.sub] = tol2;
-    double rr = acc[2];
+    double rr = acc[1];
     bool conv = rr <= tol2;
     int sweeps = 1, iters = 0;
     zero_halo<L, float>(pg, z);     // the float view of the grid from here on
     lds_barrier();
     const double othr = lane_threshold<L>(otol_s, cnt);
-    bool ogo = red3.any_above(othr);
+    bool ogo = red2.any_above(othr);
     while (ogo && sweeps <= A.max_refine) {
         // Inner FP32 solve of S d = r / ||r|| by the Chronopoulos-Gear form of
         // PCG: s = S p is carried by a recurrence, so each iteration needs one
@@ -936,7 +936,7 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
     if constexpr (MODE == 2) {
         __shared__ __attribute__((aligned(16))) float planes[L::PS * L::IPP + 2 * L::NP];
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_refine<L>(A, meta, cnt, lds, planes, red1, red3, rf2, prefetch);
+            pack_refine<L>(A, meta, cnt, lds, planes, red1, red2, rf2, prefetch);
         });
     } else {
         __shared__ double xs[L::R * NTP];
@@ -960,9 +960,9 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
     if constexpr (MODE == 2) {
         __shared__ __attribute__((aligned(16))) float planes[kPlaneFloats];
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
-            if (lvl == 64) pack_refine<L64>(A, meta, cnt, lds, planes, red1, red3, rf2, prefetch);
-            else if (lvl == 32) pack_refine<L32>(A, meta, cnt, lds, planes, red1, red3, rf2, prefetch);
-            else pack_refine<L16>(A, meta, cnt, lds, planes, red1, red3, rf2, prefetch);
+            if (lvl == 64) pack_refine<L64>(A, meta, cnt, lds, planes, red1, red2, rf2, prefetch);
+            else if (lvl == 32) pack_refine<L32>(A, meta, cnt, lds, planes, red1, red2, rf2, prefetch);
+            else pack_refine<L16>(A, meta, cnt, lds, planes, red1, red2, rf2, prefetch);
         });
     } else {
         __shared__ double xs[kFp64Rows * NTP];
