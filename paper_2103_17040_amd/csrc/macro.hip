@@ -70,7 +70,51 @@ __global__ void residual_kernel(MacroArgs m, const double* u, const double* rhs,
 }
 
 // C = A B for n x n row-major FP64 matrices, 16x16 output tile per workgroup.
+// For n <= kStripMax the tile's whole row strip of A and column strip of B
+// are loaded into LDS at once (one memory round trip, one barrier); larger n
+// go through 16-wide k tiles.
 constexpr int TG = 16;
+constexpr int kStripMax = 128;
+
+__global__ __launch_bounds__(TG * TG) void gemm_strip_kernel(int n, const double* A, const double* B, double* C,
+                                                            int epi, const double* lam, double* u, int NM) {
+    __shared__ double As[TG][kStripMax + 1];
+    __shared__ double Bs[kStripMax][TG + 1];
+    const int tx = threadIdx.x % TG, ty = threadIdx.x / TG;
+    const int r0 = blockIdx.y * TG, c0 = blockIdx.x * TG;
+    // the 16 x n strip of A (rows r0..) and the n x 16 strip of B (cols c0..):
+    // every load in flight before the first LDS store
+    constexpr int kPer = TG * kStripMax / (TG * TG);
+    double av[kPer], bv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = threadIdx.x + q * TG * TG;
+        const int i = e / kStripMax, k = e % kStripMax;
+        av[q] = (r0 + i < n && k < n) ? A[(int64_t)(r0 + i) * n + k] : 0.0;
+        const int kb = e / TG, j = e % TG;
+        bv[q] = (kb < n && c0 + j < n) ? B[(int64_t)kb * n + c0 + j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = threadIdx.x + q * TG * TG;
+        As[e / kStripMax][e % kStripMax] = av[q];
+        Bs[e / TG][e % TG] = bv[q];
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += As[ty][k] * Bs[k][tx];
+    const int row = r0 + ty, col = c0 + tx;
+    if (row >= n || col >= n) return;
+    const int64_t o = (int64_t)row * n + col;
+    if (epi == 0) {
+        C[o] = acc;
+    } else if (epi == 1) {
+        C[o] = acc / lam[o];
+    } else {
+        const int W = NM + 1;
+        u[(row + 1) * W + (col + 1)] += acc;
+    }
+}
 __global__ __launch_bounds__(TG * TG) void gemm_kernel(int n, const double* A, const double* B, double* C,
                                                       int epi, const double* lam, double* u, int NM) {
     __shared__ double As[TG][TG + 1];
@@ -195,7 +239,10 @@ hipError_t launch_macro_residual(const MacroArgs& m, const double* u, const doub
 hipError_t launch_gemm(int n, const double* A, const double* B, double* C, int epilogue,
                        const double* lam, double* u, int NM, hipStream_t s) {
     const dim3 grid(blocks(n, TG), blocks(n, TG));
-    hipLaunchKernelGGL(gemm_kernel, grid, dim3(TG * TG), 0, s, n, A, B, C, epilogue, lam, u, NM);
+    if (n <= kStripMax)
+        hipLaunchKernelGGL(gemm_strip_kernel, grid, dim3(TG * TG), 0, s, n, A, B, C, epilogue, lam, u, NM);
+    else
+        hipLaunchKernelGGL(gemm_kernel, grid, dim3(TG * TG), 0, s, n, A, B, C, epilogue, lam, u, NM);
     return hipGetLastError();
 }
 
