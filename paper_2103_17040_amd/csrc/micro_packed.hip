@@ -333,9 +333,9 @@ struct RegStencil {
 // k's base (wave-uniform, SGPRs) + the byte offset of the lane's node in
 // strip row 0 (VGPR) + a compile-time offset for the row and the neighbour
 // (the instruction's immediate), so a whole batch of loads is in flight with
-// no address registers of its own.  Strip rows past the mesh read past the
-// instance's block (the planes carry kPlanePad zeroed entries at the end);
-// their products are discarded.
+// no address registers of its own.  Strip rows past the mesh of active lanes
+// read at most 2(N+1) entries past the instance's block (the planes carry
+// kPlanePad zeroed entries at the end); their products are discarded.
 template <class L, typename TS>
 struct SymStencil {
     static constexpr bool kGlobal = true;
@@ -347,7 +347,10 @@ struct SymStencil {
     __device__ __forceinline__ void prepare(const Lane& z) {
 #pragma unroll
         for (int p = 0; p < kSym; ++p) pb[p] = opaque(base + p * L::n);
-        vofs = (uint32_t)((z.r0 * L::NP + z.col) * (int)sizeof(TS));
+        // lanes past the last strip address from the block's start instead
+        // (their strip would lie up to 2 strips past the mesh; what they
+        // load is discarded)
+        vofs = z.act ? (uint32_t)((z.r0 * L::NP + z.col) * (int)sizeof(TS)) : 0u;
     }
     __device__ __forceinline__ TS load(const Lane& z, int i, int k) const {
         int p, d;

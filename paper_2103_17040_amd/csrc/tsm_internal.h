@@ -21,7 +21,8 @@ constexpr int kStencil = 9;               // 9-point Q1 stencil, k = (dj2+1)*3 +
 //   k=0 (SW) = NE of j-NP-1,   k=2 (SE) = NW of j-NP+1.
 constexpr int kSym = 5;
 // Zeroed entries after the last instance's planes: a packed kernel reads up
-// to 2(N+1) entries past an instance's block (strip rows past its mesh).
+// to 2(N+1) entries past an instance's block (strip rows past its mesh, on
+// lanes that own mesh rows; the other lanes address from the block's start).
 constexpr int kPlanePad = 4 * (kMaxLevel + 1);
 // Tightest relative tolerance asked of an FP32 inner solve (2^-18, 32 FP32
 // ulps).  The correction of an FP32 solve is accurate to about cond(S)
