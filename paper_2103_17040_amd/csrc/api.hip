@@ -1095,6 +1095,7 @@ tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* fla
                                TSM_FLAG_GENERIC_64;
     const uint64_t timing = c->prm.flags & TSM_FLAG_TIMING;
     const uint64_t keep = c->prm.flags & ~(plan_bits | TSM_FLAG_TIMING);
+    const uint64_t entry_flags = c->prm.flags;
     double ms[4] = {-1.0, -1.0, -1.0, -1.0};
     double *su = nullptr, *sv = nullptr, *sF = nullptr;
     if (dalloc(&su, ni) != hipSuccess || dalloc(&sv, tot) != hipSuccess || dalloc(&sF, ni) != hipSuccess) {
@@ -1160,6 +1161,11 @@ tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* fla
         c->steps_taken = taken;
         if (ms_out) std::memcpy(ms_out, ms, sizeof(ms));
         if (flags_out) *flags_out = best;
+    } else {
+        // a trial failed: back to the caller's plan (its error stays reported)
+        const std::string err = c->err;
+        (void)tsm_set_flags(c, entry_flags);
+        c->err = err;
     }
     (void)hipStreamSynchronize(c->stream);
     dfree(su); dfree(sv); dfree(sF);
