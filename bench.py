@@ -153,14 +153,19 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan
         else:
             g.set_flags(PLAN_FLAGS[plan])
             plan = {"flags": PLAN_FLAGS[plan], "ms_per_step": None}
+        # the state the timed steps start from, so that the roofline pass
+        # times the same steps
+        u_start, v_start = g.macro().clone(), g.micro().clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g.step(steps)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         st = g.stats()
-        # roofline pass: same steps, direct launches bracketed by HIP events
+        # roofline pass: the same steps again, direct launches bracketed by
+        # HIP events
         g.set_flags(tsm.TSM_FLAG_TIMING | plan["flags"])
+        g.set_state(u_start, v_start)
         g.step(steps)
         tst = g.stats()
         g.set_flags(plan["flags"])
@@ -328,7 +333,8 @@ def cpu_baseline(w, a, th, lv, seconds_hint=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=0,
+                    help="timed steps (0: the workload's own step count, 200 for the large batch)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large_mixed", choices=sorted(W.WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
@@ -364,6 +370,8 @@ def main():
         _log(f"calibration copy: {args.calib_bytes} bytes read + written, 3 times")
         del src, dst
     w, a, th, lv = W.make(args.workload, args.seed)
+    if args.steps <= 0:
+        args.steps = w.steps
     refine = w.precision == "fp32_refine"
     _log(f"workload {w.name}: {w.n_inst} instances, levels {sorted(set(lv.tolist()))}, "
          f"{int(W.offsets(lv)[-1])} micro DoFs, precision {w.precision}, rtol {w.rtol}")

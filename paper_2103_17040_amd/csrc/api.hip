@@ -78,6 +78,8 @@ struct tsm_ctx {
     // ragged
     double *S64 = nullptr, *M64 = nullptr, *b = nullptr, *w = nullptr, *v0 = nullptr;
     double* Mw = nullptr;          // M_i w_i (packed step solves start from v0)
+    // b at the boundary nodes, compact (kBndStride per instance, bnd_node order)
+    double* bcomp = nullptr;
     float *S32 = nullptr, *Slo = nullptr;
     // symmetric upper-half planes [kSym][n] of S, K = S - M/dt, M (FP32), S split in FP32
     double *Ss64 = nullptr, *Ks64 = nullptr;
@@ -119,6 +121,7 @@ struct tsm_ctx {
         dfree(Ss64); dfree(Ks64); dfree(Ss32); dfree(Sslo);
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(Mw); dfree(v0); dfree(S32); dfree(Slo);
+        dfree(bcomp);
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
@@ -200,7 +203,7 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
         }
     }
     if (c->n_packs > 0 && base.bx_out != nullptr)
-        HIPCHK(launch_bdot_boundary((int)c->n_packed_tasks, c->order, c->level, c->offsets, c->b, base.X_out,
+        HIPCHK(launch_bdot_boundary((int)c->n_packed_tasks, c->order, c->level, c->offsets, c->bcomp, base.X_out,
                                     base.bx_out, c->stream));
     for (const Group& g : c->groups) {
         MicroArgs a = base;
@@ -592,6 +595,7 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPCHK(hipMemset(c->Ss32 + pe, 0, kPlanePad * sizeof(float)));
     HIPCHK(hipMemset(c->Sslo + pe, 0, kPlanePad * sizeof(float)));
     HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot); HIPALLOC(c->Mw, tot);
+    HIPALLOC(c->bcomp, ni * kBndStride);
     HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());
     HIPCHK(hipMemcpy(c->level, c->level_h.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -632,6 +636,7 @@ namespace {
 template <class What>
 tsm_status finish_setup(tsm_ctx* c, std::chrono::steady_clock::time_point t0, What what) {
     const int64_t n_inst = c->n_inst;
+    HIPCHK(launch_bnd_gather((int)n_inst, c->level, c->offsets, c->b, c->bcomp, c->stream));
     std::vector<double> jm(n_inst);
     HIPCHK(hipMemcpyAsync(jm.data(), c->jmin, n_inst * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));

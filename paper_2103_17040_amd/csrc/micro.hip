@@ -420,31 +420,34 @@ __global__ __launch_bounds__(NT) void bdot_kernel(const int64_t* offsets, const 
 }
 
 // b_i^T x_i over the boundary nodes only (b is the boundary load B 1, zero at
-// every interior node): one wave per task, 4N nodes per N x N instance.
+// every interior node), with b in the compact boundary order, gathered once at
+// set-up, so only x is read at strided nodes: one wave per task, 4N nodes per
+// N x N instance.
 constexpr int kBdotWaves = 4;
 __global__ __launch_bounds__(kBdotWaves * kWave) void bdot_boundary_kernel(int n_tasks, const int32_t* order,
                                                                            const int32_t* level,
-                                                                           const int64_t* offsets, const double* b,
+                                                                           const int64_t* offsets, const double* bc,
                                                                            const double* x, double* out) {
     const int t = blockIdx.x * kBdotWaves + (int)(threadIdx.x / kWave);
     if (t >= n_tasks) return;                // whole waves leave together
     const int lane = threadIdx.x & (kWave - 1);
     const int inst = order[t];
-    const int N = level[inst], NP = N + 1;
-    const int64_t off = offsets[inst];
+    const int N = level[inst];
+    const int64_t o = (int64_t)inst * kBndStride;
+    const double* xi = x + offsets[inst];
     double v = 0.0;
-    for (int k = lane; k < 4 * N; k += kWave) {
-        // bottom row (NP nodes), top row (NP), then the interior rows' first
-        // and last columns (N-1 each)
-        int j;
-        if (k < NP) j = k;
-        else if (k < 2 * NP) j = N * NP + (k - NP);
-        else if (k < 2 * NP + N - 1) j = (k - 2 * NP + 1) * NP;
-        else j = (k - 2 * NP - N + 2) * NP + N;
-        v += b[off + j] * x[off + j];
-    }
+    for (int k = lane; k < 4 * N; k += kWave) v += bc[o + k] * xi[bnd_node(N, k)];
     v = wave_total_last(v);
     if (lane == kWave - 1) out[inst] = v;
+}
+
+__global__ void bnd_gather_kernel(int n_inst, const int32_t* level, const int64_t* offsets, const double* b,
+                                  double* bc) {
+    const int inst = blockIdx.x;
+    if (inst >= n_inst) return;
+    const int N = level[inst];
+    for (int k = threadIdx.x; k < 4 * N; k += blockDim.x)
+        bc[(int64_t)inst * kBndStride + k] = b[offsets[inst] + bnd_node(N, k)];
 }
 
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, int n) {
@@ -480,10 +483,17 @@ hipError_t launch_bdot(int n_inst, const int64_t* offsets, const double* b, cons
 }
 
 hipError_t launch_bdot_boundary(int n_tasks, const int32_t* order, const int32_t* level, const int64_t* offsets,
-                                const double* b, const double* x, double* out, hipStream_t s) {
+                                const double* bc, const double* x, double* out, hipStream_t s) {
     if (n_tasks <= 0) return hipSuccess;
     hipLaunchKernelGGL(bdot_boundary_kernel, dim3((n_tasks + kBdotWaves - 1) / kBdotWaves), dim3(kBdotWaves * kWave),
-                       0, s, n_tasks, order, level, offsets, b, x, out);
+                       0, s, n_tasks, order, level, offsets, bc, x, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bnd_gather(int n_inst, const int32_t* level, const int64_t* offsets, const double* b, double* bc,
+                             hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bnd_gather_kernel, dim3(n_inst), dim3(256), 0, s, n_inst, level, offsets, b, bc);
     return hipGetLastError();
 }
 

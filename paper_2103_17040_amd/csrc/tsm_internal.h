@@ -24,6 +24,19 @@ constexpr int kSym = 5;
 // to 2(N+1) entries past an instance's block (strip rows past its mesh, on
 // lanes that own mesh rows; the other lanes address from the block's start).
 constexpr int kPlanePad = 4 * (kMaxLevel + 1);
+
+// Boundary nodes of an N x N instance in a compact order: the bottom row
+// (N+1 nodes), the top row (N+1), then the first and the last column of the
+// interior rows (N-1 each), 4N in all; per instance at stride kBndStride.
+constexpr int kBndStride = 4 * kMaxLevel;
+__host__ __device__ inline int bnd_node(int N, int k) {
+    const int NP = N + 1;
+    if (k < NP) return k;
+    if (k < 2 * NP) return N * NP + (k - NP);
+    if (k < 2 * NP + N - 1) return (k - 2 * NP + 1) * NP;
+    return (k - 2 * NP - N + 2) * NP + N;
+}
+
 // Tightest relative tolerance asked of an FP32 inner solve (2^-18, 32 FP32
 // ulps).  The correction of an FP32 solve is accurate to about cond(S)
 // FP32 ulps whatever its own residual says, so iterating further only
@@ -174,9 +187,12 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int n, hipStream_t s);
 hipError_t launch_bdot(int n_inst, const int64_t* offsets, const double* b, const double* x, double* out,
                        hipStream_t s);
 // out[order[t]] = b^T x over the boundary nodes of instance order[t], t < n_tasks
-// (b vanishes at interior nodes)
+// (b vanishes at interior nodes), with b in the compact boundary order
 hipError_t launch_bdot_boundary(int n_tasks, const int32_t* order, const int32_t* level, const int64_t* offsets,
-                                const double* b, const double* x, double* out, hipStream_t s);
+                                const double* bc, const double* x, double* out, hipStream_t s);
+// bc[i * kBndStride + k] = b_i at boundary node bnd_node(N_i, k)
+hipError_t launch_bnd_gather(int n_inst, const int32_t* level, const int64_t* offsets, const double* b, double* bc,
+                             hipStream_t s);
 // residual sum of the alternating coupling: out[0] = ||R||_2 (nR interior macro rows),
 // out[1] = mean over instances of res (per-instance micro residual norms)
 hipError_t launch_coupling_residual(int nR, const double* R, int n_inst, const double* res, double* out,
