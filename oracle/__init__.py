@@ -14,4 +14,7 @@ twoscale     the coupled implicit-Euler step: exact Schur route, the paper's
              fixed-point coupling (Section 3.3) and a dense monolithic solve
 adjoint      discrete adjoint of the time-stepped system (no counterpart in
              the paper; the derivation is written out in the module)
+stationary   the paper's stationary three-field system (Section 2.1) with
+             Robin exchange on parts of each cell boundary, solved as one
+             sparse system
 """
