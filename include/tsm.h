@@ -237,6 +237,82 @@ tsm_status tsm_get_stats(const tsm_ctx* c, tsm_stats* s);
 const char* tsm_last_error(const tsm_ctx* c);
 void tsm_destroy(tsm_ctx* c);   /* NULL-safe */
 
+/* ---------------------------------------------------------------------------
+ * The paper's stationary three-field system (Section 2.1 model; the Case A/B
+ * experiments of Section 4 solve it with the Table 3 parameters):
+ *   -Lap u = f^u - int_{G^I} (k1 u - k2 v) dsigma_y     in [-1,1]^2,
+ *            u = u_dirichlet on the Dirichlet sides, grad u . n = 0 elsewhere
+ *   -Dv Lap_y v = f^v  in Y_x,   Dv grad_y v . n = k1 u - k2 v  on G^I
+ *                                                 k3 w - k4 v  on G^O
+ *                                                 0            on G^N
+ *   -Dw Lap w = f^w - int_{G^O} (k3 w - k4 v) dsigma_y, Dw grad w . n = 0 on the boundary
+ * with constant sources; G^I, G^O, G^N are images of whole sides of Z
+ * (parts[]).  Same discretisation as the time-dependent system (Q1, the map
+ * through its Jacobian at the quadrature points, one micro system per macro
+ * node fed u_k and w_k), exchange integrals of the macro rows taken at the
+ * nodes with weights L = diag(M_H 1).  Solved exactly by elimination: per
+ * instance three micro PCG solves with the FP64 operator
+ *   S = Dv A + k2 B^I + k4 B^O:  z^I = S^{-1} b_I,  z^O = S^{-1} b_O,
+ *   z^0 = S^{-1} (f^v M 1)       (b_I = B^I 1, b_O = B^O 1),
+ * one macro PCG for (u, w) -- symmetric positive definite once the u rows
+ * are scaled by k1/k2 and the w rows by k3/k4 -- and v = z^0 + k1 u z^I +
+ * k3 w z^O.
+ * Use: tsm_stationary_create, tsm_set_reference_mesh, tsm_set_deformation
+ * or tsm_set_jacobians (assemble S, b_I, b_O, M 1 and check the geometry),
+ * tsm_stationary_solve.  tsm_apply_operator applies this S; tsm_set_flags
+ * takes the launch-plan flags; the time-stepping calls return ESTATE.
+ * ------------------------------------------------------------------------- */
+enum { TSM_PART_N = 0, TSM_PART_I = 1, TSM_PART_O = 2 };
+
+typedef struct {
+    int32_t macro_cells;      /* N_M in 2..256: macro Q1 cells per side on [-1,1]^2 */
+    double Dv, Dw;            /* micro and macro-w diffusion, > 0 */
+    double kappa1, kappa2, kappa3, kappa4;   /* exchange rates, > 0 */
+    double fu, fv, fw;        /* constant bulk sources (finite) */
+    double u_dirichlet;       /* u on the Dirichlet sides (finite) */
+    int32_t parts[4];         /* part of each side of Z -- bottom (y2 = -1), top (y2 = +1),
+                                 left (y1 = -1), right (y1 = +1): TSM_PART_*; at least one
+                                 side in G^I and one in G^O */
+    int32_t dirichlet[4];     /* sides of [-1,1]^2 in the same order: nonzero = u prescribed;
+                                 at least one */
+    double rtol;              /* micro PCG (FP64): ||b - S x||_2 <= rtol ||b||_2 */
+    double macro_rtol;        /* macro PCG: same test on the eliminated (u, w) system */
+    int32_t max_iter;         /* micro PCG iterations per solve, >= 1 */
+    int32_t macro_max_iter;   /* macro PCG iterations, >= 1 */
+    uint64_t flags;           /* launch-plan flags (TSM_FLAG_GENERIC*, TSM_FLAG_PERSISTENT,
+                                 TSM_FLAG_STENCIL_STREAM) */
+} tsm_stationary_params;
+
+typedef struct {
+    int32_t micro_iters_max[3];  /* PCG iterations, most over instances, of the z^I, z^O, z^0
+                                    solves of the last tsm_stationary_solve (0: not solved) */
+    double micro_iters_mean[3];
+    int32_t unconverged;         /* micro solves that missed rtol */
+    int32_t macro_iters;         /* macro PCG iterations */
+    double macro_rel_residual;   /* its final ||r||_2 / ||b||_2 */
+    double solve_ms;             /* the whole solve, between events on the context's stream */
+    double micro_ms;             /* the three batched micro solves */
+} tsm_stationary_stats;
+
+/* Defaults: the Table 3 parameters (Dv 1, Dw 0.1, k1..k4 = 0.5, 1, 0.25, 1,
+ * f^u = f^v = f^w = 0, u_dirichlet 1), macro_cells 8, parts
+ * (N, N, I, O), Dirichlet side left (x1 = -1), rtol 1e-12, macro_rtol 1e-14,
+ * max_iter 20000, macro_max_iter 200000, flags 0. */
+void tsm_stationary_default_params(tsm_stationary_params* p);
+
+/* Create a stationary context on the current HIP device (stream as for
+ * tsm_create).  EINVAL on bad parameters. */
+tsm_status tsm_stationary_create(const tsm_stationary_params* p, void* stream, tsm_ctx** out);
+
+/* Solve the system.  u_out, w_out: device pointers, n_inst doubles each;
+ * v_out: device pointer, ragged (or NULL to skip).  ESTATE before the
+ * geometry is set or on a context made by tsm_create; ENOCONV if a micro
+ * solve missed rtol or the macro solve missed macro_rtol (outputs are still
+ * written, from the last iterates). */
+tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double* v_out);
+
+tsm_status tsm_stationary_get_stats(const tsm_ctx* c, tsm_stationary_stats* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -237,26 +237,3 @@ def solve(prm: StationaryParams, levels, jacobians, data: Optional[StationaryDat
         v.append(sol[pos:pos + n])
         pos += n
     return {"u": u, "w": w, "v": v, "lenI": lenI, "lenO": lenO}
-
-
-# ---------------------------------------------------------------------------
-# maps of the Case A/B experiments (Section 4.4), x = macro node, y in Z:
-#   zeta_0(x, y) = y,   zeta_1(x, y) = ((2 x1 + 3) y1 / 4 - x2 y2 / 5, (2 - x2) y2 / 4)
-# Both are affine in y, so D zeta is constant on each cell.
-# ---------------------------------------------------------------------------
-
-def map_jacobian(case, x1, x2):
-    """D_y zeta of the Case A (identity) or Case B map at macro point x."""
-    if case == "A":
-        return np.eye(2)
-    if case == "B":
-        return np.array([[(2.0 * x1 + 3.0) / 4.0, -x2 / 5.0], [0.0, (2.0 - x2) / 4.0]])
-    raise ValueError(case)
-
-
-def constant_jacobians(N, F):
-    """Jacobian tables of a map with constant D zeta = F, in the layout of
-    fem.quadrature_points(N)."""
-    Fc = np.broadcast_to(F, (N * N, 4, 2, 2)).copy()
-    Fb = np.broadcast_to(F, (4, N, 2, 2, 2)).copy()
-    return Fc, Fb

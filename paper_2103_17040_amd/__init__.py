@@ -3,10 +3,11 @@
 ``tsm``            ctypes binding of libtsm.so (same names as include/tsm.h)
 ``TwoScaleBatch``  owner of one library context plus torch-allocated device
                    buffers for its inputs and outputs
+``StationarySystem`` the same for the stationary three-field system
 """
 from __future__ import annotations
 
-__all__ = ["TwoScaleBatch"]
+__all__ = ["TwoScaleBatch", "StationarySystem"]
 
 
 class TwoScaleBatch:
@@ -151,6 +152,93 @@ class TwoScaleBatch:
 
     def stats(self):
         return tsm.tsm_get_stats(self.ctx)
+
+    def close(self):
+        from . import tsm
+        if getattr(self, "ctx", None):
+            tsm.tsm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class StationarySystem:
+    """The stationary three-field system (u, w macro; v per macro node) on
+    [-1,1]^2: one library context.  Geometry from amplitudes a (the
+    sinusoidal family) or from Jacobian tables (any map).  All arithmetic
+    happens in libtsm; outputs are torch CUDA tensors (float64)."""
+
+    _NAMES = ("Dv", "Dw", "kappa1", "kappa2", "kappa3", "kappa4", "fu", "fv", "fw", "u_dirichlet", "rtol",
+              "macro_rtol", "max_iter", "macro_max_iter")
+
+    def __init__(self, macro_cells, micro_cells, a=None, theta=None, *, jacobians=None, parts=None,
+                 dirichlet=None, flags=0, device="cuda:0", **kw):
+        import numpy as np
+        import torch
+        global tsm
+        from . import tsm
+        self.torch = torch
+        self.device = torch.device(device)
+        prm = tsm.tsm_stationary_default_params()
+        prm.macro_cells = int(macro_cells)
+        for k, v in kw.items():
+            if k not in self._NAMES:
+                raise TypeError(f"unknown parameter {k}")
+            setattr(prm, k, type(getattr(prm, k))(v))
+        if parts is not None:
+            for s, v in enumerate(parts):
+                prm.parts[s] = int(v)
+        if dirichlet is not None:
+            for s, v in enumerate(dirichlet):
+                prm.dirichlet[s] = int(bool(v))
+        prm.flags = int(flags)
+        self.params = prm
+        self.n_inst = (int(macro_cells) + 1) ** 2
+        with torch.cuda.device(self.device):
+            self.ctx = tsm.tsm_stationary_create(prm, None)
+        try:
+            self._levels = np.asarray(micro_cells, dtype=np.int32)
+            tsm.tsm_set_reference_mesh(self.ctx, self._levels)
+            self.offsets = tsm.tsm_get_offsets(self.ctx, self.n_inst)
+            self.n_micro = int(self.offsets[-1])
+            if jacobians is not None:
+                Fc = torch.as_tensor(jacobians[0], dtype=torch.float64, device=self.device).contiguous()
+                Fb = torch.as_tensor(jacobians[1], dtype=torch.float64, device=self.device).contiguous()
+                tsm.tsm_set_jacobians(self.ctx, Fc, Fc.numel(), Fb, Fb.numel())
+            else:
+                ta = torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+                tt = None if theta is None else torch.as_tensor(theta, dtype=torch.float64,
+                                                               device=self.device).contiguous()
+                tsm.tsm_set_deformation(self.ctx, ta, tt, self.n_inst)
+        except Exception:
+            self.close()
+            raise
+
+    def solve(self, with_micro=True):
+        """Returns (u, w, v) (v None unless with_micro)."""
+        t = self.torch
+        u = t.empty(self.n_inst, dtype=t.float64, device=self.device)
+        w = t.empty_like(u)
+        v = t.empty(self.n_micro, dtype=t.float64, device=self.device) if with_micro else None
+        tsm.tsm_stationary_solve(self.ctx, u, w, v)
+        return u, w, v
+
+    def apply(self, x):
+        t = self.torch
+        tx = t.as_tensor(x, dtype=t.float64, device=self.device).contiguous()
+        y = t.empty(self.n_micro, dtype=t.float64, device=self.device)
+        tsm.tsm_apply_operator(self.ctx, tx, y)
+        return y
+
+    def set_flags(self, flags):
+        tsm.tsm_set_flags(self.ctx, flags)
+
+    def stats(self):
+        return tsm.tsm_stationary_get_stats(self.ctx)
 
     def close(self):
         from . import tsm

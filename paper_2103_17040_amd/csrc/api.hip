@@ -102,6 +102,18 @@ struct tsm_ctx {
     double *lam0 = nullptr, *mu = nullptr, *coef = nullptr, *grad = nullptr, *Jd = nullptr;
     double grad_fwd_ms = 0.0, grad_bwd_ms = 0.0;
 
+    // stationary three-field system (tsm_stationary_create): b holds b_I and
+    // len |G^I|; b_O, |G^O|, M 1, the three micro solutions, the five
+    // products per instance, w, the macro scratch and the iterations of the
+    // three solves
+    bool stationary = false;
+    tsm_stationary_params sp{};
+    double *st_bO = nullptr, *st_lenO = nullptr, *st_m1 = nullptr, *st_zI = nullptr, *st_zO = nullptr,
+           *st_z0 = nullptr, *st_dots = nullptr, *st_w = nullptr, *st_work = nullptr, *st_info = nullptr;
+    int32_t* st_iters = nullptr;
+    hipEvent_t ev_mid = nullptr;
+    tsm_stationary_stats st_stats{};
+
     bool have_mesh = false, have_geom = false, have_state = false;
     hipGraphExec_t graph = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -125,6 +137,8 @@ struct tsm_ctx {
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
+        dfree(st_bO); dfree(st_lenO); dfree(st_m1); dfree(st_zI); dfree(st_zO); dfree(st_z0); dfree(st_dots);
+        dfree(st_w); dfree(st_work); dfree(st_info); dfree(st_iters);
         drop_graph();
         have_mesh = have_geom = have_state = false;
     }
@@ -596,6 +610,12 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPCHK(hipMemset(c->Sslo + pe, 0, kPlanePad * sizeof(float)));
     HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot); HIPALLOC(c->Mw, tot);
     HIPALLOC(c->bcomp, ni * kBndStride);
+    if (c->stationary) {
+        HIPALLOC(c->st_bO, tot); HIPALLOC(c->st_lenO, ni); HIPALLOC(c->st_m1, tot);
+        HIPALLOC(c->st_zI, tot); HIPALLOC(c->st_zO, tot); HIPALLOC(c->st_z0, tot);
+        HIPALLOC(c->st_dots, 5 * ni); HIPALLOC(c->st_w, ni); HIPALLOC(c->st_work, 11 * ni);
+        HIPALLOC(c->st_info, 2); HIPALLOC(c->st_iters, 3 * ni);
+    }
     HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());
     HIPCHK(hipMemcpy(c->level, c->level_h.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -633,6 +653,42 @@ namespace {
 // Everything after the assembly, shared by both geometry inputs: the det
 // check, the responses w_i, beta, the macro solver and the step graph.
 // what(i) describes instance i for the geometry error message.
+// Assembly arguments of the context's operator: S = M/dt + d A + kappa B
+// with b = B 1 (time-dependent system), or S = Dv A + k2 B^I + k4 B^O with
+// b = b_I, b2 = b_O and M 1 (stationary system).
+AssembleArgs assemble_base(tsm_ctx* c) {
+    AssembleArgs as{};
+    as.n_inst = (int)c->n_inst;
+    as.level = c->level;
+    as.offsets = c->offsets;
+    as.amp = c->amp;
+    as.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
+    as.S64 = c->S64; as.S32 = c->S32; as.Slo = c->Slo; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
+    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
+    if (!c->stationary) {
+        as.d = c->prm.d;
+        as.inv_dt = 1.0 / c->prm.dt;
+        for (int s = 0; s < 4; ++s) {
+            as.kside[s] = c->prm.kappa;
+            as.bw[s] = 1.0;
+            as.bw2[s] = 0.0;
+        }
+    } else {
+        as.d = c->sp.Dv;
+        as.inv_dt = 0.0;
+        for (int s = 0; s < 4; ++s) {
+            const int part = c->sp.parts[s];
+            as.kside[s] = part == TSM_PART_I ? c->sp.kappa2 : part == TSM_PART_O ? c->sp.kappa4 : 0.0;
+            as.bw[s] = part == TSM_PART_I ? 1.0 : 0.0;
+            as.bw2[s] = part == TSM_PART_O ? 1.0 : 0.0;
+        }
+        as.b2 = c->st_bO;
+        as.len2 = c->st_lenO;
+        as.m1 = c->st_m1;
+    }
+    return as;
+}
+
 template <class What>
 tsm_status finish_setup(tsm_ctx* c, std::chrono::steady_clock::time_point t0, What what) {
     const int64_t n_inst = c->n_inst;
@@ -647,6 +703,11 @@ tsm_status finish_setup(tsm_ctx* c, std::chrono::steady_clock::time_point t0, Wh
                           jm[i], (long long)i, what(i).c_str());
             return c->fail(TSM_EGEOM, buf);
         }
+    if (c->stationary) {   // the solves belong to tsm_stationary_solve
+        c->have_geom = true;
+        c->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return TSM_OK;
+    }
 
     // responses w_i = kappa p S_i^{-1} b_i (FP64, zero initial guess)
     HIPCHK(hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->stream));
@@ -749,17 +810,7 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
     c->drop_graph();
     HIPCHK(hipMemcpyAsync(c->amp, a, n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
 
-    AssembleArgs as;
-    as.n_inst = (int)n_inst;
-    as.level = c->level;
-    as.offsets = c->offsets;
-    as.amp = c->amp;
-    as.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
-    as.d = c->prm.d;
-    as.kappa = c->prm.kappa;
-    as.inv_dt = 1.0 / c->prm.dt;
-    as.S64 = c->S64; as.S32 = c->S32; as.Slo = c->Slo; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
-    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
+    const AssembleArgs as = assemble_base(c);
     HIPCHK(launch_assemble(as, c->stream));
     return finish_setup(c, t0, [&](int64_t i) {
         char b[48];
@@ -796,17 +847,7 @@ tsm_status tsm_set_jacobians(tsm_ctx* c, const double* Fcell, int64_t n_cell, co
     HIPCHK(hipMemcpy(c->bnd_off, bo.data(), n_inst * sizeof(int64_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemsetAsync(c->amp, 0, n_inst * sizeof(double), c->stream));
 
-    AssembleArgs as{};
-    as.n_inst = (int)n_inst;
-    as.level = c->level;
-    as.offsets = c->offsets;
-    as.amp = c->amp;
-    as.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
-    as.d = c->prm.d;
-    as.kappa = c->prm.kappa;
-    as.inv_dt = 1.0 / c->prm.dt;
-    as.S64 = c->S64; as.S32 = c->S32; as.Slo = c->Slo; as.M64 = c->M64; as.b = c->b; as.len = c->len; as.jmin = c->jmin;
-    as.Ss64 = c->Ss64; as.Ks64 = c->Ks64; as.Ss32 = c->Ss32; as.Sslo = c->Sslo;
+    AssembleArgs as = assemble_base(c);
     as.Fcell = Fcell; as.Fbnd = Fbnd; as.cell_off = c->cell_off; as.bnd_off = c->bnd_off;
     HIPCHK(launch_assemble_tables(as, c->stream));
     c->geom_tables = true;
@@ -815,6 +856,7 @@ tsm_status tsm_set_jacobians(tsm_ctx* c, const double* Fcell, int64_t n_cell, co
 
 tsm_status tsm_set_state(tsm_ctx* c, const double* u, const double* v) {
     if (!c) return TSM_EINVAL;
+    if (c->stationary) return c->fail(TSM_ESTATE, "stationary context: no time stepping (tsm_stationary_solve)");
     if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation first");
     if (!u) return c->fail(TSM_EINVAL, "u is NULL");
     HIPCHK(hipDeviceSynchronize());
@@ -920,6 +962,7 @@ tsm_status tsm_get_setup(const tsm_ctx* cc, double* beta_out, double* len_out, d
     tsm_ctx* c = const_cast<tsm_ctx*>(cc);
     if (!c) return TSM_EINVAL;
     if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation first");
+    if (c->stationary) return c->fail(TSM_ESTATE, "stationary context: no response functionals");
     HIPCHK(hipDeviceSynchronize());
     if (beta_out) HIPCHK(hipMemcpyAsync(beta_out, c->beta, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (len_out) HIPCHK(hipMemcpyAsync(len_out, c->len, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1086,7 +1129,7 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
         tsm_status st = plan_tasks(c);
         if (st != TSM_OK) return st;
     }
-    if (c->have_geom) return build_graph(c);
+    if (c->have_geom && !c->stationary) return build_graph(c);
     return TSM_OK;
 }
 
@@ -1220,6 +1263,177 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
 
 const char* tsm_last_error(const tsm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
+void tsm_stationary_default_params(tsm_stationary_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->macro_cells = 8;
+    p->Dv = 1.0;
+    p->Dw = 0.1;
+    p->kappa1 = 0.5;
+    p->kappa2 = 1.0;
+    p->kappa3 = 0.25;
+    p->kappa4 = 1.0;
+    p->u_dirichlet = 1.0;
+    p->parts[0] = TSM_PART_N;
+    p->parts[1] = TSM_PART_N;
+    p->parts[2] = TSM_PART_I;
+    p->parts[3] = TSM_PART_O;
+    p->dirichlet[2] = 1;
+    p->rtol = 1e-12;
+    p->macro_rtol = 1e-14;
+    p->max_iter = 20000;
+    p->macro_max_iter = 200000;
+    p->flags = 0;
+}
+
+tsm_status tsm_stationary_create(const tsm_stationary_params* sp, void* stream, tsm_ctx** out) {
+    if (!out) return create_failed(nullptr, TSM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!sp) return create_failed(nullptr, TSM_EINVAL, "params is NULL");
+    int n_in = 0, n_out = 0, n_dir = 0;
+    bool parts_ok = true;
+    for (int s = 0; s < 4; ++s) {
+        parts_ok = parts_ok && sp->parts[s] >= TSM_PART_N && sp->parts[s] <= TSM_PART_O;
+        n_in += sp->parts[s] == TSM_PART_I;
+        n_out += sp->parts[s] == TSM_PART_O;
+        n_dir += sp->dirichlet[s] != 0;
+    }
+    const uint64_t plan = TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT |
+                          TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64;
+    const double pos[] = {sp->Dv, sp->Dw, sp->kappa1, sp->kappa2, sp->kappa3, sp->kappa4, sp->rtol, sp->macro_rtol};
+    bool ok = sp->macro_cells >= 2 && sp->macro_cells <= 256 && parts_ok && n_in >= 1 && n_out >= 1 && n_dir >= 1 &&
+              sp->max_iter >= 1 && sp->macro_max_iter >= 1 && !(sp->flags & ~plan) && std::isfinite(sp->fu) &&
+              std::isfinite(sp->fv) && std::isfinite(sp->fw) && std::isfinite(sp->u_dirichlet);
+    for (double v : pos) ok = ok && v > 0 && std::isfinite(v);
+    if (!ok) return create_failed(nullptr, TSM_EINVAL, "stationary parameter out of range");
+    tsm_params p;
+    tsm_default_params(&p);
+    p.macro_cells = sp->macro_cells;
+    p.d = sp->Dv;
+    p.rtol = sp->rtol;
+    p.setup_rtol = sp->rtol;
+    p.max_iter = sp->max_iter;
+    p.flags = sp->flags;
+    const tsm_status st = tsm_create(&p, stream, out);
+    if (st != TSM_OK) return st;
+    (*out)->stationary = true;
+    (*out)->sp = *sp;
+    return TSM_OK;
+}
+
+tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double* v_out) {
+    if (!c) return TSM_EINVAL;
+    if (!c->stationary) return c->fail(TSM_ESTATE, "not a stationary context (tsm_stationary_create)");
+    if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation or set_jacobians first");
+    if (!u_out || !w_out) return c->fail(TSM_EINVAL, "u_out or w_out is NULL");
+    const int64_t ni = c->n_inst;
+    const tsm_stationary_params& sp = c->sp;
+    if (!c->ev_mid) HIPCHK(hipEventCreate(&c->ev_mid));
+    HIPCHK(hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->stream));
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    // three batched micro solves (FP64, zero initial guess)
+    const bool with_f = sp.fv != 0.0;
+    const double* rhs[3] = {c->b, c->st_bO, c->st_m1};
+    const double scale[3] = {1.0, 1.0, sp.fv};
+    double* sol[3] = {c->st_zI, c->st_zO, c->st_z0};
+    MicroArgs ma = micro_base(c);
+    ma.X0 = nullptr;
+    ma.coef = nullptr;
+    ma.zero_init = 1;
+    ma.inv_dt = 0.0;
+    ma.rtol = sp.rtol;
+    ma.max_iter = sp.max_iter;
+    for (int q = 0; q < 3; ++q) {
+        if (q == 2 && !with_f) {
+            HIPCHK(launch_fill_i32(c->st_iters + 2 * ni, 0, (int)ni, c->stream));
+            continue;
+        }
+        ma.rhs_vec = rhs[q];
+        ma.rhs_scale = scale[q];
+        ma.X_out = sol[q];
+        const tsm_status st = enqueue_micro(c, ma, true);
+        if (st != TSM_OK) return st;
+        HIPCHK(hipMemcpyAsync(c->st_iters + q * ni, c->iters, ni * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                              c->stream));
+    }
+    HIPCHK(hipEventRecord(c->ev_mid, c->stream));
+    // b_I^T z^I, b_O^T z^O, b_I^T z^O, b_I^T z^0, b_O^T z^0
+    HIPCHK(launch_bdot((int)ni, c->offsets, c->b, c->st_zI, c->st_dots, c->stream));
+    HIPCHK(launch_bdot((int)ni, c->offsets, c->st_bO, c->st_zO, c->st_dots + ni, c->stream));
+    HIPCHK(launch_bdot((int)ni, c->offsets, c->b, c->st_zO, c->st_dots + 2 * ni, c->stream));
+    if (with_f) {
+        HIPCHK(launch_bdot((int)ni, c->offsets, c->b, c->st_z0, c->st_dots + 3 * ni, c->stream));
+        HIPCHK(launch_bdot((int)ni, c->offsets, c->st_bO, c->st_z0, c->st_dots + 4 * ni, c->stream));
+    } else {
+        HIPCHK(hipMemsetAsync(c->st_dots + 3 * ni, 0, 2 * ni * sizeof(double), c->stream));
+    }
+    StationaryMacroArgs m{};
+    m.NM = c->NM;
+    m.Dw = sp.Dw;
+    m.k1 = sp.kappa1;
+    m.k2 = sp.kappa2;
+    m.k3 = sp.kappa3;
+    m.k4 = sp.kappa4;
+    m.fu = sp.fu;
+    m.fw = sp.fw;
+    m.uD = sp.u_dirichlet;
+    for (int s = 0; s < 4; ++s) m.dirichlet[s] = sp.dirichlet[s] != 0;
+    m.lenI = c->len;
+    m.lenO = c->st_lenO;
+    m.dots = c->st_dots;
+    m.u = c->u;
+    m.w = c->st_w;
+    m.work = c->st_work;
+    m.rtol = sp.macro_rtol;
+    m.max_iter = sp.macro_max_iter;
+    m.info = c->st_info;
+    HIPCHK(launch_stationary_macro(m, c->stream));
+    if (v_out)
+        HIPCHK(launch_stationary_micro((int)ni, c->offsets, with_f ? c->st_z0 : nullptr, c->st_zI, c->st_zO, c->u,
+                                       c->st_w, sp.kappa1, sp.kappa3, v_out, c->stream));
+    HIPCHK(hipMemcpyAsync(u_out, c->u, ni * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(w_out, c->st_w, ni * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+
+    std::vector<int32_t> it(3 * ni);
+    double info[2];
+    int32_t nc = 0;
+    HIPCHK(hipMemcpy(it.data(), c->st_iters, 3 * ni * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(info, c->st_info, sizeof(info), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&nc, c->counters, sizeof(int32_t), hipMemcpyDeviceToHost));
+    tsm_stationary_stats& S = c->st_stats;
+    std::memset(&S, 0, sizeof(S));
+    for (int q = 0; q < 3; ++q) {
+        double sum = 0.0;
+        int32_t mx = 0;
+        for (int64_t i = 0; i < ni; ++i) {
+            sum += it[q * ni + i];
+            mx = std::max(mx, it[q * ni + i]);
+        }
+        S.micro_iters_max[q] = mx;
+        S.micro_iters_mean[q] = sum / (double)ni;
+    }
+    S.unconverged = nc;
+    S.macro_iters = (int32_t)info[0];
+    S.macro_rel_residual = info[1];
+    float ms = 0.0f, ms_micro = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    HIPCHK(hipEventElapsedTime(&ms_micro, c->ev0, c->ev_mid));
+    S.solve_ms = ms;
+    S.micro_ms = ms_micro;
+    if (nc > 0) return c->fail(TSM_ENOCONV, std::to_string(nc) + " micro solves missed rtol");
+    if (!(info[1] <= sp.macro_rtol))
+        return c->fail(TSM_ENOCONV, "macro solve stopped at relative residual " + std::to_string(info[1]));
+    return TSM_OK;
+}
+
+tsm_status tsm_stationary_get_stats(const tsm_ctx* c, tsm_stationary_stats* s) {
+    if (!c || !s) return TSM_EINVAL;
+    *s = c->st_stats;
+    return TSM_OK;
+}
+
 void tsm_destroy(tsm_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -1229,6 +1443,7 @@ void tsm_destroy(tsm_ctx* c) {
     dfree(c->queue);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->ev_mid) (void)hipEventDestroy(c->ev_mid);
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

@@ -2,11 +2,13 @@
 //
 // For node j of instance i the kernel integrates, over the (at most four)
 // cells around j with the 2x2 Gauss rule, the row of
-//     S_i = M_i/dt + d A_i + kappa B_i,   M_i = int eta eta J,
+//     S_i = M_i/dt + d A_i + sum over sides kappa_side B_side,   M_i = int eta eta J,
 //     A_i = int grad eta . (K K^T J) grad eta
 // (discrete weak form on the reference cell, paper Section 3.1) and over the
 // (at most two) boundary edges at j, with the 2-point rule, the row of
-//     B_i = int_dZ eta eta |cof(F) nu|      (boundary change of variables).
+//     B_side = int_side eta eta |cof(F) nu|      (boundary change of variables).
+// The time-dependent system has kappa on every side; the stationary system
+// has its exchange rates on the sides that form G^I and G^O and none on G^N.
 // Each node gathers its own row -- no atomics, fixed summation order.
 // Besides the full rows (generic kernels) it stores the upper half
 // of S, of K = d A + kappa B and of M (FP32) as symmetric planes for the
@@ -27,9 +29,9 @@ namespace {
 template <int MODE>
 __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A) {
     constexpr bool TAB = MODE == 2;
-    __shared__ double red_s[2][1][kMicroThreads / kWave];
+    __shared__ double red_s[2][2][kMicroThreads / kWave];
     __shared__ double mins[kMicroThreads / kWave];
-    BlockReducer<kMicroThreads / kWave, 1, double> red(red_s);
+    BlockReducer<kMicroThreads / kWave, 2, double> red(red_s);
 
     const int inst = blockIdx.x;
     const int N = A.level[inst];
@@ -49,14 +51,14 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
     const double* Fb = TAB ? A.Fbnd + A.bnd_off[inst] : nullptr;
     bool bad = false;                      // TAB: a non-finite Jacobian entry
 
-    double len_part = 0.0;
+    double len_part = 0.0, len2_part = 0.0;
     double jmin = 1e300;
     for (int j = threadIdx.x; j < n; j += kMicroThreads) {
         const int j1 = j % NP, j2 = j / NP;
         double S[kStencil], M[kStencil], K[kStencil];
 #pragma unroll
         for (int k = 0; k < kStencil; ++k) { S[k] = 0.0; M[k] = 0.0; K[k] = 0.0; }
-        double bj = 0.0;
+        double bj = 0.0, bj2 = 0.0;
         // ---- cells around node j
         for (int dc2 = -1; dc2 <= 0; ++dc2) {
             const int c2 = j2 + dc2;
@@ -130,9 +132,10 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     if constexpr (TAB) bad |= !isfinite(om);
                     for (int m1 = 0; m1 < 2; ++m1) {
                         const double v = wb * om * lin(l1, g) * lin(m1, g);
-                        S[3 + (m1 - l1 + 1)] += A.kappa * v;
-                        K[3 + (m1 - l1 + 1)] += A.kappa * v;
-                        bj += v;
+                        S[3 + (m1 - l1 + 1)] += A.kside[side] * v;
+                        K[3 + (m1 - l1 + 1)] += A.kside[side] * v;
+                        bj += A.bw[side] * v;
+                        bj2 += A.bw2[side] * v;
                     }
                 }
             }
@@ -160,9 +163,10 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     if constexpr (TAB) bad |= !isfinite(om);
                     for (int m2 = 0; m2 < 2; ++m2) {
                         const double v = wb * om * lin(l2, g) * lin(m2, g);
-                        S[(m2 - l2 + 1) * 3 + 1] += A.kappa * v;
-                        K[(m2 - l2 + 1) * 3 + 1] += A.kappa * v;
-                        bj += v;
+                        S[(m2 - l2 + 1) * 3 + 1] += A.kside[2 + side] * v;
+                        K[(m2 - l2 + 1) * 3 + 1] += A.kside[2 + side] * v;
+                        bj += A.bw[2 + side] * v;
+                        bj2 += A.bw2[2 + side] * v;
                     }
                 }
             }
@@ -189,8 +193,18 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
         }
         A.b[off + j] = bj;
         len_part += bj;
+        if (A.b2 != nullptr) {
+            A.b2[off + j] = bj2;
+            len2_part += bj2;
+        }
+        if (A.m1 != nullptr) {
+            double m = 0.0;
+#pragma unroll
+            for (int k = 0; k < kStencil; ++k) m += M[k];
+            A.m1[off + j] = m;
+        }
     }
-    double v[1] = {len_part};
+    double v[2] = {len_part, len2_part};
     red.sum(v);
     double m = bad ? -1.0 : jmin;
 #pragma unroll
@@ -201,6 +215,7 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
         double mm = mins[0];
         for (int w = 1; w < kMicroThreads / kWave; ++w) mm = fmin(mm, mins[w]);
         A.len[inst] = v[0];
+        if (A.b2 != nullptr) A.len2[inst] = v[1];
         A.jmin[inst] = mm;
     }
 }

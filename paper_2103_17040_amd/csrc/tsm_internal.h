@@ -76,7 +76,14 @@ struct AssembleArgs {
     const int64_t* offsets;
     const double* amp;
     Tables tab;
-    double d, kappa, inv_dt;
+    double d, inv_dt;
+    // sides of Z in the order bottom (y2 = -1), top (y2 = +1), left (y1 = -1), right (y1 = +1)
+    double kside[4];      // Robin coefficient of each side in S (kappa on every side: whole-boundary exchange)
+    double bw[4];         // b = sum over sides of bw[side] (B_side 1)
+    double* b2;           // optional second load sum bw2[side] (B_side 1) (null: none)
+    double bw2[4];
+    double* len2;         // [n_inst] 1^T b2 (with b2)
+    double* m1;           // optional: M 1 (the integrals of eta_j J), may be null
     double* S64;          // [9 * total] : instance block at 9*off, coefficient-major [k][n]
     float* S32;           // S rounded to FP32
     float* Slo;           // S - S32 rounded to FP32: S32 + Slo equals S to about 2^-48 relative
@@ -168,6 +175,23 @@ struct MacroArgs {
     const double* len;    // [n_inst]
 };
 
+// The eliminated macro system of the stationary three-field model, solved by
+// one workgroup (Jacobi-PCG).
+struct StationaryMacroArgs {
+    int NM;                       // macro cells per side of [-1,1]^2
+    double Dw, k1, k2, k3, k4, fu, fw, uD;
+    int dirichlet[4];             // sides bottom, top, left, right: u prescribed
+    const double* lenI;           // [n] |G^I| = 1^T b_I per node
+    const double* lenO;           // [n] |G^O|
+    const double* dots;           // [5][n] b_I^T z^I, b_O^T z^O, b_I^T z^O, b_I^T z^0, b_O^T z^0
+    double* u;                    // [n] out
+    double* w;                    // [n] out
+    double* work;                 // [11 n] scratch
+    double rtol;
+    int max_iter;
+    double* info;                 // [2] out: iterations, final ||r|| / ||b||
+};
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s);
 // same gather for maps given by their Jacobian tables (a.Fcell, a.Fbnd)
@@ -191,6 +215,11 @@ hipError_t launch_bdot(int n_inst, const int64_t* offsets, const double* b, cons
 hipError_t launch_bdot_boundary(int n_tasks, const int32_t* order, const int32_t* level, const int64_t* offsets,
                                 const double* bc, const double* x, double* out, hipStream_t s);
 // bc[i * kBndStride + k] = b_i at boundary node bnd_node(N_i, k)
+hipError_t launch_stationary_macro(const StationaryMacroArgs& a, hipStream_t s);
+// v_i = z0_i + k1 u_i zI_i + k3 w_i zO_i (z0 may be null: zero), ragged
+hipError_t launch_stationary_micro(int n_inst, const int64_t* offsets, const double* z0, const double* zI,
+                                   const double* zO, const double* u, const double* w, double k1, double k3,
+                                   double* v, hipStream_t s);
 hipError_t launch_bnd_gather(int n_inst, const int32_t* level, const int64_t* offsets, const double* b, double* bc,
                              hipStream_t s);
 // residual sum of the alternating coupling: out[0] = ||R||_2 (nR interior macro rows),

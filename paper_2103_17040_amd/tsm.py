@@ -30,6 +30,7 @@ TSM_FLAG_FIXED_POINT = 1 << 5
 TSM_FLAG_GENERIC_16 = 1 << 6
 TSM_FLAG_GENERIC_32 = 1 << 7
 TSM_FLAG_GENERIC_64 = 1 << 8
+TSM_PART_N, TSM_PART_I, TSM_PART_O = 0, 1, 2
 
 STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV",
                 -4: "TSM_EHIP", -5: "TSM_ENOMEM", -6: "TSM_ESTATE"}
@@ -37,7 +38,8 @@ STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV
 EXPORTED = ["tsm_default_params", "tsm_create", "tsm_set_reference_mesh", "tsm_get_offsets",
             "tsm_set_deformation", "tsm_set_jacobians", "tsm_set_state", "tsm_step", "tsm_get_macro", "tsm_get_fluxes",
             "tsm_get_micro", "tsm_get_setup", "tsm_apply_operator", "tsm_gradient", "tsm_set_flags", "tsm_autotune", "tsm_get_stats",
-            "tsm_last_error", "tsm_destroy"]
+            "tsm_last_error", "tsm_destroy", "tsm_stationary_default_params", "tsm_stationary_create",
+            "tsm_stationary_solve", "tsm_stationary_get_stats"]
 
 
 class tsm_params(ctypes.Structure):
@@ -61,6 +63,22 @@ class tsm_stats(ctypes.Structure):
                 ("grad_forward_ms", ctypes.c_double), ("grad_backward_ms", ctypes.c_double),
                 ("sweeps_mean", ctypes.c_double),
                 ("fp_iters_last", ctypes.c_int32), ("fp_iters_max", ctypes.c_int32)]
+
+
+class tsm_stationary_params(ctypes.Structure):
+    _fields_ = [("macro_cells", ctypes.c_int32), ("Dv", ctypes.c_double), ("Dw", ctypes.c_double),
+                ("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double), ("kappa3", ctypes.c_double),
+                ("kappa4", ctypes.c_double), ("fu", ctypes.c_double), ("fv", ctypes.c_double),
+                ("fw", ctypes.c_double), ("u_dirichlet", ctypes.c_double), ("parts", ctypes.c_int32 * 4),
+                ("dirichlet", ctypes.c_int32 * 4), ("rtol", ctypes.c_double), ("macro_rtol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("macro_max_iter", ctypes.c_int32), ("flags", ctypes.c_uint64)]
+
+
+class tsm_stationary_stats(ctypes.Structure):
+    _fields_ = [("micro_iters_max", ctypes.c_int32 * 3), ("micro_iters_mean", ctypes.c_double * 3),
+                ("unconverged", ctypes.c_int32), ("macro_iters", ctypes.c_int32),
+                ("macro_rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("micro_ms", ctypes.c_double)]
 
 
 class TsmError(RuntimeError):
@@ -95,6 +113,10 @@ def _load():
         "tsm_get_stats": (I32, [P, ctypes.POINTER(tsm_stats)]),
         "tsm_last_error": (ctypes.c_char_p, [P]),
         "tsm_destroy": (None, [P]),
+        "tsm_stationary_default_params": (None, [ctypes.POINTER(tsm_stationary_params)]),
+        "tsm_stationary_create": (I32, [ctypes.POINTER(tsm_stationary_params), VP, ctypes.POINTER(P)]),
+        "tsm_stationary_solve": (I32, [P, VP, VP, VP]),
+        "tsm_stationary_get_stats": (I32, [P, ctypes.POINTER(tsm_stationary_stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -230,3 +252,31 @@ def tsm_last_error(ctx) -> str:
 
 def tsm_destroy(ctx) -> None:
     _lib.tsm_destroy(ctx)
+
+
+def tsm_stationary_default_params() -> tsm_stationary_params:
+    p = tsm_stationary_params()
+    _lib.tsm_stationary_default_params(ctypes.byref(p))
+    return p
+
+
+def tsm_stationary_create(params: tsm_stationary_params, stream=None):
+    out = ctypes.c_void_p()
+    st = _lib.tsm_stationary_create(ctypes.byref(params), stream, ctypes.byref(out))
+    if st != TSM_OK:
+        raise TsmError(st, "tsm_stationary_create: " + _lib.tsm_last_error(None).decode())
+    return out.value
+
+
+def tsm_stationary_solve(ctx, u_out, w_out, v_out=None) -> None:
+    _check(ctx, _lib.tsm_stationary_solve(ctx, _ptr(u_out), _ptr(w_out), _ptr(v_out)))
+
+
+def tsm_stationary_get_stats(ctx) -> dict:
+    s = tsm_stationary_stats()
+    _check(ctx, _lib.tsm_stationary_get_stats(ctx, ctypes.byref(s)))
+    out = {}
+    for name, _ in tsm_stationary_stats._fields_:
+        v = getattr(s, name)
+        out[name] = list(v) if hasattr(v, "__len__") else v
+    return out

@@ -66,12 +66,44 @@ def test_null_safety(lib_built):
     assert isinstance(tsm._lib.tsm_last_error(None), bytes)
 
 
+def STRUCTS(tsm):
+    return (("tsm_params", tsm.tsm_params), ("tsm_stats", tsm.tsm_stats),
+            ("tsm_stationary_params", tsm.tsm_stationary_params),
+            ("tsm_stationary_stats", tsm.tsm_stationary_stats))
+
+
+def test_stationary_params_defaults_and_validation(lib_built):
+    """Defaults are the Table 3 parameters; bad values are rejected on the
+    host before any device call."""
+    from paper_2103_17040_amd import tsm
+    p = tsm.tsm_stationary_default_params()
+    assert (p.Dv, p.Dw, p.kappa1, p.kappa2, p.kappa3, p.kappa4, p.u_dirichlet) == (1.0, 0.1, 0.5, 1.0, 0.25, 1.0, 1.0)
+    assert list(p.parts) == [tsm.TSM_PART_N, tsm.TSM_PART_N, tsm.TSM_PART_I, tsm.TSM_PART_O]
+    assert list(p.dirichlet) == [0, 0, 1, 0] and p.macro_cells == 8
+    cases = [("Dv", 0.0), ("Dw", -1.0), ("kappa3", 0.0), ("kappa2", float("inf")), ("fv", float("nan")),
+             ("macro_cells", 1), ("macro_cells", 257), ("max_iter", 0), ("macro_rtol", 0.0), ("flags", 1 << 5)]
+    for field, value in cases:
+        q = tsm.tsm_stationary_default_params()
+        setattr(q, field, value)
+        with pytest.raises(tsm.TsmError) as e:
+            tsm.tsm_stationary_create(q, None)
+        assert e.value.status == tsm.TSM_EINVAL, field
+    for parts, dirichlet in (((0, 0, 1, 1), (0, 0, 1, 0)), ((0, 0, 2, 2), (0, 0, 1, 0)),
+                             ((0, 0, 1, 3), (0, 0, 1, 0)), ((0, 0, 1, 2), (0, 0, 0, 0))):
+        q = tsm.tsm_stationary_default_params()
+        for s in range(4):
+            q.parts[s], q.dirichlet[s] = parts[s], dirichlet[s]
+        with pytest.raises(tsm.TsmError) as e:
+            tsm.tsm_stationary_create(q, None)
+        assert e.value.status == tsm.TSM_EINVAL, (parts, dirichlet)
+
+
 def test_struct_layouts_match_header(tmp_path):
     """The ctypes structs have the size and field offsets that a C compiler
     gives the header's structs."""
     from paper_2103_17040_amd import tsm
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tsm.h"', 'int main(void) {']
-    for cname, py in (("tsm_params", tsm.tsm_params), ("tsm_stats", tsm.tsm_stats)):
+    for cname, py in STRUCTS(tsm):
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
@@ -86,7 +118,7 @@ def test_struct_layouts_match_header(tmp_path):
         if ln:
             c, f, v = ln.split()
             want[(c, f)] = int(v)
-    for cname, py in (("tsm_params", tsm.tsm_params), ("tsm_stats", tsm.tsm_stats)):
+    for cname, py in STRUCTS(tsm):
         assert ctypes.sizeof(py) == want[(cname, "size")], cname
         for f, _ in py._fields_:
             assert getattr(py, f).offset == want[(cname, f)], (cname, f)

@@ -1,0 +1,194 @@
+"""GPU parity of the stationary three-field solve (paper Section 2.1 model,
+Case A/B experiments of Section 4.4) against the oracle's monolithic
+sparse solve, through the C ABI."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import stationary as st
+from gpu_helpers import banner, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+PHYS = dict(Dv=1.0, Dw=0.1, kappa1=0.5, kappa2=1.0, kappa3=0.25, kappa4=1.0)
+
+
+def _oracle(NM, levels, per, fu=0.0, fv=0.0, fw=0.0, uD=1.0, parts=(0, 0, 1, 2), dirichlet=(0, 0, 1, 0), **phys):
+    prm = st.StationaryParams(macro_cells=NM, parts=tuple(parts), dirichlet=tuple(bool(d) for d in dirichlet),
+                              **{**PHYS, **phys})
+    return st.solve(prm, levels, per, st.constant_data(fu=fu, fv=fv, fw=fw, u_dirichlet=uD))
+
+
+def _gpu(NM, levels, jac=None, a=None, theta=None, fu=0.0, fv=0.0, fw=0.0, uD=1.0, parts=(0, 0, 1, 2),
+         dirichlet=(0, 0, 1, 0), flags=0, rtol=1e-14, **phys):
+    from paper_2103_17040_amd import StationarySystem
+    g = StationarySystem(NM, levels, a, theta, jacobians=jac, parts=parts, dirichlet=dirichlet, flags=flags,
+                         fu=fu, fv=fv, fw=fw, u_dirichlet=uD, rtol=rtol, **{**PHYS, **phys})
+    try:
+        u, w, v = g.solve()
+        return u.cpu().numpy(), w.cpu().numpy(), v.cpu().numpy(), g.stats()
+    finally:
+        g.close()
+
+
+def _case_tables(case, NM, levels):
+    return W.jacobian_tables(np.asarray(levels), W.stationary_case_jacobian(case),
+                             [tuple(x) for x in W.stationary_macro_nodes(NM)])
+
+
+def _compare(ref, out, tol=TOL):
+    u, w, v, stats = out
+    eu, ew, ev = rel(u, ref["u"]), rel(w, ref["w"]), rel(v, np.concatenate(ref["v"]))
+    banner(f"  rel u {eu:.2e} w {ew:.2e} v {ev:.2e} micro iters {stats['micro_iters_max']} "
+           f"macro iters {stats['macro_iters']}")
+    assert eu <= tol and ew <= tol and ev <= tol, (eu, ew, ev)
+
+
+def test_operator_matches_oracle():
+    """S x = (Dv A + k2 B^I + k4 B^O) x per instance, ragged sizes incl. the
+    packed ones, Case B map."""
+    from paper_2103_17040_amd import StationarySystem
+    NM = 3
+    levels = np.array([4, 8, 16, 32] * 4, dtype=np.int32)
+    per, Fc, Fb = _case_tables("B", NM, levels)
+    banner(f"stationary operator NM={NM} levels={sorted(set(levels.tolist()))}")
+    g = StationarySystem(NM, levels, jacobians=(Fc, Fb), **PHYS)
+    try:
+        x = np.random.default_rng(3).standard_normal(g.n_micro)
+        y = g.apply(x).cpu().numpy()
+    finally:
+        g.close()
+    prm = st.StationaryParams(macro_cells=NM, **PHYS)
+    x1, x2 = st.macro_nodes(NM)
+    off = W.offsets(levels)
+    for k in range(len(levels)):
+        S = st.micro_system(prm, int(levels[k]), per[k][0], per[k][1], x1[k], x2[k], st.constant_data())[0]
+        ref = S @ x[off[k]:off[k + 1]]
+        assert rel(y[off[k]:off[k + 1]], ref) <= 1e-14
+
+
+CASES = {
+    # name: (NM, levels, geometry, sources, parts, dirichlet, phys)
+    "caseB_ragged": (4, [4, 8, 16, 32, 64], "B", dict(fu=0.3, fv=1.0, fw=-0.2), (0, 0, 1, 2), (0, 0, 1, 0), {}),
+    "caseA_packed16": (4, [16], "A", dict(fv=-0.5, uD=2.0), (0, 0, 1, 2), (0, 0, 1, 0), {}),
+    "amplitudes_ragged": (3, [8, 16, 32], "amp", dict(fv=0.7, fw=0.4), (0, 0, 1, 2), (0, 0, 1, 0), {}),
+    "parts_swapped": (3, [16, 32], "B", dict(fv=1.0, uD=-1.0), (1, 2, 0, 0), (1, 0, 1, 0),
+                      dict(kappa1=1.3, kappa2=0.6, kappa3=0.9, kappa4=2.0, Dw=0.5)),
+    "mixed_sides": (4, [12, 16, 24], "B", dict(fu=-0.4, fv=0.3), (1, 2, 1, 0), (0, 1, 0, 1),
+                    dict(Dv=0.6, Dw=0.05)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_matches_oracle(name):
+    NM, lv_set, geom, src, parts, dirichlet, phys = CASES[name]
+    n = (NM + 1) ** 2
+    levels = np.asarray([lv_set[i % len(lv_set)] for i in range(n)], dtype=np.int32)
+    banner(f"stationary {name}: NM={NM} levels={lv_set} geometry={geom}")
+    if geom == "amp":
+        rng = np.random.default_rng(11)
+        a = rng.uniform(-0.3, 0.3, n)
+        th = rng.uniform(0.0, np.pi / 8, n)
+        per, _, _ = W.jacobian_tables(levels, W.sinusoidal_map_jacobian, list(zip(a, th)))
+        out = _gpu(NM, levels, a=a, theta=th, parts=parts, dirichlet=dirichlet, **src, **phys)
+    else:
+        per, Fc, Fb = _case_tables(geom, NM, levels)
+        out = _gpu(NM, levels, jac=(Fc, Fb), parts=parts, dirichlet=dirichlet, **src, **phys)
+    ref = _oracle(NM, levels, per, parts=parts, dirichlet=dirichlet, **src, **phys)
+    _compare(ref, out)
+
+
+def test_launch_plans_agree():
+    """Per-size and persistent packed launches give the same bits; the
+    one-instance-per-workgroup kernels agree within the solver tolerance."""
+    from paper_2103_17040_amd import tsm
+    NM = 4
+    levels = np.asarray([[16, 32, 64, 8][i % 4] for i in range(25)], dtype=np.int32)
+    _, Fc, Fb = _case_tables("B", NM, levels)
+    banner("stationary launch plans")
+    base = _gpu(NM, levels, jac=(Fc, Fb), fv=1.0)
+    pers = _gpu(NM, levels, jac=(Fc, Fb), fv=1.0, flags=tsm.TSM_FLAG_PERSISTENT)
+    gen = _gpu(NM, levels, jac=(Fc, Fb), fv=1.0, flags=tsm.TSM_FLAG_GENERIC)
+    for a, b in zip(base[:3], pers[:3]):
+        assert np.array_equal(a, b)
+    for a, b in zip(base[:3], gen[:3]):
+        assert rel(b, a) <= TOL
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_table3_constant_state_at_paper_size(case):
+    """Table 3 data (no sources, u_0 = 1 on the left side, no flux
+    elsewhere) at the paper's sizes (81 macro, 4225 micro DoFs): the exact
+    solution is the constant state u = 1, v = k1/k2, w = k1 k4/(k2 k3)."""
+    lv, _, Fc, Fb = W.stationary_case(case, 8, 64)
+    banner(f"stationary Table 3 Case {case} constant state")
+    u, w, v, stats = _gpu(8, lv, jac=(Fc, Fb))
+    cv = PHYS["kappa1"] / PHYS["kappa2"]
+    cw = PHYS["kappa4"] * cv / PHYS["kappa3"]
+    assert np.max(np.abs(u - 1.0)) <= 1e-10
+    assert np.max(np.abs(w - cw)) <= 1e-10 * cw
+    assert np.max(np.abs(v - cv)) <= 1e-10
+
+
+def test_case_B_paper_size_matches_oracle():
+    """Case B at the paper's sizes with a unit micro source (the Table 3 data
+    alone give the constant state), against the oracle's sparse solve."""
+    lv, per, Fc, Fb = W.stationary_case("B", 8, 64)
+    banner("stationary Case B 81 x 4225 with f^v = 1")
+    out = _gpu(8, lv, jac=(Fc, Fb), fv=1.0)
+    ref = _oracle(8, lv, per, fv=1.0)
+    _compare(ref, out)
+
+
+def test_case_A_symmetry_at_paper_size():
+    """Case A is symmetric about the horizontal centre line (the Case B map
+    is what breaks the symmetry, Section 4.4)."""
+    lv, _, Fc, Fb = W.stationary_case("A", 8, 64)
+    banner("stationary Case A symmetry")
+    u, w, v, _ = _gpu(8, lv, jac=(Fc, Fb), fv=1.0, fu=0.5)
+    U, Wm = u.reshape(9, 9), w.reshape(9, 9)
+    assert np.max(np.abs(U - U[::-1])) <= 1e-10 * np.max(np.abs(U))
+    assert np.max(np.abs(Wm - Wm[::-1])) <= 1e-10 * np.max(np.abs(Wm))
+    assert np.ptp(u) > 1e-2
+
+
+def test_state_errors():
+    from paper_2103_17040_amd import StationarySystem, TwoScaleBatch, tsm
+    levels = np.full(9, 4, dtype=np.int32)
+    _, Fc, Fb = _case_tables("A", 2, levels)
+    banner("stationary state errors")
+    g = StationarySystem(2, levels, jacobians=(Fc, Fb))
+    try:
+        z = g.torch.zeros(9, dtype=g.torch.float64, device=g.device)
+        for call in (lambda: tsm.tsm_set_state(g.ctx, z, None), lambda: tsm.tsm_get_setup(g.ctx, z, z, None),
+                     lambda: tsm.tsm_step(g.ctx, 1)):
+            with pytest.raises(tsm.TsmError) as e:
+                call()
+            assert e.value.status == tsm.TSM_ESTATE
+    finally:
+        g.close()
+    t = TwoScaleBatch(2, levels, np.zeros(9))
+    try:
+        z = t.torch.zeros(9, dtype=t.torch.float64, device=t.device)
+        with pytest.raises(tsm.TsmError) as e:
+            tsm.tsm_stationary_solve(t.ctx, z, z, None)
+        assert e.value.status == tsm.TSM_ESTATE
+    finally:
+        t.close()
+    # solve before the geometry is set
+    p = tsm.tsm_stationary_default_params()
+    p.macro_cells = 2
+    ctx = tsm.tsm_stationary_create(p, None)
+    try:
+        import torch
+        z = torch.zeros(9, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(tsm.TsmError) as e:
+            tsm.tsm_stationary_solve(ctx, z, z, None)
+        assert e.value.status == tsm.TSM_ESTATE
+        tsm.tsm_set_reference_mesh(ctx, levels)
+        with pytest.raises(tsm.TsmError) as e:
+            tsm.tsm_stationary_solve(ctx, z, z, None)
+        assert e.value.status == tsm.TSM_ESTATE
+    finally:
+        tsm.tsm_destroy(ctx)

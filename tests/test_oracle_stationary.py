@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 import sympy as sy
 
+import workloads as W
 from oracle import fem
 from oracle import stationary as st
 
@@ -173,9 +174,9 @@ def test_table3_data_give_the_constant_state(case):
     """Table 3 (f^u = f^w = f^v = 0, u_0 = 1, no-flux elsewhere): the
     constant state (1, k1/k2, k1 k4/(k2 k3)) satisfies every equation."""
     prm = st.StationaryParams(macro_cells=4)
-    x1, x2 = st.macro_nodes(4)
-    levels = [4, 8] * 12 + [4]
-    jac = [st.constant_jacobians(N, st.map_jacobian(case, a, b)) for N, a, b in zip(levels, x1, x2)]
+    levels = np.array([4, 8] * 12 + [4])
+    jac, _, _ = W.jacobian_tables(levels, W.stationary_case_jacobian(case),
+                                  [tuple(x) for x in W.stationary_macro_nodes(4)])
     out = st.solve(prm, levels, jac, st.constant_data())
     cv = prm.kappa1 / prm.kappa2
     assert np.max(np.abs(out["u"] - 1.0)) < 1e-12
@@ -185,13 +186,11 @@ def test_table3_data_give_the_constant_state(case):
 
 def test_case_A_is_symmetric_about_the_centre_line():
     prm = st.StationaryParams(macro_cells=4)
-    x1, x2 = st.macro_nodes(4)
-    levels = [6] * 25
-    jac = [st.constant_jacobians(6, st.map_jacobian("A", a, b)) for a, b in zip(x1, x2)]
+    levels, jac, _, _ = W.stationary_case("A", 4, 6)
     out = st.solve(prm, levels, jac, st.constant_data(fv=1.0, fu=0.3))
     U = out["u"].reshape(5, 5)
-    W = out["w"].reshape(5, 5)
-    assert np.max(np.abs(U - U[::-1])) < 1e-12 and np.max(np.abs(W - W[::-1])) < 1e-12
+    Wm = out["w"].reshape(5, 5)
+    assert np.max(np.abs(U - U[::-1])) < 1e-12 and np.max(np.abs(Wm - Wm[::-1])) < 1e-12
     assert np.ptp(out["u"]) > 1e-2          # not the trivial constant state
     # v of node (k1, k2) is v of node (k1, 4 - k2) mirrored in z2
     for k in range(25):
@@ -199,7 +198,7 @@ def test_case_A_is_symmetric_about_the_centre_line():
         V = out["v"][k].reshape(7, 7)
         assert np.max(np.abs(V - out["v"][km].reshape(7, 7)[::-1])) < 1e-12
     # Case B breaks it
-    jb = [st.constant_jacobians(6, st.map_jacobian("B", a, b)) for a, b in zip(x1, x2)]
+    _, jb, _, _ = W.stationary_case("B", 4, 6)
     Ub = st.solve(prm, levels, jb, st.constant_data(fv=1.0, fu=0.3))["u"].reshape(5, 5)
     assert np.max(np.abs(Ub - Ub[::-1])) > 1e-4
 
@@ -254,7 +253,8 @@ def test_manufactured_convergence_orders():
         p = st.StationaryParams(**{**prm.__dict__, "macro_cells": N})
         nM = (N + 1) ** 2
         levels = [N] * nM
-        jac = [st.constant_jacobians(N, Fm)] * nM
+        jac, _, _ = W.jacobian_tables(np.array(levels), lambda y1, y2: np.broadcast_to(Fm, np.shape(y1) + (2, 2)),
+                                      [()] * nM)
         out = st.solve(p, levels, jac, data)
         a0, a1 = _q1_errors(N, -1.0, out["u"], uf, lambda s, t: np.array([gu[0](s, t), gu[1](s, t)]))
         b0, b1 = _q1_errors(N, -1.0, out["w"], wf, lambda s, t: np.array([gw[0](s, t), gw[1](s, t)]))

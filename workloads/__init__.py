@@ -254,3 +254,40 @@ def polynomial_map_params(n_inst: int, seed: int = 0, strength: float = 0.25):
     d = rng.uniform(-strength, strength, n_inst)
     th = rng.uniform(0.0, 2.0 * math.pi, n_inst)
     return list(zip(c.tolist(), d.tolist(), th.tolist()))
+
+
+# ---------------------------------------------------------------------------
+# The stationary three-field experiments (Section 4.4): macro domain
+# [-1,1]^2, one micro system per macro node, the Table 3 parameters and two
+# maps, zeta_0(x, y) = y (Case A) and the heterogeneous zeta_1 (Case B),
+#   zeta_1(x, y) = ((2 x1 + 3) y1 / 4 - x2 y2 / 5,  (2 - x2) y2 / 4),
+# both affine in y.  The paper's runs have 81 macro and 4225 micro DoFs.
+# ---------------------------------------------------------------------------
+
+def stationary_macro_nodes(macro_cells: int) -> np.ndarray:
+    """Node coordinates of the macro mesh of [-1,1]^2, shape (n_inst, 2), x1 fastest."""
+    t = -1.0 + 2.0 * np.arange(macro_cells + 1, dtype=np.float64) / macro_cells
+    x1, x2 = np.meshgrid(t, t, indexing="xy")
+    return np.stack([x1.ravel(), x2.ravel()], axis=1)
+
+
+def stationary_case_jacobian(case: str):
+    """D_y zeta of the Case A or Case B map as jac_fn(y1, y2, x1, x2) for
+    jacobian_tables (params: the macro node of each instance)."""
+    if case not in ("A", "B"):
+        raise ValueError(case)
+
+    def fn(y1, y2, x1, x2):
+        F = np.eye(2) if case == "A" else np.array([[(2.0 * x1 + 3.0) / 4.0, -x2 / 5.0], [0.0, (2.0 - x2) / 4.0]])
+        return np.broadcast_to(F, np.shape(y1) + (2, 2)).copy()
+    return fn
+
+
+def stationary_case(case: str, macro_cells: int = 8, micro_cells: int = 64):
+    """(levels, per-instance tables, flat cell table, flat boundary table) of
+    Case A or B at the given sizes (the paper's: 8 and 64)."""
+    n = (macro_cells + 1) ** 2
+    lv = np.full(n, micro_cells, dtype=np.int32)
+    per, Fc, Fb = jacobian_tables(lv, stationary_case_jacobian(case),
+                                  [tuple(x) for x in stationary_macro_nodes(macro_cells)])
+    return lv, per, Fc, Fb
