@@ -250,6 +250,50 @@ def _rel(x, ref):
     return float(np.linalg.norm(x - ref) / (den if den > 0 else 1.0))
 
 
+def stationary_leg(reps, parity=True):
+    """The paper's stationary three-field system (Section 2.1 model) on the
+    Case B map with the Table 3 parameters and a unit micro source (the
+    Table 3 data alone give the constant state), at the paper's size (81
+    macro x 4225 micro DoFs, checked against the oracle's solution stored in
+    tests/golden) and on a 4225-node macro mesh (17.8M micro DoFs).  Each
+    solve: three batched FP64 micro PCG solves per instance, the macro PCG,
+    the micro fields; times from HIP events around the solve, median of
+    `reps` solves after one warm-up."""
+    import statistics
+    from paper_2103_17040_amd import StationarySystem
+    res = {}
+    for name, NM in (("case_B_81x4225", 8), ("case_B_4225x4225", 64)):
+        lv, _, Fc, Fb = W.stationary_case("B", NM, 64)
+        g = StationarySystem(NM, lv, jacobians=(Fc, Fb), fv=1.0)
+        try:
+            g.solve()
+            ms, micro = [], []
+            for _ in range(reps):
+                u, w, v = g.solve()
+                st = g.stats()
+                ms.append(st["solve_ms"])
+                micro.append(st["micro_ms"])
+            u, w, v = (t.cpu().numpy() for t in (u, w, v))
+        finally:
+            g.close()
+        n_micro = int(W.offsets(lv)[-1])
+        t_micro = statistics.median(micro) * 1e-3
+        dof_iters = n_micro * sum(st["micro_iters_mean"])
+        ent = {"macro_nodes": len(lv), "micro_dofs": n_micro, "solve_ms": statistics.median(ms),
+               "micro_ms": statistics.median(micro), "micro_iters_mean": st["micro_iters_mean"],
+               "micro_iters_max": st["micro_iters_max"], "macro_iters": st["macro_iters"],
+               "micro_dof_iterations_per_s": dof_iters / t_micro,
+               # a PCG streaming its FP64 vectors: 10 words per DoF and iteration
+               "streaming_model_GBs": dof_iters * 80.0 / t_micro / 1e9}
+        if parity and NM == 8:
+            ref = np.load(os.path.join(GOLD, "stationary_caseB.npz"), allow_pickle=False)
+            off = W.offsets(lv)
+            vs = np.concatenate([v[off[i]:off[i + 1]] for i in ref["inst"]])
+            ent["parity_vs_oracle"] = {"u": _rel(u, ref["u"]), "w": _rel(w, ref["w"]), "v_sampled": _rel(vs, ref["v"])}
+        res[name] = ent
+    return res
+
+
 def parity_leg():
     """Relative discrete l2 errors of every output against the FP64 oracle's
     outputs stored in tests/golden (written by tests/golden/make_goldens.py,
@@ -344,6 +388,8 @@ def main():
                     help="launch plan of the micro solves (auto: the autotuner picks on the live state)")
     ap.add_argument("--no-parity", action="store_true",
                     help="skip the parity leg (errors against the oracle's stored outputs)")
+    ap.add_argument("--st-reps", type=int, default=3,
+                    help="stationary three-field solves timed per size (0: skip that leg)")
     ap.add_argument("--gm-steps", type=int, default=5,
                     help="steps of the general-map leg (Jacobian tables, uneven batch; 0: skip)")
     ap.add_argument("--fp-steps", type=int, default=3,
@@ -482,6 +528,9 @@ def main():
     if args.gm_steps > 0:
         _log("general-map leg ...")
         out["general_map"] = general_map_leg(args.gm_steps)
+    if args.st_reps > 0:
+        _log("stationary three-field leg ...")
+        out["stationary"] = stationary_leg(args.st_reps, parity=not args.no_parity)
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, a, th, lv)

@@ -1,12 +1,14 @@
 """Write the oracle's expected outputs for the full-size parity tests.
 
-    python tests/golden/make_goldens.py [batched_fp64 uneven_mixed adjoint_fp64]
+    python tests/golden/make_goldens.py [batched_fp64 uneven_mixed adjoint_fp64 stationary_caseB]
 
 Calls only the FP64 oracle and the seeded input generators (seed 0).  Each
 file stores a compact, sampled set of outputs (compressed .npz, no pickles):
 macro fields at a few steps, all fluxes of the first and last step, the micro
 field of a few sampled instances at the end, the response functionals, and
-for the adjoint workload J and dJ/da.
+for the adjoint workload J and dJ/da; for the stationary Case B solve
+(81 macro x 4225 micro DoFs, Table 3 parameters with a unit micro source)
+u, w and v of nine instances spread over the macro mesh.
 """
 import os
 import sys
@@ -19,7 +21,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402
-from oracle import adjoint, twoscale  # noqa: E402
+from oracle import adjoint, stationary, twoscale  # noqa: E402
 
 SAMPLE_STEPS = (1, 2, 10)
 
@@ -80,10 +82,23 @@ def adjoint_golden(name="adjoint_fp64"):
     np.savez_compressed(os.path.join(HERE, f"{name}_seed0.npz"), J=np.array(J), g=g)
 
 
+def stationary_golden(name="stationary_caseB"):
+    lv, per, _, _ = W.stationary_case("B", 8, 64)
+    t0 = time.time()
+    out = stationary.solve(stationary.StationaryParams(macro_cells=8), lv, per,
+                           stationary.constant_data(fv=1.0))
+    print(f"{name}: solve {time.time() - t0:.1f} s", flush=True)
+    inst = np.array([0, 8, 20, 31, 40, 49, 60, 72, 80], dtype=np.int64)
+    np.savez_compressed(os.path.join(HERE, f"{name}.npz"), u=out["u"], w=out["w"], inst=inst,
+                        v=np.concatenate([out["v"][i] for i in inst]))
+
+
 if __name__ == "__main__":
-    names = sys.argv[1:] or ["batched_fp64", "uneven_mixed", "adjoint_fp64"]
+    names = sys.argv[1:] or ["batched_fp64", "uneven_mixed", "adjoint_fp64", "stationary_caseB"]
     for nm in names:
         if nm == "adjoint_fp64":
             adjoint_golden(nm)
+        elif nm == "stationary_caseB":
+            stationary_golden(nm)
         else:
             forward_golden(nm)
