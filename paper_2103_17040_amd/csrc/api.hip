@@ -110,7 +110,12 @@ struct tsm_ctx {
     tsm_stationary_params sp{};
     double *st_bO = nullptr, *st_lenO = nullptr, *st_m1 = nullptr, *st_zI = nullptr, *st_zO = nullptr,
            *st_z0 = nullptr, *st_dots = nullptr, *st_w = nullptr, *st_work = nullptr, *st_info = nullptr;
-    int32_t* st_iters = nullptr;
+    int32_t *st_iters = nullptr, *st_sweeps = nullptr;
+    // the three micro solves run side by side: two more streams (default
+    // priority), their work counters and the fork/join events
+    hipStream_t st_side[2] = {nullptr, nullptr};
+    int32_t* st_queue = nullptr;
+    hipEvent_t st_ev[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_mid = nullptr;
     tsm_stationary_stats st_stats{};
 
@@ -138,7 +143,7 @@ struct tsm_ctx {
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
         dfree(st_bO); dfree(st_lenO); dfree(st_m1); dfree(st_zI); dfree(st_zO); dfree(st_z0); dfree(st_dots);
-        dfree(st_w); dfree(st_work); dfree(st_info); dfree(st_iters);
+        dfree(st_w); dfree(st_work); dfree(st_info); dfree(st_iters); dfree(st_sweeps);
         drop_graph();
         have_mesh = have_geom = have_state = false;
     }
@@ -185,7 +190,9 @@ namespace {
 
 // One batched micro solve: the packed launch (16/32/64 cells) and one
 // generic launch per remaining slot class.  setup: FP64 whatever the precision.
-tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
+// On stream st with the persistent work counter queue (the context's own,
+// or another for launches that run beside it).
+tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st, int32_t* queue) {
     const bool refine = c->prm.precision == TSM_FP32_REFINE && !setup;
     // the packed kernels leave b^T x to one boundary pass over their instances
     MicroArgs pbase = base;
@@ -198,13 +205,13 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
         a.n_tasks = (int)c->n_inst;
         a.order = c->order;
         a.order_off = c->order_off;
-        a.queue = c->queue;
-        HIPCHK(launch_fill_i32(c->queue, 0, 1, c->stream));
+        a.queue = queue;
+        HIPCHK(launch_fill_i32(queue, 0, 1, st));
         const int grid = std::min(c->n_packs, c->n_cu);
         if (c->pack_groups.size() == 1)   // one mesh size: its own kernel, same queue
-            HIPCHK(launch_packed(a, pl, c->pack_groups[0][0], refine ? 2 : 1, grid, c->stream));
+            HIPCHK(launch_packed(a, pl, c->pack_groups[0][0], refine ? 2 : 1, grid, st));
         else
-            HIPCHK(launch_packed_mixed(a, pl, c->pk_level, refine ? 2 : 1, grid, c->pack_lds_max, c->stream));
+            HIPCHK(launch_packed_mixed(a, pl, c->pk_level, refine ? 2 : 1, grid, c->pack_lds_max, st));
     } else {
         for (const auto& pg : c->pack_groups) {
             PackList pl{pg[2], c->pk_first + pg[1], c->pk_count + pg[1], c->pk_slot_inst + (int64_t)pg[1] * kPackSlots,
@@ -213,12 +220,12 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
             a.n_tasks = (int)c->n_inst;
             a.order = c->order;
             a.order_off = c->order_off;
-            HIPCHK(launch_packed(a, pl, pg[0], refine ? 2 : 1, pg[2], c->stream));
+            HIPCHK(launch_packed(a, pl, pg[0], refine ? 2 : 1, pg[2], st));
         }
     }
     if (c->n_packs > 0 && base.bx_out != nullptr)
         HIPCHK(launch_bdot_boundary((int)c->n_packed_tasks, c->order, c->level, c->offsets, c->bcomp, base.X_out,
-                                    base.bx_out, c->stream));
+                                    base.bx_out, st));
     for (const Group& g : c->groups) {
         MicroArgs a = base;
         a.n_tasks = g.count;
@@ -228,9 +235,13 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
         const int NP = g.max_level + 1;
         const size_t n_pad = (size_t)NP * NP + 2 * (size_t)(NP + 1);
         const size_t lds = n_pad * (sizeof(double) + sizeof(float));
-        HIPCHK(launch_micro(a, g.slots, mode, g.count, lds, c->stream));
+        HIPCHK(launch_micro(a, g.slots, mode, g.count, lds, st));
     }
     return TSM_OK;
+}
+
+tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup) {
+    return enqueue_micro(c, base, setup, c->stream, c->queue);
 }
 
 // Task order, packs and generic groups for the current mesh and flags.
@@ -614,7 +625,7 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
         HIPALLOC(c->st_bO, tot); HIPALLOC(c->st_lenO, ni); HIPALLOC(c->st_m1, tot);
         HIPALLOC(c->st_zI, tot); HIPALLOC(c->st_zO, tot); HIPALLOC(c->st_z0, tot);
         HIPALLOC(c->st_dots, 5 * ni); HIPALLOC(c->st_w, ni); HIPALLOC(c->st_work, 11 * ni);
-        HIPALLOC(c->st_info, 2); HIPALLOC(c->st_iters, 3 * ni);
+        HIPALLOC(c->st_info, 2); HIPALLOC(c->st_iters, 3 * ni); HIPALLOC(c->st_sweeps, 3 * ni);
     }
     HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());
@@ -1316,8 +1327,18 @@ tsm_status tsm_stationary_create(const tsm_stationary_params* sp, void* stream, 
     p.flags = sp->flags;
     const tsm_status st = tsm_create(&p, stream, out);
     if (st != TSM_OK) return st;
-    (*out)->stationary = true;
-    (*out)->sp = *sp;
+    tsm_ctx* c = *out;
+    c->stationary = true;
+    c->sp = *sp;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&c->st_side[k], hipStreamNonBlocking);
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&c->st_ev[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = dalloc(&c->st_queue, 2);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return create_failed(c, TSM_EHIP, std::string("stationary context resources: ") + hipGetErrorString(e));
+    }
     return TSM_OK;
 }
 
@@ -1331,11 +1352,25 @@ tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double
     if (!c->ev_mid) HIPCHK(hipEventCreate(&c->ev_mid));
     HIPCHK(hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->stream));
     HIPCHK(hipEventRecord(c->ev0, c->stream));
-    // three batched micro solves (FP64, zero initial guess)
+    // the three batched micro solves (FP64, zero initial guess) are
+    // independent: they run side by side on the context's stream and the two
+    // side streams, each with its own work counter, so that a small batch
+    // still fills the chip.  Each leaves b_I^T x (the kernels' b is b_I):
+    // b_I^T z^I, b_I^T z^O and b_I^T z^0 come with the solves.
     const bool with_f = sp.fv != 0.0;
+    const int n_solve = with_f ? 3 : 2;
     const double* rhs[3] = {c->b, c->st_bO, c->st_m1};
     const double scale[3] = {1.0, 1.0, sp.fv};
     double* sol[3] = {c->st_zI, c->st_zO, c->st_z0};
+    double* bx[3] = {c->st_dots, c->st_dots + 2 * ni, c->st_dots + 3 * ni};
+    hipStream_t strm[3] = {c->stream, c->st_side[0], c->st_side[1]};
+    int32_t* queue[3] = {c->queue, c->st_queue, c->st_queue + 1};
+    if (!with_f) {
+        HIPCHK(launch_fill_i32(c->st_iters + 2 * ni, 0, (int)ni, c->stream));
+        HIPCHK(hipMemsetAsync(c->st_dots + 3 * ni, 0, 2 * ni * sizeof(double), c->stream));
+    }
+    HIPCHK(hipEventRecord(c->st_ev[0], c->stream));
+    for (int q = 1; q < n_solve; ++q) HIPCHK(hipStreamWaitEvent(strm[q], c->st_ev[0], 0));
     MicroArgs ma = micro_base(c);
     ma.X0 = nullptr;
     ma.coef = nullptr;
@@ -1343,30 +1378,27 @@ tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double
     ma.inv_dt = 0.0;
     ma.rtol = sp.rtol;
     ma.max_iter = sp.max_iter;
-    for (int q = 0; q < 3; ++q) {
-        if (q == 2 && !with_f) {
-            HIPCHK(launch_fill_i32(c->st_iters + 2 * ni, 0, (int)ni, c->stream));
-            continue;
-        }
+    for (int q = 0; q < n_solve; ++q) {
         ma.rhs_vec = rhs[q];
         ma.rhs_scale = scale[q];
         ma.X_out = sol[q];
-        const tsm_status st = enqueue_micro(c, ma, true);
-        if (st != TSM_OK) return st;
-        HIPCHK(hipMemcpyAsync(c->st_iters + q * ni, c->iters, ni * sizeof(int32_t), hipMemcpyDeviceToDevice,
-                              c->stream));
+        ma.bx_out = bx[q];
+        ma.iters_out = c->st_iters + q * ni;
+        ma.sweeps_out = c->st_sweeps + q * ni;
+        const tsm_status st = enqueue_micro(c, ma, true, strm[q], queue[q]);
+        if (st != TSM_OK) {
+            (void)hipDeviceSynchronize();   // nothing left running on the side streams
+            return st;
+        }
+    }
+    for (int q = 1; q < n_solve; ++q) {
+        HIPCHK(hipEventRecord(c->st_ev[q], strm[q]));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->st_ev[q], 0));
     }
     HIPCHK(hipEventRecord(c->ev_mid, c->stream));
-    // b_I^T z^I, b_O^T z^O, b_I^T z^O, b_I^T z^0, b_O^T z^0
-    HIPCHK(launch_bdot((int)ni, c->offsets, c->b, c->st_zI, c->st_dots, c->stream));
+    // b_O^T z^O and b_O^T z^0
     HIPCHK(launch_bdot((int)ni, c->offsets, c->st_bO, c->st_zO, c->st_dots + ni, c->stream));
-    HIPCHK(launch_bdot((int)ni, c->offsets, c->b, c->st_zO, c->st_dots + 2 * ni, c->stream));
-    if (with_f) {
-        HIPCHK(launch_bdot((int)ni, c->offsets, c->b, c->st_z0, c->st_dots + 3 * ni, c->stream));
-        HIPCHK(launch_bdot((int)ni, c->offsets, c->st_bO, c->st_z0, c->st_dots + 4 * ni, c->stream));
-    } else {
-        HIPCHK(hipMemsetAsync(c->st_dots + 3 * ni, 0, 2 * ni * sizeof(double), c->stream));
-    }
+    if (with_f) HIPCHK(launch_bdot((int)ni, c->offsets, c->st_bO, c->st_z0, c->st_dots + 4 * ni, c->stream));
     StationaryMacroArgs m{};
     m.NM = c->NM;
     m.Dw = sp.Dw;
@@ -1444,6 +1476,14 @@ void tsm_destroy(tsm_ctx* c) {
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev_mid) (void)hipEventDestroy(c->ev_mid);
+    for (hipEvent_t e : c->st_ev)
+        if (e) (void)hipEventDestroy(e);
+    dfree(c->st_queue);
+    for (hipStream_t s : c->st_side)
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
