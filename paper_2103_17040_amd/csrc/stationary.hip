@@ -16,7 +16,9 @@
 // (k3/sqrt k4 w - sqrt k4 v)^2 on G^I and G^O.  K is the Q1 stiffness of
 // the uniform macro mesh, applied matrix-free.  The system is small (two
 // values per macro node), so one workgroup runs the whole Jacobi-PCG with
-// its vectors in global memory and block reductions in a fixed order.
+// block reductions in a fixed order; its vectors live in global memory,
+// except the search direction -- the one vector read at neighbouring nodes
+// -- which sits in LDS when it fits (up to kMacroLdsNodes nodes).
 #include "device_common.h"
 
 namespace tsm {
@@ -25,6 +27,7 @@ namespace {
 
 constexpr int NT = 1024;
 constexpr int NW = NT / kWave;
+constexpr int kMacroLdsNodes = 9216;    // 2 x 9216 doubles = 144 KB of LDS
 
 // (K p)_k: the rows of the Q1 element stiffness of the cells at node
 // (k1, k2).  On a square cell it is 2/3 on the diagonal, -1/6 between
@@ -62,8 +65,10 @@ __device__ bool dirichlet_node(const StationaryMacroArgs& A, int k1, int k2) {
            (A.dirichlet[3] && k1 == A.NM);
 }
 
+template <bool LDSP>
 __global__ __launch_bounds__(NT) void stationary_macro_kernel(StationaryMacroArgs A) {
     __shared__ double red_s[2][2][NW];
+    __shared__ double p_s[LDSP ? 2 * kMacroLdsNodes : 1];
     BlockReducer<NW, 2, double> red(red_s);
     const int NM = A.NM, W = NM + 1, n = W * W;
     const double H = 2.0 / NM;
@@ -72,9 +77,9 @@ __global__ __launch_bounds__(NT) void stationary_macro_kernel(StationaryMacroArg
     double* xw = A.w;
     double* ru = A.work;
     double* rw = ru + n;
-    double* pu = rw + n;
-    double* pw = pu + n;
-    double* qu = pw + n;
+    double* pu = LDSP ? p_s : rw + n;
+    double* pw = LDSP ? p_s + kMacroLdsNodes : rw + 2 * n;
+    double* qu = rw + 3 * n;
     double* qw = qu + n;
     double* cuu = qw + n;
     double* cww = cuu + n;
@@ -153,8 +158,8 @@ __global__ __launch_bounds__(NT) void stationary_macro_kernel(StationaryMacroArg
         rr = s2[1];
         const double beta = s2[0] / rz;
         rz = s2[0];
-        // every thread reads only its own entries of r and p here, and the
-        // next apply reads p after the barrier in the reduction
+        // p = D^{-1} r + beta p at the thread's own nodes; the barrier below
+        // orders these writes before the next apply reads p at neighbours
         for (int k = threadIdx.x; k < n; k += NT) {
             const int k1 = k % W, k2 = k / W;
             const double kd = (2.0 / 3.0) * cells_at(NM, k1, k2);
@@ -185,7 +190,11 @@ __global__ void stationary_micro_kernel(int n_inst, const int64_t* offsets, cons
 }  // namespace
 
 hipError_t launch_stationary_macro(const StationaryMacroArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(stationary_macro_kernel, dim3(1), dim3(NT), 0, s, a);
+    const int n = (a.NM + 1) * (a.NM + 1);
+    if (n <= kMacroLdsNodes)
+        hipLaunchKernelGGL(stationary_macro_kernel<true>, dim3(1), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL(stationary_macro_kernel<false>, dim3(1), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 

@@ -8,7 +8,8 @@ macro fields at a few steps, all fluxes of the first and last step, the micro
 field of a few sampled instances at the end, the response functionals, and
 for the adjoint workload J and dJ/da; for the stationary Case B solve
 (81 macro x 4225 micro DoFs, Table 3 parameters with a unit micro source)
-u, w and v of nine instances spread over the macro mesh.
+u, w and v of nine instances spread over the macro mesh; for a 9409-node
+macro mesh with 2 x 2 micro meshes u, w and v.
 """
 import os
 import sys
@@ -93,12 +94,26 @@ def stationary_golden(name="stationary_caseB"):
                         v=np.concatenate([out["v"][i] for i in inst]))
 
 
+def stationary_large_macro_golden(name="stationary_large_macro"):
+    """Case B map on a 97 x 97 macro mesh (9409 nodes) with 2 x 2 micro
+    meshes, unit micro source and f^u = 0.2: u, w and v of every instance."""
+    lv, per, _, _ = W.stationary_case("B", 96, 2)
+    t0 = time.time()
+    out = stationary.solve(stationary.StationaryParams(macro_cells=96), lv, per,
+                           stationary.constant_data(fv=1.0, fu=0.2))
+    print(f"{name}: solve {time.time() - t0:.1f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, f"{name}.npz"), u=out["u"], w=out["w"], v=np.concatenate(out["v"]))
+
+
 if __name__ == "__main__":
-    names = sys.argv[1:] or ["batched_fp64", "uneven_mixed", "adjoint_fp64", "stationary_caseB"]
+    names = sys.argv[1:] or ["batched_fp64", "uneven_mixed", "adjoint_fp64", "stationary_caseB",
+                             "stationary_large_macro"]
     for nm in names:
         if nm == "adjoint_fp64":
             adjoint_golden(nm)
         elif nm == "stationary_caseB":
             stationary_golden(nm)
+        elif nm == "stationary_large_macro":
+            stationary_large_macro_golden(nm)
         else:
             forward_golden(nm)

@@ -192,3 +192,31 @@ def test_state_errors():
         assert e.value.status == tsm.TSM_ESTATE
     finally:
         tsm.tsm_destroy(ctx)
+
+
+def test_large_macro_mesh_matches_oracle():
+    """9409 macro nodes (more than the search direction's LDS capacity, so
+    the macro PCG keeps it in global memory) with 2 x 2 micro meshes (the
+    one-instance-per-workgroup kernels), against the oracle's solution stored
+    by tests/golden/make_goldens.py."""
+    import os
+    lv, _, Fc, Fb = W.stationary_case("B", 96, 2)
+    banner("stationary 9409 macro nodes x 2^2 micro")
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "stationary_large_macro.npz"),
+                  allow_pickle=False)
+    u, w, v, stats = _gpu(96, lv, jac=(Fc, Fb), fv=1.0, fu=0.2)
+    banner(f"  rel u {rel(u, ref['u']):.2e} w {rel(w, ref['w']):.2e} v {rel(v, ref['v']):.2e} "
+           f"macro iters {stats['macro_iters']}")
+    assert rel(u, ref["u"]) <= TOL and rel(w, ref["w"]) <= TOL and rel(v, ref["v"]) <= TOL
+
+
+def test_constant_state_on_a_large_macro_mesh():
+    """The Table 3 constant state on 101 x 101 macro nodes (closed form)."""
+    lv, _, Fc, Fb = W.stationary_case("A", 100, 4)
+    banner("stationary constant state 10201 macro nodes")
+    u, w, v, _ = _gpu(100, lv, jac=(Fc, Fb))
+    cv = PHYS["kappa1"] / PHYS["kappa2"]
+    cw = PHYS["kappa4"] * cv / PHYS["kappa3"]
+    assert np.max(np.abs(u - 1.0)) <= 1e-10
+    assert np.max(np.abs(w - cw)) <= 1e-10 * cw
+    assert np.max(np.abs(v - cv)) <= 1e-10
