@@ -460,10 +460,9 @@ def main():
         kname = "packed_kernel (micro PCG)"
     if 0 < n_packed and any(not packed_under(int(N), plan_flags) for N in set(lv.tolist())):
         kname += " + micro_kernel"
-    # achieved: the algorithmic bytes of one DoF-update as the survey's
-    # measurement plan counts them (a PCG that streams its vectors through
-    # HBM every iteration) times the DoF-updates of one launch, over the
-    # launch time.  Above 1 means the kernel needs fewer bytes than that
+    # achieved: the algorithmic bytes of one DoF-update of a PCG that
+    # streams its vectors through HBM every iteration, times the DoF-updates
+    # of one launch, over the launch time.  Above 1 means the kernel needs fewer bytes than that
     # model, since it keeps every vector on chip; the kernel's own minimum
     # (resident) bytes, the counter-measured traffic and the ALU share are
     # reported beside it.
