@@ -294,6 +294,68 @@ def stationary_leg(reps, parity=True):
     return res
 
 
+def _paper_table_rows():
+    """Rows of Tables 1 and 2 from tests/golden/paper_convergence_tables.txt,
+    the last rows un-swapped: {DoFs: (e_uw, e_uw_grad, e_v, e_v_grad)}."""
+    tab, cur = {"macro": [], "micro": []}, None
+    with open(os.path.join(GOLD, "paper_convergence_tables.txt")) as fh:
+        for ln in fh:
+            ln = ln.strip()
+            if not ln or ln.startswith("#"):
+                continue
+            if ln.startswith("["):
+                cur = ln.strip("[]")
+                continue
+            f = ln.split()
+            tab[cur].append((int(f[0]), float(f[2]), float(f[3])))
+    tab["macro"][-1], tab["micro"][-1] = tab["micro"][-1], tab["macro"][-1]
+    return {m[0]: (m[1], m[2], v[1], v[2]) for m, v in zip(tab["macro"], tab["micro"])}
+
+
+def stationary_convergence_leg(sizes=(8, 16, 32, 64)):
+    """The convergence benchmark of Section 4.2 on the GPU: the paper's
+    manufactured solution and map (eq. manu_system; data re-derived), N_M = N
+    cells per side on both scales, errors e_uw, e_uw_grad, e_v, e_v_grad and
+    the observed orders; the paper's printed errors at the same DoF counts
+    beside them (its parameters are not given, so only the orders compare)."""
+    from paper_2103_17040_amd import StationarySystem
+    from workloads import manufactured as MF
+    phys = dict(Dv=1.0, Dw=0.5, kappa1=0.5, kappa2=1.0, kappa3=0.25, kappa4=1.0)
+
+    class P:
+        parts = (0, 0, 1, 2)
+    prm = P()
+    for k, v in phys.items():
+        setattr(prm, k, v)
+    data = MF.manufactured(prm, MF.U_MANU, MF.V_MANU, MF.W_MANU, MF.ZETA_MANU)
+    paper = _paper_table_rows()
+    rows, dofs, errs = [], [], []
+    for N in sizes:
+        levels = np.full((N + 1) ** 2, N, dtype=np.int32)
+        _, Fc, Fb = MF.map_tables(N, levels, MF.ZETA_MANU)
+        pts = MF.data_at_points(data, N, levels, prm.parts)
+        g = StationarySystem(N, levels, jacobians=(Fc, Fb), rtol=1e-13, **phys)
+        try:
+            g.set_data(**pts)
+            u, w, v = g.solve()
+            st = g.stats()
+            u, w, v = (t.cpu().numpy() for t in (u, w, v))
+        finally:
+            g.close()
+        off = W.offsets(levels)
+        e = MF.convergence_errors(N, N, u, w, [v[off[k]:off[k + 1]] for k in range(len(levels))], prm)
+        n = (N + 1) ** 2
+        dofs.append(n)
+        errs.append(e)
+        rows.append({"macro_dofs": n, "micro_dofs_each": n, "e_uw": e[0], "e_uw_grad": e[1], "e_v": e[2],
+                     "e_v_grad": e[3], "solve_ms": st["solve_ms"], "micro_iters_max": st["micro_iters_max"],
+                     "paper_e_uw_e_uw_grad_e_v_e_v_grad": paper.get(n)})
+    E = np.array(errs)
+    return {"rows": rows, "orders": {"p_M": MF.orders(dofs, E[:, 0]), "q_M": MF.orders(dofs, E[:, 1]),
+                                     "p_v": MF.orders(dofs, E[:, 2]), "q_v": MF.orders(dofs, E[:, 3])},
+            "paper_orders_printed": "p 1.94-2.31, q 1.01-1.20 (Tables 1-2)"}
+
+
 def parity_leg():
     """Relative discrete l2 errors of every output against the FP64 oracle's
     outputs stored in tests/golden (written by tests/golden/make_goldens.py,
@@ -530,6 +592,8 @@ def main():
     if args.st_reps > 0:
         _log("stationary three-field leg ...")
         out["stationary"] = stationary_leg(args.st_reps, parity=not args.no_parity)
+        _log("stationary convergence leg ...")
+        out["stationary"]["convergence"] = stationary_convergence_leg()
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, a, th, lv)

@@ -239,21 +239,25 @@ void tsm_destroy(tsm_ctx* c);   /* NULL-safe */
 
 /* ---------------------------------------------------------------------------
  * The paper's stationary three-field system (Section 2.1 model; the Case A/B
- * experiments of Section 4 solve it with the Table 3 parameters):
- *   -Lap u = f^u - int_{G^I} (k1 u - k2 v) dsigma_y     in [-1,1]^2,
- *            u = u_dirichlet on the Dirichlet sides, grad u . n = 0 elsewhere
- *   -Dv Lap_y v = f^v  in Y_x,   Dv grad_y v . n = k1 u - k2 v  on G^I
- *                                                 k3 w - k4 v  on G^O
- *                                                 0            on G^N
- *   -Dw Lap w = f^w - int_{G^O} (k3 w - k4 v) dsigma_y, Dw grad w . n = 0 on the boundary
- * with constant sources; G^I, G^O, G^N are images of whole sides of Z
- * (parts[]).  Same discretisation as the time-dependent system (Q1, the map
+ * experiments of Section 4 solve it with the Table 3 parameters, the
+ * convergence benchmark of Section 4.2 its manufactured form):
+ *   -Lap u = f^u - int_{G^I} (k1 u - k2 v + g^v_1) dsigma_y   in [-1,1]^2,
+ *            u = u_D on the Dirichlet sides, grad u . n = g^u elsewhere
+ *   -Dv Lap_y v = f^v  in Y_x,   Dv grad_y v . n = k1 u - k2 v + g^v_1  on G^I
+ *                                                 k3 w - k4 v + g^v_2  on G^O
+ *                                                 g^v_3                on G^N
+ *   -Dw Lap w = f^w - int_{G^O} (k3 w - k4 v + g^v_2) dsigma_y,
+ *            Dw grad w . n = g^w on the boundary
+ * The model has every g zero; by default the sources are the constants of
+ * tsm_stationary_params and u_D = u_dirichlet (tsm_stationary_set_data
+ * replaces them by values at the quadrature points).  G^I, G^O, G^N are
+ * images of whole sides of Z (parts[]).  Same discretisation as the time-dependent system (Q1, the map
  * through its Jacobian at the quadrature points, one micro system per macro
  * node fed u_k and w_k), exchange integrals of the macro rows taken at the
  * nodes with weights L = diag(M_H 1).  Solved exactly by elimination: per
  * instance three micro PCG solves with the FP64 operator
  *   S = Dv A + k2 B^I + k4 B^O:  z^I = S^{-1} b_I,  z^O = S^{-1} b_O,
- *   z^0 = S^{-1} (f^v M 1)       (b_I = B^I 1, b_O = B^O 1),
+ *   z^0 = S^{-1} F^v    (b_I = B^I 1, b_O = B^O 1, F^v the load of f^v and g^v),
  * one macro PCG for (u, w) -- symmetric positive definite once the u rows
  * are scaled by k1/k2 and the w rows by k3/k4 -- and v = z^0 + k1 u z^I +
  * k3 w z^O.
@@ -268,7 +272,7 @@ typedef struct {
     int32_t macro_cells;      /* N_M in 2..256: macro Q1 cells per side on [-1,1]^2 */
     double Dv, Dw;            /* micro and macro-w diffusion, > 0 */
     double kappa1, kappa2, kappa3, kappa4;   /* exchange rates, > 0 */
-    double fu, fv, fw;        /* constant bulk sources (finite) */
+    double fu, fv, fw;        /* constant bulk sources (finite; see tsm_stationary_set_data) */
     double u_dirichlet;       /* u on the Dirichlet sides (finite) */
     int32_t parts[4];         /* part of each side of Z -- bottom (y2 = -1), top (y2 = +1),
                                  left (y1 = -1), right (y1 = +1): TSM_PART_*; at least one
@@ -310,6 +314,24 @@ tsm_status tsm_stationary_create(const tsm_stationary_params* p, void* stream, t
  * solve missed rtol or the macro solve missed macro_rtol (outputs are still
  * written, from the last iterates). */
 tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double* v_out);
+
+/* Data at quadrature points instead of the constants (Section 4.1, the
+ * manufactured form; NULL keeps the constant of the parameters, or zero for
+ * the g data).  Device pointers, copied; values must be finite.  Layouts
+ * (the points of tsm_set_jacobians, one value per point):
+ *   fv_cell: f^v, per instance its N_i^2 cells (c2*N+c1) x 4 points (g2*2+g1): 4 sum N_i^2 values;
+ *   gv_bnd:  g^v of the part of each side, per instance its sides (bottom,
+ *            top, left, right) x N_i edges x 2 points: 8 sum N_i values;
+ *   fu_cell, fw_cell: f^u, f^w at the macro cells' points, same order on the
+ *            N_M x N_M macro mesh of [-1,1]^2: 4 N_M^2 values each;
+ *   gu_bnd, gw_bnd: grad u . n and Dw grad w . n at the macro boundary
+ *            points, same order: 8 N_M values each (gu ignored on Dirichlet sides);
+ *   uD: u at the (N_M+1)^2 macro nodes (read on the Dirichlet sides only).
+ * A source at the micro points is f^v(x_k, zeta(x_k, y)) at the reference
+ * point y of instance k.  Needs set_reference_mesh; a new mesh drops the data. */
+tsm_status tsm_stationary_set_data(tsm_ctx* c, const double* fv_cell, const double* gv_bnd, const double* fu_cell,
+                                   const double* fw_cell, const double* gu_bnd, const double* gw_bnd,
+                                   const double* uD);
 
 tsm_status tsm_stationary_get_stats(const tsm_ctx* c, tsm_stationary_stats* s);
 

@@ -218,6 +218,14 @@ class StationarySystem:
             self.close()
             raise
 
+    def set_data(self, fv_cell=None, gv_bnd=None, fu_cell=None, fw_cell=None, gu_bnd=None, gw_bnd=None, uD=None):
+        """Sources and boundary data at the quadrature points (layouts of
+        tsm_stationary_set_data in include/tsm.h); None keeps the constant."""
+        t = self.torch
+        dev = [None if x is None else t.as_tensor(x, dtype=t.float64, device=self.device).contiguous()
+               for x in (fv_cell, gv_bnd, fu_cell, fw_cell, gu_bnd, gw_bnd, uD)]
+        tsm.tsm_stationary_set_data(self.ctx, *dev)
+
     def solve(self, with_micro=True):
         """Returns (u, w, v) (v None unless with_micro)."""
         t = self.torch

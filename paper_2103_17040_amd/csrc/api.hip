@@ -108,9 +108,19 @@ struct tsm_ctx {
     // three solves
     bool stationary = false;
     tsm_stationary_params sp{};
-    double *st_bO = nullptr, *st_lenO = nullptr, *st_m1 = nullptr, *st_zI = nullptr, *st_zO = nullptr,
+    double *st_bO = nullptr, *st_lenO = nullptr, *st_zI = nullptr, *st_zO = nullptr,
            *st_z0 = nullptr, *st_dots = nullptr, *st_w = nullptr, *st_work = nullptr, *st_info = nullptr;
     int32_t *st_iters = nullptr, *st_sweeps = nullptr;
+    // loads: point weights of the geometry (wq J, wb |F tau|) and their
+    // offsets, the micro load, part integrals, macro loads and Dirichlet
+    // values; data at quadrature points given by tsm_stationary_set_data
+    double *st_wcell = nullptr, *st_wbnd = nullptr, *st_Fv = nullptr, *st_GI = nullptr, *st_GO = nullptr,
+           *st_Fu = nullptr, *st_Fw = nullptr, *st_uDn = nullptr;
+    int64_t *st_wcoff = nullptr, *st_wboff = nullptr;
+    int64_t st_ncell = 0, st_nbnd = 0;
+    double *st_dfv = nullptr, *st_dgv = nullptr, *st_dfu = nullptr, *st_dfw = nullptr, *st_dgu = nullptr,
+           *st_dgw = nullptr, *st_duD = nullptr;
+    bool st_has[7] = {false, false, false, false, false, false, false};
     // the three micro solves run side by side: two more streams (default
     // priority), their work counters and the fork/join events
     hipStream_t st_side[2] = {nullptr, nullptr};
@@ -142,8 +152,12 @@ struct tsm_ctx {
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
-        dfree(st_bO); dfree(st_lenO); dfree(st_m1); dfree(st_zI); dfree(st_zO); dfree(st_z0); dfree(st_dots);
+        dfree(st_bO); dfree(st_lenO); dfree(st_zI); dfree(st_zO); dfree(st_z0); dfree(st_dots);
         dfree(st_w); dfree(st_work); dfree(st_info); dfree(st_iters); dfree(st_sweeps);
+        dfree(st_wcell); dfree(st_wbnd); dfree(st_Fv); dfree(st_GI); dfree(st_GO); dfree(st_Fu); dfree(st_Fw);
+        dfree(st_uDn); dfree(st_wcoff); dfree(st_wboff);
+        dfree(st_dfv); dfree(st_dgv); dfree(st_dfu); dfree(st_dfw); dfree(st_dgu); dfree(st_dgw); dfree(st_duD);
+        for (bool& h : st_has) h = false;
         drop_graph();
         have_mesh = have_geom = have_state = false;
     }
@@ -622,10 +636,26 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot); HIPALLOC(c->Mw, tot);
     HIPALLOC(c->bcomp, ni * kBndStride);
     if (c->stationary) {
-        HIPALLOC(c->st_bO, tot); HIPALLOC(c->st_lenO, ni); HIPALLOC(c->st_m1, tot);
+        HIPALLOC(c->st_bO, tot); HIPALLOC(c->st_lenO, ni);
         HIPALLOC(c->st_zI, tot); HIPALLOC(c->st_zO, tot); HIPALLOC(c->st_z0, tot);
         HIPALLOC(c->st_dots, 5 * ni); HIPALLOC(c->st_w, ni); HIPALLOC(c->st_work, 11 * ni);
         HIPALLOC(c->st_info, 2); HIPALLOC(c->st_iters, 3 * ni); HIPALLOC(c->st_sweeps, 3 * ni);
+        std::vector<int64_t> wco(ni), wbo(ni);
+        int64_t nc = 0, nb = 0;
+        for (int64_t i = 0; i < ni; ++i) {
+            const int64_t N = c->level_h[i];
+            wco[i] = nc;
+            wbo[i] = nb;
+            nc += 4 * N * N;
+            nb += 8 * N;
+        }
+        c->st_ncell = nc;
+        c->st_nbnd = nb;
+        HIPALLOC(c->st_wcell, nc); HIPALLOC(c->st_wbnd, nb); HIPALLOC(c->st_wcoff, ni); HIPALLOC(c->st_wboff, ni);
+        HIPCHK(hipMemcpy(c->st_wcoff, wco.data(), ni * sizeof(int64_t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->st_wboff, wbo.data(), ni * sizeof(int64_t), hipMemcpyHostToDevice));
+        HIPALLOC(c->st_Fv, tot); HIPALLOC(c->st_GI, ni); HIPALLOC(c->st_GO, ni);
+        HIPALLOC(c->st_Fu, ni); HIPALLOC(c->st_Fw, ni); HIPALLOC(c->st_uDn, ni);
     }
     HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());
@@ -695,7 +725,10 @@ AssembleArgs assemble_base(tsm_ctx* c) {
         }
         as.b2 = c->st_bO;
         as.len2 = c->st_lenO;
-        as.m1 = c->st_m1;
+        as.wcell = c->st_wcell;
+        as.wbnd = c->st_wbnd;
+        as.wc_off = c->st_wcoff;
+        as.wb_off = c->st_wboff;
     }
     return as;
 }
@@ -1352,15 +1385,48 @@ tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double
     if (!c->ev_mid) HIPCHK(hipEventCreate(&c->ev_mid));
     HIPCHK(hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), c->stream));
     HIPCHK(hipEventRecord(c->ev0, c->stream));
+    // loads: micro F^v (bulk source and Robin/Neumann data), the part
+    // integrals of the data, the macro loads and the Dirichlet values
+    StationaryLoadArgs la{};
+    la.n_inst = (int)ni;
+    la.level = c->level;
+    la.offsets = c->offsets;
+    la.wc_off = c->st_wcoff;
+    la.wb_off = c->st_wboff;
+    la.wcell = c->st_wcell;
+    la.wbnd = c->st_wbnd;
+    la.fv = c->st_has[0] ? c->st_dfv : nullptr;
+    la.gv = c->st_has[1] ? c->st_dgv : nullptr;
+    la.fv_const = sp.fv;
+    for (int s = 0; s < 4; ++s) {
+        la.parts[s] = sp.parts[s];
+        la.dirichlet[s] = sp.dirichlet[s] != 0;
+    }
+    la.Fv = c->st_Fv;
+    la.GI = c->st_GI;
+    la.GO = c->st_GO;
+    la.NM = c->NM;
+    la.fu = c->st_has[2] ? c->st_dfu : nullptr;
+    la.fw = c->st_has[3] ? c->st_dfw : nullptr;
+    la.gu = c->st_has[4] ? c->st_dgu : nullptr;
+    la.gw = c->st_has[5] ? c->st_dgw : nullptr;
+    la.uD = c->st_has[6] ? c->st_duD : nullptr;
+    la.fu_const = sp.fu;
+    la.fw_const = sp.fw;
+    la.uD_const = sp.u_dirichlet;
+    la.Fu = c->st_Fu;
+    la.Fw = c->st_Fw;
+    la.uDn = c->st_uDn;
+    HIPCHK(launch_stationary_loads(la, c->stream));
     // the three batched micro solves (FP64, zero initial guess) are
     // independent: they run side by side on the context's stream and the two
     // side streams, each with its own work counter, so that a small batch
     // still fills the chip.  Each leaves b_I^T x (the kernels' b is b_I):
     // b_I^T z^I, b_I^T z^O and b_I^T z^0 come with the solves.
-    const bool with_f = sp.fv != 0.0;
+    const bool with_f = sp.fv != 0.0 || c->st_has[0] || c->st_has[1];
     const int n_solve = with_f ? 3 : 2;
-    const double* rhs[3] = {c->b, c->st_bO, c->st_m1};
-    const double scale[3] = {1.0, 1.0, sp.fv};
+    const double* rhs[3] = {c->b, c->st_bO, c->st_Fv};
+    const double scale[3] = {1.0, 1.0, 1.0};
     double* sol[3] = {c->st_zI, c->st_zO, c->st_z0};
     double* bx[3] = {c->st_dots, c->st_dots + 2 * ni, c->st_dots + 3 * ni};
     hipStream_t strm[3] = {c->stream, c->st_side[0], c->st_side[1]};
@@ -1406,9 +1472,11 @@ tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double
     m.k2 = sp.kappa2;
     m.k3 = sp.kappa3;
     m.k4 = sp.kappa4;
-    m.fu = sp.fu;
-    m.fw = sp.fw;
-    m.uD = sp.u_dirichlet;
+    m.Fu = c->st_Fu;
+    m.Fw = c->st_Fw;
+    m.uDn = c->st_uDn;
+    m.GI = c->st_GI;
+    m.GO = c->st_GO;
     for (int s = 0; s < 4; ++s) m.dirichlet[s] = sp.dirichlet[s] != 0;
     m.lenI = c->len;
     m.lenO = c->st_lenO;
@@ -1457,6 +1525,27 @@ tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double
     if (nc > 0) return c->fail(TSM_ENOCONV, std::to_string(nc) + " micro solves missed rtol");
     if (!(info[1] <= sp.macro_rtol))
         return c->fail(TSM_ENOCONV, "macro solve stopped at relative residual " + std::to_string(info[1]));
+    return TSM_OK;
+}
+
+tsm_status tsm_stationary_set_data(tsm_ctx* c, const double* fv_cell, const double* gv_bnd, const double* fu_cell,
+                                    const double* fw_cell, const double* gu_bnd, const double* gw_bnd,
+                                    const double* uD) {
+    if (!c) return TSM_EINVAL;
+    if (!c->stationary) return c->fail(TSM_ESTATE, "not a stationary context (tsm_stationary_create)");
+    if (!c->have_mesh) return c->fail(TSM_ESTATE, "set_reference_mesh first");
+    const int64_t nM = c->NM, ni = c->n_inst;
+    const double* src[7] = {fv_cell, gv_bnd, fu_cell, fw_cell, gu_bnd, gw_bnd, uD};
+    double** dst[7] = {&c->st_dfv, &c->st_dgv, &c->st_dfu, &c->st_dfw, &c->st_dgu, &c->st_dgw, &c->st_duD};
+    const int64_t len[7] = {c->st_ncell, c->st_nbnd, 4 * nM * nM, 4 * nM * nM, 8 * nM, 8 * nM, ni};
+    HIPCHK(hipDeviceSynchronize());   // the caller's producers of the data
+    for (int q = 0; q < 7; ++q) {
+        c->st_has[q] = src[q] != nullptr;
+        if (!src[q]) continue;
+        if (!*dst[q]) HIPALLOC(*dst[q], len[q]);
+        HIPCHK(hipMemcpyAsync(*dst[q], src[q], len[q] * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
     return TSM_OK;
 }
 

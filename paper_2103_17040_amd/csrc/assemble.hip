@@ -81,6 +81,9 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                             P = pullback_at(a, ys[t1], ys[t2], ss[t1], cs[t1], ss[t2], cs[t2]);
                         }
                         jmin = fmin(jmin, P.J);
+                        // each cell's point weights are kept by its first node
+                        if (A.wcell != nullptr && l1 == 0 && l2 == 0)
+                            A.wcell[A.wc_off[inst] + (int64_t)(c2 * N + c1) * 4 + g2 * 2 + g1] = wq * P.J;
                         // basis of local node (l1,l2) and its reference gradient
                         const double f1 = lin(l1, g1), f2 = lin(l2, g2);
                         const double phl = f1 * f2;
@@ -130,6 +133,7 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     }
                     double om = sqrt(M11 * M11 + M21 * M21);
                     if constexpr (TAB) bad |= !isfinite(om);
+                    if (A.wbnd != nullptr && l1 == 0) A.wbnd[A.wb_off[inst] + (int64_t)(side * N + e) * 2 + g] = wb * om;
                     for (int m1 = 0; m1 < 2; ++m1) {
                         const double v = wb * om * lin(l1, g) * lin(m1, g);
                         S[3 + (m1 - l1 + 1)] += A.kside[side] * v;
@@ -161,6 +165,8 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
                     }
                     double om = sqrt(M12 * M12 + M22 * M22);
                     if constexpr (TAB) bad |= !isfinite(om);
+                    if (A.wbnd != nullptr && l2 == 0)
+                        A.wbnd[A.wb_off[inst] + (int64_t)((2 + side) * N + e) * 2 + g] = wb * om;
                     for (int m2 = 0; m2 < 2; ++m2) {
                         const double v = wb * om * lin(l2, g) * lin(m2, g);
                         S[(m2 - l2 + 1) * 3 + 1] += A.kside[2 + side] * v;
@@ -196,12 +202,6 @@ __global__ __launch_bounds__(kMicroThreads) void assemble_kernel(AssembleArgs A)
         if (A.b2 != nullptr) {
             A.b2[off + j] = bj2;
             len2_part += bj2;
-        }
-        if (A.m1 != nullptr) {
-            double m = 0.0;
-#pragma unroll
-            for (int k = 0; k < kStencil; ++k) m += M[k];
-            A.m1[off + j] = m;
         }
     }
     double v[2] = {len_part, len2_part};

@@ -83,7 +83,14 @@ struct AssembleArgs {
     double* b2;           // optional second load sum bw2[side] (B_side 1) (null: none)
     double bw2[4];
     double* len2;         // [n_inst] 1^T b2 (with b2)
-    double* m1;           // optional: M 1 (the integrals of eta_j J), may be null
+    // optional (null: none): the quadrature weights times the geometry at every
+    // point, for load assembly -- wq J at the cell points (per instance at
+    // wc_off[i], cells c2*N+c1, points g2*2+g1) and wb |F tau| at the
+    // boundary points (at wb_off[i], sides bottom, top, left, right; edges; 2 points)
+    double* wcell;
+    double* wbnd;
+    const int64_t* wc_off;
+    const int64_t* wb_off;
     double* S64;          // [9 * total] : instance block at 9*off, coefficient-major [k][n]
     float* S32;           // S rounded to FP32
     float* Slo;           // S - S32 rounded to FP32: S32 + Slo equals S to about 2^-48 relative
@@ -179,11 +186,16 @@ struct MacroArgs {
 // one workgroup (Jacobi-PCG).
 struct StationaryMacroArgs {
     int NM;                       // macro cells per side of [-1,1]^2
-    double Dw, k1, k2, k3, k4, fu, fw, uD;
+    double Dw, k1, k2, k3, k4;
     int dirichlet[4];             // sides bottom, top, left, right: u prescribed
     const double* lenI;           // [n] |G^I| = 1^T b_I per node
     const double* lenO;           // [n] |G^O|
     const double* dots;           // [5][n] b_I^T z^I, b_O^T z^O, b_I^T z^O, b_I^T z^0, b_O^T z^0
+    const double* Fu;             // [n] int f^u xi_k + the Neumann load of u (non-Dirichlet sides)
+    const double* Fw;             // [n] int f^w xi_k + the Neumann load of w
+    const double* uDn;            // [n] u at the Dirichlet nodes
+    const double* GI;             // [n] int over G^I of g^v_1 at node k
+    const double* GO;             // [n] int over G^O of g^v_2
     double* u;                    // [n] out
     double* w;                    // [n] out
     double* work;                 // [11 n] scratch
@@ -216,6 +228,40 @@ hipError_t launch_bdot_boundary(int n_tasks, const int32_t* order, const int32_t
                                 const double* bc, const double* x, double* out, hipStream_t s);
 // bc[i * kBndStride + k] = b_i at boundary node bnd_node(N_i, k)
 hipError_t launch_stationary_macro(const StationaryMacroArgs& a, hipStream_t s);
+// Micro loads of the stationary system: Fv_i = int f^v eta J + int g^v eta |F tau|
+// (f^v and g^v at the quadrature points, or fv_const / 0 where null), and the
+// part integrals GI_i, GO_i of g^v; from the weights of AssembleArgs::wcell/wbnd.
+struct StationaryLoadArgs {
+    int n_inst;
+    const int32_t* level;
+    const int64_t* offsets;
+    const int64_t* wc_off;
+    const int64_t* wb_off;
+    const double* wcell;
+    const double* wbnd;
+    const double* fv;             // [4 sum N^2] or null
+    const double* gv;             // [8 sum N] or null
+    double fv_const;
+    int parts[4];
+    double* Fv;                   // ragged out
+    double* GI;                   // [n_inst] out
+    double* GO;                   // [n_inst] out
+    // macro loads (one extra block): f^u, f^w at the macro cell points and
+    // grad u . n, Dw grad w . n at the macro boundary points (null: constants, 0),
+    // u at the nodes (null: uD_const)
+    int NM;
+    const double* fu;
+    const double* fw;
+    const double* gu;
+    const double* gw;
+    const double* uD;
+    double fu_const, fw_const, uD_const;
+    int dirichlet[4];
+    double* Fu;
+    double* Fw;
+    double* uDn;
+};
+hipError_t launch_stationary_loads(const StationaryLoadArgs& a, hipStream_t s);
 // v_i = z0_i + k1 u_i zI_i + k3 w_i zO_i (z0 may be null: zero), ragged
 hipError_t launch_stationary_micro(int n_inst, const int64_t* offsets, const double* z0, const double* zI,
                                    const double* zO, const double* u, const double* w, double k1, double k3,

@@ -39,7 +39,7 @@ EXPORTED = ["tsm_default_params", "tsm_create", "tsm_set_reference_mesh", "tsm_g
             "tsm_set_deformation", "tsm_set_jacobians", "tsm_set_state", "tsm_step", "tsm_get_macro", "tsm_get_fluxes",
             "tsm_get_micro", "tsm_get_setup", "tsm_apply_operator", "tsm_gradient", "tsm_set_flags", "tsm_autotune", "tsm_get_stats",
             "tsm_last_error", "tsm_destroy", "tsm_stationary_default_params", "tsm_stationary_create",
-            "tsm_stationary_solve", "tsm_stationary_get_stats"]
+            "tsm_stationary_solve", "tsm_stationary_set_data", "tsm_stationary_get_stats"]
 
 
 class tsm_params(ctypes.Structure):
@@ -116,6 +116,7 @@ def _load():
         "tsm_stationary_default_params": (None, [ctypes.POINTER(tsm_stationary_params)]),
         "tsm_stationary_create": (I32, [ctypes.POINTER(tsm_stationary_params), VP, ctypes.POINTER(P)]),
         "tsm_stationary_solve": (I32, [P, VP, VP, VP]),
+        "tsm_stationary_set_data": (I32, [P, VP, VP, VP, VP, VP, VP, VP]),
         "tsm_stationary_get_stats": (I32, [P, ctypes.POINTER(tsm_stationary_stats)]),
     }
     for name, (res, args) in sig.items():
@@ -270,6 +271,12 @@ def tsm_stationary_create(params: tsm_stationary_params, stream=None):
 
 def tsm_stationary_solve(ctx, u_out, w_out, v_out=None) -> None:
     _check(ctx, _lib.tsm_stationary_solve(ctx, _ptr(u_out), _ptr(w_out), _ptr(v_out)))
+
+
+def tsm_stationary_set_data(ctx, fv_cell=None, gv_bnd=None, fu_cell=None, fw_cell=None, gu_bnd=None, gw_bnd=None,
+                            uD=None) -> None:
+    _check(ctx, _lib.tsm_stationary_set_data(ctx, _ptr(fv_cell), _ptr(gv_bnd), _ptr(fu_cell), _ptr(fw_cell),
+                                             _ptr(gu_bnd), _ptr(gw_bnd), _ptr(uD)))
 
 
 def tsm_stationary_get_stats(ctx) -> dict:

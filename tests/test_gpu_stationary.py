@@ -220,3 +220,61 @@ def test_constant_state_on_a_large_macro_mesh():
     assert np.max(np.abs(u - 1.0)) <= 1e-10
     assert np.max(np.abs(w - cw)) <= 1e-10 * cw
     assert np.max(np.abs(v - cv)) <= 1e-10
+
+
+MANU = dict(Dv=1.0, Dw=0.5, kappa1=0.5, kappa2=1.0, kappa3=0.25, kappa4=1.0)
+
+
+def _manufactured_gpu(NM, levels, data, parts=(0, 0, 1, 2)):
+    from paper_2103_17040_amd import StationarySystem
+    from workloads import manufactured as MF
+    _, Fc, Fb = MF.map_tables(NM, levels, MF.ZETA_MANU)
+    pts = MF.data_at_points(data, NM, levels, parts)
+    g = StationarySystem(NM, levels, jacobians=(Fc, Fb), parts=parts, rtol=1e-14, **MANU)
+    try:
+        g.set_data(**pts)
+        u, w, v = g.solve()
+        return u.cpu().numpy(), w.cpu().numpy(), v.cpu().numpy(), g.stats()
+    finally:
+        g.close()
+
+
+def test_manufactured_data_matches_oracle():
+    """The manufactured form (Section 4.1: Robin data on every part, Neumann
+    data, Dirichlet values, sources varying in x and y) on ragged meshes."""
+    from workloads import manufactured as MF
+    NM = 4
+    levels = np.asarray([[4, 6, 16][i % 3] for i in range(25)], dtype=np.int32)
+    prm = st.StationaryParams(macro_cells=NM, **MANU)
+    data = MF.manufactured(prm, MF.U_MANU, MF.V_MANU, MF.W_MANU, MF.ZETA_MANU)
+    banner("stationary manufactured data vs oracle")
+    out = _manufactured_gpu(NM, levels, data)
+    per, _, _ = MF.map_tables(NM, levels, MF.ZETA_MANU)
+    ref = st.solve(prm, levels, per, data)
+    _compare(ref, out)
+
+
+def test_manufactured_orders_on_gpu():
+    """The convergence benchmark of Section 4.2 solved on the GPU: orders ~2
+    (L2) and ~1 (H1) for (u, w) and v, the pattern of Tables 1 and 2."""
+    from workloads import manufactured as MF
+    prm = st.StationaryParams(macro_cells=0, **MANU)
+    data = MF.manufactured(prm, MF.U_MANU, MF.V_MANU, MF.W_MANU, MF.ZETA_MANU)
+    dofs, errs = [], []
+    for N in (4, 8, 16, 32):
+        banner(f"stationary manufactured N = N_M = {N}")
+        levels = np.full((N + 1) ** 2, N, dtype=np.int32)
+        u, w, v, _ = _manufactured_gpu(N, levels, data)
+        off = W.offsets(levels)
+        vh = [v[off[k]:off[k + 1]] for k in range(len(levels))]
+        errs.append(MF.convergence_errors(N, N, u, w, vh, prm))
+        dofs.append((N + 1) ** 2)
+    E = np.array(errs)
+    pM, qM, pV, qV = (MF.orders(dofs, E[:, i]) for i in range(4))
+    banner(f"  orders p_M {pM} q_M {qM} p_v {pV} q_v {qV}")
+    for r in pM + pV:
+        assert 1.8 < r < 2.5, (pM, pV)
+    for r in qM + qV:
+        assert 0.9 < r < 1.3, (qM, qV)
+    assert 1.9 < pM[-1] < 2.31 and 1.9 < pV[-1] < 2.31, (pM, pV)
+    assert 0.95 < qM[-1] < 1.2 and 0.95 < qV[-1] < 1.2, (qM, qV)

@@ -21,109 +21,14 @@ import workloads as W
 from oracle import fem
 from oracle import stationary as st
 
-X1, X2, Y1, Y2, Z1, Z2 = sy.symbols("x1 x2 y1 y2 z1 z2")
-GL_S, GL_W = np.polynomial.legendre.leggauss(12)
-
-
-def manufactured(prm, u, v, w, zeta):
-    """StationaryData for exact fields u(x), w(x), v(x, y) and a map
-    y = zeta(x, z) (SymPy expressions in X1, X2, Y1, Y2, Z1, Z2)."""
-    Dv, Dw = prm.Dv, prm.Dw
-    F = sy.Matrix([[sy.diff(zeta[r], zc) for zc in (Z1, Z2)] for r in range(2)])
-    sub = {Y1: zeta[0], Y2: zeta[1]}
-    gv_y = [sy.diff(v, s) for s in (Y1, Y2)]
-    fv = (-Dv * (sy.diff(v, Y1, 2) + sy.diff(v, Y2, 2))).subs(sub)
-    cof = F.det() * F.inv().T
-    lam = lambda e: sy.lambdify((X1, X2, Z1, Z2), e, "numpy")
-    fv_f = lam(fv)
-    flux, coupling = {}, {st.PART_N: 0, st.PART_I: prm.kappa1 * u - prm.kappa2 * v,
-                          st.PART_O: prm.kappa3 * w - prm.kappa4 * v}
-    g_f, flux_f = {}, {}
-    for s, nu in enumerate(st.SIDE_NORMALS):
-        cn = cof * sy.Matrix(nu)
-        nrm = cn / sy.sqrt(cn[0] ** 2 + cn[1] ** 2)
-        fl = Dv * (gv_y[0] * nrm[0] + gv_y[1] * nrm[1])
-        part = prm.parts[s]
-        g_f[s] = lam((fl - coupling[part]).subs(sub))
-        flux_f[s] = lam(fl.subs(sub))
-
-    def side_pts(s):
-        if s < 2:
-            return GL_S, np.full_like(GL_S, -1.0 if s == 0 else 1.0), (1.0, 0.0)
-        return np.full_like(GL_S, -1.0 if s == 2 else 1.0), GL_S, (0.0, 1.0)
-
-    Fn = sy.lambdify((X1, X2, Z1, Z2), F, "numpy")
-
-    def part_integral(part, x1, x2):
-        tot = 0.0
-        for s in range(4):
-            if prm.parts[s] != part:
-                continue
-            z1, z2, tau = side_pts(s)
-            Fv = np.array([[np.broadcast_to(np.asarray(Fn(x1, x2, a, b), dtype=float), (2, 2))
-                            for a, b in zip(z1, z2)]]).reshape(-1, 2, 2)
-            om = np.linalg.norm(Fv @ np.asarray(tau), axis=-1)
-            tot += np.sum(GL_W * om * np.broadcast_to(flux_f[s](x1, x2, z1, z2), z1.shape))
-        return tot
-
-    lap = lambda e: sy.diff(e, X1, 2) + sy.diff(e, X2, 2)
-    fu_base = sy.lambdify((X1, X2), -lap(u), "numpy")
-    fw_base = sy.lambdify((X1, X2), -Dw * lap(w), "numpy")
-
-    def fu(x1, x2):
-        x1, x2 = np.asarray(x1, float), np.asarray(x2, float)
-        extra = np.vectorize(lambda a, b: part_integral(st.PART_I, a, b))(x1, x2)
-        return np.broadcast_to(fu_base(x1, x2), x1.shape) + extra
-
-    def fw(x1, x2):
-        x1, x2 = np.asarray(x1, float), np.asarray(x2, float)
-        extra = np.vectorize(lambda a, b: part_integral(st.PART_O, a, b))(x1, x2)
-        return np.broadcast_to(fw_base(x1, x2), x1.shape) + extra
-
-    du = [sy.lambdify((X1, X2), sy.diff(u, s), "numpy") for s in (X1, X2)]
-    dw = [sy.lambdify((X1, X2), Dw * sy.diff(w, s), "numpy") for s in (X1, X2)]
-    uf = sy.lambdify((X1, X2), u, "numpy")
-    bc = lambda f, x1: np.broadcast_to(np.asarray(f, float), np.shape(x1))
-    return st.StationaryData(
-        fu=fu, fw=fw,
-        fv=lambda x1, x2, z1, z2: bc(fv_f(x1, x2, z1, z2), z1),
-        gv=lambda part, x1, x2, z1, z2: bc(g_f[_side_of(z1, z2)](x1, x2, z1, z2), z1),
-        uD=lambda x1, x2: bc(uf(x1, x2), x1),
-        gu=lambda x1, x2, n: bc(du[0](x1, x2), x1) * n[0] + bc(du[1](x1, x2), x1) * n[1],
-        gw=lambda x1, x2, n: bc(dw[0](x1, x2), x1) * n[0] + bc(dw[1](x1, x2), x1) * n[1])
-
-
-def _side_of(z1, z2):
-    """The side of Z on which the points lie (bottom, top, left, right)."""
-    z1, z2 = np.asarray(z1), np.asarray(z2)
-    if np.all(z2 == -1.0):
-        return 0
-    if np.all(z2 == 1.0):
-        return 1
-    if np.all(z1 == -1.0):
-        return 2
-    assert np.all(z1 == 1.0)
-    return 3
+from workloads.manufactured import X1, X2, Y1, Y2, Z1, Z2, ZETA_MANU, manufactured
 
 
 def _jacobian_tables(NM, levels, zeta):
-    Fn = sy.lambdify((X1, X2, Z1, Z2), sy.Matrix([[sy.diff(zeta[r], zc) for zc in (Z1, Z2)] for r in range(2)]),
-                     "numpy")
-    x1, x2 = st.macro_nodes(NM)
-    out = []
-    for k in range(len(levels)):
-        (c1, c2), (b1, b2) = fem.quadrature_points(levels[k])
-        Fc = np.stack([np.broadcast_to(np.asarray(Fn(x1[k], x2[k], a, b), float), (2, 2))
-                       for a, b in zip(c1.ravel(), c2.ravel())]).reshape(c1.shape + (2, 2))
-        Fb = np.stack([np.broadcast_to(np.asarray(Fn(x1[k], x2[k], a, b), float), (2, 2))
-                       for a, b in zip(b1.ravel(), b2.ravel())]).reshape(b1.shape + (2, 2))
-        out.append((Fc, Fb))
-    return out
+    from workloads.manufactured import map_tables
+    return map_tables(NM, levels, zeta)[0]
 
 
-# the paper's manufactured map (eq. manu_system) and the Case B map (Section 4.4)
-ZETA_MANU = (sy.Rational(2, 5) * ((X1 + sy.Rational(13, 10)) + (sy.Rational(7, 5) * Z1 - sy.Rational(27, 50) * Z2)),
-             sy.Rational(3, 10) * ((X2 + sy.Rational(6, 5)) + (-sy.Rational(2, 5) * Z1 + sy.Rational(4, 5) * Z2)))
 # a sheared cell translated with x (D_y zeta independent of x)
 ZETA_SHEAR = (X1 + sy.Rational(9, 10) * Z1 + sy.Rational(3, 10) * Z2, X2 - Z1 / 5 + sy.Rational(7, 10) * Z2)
 
@@ -207,74 +112,21 @@ def test_case_A_is_symmetric_about_the_centre_line():
 # manufactured convergence (Section 4.2)
 # ---------------------------------------------------------------------------
 
-G3_X = 0.5 + 0.5 * np.array([-np.sqrt(0.6), 0.0, np.sqrt(0.6)])
-G3_W = np.array([5.0, 8.0, 5.0]) / 18.0
-
-
-def _q1_errors(N, origin, nodal, exact, grad_exact, F=None):
-    """L2 and H1-seminorm errors of a Q1 nodal field on an N x N mesh of a
-    square of side 2 (3x3 Gauss per cell).  With F (constant map Jacobian)
-    the integrals are over the image: weight det F, gradients through F^-T."""
-    h = 2.0 / N
-    U = nodal.reshape(N + 1, N + 1)
-    e0 = e1 = 0.0
-    J = 1.0 if F is None else abs(np.linalg.det(F))
-    Kt = np.eye(2) if F is None else np.linalg.inv(F).T
-    for c2 in range(N):
-        for c1 in range(N):
-            for g2, w2 in zip(G3_X, G3_W):
-                for g1, w1 in zip(G3_X, G3_W):
-                    p1, p2 = origin + (c1 + g1) * h, origin + (c2 + g2) * h
-                    a, b, c, d = U[c2, c1], U[c2, c1 + 1], U[c2 + 1, c1], U[c2 + 1, c1 + 1]
-                    val = a * (1 - g1) * (1 - g2) + b * g1 * (1 - g2) + c * (1 - g1) * g2 + d * g1 * g2
-                    gz = np.array([(b - a) * (1 - g2) + (d - c) * g2, (c - a) * (1 - g1) + (d - b) * g1]) / h
-                    ww = w1 * w2 * h * h * J
-                    e0 += ww * (val - exact(p1, p2)) ** 2
-                    gd = Kt @ gz - grad_exact(p1, p2)
-                    e1 += ww * gd @ gd
-    return e0, e1
-
-
 def test_manufactured_convergence_orders():
+    from workloads import manufactured as MF
     prm = st.StationaryParams(macro_cells=0, Dv=1.0, Dw=0.5, kappa1=0.5, kappa2=1.0, kappa3=0.25, kappa4=1.0)
-    u = X2 * sy.sin(X1)
-    v = X1 + X2 + Y1 * Y2 * (1 - Y2)
-    w = X1 * sy.cos(X2)
-    Fm = np.array([[0.4 * 1.4, -0.4 * 0.54], [-0.3 * 0.4, 0.3 * 0.8]])
-    data = manufactured(prm, u, v, w, ZETA_MANU)
-    uf, wf = sy.lambdify((X1, X2), u), sy.lambdify((X1, X2), w)
-    gu = [sy.lambdify((X1, X2), sy.diff(u, s)) for s in (X1, X2)]
-    gw = [sy.lambdify((X1, X2), sy.diff(w, s)) for s in (X1, X2)]
-    vy = sy.lambdify((X1, X2, Y1, Y2), v)
-    gvy = [sy.lambdify((X1, X2, Y1, Y2), sy.diff(v, s)) for s in (Y1, Y2)]
-    zmap = sy.lambdify((X1, X2, Z1, Z2), ZETA_MANU)
+    data = manufactured(prm, MF.U_MANU, MF.V_MANU, MF.W_MANU, ZETA_MANU)
     dofs, EM, GM, EV, GV = [], [], [], [], []
     for N in (4, 8, 16):
         p = st.StationaryParams(**{**prm.__dict__, "macro_cells": N})
         nM = (N + 1) ** 2
         levels = [N] * nM
-        jac, _, _ = W.jacobian_tables(np.array(levels), lambda y1, y2: np.broadcast_to(Fm, np.shape(y1) + (2, 2)),
-                                      [()] * nM)
-        out = st.solve(p, levels, jac, data)
-        a0, a1 = _q1_errors(N, -1.0, out["u"], uf, lambda s, t: np.array([gu[0](s, t), gu[1](s, t)]))
-        b0, b1 = _q1_errors(N, -1.0, out["w"], wf, lambda s, t: np.array([gw[0](s, t), gw[1](s, t)]))
-        # micro errors: nodal quadrature in x (weights L = int of each hat)
-        _, L, *_ = st.macro_system(p, st.constant_data())
-        x1, x2 = st.macro_nodes(N)
-        v0 = v1 = 0.0
-        for k in range(nM):
-            ex = lambda s, t: vy(x1[k], x2[k], *zmap(x1[k], x2[k], s, t))
-            gex = lambda s, t: np.array([g(x1[k], x2[k], *zmap(x1[k], x2[k], s, t)) for g in gvy])
-            c0, c1 = _q1_errors(N, -1.0, out["v"][k], ex, gex, F=Fm)
-            v0 += L[k] * c0
-            v1 += L[k] * c1
+        out = st.solve(p, levels, _jacobian_tables(N, levels, ZETA_MANU), data)
+        e = MF.convergence_errors(N, N, out["u"], out["w"], out["v"], p)
         dofs.append(nM)
-        EM.append(np.sqrt(a0) + np.sqrt(b0))
-        GM.append(np.sqrt(a1) + np.sqrt(b1))
-        EV.append(np.sqrt(v0))
-        GV.append(np.sqrt(v1))
-    rate = lambda e: [np.log(e[i - 1] / e[i]) / np.log(np.sqrt(dofs[i] / dofs[i - 1])) for i in range(1, len(e))]
-    pM, qM, pV, qV = rate(EM), rate(GM), rate(EV), rate(GV)
+        for lst, val in zip((EM, GM, EV, GV), e):
+            lst.append(val)
+    pM, qM, pV, qV = MF.orders(dofs, EM), MF.orders(dofs, GM), MF.orders(dofs, EV), MF.orders(dofs, GV)
     print("orders", pM, qM, pV, qV)
     # Tables 1-2 print p 1.94-2.31 and q 1.01-1.20; the coarsest pair here
     # (5^2 -> 9^2 DoFs) is still pre-asymptotic
