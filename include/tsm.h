@@ -238,6 +238,42 @@ const char* tsm_last_error(const tsm_ctx* c);
 void tsm_destroy(tsm_ctx* c);   /* NULL-safe */
 
 /* ---------------------------------------------------------------------------
+ * Refinement of the micro meshes from an error indicator -- an extension the
+ * paper's conclusions propose (an indicator defined over all micro grids,
+ * used to refine so as to reduce the error globally); the indicator, the
+ * marking and the transfer below are this library's reading.
+ * ------------------------------------------------------------------------- */
+
+/* Indicator of the current micro state, gradient-jump form: eta2_out[i]
+ * (device pointer, n_inst doubles) = sum over the interior edges e of
+ * instance i's reference mesh of (h/12) int_e [[ d (C grad_z v_i) . nu_e ]]^2,
+ * the jump of the pulled-back flux (C = K K^T J, Section 3.1) integrated with
+ * the 2-point rule.  Needs set_state; ESTATE for a geometry given by Jacobian
+ * tables (C is needed at points the tables do not hold) and for a
+ * stationary context. */
+tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out);
+
+/* Bulk marking over the global functional sum_i eta2[i]: the fewest
+ * instances with 2 level[i] <= max_level, largest eta2 first (ties: lower
+ * index first), whose indicators reach theta times the functional get
+ * level_new[i] = 2 level[i]; the others keep level[i].  Host pointers, n_inst
+ * entries each; *n_marked (may be NULL) receives the count.  EINVAL on
+ * theta outside [0, 1], a negative or non-finite eta2 or a bad level
+ * (message in tsm_last_error(NULL)). */
+tsm_status tsm_mark_refine(int64_t n_inst, const double* eta2, const int32_t* level, double theta, int32_t max_level,
+                           int32_t* level_new, int64_t* n_marked);
+
+/* Nested Q1 interpolation of a ragged micro field from the meshes level_old
+ * to level_new (host pointers, n_inst each; level_new[i] is level_old[i] or
+ * 2 level_old[i], at most 64): v_old (ragged by level_old) to v_new (ragged
+ * by level_new), device pointers.  A fine node takes the coarse value at a
+ * corner, the mean of 2 on an edge midpoint, of 4 at a cell centre.  Runs on
+ * `stream` (a hipStream_t, NULL: the null stream) and synchronises it.
+ * EINVAL on bad levels (message in tsm_last_error(NULL)). */
+tsm_status tsm_prolong(int64_t n_inst, const int32_t* level_old, const int32_t* level_new, const double* v_old,
+                       double* v_new, void* stream);
+
+/* ---------------------------------------------------------------------------
  * The paper's stationary three-field system (Section 2.1 model; the Case A/B
  * experiments of Section 4 solve it with the Table 3 parameters, the
  * convergence benchmark of Section 4.2 its manufactured form):

@@ -27,6 +27,10 @@ class TwoScaleBatch:
         from . import tsm
         self.torch = torch
         self.device = torch.device(device)
+        self._ctor = dict(D=D, d=d, kappa=kappa, p=p, dt=dt, sigma=sigma, precision=precision, rtol=rtol,
+                          inner_rtol=inner_rtol, setup_rtol=setup_rtol, max_iter=max_iter, max_refine=max_refine,
+                          checkpoint_every=checkpoint_every, flags=flags, coupling=coupling, fp_rtol=fp_rtol,
+                          fp_max_iter=fp_max_iter, device=device)
         prm = tsm.tsm_default_params()
         prm.macro_cells = int(macro_cells)
         prm.D, prm.d, prm.kappa, prm.p, prm.dt = float(D), float(d), float(kappa), float(p), float(dt)
@@ -116,6 +120,31 @@ class TwoScaleBatch:
     def set_flags(self, flags):
         tsm.tsm_set_flags(self.ctx, flags)
         self._flags = int(flags)
+
+    def error_indicator(self):
+        """eta_i^2 of the current micro state (tsm_error_indicator)."""
+        out = self._empty(self.n_inst)
+        tsm.tsm_error_indicator(self.ctx, out)
+        return out
+
+    def refine(self, theta=0.5, max_level=64):
+        """Refine the micro meshes from the indicator: bulk marking over all
+        instances (tsm_mark_refine), marked instances get twice the cells per
+        side, and a new batch with the same parameters, deformation and state
+        (micro fields carried over by tsm_prolong) is returned with the new
+        levels and the indicator.  This batch is left unchanged."""
+        import numpy as np
+        eta2 = self.error_indicator().cpu().numpy()
+        levels = np.asarray(self._levels, dtype=np.int32)
+        new_levels, _ = tsm.tsm_mark_refine(eta2, levels, theta, max_level)
+        u, v = self.macro(), self.micro()
+        n_new = int(((new_levels.astype(np.int64) + 1) ** 2).sum())
+        v_new = self._empty(n_new)
+        self.torch.cuda.synchronize(self.device)
+        tsm.tsm_prolong(levels, new_levels, v, v_new)
+        g = TwoScaleBatch(self.params.macro_cells, new_levels, self._a, self._theta, **self._ctor)
+        g.set_state(u, v_new)
+        return g, new_levels, eta2
 
     def autotune(self, steps=2, cache=None):
         """Pick the fastest launch plan on the current state (which is left

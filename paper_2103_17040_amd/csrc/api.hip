@@ -1307,6 +1307,94 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
 
 const char* tsm_last_error(const tsm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
+tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out) {
+    if (!c) return TSM_EINVAL;
+    if (!eta2_out) return c->fail(TSM_EINVAL, "eta2_out is NULL");
+    if (c->stationary) return c->fail(TSM_ESTATE, "stationary context: no time-stepped micro state");
+    if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
+    if (c->geom_tables) return c->fail(TSM_ESTATE, "indicator needs the amplitude geometry (not Jacobian tables)");
+    IndicatorArgs a{};
+    a.n_inst = (int)c->n_inst;
+    a.level = c->level;
+    a.offsets = c->offsets;
+    a.amp = c->amp;
+    a.u = c->u;
+    a.v0 = c->v0;
+    a.w = c->w;
+    a.d = c->prm.d;
+    a.eta2 = eta2_out;
+    HIPCHK(launch_indicator(a, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TSM_OK;
+}
+
+tsm_status tsm_mark_refine(int64_t n_inst, const double* eta2, const int32_t* level, double theta, int32_t max_level,
+                           int32_t* level_new, int64_t* n_marked) {
+    if (n_inst < 0 || (n_inst > 0 && (!eta2 || !level || !level_new)))
+        return create_failed(nullptr, TSM_EINVAL, "tsm_mark_refine: bad arguments");
+    if (!(theta >= 0.0 && theta <= 1.0)) return create_failed(nullptr, TSM_EINVAL, "tsm_mark_refine: theta outside [0, 1]");
+    double total = 0.0;
+    std::vector<int64_t> cand;
+    for (int64_t i = 0; i < n_inst; ++i) {
+        if (!(eta2[i] >= 0.0) || !std::isfinite(eta2[i]))
+            return create_failed(nullptr, TSM_EINVAL, "tsm_mark_refine: eta2 negative or not finite");
+        if (level[i] < kMinLevel || level[i] > kMaxLevel)
+            return create_failed(nullptr, TSM_EINVAL, "tsm_mark_refine: level outside 2..64");
+        total += eta2[i];
+        if (2 * level[i] <= max_level) cand.push_back(i);
+        level_new[i] = level[i];
+    }
+    std::sort(cand.begin(), cand.end(), [&](int64_t x, int64_t y) {
+        if (eta2[x] != eta2[y]) return eta2[x] > eta2[y];
+        return x < y;
+    });
+    double acc = 0.0;
+    int64_t nm = 0;
+    for (int64_t i : cand) {
+        if (acc >= theta * total) break;
+        level_new[i] = 2 * level[i];
+        acc += eta2[i];
+        ++nm;
+    }
+    if (n_marked) *n_marked = nm;
+    return TSM_OK;
+}
+
+tsm_status tsm_prolong(int64_t n_inst, const int32_t* lo, const int32_t* ln, const double* vo, double* vn,
+                       void* stream) {
+    if (n_inst < 1 || !lo || !ln || !vo || !vn) return create_failed(nullptr, TSM_EINVAL, "tsm_prolong: bad arguments");
+    std::vector<int64_t> oo(n_inst + 1, 0), on(n_inst + 1, 0);
+    for (int64_t i = 0; i < n_inst; ++i) {
+        if (lo[i] < kMinLevel || lo[i] > kMaxLevel || !(ln[i] == lo[i] || ln[i] == 2 * lo[i]) || ln[i] > kMaxLevel)
+            return create_failed(nullptr, TSM_EINVAL,
+                                 "tsm_prolong: level_new[" + std::to_string(i) + "] is neither level_old nor twice it (<= 64)");
+        oo[i + 1] = oo[i] + (int64_t)(lo[i] + 1) * (lo[i] + 1);
+        on[i + 1] = on[i] + (int64_t)(ln[i] + 1) * (ln[i] + 1);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *dlo = nullptr, *dln = nullptr;
+    int64_t *doo = nullptr, *don = nullptr;
+    hipError_t e = dalloc(&dlo, n_inst);
+    if (e == hipSuccess) e = dalloc(&dln, n_inst);
+    if (e == hipSuccess) e = dalloc(&doo, n_inst + 1);
+    if (e == hipSuccess) e = dalloc(&don, n_inst + 1);
+    if (e == hipSuccess) e = hipMemcpy(dlo, lo, n_inst * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dln, ln, n_inst * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(doo, oo.data(), (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(don, on.data(), (n_inst + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_prolong((int)n_inst, dlo, dln, doo, don, vo, vn, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(dlo);
+    dfree(dln);
+    dfree(doo);
+    dfree(don);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return create_failed(nullptr, TSM_EHIP, std::string("tsm_prolong: ") + hipGetErrorString(e));
+    }
+    return TSM_OK;
+}
+
 void tsm_stationary_default_params(tsm_stationary_params* p) {
     if (!p) return;
     std::memset(p, 0, sizeof(*p));

@@ -262,6 +262,23 @@ struct StationaryLoadArgs {
     double* uDn;
 };
 hipError_t launch_stationary_loads(const StationaryLoadArgs& a, hipStream_t s);
+
+// Error indicator eta_i^2 of the micro fields v = v0 + u_i w (refine.hip).
+struct IndicatorArgs {
+    int n_inst;
+    const int32_t* level;
+    const int64_t* offsets;
+    const double* amp;
+    const double* u;
+    const double* v0;
+    const double* w;
+    double d;
+    double* eta2;          // [n_inst] out
+};
+hipError_t launch_indicator(const IndicatorArgs& a, hipStream_t s);
+// Nested Q1 interpolation of ragged fields: level ln[i] is lo[i] or 2 lo[i]
+hipError_t launch_prolong(int n_inst, const int32_t* lo, const int32_t* ln, const int64_t* oo, const int64_t* on,
+                          const double* vo, double* vn, hipStream_t s);
 // v_i = z0_i + k1 u_i zI_i + k3 w_i zO_i (z0 may be null: zero), ragged
 hipError_t launch_stationary_micro(int n_inst, const int64_t* offsets, const double* z0, const double* zI,
                                    const double* zO, const double* u, const double* w, double k1, double k3,

@@ -39,7 +39,8 @@ EXPORTED = ["tsm_default_params", "tsm_create", "tsm_set_reference_mesh", "tsm_g
             "tsm_set_deformation", "tsm_set_jacobians", "tsm_set_state", "tsm_step", "tsm_get_macro", "tsm_get_fluxes",
             "tsm_get_micro", "tsm_get_setup", "tsm_apply_operator", "tsm_gradient", "tsm_set_flags", "tsm_autotune", "tsm_get_stats",
             "tsm_last_error", "tsm_destroy", "tsm_stationary_default_params", "tsm_stationary_create",
-            "tsm_stationary_solve", "tsm_stationary_set_data", "tsm_stationary_get_stats"]
+            "tsm_stationary_solve", "tsm_stationary_set_data", "tsm_stationary_get_stats",
+            "tsm_error_indicator", "tsm_mark_refine", "tsm_prolong"]
 
 
 class tsm_params(ctypes.Structure):
@@ -117,6 +118,10 @@ def _load():
         "tsm_stationary_create": (I32, [ctypes.POINTER(tsm_stationary_params), VP, ctypes.POINTER(P)]),
         "tsm_stationary_solve": (I32, [P, VP, VP, VP]),
         "tsm_stationary_set_data": (I32, [P, VP, VP, VP, VP, VP, VP, VP]),
+        "tsm_error_indicator": (I32, [P, VP]),
+        "tsm_mark_refine": (I32, [I64, ctypes.POINTER(D), ctypes.POINTER(I32), D, I32, ctypes.POINTER(I32),
+                                  ctypes.POINTER(I64)]),
+        "tsm_prolong": (I32, [I64, ctypes.POINTER(I32), ctypes.POINTER(I32), VP, VP, VP]),
         "tsm_stationary_get_stats": (I32, [P, ctypes.POINTER(tsm_stationary_stats)]),
     }
     for name, (res, args) in sig.items():
@@ -277,6 +282,33 @@ def tsm_stationary_set_data(ctx, fv_cell=None, gv_bnd=None, fu_cell=None, fw_cel
                             uD=None) -> None:
     _check(ctx, _lib.tsm_stationary_set_data(ctx, _ptr(fv_cell), _ptr(gv_bnd), _ptr(fu_cell), _ptr(fw_cell),
                                              _ptr(gu_bnd), _ptr(gw_bnd), _ptr(uD)))
+
+
+def tsm_error_indicator(ctx, eta2_out) -> None:
+    _check(ctx, _lib.tsm_error_indicator(ctx, _ptr(eta2_out)))
+
+
+def tsm_mark_refine(eta2, level, theta: float, max_level: int = 64):
+    """Returns (new levels, number marked)."""
+    e = np.ascontiguousarray(eta2, dtype=np.float64)
+    lv = np.ascontiguousarray(level, dtype=np.int32)
+    out = np.empty_like(lv)
+    nm = ctypes.c_int64()
+    st = _lib.tsm_mark_refine(lv.size, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(theta), int(max_level),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(nm))
+    if st != TSM_OK:
+        raise TsmError(st, _lib.tsm_last_error(None).decode())
+    return out, nm.value
+
+
+def tsm_prolong(level_old, level_new, v_old, v_new, stream=None) -> None:
+    lo = np.ascontiguousarray(level_old, dtype=np.int32)
+    ln = np.ascontiguousarray(level_new, dtype=np.int32)
+    st = _lib.tsm_prolong(lo.size, lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(v_old), _ptr(v_new), stream)
+    if st != TSM_OK:
+        raise TsmError(st, _lib.tsm_last_error(None).decode())
 
 
 def tsm_stationary_get_stats(ctx) -> dict:

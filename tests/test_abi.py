@@ -134,3 +134,31 @@ def test_binding_constants_match_header():
     for name, base, shift in defs:
         value = int(base) << int(shift or 0)
         assert getattr(tsm, name) == value, name
+
+
+def test_mark_refine_matches_the_oracle(lib_built):
+    """Bulk marking is host code in the library: the same decisions as the
+    oracle's marking on seeded indicators (with ties), and its errors."""
+    import numpy as np
+    from oracle import refine
+    from paper_2103_17040_amd import tsm
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        n = int(rng.integers(1, 200))
+        eta = rng.exponential(size=n)
+        eta[rng.integers(0, n, size=n // 4)] = eta[0]          # ties
+        lv = rng.choice(np.array([8, 16, 32, 64], np.int32), n)
+        theta = float(rng.uniform(0, 1))
+        new, nm = tsm.tsm_mark_refine(eta, lv, theta, 64)
+        m = refine.mark(eta, lv, theta, 64)
+        expect = lv.copy()
+        expect[m] *= 2
+        assert np.array_equal(new, expect) and nm == len(m), trial
+    for eta, lv, th in (([1.0, -1.0], [8, 8], 0.5), ([1.0, np.nan], [8, 8], 0.5), ([1.0], [8], 1.5),
+                        ([1.0], [1], 0.5)):
+        with pytest.raises(tsm.TsmError) as e:
+            tsm.tsm_mark_refine(np.array(eta), np.array(lv, np.int32), th)
+        assert e.value.status == tsm.TSM_EINVAL
+    with pytest.raises(tsm.TsmError) as e:   # bad levels are refused before any device call
+        tsm.tsm_prolong(np.array([8], np.int32), np.array([12], np.int32), 0, 0)
+    assert e.value.status == tsm.TSM_EINVAL
