@@ -294,6 +294,68 @@ def stationary_leg(reps, parity=True):
     return res
 
 
+def refinement_leg(steps=5, theta=0.3):
+    """Error-indicator-driven micro refinement on the uneven 4225-instance
+    batch (16/32/64 cells, FP32+refinement): step, indicator of every micro
+    field, bulk marking over the global functional, nested interpolation
+    into the refined batch (new context: setup), and the step time before
+    and after.  Times: HIP-synchronised wall clock, median of 5 (indicator,
+    marking, interpolation)."""
+    import statistics
+    import torch
+    from paper_2103_17040_amd import TwoScaleBatch, tsm
+    w, a, th, lv = W.make("uneven_mixed", 0)
+    g = TwoScaleBatch(w.macro_cells, lv, a, th, D=w.D, d=w.d, kappa=w.kappa, p=w.p, dt=w.dt, sigma=w.sigma,
+                      precision="fp32_refine", rtol=w.rtol)
+
+    def timed(fn, reps=5):
+        ts, out = [], None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return statistics.median(ts), out
+
+    def step_ms(b):
+        b.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    try:
+        g.set_state(W.initial_macro(w.macro_cells), None)
+        before = step_ms(g)
+        ms_ind, eta = timed(lambda: g.error_indicator())
+        eta = eta.cpu().numpy()
+        ms_mark, (new, n_marked) = timed(lambda: tsm.tsm_mark_refine(eta, lv, theta, 64))
+        v = g.micro()
+        vn = torch.empty(int(W.offsets(new)[-1]), dtype=torch.float64, device="cuda:0")
+        ms_pro, _ = timed(lambda: tsm.tsm_prolong(lv, new, v, vn))
+        t0 = time.perf_counter()
+        g2, new2, _ = g.refine(theta)
+        t_refine = (time.perf_counter() - t0) * 1e3
+    finally:
+        g.close()
+    try:
+        after = step_ms(g2)
+        setup2 = g2.stats()["setup_ms"]
+    finally:
+        g2.close()
+    lv_b, c_b = np.unique(lv, return_counts=True)
+    lv_a, c_a = np.unique(new2, return_counts=True)
+    return {"workload": "4225 instances, 16/32/64 cells (uneven batch), FP32+refinement, theta %.2f" % theta,
+            "levels_before": dict(zip(map(str, lv_b.tolist()), c_b.tolist())),
+            "levels_after": dict(zip(map(str, lv_a.tolist()), c_a.tolist())), "marked": int(n_marked),
+            "micro_dofs_before": int(W.offsets(lv)[-1]), "micro_dofs_after": int(W.offsets(new2)[-1]),
+            "indicator_ms": ms_ind, "marking_ms": ms_mark, "prolong_ms": ms_pro,
+            "refine_total_ms": t_refine, "setup_ms_refined": setup2,
+            "ms_per_step_before": before, "ms_per_step_after": after}
+
+
 def _paper_table_rows():
     """Rows of Tables 1 and 2 from tests/golden/paper_convergence_tables.txt,
     the last rows un-swapped: {DoFs: (e_uw, e_uw_grad, e_v, e_v_grad)}."""
@@ -589,6 +651,9 @@ def main():
     if args.gm_steps > 0:
         _log("general-map leg ...")
         out["general_map"] = general_map_leg(args.gm_steps)
+    if args.gm_steps > 0:
+        _log("refinement leg ...")
+        out["refinement"] = refinement_leg()
     if args.st_reps > 0:
         _log("stationary three-field leg ...")
         out["stationary"] = stationary_leg(args.st_reps, parity=not args.no_parity)
