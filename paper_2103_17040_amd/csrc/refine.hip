@@ -20,16 +20,15 @@ namespace {
 
 constexpr int NT = 256;
 
-__device__ Pull pull_at_point(double a, double y1, double y2) {
-    double s1, c1, s2, c2;
-    sincospi(y1, &s1, &c1);
-    sincospi(y2, &s2, &c2);
-    return pullback_at(a, y1, y2, 0.25 * s1, 0.25 * M_PI * c1, 0.25 * s2, 0.25 * M_PI * c2);
-}
+constexpr int kCoords = 3 * kMaxLevel + 1;   // N+1 node and 2N Gauss coordinates of a side
 
-// one workgroup per instance; the micro state is v = v0 + u w
+// one workgroup per instance; the micro state v = v0 + u w is formed once
+// into LDS, and sin/cos of every node and Gauss coordinate of the mesh
+// (the only points the indicator visits) are tabulated there too
 __global__ __launch_bounds__(NT) void indicator_kernel(IndicatorArgs A) {
     __shared__ double red_s[2][1][NT / kWave];
+    __shared__ double vs[(kMaxLevel + 1) * (kMaxLevel + 1)];
+    __shared__ double ycoord[kCoords], ysin[kCoords], ycos[kCoords];
     BlockReducer<NT / kWave, 1, double> red(red_s);
     const int inst = blockIdx.x;
     const int N = A.level[inst], NP = N + 1;
@@ -38,7 +37,22 @@ __global__ __launch_bounds__(NT) void indicator_kernel(IndicatorArgs A) {
     const double* v0 = A.v0 + off;
     const double* w = A.w + off;
     const double h = 2.0 / N;
-    auto V = [&](int j1, int j2) { return v0[j2 * NP + j1] + u * w[j2 * NP + j1]; };
+    for (int j = threadIdx.x; j < NP * NP; j += NT) vs[j] = v0[j] + u * w[j];
+    // coordinate k: node k (k <= N), or Gauss point g of cell c at N + 1 + 2c + g
+    for (int k = threadIdx.x; k < 3 * N + 1; k += NT) {
+        const double y = k <= N ? -1.0 + k * h : -1.0 + (((k - NP) >> 1) + gauss_x((k - NP) & 1)) * h;
+        double s, c;
+        sincospi(y, &s, &c);
+        ycoord[k] = y;
+        ysin[k] = 0.25 * s;
+        ycos[k] = 0.25 * M_PI * c;
+    }
+    __syncthreads();
+    auto V = [&](int j1, int j2) { return vs[j2 * NP + j1]; };
+    // C at (node coordinate kn along one axis, Gauss coordinate kg along the other)
+    auto pull = [&](int k1, int k2) {
+        return pullback_at(a, ycoord[k1], ycoord[k2], ysin[k1], ycos[k1], ysin[k2], ycos[k2]);
+    };
     // work items: direction x interior line (1..N-1) x segment (0..N-1) x point
     const int lines = N - 1;
     const int n_items = 2 * lines * N * 2;
@@ -57,7 +71,7 @@ __global__ __launch_bounds__(NT) void indicator_kernel(IndicatorArgs A) {
                 ((V(j1, c2) - V(j1 - 1, c2)) * (1 - gx) + (V(j1, c2 + 1) - V(j1 - 1, c2 + 1)) * gx) / h;
             const double right =
                 ((V(j1 + 1, c2) - V(j1, c2)) * (1 - gx) + (V(j1 + 1, c2 + 1) - V(j1, c2 + 1)) * gx) / h;
-            const Pull P = pull_at_point(a, -1.0 + j1 * h, -1.0 + (c2 + gx) * h);
+            const Pull P = pull(j1, NP + 2 * c2 + g);
             jump = A.d * P.C11 * (right - left);
         } else {
             // line z2 = -1 + line h between the cells (seg, line-1) and (seg, line)
@@ -66,7 +80,7 @@ __global__ __launch_bounds__(NT) void indicator_kernel(IndicatorArgs A) {
                 ((V(c1, j2) - V(c1, j2 - 1)) * (1 - gx) + (V(c1 + 1, j2) - V(c1 + 1, j2 - 1)) * gx) / h;
             const double above =
                 ((V(c1, j2 + 1) - V(c1, j2)) * (1 - gx) + (V(c1 + 1, j2 + 1) - V(c1 + 1, j2)) * gx) / h;
-            const Pull P = pull_at_point(a, -1.0 + (c1 + gx) * h, -1.0 + j2 * h);
+            const Pull P = pull(NP + 2 * c1 + g, j2);
             jump = A.d * P.C22 * (above - below);
         }
         s += (h / 12.0) * 0.5 * h * jump * jump;
