@@ -298,7 +298,8 @@ tsm_status tsm_prolong(int64_t n_inst, const int32_t* level_old, const int32_t* 
  * are scaled by k1/k2 and the w rows by k3/k4 -- and v = z^0 + k1 u z^I +
  * k3 w z^O.
  * Use: tsm_stationary_create, tsm_set_reference_mesh, tsm_set_deformation
- * or tsm_set_jacobians (assemble S, b_I, b_O, M 1 and check the geometry),
+ * or tsm_set_jacobians (assemble S, b_I, b_O, the point weights of the loads
+ * and check the geometry), optionally tsm_stationary_set_data,
  * tsm_stationary_solve.  tsm_apply_operator applies this S; tsm_set_flags
  * takes the launch-plan flags; the time-stepping calls return ESTATE.
  * ------------------------------------------------------------------------- */

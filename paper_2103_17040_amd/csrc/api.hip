@@ -103,7 +103,7 @@ struct tsm_ctx {
     double grad_fwd_ms = 0.0, grad_bwd_ms = 0.0;
 
     // stationary three-field system (tsm_stationary_create): b holds b_I and
-    // len |G^I|; b_O, |G^O|, M 1, the three micro solutions, the five
+    // len |G^I|; b_O, |G^O|, the three micro solutions, the five
     // products per instance, w, the macro scratch and the iterations of the
     // three solves
     bool stationary = false;
@@ -696,7 +696,7 @@ namespace {
 // what(i) describes instance i for the geometry error message.
 // Assembly arguments of the context's operator: S = M/dt + d A + kappa B
 // with b = B 1 (time-dependent system), or S = Dv A + k2 B^I + k4 B^O with
-// b = b_I, b2 = b_O and M 1 (stationary system).
+// b = b_I, b2 = b_O and the point weights for the loads (stationary system).
 AssembleArgs assemble_base(tsm_ctx* c) {
     AssembleArgs as{};
     as.n_inst = (int)c->n_inst;

@@ -2,7 +2,7 @@
 // unknowns are eliminated.
 //
 // With the three micro solutions z^I = S^{-1} b_I, z^O = S^{-1} b_O and
-// z^0 = S^{-1} f^v M 1 of instance k, the micro field is
+// z^0 = S^{-1} F^v of instance k (F^v the load of f^v and g^v), the micro field is
 // v_k = z^0 + k1 u_k z^I + k3 w_k z^O, and the macro rows of u and w
 // (exchange integrals at the nodes with weights L_k) become, after scaling
 // the u rows by k1/k2 and the w rows by k3/k4,
