@@ -143,7 +143,8 @@ def test_case_B_paper_size_matches_oracle():
 
 def test_case_A_symmetry_at_paper_size():
     """Case A is symmetric about the horizontal centre line (the Case B map
-    is what breaks the symmetry, Section 4.4)."""
+    is what breaks the symmetry, Section 4.4) -- with data independent of
+    x2 and the identity map, independent of x2 altogether."""
     lv, _, Fc, Fb = W.stationary_case("A", 8, 64)
     banner("stationary Case A symmetry")
     u, w, v, _ = _gpu(8, lv, jac=(Fc, Fb), fv=1.0, fu=0.5)
@@ -151,6 +152,9 @@ def test_case_A_symmetry_at_paper_size():
     assert np.max(np.abs(U - U[::-1])) <= 1e-10 * np.max(np.abs(U))
     assert np.max(np.abs(Wm - Wm[::-1])) <= 1e-10 * np.max(np.abs(Wm))
     assert np.ptp(u) > 1e-2
+    # indeed independent of x2, as its data are
+    assert np.max(np.abs(U - U[0])) <= 1e-10 * np.max(np.abs(U))
+    assert np.max(np.abs(Wm - Wm[0])) <= 1e-10 * np.max(np.abs(Wm))
 
 
 def test_state_errors():

@@ -8,7 +8,12 @@ Section 4 experiments) against facts that do not come from the oracle:
   v = k1 u_D / k2, w = k4 v / k3 solves the system for every map (closed
   form) -- this is the Case A/B data of Table 3 as the text states them;
 * Case A is symmetric about the horizontal centre line (Section 4.4: the
-  Case B map is what breaks that symmetry);
+  Case B map is what breaks that symmetry), indeed independent of x2 (its
+  data are);
+* the normals in the printed Robin data of the manufactured problem (eq.
+  manu_data, fixture tests/golden/paper_manufactured_normals.txt) are those
+  of the left (G^I), right (G^O) and top (G^N) sides of the mapped cell:
+  they pin the data generator and the reading of the boundary parts;
 * manufactured solution of Section 4.2 (eq. manu_system, data re-derived
   with SymPy): observed orders ~2 in L2 and ~1 in H1 for the macro pair
   (u, w) and for v, the pattern of Tables 1 and 2.
@@ -96,6 +101,8 @@ def test_case_A_is_symmetric_about_the_centre_line():
     U = out["u"].reshape(5, 5)
     Wm = out["w"].reshape(5, 5)
     assert np.max(np.abs(U - U[::-1])) < 1e-12 and np.max(np.abs(Wm - Wm[::-1])) < 1e-12
+    # the data do not depend on x2, so neither does the solution
+    assert np.max(np.abs(U - U[0])) < 1e-12 and np.max(np.abs(Wm - Wm[0])) < 1e-12
     assert np.ptp(out["u"]) > 1e-2          # not the trivial constant state
     # v of node (k1, k2) is v of node (k1, 4 - k2) mirrored in z2
     for k in range(25):
@@ -136,3 +143,52 @@ def test_manufactured_convergence_orders():
         assert 0.9 < r < 1.3, (qM, qV)
     assert 1.9 < pM[-1] < 2.31 and 1.9 < pV[-1] < 2.31, (pM, pV)
     assert 0.95 < qM[-1] < 1.2 and 0.95 < qV[-1] < 1.2, (qM, qV)
+
+
+def _printed_normals():
+    import os
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_manufactured_normals.txt")) as fh:
+        for ln in fh:
+            if ln.strip() and not ln.startswith("#"):
+                k, v = ln.split()
+                vals[k] = float(v)
+    return vals
+
+
+@pytest.mark.parametrize("x", [(0.3, -0.4), (-0.7, 0.9)])
+def test_manufactured_data_match_the_printed_normals(x):
+    """The generated Robin data agree with the paper's printed g^v_1,
+    g^v_2 (and the top side's g^v_3) to the printed precision when G^I is
+    the left side, G^O the right and G^N top and bottom; another part
+    assignment does not reproduce them."""
+    from workloads import manufactured as MF
+    P = _printed_normals()
+    a, b, c, e = P["a"], P["b"], P["c"], P["e"]
+    prm = st.StationaryParams(macro_cells=0, Dv=1.3, Dw=0.5, kappa1=0.5, kappa2=1.2, kappa3=0.25, kappa4=0.9)
+    data = MF.manufactured(prm, MF.U_MANU, MF.V_MANU, MF.W_MANU, MF.ZETA_MANU)
+    zm = sy.lambdify((X1, X2, Z1, Z2), ZETA_MANU)
+    x1, x2 = x
+    u, w = x2 * np.sin(x1), x1 * np.cos(x2)
+    t = np.linspace(-0.9, 0.9, 7)
+    one = np.ones_like(t)
+    printed = [
+        (-one, t, lambda y0, y1, v: prm.Dv * (a * y0 * y1 - a * y0 * (1 - y1) - b * y1 * (1 - y1))
+         - prm.kappa1 * u + prm.kappa2 * v),
+        (one, t, lambda y0, y1, v: prm.Dv * (-a * y0 * y1 + a * y0 * (1 - y1) + b * y1 * (1 - y1))
+         - prm.kappa3 * w + prm.kappa4 * v),
+        (t, one, lambda y0, y1, v: prm.Dv * (-c * y0 * y1 + c * y0 * (1 - y1) + e * y1 * (1 - y1))),
+    ]
+    for z1, z2, g in printed:
+        y0, y1 = zm(x1, x2, z1, z2)
+        v = x1 + x2 + y0 * y1 * (1 - y1)
+        gen = data.gv(None, x1, x2, z1, z2)
+        assert np.max(np.abs(gen - g(y0, y1, v))) < 2e-4 * (1 + np.max(np.abs(gen)))
+    # G^I on the bottom side instead: the printed g^v_1 is not its datum
+    prm2 = st.StationaryParams(macro_cells=0, Dv=1.3, Dw=0.5, kappa1=0.5, kappa2=1.2, kappa3=0.25, kappa4=0.9,
+                               parts=(1, 0, 0, 2))
+    d2 = MF.manufactured(prm2, MF.U_MANU, MF.V_MANU, MF.W_MANU, MF.ZETA_MANU)
+    y0, y1 = zm(x1, x2, t, -one)
+    v = x1 + x2 + y0 * y1 * (1 - y1)
+    g1 = printed[0][2]
+    assert np.max(np.abs(d2.gv(None, x1, x2, t, -one) - g1(y0, y1, v))) > 1e-2
