@@ -102,6 +102,52 @@ def test_refined_batch_steps_like_the_oracle():
     assert rel(u, r2["u"][-1]) <= 1e-10 and rel(v, r2["v"]) <= 1e-10
 
 
+def test_two_refinements_step_like_the_oracle():
+    """Two rounds of step and refine (theta = 0.6: meshes go up to twice
+    refined), then steps on the final meshes, against the oracle."""
+    from paper_2103_17040_amd import TwoScaleBatch
+    NM, lv, a = _case(seed=12)
+    dt, k = 0.01, 2
+    u0 = W.initial_macro(NM)
+    banner(f"two refinements NM={NM} levels={sorted(set(lv.tolist()))}")
+    # oracle
+    levels, u, v = lv.copy(), u0, np.zeros(int(W.offsets(lv)[-1]))
+    marks = []
+    for _ in range(2):
+        ts = twoscale.TwoScale(twoscale.Params(NM, dt), levels, a)
+        r = ts.run(u, v, k)
+        u, v = r["u"][-1], r["v"]
+        off = W.offsets(levels)
+        eta = np.array([refine.indicator(int(levels[i]), v[off[i]:off[i + 1]], a[i], d=0.5)
+                        for i in range(len(levels))])
+        m = refine.mark(eta, levels, 0.6)
+        srt = np.sort(eta[levels * 2 <= 64])[::-1]
+        assert len(m) < len(srt) and (srt[len(m) - 1] - srt[len(m)]) > 1e-6 * srt[0]
+        new = levels.copy()
+        new[m] *= 2
+        v = np.concatenate([refine.prolong(int(levels[i]), v[off[i]:off[i + 1]]) if new[i] != levels[i]
+                            else v[off[i]:off[i + 1]] for i in range(len(levels))])
+        levels = new
+        marks.append(new)
+    r = twoscale.TwoScale(twoscale.Params(NM, dt), levels, a).run(u, v, k)
+    # GPU
+    g = TwoScaleBatch(NM, lv, a, dt=dt, rtol=1e-13)
+    try:
+        g.set_state(u0, None)
+        for rnd in range(2):
+            g.step(k)
+            g2, new, _ = g.refine(0.6)
+            g.close()
+            g = g2
+            assert np.array_equal(new, marks[rnd]), rnd
+        g.step(k)
+        ug, vg = g.macro().cpu().numpy(), g.micro().cpu().numpy()
+    finally:
+        g.close()
+    banner(f"  final levels {sorted(set(levels.tolist()))}; rel u {rel(ug, r['u'][-1]):.2e} v {rel(vg, r['v']):.2e}")
+    assert rel(ug, r["u"][-1]) <= 1e-10 and rel(vg, r["v"]) <= 1e-10
+
+
 def test_indicator_state_errors():
     from paper_2103_17040_amd import TwoScaleBatch, tsm
     NM, lv, a = _case(NM=2)

@@ -282,3 +282,27 @@ def test_manufactured_orders_on_gpu():
         assert 0.9 < r < 1.3, (qM, qV)
     assert 1.9 < pM[-1] < 2.31 and 1.9 < pV[-1] < 2.31, (pM, pV)
     assert 0.95 < qM[-1] < 1.2 and 0.95 < qV[-1] < 1.2, (qM, qV)
+
+
+def test_data_arrays_equal_the_constants():
+    """Sources and Dirichlet values given at the quadrature points with the
+    constant values reproduce the constant path bit for bit (the loads
+    kernel does the same arithmetic), and zero Robin/Neumann data change
+    nothing."""
+    from paper_2103_17040_amd import StationarySystem
+    NM = 4
+    levels = np.asarray([[8, 16, 32][i % 3] for i in range(25)], dtype=np.int32)
+    _, Fc, Fb = _case_tables("B", NM, levels)
+    banner("stationary data arrays vs constants")
+    ref = _gpu(NM, levels, jac=(Fc, Fb), fu=0.3, fv=1.0, fw=-0.2, uD=1.5)
+    n_cell = int(4 * np.sum(levels.astype(np.int64) ** 2))
+    n_bnd = int(8 * np.sum(levels))
+    g = StationarySystem(NM, levels, jacobians=(Fc, Fb), rtol=1e-14, **PHYS)
+    try:
+        g.set_data(fv_cell=np.full(n_cell, 1.0), gv_bnd=np.zeros(n_bnd), fu_cell=np.full(4 * NM * NM, 0.3),
+                   fw_cell=np.full(4 * NM * NM, -0.2), gu_bnd=np.zeros(8 * NM), gw_bnd=np.zeros(8 * NM),
+                   uD=np.full(25, 1.5))
+        u, w, v = (t.cpu().numpy() for t in g.solve())
+    finally:
+        g.close()
+    assert np.array_equal(u, ref[0]) and np.array_equal(w, ref[1]) and np.array_equal(v, ref[2])
