@@ -294,6 +294,50 @@ def stationary_leg(reps, parity=True):
     return res
 
 
+def stationary_oracle_time():
+    """The oracle (test infrastructure) on the same Case B problem at the
+    paper's size: one monolithic sparse LU solve (scipy), timed on the host."""
+    from oracle import stationary as ost
+    lv, per, _, _ = W.stationary_case("B", 8, 64)
+    t0 = time.perf_counter()
+    ost.solve(ost.StationaryParams(macro_cells=8), lv, per, ost.constant_data(fv=1.0))
+    return {"solve_s": time.perf_counter() - t0, "kind": "oracle", "cores": 1,
+            "sample": "the whole Case B problem at 81 x 4225 DoFs: one sparse LU of the monolithic system"}
+
+
+def refinement_oracle_time(theta=0.3, sample=12):
+    """The oracle's indicator, marking and interpolation (test
+    infrastructure) on a sample of the refinement leg's instances, scaled to
+    the batch by DoFs; the marking on the whole batch."""
+    from oracle import refine as orf
+    w, a, th, lv = W.make("uneven_mixed", 0)
+    rng = np.random.default_rng(1)
+    pick = rng.choice(len(lv), size=sample, replace=False)
+    n_b = float(((lv.astype(np.int64) + 1) ** 2).sum())
+    n_s = float(((lv[pick].astype(np.int64) + 1) ** 2).sum())
+    t0 = time.perf_counter()
+    for i in pick:
+        N = int(lv[i])
+        z = np.linspace(-1.0, 1.0, N + 1)
+        v = np.add.outer(z ** 2, np.abs(z)).ravel()
+        orf.indicator(N, v, a[i], th[i] if th is not None else 0.0)
+    t_ind = time.perf_counter() - t0
+    eta = rng.exponential(size=len(lv))
+    t0 = time.perf_counter()
+    orf.mark(eta, lv, theta)
+    t_mark = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for i in pick:
+        N = int(lv[i])
+        if 2 * N <= 64:
+            orf.prolong(N, np.zeros((N + 1) ** 2))
+    t_pro = time.perf_counter() - t0
+    return {"indicator_ms": t_ind * n_b / n_s * 1e3, "marking_ms": t_mark * 1e3,
+            "prolong_ms": t_pro * n_b / n_s * 1e3, "kind": "oracle", "cores": 1,
+            "sample": f"indicator and interpolation on {sample} sampled instances, scaled to the batch by DoFs; "
+                      "marking on the whole batch"}
+
+
 def refinement_leg(steps=5, theta=0.3):
     """Error-indicator-driven micro refinement on the uneven 4225-instance
     batch (16/32/64 cells, FP32+refinement): step, indicator of every micro
@@ -654,9 +698,13 @@ def main():
     if args.gm_steps > 0:
         _log("refinement leg ...")
         out["refinement"] = refinement_leg()
+        if not args.no_cpu_baseline:
+            out["refinement"]["cpu_oracle"] = refinement_oracle_time()
     if args.st_reps > 0:
         _log("stationary three-field leg ...")
         out["stationary"] = stationary_leg(args.st_reps, parity=not args.no_parity)
+        if not args.no_cpu_baseline:
+            out["stationary"]["case_B_81x4225"]["cpu_oracle"] = stationary_oracle_time()
         _log("stationary convergence leg ...")
         out["stationary"]["convergence"] = stationary_convergence_leg()
     if not args.no_cpu_baseline:
