@@ -542,6 +542,29 @@ def cpu_baseline(w, a, th, lv, seconds_hint=15.0):
                       f"(setup {t_setup:.1f} s excluded, as for the GPU value)"}
 
 
+def oracle_rate(w, lv, a, th, jacobians=None, fixed_point=False, S=3, seconds=4.0):
+    """The oracle (as it stands, one core) on (S+1)^2 instances with the
+    given micro meshes and geometry: micro DoF-updates per second of its
+    exact step, or of the paper's alternating step (fixed_point)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import twoscale
+    n = (S + 1) ** 2
+    with threadpool_limits(limits=1):
+        ts = twoscale.TwoScale(twoscale.Params(S, w.dt, w.D, w.d, w.kappa, w.p, w.sigma), np.resize(lv, n)[:n],
+                               a[:n], None if th is None else th[:n],
+                               jacobians=None if jacobians is None else jacobians[:n])
+        u, v = W.initial_macro(S), np.zeros(int(ts.offsets[-1]))
+        K, t0 = 0, time.perf_counter()
+        while K < 1 or time.perf_counter() - t0 < seconds:
+            u, v = (ts.step_fixed_point(u, v)[:2] if fixed_point else ts.step(u, v)[:2])
+            K += 1
+        t = time.perf_counter() - t0
+    return {"value": int(ts.offsets[-1]) * K / t, "unit": "micro DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} instances ({S}x{S} macro cells), {K} steps"
+                      + (", the alternating coupling" if fixed_point else "")
+                      + (", geometry from the Jacobian tables" if jacobians is not None else "")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -688,6 +711,9 @@ def main():
     fpl = main_form["fixed_point"]
     if fpl is not None:
         fpl["over_exact_step"] = fpl["ms_per_step"] / out["ms_per_step"]
+        fpl["value"] = n_dofs / (fpl["ms_per_step"] * 1e-3)
+        if not args.no_cpu_baseline:
+            fpl["cpu_oracle"] = oracle_rate(w, lv, a, th, fixed_point=True)
         out["fixed_point_coupling"] = fpl
     if not args.no_parity:
         _log("parity leg ...")
@@ -695,6 +721,13 @@ def main():
     if args.gm_steps > 0:
         _log("general-map leg ...")
         out["general_map"] = general_map_leg(args.gm_steps)
+        gm = out["general_map"]
+        gm["value"] = gm["micro_dofs"] / (gm["ms_per_step"] * 1e-3)
+        if not args.no_cpu_baseline:
+            wu, au, thu, lvu = W.make("uneven_mixed", 0)
+            per, _, _ = W.jacobian_tables(lvu[:16], W.polynomial_map_jacobian,
+                                          W.polynomial_map_params(len(lvu), seed=2)[:16])
+            gm["cpu_oracle"] = oracle_rate(wu, lvu[:16], au, thu, jacobians=per)
     if args.gm_steps > 0:
         _log("refinement leg ...")
         out["refinement"] = refinement_leg()
