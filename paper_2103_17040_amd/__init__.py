@@ -142,7 +142,9 @@ class TwoScaleBatch:
         v_new = self._empty(n_new)
         self.torch.cuda.synchronize(self.device)
         tsm.tsm_prolong(levels, new_levels, v, v_new)
-        g = TwoScaleBatch(self.params.macro_cells, new_levels, self._a, self._theta, **self._ctor)
+        kw = dict(self._ctor)
+        kw["flags"] = self._flags          # keep a plan chosen since construction
+        g = TwoScaleBatch(self.params.macro_cells, new_levels, self._a, self._theta, **kw)
         g.set_state(u, v_new)
         return g, new_levels, eta2
 
