@@ -263,6 +263,55 @@ def test_kappa_zero_macro_closed_form():
     assert np.abs(out["F"]).max() == 0.0
 
 
+def _integral_of_square_by_quadrature(NM, u):
+    """int_Omega u_h^2 of the Q1 interpolant with nodal values u, by a 3x3
+    Gauss rule on every macro cell (exact: u_h^2 has degree 2 per variable).
+    Written from the bilinear interpolant itself, not from any mass matrix."""
+    H = 1.0 / NM
+    g, wg = np.polynomial.legendre.leggauss(3)
+    t, wt = 0.5 * (g + 1.0), 0.5 * wg
+    U = np.asarray(u).reshape(NM + 1, NM + 1)          # [k2, k1]
+    total = 0.0
+    for c2 in range(NM):
+        for c1 in range(NM):
+            u00, u10 = U[c2, c1], U[c2, c1 + 1]
+            u01, u11 = U[c2 + 1, c1], U[c2 + 1, c1 + 1]
+            for s, ws in zip(t, wt):
+                for r, wr in zip(t, wt):
+                    val = (u00 * (1 - s) * (1 - r) + u10 * s * (1 - r)
+                           + u01 * (1 - s) * r + u11 * s * r)
+                    total += ws * wr * H * H * val * val
+    return total
+
+
+@pytest.mark.parametrize("NM", [3, 8, 13])
+def test_observable_is_integral_of_square(NM):
+    """J = u^T M_H u is the integral of u_h^2 over Omega.  For
+    u = I_h(sin pi x1 sin pi x2) it has the closed form
+    J = m1^2 (NM/2)^2, m1 = H/6 (4 + 2 cos pi H) (the 1D Q1 mass eigenvalue
+    of the sine mode, whose squared nodal norm is NM/2); at NM = 8 this is
+    0.2374742089066.  A direct quadrature of u_h^2 agrees for any nodal
+    values (here random ones, boundary included).  A lumped-mass J
+    (L = diag(M_H 1) in place of M_H) differs from both, so this pin sees it."""
+    prm = _prm(NM)
+    ts = twoscale.TwoScale(prm, np.full((NM + 1) ** 2, 2), np.zeros((NM + 1) ** 2))
+    u = W.initial_macro(NM)
+    H = 1.0 / NM
+    m1 = H / 6 * (4 + 2 * math.cos(math.pi * H))
+    closed = m1 * m1 * (NM / 2.0) ** 2
+    assert abs(ts.observable(u) - closed) <= 1e-14 * closed
+    if NM == 8:
+        assert abs(closed - 0.2374742089066) < 1e-12
+    rng = np.random.default_rng(NM)
+    ur = rng.standard_normal((NM + 1) ** 2)
+    q = _integral_of_square_by_quadrature(NM, ur)
+    assert abs(ts.observable(ur) - q) <= 1e-13 * q
+    # a planted mistake: the lumped mass in place of M_H
+    lumped = float(np.sum(ts.L * u * u))
+    assert abs(lumped - closed) > 1e-3 * closed
+    assert abs(float(np.sum(ts.L * ur * ur)) - q) > 1e-3 * q
+
+
 def test_constant_amplitude_rank_one_reduction():
     """a = const, v^0 = 0, u^0 = I_h(sin sin): u^n = rho_n u^0 and
     v_i^n = u^0_i V^n, where (rho, V) solve a one-instance system with the
