@@ -4,8 +4,8 @@
  * Method (arXiv 2103.17040):
  *   - one micro problem per macro degree of freedom, posed on a shared
  *     reference cell Z = [-1,1]^2 and fed the nodal macro value u_i
- *     (Section 3.3, micro system at the support point of the macro basis
- *     function);
+ *     (Section 3.3, structure of the implementation: the micro system sits
+ *     at the support point of the macro basis function);
  *   - micro integrals pulled back to Z with K = (D zeta)^{-1} and
  *     J = det D zeta (Section 3.1, equations grad_map and det_map): the
  *     stiffness weight is K K^T J per quadrature point and the boundary
@@ -17,7 +17,9 @@
  *     micro boundary and its mean as the macro source (Section 2.1, model
  *     system; the macro source carries the sign source_sign, -1 being the
  *     paper's sink);
- *   - every system solved by preconditioned conjugate gradients (Section 3.3).
+ *   - every system solved by preconditioned conjugate gradients, the
+ *     systems distributed over the processors (Section 3.5, parallelization
+ *     in assembly).
  *
  * Time-dependent system stepped by implicit Euler with step dt:
  *   u_t - D Lap u = source_sign * mean_{dY_x} kappa (p u - v)  in [0,1]^2, u = 0 on the boundary
@@ -76,7 +78,8 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
 #define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
                                             HIP events on the context's stream (see tsm_stats) */
 #define TSM_FLAG_FIXED_POINT (1ull << 5) /* tsm_step couples macro and micro solves by the paper's
-                                            alternating iteration (Section 3.3): macro solve with
+                                            alternating iteration (Section 3.3; the residual sum is
+                                            the threshold of Section 3.5): macro solve with
                                             the micro data lagged, then every micro solve with the
                                             new macro values, until the residual sum (macro
                                             residual norm + mean micro residual norm) changes by
@@ -142,30 +145,48 @@ typedef struct tsm_ctx tsm_ctx;
  * fp_max_iter 50. */
 void tsm_default_params(tsm_params* p);
 
-/* Create a context on the current HIP device.  stream is a hipStream_t
- * (NULL: the null stream).  The context owns every device buffer it
- * allocates.  EINVAL on bad parameters. */
+/* Create a context on the current HIP device.  The parameters are those of
+ * the model (Section 2.1, model problem: diffusions D and d, exchange rate
+ * kappa, partition coefficient p, the sign of the macro exchange term) plus
+ * the time step and the solver controls (conjugate gradients, Section 3.5).
+ * p: host pointer, read during the call.  stream is a hipStream_t (NULL: the
+ * context creates its own non-blocking stream).  *out receives the context,
+ * which owns every device buffer it allocates (free with tsm_destroy).
+ * EINVAL on a parameter out of range (message in tsm_last_error(NULL)),
+ * EHIP if the device cannot be queried. */
 tsm_status tsm_create(const tsm_params* p, void* stream, tsm_ctx** out);
 
-/* Reference mesh of every instance: micro_cells[i] = N_i in 2..64 cells per
- * side of K_h (host pointer, n_inst entries, n_inst == (N_M+1)^2).
- * Allocates the ragged buffers.  Invalidates any deformation and state. */
+/* Reference mesh of every instance (Section 3.1, approximation: the
+ * partition K_h of the reference domain Z and its Q1 space V_h; Section
+ * 3.3: one micro system per macro degree of freedom, so instance i belongs
+ * to macro node i of the partition B_H): micro_cells[i] = N_i in 2..64
+ * cells per side of K_h (host pointer, n_inst entries, read during the call;
+ * n_inst == (N_M+1)^2, else EINVAL; a size outside 2..64: EINVAL).
+ * Allocates the ragged buffers (ENOMEM if that fails).  Invalidates any
+ * deformation and state. */
 tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_t n_inst);
 
 /* Ragged layout: offsets_out[0..n_inst] (host pointer, n_inst+1 entries). */
 tsm_status tsm_get_offsets(const tsm_ctx* c, int64_t* offsets_out);
 
-/* Deformation amplitudes a_i and rotation angles theta_i (device pointers,
- * n_inst doubles each; theta may be NULL = 0).  Checks that every value is
- * finite (EINVAL) and det D zeta > 0 at every quadrature point (EGEOM), then
- * runs setup: assembles each S_i = M_i/dt + d A_i + kappa B_i, solves the
- * responses w_i and builds the macro solver.  The rotation leaves K K^T J and
- * |cof(F) nu| unchanged, so it does not enter the arithmetic. */
+/* The domain map zeta_x of every instance (Section 2.1: the micro domain
+ * Y_x is the image of Z under zeta(x, .); Section 3.1, equations grad_map and
+ * det_map: K = (D zeta)^{-1}, J = det D zeta, and the change of variables with
+ * |cof(F) nu| on the boundary; Section 3.4, domain mappings: J and K K^T J
+ * per quadrature point): the family zeta_x(y) = R_theta (y + a (sin(pi y1)
+ * y2, sin(pi y2) y1) / 4) with amplitudes a_i and rotation angles theta_i
+ * (device pointers, n_inst doubles each, caller-owned, read during the call;
+ * theta may be NULL = 0).  EINVAL if n_inst differs from the mesh's or a
+ * value is not finite, ESTATE before tsm_set_reference_mesh, EGEOM if
+ * det D zeta <= 0 at some quadrature point.  Then runs setup: assembles each
+ * S_i = M_i/dt + d A_i + kappa B_i, solves the responses w_i and builds the
+ * macro solver.  The rotation leaves K K^T J and |cof(F) nu| unchanged, so it
+ * does not enter the arithmetic. */
 tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta, int64_t n_inst);
 
 /* General maps (Section 3.1: the map zeta enters the discrete problem only
- * through its Jacobian at the quadrature points, whence the paper's cache of
- * J and K K^T J per point).  Fcell and Fbnd (device pointers, row-major 2x2
+ * through its Jacobian at the quadrature points; Section 3.4, domain
+ * mappings: the paper caches J and K K^T J per point).  Fcell and Fbnd (device pointers, row-major 2x2
  * Jacobians F = D zeta, entries F11 F12 F21 F22) give D zeta of every
  * instance at the reference points y = -1 + (cell + g) h, h = 2/N,
  * g in {1/2 - 1/(2 sqrt 3), 1/2 + 1/(2 sqrt 3)}:
@@ -183,37 +204,65 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
  * for a geometry given this way (ESTATE). */
 tsm_status tsm_set_jacobians(tsm_ctx* c, const double* Fcell, int64_t n_cell, const double* Fbnd, int64_t n_bnd);
 
-/* State (device pointers): u has n_inst entries (macro-boundary entries
- * are forced to 0), v is ragged or NULL (= 0).  Resets steps_taken. */
-tsm_status tsm_set_state(tsm_ctx* c, const double* u, const double* v);
+/* State of the coupled system (Section 2.1, the fields u and v; Section 3.1,
+ * their expansions u = sum_i u_i xi_i and v = sum_ij v_ij xi_i (eta_j pulled
+ * back to Z)): u the nodal macro values (device pointer, n_u == n_inst
+ * entries; macro-boundary entries are forced to 0), v the ragged micro
+ * coefficients (device pointer, n_v == total micro DoFs, or NULL = 0 with n_v
+ * ignored).  Copied during the call.  EINVAL on a NULL u, a wrong count or a
+ * non-finite u; ESTATE before the geometry is set or on a stationary context.
+ * Resets steps_taken. */
+tsm_status tsm_set_state(tsm_ctx* c, const double* u, int64_t n_u, const double* v, int64_t n_v);
 
-/* Advance n_steps >= 0 implicit-Euler steps on the context's stream, then
- * synchronise it.  ENOCONV if any solve missed its tolerance (the state is
- * still advanced with the last iterate; see tsm_get_stats). */
+/* Advance n_steps >= 0 implicit-Euler steps of the coupled discrete system
+ * (the discrete weak form on the reference cell, Section 3.1, in its
+ * time-dependent two-field form; one micro solve per macro node, Section
+ * 3.3, by preconditioned CG, Section 3.5) on the context's stream, then
+ * synchronise it.  EINVAL if n_steps < 0, ESTATE before tsm_set_state,
+ * ENOCONV if any solve missed its tolerance (the state is still advanced with
+ * the last iterate; see tsm_get_stats), EHIP on a runtime error. */
 tsm_status tsm_step(tsm_ctx* c, int32_t n_steps);
 
-/* Outputs (device pointers, written on the context's stream, then synchronised):
- * macro field u (n_inst), mean Robin fluxes F_i of the last step (n_inst),
- * micro field v (ragged). */
-tsm_status tsm_get_macro(const tsm_ctx* c, double* u_out);
-tsm_status tsm_get_fluxes(const tsm_ctx* c, double* F_out);
-tsm_status tsm_get_micro(const tsm_ctx* c, double* v_out);
+/* Outputs (caller-owned device pointers with their entry counts, written on
+ * the context's stream, then synchronised; ESTATE without a state, EINVAL on
+ * NULL or a wrong count):
+ *   tsm_get_macro   the macro field u (Section 2.1; its nodal values,
+ *                   Section 3.1), n == n_inst;
+ *   tsm_get_fluxes  the mean micro Robin flux of every instance in the last
+ *                   step, F_i = mean over dY_i of kappa (p u_i - v) (the
+ *                   exchange integral of the macro equation, Section 2.1),
+ *                   n == n_inst;
+ *   tsm_get_micro   the micro field v (ragged, offsets via tsm_get_offsets),
+ *                   n == total micro DoFs. */
+tsm_status tsm_get_macro(const tsm_ctx* c, double* u_out, int64_t n);
+tsm_status tsm_get_fluxes(const tsm_ctx* c, double* F_out, int64_t n);
+tsm_status tsm_get_micro(const tsm_ctx* c, double* v_out, int64_t n);
 
-/* Setup quantities (device pointers, n_inst each or NULL to skip): response
- * functional beta_i = kappa p - (kappa/|dY_i|) b_i^T w_i, boundary length
- * |dY_i| = 1^T b_i; and the ragged response w (NULL to skip). */
-tsm_status tsm_get_setup(const tsm_ctx* c, double* beta_out, double* len_out, double* w_out);
+/* Setup quantities (caller-owned device pointers, NULL to skip): response
+ * functional beta_i = kappa p - (kappa/|dY_i|) b_i^T w_i and boundary length
+ * |dY_i| = 1^T b_i (n_inst entries each, n_inst must match when either is
+ * given), and the ragged response w (n_w == total micro DoFs when given).
+ * EINVAL on a wrong count, ESTATE before the geometry is set. */
+tsm_status tsm_get_setup(const tsm_ctx* c, double* beta_out, double* len_out, int64_t n_inst, double* w_out,
+                         int64_t n_w);
 
-/* y = S x for every instance with the assembled FP64 operator
- * (device pointers, ragged). */
-tsm_status tsm_apply_operator(tsm_ctx* c, const double* x, double* y);
+/* y = S x for every instance with the assembled FP64 operator (the micro
+ * matrix of the discrete weak form, Section 3.1); x and y are caller-owned
+ * ragged device vectors of n == total micro DoFs entries.  EINVAL on NULL or
+ * a wrong count, ESTATE before the geometry is set. */
+tsm_status tsm_apply_operator(tsm_ctx* c, const double* x, double* y, int64_t n);
 
 /* Gradient of J = u(T)^T M_H u(T) (the integral of u_h(T)^2) after n_steps
- * steps from the current state with respect to the amplitudes a_i:
- * forward with checkpoints every checkpoint_every steps, then the discrete
- * adjoint backwards.  J_out is a host pointer, dJda_out a device pointer
- * (n_inst).  The current state is left unchanged. */
-tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda_out);
+ * steps from the current state with respect to the amplitudes a_i of the
+ * domain map (the paper has no adjoint; this is the exact derivative of the
+ * discrete forward map of tsm_step): forward with checkpoints every
+ * checkpoint_every steps, then the discrete adjoint backwards, segment by
+ * segment.  J_out is a host pointer, dJda_out a caller-owned device pointer
+ * of n == n_inst entries.  The current state is left unchanged.  EINVAL on
+ * n_steps < 1, NULL or a wrong count; ESTATE before tsm_set_state or for a
+ * geometry given by Jacobian tables; ENOMEM if the checkpoint buffers cannot
+ * be allocated; ENOCONV if a solve missed its tolerance. */
+tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda_out, int64_t n);
 
 /* Replace the launch flags (TSM_FLAG_*) of a context; rebuilds the step
  * graph if set_deformation has run.  Results are bitwise identical under
@@ -233,9 +282,15 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags);
  * set_state first. */
 tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* flags_out);
 
+/* Statistics of the last calls (host pointer *s, filled; EINVAL on NULL).
+ * Bookkeeping only: iterations, sweeps and times, no passage of the method. */
 tsm_status tsm_get_stats(const tsm_ctx* c, tsm_stats* s);
+/* The context's last error message (owned by the context, valid until the
+ * next call on it); NULL: the calling thread's last failure of a call that
+ * has no context (create, mark, prolong). */
 const char* tsm_last_error(const tsm_ctx* c);
-void tsm_destroy(tsm_ctx* c);   /* NULL-safe */
+/* Release the context and every device buffer it owns.  NULL-safe. */
+void tsm_destroy(tsm_ctx* c);
 
 /* ---------------------------------------------------------------------------
  * Refinement of the micro meshes from an error indicator -- an extension the
@@ -250,8 +305,8 @@ void tsm_destroy(tsm_ctx* c);   /* NULL-safe */
  * the jump of the pulled-back flux (C = K K^T J, Section 3.1) integrated with
  * the 2-point rule.  Needs set_state; ESTATE for a geometry given by Jacobian
  * tables (C is needed at points the tables do not hold) and for a
- * stationary context. */
-tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out);
+ * stationary context; EINVAL unless n == n_inst. */
+tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out, int64_t n);
 
 /* Bulk marking over the global functional sum_i eta2[i]: the fewest
  * instances with 2 level[i] <= max_level, largest eta2 first (ties: lower
@@ -265,13 +320,15 @@ tsm_status tsm_mark_refine(int64_t n_inst, const double* eta2, const int32_t* le
 
 /* Nested Q1 interpolation of a ragged micro field from the meshes level_old
  * to level_new (host pointers, n_inst each; level_new[i] is level_old[i] or
- * 2 level_old[i], at most 64): v_old (ragged by level_old) to v_new (ragged
- * by level_new), device pointers.  A fine node takes the coarse value at a
- * corner, the mean of 2 on an edge midpoint, of 4 at a cell centre.  Runs on
- * `stream` (a hipStream_t, NULL: the null stream) and synchronises it.
- * EINVAL on bad levels (message in tsm_last_error(NULL)). */
+ * 2 level_old[i], at most 64): v_old (ragged by level_old, n_old entries)
+ * to v_new (ragged by level_new, n_new entries), device pointers.  A fine
+ * node takes the coarse value at a corner, the mean of 2 on an edge
+ * midpoint, of 4 at a cell centre.  Runs on `stream` (a hipStream_t, NULL:
+ * the null stream) and synchronises it.  Stages the level and offset arrays
+ * in device memory it allocates for the call.  EINVAL on bad levels or
+ * counts (message in tsm_last_error(NULL)). */
 tsm_status tsm_prolong(int64_t n_inst, const int32_t* level_old, const int32_t* level_new, const double* v_old,
-                       double* v_new, void* stream);
+                       int64_t n_old, double* v_new, int64_t n_new, void* stream);
 
 /* ---------------------------------------------------------------------------
  * The paper's stationary three-field system (Section 2.1 model; the Case A/B
@@ -346,11 +403,12 @@ void tsm_stationary_default_params(tsm_stationary_params* p);
 tsm_status tsm_stationary_create(const tsm_stationary_params* p, void* stream, tsm_ctx** out);
 
 /* Solve the system.  u_out, w_out: device pointers, n_inst doubles each;
- * v_out: device pointer, ragged (or NULL to skip).  ESTATE before the
- * geometry is set or on a context made by tsm_create; ENOCONV if a micro
- * solve missed rtol or the macro solve missed macro_rtol (outputs are still
- * written, from the last iterates). */
-tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double* v_out);
+ * v_out: device pointer, ragged, n_v == total micro DoFs (or NULL to skip).
+ * EINVAL on a wrong count; ESTATE before the geometry is set or on a context
+ * made by tsm_create; ENOCONV if a micro solve missed rtol or the macro
+ * solve missed macro_rtol (outputs are still written, from the last
+ * iterates). */
+tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, int64_t n_inst, double* v_out, int64_t n_v);
 
 /* Data at quadrature points instead of the constants (Section 4.1, the
  * manufactured form; NULL keeps the constant of the parameters, or zero for
@@ -364,11 +422,14 @@ tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double
  *   gu_bnd, gw_bnd: grad u . n and Dw grad w . n at the macro boundary
  *            points, same order: 8 N_M values each (gu ignored on Dirichlet sides);
  *   uD: u at the (N_M+1)^2 macro nodes (read on the Dirichlet sides only).
+ * Each array comes with its value count, which must equal the count above
+ * (EINVAL otherwise; a NULL array's count is ignored).
  * A source at the micro points is f^v(x_k, zeta(x_k, y)) at the reference
  * point y of instance k.  Needs set_reference_mesh; a new mesh drops the data. */
-tsm_status tsm_stationary_set_data(tsm_ctx* c, const double* fv_cell, const double* gv_bnd, const double* fu_cell,
-                                   const double* fw_cell, const double* gu_bnd, const double* gw_bnd,
-                                   const double* uD);
+tsm_status tsm_stationary_set_data(tsm_ctx* c, const double* fv_cell, int64_t n_fv, const double* gv_bnd,
+                                   int64_t n_gv, const double* fu_cell, int64_t n_fu, const double* fw_cell,
+                                   int64_t n_fw, const double* gu_bnd, int64_t n_gu, const double* gw_bnd,
+                                   int64_t n_gw, const double* uD, int64_t n_uD);
 
 tsm_status tsm_stationary_get_stats(const tsm_ctx* c, tsm_stationary_stats* s);
 

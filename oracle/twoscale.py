@@ -31,7 +31,7 @@ Section 2.2).  Three routes reach it:
                       macro solve with the previous micro data, micro solves
                       with the new macro data, until successive values of the
                       residual sum (macro residual plus mean micro residual,
-                      Section 3.3) stop changing.
+                      the threshold of Section 3.5) stop changing.
 * ``step_monolithic`` one dense solve of the whole block system (tiny cases).
 
 Solves use banded Cholesky factorisations from LAPACK (scipy).

@@ -898,11 +898,15 @@ tsm_status tsm_set_jacobians(tsm_ctx* c, const double* Fcell, int64_t n_cell, co
     return finish_setup(c, t0, [](int64_t) { return std::string("Jacobian tables; -1: non-finite entry"); });
 }
 
-tsm_status tsm_set_state(tsm_ctx* c, const double* u, const double* v) {
+tsm_status tsm_set_state(tsm_ctx* c, const double* u, int64_t n_u, const double* v, int64_t n_v) {
     if (!c) return TSM_EINVAL;
     if (c->stationary) return c->fail(TSM_ESTATE, "stationary context: no time stepping (tsm_stationary_solve)");
     if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation first");
     if (!u) return c->fail(TSM_EINVAL, "u is NULL");
+    if (n_u != c->n_inst) return c->fail(TSM_EINVAL, "u has " + std::to_string(n_u) + " entries, n_inst is " + std::to_string(c->n_inst));
+    if (v && n_v != c->total)
+        return c->fail(TSM_EINVAL, "v has " + std::to_string(n_v) + " entries, the ragged micro layout has " +
+                                       std::to_string(c->total));
     HIPCHK(hipDeviceSynchronize());
     std::vector<double> uh(c->n_inst);
     HIPCHK(hipMemcpy(uh.data(), u, c->n_inst * sizeof(double), hipMemcpyDeviceToHost));
@@ -972,41 +976,49 @@ tsm_status tsm_step(tsm_ctx* c, int32_t n_steps) {
     return TSM_OK;
 }
 
-tsm_status tsm_get_macro(const tsm_ctx* cc, double* out) {
+tsm_status tsm_get_macro(const tsm_ctx* cc, double* out, int64_t n) {
     tsm_ctx* c = const_cast<tsm_ctx*>(cc);
     if (!c || !out) return TSM_EINVAL;
     if (!c->have_state) return c->fail(TSM_ESTATE, "no state");
+    if (n != c->n_inst) return c->fail(TSM_EINVAL, "u_out must hold n_inst = " + std::to_string(c->n_inst) + " entries");
     HIPCHK(hipDeviceSynchronize());   // the caller's pending work on the output buffer
     HIPCHK(hipMemcpyAsync(out, c->u, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return TSM_OK;
 }
 
-tsm_status tsm_get_fluxes(const tsm_ctx* cc, double* out) {
+tsm_status tsm_get_fluxes(const tsm_ctx* cc, double* out, int64_t n) {
     tsm_ctx* c = const_cast<tsm_ctx*>(cc);
     if (!c || !out) return TSM_EINVAL;
     if (!c->have_state) return c->fail(TSM_ESTATE, "no state");
+    if (n != c->n_inst) return c->fail(TSM_EINVAL, "F_out must hold n_inst = " + std::to_string(c->n_inst) + " entries");
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpyAsync(out, c->F, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return TSM_OK;
 }
 
-tsm_status tsm_get_micro(const tsm_ctx* cc, double* out) {
+tsm_status tsm_get_micro(const tsm_ctx* cc, double* out, int64_t n) {
     tsm_ctx* c = const_cast<tsm_ctx*>(cc);
     if (!c || !out) return TSM_EINVAL;
     if (!c->have_state) return c->fail(TSM_ESTATE, "no state");
+    if (n != c->total) return c->fail(TSM_EINVAL, "v_out must hold the " + std::to_string(c->total) + " ragged entries");
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(launch_state_join((int)c->n_inst, c->offsets, c->u, c->v0, c->w, out, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return TSM_OK;
 }
 
-tsm_status tsm_get_setup(const tsm_ctx* cc, double* beta_out, double* len_out, double* w_out) {
+tsm_status tsm_get_setup(const tsm_ctx* cc, double* beta_out, double* len_out, int64_t n_inst, double* w_out,
+                         int64_t n_w) {
     tsm_ctx* c = const_cast<tsm_ctx*>(cc);
     if (!c) return TSM_EINVAL;
     if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation first");
     if (c->stationary) return c->fail(TSM_ESTATE, "stationary context: no response functionals");
+    if ((beta_out || len_out) && n_inst != c->n_inst)
+        return c->fail(TSM_EINVAL, "beta_out and len_out must hold n_inst = " + std::to_string(c->n_inst) + " entries");
+    if (w_out && n_w != c->total)
+        return c->fail(TSM_EINVAL, "w_out must hold the " + std::to_string(c->total) + " ragged entries");
     HIPCHK(hipDeviceSynchronize());
     if (beta_out) HIPCHK(hipMemcpyAsync(beta_out, c->beta, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (len_out) HIPCHK(hipMemcpyAsync(len_out, c->len, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1015,20 +1027,22 @@ tsm_status tsm_get_setup(const tsm_ctx* cc, double* beta_out, double* len_out, d
     return TSM_OK;
 }
 
-tsm_status tsm_apply_operator(tsm_ctx* c, const double* x, double* y) {
+tsm_status tsm_apply_operator(tsm_ctx* c, const double* x, double* y, int64_t n) {
     if (!c || !x || !y) return TSM_EINVAL;
     if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation first");
+    if (n != c->total) return c->fail(TSM_EINVAL, "x and y must hold the " + std::to_string(c->total) + " ragged entries");
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(launch_apply((int)c->n_inst, c->level, c->offsets, c->S64, x, y, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return TSM_OK;
 }
 
-tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda_out) {
+tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda_out, int64_t n) {
     if (!c) return TSM_EINVAL;
     if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
     if (n_steps < 1) return c->fail(TSM_EINVAL, "n_steps < 1");
     if (!J_out || !dJda_out) return c->fail(TSM_EINVAL, "J_out and dJda_out are required");
+    if (n != c->n_inst) return c->fail(TSM_EINVAL, "dJda_out must hold n_inst = " + std::to_string(c->n_inst) + " entries");
     if (c->geom_tables)
         return c->fail(TSM_ESTATE, "tsm_gradient differentiates with respect to the deformation amplitudes; "
                                    "the geometry came from Jacobian tables");
@@ -1307,9 +1321,10 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
 
 const char* tsm_last_error(const tsm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
-tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out) {
+tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out, int64_t n) {
     if (!c) return TSM_EINVAL;
     if (!eta2_out) return c->fail(TSM_EINVAL, "eta2_out is NULL");
+    if (n != c->n_inst) return c->fail(TSM_EINVAL, "eta2_out must hold n_inst = " + std::to_string(c->n_inst) + " entries");
     if (c->stationary) return c->fail(TSM_ESTATE, "stationary context: no time-stepped micro state");
     if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
     if (c->geom_tables) return c->fail(TSM_ESTATE, "indicator needs the amplitude geometry (not Jacobian tables)");
@@ -1360,8 +1375,8 @@ tsm_status tsm_mark_refine(int64_t n_inst, const double* eta2, const int32_t* le
     return TSM_OK;
 }
 
-tsm_status tsm_prolong(int64_t n_inst, const int32_t* lo, const int32_t* ln, const double* vo, double* vn,
-                       void* stream) {
+tsm_status tsm_prolong(int64_t n_inst, const int32_t* lo, const int32_t* ln, const double* vo, int64_t n_old,
+                       double* vn, int64_t n_new, void* stream) {
     if (n_inst < 1 || !lo || !ln || !vo || !vn) return create_failed(nullptr, TSM_EINVAL, "tsm_prolong: bad arguments");
     std::vector<int64_t> oo(n_inst + 1, 0), on(n_inst + 1, 0);
     for (int64_t i = 0; i < n_inst; ++i) {
@@ -1371,6 +1386,10 @@ tsm_status tsm_prolong(int64_t n_inst, const int32_t* lo, const int32_t* ln, con
         oo[i + 1] = oo[i] + (int64_t)(lo[i] + 1) * (lo[i] + 1);
         on[i + 1] = on[i] + (int64_t)(ln[i] + 1) * (ln[i] + 1);
     }
+    if (n_old != oo[n_inst] || n_new != on[n_inst])
+        return create_failed(nullptr, TSM_EINVAL,
+                             "tsm_prolong: v_old must hold " + std::to_string(oo[n_inst]) + " and v_new " +
+                                 std::to_string(on[n_inst]) + " entries");
     hipStream_t s = (hipStream_t)stream;
     int32_t *dlo = nullptr, *dln = nullptr;
     int64_t *doo = nullptr, *don = nullptr;
@@ -1463,11 +1482,16 @@ tsm_status tsm_stationary_create(const tsm_stationary_params* sp, void* stream, 
     return TSM_OK;
 }
 
-tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double* v_out) {
+tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, int64_t n_inst, double* v_out,
+                                int64_t n_v) {
     if (!c) return TSM_EINVAL;
     if (!c->stationary) return c->fail(TSM_ESTATE, "not a stationary context (tsm_stationary_create)");
     if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation or set_jacobians first");
     if (!u_out || !w_out) return c->fail(TSM_EINVAL, "u_out or w_out is NULL");
+    if (n_inst != c->n_inst)
+        return c->fail(TSM_EINVAL, "u_out and w_out must hold n_inst = " + std::to_string(c->n_inst) + " entries");
+    if (v_out && n_v != c->total)
+        return c->fail(TSM_EINVAL, "v_out must hold the " + std::to_string(c->total) + " ragged entries");
     const int64_t ni = c->n_inst;
     const tsm_stationary_params& sp = c->sp;
     if (!c->ev_mid) HIPCHK(hipEventCreate(&c->ev_mid));
@@ -1616,16 +1640,23 @@ tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, double
     return TSM_OK;
 }
 
-tsm_status tsm_stationary_set_data(tsm_ctx* c, const double* fv_cell, const double* gv_bnd, const double* fu_cell,
-                                    const double* fw_cell, const double* gu_bnd, const double* gw_bnd,
-                                    const double* uD) {
+tsm_status tsm_stationary_set_data(tsm_ctx* c, const double* fv_cell, int64_t n_fv, const double* gv_bnd,
+                                    int64_t n_gv, const double* fu_cell, int64_t n_fu, const double* fw_cell,
+                                    int64_t n_fw, const double* gu_bnd, int64_t n_gu, const double* gw_bnd,
+                                    int64_t n_gw, const double* uD, int64_t n_uD) {
     if (!c) return TSM_EINVAL;
     if (!c->stationary) return c->fail(TSM_ESTATE, "not a stationary context (tsm_stationary_create)");
     if (!c->have_mesh) return c->fail(TSM_ESTATE, "set_reference_mesh first");
     const int64_t nM = c->NM, ni = c->n_inst;
     const double* src[7] = {fv_cell, gv_bnd, fu_cell, fw_cell, gu_bnd, gw_bnd, uD};
+    const int64_t given[7] = {n_fv, n_gv, n_fu, n_fw, n_gu, n_gw, n_uD};
+    const char* name[7] = {"fv_cell", "gv_bnd", "fu_cell", "fw_cell", "gu_bnd", "gw_bnd", "uD"};
     double** dst[7] = {&c->st_dfv, &c->st_dgv, &c->st_dfu, &c->st_dfw, &c->st_dgu, &c->st_dgw, &c->st_duD};
     const int64_t len[7] = {c->st_ncell, c->st_nbnd, 4 * nM * nM, 4 * nM * nM, 8 * nM, 8 * nM, ni};
+    for (int q = 0; q < 7; ++q)
+        if (src[q] && given[q] != len[q])
+            return c->fail(TSM_EINVAL, std::string(name[q]) + " has " + std::to_string(given[q]) + " values, expected " +
+                                           std::to_string(len[q]));
     HIPCHK(hipDeviceSynchronize());   // the caller's producers of the data
     for (int q = 0; q < 7; ++q) {
         c->st_has[q] = src[q] != nullptr;

@@ -195,7 +195,9 @@ __global__ void adjoint_coef_kernel(MacroArgs m, const double* mu, double* coef)
 }
 
 // Residual sum of the alternating coupling (paper Section 3.3: the macro and
-// micro solves alternate until the sum of the residuals settles).
+// micro solves alternate until the difference of subsequent residuals is
+// small; Section 3.5: that residual is the sum of the macro residual and the
+// mean micro residual).
 __global__ __launch_bounds__(1024) void coupling_residual_kernel(int nR, const double* R, int n_inst,
                                                                  const double* res, double* out) {
     __shared__ double red_s[2][2][1024 / kWave];

@@ -1,5 +1,5 @@
 // Batched micro solves: Jacobi-preconditioned conjugate gradients on every
-// instance's S_i = M_i/dt + d A_i + kappa B_i (paper Section 3.3: every system
+// instance's S_i = M_i/dt + d A_i + kappa B_i (paper Section 3.5: every system
 // solved by CG, the micro systems distributed over the processors).
 //
 // Layout and mapping (one workgroup of 256 lanes per instance):

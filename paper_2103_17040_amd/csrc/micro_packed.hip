@@ -1,5 +1,5 @@
 // Packed micro solves for the common mesh sizes (16, 32 and 64 cells per
-// side): Jacobi-preconditioned CG (paper Section 3.3: CG on every micro
+// side): Jacobi-preconditioned CG (paper Section 3.5: CG on every micro
 // system, the systems distributed over the processors), laid out for a
 // 768-lane workgroup (12 waves, 3 per SIMD: 168 VGPRs per lane) that
 // solves a pack of instances of one size in lockstep:

@@ -101,14 +101,14 @@ def _load():
         "tsm_get_offsets": (I32, [P, ctypes.POINTER(I64)]),
         "tsm_set_deformation": (I32, [P, VP, VP, I64]),
         "tsm_set_jacobians": (I32, [P, VP, I64, VP, I64]),
-        "tsm_set_state": (I32, [P, VP, VP]),
+        "tsm_set_state": (I32, [P, VP, I64, VP, I64]),
         "tsm_step": (I32, [P, I32]),
-        "tsm_get_macro": (I32, [P, VP]),
-        "tsm_get_fluxes": (I32, [P, VP]),
-        "tsm_get_micro": (I32, [P, VP]),
-        "tsm_get_setup": (I32, [P, VP, VP, VP]),
-        "tsm_apply_operator": (I32, [P, VP, VP]),
-        "tsm_gradient": (I32, [P, I32, ctypes.POINTER(D), VP]),
+        "tsm_get_macro": (I32, [P, VP, I64]),
+        "tsm_get_fluxes": (I32, [P, VP, I64]),
+        "tsm_get_micro": (I32, [P, VP, I64]),
+        "tsm_get_setup": (I32, [P, VP, VP, I64, VP, I64]),
+        "tsm_apply_operator": (I32, [P, VP, VP, I64]),
+        "tsm_gradient": (I32, [P, I32, ctypes.POINTER(D), VP, I64]),
         "tsm_set_flags": (I32, [P, ctypes.c_uint64]),
         "tsm_autotune": (I32, [P, I32, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_uint64)]),
         "tsm_get_stats": (I32, [P, ctypes.POINTER(tsm_stats)]),
@@ -116,12 +116,12 @@ def _load():
         "tsm_destroy": (None, [P]),
         "tsm_stationary_default_params": (None, [ctypes.POINTER(tsm_stationary_params)]),
         "tsm_stationary_create": (I32, [ctypes.POINTER(tsm_stationary_params), VP, ctypes.POINTER(P)]),
-        "tsm_stationary_solve": (I32, [P, VP, VP, VP]),
-        "tsm_stationary_set_data": (I32, [P, VP, VP, VP, VP, VP, VP, VP]),
-        "tsm_error_indicator": (I32, [P, VP]),
+        "tsm_stationary_solve": (I32, [P, VP, VP, I64, VP, I64]),
+        "tsm_stationary_set_data": (I32, [P, VP, I64, VP, I64, VP, I64, VP, I64, VP, I64, VP, I64, VP, I64]),
+        "tsm_error_indicator": (I32, [P, VP, I64]),
         "tsm_mark_refine": (I32, [I64, ctypes.POINTER(D), ctypes.POINTER(I32), D, I32, ctypes.POINTER(I32),
                                   ctypes.POINTER(I64)]),
-        "tsm_prolong": (I32, [I64, ctypes.POINTER(I32), ctypes.POINTER(I32), VP, VP, VP]),
+        "tsm_prolong": (I32, [I64, ctypes.POINTER(I32), ctypes.POINTER(I32), VP, I64, VP, I64, VP]),
         "tsm_stationary_get_stats": (I32, [P, ctypes.POINTER(tsm_stationary_stats)]),
     }
     for name, (res, args) in sig.items():
@@ -146,6 +146,18 @@ def _ptr(x):
     if isinstance(x, int):
         return x
     return x.data_ptr()
+
+
+def _n(x, n=None):
+    """Entry count passed beside a device pointer: the tensor's numel, or n
+    for a raw integer pointer (which carries no size of its own)."""
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        if n is None:
+            raise ValueError("a raw device pointer needs an explicit entry count")
+        return int(n)
+    return int(x.numel())
 
 
 def tsm_default_params() -> tsm_params:
@@ -181,8 +193,8 @@ def tsm_set_jacobians(ctx, Fcell, n_cell: int, Fbnd, n_bnd: int) -> None:
     _check(ctx, _lib.tsm_set_jacobians(ctx, _ptr(Fcell), int(n_cell), _ptr(Fbnd), int(n_bnd)))
 
 
-def tsm_set_state(ctx, u, v) -> None:
-    _check(ctx, _lib.tsm_set_state(ctx, _ptr(u), _ptr(v)))
+def tsm_set_state(ctx, u, v, n_u=None, n_v=None) -> None:
+    _check(ctx, _lib.tsm_set_state(ctx, _ptr(u), _n(u, n_u), _ptr(v), _n(v, n_v)))
 
 
 def tsm_step(ctx, n_steps: int, allow_noconv: bool = False) -> int:
@@ -193,29 +205,34 @@ def tsm_step(ctx, n_steps: int, allow_noconv: bool = False) -> int:
     return st
 
 
-def tsm_get_macro(ctx, u_out) -> None:
-    _check(ctx, _lib.tsm_get_macro(ctx, _ptr(u_out)))
+def tsm_get_macro(ctx, u_out, n=None) -> None:
+    _check(ctx, _lib.tsm_get_macro(ctx, _ptr(u_out), _n(u_out, n)))
 
 
-def tsm_get_fluxes(ctx, F_out) -> None:
-    _check(ctx, _lib.tsm_get_fluxes(ctx, _ptr(F_out)))
+def tsm_get_fluxes(ctx, F_out, n=None) -> None:
+    _check(ctx, _lib.tsm_get_fluxes(ctx, _ptr(F_out), _n(F_out, n)))
 
 
-def tsm_get_micro(ctx, v_out) -> None:
-    _check(ctx, _lib.tsm_get_micro(ctx, _ptr(v_out)))
+def tsm_get_micro(ctx, v_out, n=None) -> None:
+    _check(ctx, _lib.tsm_get_micro(ctx, _ptr(v_out), _n(v_out, n)))
 
 
 def tsm_get_setup(ctx, beta_out=None, len_out=None, w_out=None) -> None:
-    _check(ctx, _lib.tsm_get_setup(ctx, _ptr(beta_out), _ptr(len_out), _ptr(w_out)))
+    n_inst = _n(beta_out) if beta_out is not None else _n(len_out)
+    if beta_out is not None and len_out is not None and _n(len_out) != n_inst:
+        raise ValueError("beta_out and len_out differ in size")
+    _check(ctx, _lib.tsm_get_setup(ctx, _ptr(beta_out), _ptr(len_out), n_inst, _ptr(w_out), _n(w_out)))
 
 
 def tsm_apply_operator(ctx, x, y) -> None:
-    _check(ctx, _lib.tsm_apply_operator(ctx, _ptr(x), _ptr(y)))
+    if _n(x) != _n(y):
+        raise ValueError("x and y differ in size")
+    _check(ctx, _lib.tsm_apply_operator(ctx, _ptr(x), _ptr(y), _n(x)))
 
 
 def tsm_gradient(ctx, n_steps: int, dJda_out) -> float:
     J = ctypes.c_double()
-    _check(ctx, _lib.tsm_gradient(ctx, int(n_steps), ctypes.byref(J), _ptr(dJda_out)))
+    _check(ctx, _lib.tsm_gradient(ctx, int(n_steps), ctypes.byref(J), _ptr(dJda_out), _n(dJda_out)))
     return J.value
 
 
@@ -275,17 +292,21 @@ def tsm_stationary_create(params: tsm_stationary_params, stream=None):
 
 
 def tsm_stationary_solve(ctx, u_out, w_out, v_out=None) -> None:
-    _check(ctx, _lib.tsm_stationary_solve(ctx, _ptr(u_out), _ptr(w_out), _ptr(v_out)))
+    if _n(u_out) != _n(w_out):
+        raise ValueError("u_out and w_out differ in size")
+    _check(ctx, _lib.tsm_stationary_solve(ctx, _ptr(u_out), _ptr(w_out), _n(u_out), _ptr(v_out), _n(v_out)))
 
 
 def tsm_stationary_set_data(ctx, fv_cell=None, gv_bnd=None, fu_cell=None, fw_cell=None, gu_bnd=None, gw_bnd=None,
                             uD=None) -> None:
-    _check(ctx, _lib.tsm_stationary_set_data(ctx, _ptr(fv_cell), _ptr(gv_bnd), _ptr(fu_cell), _ptr(fw_cell),
-                                             _ptr(gu_bnd), _ptr(gw_bnd), _ptr(uD)))
+    args = []
+    for x in (fv_cell, gv_bnd, fu_cell, fw_cell, gu_bnd, gw_bnd, uD):
+        args += [_ptr(x), _n(x)]
+    _check(ctx, _lib.tsm_stationary_set_data(ctx, *args))
 
 
 def tsm_error_indicator(ctx, eta2_out) -> None:
-    _check(ctx, _lib.tsm_error_indicator(ctx, _ptr(eta2_out)))
+    _check(ctx, _lib.tsm_error_indicator(ctx, _ptr(eta2_out), _n(eta2_out)))
 
 
 def tsm_mark_refine(eta2, level, theta: float, max_level: int = 64):
@@ -302,11 +323,12 @@ def tsm_mark_refine(eta2, level, theta: float, max_level: int = 64):
     return out, nm.value
 
 
-def tsm_prolong(level_old, level_new, v_old, v_new, stream=None) -> None:
+def tsm_prolong(level_old, level_new, v_old, v_new, stream=None, n_old=None, n_new=None) -> None:
     lo = np.ascontiguousarray(level_old, dtype=np.int32)
     ln = np.ascontiguousarray(level_new, dtype=np.int32)
     st = _lib.tsm_prolong(lo.size, lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                          ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(v_old), _ptr(v_new), stream)
+                          ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(v_old), _n(v_old, n_old),
+                          _ptr(v_new), _n(v_new, n_new), stream)
     if st != TSM_OK:
         raise TsmError(st, _lib.tsm_last_error(None).decode())
 

@@ -160,5 +160,31 @@ def test_mark_refine_matches_the_oracle(lib_built):
             tsm.tsm_mark_refine(np.array(eta), np.array(lv, np.int32), th)
         assert e.value.status == tsm.TSM_EINVAL
     with pytest.raises(tsm.TsmError) as e:   # bad levels are refused before any device call
-        tsm.tsm_prolong(np.array([8], np.int32), np.array([12], np.int32), 0, 0)
+        tsm.tsm_prolong(np.array([8], np.int32), np.array([12], np.int32), 0, 0, n_old=81, n_new=289)
     assert e.value.status == tsm.TSM_EINVAL
+    # so are vectors whose entry counts do not match the levels (81 and 289
+    # here); the pointers are never touched, the counts are checked first
+    for n_old, n_new in ((80, 289), (81, 288), (0, 0)):
+        with pytest.raises(tsm.TsmError) as e:
+            tsm.tsm_prolong(np.array([8], np.int32), np.array([16], np.int32), 256, 512, n_old=n_old, n_new=n_new)
+        assert e.value.status == tsm.TSM_EINVAL and "must hold" in str(e.value), (n_old, n_new)
+
+
+def _declared_arity():
+    """Parameter count of every function the header declares."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for name, params in re.findall(r"\b(tsm_[a-z_]+)\s*\(([^)]*)\)\s*;", src):
+        params = params.strip()
+        out[name] = 0 if params in ("", "void") else len(params.split(","))
+    return out
+
+
+def test_binding_signatures_match_header(lib_built):
+    """Every ctypes prototype of the binding has as many arguments as the
+    header's declaration (a count passed beside each caller array included)."""
+    from paper_2103_17040_amd import tsm
+    arity = _declared_arity()
+    assert sorted(arity) == _declared()
+    for name, n in arity.items():
+        assert len(getattr(tsm._lib, name).argtypes) == n, name

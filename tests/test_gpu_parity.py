@@ -179,5 +179,24 @@ def test_error_paths():
         st = g.step(1, allow_noconv=True)
         assert st == tsm.TSM_ENOCONV
         assert g.stats()["unconverged"] > 0
+        # caller arrays of the wrong size are refused before any copy
+        import torch
+        short_u = torch.zeros(8, dtype=torch.float64, device="cuda")
+        short_v = torch.zeros(g.n_micro - 1, dtype=torch.float64, device="cuda")
+        good_u = torch.zeros(9, dtype=torch.float64, device="cuda")
+        for call in (lambda: tsm.tsm_set_state(g.ctx, short_u, None),
+                     lambda: tsm.tsm_set_state(g.ctx, good_u, short_v),
+                     lambda: tsm.tsm_get_macro(g.ctx, short_u),
+                     lambda: tsm.tsm_get_fluxes(g.ctx, short_u),
+                     lambda: tsm.tsm_get_micro(g.ctx, short_v),
+                     lambda: tsm.tsm_apply_operator(g.ctx, short_v, short_v),
+                     lambda: tsm.tsm_get_setup(g.ctx, short_u, None, None),
+                     lambda: tsm.tsm_get_setup(g.ctx, None, None, short_v),
+                     lambda: tsm.tsm_gradient(g.ctx, 1, short_u),
+                     lambda: tsm.tsm_error_indicator(g.ctx, short_u)):
+            with pytest.raises(tsm.TsmError) as e:
+                call()
+            assert e.value.status == tsm.TSM_EINVAL
+        torch.cuda.synchronize()
     finally:
         g.close()

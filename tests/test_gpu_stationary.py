@@ -170,6 +170,17 @@ def test_state_errors():
             with pytest.raises(tsm.TsmError) as e:
                 call()
             assert e.value.status == tsm.TSM_ESTATE
+        # data and outputs of the wrong size are refused before any copy
+        short = g.torch.zeros(5, dtype=g.torch.float64, device=g.device)
+        for call in (lambda: tsm.tsm_stationary_set_data(g.ctx, fv_cell=short),
+                     lambda: tsm.tsm_stationary_set_data(g.ctx, gv_bnd=short),
+                     lambda: tsm.tsm_stationary_set_data(g.ctx, fu_cell=short),
+                     lambda: tsm.tsm_stationary_set_data(g.ctx, uD=short),
+                     lambda: tsm.tsm_stationary_solve(g.ctx, short, short, None),
+                     lambda: tsm.tsm_stationary_solve(g.ctx, z, z, short)):
+            with pytest.raises(tsm.TsmError) as e:
+                call()
+            assert e.value.status == tsm.TSM_EINVAL
     finally:
         g.close()
     t = TwoScaleBatch(2, levels, np.zeros(9))
