@@ -37,8 +37,13 @@ import workloads as W  # noqa: E402
 PEAK_HBM_GBS = 8000.0
 # FP64 FMA and non-packed FP32 FMA issue at 64 lanes per clock per CU on
 # gfx950: 256 CUs * 2.4 GHz * 64 FMA * 2 flop = 78.6 TFLOP/s for either type
-# (packed FP32, which would double FP32, is not used).
+# (packed FP32, which would double FP32, is not used).  The published FP32
+# vector figure (157.3 TFLOP/s) counts packed FP32; both are reported.
 PEAK_ALU_TFLOPS = 78.6
+PEAK_FP32_PUBLISHED_TFLOPS = 157.3
+# The state floor of one micro DoF-update: read v0 and M w, write v (FP64).
+# Everything else a solve touches can stay on chip for a whole instance.
+B_FLOOR = 24.0
 
 # Algorithmic work per micro DoF-update of the micro kernel.
 # Flops: per PCG iteration 9-point stencil (9 FMA), p.q, x/d update, r update,
@@ -510,20 +515,45 @@ def parity_leg():
     return res
 
 
-def cpu_baseline(w, a, th, lv, seconds_hint=15.0):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload:
-    a macro mesh of S cells per side (so (S+1)^2 instances) with the
-    workload's micro mesh, dt and first (S+1)^2 amplitudes, stepped K times.
-    BLAS/LAPACK threads are limited to one; the oracle itself is serial."""
+def host_info():
+    """CPU model, logical cores usable by this process and RAM of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ram = 0
+    try:
+        with open("/proc/meminfo") as fh:
+            for ln in fh:
+                if ln.startswith("MemTotal"):
+                    ram = int(ln.split()[1]) * 1024
+                    break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0))
+    # a box's CPU share is what OMP_NUM_THREADS states there, whatever the
+    # affinity mask shows
+    share = os.environ.get("OMP_NUM_THREADS")
+    if share and share.isdigit() and int(share) > 0:
+        cores = min(cores, int(share))
+    return {"cpu_model": model, "cores": cores, "ram_bytes": ram}
+
+
+def _oracle_worker(job):
+    """One process of the CPU baseline: the FP64 oracle's exact step, as it
+    stands, on its own (S+1)^2-instance batch, one BLAS thread; setup first,
+    then steps until `seconds` have passed."""
+    S, lvl, a, th, prm, seconds = job
     from threadpoolctl import threadpool_limits
     from oracle import twoscale
-    S = 7
-    ninst = (S + 1) ** 2
-    lvl = np.resize(lv, ninst)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        ts = twoscale.TwoScale(twoscale.Params(S, w.dt, w.D, w.d, w.kappa, w.p, w.sigma), lvl,
-                               a[:ninst], None if th is None else th[:ninst])
+        ts = twoscale.TwoScale(twoscale.Params(S, *prm), lvl, a, th)
         t_setup = time.perf_counter() - t0
         u = W.initial_macro(S)
         v = np.zeros(int(ts.offsets[-1]))
@@ -532,14 +562,44 @@ def cpu_baseline(w, a, th, lv, seconds_hint=15.0):
         while True:
             u, v, _ = ts.step(u, v)
             K += 1
-            if time.perf_counter() - t0 > seconds_hint or K >= 200:
+            if time.perf_counter() - t0 > seconds or K >= 400:
                 break
         t = time.perf_counter() - t0
-    dofs = int(ts.offsets[-1])
-    return {"value": dofs * K / t, "unit": "micro DoF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{ninst} instances ({S}x{S} macro cells) of the workload's micro meshes, "
-                      f"{K} implicit-Euler steps, banded-Cholesky micro solves factored once "
-                      f"(setup {t_setup:.1f} s excluded, as for the GPU value)"}
+    return int(ts.offsets[-1]), K, t, t_setup
+
+
+def cpu_baseline(w, a, th, lv, seconds_hint=12.0):
+    """The FP64 oracle, as it stands, on every host core: one process per
+    core (spawned, one BLAS thread each), each stepping its own bounded
+    sample of the workload -- a macro mesh of S cells per side, so (S+1)^2
+    instances, with the workload's micro meshes, dt and amplitudes (process
+    q takes the next (S+1)^2 of them).  The rate is the sum of the
+    processes' micro DoF-updates per second; they run at the same time."""
+    import multiprocessing as mp
+    info = host_info()
+    P = info["cores"]
+    S = 3
+    n = (S + 1) ** 2
+    prm = (w.dt, w.D, w.d, w.kappa, w.p, w.sigma)
+    jobs = []
+    for q in range(P):
+        idx = (np.arange(n) + q * n) % len(lv)
+        jobs.append((S, lv[idx], a[idx], None if th is None else th[idx], prm, seconds_hint))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    rate = sum(d * K / t for d, K, t, _ in res)
+    Ks = [K for _, K, _, _ in res]
+    return {"value": rate, "unit": "micro DoF-updates/s", "cores": P, "kind": "oracle",
+            "cpu_model": info["cpu_model"], "ram_bytes": info["ram_bytes"],
+            "sample": f"{P} processes at once (one per core, one BLAS thread each), each the oracle's exact "
+                      f"step on its own {n} instances ({S}x{S} macro cells) of the workload's micro meshes "
+                      f"and amplitudes, {min(Ks)}-{max(Ks)} implicit-Euler steps of ~{seconds_hint:.0f} s, "
+                      f"banded-Cholesky micro solves factored once (setup "
+                      f"{max(r[3] for r in res):.1f} s excluded, as for the GPU value); "
+                      f"{wall:.0f} s wall clock in all"}
 
 
 def oracle_rate(w, lv, a, th, jacobians=None, fixed_point=False, S=3, seconds=4.0):
@@ -585,8 +645,9 @@ def main():
                     help="steps of the general-map leg (Jacobian tables, uneven batch; 0: skip)")
     ap.add_argument("--fp-steps", type=int, default=3,
                     help="steps of the alternating-coupling leg (0: skip), timed against the exact step")
-    ap.add_argument("--adjoint-steps", type=int, default=40,
-                    help="steps of the gradient leg (0: skip); checkpoint spacing from the workload")
+    ap.add_argument("--adjoint-steps", type=int, default=-1,
+                    help="steps of the gradient leg (-1: the workload's step count; 0: skip); "
+                         "checkpoint spacing from the workload")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="first run a plain device copy of this many bytes (3 times), the reference "
                          "for scaling HBM counters (FETCH_SIZE, WRITE_SIZE) in profiles")
@@ -609,6 +670,8 @@ def main():
     w, a, th, lv = W.make(args.workload, args.seed)
     if args.steps <= 0:
         args.steps = w.steps
+    if args.adjoint_steps < 0:
+        args.adjoint_steps = w.steps if w.checkpoint_every > 0 else 0
     refine = w.precision == "fp32_refine"
     _log(f"workload {w.name}: {w.n_inst} instances, levels {sorted(set(lv.tolist()))}, "
          f"{int(W.offsets(lv)[-1])} micro DoFs, precision {w.precision}, rtol {w.rtol}")
@@ -651,26 +714,51 @@ def main():
         kname = "packed_kernel (micro PCG)"
     if 0 < n_packed and any(not packed_under(int(N), plan_flags) for N in set(lv.tolist())):
         kname += " + micro_kernel"
-    # achieved: the algorithmic bytes of one DoF-update of a PCG that
-    # streams its vectors through HBM every iteration, times the DoF-updates
-    # of one launch, over the launch time.  Above 1 means the kernel needs fewer bytes than that
-    # model, since it keeps every vector on chip; the kernel's own minimum
-    # (resident) bytes, the counter-measured traffic and the ALU share are
-    # reported beside it.
+    # The roofline object of the dominant kernel.  Algorithmic bytes: the
+    # state floor (24 B per DoF-update: v0 and M w read, v written; the
+    # vectors of every iteration stay on chip) plus the boundary pass of the
+    # flux average; algorithmic flops: the arithmetic of the kernel's own
+    # work model (FLOP_*).  The bound is the roof with the larger fraction.
+    # The counter-measured traffic and its ratio to the algorithmic bytes,
+    # the bytes of the kernel's current data flow (resident model) and the
+    # bytes a PCG streaming its vectors through HBM would need are reported
+    # beside it.
+    floor_units = dofs_per_launch
+    bdot_bytes = sum(16.0 * 4 * int(N) for N in lv.tolist() if packed_under(int(N), plan_flags)) / max(
+        tst["micro_launches"], 1)
+    alg_bytes = B_FLOOR * floor_units + bdot_bytes
+    hbm_alg = alg_bytes / t_launch / 1e9
+    hbm_frac = hbm_alg / PEAK_HBM_GBS
+    alu_frac = alu / PEAK_ALU_TFLOPS
+    if alu_frac >= hbm_frac:
+        roof = {"bound": "alu", "achieved": alu, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": alu_frac,
+                "traffic": traffic}
+    else:
+        roof = {"bound": "hbm", "achieved": hbm_alg, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": hbm_frac,
+                "traffic": traffic}
     per_unit = streaming_bytes(refine, iters, sweeps)
-    ach = dofs_per_launch * per_unit / t_launch / 1e9
-    roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": ach / PEAK_HBM_GBS, "traffic": traffic,
-            "kernel": kname, "launch_ms": micro_ms_per_launch,
-            "per_unit_bytes": per_unit, "units_per_launch": dofs_per_launch,
-            "per_unit_model": "streaming PCG: 10 words per inner iteration (FP32 in refinement), "
-                              "6 FP64 words per refinement sweep, 3 FP64 state words",
-            "resident_bytes_per_unit": nbytes / max(dofs_per_launch, 1),
-            "resident_model_GBs": hbm, "resident_model_frac": hbm / PEAK_HBM_GBS,
-            "measured_traffic_frac": (traffic / t_launch / 1e9 / PEAK_HBM_GBS) if traffic else None,
-            "alu_model_TFLOPs": alu, "alu_frac": alu / PEAK_ALU_TFLOPS,
-            "algorithmic_flops_per_launch": flops,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
+    roof.update({
+        "kernel": kname, "launch_ms": micro_ms_per_launch, "units_per_launch": dofs_per_launch,
+        "unit_of_work": "one micro DoF-update (one DoF of one instance, one time step)",
+        "peak_note": "alu peak: FP64 and non-packed FP32 FMA at 64 lanes/clock/CU, 256 CUs, 2.4 GHz "
+                     "(packed FP32 is off in this build); hbm peak 8 TB/s",
+        "alu_achieved_TFLOPs": alu, "alu_frac": alu_frac,
+        "alu_frac_of_published_fp32_157_3": alu / PEAK_FP32_PUBLISHED_TFLOPS,
+        "algorithmic_flops_per_launch": flops,
+        "hbm_algorithmic_bytes_per_unit": alg_bytes / max(floor_units, 1),
+        "hbm_algorithmic_GBs": hbm_alg, "hbm_frac": hbm_frac,
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated); "
+                        "null when the kernel sources changed since the counters were taken",
+        "traffic_over_algorithmic": (traffic / alg_bytes) if traffic else None,
+        "traffic_frac_of_hbm_peak": (traffic / t_launch / 1e9 / PEAK_HBM_GBS) if traffic else None,
+        "resident_model_bytes_per_unit": nbytes / max(dofs_per_launch, 1),
+        "resident_model_frac": hbm / PEAK_HBM_GBS,
+        "streaming_model": {"bytes_per_unit": per_unit,
+                            "GBs_equivalent": dofs_per_launch * per_unit / t_launch / 1e9,
+                            "what": "a PCG streaming its vectors through HBM: 10 words per inner iteration "
+                                    "(FP32 in refinement), 6 FP64 words per refinement sweep, 3 FP64 state "
+                                    "words; the resident kernel moves far fewer bytes"},
+    })
 
     out = {
         "metric": "micro DoF-updates/s (batched FP32+refine vs plain FP64) at 1e-8 rel; adjoint/fwd",
