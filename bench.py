@@ -144,7 +144,7 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan
     import torch
     from paper_2103_17040_amd import TwoScaleBatch, tsm
     g = TwoScaleBatch(w.macro_cells, lv, a, th, D=w.D, d=w.d, kappa=w.kappa, p=w.p, dt=w.dt,
-                      sigma=w.sigma, precision=precision, rtol=rtol,
+                      sigma=w.sigma, precision=precision, rtol=rtol, grad_rtol=w.grad_rtol,
                       checkpoint_every=max(w.checkpoint_every, 1))
     try:
         setup_ms = g.stats()["setup_ms"]
@@ -203,6 +203,7 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan
             tg = time.perf_counter() - t0
             gs = g.stats()
             adj = {"steps": adjoint_steps, "checkpoint_every": max(w.checkpoint_every, 1),
+                   "grad_rtol": w.grad_rtol if w.grad_rtol > 0 else rtol,
                    "J": J, "grad_norm": float(dJ.norm()), "wall_s": tg,
                    "forward_ms": gs["grad_forward_ms"], "backward_ms": gs["grad_backward_ms"]}
         plan = {"plan": tsm.plan_name(plan["flags"]), "flags": plan["flags"], "ms_per_step": plan["ms_per_step"]}

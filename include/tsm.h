@@ -111,6 +111,11 @@ typedef struct {
     double fp_rtol;          /* TSM_FLAG_FIXED_POINT: stop when the residual sum changes by
                                 less than fp_rtol x its first value, > 0 */
     int32_t fp_max_iter;     /* TSM_FLAG_FIXED_POINT: iterations per step, >= 2 */
+    double grad_rtol;        /* tsm_gradient: tolerance of every micro solve of the gradient
+                                (its checkpointed forward, the segment recompute and the adjoint
+                                solves), > 0; 0 = rtol.  The gradient of this family is small
+                                against J (the cells keep their shape), so its relative error is
+                                about 1e3 x the solver tolerance: 1e-11 gives ~1e-7. */
 } tsm_params;
 
 typedef struct {
@@ -142,7 +147,7 @@ typedef struct tsm_ctx tsm_ctx;
 /* Fill *p with the defaults: kappa = p = 1, D = 1, d = 0.5, dt = 0.01,
  * source_sign = -1, FP64, rtol 1e-12, inner_rtol 1e-2, setup_rtol 1e-14,
  * max_iter 1000, max_refine 12, checkpoint_every 10, flags 0, fp_rtol 1e-10,
- * fp_max_iter 50. */
+ * fp_max_iter 50, grad_rtol 0 (= rtol). */
 void tsm_default_params(tsm_params* p);
 
 /* Create a context on the current HIP device.  The parameters are those of
@@ -329,6 +334,7 @@ tsm_status tsm_mark_refine(int64_t n_inst, const double* eta2, const int32_t* le
  * counts (message in tsm_last_error(NULL)). */
 tsm_status tsm_prolong(int64_t n_inst, const int32_t* level_old, const int32_t* level_new, const double* v_old,
                        int64_t n_old, double* v_new, int64_t n_new, void* stream);
+
 
 /* ---------------------------------------------------------------------------
  * The paper's stationary three-field system (Section 2.1 model; the Case A/B

@@ -20,7 +20,7 @@ class TwoScaleBatch:
     def __init__(self, macro_cells, micro_cells, a=None, theta=None, *, jacobians=None, D=1.0, d=0.5, kappa=1.0, p=1.0,
                  dt=0.01, sigma=-1, precision="fp64", rtol=1e-12, inner_rtol=1e-2, setup_rtol=1e-14,
                  max_iter=1000, max_refine=12, checkpoint_every=10, flags=0, coupling="schur",
-                 fp_rtol=1e-10, fp_max_iter=50, device="cuda:0"):
+                 fp_rtol=1e-10, fp_max_iter=50, grad_rtol=0.0, device="cuda:0"):
         import numpy as np
         import torch
         global tsm
@@ -30,7 +30,7 @@ class TwoScaleBatch:
         self._ctor = dict(D=D, d=d, kappa=kappa, p=p, dt=dt, sigma=sigma, precision=precision, rtol=rtol,
                           inner_rtol=inner_rtol, setup_rtol=setup_rtol, max_iter=max_iter, max_refine=max_refine,
                           checkpoint_every=checkpoint_every, flags=flags, coupling=coupling, fp_rtol=fp_rtol,
-                          fp_max_iter=fp_max_iter, device=device)
+                          fp_max_iter=fp_max_iter, grad_rtol=grad_rtol, device=device)
         prm = tsm.tsm_default_params()
         prm.macro_cells = int(macro_cells)
         prm.D, prm.d, prm.kappa, prm.p, prm.dt = float(D), float(d), float(kappa), float(p), float(dt)
@@ -40,6 +40,7 @@ class TwoScaleBatch:
         prm.max_iter, prm.max_refine, prm.checkpoint_every = int(max_iter), int(max_refine), int(checkpoint_every)
         prm.flags = int(flags) | {"schur": 0, "fixed_point": tsm.TSM_FLAG_FIXED_POINT}[coupling]
         prm.fp_rtol, prm.fp_max_iter = float(fp_rtol), int(fp_max_iter)
+        prm.grad_rtol = float(grad_rtol)
         self.params = prm
         self._flags = int(prm.flags)
         self.n_inst = (int(macro_cells) + 1) ** 2

@@ -524,6 +524,7 @@ void tsm_default_params(tsm_params* p) {
     p->flags = 0;
     p->fp_rtol = 1e-10;
     p->fp_max_iter = 50;
+    p->grad_rtol = 0.0;
 }
 
 namespace {
@@ -544,7 +545,7 @@ tsm_status tsm_create(const tsm_params* p, void* stream, tsm_ctx** out) {
                     p->p > 0 && p->dt > 0 && (p->source_sign == 1 || p->source_sign == -1) &&
                     (p->precision == TSM_FP64 || p->precision == TSM_FP32_REFINE) && p->rtol > 0 &&
                     p->inner_rtol > 0 && p->inner_rtol < 1 && p->setup_rtol > 0 && p->max_iter >= 1 &&
-                    p->max_refine >= 1 && p->checkpoint_every >= 1 && p->fp_rtol > 0 && p->fp_max_iter >= 2 && std::isfinite(p->D) &&
+                    p->max_refine >= 1 && p->checkpoint_every >= 1 && p->fp_rtol > 0 && p->fp_max_iter >= 2 && p->grad_rtol >= 0 && std::isfinite(p->grad_rtol) && std::isfinite(p->D) &&
                     std::isfinite(p->d) && std::isfinite(p->kappa) && std::isfinite(p->p) && std::isfinite(p->dt);
     if (!ok) return create_failed(nullptr, TSM_EINVAL, "parameter out of range");
     tsm_ctx* c = new tsm_ctx();
@@ -1168,8 +1169,23 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
         if (nc > 0) return c->fail(TSM_ENOCONV, std::to_string(nc) + " solves missed rtol during the gradient");
         return TSM_OK;
     };
-    st = run();
+    // every solve of the gradient at its own tolerance (the step graph is
+    // rebuilt for it and restored afterwards)
+    const double step_rtol = c->prm.rtol;
+    const bool own_rtol = c->prm.grad_rtol > 0.0 && c->prm.grad_rtol != step_rtol;
+    if (own_rtol) {
+        c->prm.rtol = c->prm.grad_rtol;
+        st = build_graph(c);
+    }
+    if (st == TSM_OK) st = run();
     (void)hipStreamSynchronize(c->stream);
+    if (own_rtol) {
+        c->prm.rtol = step_rtol;
+        const std::string err = c->err;
+        const tsm_status gs = build_graph(c);
+        if (st == TSM_OK) st = gs;
+        else c->err = err;
+    }
     release();
     return st;
 }

@@ -50,7 +50,7 @@ class tsm_params(ctypes.Structure):
                 ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("setup_rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("checkpoint_every", ctypes.c_int32), ("flags", ctypes.c_uint64),
-                ("fp_rtol", ctypes.c_double), ("fp_max_iter", ctypes.c_int32)]
+                ("fp_rtol", ctypes.c_double), ("fp_max_iter", ctypes.c_int32), ("grad_rtol", ctypes.c_double)]
 
 
 class tsm_stats(ctypes.Structure):

@@ -67,9 +67,12 @@ def test_checkpoint_spacing_is_bitwise_invisible_and_state_restored():
 
 def test_refine_gradient_matches_oracle_adjoint_mid_size():
     """The gradient in the measured form (FP32 inner solves inside FP64
-    refinement to 1e-8, dt = 0.0025, checkpoints every 20 steps, rotated
-    cells, amplitudes U[-0.3, 0.3]) on 81 instances of 64 x 64 cells over 40
-    steps, against the oracle's FP64 discrete adjoint."""
+    refinement, the gradient's solves to 1e-11, dt = 0.0025, checkpoints
+    every 20 steps, rotated cells, amplitudes U[-0.3, 0.3]) on 81 instances
+    of 64 x 64 cells over 40 steps, against the oracle's FP64 discrete
+    adjoint.  The cells keep their shape under this family, so dJ/da is
+    ~3e-7 |J| here and its relative error is ~1e3 x the solver tolerance
+    (measured: 2.3e-5 at 1e-8, 9.4e-7 at 1e-10, 1.0e-7 at 1e-11)."""
     NM, steps, ck, dt = 8, 40, 20, 0.0025
     n = (NM + 1) ** 2
     rng = np.random.default_rng(23)
@@ -78,10 +81,10 @@ def test_refine_gradient_matches_oracle_adjoint_mid_size():
     th = rng.uniform(0.0, np.pi / 8, n)
     u0 = W.initial_macro(NM)
     v0 = np.zeros(int(W.offsets(lv)[-1]))
-    banner(f"adjoint mid-size NM={NM} 64^2 steps={steps} ck={ck} fp32_refine rtol 1e-8")
+    banner(f"adjoint mid-size NM={NM} 64^2 steps={steps} ck={ck} fp32_refine rtol 1e-8, gradient 1e-11")
     ts = oracle_for(NM, lv, a, th, dt=dt)
     J_ref, g_ref = adjoint.gradient(ts, u0, v0, steps)
-    g = gpu_for(NM, lv, a, th, dt=dt, precision="fp32_refine", rtol=1e-8, checkpoint_every=ck)
+    g = gpu_for(NM, lv, a, th, dt=dt, precision="fp32_refine", rtol=1e-8, grad_rtol=1e-11, checkpoint_every=ck)
     try:
         g.set_state(u0, v0)
         J, dJ = g.gradient(steps)

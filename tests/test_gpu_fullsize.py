@@ -102,7 +102,7 @@ def test_large_mixed_one_step_relations():
     w, a, th, lv = W.make("large_mixed", 0)
     NM = w.macro_cells
     u0, v0 = W.random_state(lv, NM, seed=1)
-    banner("full-size large_mixed one step, refine rtol 1e-8")
+    banner(f"full-size large_mixed one step, refine rtol {w.rtol}")
     g = gpu_for(NM, lv, a, th, w.dt, precision="fp32_refine", rtol=w.rtol,
                 D=w.D, d=w.d, kappa=w.kappa, p=w.p, sigma=w.sigma)
     try:
@@ -146,25 +146,23 @@ def test_large_mixed_one_step_relations():
     assert np.abs(u1[~inner]).max() == 0.0
 
 
-def test_large_mixed_full_run_replayed_through_the_oracle():
-    """The measured configuration end to end: 16641 x 64^2, FP32 + FP64
-    refinement at its tolerance, 200 steps from u0 = I_h(sin sin), v0 = 0.
-    64 seeded interior instances are replayed through the oracle (banded
-    Cholesky, FP64) driven by the GPU's macro values u_i^n:
-        v_i^{n+1} = S_i^{-1} (M_i v_i^n / dt + kappa p u_i^{n+1} b_i),
-        F_i^{n+1} = kappa p u_i^{n+1} - kappa / |dY_i| b_i^T v_i^{n+1};
-    F of every step and the final v agree to 1e-8 (relative l2 over the
-    sample).  The macro equation holds on every interior row at every step."""
+def replay_large_mixed(rtol, steps=None, count=64):
+    """Run 16641 x 64^2 (FP32 + FP64 refinement to rtol) from u0 = I_h(sin sin),
+    v0 = 0, recording the macro field and the fluxes every step, and replay
+    `count` seeded interior instances through the oracle along the recorded
+    macro values.  Returns the relative l2 errors and the macro-equation
+    residual."""
     w, a, th, lv = W.make("large_mixed", 0)
+    steps = w.steps if steps is None else steps
     NM = w.macro_cells
     u0 = W.initial_macro(NM)
-    banner(f"full-size large_mixed {w.steps} steps, refine rtol {w.rtol}, macro trajectory recorded")
-    g = gpu_for(NM, lv, a, th, w.dt, precision="fp32_refine", rtol=w.rtol,
+    banner(f"full-size large_mixed {steps} steps, refine rtol {rtol}, macro trajectory recorded")
+    g = gpu_for(NM, lv, a, th, w.dt, precision="fp32_refine", rtol=rtol,
                 D=w.D, d=w.d, kappa=w.kappa, p=w.p, sigma=w.sigma, flags=_persistent())
     try:
         g.set_state(u0, None)
         us, Fs = [u0.copy()], []
-        for n in range(w.steps):
+        for n in range(steps):
             g.step(1)
             us.append(g.macro().cpu().numpy())
             Fs.append(g.fluxes().cpu().numpy())
@@ -178,34 +176,50 @@ def test_large_mixed_full_run_replayed_through_the_oracle():
     MH, KH, L = fem.macro_matrices(NM)
     inner = ~fem.macro_boundary(NM)
     AM = (MH / w.dt + w.D * KH).tocsr()
-    worst = 0.0
-    for n in range(w.steps):
+    worst, bnd_max = 0.0, 0.0
+    for n in range(steps):
         r = (AM @ us[n + 1] - w.sigma * L * Fs[n] - MH @ us[n] / w.dt)[inner]
         worst = max(worst, np.linalg.norm(r) / np.linalg.norm((MH @ us[n] / w.dt)[inner]))
-        assert np.abs(us[n + 1][~inner]).max() == 0.0
-    banner(f"macro equation: worst relative row residual {worst:.2e}")
-    assert worst <= 1e-12
+        bnd_max = max(bnd_max, float(np.abs(us[n + 1][~inner]).max()))
     # oracle replay of the sampled instances along the recorded u
     prm = twoscale.Params(NM, w.dt, w.D, w.d, w.kappa, w.p, w.sigma)
     kp = w.kappa * w.p
     off = W.offsets(lv)
-    picks = _large_sample(w, count=64, seed=11)
-    F_ref = np.empty((w.steps, len(picks)))
+    picks = _large_sample(w, count=count, seed=11)
+    F_ref = np.empty((steps, len(picks)))
     v_ref, v_gpu = [], []
     for q, i in enumerate(picks):
         I = twoscale.Instance(lv[i], a[i], th[i], prm)
         x = np.zeros(I.n)
-        for n in range(w.steps):
+        for n in range(steps):
             x = I.chol.solve(I.M @ x / w.dt + kp * us[n + 1][i] * I.b)
             F_ref[n, q] = kp * us[n + 1][i] - w.kappa / I.len * float(I.b @ x)
         v_ref.append(x)
         v_gpu.append(v[off[i]:off[i + 1]])
-    eF = rel(Fs[:, picks], F_ref)
-    ev = rel(np.concatenate(v_gpu), np.concatenate(v_ref))
-    eF_last = rel(Fs[-1, picks], F_ref[-1])
-    banner(f"replay of {len(picks)} instances: F (all steps) rel err {eF:.2e}, "
-           f"F last {eF_last:.2e}, v final {ev:.2e}")
-    assert eF <= 1e-8 and ev <= 1e-8, (eF, ev)
+    out = {"macro_row_residual": worst, "macro_boundary_max": bnd_max,
+           "F_all": rel(Fs[:, picks], F_ref), "F_last": rel(Fs[-1, picks], F_ref[-1]),
+           "v_final": rel(np.concatenate(v_gpu), np.concatenate(v_ref))}
+    banner(f"replay of {len(picks)} instances at rtol {rtol}: " +
+           ", ".join(f"{k} {v:.2e}" for k, v in out.items()))
+    return out
+
+
+def test_large_mixed_full_run_replayed_through_the_oracle():
+    """The measured configuration end to end: 16641 x 64^2, FP32 + FP64
+    refinement at its tolerance (1e-9; measured v_final 2.8e-9, F_last
+    1.7e-9; at 1e-8 v_final would miss: 4.6e-8), 200 steps from
+    u0 = I_h(sin sin), v0 = 0.
+    64 seeded interior instances are replayed through the oracle (banded
+    Cholesky, FP64) driven by the GPU's macro values u_i^n:
+        v_i^{n+1} = S_i^{-1} (M_i v_i^n / dt + kappa p u_i^{n+1} b_i),
+        F_i^{n+1} = kappa p u_i^{n+1} - kappa / |dY_i| b_i^T v_i^{n+1};
+    F of every step, F of the last step and the final v agree to 1e-8
+    (relative l2 over the sample).  The macro equation holds on every
+    interior row at every step."""
+    w = W.WORKLOADS["large_mixed"]
+    e = replay_large_mixed(w.rtol)
+    assert e["macro_row_residual"] <= 1e-12 and e["macro_boundary_max"] == 0.0
+    assert e["F_all"] <= 1e-8 and e["F_last"] <= 1e-8 and e["v_final"] <= 1e-8, e
 
 
 def _persistent():

@@ -47,6 +47,7 @@ class Workload:
     precision: str             # "fp64" or "fp32_refine"
     rtol: float                # relative residual target of every micro solve
     checkpoint_every: int = 0  # adjoint checkpoint spacing (0: no adjoint)
+    grad_rtol: float = 0.0     # tolerance of the gradient's solves (0: rtol)
     fd_dirs: int = 0
     fd_h: float = 0.0
     # physical parameters of the two-scale system
@@ -77,9 +78,12 @@ WORKLOADS = {
                              False, False, 0.01, 50, "fp64", 1e-12,
                              checkpoint_every=10, fd_dirs=16, fd_h=1e-6),
     # 16641 instances of 64x64 (70.3M micro DoFs), rotated, 200 steps + adjoint.
+    # Solved to 1e-9: the outputs then agree with the FP64 oracle to 1e-8
+    # after 200 steps (at 1e-8 the final micro state misses it, 4.6e-8:
+    # the per-step errors accumulate); the gradient's solves to 1e-11.
     "large_mixed": Workload("large_mixed", 128, (64,), (1.0,), "uniform", 0.3,
-                            False, True, 0.0025, 200, "fp32_refine", 1e-8,
-                            checkpoint_every=20),
+                            False, True, 0.0025, 200, "fp32_refine", 1e-9,
+                            checkpoint_every=20, grad_rtol=1e-11),
 }
 
 
