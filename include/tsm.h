@@ -335,6 +335,17 @@ tsm_status tsm_mark_refine(int64_t n_inst, const double* eta2, const int32_t* le
 tsm_status tsm_prolong(int64_t n_inst, const int32_t* level_old, const int32_t* level_new, const double* v_old,
                        int64_t n_old, double* v_new, int64_t n_new, void* stream);
 
+/* tsm_prolong for callers that cannot allocate device memory (code that
+ * runs under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, checks and results, with the level and
+ * offset arrays staged in a static device array of the library (3 MiB per
+ * GPU, held until the process ends) instead of buffers allocated per call.
+ * At most 131072 instances (TSM_ENOMEM beyond, with a message in
+ * tsm_last_error(NULL)).  Calls allocate nothing; every call on one GPU uses
+ * that GPU's array, so calls that overlap on one GPU (from several host
+ * threads) race -- serialise them. */
+tsm_status tsm_prolong_noalloc(int64_t n_inst, const int32_t* level_old, const int32_t* level_new,
+                               const double* v_old, int64_t n_old, double* v_new, int64_t n_new, void* stream);
 
 /* ---------------------------------------------------------------------------
  * The paper's stationary three-field system (Section 2.1 model; the Case A/B

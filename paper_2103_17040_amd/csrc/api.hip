@@ -537,6 +537,15 @@ tsm_status create_failed(tsm_ctx* c, tsm_status st, const std::string& msg) {
 }
 }  // namespace
 
+extern "C++" {
+namespace tsm {
+tsm_status call_failed(tsm_status st, const std::string& msg) {
+    g_create_error = msg;
+    return st;
+}
+}  // namespace tsm
+}  // extern "C++"
+
 tsm_status tsm_create(const tsm_params* p, void* stream, tsm_ctx** out) {
     if (!out) return create_failed(nullptr, TSM_EINVAL, "out is NULL");
     *out = nullptr;

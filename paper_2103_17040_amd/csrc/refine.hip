@@ -12,6 +12,9 @@
 // C = K K^T J at the edge's points (Section 3.1), from the amplitude.
 // Refinement doubles the cells per side of an instance; its field is carried
 // to the nested mesh by Q1 interpolation.
+#include <mutex>
+#include <string>
+
 #include "device_common.h"
 
 namespace tsm {
@@ -132,3 +135,127 @@ hipError_t launch_prolong(int n_inst, const int32_t* lo, const int32_t* ln, cons
 }
 
 }  // namespace tsm
+
+// ---------------------------------------------------------------------------
+// Interpolation without device allocation (tsm_prolong_noalloc): the level
+// arrays are staged, and the ragged offsets formed, in one static device
+// array per GPU instead of buffers allocated per call.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNoAllocMaxInst = 131072;
+// layout: level_old int32[MAX], level_new int32[MAX], offsets_old int64[MAX+1], offsets_new int64[MAX+1]
+constexpr size_t kScratchLoOff = 0;
+constexpr size_t kScratchLnOff = kScratchLoOff + 4 * kNoAllocMaxInst;
+constexpr size_t kScratchOoOff = kScratchLnOff + 4 * kNoAllocMaxInst;
+constexpr size_t kScratchOnOff = kScratchOoOff + 8 * (kNoAllocMaxInst + 1);
+constexpr size_t kScratchBytes = kScratchOnOff + 8 * (kNoAllocMaxInst + 1);
+static_assert(kScratchOoOff % 8 == 0 && kScratchOnOff % 8 == 0, "int64 regions aligned");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Exclusive prefix sums of (N+1)^2 over both level arrays, offsets[n] the
+// total: one workgroup, each lane a contiguous chunk of instances.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void level_offsets_kernel(int n, const int32_t* lo, const int32_t* ln,
+                                                                   int64_t* oo, int64_t* on) {
+    __shared__ int64_t part[2][kScanThreads];
+    const int t = threadIdx.x;
+    const int per = (n + kScanThreads - 1) / kScanThreads;
+    const int b = t * per;
+    const int e = b + per < n ? b + per : n;
+    int64_t so = 0, sn = 0;
+    for (int i = b; i < e; ++i) {
+        so += (int64_t)(lo[i] + 1) * (lo[i] + 1);
+        sn += (int64_t)(ln[i] + 1) * (ln[i] + 1);
+    }
+    part[0][t] = so;
+    part[1][t] = sn;
+    __syncthreads();
+    if (t == 0) {
+        int64_t ao = 0, an = 0;
+        for (int k = 0; k < kScanThreads; ++k) {
+            const int64_t xo = part[0][k], xn = part[1][k];
+            part[0][k] = ao;
+            part[1][k] = an;
+            ao += xo;
+            an += xn;
+        }
+        oo[n] = ao;
+        on[n] = an;
+    }
+    __syncthreads();
+    so = part[0][t];
+    sn = part[1][t];
+    for (int i = b; i < e; ++i) {
+        oo[i] = so;
+        on[i] = sn;
+        so += (int64_t)(lo[i] + 1) * (lo[i] + 1);
+        sn += (int64_t)(ln[i] + 1) * (ln[i] + 1);
+    }
+}
+
+}  // namespace
+
+// Stand-in on the host for the device array; its device address is taken
+// with hipGetSymbolAddress once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+extern "C" tsm_status tsm_prolong_noalloc(int64_t n_inst, const int32_t* lo, const int32_t* ln, const double* vo,
+                                          int64_t n_old, double* vn, int64_t n_new, void* stream) {
+    using namespace tsm;
+    if (n_inst < 1 || !lo || !ln || !vo || !vn) return call_failed(TSM_EINVAL, "tsm_prolong_noalloc: bad arguments");
+    if (n_inst > kNoAllocMaxInst)
+        return call_failed(TSM_ENOMEM, "tsm_prolong_noalloc: " + std::to_string(n_inst) +
+                                           " instances exceed its static workspace of " +
+                                           std::to_string(kNoAllocMaxInst));
+    int64_t to = 0, tn = 0;
+    for (int64_t i = 0; i < n_inst; ++i) {
+        if (lo[i] < kMinLevel || lo[i] > kMaxLevel || !(ln[i] == lo[i] || ln[i] == 2 * lo[i]) || ln[i] > kMaxLevel)
+            return call_failed(TSM_EINVAL, "tsm_prolong_noalloc: level_new[" + std::to_string(i) +
+                                               "] is neither level_old nor twice it (<= 64)");
+        to += (int64_t)(lo[i] + 1) * (lo[i] + 1);
+        tn += (int64_t)(ln[i] + 1) * (ln[i] + 1);
+    }
+    if (n_old != to || n_new != tn)
+        return call_failed(TSM_EINVAL, "tsm_prolong_noalloc: v_old must hold " + std::to_string(to) + " and v_new " +
+                                           std::to_string(tn) + " entries");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return call_failed(TSM_EHIP, std::string("tsm_prolong_noalloc: hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return call_failed(TSM_EINVAL, "tsm_prolong_noalloc: device index out of range");
+    unsigned char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return call_failed(TSM_EHIP, std::string("tsm_prolong_noalloc: hipGetSymbolAddress: ") +
+                                                 hipGetErrorString(e));
+            g_scratch_ptr[dev] = p;
+        }
+        base = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    }
+    int32_t* dlo = reinterpret_cast<int32_t*>(base + kScratchLoOff);
+    int32_t* dln = reinterpret_cast<int32_t*>(base + kScratchLnOff);
+    int64_t* doo = reinterpret_cast<int64_t*>(base + kScratchOoOff);
+    int64_t* don = reinterpret_cast<int64_t*>(base + kScratchOnOff);
+    hipStream_t s = (hipStream_t)stream;
+    // every scratch entry the kernels read is written first in this call
+    e = hipMemcpyAsync(dlo, lo, n_inst * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dln, ln, n_inst * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(level_offsets_kernel, dim3(1), dim3(kScanThreads), 0, s, (int)n_inst, dlo, dln, doo, don);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = launch_prolong((int)n_inst, dlo, dln, doo, don, vo, vn, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return call_failed(TSM_EHIP, std::string("tsm_prolong_noalloc: ") + hipGetErrorString(e));
+    }
+    return TSM_OK;
+}

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <string>
 
 #include "tsm.h"
 
@@ -289,6 +290,9 @@ hipError_t launch_bnd_gather(int n_inst, const int32_t* level, const int64_t* of
 // out[1] = mean over instances of res (per-instance micro residual norms)
 hipError_t launch_coupling_residual(int nR, const double* R, int n_inst, const double* res, double* out,
                                     hipStream_t s);
+// Failure of a call that has no context: the message becomes
+// tsm_last_error(NULL) of the calling thread; returns st.
+tsm_status call_failed(tsm_status st, const std::string& msg);
 
 // macro kernels
 hipError_t launch_macro_rhs_forward(const MacroArgs& m, const double* u, const double* bx,

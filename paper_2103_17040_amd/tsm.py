@@ -40,7 +40,7 @@ EXPORTED = ["tsm_default_params", "tsm_create", "tsm_set_reference_mesh", "tsm_g
             "tsm_get_micro", "tsm_get_setup", "tsm_apply_operator", "tsm_gradient", "tsm_set_flags", "tsm_autotune", "tsm_get_stats",
             "tsm_last_error", "tsm_destroy", "tsm_stationary_default_params", "tsm_stationary_create",
             "tsm_stationary_solve", "tsm_stationary_set_data", "tsm_stationary_get_stats",
-            "tsm_error_indicator", "tsm_mark_refine", "tsm_prolong"]
+            "tsm_error_indicator", "tsm_mark_refine", "tsm_prolong", "tsm_prolong_noalloc"]
 
 
 class tsm_params(ctypes.Structure):
@@ -122,6 +122,7 @@ def _load():
         "tsm_mark_refine": (I32, [I64, ctypes.POINTER(D), ctypes.POINTER(I32), D, I32, ctypes.POINTER(I32),
                                   ctypes.POINTER(I64)]),
         "tsm_prolong": (I32, [I64, ctypes.POINTER(I32), ctypes.POINTER(I32), VP, I64, VP, I64, VP]),
+        "tsm_prolong_noalloc": (I32, [I64, ctypes.POINTER(I32), ctypes.POINTER(I32), VP, I64, VP, I64, VP]),
         "tsm_stationary_get_stats": (I32, [P, ctypes.POINTER(tsm_stationary_stats)]),
     }
     for name, (res, args) in sig.items():
@@ -329,6 +330,18 @@ def tsm_prolong(level_old, level_new, v_old, v_new, stream=None, n_old=None, n_n
     st = _lib.tsm_prolong(lo.size, lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                           ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(v_old), _n(v_old, n_old),
                           _ptr(v_new), _n(v_new, n_new), stream)
+    if st != TSM_OK:
+        raise TsmError(st, _lib.tsm_last_error(None).decode())
+
+
+def tsm_prolong_noalloc(level_old, level_new, v_old, v_new, stream=None, n_old=None, n_new=None) -> None:
+    """tsm_prolong without device allocation (static workspace, at most
+    131072 instances)."""
+    lo = np.ascontiguousarray(level_old, dtype=np.int32)
+    ln = np.ascontiguousarray(level_new, dtype=np.int32)
+    st = _lib.tsm_prolong_noalloc(lo.size, lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(v_old), _n(v_old, n_old),
+                                  _ptr(v_new), _n(v_new, n_new), stream)
     if st != TSM_OK:
         raise TsmError(st, _lib.tsm_last_error(None).decode())
 
