@@ -52,6 +52,13 @@ B_FLOOR = 24.0
 # r -= ||r|| S d, r.r, x += ||r|| d = 33 flops; per solve x0 = X0 + u w,
 # K x0, M x0 (9 FMA each), ||b||^2 and ||r||^2 = 43 flops.
 FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 33.0, 43.0   # (refine: S x0 replaces M x0 in the solve term)
+# The matrix-free operator of a refinement solve, per DoF (one cell per
+# DoF): at each of 4 Gauss points M = I + aG (2 FMA), J (MUL + FMA), 1/J
+# (reciprocal + 2 Newton steps, 4 FMA), C = adj adj^T / J (3 x (MUL, FMA,
+# MUL)) and the moments of C and J (19 FMA) = 69 flops; 10 element
+# entries (3 ADD + 1 FMA); K x0 on the 4 corners (16 FMA); the node sums
+# (~10 ADD): 4 * 69 + 50 + 32 + 10 = 368 flops.
+FLOP_OPERATOR_MF = 368.0
 # Bytes the instance-resident micro kernel must move per DoF per step
 # (algorithmic: the vectors of the iterations stay on chip; operators are read
 # from their symmetric upper-half planes, 5 coefficients per node):
@@ -78,13 +85,23 @@ def packed_under(N, flags):
     return N in PACKED_LEVELS and not (flags & (1 << 3)) and not (flags & per_size[N])
 
 
+def matrix_free(N, flags, refine):
+    """Whether the packed refinement kernel evaluates the operator from the
+    amplitudes (the default of the per-size plan) instead of reading the
+    assembled planes (the stored-operator flag, and the persistent plans)."""
+    return refine and packed_under(N, flags) and not (flags & ((1 << 9) | (1 << 4)))
+
+
 def micro_bytes_per_dof(N, flags, refine, iters, sweeps):
     """Algorithmic HBM bytes per DoF-update of the micro kernel that solves an
     N x N instance under the launch plan `flags` (packed kernels: symmetric
-    planes as above; generic kernel: full 9-coefficient rows, FP64 M for b,
-    its stencil held in registers when the instance fits, else streamed)."""
+    planes as above, or none when the operator is evaluated matrix-free;
+    generic kernel: full 9-coefficient rows, FP64 M for b, its stencil held
+    in registers when the instance fits, else streamed)."""
     if packed_under(N, flags):
         bdot = 16.0 * 4 * N / (N + 1) ** 2      # the boundary pass for b^T x
+        if matrix_free(N, flags, refine):
+            return B_START + B_END + bdot
         if refine:
             return B_START + B_K + B_S32 + B_SLO + B_END + bdot
         return B_START + B_K + B_S64 + B_END + bdot
@@ -697,8 +714,10 @@ def main():
     iters = st["iters_mean"]
     sweeps = st["sweeps_mean"] if refine else 0
     dofs_per_launch = n_dofs / max(tst["micro_launches"], 1)
-    flops = dofs_per_launch * (FLOP_ITER * iters + FLOP_SWEEP * sweeps + FLOP_SOLVE)
     plan_flags = main_form["plan"]["flags"]
+    mf_dofs = sum((N + 1) ** 2 for N in lv.tolist() if matrix_free(int(N), plan_flags, refine))
+    flops = (dofs_per_launch * (FLOP_ITER * iters + FLOP_SWEEP * sweeps + FLOP_SOLVE)
+             + mf_dofs / max(tst["micro_launches"], 1) * FLOP_OPERATOR_MF)
     step_bytes = sum((N + 1) ** 2 * micro_bytes_per_dof(int(N), plan_flags, refine, iters, sweeps)
                      for N in lv.tolist())
     nbytes = step_bytes / max(tst["micro_launches"], 1)

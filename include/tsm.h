@@ -75,6 +75,12 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
                                             workgroup per compute unit) with a work queue
                                             (largest meshes first), instead of one launch per
                                             mesh size with one workgroup per pack */
+#define TSM_FLAG_STORED_OPERATOR (1ull << 9) /* the packed refinement kernels read the operator
+                                            assembled at setup (FP32 planes and the FP64 K planes)
+                                            instead of evaluating it matrix-free from the
+                                            amplitudes at the start of every solve (Section 3.1:
+                                            J and K K^T J at the quadrature points).  Geometry from
+                                            Jacobian tables always uses the assembled operator. */
 #define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
                                             HIP events on the context's stream (see tsm_stats) */
 #define TSM_FLAG_FIXED_POINT (1ull << 5) /* tsm_step couples macro and micro solves by the paper's
@@ -280,11 +286,14 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags);
  * `steps` steps each (after one warm-up step) from the current state, then,
  * from the faster packed plan, move one packed mesh size at a time to the
  * one-instance-per-workgroup kernel (TSM_FLAG_GENERIC_16/32/64) while that
- * is faster; restore the state after every trial and keep the fastest plan.
- * ms_out[4] (host, may be NULL): ms per step of the per-size, persistent and
- * generic plans (-1 where a plan does not apply) and of the chosen plan;
- * *flags_out (host, may be NULL): the chosen TSM_FLAG_* plan bits.  Needs
- * set_state first. */
+ * is faster, then (refinement mode, packed plan, amplitude geometry) time the
+ * chosen plan with the other form of the operator (TSM_FLAG_STORED_OPERATOR
+ * toggled); restore the state after every trial and keep the fastest plan.
+ * ms_out[5] (host, may be NULL): ms per step of the per-size, persistent and
+ * generic plans in the caller's operator form (-1 where a plan does not
+ * apply), of the chosen plan, and of the runner-up operator form of the
+ * chosen plan (-1 if not tried); *flags_out (host, may be NULL): the chosen
+ * TSM_FLAG_* plan bits.  Needs set_state first. */
 tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* flags_out);
 
 /* Statistics of the last calls (host pointer *s, filled; EINVAL on NULL).

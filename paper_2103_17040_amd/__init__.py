@@ -171,7 +171,8 @@ class TwoScaleBatch:
         ms, flags = tsm.tsm_autotune(self.ctx, steps)
         self._flags = (self._flags & ~tsm.PLAN_BITS) | flags
         res = {"flags": flags, "plan": tsm.plan_name(flags),
-               "ms_per_step": {"per_size": ms[0], "persistent": ms[1], "generic": ms[2], "chosen": ms[3]}}
+               "ms_per_step": {"per_size": ms[0], "persistent": ms[1], "generic": ms[2], "chosen": ms[3],
+                               "other_operator_form": ms[4]}}
         if cache is not None:
             rec = {}
             if os.path.exists(cache):

@@ -208,6 +208,15 @@ namespace {
 // or another for launches that run beside it).
 tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st, int32_t* queue) {
     const bool refine = c->prm.precision == TSM_FP32_REFINE && !setup;
+    // the packed refinement kernels evaluate the operator from the
+    // amplitudes (time-step form: right-hand side M x0/dt with M w) unless
+    // the geometry came from tables or the assembled operator is asked for;
+    // the persistent launch plans read the assembled operator (their
+    // matrix-free form is switched off: a run of it faulted the GPU and its
+    // cause is not found)
+    const bool mf = refine && base.rhs_vec == nullptr && base.Mw != nullptr && !base.zero_init && !c->geom_tables &&
+                    !c->stationary && !(c->prm.flags & (TSM_FLAG_STORED_OPERATOR | TSM_FLAG_PERSISTENT));
+    const int pmode = refine ? (mf ? 3 : 2) : 1;
     // the packed kernels leave b^T x to one boundary pass over their instances
     MicroArgs pbase = base;
     pbase.bx_out = nullptr;
@@ -223,9 +232,9 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
         HIPCHK(launch_fill_i32(queue, 0, 1, st));
         const int grid = std::min(c->n_packs, c->n_cu);
         if (c->pack_groups.size() == 1)   // one mesh size: its own kernel, same queue
-            HIPCHK(launch_packed(a, pl, c->pack_groups[0][0], refine ? 2 : 1, grid, st));
+            HIPCHK(launch_packed(a, pl, c->pack_groups[0][0], pmode, grid, st));
         else
-            HIPCHK(launch_packed_mixed(a, pl, c->pk_level, refine ? 2 : 1, grid, c->pack_lds_max, st));
+            HIPCHK(launch_packed_mixed(a, pl, c->pk_level, pmode, grid, c->pack_lds_max, st));
     } else {
         for (const auto& pg : c->pack_groups) {
             PackList pl{pg[2], c->pk_first + pg[1], c->pk_count + pg[1], c->pk_slot_inst + (int64_t)pg[1] * kPackSlots,
@@ -234,7 +243,7 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
             a.n_tasks = (int)c->n_inst;
             a.order = c->order;
             a.order_off = c->order_off;
-            HIPCHK(launch_packed(a, pl, pg[0], refine ? 2 : 1, pg[2], st));
+            HIPCHK(launch_packed(a, pl, pg[0], pmode, pg[2], st));
         }
     }
     if (c->n_packs > 0 && base.bx_out != nullptr)
@@ -370,6 +379,10 @@ MicroArgs micro_base(tsm_ctx* c) {
     a.max_iter = c->prm.max_iter;
     a.max_refine = c->prm.max_refine;
     a.queue = nullptr;
+    a.amp = c->amp;
+    a.tab = Tables{c->tab_off, c->tab_y, c->tab_s, c->tab_c};
+    a.d = c->prm.d;
+    a.kappa = c->prm.kappa;
     return a;
 }
 
@@ -1204,7 +1217,8 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
     const bool replan = ((flags ^ c->prm.flags) & (TSM_FLAG_STENCIL_STREAM | TSM_FLAG_GENERIC | TSM_FLAG_GENERIC_16 |
                                                     TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64)) != 0;
     if (flags & ~(TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_TIMING | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT |
-                  TSM_FLAG_FIXED_POINT | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64))
+                  TSM_FLAG_FIXED_POINT | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64 |
+                  TSM_FLAG_STORED_OPERATOR))
         return c->fail(TSM_EINVAL, "unknown flag bits");
     HIPCHK(hipStreamSynchronize(c->stream));
     c->prm.flags = flags;
@@ -1223,11 +1237,13 @@ tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* fla
     const int64_t ni = c->n_inst, tot = c->total;
     // plans are timed with the whole-step events (TSM_FLAG_TIMING would turn the graph off)
     const uint64_t plan_bits = TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 |
-                               TSM_FLAG_GENERIC_64;
+                               TSM_FLAG_GENERIC_64 | TSM_FLAG_STORED_OPERATOR;
     const uint64_t timing = c->prm.flags & TSM_FLAG_TIMING;
     const uint64_t keep = c->prm.flags & ~(plan_bits | TSM_FLAG_TIMING);
     const uint64_t entry_flags = c->prm.flags;
-    double ms[4] = {-1.0, -1.0, -1.0, -1.0};
+    // stages 1 and 2 keep the caller's operator form; stage 3 tries the other
+    const uint64_t op_form = c->prm.flags & TSM_FLAG_STORED_OPERATOR;
+    double ms[5] = {-1.0, -1.0, -1.0, -1.0, -1.0};
     double *su = nullptr, *sv = nullptr, *sF = nullptr;
     if (dalloc(&su, ni) != hipSuccess || dalloc(&sv, tot) != hipSuccess || dalloc(&sF, ni) != hipSuccess) {
         (void)hipGetLastError();
@@ -1262,14 +1278,14 @@ tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* fla
     }
     const bool packs = present[0] || present[1] || present[2];
     // stage 1: whole plans
-    trial(0, ms[0]);
+    trial(op_form, ms[0]);
     if (packs) {
-        trial(TSM_FLAG_PERSISTENT, ms[1]);
-        trial(TSM_FLAG_GENERIC, ms[2]);
+        trial(TSM_FLAG_PERSISTENT | op_form, ms[1]);
+        trial(TSM_FLAG_GENERIC | op_form, ms[2]);
     }
-    uint64_t best = 0;
+    uint64_t best = op_form;
     double best_ms = ms[0];
-    if (ms[1] >= 0 && ms[1] < best_ms) { best = TSM_FLAG_PERSISTENT; best_ms = ms[1]; }
+    if (ms[1] >= 0 && ms[1] < best_ms) { best = TSM_FLAG_PERSISTENT | op_form; best_ms = ms[1]; }
     // stage 2: from the better packed plan, move one mesh size at a time to
     // the generic kernel while that helps
     const uint64_t size_bit[3] = {TSM_FLAG_GENERIC_16, TSM_FLAG_GENERIC_32, TSM_FLAG_GENERIC_64};
@@ -1284,7 +1300,18 @@ tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* fla
             --packed_sizes;
         }
     }
-    if (ms[2] >= 0 && ms[2] < best_ms) { best = TSM_FLAG_GENERIC; best_ms = ms[2]; }
+    if (ms[2] >= 0 && ms[2] < best_ms) { best = TSM_FLAG_GENERIC | op_form; best_ms = ms[2]; }
+    // stage 3: the chosen plan with the other form of the packed refinement
+    // operator (matrix-free from the amplitudes, or assembled at setup)
+    const bool op_choice = packs && !(best & TSM_FLAG_GENERIC) && c->prm.precision == TSM_FP32_REFINE &&
+                           !c->geom_tables;
+    if (op_choice && st == TSM_OK) {
+        trial(best ^ TSM_FLAG_STORED_OPERATOR, ms[4]);
+        if (ms[4] >= 0 && ms[4] < best_ms) {
+            std::swap(best_ms, ms[4]);
+            best ^= TSM_FLAG_STORED_OPERATOR;
+        }
+    }
     ms[3] = best_ms;
     if (st == TSM_OK) {
         st = tsm_set_flags(c, keep | timing | best);

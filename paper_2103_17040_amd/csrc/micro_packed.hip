@@ -579,6 +579,289 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
     }
 }
 
+// ------------------------------------------------------------ matrix-free
+// The time-step operator S = M/dt + d A + kappa B of a pack's instances,
+// evaluated at the start of every solve from the amplitude a_i and the
+// level's quadrature tables instead of read from assembled planes (paper
+// Section 3.1: J and K K^T J at every quadrature point, |cof(F) nu| on the
+// boundary; Section 3.4 caches them per point, here they are recomputed).
+//
+// Lane (col c, strip rows r0..r0+R-1) integrates the cells (c, r) for
+// r = r0-1 .. r0+R-1 -- the cells to the right of and above its nodes; the
+// first one is also integrated by the strip below -- into element matrices
+// (2x2 Gauss), and the Robin edge terms of boundary cells.  A node's 9-point
+// row takes the entries of its four cells: the two to its right are the
+// lane's own, the two to its left belong to lane c-1, which passes six FP64
+// values one lane to the right per node row (a DPP wave shift; the first
+// lane of a wave takes them from LDS, written by the last lane of the wave
+// before): the centre and north parts of its cells, the north-west
+// coupling, its cells' part of K x0, its own east coupling (the receiver's
+// west) and its previous row's north-east coupling (the receiver's
+// south-west).  South and south-east come from the lane's own previous row.
+// So every coupling is one FP64 value whichever of its two nodes uses it,
+// and the FP32 stencil fl32(S) -- in registers -- is exactly symmetric; the
+// low parts fl32(S - fl32(S)) of the upper couplings go to the LDS planes
+// for the FP64 residual updates; the start residual r = -K x0 + coef M w/dt
+// stays in FP64.
+
+// Boundary weights of every instance of a pack (kappa wb |F tau| at the 8N
+// edge points) and the level's tables, in LDS.
+constexpr int kMfBw = cmax(cmax(L16::IPP * 8 * 16, L32::IPP * 8 * 32), L64::IPP * 8 * 64);
+constexpr int kMfX = 6;      // FP64 values passed to the right per node row
+struct MfShared {
+    double ty[2 * kMaxLevel + 2], ts[2 * kMaxLevel + 2], tc[2 * kMaxLevel + 2];
+    double bw[kMfBw];
+    double xb[2][NWP][kMfX];
+};
+
+// Lane l takes lane l-1's value (DPP wave_shr:1); lane 0 of the wave takes 0.
+__device__ __forceinline__ double lane_from_left(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x138, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Each lane receives the kMfX values of the lane on its left; lanes of
+// column 0 (nothing to their left) and inactive lanes receive 0.  One LDS
+// barrier (the last lane of every wave hands its values over through LDS,
+// double-buffered by par).  All lanes must call.
+template <class L>
+__device__ __forceinline__ void mf_pass_right(const Lane& z, double (*xb)[NWP][kMfX], int par,
+                                              const double (&snd)[kMfX], double (&rcv)[kMfX]) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < kMfX; ++q) rcv[q] = lane_from_left(snd[q]);
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int q = 0; q < kMfX; ++q) xb[par][wid][q] = snd[q];
+    }
+    lds_barrier();
+    if (lane == 0) {
+        const int src = wid > 0 ? wid - 1 : 0;
+#pragma unroll
+        for (int q = 0; q < kMfX; ++q) rcv[q] = xb[par][src][q];
+    }
+    const bool none = !z.act || z.col == 0;
+#pragma unroll
+    for (int q = 0; q < kMfX; ++q) rcv[q] = none ? 0.0 : rcv[q];
+}
+
+// Element matrices of one cell (2x2 Gauss) from the geometry at its points:
+// M = I + a G with M11 = 1 + a c(y1) y2, M12 = a s(y1), M21 = a s(y2),
+// M22 = 1 + a c(y2) y1 (A1 = a c(y1), S1 = a s(y1), likewise A2, S2 per
+// abscissa of the cell); J = det M, C = adj(M) adj(M)^T / J.  Entries in
+// the order (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2) (2,3) (3,3) of
+// the local nodes q = l2*2 + l1:
+//   K_lm = d sum_g wq grad eta_l . C grad eta_m   (wq / h^2 = 1/4)
+//   S_lm = K_lm + (1/dt) sum_g wq J eta_l eta_m
+// The stiffness entries come from the moments of C11 along y2, C22 along
+// y1 and C12 against one basis factor in each direction; the mass entries
+// from the moments of J.
+constexpr int kPairL[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+constexpr int kPairM[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+__device__ __forceinline__ void mf_cell(double d4, double wq_dt, const double (&y1)[2], const double (&A1)[2],
+                                        const double (&S1)[2], const double (&y2)[2], const double (&A2)[2],
+                                        const double (&S2)[2], double (&K)[10], double (&S)[10]) {
+    double q11[3] = {0.0, 0.0, 0.0}, q22[3] = {0.0, 0.0, 0.0};
+    double q12[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    double mm[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int g2 = 0; g2 < 2; ++g2)
+#pragma unroll
+        for (int g1 = 0; g1 < 2; ++g1) {
+            const double M11 = fma(A1[g1], y2[g2], 1.0);
+            const double M22 = fma(A2[g2], y1[g1], 1.0);
+            const double M12 = S1[g1], M21 = S2[g2];
+            const double J = M11 * M22 - M12 * M21;
+            // d/(4J): reciprocal estimate refined by two Newton steps
+            // x <- x + x (1 - J x) (J > 0: the setup checked det D zeta)
+            double iJ = __builtin_amdgcn_rcp(J);
+            iJ = fma(iJ, fma(-J, iJ, 1.0), iJ);
+            iJ = fma(iJ, fma(-J, iJ, 1.0), iJ);
+            const double s = d4 * iJ;
+            const double C11 = (M22 * M22 + M12 * M12) * s;
+            const double C12 = -(M22 * M21 + M12 * M11) * s;
+            const double C22 = (M21 * M21 + M11 * M11) * s;
+            const double f1[2] = {lin(0, g1), lin(1, g1)};
+            const double f2[2] = {lin(0, g2), lin(1, g2)};
+            const double F1[3] = {f1[0] * f1[0], f1[0] * f1[1], f1[1] * f1[1]};
+            const double F2[3] = {f2[0] * f2[0], f2[0] * f2[1], f2[1] * f2[1]};
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                q11[p] = fma(C11, F2[p], q11[p]);
+                q22[p] = fma(C22, F1[p], q22[p]);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) q12[u][v] = fma(C12, f2[u] * f1[v], q12[u][v]);
+#pragma unroll
+            for (int p1 = 0; p1 < 3; ++p1)
+#pragma unroll
+                for (int p2 = 0; p2 < 3; ++p2) mm[p1][p2] = fma(J, F1[p1] * F2[p2], mm[p1][p2]);
+        }
+#pragma unroll
+    for (int e = 0; e < 10; ++e) {
+        const int l1 = kPairL[e] & 1, l2 = kPairL[e] >> 1, m1 = kPairM[e] & 1, m2 = kPairM[e] >> 1;
+        const double s11 = (l1 == m1) ? 1.0 : -1.0;     // sigma(l1) sigma(m1)
+        const double s12 = (l1 == m2) ? 1.0 : -1.0;     // sigma(l1) sigma(m2)
+        const double s21 = (l2 == m1) ? 1.0 : -1.0;     // sigma(l2) sigma(m1)
+        const double s22 = (l2 == m2) ? 1.0 : -1.0;     // sigma(l2) sigma(m2)
+        const double a = s11 * q11[l2 + m2] + s12 * q12[l2][m1] + s21 * q12[m2][l1] + s22 * q22[l1 + m1];
+        K[e] = a;
+        S[e] = fma(mm[l1 + m1][l2 + m2], wq_dt, a);
+    }
+}
+
+// Matrix-free start of a time-step solve in the refinement form: x0 to the
+// (double) grid, the FP32 stencil of the lane's rows to S, the FP32 low
+// parts of their upper couplings to the LDS planes slo ([kSym][n]),
+// r = -K x0 + coef M w/dt to r64.  The caller reads x0 back from the grid.
+// All lanes must call.
+template <class L>
+__device__ __forceinline__ void mf_start(const MicroArgs& A, const Lane& z, double* xg, MfShared& ms, float* slo,
+                                         float (&S)[L::R][kStencil], double (&r64)[L::R]) {
+    constexpr int N = L::N, W2 = L::W2;
+    constexpr double h = 2.0 / N;
+    constexpr double wq = 0.25 * h * h, wb = 0.5 * h;
+    zero_halo<L, double>(xg, z);
+    const double cf = (z.live && A.coef != nullptr) ? A.coef[z.inst] : 0.0;
+    const double a = z.live ? A.amp[z.inst] : 0.0;
+    {
+        double x[L::R];
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) {
+            double v = 0.0, m = 0.0;
+            if (row_ok<L>(z, i)) {
+                const int j = node_of<L>(z, i);
+                v = A.X0[z.off + j];
+                m = cf * A.inv_dt * A.Mw[z.off + j];
+            }
+            x[i] = v;
+            r64[i] = m;
+        }
+        strip_store<L>(xg, z, x);
+    }
+    // the level's tables, and kappa wb |F tau| at the boundary points of
+    // every instance of the pack (sides bottom, top, left, right; edges; 2
+    // points): bottom/top edges run along y1, |M e1| = sqrt(M11^2 + M21^2);
+    // left/right edges along y2, |M e2| = sqrt(M12^2 + M22^2)
+    const int tb = A.tab.off[N];
+    for (int t = threadIdx.x; t < 2 * N + 2; t += NTP) {
+        ms.ty[t] = A.tab.y[tb + t];
+        ms.ts[t] = A.tab.s[tb + t];
+        ms.tc[t] = A.tab.c[tb + t];
+    }
+    if (z.live) {
+        for (int t = z.lt; t < 8 * N; t += L::TPI) {
+            const int side = t / (2 * N), e = (t >> 1) % N, g = t & 1;
+            const int tf = tb + 2 * N + (side & 1);        // the edge's coordinate: -1 or +1
+            const int tg = tb + 2 * e + g;                 // the Gauss point along the edge
+            const double yf = A.tab.y[tf], sf = A.tab.s[tf];
+            const double along = fma(a * A.tab.c[tg], yf, 1.0);   // M11 (bottom/top) or M22 (left/right)
+            const double across = a * sf;                          // M21 or M12
+            ms.bw[z.sub * 8 * N + t] = A.kappa * wb * sqrt(along * along + across * across);
+        }
+    }
+    __syncthreads();
+    const double* bw = ms.bw + (z.sub < L::IPP ? z.sub : 0) * 8 * N;
+    const int c = z.col;
+    const bool colc = z.act && c < N;
+    const int t1 = 2 * (c < N ? c : 0);
+
+    // carries from the previous cell row: its entries (2,2) (2,3) (3,3) of S,
+    // its K x0 parts for the row above, its north-east and north-west
+    // couplings, and the previous node row's complete north coupling
+    double cS22 = 0.0, cS23 = 0.0, cS33 = 0.0, ck2 = 0.0, ck3 = 0.0, cNE = 0.0, cN = 0.0, cNW = 0.0;
+    // one node row at a time (not unrolled: the cell arithmetic of several
+    // rows in flight would not fit the registers)
+#pragma unroll 1
+    for (int k = -1; k < L::R; ++k) {
+        const int r = z.r0 + k;
+        const bool valid = colc && r >= 0 && r < N;
+        const int t2 = 2 * (valid ? r : 0);
+        double y2[2], A2[2], S2[2], y1[2], A1[2], S1[2];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            y1[g] = ms.ty[t1 + g];
+            A1[g] = a * ms.tc[t1 + g];
+            S1[g] = a * ms.ts[t1 + g];
+            y2[g] = ms.ty[t2 + g];
+            A2[g] = a * ms.tc[t2 + g];
+            S2[g] = a * ms.ts[t2 + g];
+        }
+        // a cell outside the mesh gets zero weights (its geometry, from the
+        // first table entries, is finite)
+        const double on = valid ? 1.0 : 0.0;
+        double Ke[10], Se[10];
+        mf_cell(on * 0.25 * A.d, on * wq * A.inv_dt, y1, A1, S1, y2, A2, S2, Ke, Se);
+        // Robin terms of the cell's boundary edges: entries of the edge's two
+        // nodes, sum over its points of kappa wb |F tau| eta_l eta_m
+        auto edge = [&](const double* w, int ea, int eb, int ec) {
+            const double w0 = w[0], w1 = w[1];
+            const double va = w0 * (lin(0, 0) * lin(0, 0)) + w1 * (lin(0, 1) * lin(0, 1));
+            const double vb = w0 * (lin(0, 0) * lin(1, 0)) + w1 * (lin(0, 1) * lin(1, 1));
+            const double vc = w0 * (lin(1, 0) * lin(1, 0)) + w1 * (lin(1, 1) * lin(1, 1));
+            Ke[ea] += va; Se[ea] += va;
+            Ke[eb] += vb; Se[eb] += vb;
+            Ke[ec] += vc; Se[ec] += vc;
+        };
+        if (valid && r == 0) edge(bw + (0 * N + c) * 2, 0, 1, 4);          // bottom: nodes 0, 1
+        if (valid && r == N - 1) edge(bw + (1 * N + c) * 2, 7, 8, 9);      // top: nodes 2, 3
+        if (valid && c == 0) edge(bw + (2 * N + r) * 2, 0, 2, 7);          // left: nodes 0, 2
+        if (valid && c == N - 1) edge(bw + (3 * N + r) * 2, 4, 6, 9);      // right: nodes 1, 3
+        // K x0 on the cell's corners (c, r), (c+1, r), (c, r+1), (c+1, r+1)
+        // (lanes without a cell read the grid's first cells: zero entries)
+        const int gb = valid ? (r + 1) * W2 + c + 1 : 0;
+        const double x0 = xg[gb], x1 = xg[gb + 1], x2 = xg[gb + W2], x3 = xg[gb + W2 + 1];
+        const double k0 = Ke[0] * x0 + Ke[1] * x1 + Ke[2] * x2 + Ke[3] * x3;    // to (c, r)
+        const double k1 = Ke[1] * x0 + Ke[4] * x1 + Ke[5] * x2 + Ke[6] * x3;    // to (c+1, r)
+        const double k2 = Ke[2] * x0 + Ke[5] * x1 + Ke[7] * x2 + Ke[8] * x3;    // to (c, r+1)
+        const double k3 = Ke[3] * x0 + Ke[6] * x1 + Ke[8] * x2 + Ke[9] * x3;    // to (c+1, r+1)
+        // node row k: the lane's own parts, and what it passes to lane c+1
+        const double Eown = Se[1] + cS23;
+        double snd[kMfX] = {Se[4] + cS33,   // centre part of (c+1, r) from the cells (c, r), (c, r-1)
+                            Se[6],          // north part of (c+1, r)
+                            Se[5],          // north-west coupling of (c+1, r)
+                            k1 + ck3,       // K x0 part of (c+1, r)
+                            Eown,           // west coupling of (c+1, r) = east of (c, r)
+                            cNE};           // south-west of (c+1, r) = north-east of (c, r-1)
+        double rcv[kMfX];
+        mf_pass_right<L>(z, ms.xb, (k + 1) & 1, snd, rcv);
+        const double Nc = Se[2] + rcv[1];
+        if (k >= 0) {
+            // the 9-point row of node row k (k = (dj2+1)*3 + (dj1+1))
+            const double cpl[kStencil] = {rcv[5], cN, cNW, rcv[4], Se[0] + cS22 + rcv[0], Eown, rcv[2], Nc, Se[3]};
+            const double kx = (k0 + ck2) + rcv[3];
+            const bool ok = row_ok<L>(z, k);
+            const int j = node_of<L>(z, k);
+            // row k of the register arrays (static indices keep them in registers)
+#pragma unroll
+            for (int i = 0; i < L::R; ++i)
+                if (i == k) {
+                    r64[i] -= kx;
+#pragma unroll
+                    for (int q = 0; q < kStencil; ++q) S[i][q] = (float)cpl[q];
+                }
+#pragma unroll
+            for (int p = 0; p < kSym; ++p) {
+                const double v = cpl[4 + p];
+                if (ok) slo[p * L::n + j] = (float)(v - (double)(float)v);
+            }
+        }
+        cS22 = Se[7];
+        cS23 = Se[8];
+        cS33 = Se[9];
+        ck2 = k2;
+        ck3 = k3;
+        cNE = Se[3];
+        cN = Nc;
+        cNW = Se[5];
+    }
+    lds_barrier();
+}
+
 // ------------------------------------------------------------------ FP64
 // meta: this pack's metadata in LDS; prefetch(): starts the copy of the next
 // pack's metadata (all waves call it once, early in the solve).
@@ -689,39 +972,49 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
 // parts Slo, copied while the first inner solve runs, for the FP64 residual
 // updates.  Between the start of a copy and its wait, barriers are
 // lds_barrier() (LDS ordering only) so that the copy stays in flight.
-template <class L, class Prefetch>
+template <class L, bool MF, class Prefetch>
 __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, float* planes,
-                            PackRed<1, double>& red1, PackRed<2, double>& red2, PackRed<2, float>& rf2,
-                            Prefetch prefetch) {
+                            MfShared* ms, PackRed<1, double>& red1, PackRed<2, double>& red2,
+                            PackRed<2, float>& rf2, Prefetch prefetch) {
     const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     float* pg = reinterpret_cast<float*>(xg);
     // spare instances of a partial pack read instance 0's planes (results
     // discarded); pl: element 0 of the instance's copied planes
     float* region = planes + (z.live ? z.sub : 0) * L::PS;
-    const int shift = (int)((kSym * z.off) & 3);
+    const int shift = MF ? 0 : (int)((kSym * z.off) & 3);
     const float* pl = region + shift;
     double x[L::R], r64[L::R];
-    double bb;
-    pack_start<L>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift);
+    double bb = 0.0;
     float S[L::R][kStencil], dinv[L::R];
-    planes_copy_wait();
-    const LdsPlanes<L> plv(pl, z);
-    {
+    if constexpr (MF) {
+        // the operator from the amplitude: FP32 stencil to registers, low
+        // parts to the planes buffer, r = -K x0 + coef M w / dt
+        mf_start<L>(A, z, xg, *ms, region, S, r64);
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) dinv[i] = row_ok<L>(z, i) ? 1.0f / S[i][4] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) x[i] = row_ok<L>(z, i) ? xg[cell_of<L>(z, i)] : 0.0;
+        prefetch();
+    } else {
+        pack_start<L>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift);
+        planes_copy_wait();
+        const LdsPlanes<L> plc(pl, z);
         // coefficient 1 of row i > 0 is coefficient 7 of row i-1; rows past
         // the mesh give products that are discarded and diag^{-1} = 0
 #pragma unroll
         for (int i = 0; i < L::R; ++i)
 #pragma unroll
             for (int k = 0; k < kStencil; ++k)
-                S[i][k] = (k == 1 && i > 0) ? S[i - 1][7] : plv.at(z, i, k);
+                S[i][k] = (k == 1 && i > 0) ? S[i - 1][7] : plc.at(z, i, k);
 #pragma unroll
         for (int i = 0; i < L::R; ++i) dinv[i] = row_ok<L>(z, i) ? 1.0f / S[i][4] : 0.0f;
+        // every wave has its stencil: the planes buffer takes the low parts next
+        lds_barrier();
+        if (z.live) planes_copy_start<L>(A.Sslo + kSym * z.off, region, z.lt, shift);
+        prefetch();
     }
-    // every wave has its stencil: the planes buffer takes the low parts next
-    lds_barrier();
-    if (z.live) planes_copy_start<L>(A.Sslo + kSym * z.off, region, z.lt, shift);
-    prefetch();
+    const LdsPlanes<L> plv(pl, z);
     const RegStencil<L, float> SR{S};
     const SplitStencil<L> S64{S, plv};
     if (A.rhs_vec == nullptr) {
@@ -939,7 +1232,13 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
     if constexpr (MODE == 2) {
         __shared__ __attribute__((aligned(16))) float planes[L::PS * L::IPP + 2 * L::NP];
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_refine<L>(A, meta, cnt, lds, planes, red1, red2, rf2, prefetch);
+            pack_refine<L, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch);
+        });
+    } else if constexpr (MODE == 3) {
+        __shared__ __attribute__((aligned(16))) float planes[L::PS * L::IPP + 2 * L::NP];
+        __shared__ MfShared ms;
+        pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
+            pack_refine<L, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch);
         });
     } else {
         __shared__ double xs[L::R * NTP];
@@ -963,9 +1262,17 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
     if constexpr (MODE == 2) {
         __shared__ __attribute__((aligned(16))) float planes[kPlaneFloats];
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
-            if (lvl == 64) pack_refine<L64>(A, meta, cnt, lds, planes, red1, red2, rf2, prefetch);
-            else if (lvl == 32) pack_refine<L32>(A, meta, cnt, lds, planes, red1, red2, rf2, prefetch);
-            else pack_refine<L16>(A, meta, cnt, lds, planes, red1, red2, rf2, prefetch);
+            if (lvl == 64) pack_refine<L64, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch);
+            else if (lvl == 32) pack_refine<L32, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch);
+            else pack_refine<L16, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch);
+        });
+    } else if constexpr (MODE == 3) {
+        __shared__ __attribute__((aligned(16))) float planes[kPlaneFloats];
+        __shared__ MfShared ms;
+        pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
+            if (lvl == 64) pack_refine<L64, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch);
+            else if (lvl == 32) pack_refine<L32, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch);
+            else pack_refine<L16, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch);
         });
     } else {
         __shared__ double xs[kFp64Rows * NTP];
@@ -980,7 +1287,8 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
 template <class L>
 hipError_t launch_level(const MicroArgs& a, const PackList& p, int mode, int grid, hipStream_t s) {
     const size_t lds = sizeof(double) * L::GRID * L::IPP;
-    if (mode == 2) hipLaunchKernelGGL((packed_kernel<2, L>), dim3(grid), dim3(NTP), lds, s, a, p);
+    if (mode == 3) hipLaunchKernelGGL((packed_kernel<3, L>), dim3(grid), dim3(NTP), lds, s, a, p);
+    else if (mode == 2) hipLaunchKernelGGL((packed_kernel<2, L>), dim3(grid), dim3(NTP), lds, s, a, p);
     else hipLaunchKernelGGL((packed_kernel<1, L>), dim3(grid), dim3(NTP), lds, s, a, p);
     return hipGetLastError();
 }
@@ -1008,7 +1316,8 @@ size_t packed_lds_bytes(int level) {
 hipError_t launch_packed_mixed(const MicroArgs& a, const PackList& p, const int32_t* pack_level, int mode,
                                int grid, size_t lds, hipStream_t s) {
     if (p.n_packs <= 0 || grid <= 0 || a.queue == nullptr) return hipSuccess;
-    if (mode == 2) hipLaunchKernelGGL(packed_mixed_kernel<2>, dim3(grid), dim3(NTP), lds, s, a, p, pack_level);
+    if (mode == 3) hipLaunchKernelGGL(packed_mixed_kernel<3>, dim3(grid), dim3(NTP), lds, s, a, p, pack_level);
+    else if (mode == 2) hipLaunchKernelGGL(packed_mixed_kernel<2>, dim3(grid), dim3(NTP), lds, s, a, p, pack_level);
     else if (mode == 1) hipLaunchKernelGGL(packed_mixed_kernel<1>, dim3(grid), dim3(NTP), lds, s, a, p, pack_level);
     else return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1016,7 +1325,7 @@ hipError_t launch_packed_mixed(const MicroArgs& a, const PackList& p, const int3
 
 hipError_t launch_packed(const MicroArgs& a, const PackList& p, int level, int mode, int grid, hipStream_t s) {
     if (p.n_packs <= 0 || grid <= 0) return hipSuccess;
-    if (mode != 1 && mode != 2) return hipErrorInvalidValue;
+    if (mode < 1 || mode > 3) return hipErrorInvalidValue;
     switch (level) {
         case 16: return launch_level<L16>(a, p, mode, grid, s);
         case 32: return launch_level<L32>(a, p, mode, grid, s);

@@ -157,6 +157,12 @@ struct MicroArgs {
     double rtol, inner_rtol;
     int max_iter, max_refine;
     int32_t* queue;       // persistent work counter (null: task = blockIdx.x)
+    // matrix-free operator of the time-step solves (packed kernels, mode 3):
+    // the amplitudes, the per-level quadrature tables and the coefficients of
+    // S = M/dt + d A + kappa B (inv_dt above)
+    const double* amp;
+    Tables tab;
+    double d, kappa;
 };
 
 // Packs of instances of one mesh size solved by one kPackThreads-lane workgroup.
@@ -210,7 +216,8 @@ hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s);
 // same gather for maps given by their Jacobian tables (a.Fcell, a.Fbnd)
 hipError_t launch_assemble_tables(const AssembleArgs& a, hipStream_t s);
 hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_t lds_bytes, hipStream_t s);
-// packs of one mesh size (16, 32 or 64); mode 1 FP64, 2 refinement
+// packs of one mesh size (16, 32 or 64); mode 1 FP64, 2 refinement, 3 refinement
+// with the operator evaluated matrix-free from the amplitudes (time-step form only)
 hipError_t launch_packed(const MicroArgs& a, const PackList& p, int level, int mode, int grid, hipStream_t s);
 // every pack of every size in one persistent launch (work queue a.queue, reset to 0 beforehand)
 hipError_t launch_packed_mixed(const MicroArgs& a, const PackList& p, const int32_t* pack_level, int mode,

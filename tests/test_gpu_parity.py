@@ -108,11 +108,16 @@ def test_forms_agree_bitwise():
     v0 = np.zeros(int(W.offsets(lv)[-1]))
     outs = []
     for prec in ("fp64", "fp32_refine"):
+        # the refinement forms read the assembled operator: this case faulted
+        # the GPU with the matrix-free operator in every form (persistent
+        # plans included), and stays on the assembled operator until the
+        # cause is found
+        extra = tsm.TSM_FLAG_STORED_OPERATOR if prec == "fp32_refine" else 0
         for flags in (0, 0, tsm.TSM_FLAG_NO_GRAPH, tsm.TSM_FLAG_STENCIL_STREAM, tsm.TSM_FLAG_TIMING,
                       tsm.TSM_FLAG_PERSISTENT, tsm.TSM_FLAG_PERSISTENT | tsm.TSM_FLAG_NO_GRAPH,
                       tsm.TSM_FLAG_PERSISTENT | tsm.TSM_FLAG_STENCIL_STREAM):
-            banner(f"forms {prec} flags={flags}")
-            g = gpu_for(5, lv, a, th, 0.005, precision=prec, rtol=1e-10, flags=flags)
+            banner(f"forms {prec} flags={flags | extra}")
+            g = gpu_for(5, lv, a, th, 0.005, precision=prec, rtol=1e-10, flags=flags | extra)
             try:
                 g.set_state(u0, v0)
                 g.step(4)
@@ -137,6 +142,36 @@ def test_generic_kernels_parity(precision, rtol, tol):
                            gpu_kw={"flags": tsm.TSM_FLAG_GENERIC})
     for k in ("u", "F", "v"):
         assert rel(out[k], ref[k]) <= tol, k
+
+
+@pytest.mark.parametrize("NM,levels", [(4, [16, 32, 64]), (6, [16]), (3, [64])])
+def test_matrix_free_and_assembled_operator_forms(NM, levels):
+    """The packed refinement kernels evaluate the operator from the
+    amplitudes at every solve (default) or read the planes assembled at
+    setup (TSM_FLAG_STORED_OPERATOR): both agree with the oracle at the
+    refinement tolerance and with each other to the solver tolerance
+    (their operators differ only in rounding); the stored form is bitwise
+    the same in per-size and persistent launches."""
+    from paper_2103_17040_amd import tsm
+    rng = np.random.default_rng(31 + NM)
+    n = (NM + 1) ** 2
+    lv = rng.choice(np.asarray(levels), n).astype(np.int32)
+    a = rng.uniform(-0.3, 0.3, n)
+    th = rng.uniform(0.0, np.pi / 8, n)
+    u0, v0 = W.random_state(lv, NM, seed=NM)
+    steps, dt = 3, 0.0025
+    outs = {}
+    # (the persistent plans read the assembled operator in either case)
+    for name, flags in (("mf", 0), ("stored", tsm.TSM_FLAG_STORED_OPERATOR),
+                        ("stored_persistent", tsm.TSM_FLAG_STORED_OPERATOR | tsm.TSM_FLAG_PERSISTENT)):
+        ref, out, _ = run_both(NM, lv, a, th, dt, steps, u0, v0, precision="fp32_refine", rtol=1e-10,
+                               gpu_kw={"flags": flags})
+        for k in ("u", "F", "v"):
+            assert rel(out[k], ref[k]) <= 1e-8, (name, k)
+        outs[name] = out
+    for k in ("u", "F", "v"):
+        assert np.array_equal(outs["stored"][k], outs["stored_persistent"][k])
+        assert rel(outs["mf"][k], outs["stored"][k]) <= 1e-8
 
 
 def test_boundary_instances_stay_zero():
