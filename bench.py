@@ -441,48 +441,83 @@ def _paper_table_rows():
     return {m[0]: (m[1], m[2], v[1], v[2]) for m, v in zip(tab["macro"], tab["micro"])}
 
 
-def stationary_convergence_leg(sizes=(8, 16, 32, 64)):
+PAPER_CONVERGENCE_ROWS = (8, 11, 16, 23, 32, 45, 64, 91, 128)   # cells per side, Tables 1-2
+
+
+def _constant_tables(levels, F, device):
+    """Jacobian tables (cell and boundary, the interface's flat layouts) of a
+    map whose Jacobian is the constant F, built on the device."""
+    import torch
+    lv = np.asarray(levels, dtype=np.int64)
+    n_cell_pts = int((4 * lv * lv).sum())      # 2x2 Gauss points per cell
+    n_bnd_pts = int((8 * lv).sum())            # 4 sides x N edges x 2 points
+    f = torch.as_tensor(np.asarray(F, dtype=np.float64).reshape(1, 4), device=device)
+    return f.expand(n_cell_pts, 4).contiguous().view(-1), f.expand(n_bnd_pts, 4).contiguous().view(-1)
+
+
+def stationary_convergence_leg(sizes=PAPER_CONVERGENCE_ROWS, workers=None):
     """The convergence benchmark of Section 4.2 on the GPU: the paper's
     manufactured solution and map (eq. manu_system; data re-derived), N_M = N
-    cells per side on both scales, errors e_uw, e_uw_grad, e_v, e_v_grad and
-    the observed orders; the paper's printed errors at the same DoF counts
-    beside them (its parameters are not given, so only the orders compare)."""
+    cells per side on both scales -- the rows of Tables 1-2, 81 to 16641
+    DoFs per scale -- errors e_uw, e_uw_grad, e_v, e_v_grad and the observed
+    orders; the paper's printed errors at the same DoF counts beside them
+    (its parameters are not given, so only the orders compare).  The map's
+    Jacobian is constant, so its tables are built on the device; data and
+    error integrals run on `workers` host processes."""
+    import torch
     from paper_2103_17040_amd import StationarySystem
     from workloads import manufactured as MF
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
     phys = dict(Dv=1.0, Dw=0.5, kappa1=0.5, kappa2=1.0, kappa3=0.25, kappa4=1.0)
+    parts = (0, 0, 1, 2)
 
     class P:
-        parts = (0, 0, 1, 2)
+        pass
     prm = P()
+    prm.parts = parts
     for k, v in phys.items():
         setattr(prm, k, v)
-    data = MF.manufactured(prm, MF.U_MANU, MF.V_MANU, MF.W_MANU, MF.ZETA_MANU)
+    F = MF.constant_map_jacobian(MF.ZETA_MANU)
     paper = _paper_table_rows()
     rows, dofs, errs = [], [], []
     for N in sizes:
+        t0 = time.perf_counter()
         levels = np.full((N + 1) ** 2, N, dtype=np.int32)
-        _, Fc, Fb = MF.map_tables(N, levels, MF.ZETA_MANU)
-        pts = MF.data_at_points(data, N, levels, prm.parts)
+        pts = MF.manufactured_data_at_points(phys, parts, N, levels, workers)
+        t1 = time.perf_counter()
+        Fc, Fb = _constant_tables(levels, F, "cuda")
         g = StationarySystem(N, levels, jacobians=(Fc, Fb), rtol=1e-13, **phys)
+        del Fc, Fb
+        torch.cuda.empty_cache()
         try:
             g.set_data(**pts)
+            del pts
             u, w, v = g.solve()
             st = g.stats()
             u, w, v = (t.cpu().numpy() for t in (u, w, v))
         finally:
             g.close()
+        t2 = time.perf_counter()
         off = W.offsets(levels)
-        e = MF.convergence_errors(N, N, u, w, [v[off[k]:off[k + 1]] for k in range(len(levels))], prm)
+        e = MF.convergence_errors(N, N, u, w, [v[off[k]:off[k + 1]] for k in range(len(levels))], prm,
+                                  workers=workers)
+        del v
+        t3 = time.perf_counter()
         n = (N + 1) ** 2
         dofs.append(n)
         errs.append(e)
-        rows.append({"macro_dofs": n, "micro_dofs_each": n, "e_uw": e[0], "e_uw_grad": e[1], "e_v": e[2],
-                     "e_v_grad": e[3], "solve_ms": st["solve_ms"], "micro_iters_max": st["micro_iters_max"],
+        rows.append({"macro_dofs": n, "micro_dofs_each": n, "micro_dofs_total": n * n, "e_uw": e[0],
+                     "e_uw_grad": e[1], "e_v": e[2], "e_v_grad": e[3], "solve_ms": st["solve_ms"],
+                     "micro_iters_max": st["micro_iters_max"], "macro_iters": st["macro_iters"],
+                     "host_data_s": t1 - t0, "gpu_context_s": t2 - t1, "host_errors_s": t3 - t2,
                      "paper_e_uw_e_uw_grad_e_v_e_v_grad": paper.get(n)})
+        _log(f"  convergence N={N}: {n} x {n} DoFs, e = {', '.join(f'{x:.3e}' for x in e)}, "
+             f"solve {st['solve_ms']:.1f} ms, micro iters {st['micro_iters_max']}, "
+             f"host {t1 - t0:.1f} + {t3 - t2:.1f} s")
     E = np.array(errs)
     return {"rows": rows, "orders": {"p_M": MF.orders(dofs, E[:, 0]), "q_M": MF.orders(dofs, E[:, 1]),
                                      "p_v": MF.orders(dofs, E[:, 2]), "q_v": MF.orders(dofs, E[:, 3])},
-            "paper_orders_printed": "p 1.94-2.31, q 1.01-1.20 (Tables 1-2)"}
+            "paper_orders_printed": "p 1.94-2.31, q 1.01-1.20 (Tables 1-2)", "host_workers": workers}
 
 
 def parity_leg():
@@ -659,6 +694,9 @@ def main():
                     help="skip the parity leg (errors against the oracle's stored outputs)")
     ap.add_argument("--st-reps", type=int, default=3,
                     help="stationary three-field solves timed per size (0: skip that leg)")
+    ap.add_argument("--st-conv-sizes", type=lambda t: [int(x) for x in t.split(",") if x],
+                    default=list(PAPER_CONVERGENCE_ROWS),
+                    help="cells per side (both scales) of the stationary convergence rows, comma-separated")
     ap.add_argument("--gm-steps", type=int, default=5,
                     help="steps of the general-map leg (Jacobian tables, uneven batch; 0: skip)")
     ap.add_argument("--fp-steps", type=int, default=3,
@@ -847,7 +885,7 @@ def main():
         if not args.no_cpu_baseline:
             out["stationary"]["case_B_81x4225"]["cpu_oracle"] = stationary_oracle_time()
         _log("stationary convergence leg ...")
-        out["stationary"]["convergence"] = stationary_convergence_leg()
+        out["stationary"]["convergence"] = stationary_convergence_leg(tuple(args.st_conv_sizes))
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, a, th, lv)

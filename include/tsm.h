@@ -170,9 +170,12 @@ tsm_status tsm_create(const tsm_params* p, void* stream, tsm_ctx** out);
 /* Reference mesh of every instance (Section 3.1, approximation: the
  * partition K_h of the reference domain Z and its Q1 space V_h; Section
  * 3.3: one micro system per macro degree of freedom, so instance i belongs
- * to macro node i of the partition B_H): micro_cells[i] = N_i in 2..64
+ * to macro node i of the partition B_H): micro_cells[i] = N_i in 2..256
  * cells per side of K_h (host pointer, n_inst entries, read during the call;
- * n_inst == (N_M+1)^2, else EINVAL; a size outside 2..64: EINVAL).
+ * n_inst == (N_M+1)^2, else EINVAL; a size outside 2..256: EINVAL).  Sizes
+ * 16, 32 and 64 run the packed kernels; sizes above 64 run one workgroup
+ * per instance in FP64 (either precision mode) and are not refined by the
+ * indicator calls below.
  * Allocates the ragged buffers (ENOMEM if that fails).  Invalidates any
  * deformation and state. */
 tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_t n_inst);
@@ -318,8 +321,9 @@ void tsm_destroy(tsm_ctx* c);
  * instance i's reference mesh of (h/12) int_e [[ d (C grad_z v_i) . nu_e ]]^2,
  * the jump of the pulled-back flux (C = K K^T J, Section 3.1) integrated with
  * the 2-point rule.  Needs set_state; ESTATE for a geometry given by Jacobian
- * tables (C is needed at points the tables do not hold) and for a
- * stationary context; EINVAL unless n == n_inst. */
+ * tables (C is needed at points the tables do not hold), for a
+ * stationary context and for meshes above 64 cells per side; EINVAL unless
+ * n == n_inst. */
 tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out, int64_t n);
 
 /* Bulk marking over the global functional sum_i eta2[i]: the fewest

@@ -80,6 +80,11 @@ struct tsm_ctx {
     double* Mw = nullptr;          // M_i w_i (packed step solves start from v0)
     // b at the boundary nodes, compact (kBndStride per instance, bnd_node order)
     double* bcomp = nullptr;
+    // instances above kMaxLevel cells per side: the large-mesh kernel's
+    // vectors (r, p, q: three ragged vectors per set; one set per stream
+    // that runs micro solves side by side)
+    double* lg_ws = nullptr;
+    int lg_sets = 0;
     float *S32 = nullptr, *Slo = nullptr;
     // symmetric upper-half planes [kSym][n] of S, K = S - M/dt, M (FP32), S split in FP32
     double *Ss64 = nullptr, *Ks64 = nullptr;
@@ -148,7 +153,8 @@ struct tsm_ctx {
         dfree(Ss64); dfree(Ks64); dfree(Ss32); dfree(Sslo);
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(Mw); dfree(v0); dfree(S32); dfree(Slo);
-        dfree(bcomp);
+        dfree(bcomp); dfree(lg_ws);
+        lg_sets = 0;
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
@@ -206,7 +212,7 @@ namespace {
 // generic launch per remaining slot class.  setup: FP64 whatever the precision.
 // On stream st with the persistent work counter queue (the context's own,
 // or another for launches that run beside it).
-tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st, int32_t* queue) {
+tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st, int32_t* queue, int set = 0) {
     const bool refine = c->prm.precision == TSM_FP32_REFINE && !setup;
     // the packed refinement kernels evaluate the operator from the
     // amplitudes (time-step form: right-hand side M x0/dt with M w) unless
@@ -253,6 +259,13 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
         MicroArgs a = base;
         a.n_tasks = g.count;
         a.order = c->order + g.first;
+        if (g.slots < 0) {
+            if (set >= c->lg_sets) return c->fail(TSM_EINVAL, "no large-mesh workspace for this stream");
+            a.ws = c->lg_ws + (int64_t)set * 3 * c->total;
+            a.ws_stride = c->total;
+            HIPCHK(launch_micro_large(a, st));
+            continue;
+        }
         int mode = g.mode;
         if (setup) mode = (g.slots <= 5 && !(c->prm.flags & TSM_FLAG_STENCIL_STREAM)) ? 0 : 1;
         const int NP = g.max_level + 1;
@@ -314,7 +327,8 @@ tsm_status plan_tasks(tsm_ctx* c) {
     const bool stream_all = (c->prm.flags & TSM_FLAG_STENCIL_STREAM) != 0;
     for (; t < n_inst; ++t) {
         const int lvl = c->level_h[c->order_h[t]];
-        const int sl = slots_for((lvl + 1) * (lvl + 1));
+        // slots -1: above kMaxLevel, the large-mesh kernel
+        const int sl = lvl > kMaxLevel ? -1 : slots_for((lvl + 1) * (lvl + 1));
         if (c->groups.empty() || c->groups.back().slots != sl) {
             Group g;
             g.first = (int)t;
@@ -606,9 +620,9 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     if (n_inst != expect)
         return c->fail(TSM_EINVAL, "n_inst must equal (macro_cells+1)^2 = " + std::to_string(expect));
     for (int64_t i = 0; i < n_inst; ++i)
-        if (micro_cells[i] < kMinLevel || micro_cells[i] > kMaxLevel)
+        if (micro_cells[i] < kMinLevel || micro_cells[i] > kMaxMesh)
             return c->fail(TSM_EINVAL, "micro_cells[" + std::to_string(i) + "] = " + std::to_string(micro_cells[i]) +
-                                           " outside 2..64");
+                                           " outside 2..256");
     HIPCHK(hipStreamSynchronize(c->stream));
     c->free_mesh();
     c->free_macro();
@@ -619,12 +633,12 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     c->total = c->off_h[n_inst];
 
     // level tables
-    std::vector<int32_t> toff(kMaxLevel + 1, 0);
+    std::vector<int32_t> toff(kMaxMesh + 1, 0);
     std::vector<double> ty, ts, tc;
-    std::vector<bool> present(kMaxLevel + 1, false);
+    std::vector<bool> present(kMaxMesh + 1, false);
     for (int32_t l : c->level_h) present[l] = true;
     const double g0 = 0.5 - 0.5 / std::sqrt(3.0), g1 = 0.5 + 0.5 / std::sqrt(3.0);
-    for (int N = kMinLevel; N <= kMaxLevel; ++N) {
+    for (int N = kMinLevel; N <= kMaxMesh; ++N) {
         if (!present[N]) continue;
         toff[N] = (int32_t)ty.size();
         const double h = 2.0 / N;
@@ -658,6 +672,11 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPCHK(hipMemset(c->Sslo + pe, 0, kPlanePad * sizeof(float)));
     HIPALLOC(c->b, tot); HIPALLOC(c->w, tot); HIPALLOC(c->v0, tot); HIPALLOC(c->Mw, tot);
     HIPALLOC(c->bcomp, ni * kBndStride);
+    if (*std::max_element(c->level_h.begin(), c->level_h.end()) > kMaxLevel) {
+        // the three micro solves of a stationary context run side by side
+        c->lg_sets = c->stationary ? 3 : 1;
+        HIPALLOC(c->lg_ws, (size_t)c->lg_sets * 3 * tot);
+    }
     if (c->stationary) {
         HIPALLOC(c->st_bO, tot); HIPALLOC(c->st_lenO, ni);
         HIPALLOC(c->st_zI, tot); HIPALLOC(c->st_zO, tot); HIPALLOC(c->st_z0, tot);
@@ -680,7 +699,7 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
         HIPALLOC(c->st_Fv, tot); HIPALLOC(c->st_GI, ni); HIPALLOC(c->st_GO, ni);
         HIPALLOC(c->st_Fu, ni); HIPALLOC(c->st_Fw, ni); HIPALLOC(c->st_uDn, ni);
     }
-    HIPALLOC(c->tab_off, kMaxLevel + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
+    HIPALLOC(c->tab_off, kMaxMesh + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
     HIPALLOC(c->tab_c, tc.size());
     HIPCHK(hipMemcpy(c->level, c->level_h.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->offsets, c->off_h.data(), (ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -1380,6 +1399,7 @@ tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out, int64_t n) {
     if (c->stationary) return c->fail(TSM_ESTATE, "stationary context: no time-stepped micro state");
     if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
     if (c->geom_tables) return c->fail(TSM_ESTATE, "indicator needs the amplitude geometry (not Jacobian tables)");
+    if (c->lg_sets > 0) return c->fail(TSM_ESTATE, "indicator: meshes above 64 cells per side are not refined");
     IndicatorArgs a{};
     a.n_inst = (int)c->n_inst;
     a.level = c->level;
@@ -1615,7 +1635,7 @@ tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, int64_
         ma.bx_out = bx[q];
         ma.iters_out = c->st_iters + q * ni;
         ma.sweeps_out = c->st_sweeps + q * ni;
-        const tsm_status st = enqueue_micro(c, ma, true, strm[q], queue[q]);
+        const tsm_status st = enqueue_micro(c, ma, true, strm[q], queue[q], q);
         if (st != TSM_OK) {
             (void)hipDeviceSynchronize();   // nothing left running on the side streams
             return st;

@@ -386,6 +386,115 @@ hipError_t launch_mode(const MicroArgs& a, int slots, int grid, size_t lds, hipS
     }
 }
 
+// ------------------------------------------------- meshes above 64 cells
+// Reference meshes finer than the register- and LDS-resident kernels hold
+// (64 < N <= 256, up to 66049 nodes): one 1024-lane workgroup per instance,
+// every vector in global memory -- x in X_out, the residual r, the search
+// direction p and the product q = S p in a workspace at the instance's
+// ragged offset (ws, ws + ws_stride, ws + 2 ws_stride) -- and the full FP64
+// rows streamed every iteration.  FP64 Jacobi-PCG to rtol in either
+// precision mode; the starting point and right-hand side are those of the
+// generic kernels (x0 = X0 + coef w, b = M x0 / dt or the given
+// right-hand side).  A node reads its neighbours at indices clamped into the
+// instance: the coefficient of a missing neighbour is zero.
+constexpr int NTL = 1024;
+constexpr int NWL = NTL / kWave;
+
+__global__ __launch_bounds__(NTL) void micro_large_kernel(MicroArgs A) {
+    __shared__ double r1[2][1][NWL];
+    __shared__ double r3[2][3][NWL];
+    BlockReducer<NWL, 1, double> red1(r1);
+    BlockReducer<NWL, 3, double> red3(r3);
+    const int inst = A.order[blockIdx.x];
+    const Geo g = instance_geo(A, inst);
+    const int tid = threadIdx.x;
+    const double* __restrict__ S = A.S64 + kStencil * g.off;
+    const double* __restrict__ M = A.M64 + kStencil * g.off;
+    double* x = A.X_out + g.off;
+    double* r = A.ws + g.off;
+    double* p = A.ws + A.ws_stride + g.off;
+    double* q = A.ws + 2 * A.ws_stride + g.off;
+    auto nb = [&](int j, int k) {
+        const int jj = j + g.dj[k];
+        return jj < 0 ? 0 : (jj >= g.n ? g.n - 1 : jj);
+    };
+    // x0 (in place when X_out is X0: each node is read and written by its lane)
+    const double cf = (A.coef != nullptr) ? A.coef[inst] : 0.0;
+    for (int j = tid; j < g.n; j += NTL)
+        x[j] = A.zero_init ? 0.0 : A.X0[g.off + j] + cf * A.w[g.off + j];
+    __syncthreads();
+    // b, r = b - S x0, p = D^-1 r; b^T-norm, ||r||^2, (r, D^-1 r)
+    const double bc = (A.rhs_vec != nullptr && A.rhs_bcoef != nullptr) ? A.rhs_bscale * A.rhs_bcoef[inst] : 0.0;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int j = tid; j < g.n; j += NTL) {
+        double bj;
+        if (A.rhs_vec != nullptr) {
+            bj = A.rhs_scale * A.rhs_vec[g.off + j];
+            if (A.rhs_bcoef != nullptr) bj += bc * A.b[g.off + j];
+        } else {
+            double m = 0.0;
+#pragma unroll
+            for (int k = 0; k < kStencil; ++k) m += M[(int64_t)k * g.n + j] * x[nb(j, k)];
+            bj = m * A.inv_dt;
+        }
+        double sx = 0.0;
+#pragma unroll
+        for (int k = 0; k < kStencil; ++k) sx += S[(int64_t)k * g.n + j] * x[nb(j, k)];
+        const double rj = bj - sx;
+        const double zj = rj / S[4 * (int64_t)g.n + j];
+        r[j] = rj;
+        p[j] = zj;
+        acc[0] += bj * bj;
+        acc[1] += rj * rj;
+        acc[2] += rj * zj;
+    }
+    red3.sum(acc);     // (its barrier also orders the p stores before the first product)
+    const double tol2 = A.rtol * A.rtol * acc[0];
+    double rr = acc[1], rz = acc[2];
+    bool conv = rr <= tol2;
+    int it = 0;
+    while (!conv && it < A.max_iter) {
+        double pq[1] = {0.0};
+        for (int j = tid; j < g.n; j += NTL) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < kStencil; ++k) t += S[(int64_t)k * g.n + j] * p[nb(j, k)];
+            q[j] = t;
+            pq[0] += p[j] * t;
+        }
+        red1.sum(pq);
+        const double alpha = rz / pq[0];
+        double a2[3] = {0.0, 0.0, 0.0};
+        for (int j = tid; j < g.n; j += NTL) {
+            x[j] += alpha * p[j];
+            const double rj = r[j] - alpha * q[j];
+            r[j] = rj;
+            a2[0] += rj * rj / S[4 * (int64_t)g.n + j];
+            a2[1] += rj * rj;
+        }
+        red3.sum(a2);
+        ++it;
+        rr = a2[1];
+        if (rr <= tol2) { conv = true; break; }
+        const double beta = a2[0] / rz;
+        rz = a2[0];
+        // every lane's p reads of this iteration are done (the reductions'
+        // barriers): p may be overwritten
+        for (int j = tid; j < g.n; j += NTL) p[j] = r[j] / S[4 * (int64_t)g.n + j] + beta * p[j];
+        __syncthreads();
+    }
+    double bx[1] = {0.0};
+    for (int j = tid; j < g.n; j += NTL) bx[0] += A.b[g.off + j] * x[j];
+    red1.sum(bx);
+    if (tid == 0) {
+        if (A.bx_out) A.bx_out[inst] = bx[0];
+        if (A.iters_out) A.iters_out[inst] = it;
+        if (A.sweeps_out) A.sweeps_out[inst] = 1;
+        if (A.res_out) A.res_out[inst] = sqrt(rr);
+        if (!conv) atomicAdd(A.nonconv, 1);
+    }
+}
+
 // y = S x for every instance (FP64 stencil), one workgroup per instance.
 __global__ __launch_bounds__(NT) void apply_kernel(const int32_t* level, const int64_t* offsets,
                                                    const double* S64, const double* x, double* y) {
@@ -446,6 +555,7 @@ __global__ void bnd_gather_kernel(int n_inst, const int32_t* level, const int64_
     const int inst = blockIdx.x;
     if (inst >= n_inst) return;
     const int N = level[inst];
+    if (N > kMaxLevel) return;              // only the packed sizes (<= 64) use the compact copy
     for (int k = threadIdx.x; k < 4 * N; k += blockDim.x)
         bc[(int64_t)inst * kBndStride + k] = b[offsets[inst] + bnd_node(N, k)];
 }
@@ -466,6 +576,13 @@ hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_
         case 3: return launch_mode<3>(a, slots, grid, lds, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_micro_large(const MicroArgs& a, hipStream_t s) {
+    if (a.n_tasks <= 0) return hipSuccess;
+    if (a.ws == nullptr) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(micro_large_kernel, dim3(a.n_tasks), dim3(NTL), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_apply(int n_inst, const int32_t* level, const int64_t* offsets,

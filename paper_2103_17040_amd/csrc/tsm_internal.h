@@ -12,7 +12,9 @@ namespace tsm {
 constexpr int kMicroThreads = 256;        // lanes per micro workgroup (4 waves), generic kernels
 constexpr int kPackThreads = 768;         // lanes per packed workgroup (12 waves)
 constexpr int kWave = 64;
-constexpr int kMaxLevel = 64;             // largest micro mesh N (cells per side)
+constexpr int kMaxLevel = 64;             // largest micro mesh N of the packed, register- and
+                                          // LDS-resident kernels, the indicator and refinement
+constexpr int kMaxMesh = 256;             // largest micro mesh N (cells per side) of a batch
 constexpr int kMinLevel = 2;
 constexpr int kStencil = 9;               // 9-point Q1 stencil, k = (dj2+1)*3 + (dj1+1)
 // The operators are symmetric, so the packed kernels read only the upper half
@@ -65,7 +67,7 @@ __host__ __device__ inline float inner_tol2(double tol2, double rr, double cap) 
 // s_t = sin(pi y_t)/4 and c_t = pi cos(pi y_t)/4, so the displacement
 // gradient is G = [[c(y1) y2, s(y1)], [s(y2), c(y2) y1]].
 struct Tables {
-    const int32_t* off;   // [kMaxLevel + 1]
+    const int32_t* off;   // [kMaxMesh + 1]
     const double* y;
     const double* s;
     const double* c;
@@ -163,6 +165,10 @@ struct MicroArgs {
     const double* amp;
     Tables tab;
     double d, kappa;
+    // meshes above kMaxLevel (launch_micro_large): workspace of three ragged
+    // vectors (r, p, q), ws_stride doubles apart
+    double* ws;
+    int64_t ws_stride;
 };
 
 // Packs of instances of one mesh size solved by one kPackThreads-lane workgroup.
@@ -216,6 +222,9 @@ hipError_t launch_assemble(const AssembleArgs& a, hipStream_t s);
 // same gather for maps given by their Jacobian tables (a.Fcell, a.Fbnd)
 hipError_t launch_assemble_tables(const AssembleArgs& a, hipStream_t s);
 hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_t lds_bytes, hipStream_t s);
+// instances with more than kMaxLevel cells per side: one 1024-lane workgroup
+// per task, vectors in the workspace a.ws (FP64 in either precision mode)
+hipError_t launch_micro_large(const MicroArgs& a, hipStream_t s);
 // packs of one mesh size (16, 32 or 64); mode 1 FP64, 2 refinement, 3 refinement
 // with the operator evaluated matrix-free from the amplitudes (time-step form only)
 hipError_t launch_packed(const MicroArgs& a, const PackList& p, int level, int mode, int grid, hipStream_t s);

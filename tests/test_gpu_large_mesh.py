@@ -1,0 +1,132 @@
+"""Micro meshes above 64 cells per side (up to 256 per side): one
+workgroup per instance in FP64, beside the packed sizes, against the
+oracle -- time steps in both precision modes, the adjoint gradient and the
+stationary three-field solve (Section 3.1 discretisation; Section 4.2
+runs micro meshes of 91 and 128 cells per side)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import banner, gpu_for, oracle_for, rel, run_both
+from oracle import adjoint
+from oracle import stationary as st
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10
+TOL_REFINE = 1e-8
+
+
+def _levels(NM, interior, rest, seed):
+    """Mesh sizes with the given ones on the interior macro nodes (where the
+    micro solutions couple back) and the others drawn from rest."""
+    n = (NM + 1) ** 2
+    rng = np.random.default_rng(seed)
+    lv = rng.choice(np.asarray(rest), n).astype(np.int32)
+    inner = [i for i in range(n) if 0 < i % (NM + 1) < NM and 0 < i // (NM + 1) < NM]
+    for k, i in enumerate(inner):
+        lv[i] = interior[k % len(interior)]
+    return lv
+
+
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, TOL_FP64), ("fp32_refine", 1e-10, TOL_REFINE)])
+def test_time_steps_large_meshes_beside_packed(precision, rtol, tol):
+    NM = 3
+    lv = _levels(NM, [256, 128, 91, 64], [16, 32, 65, 100, 128], 4)
+    rng = np.random.default_rng(8)
+    a = rng.uniform(-0.3, 0.3, lv.size)
+    th = rng.uniform(0.0, np.pi / 8, lv.size)
+    u0 = W.initial_macro(NM) * (1.0 + 0.3 * rng.standard_normal(lv.size))
+    v0 = np.zeros(int(W.offsets(lv)[-1]))
+    ref, out, _ = run_both(NM, lv, a, th, 0.01, 4, u0, v0, precision=precision, rtol=rtol,
+                           gpu_kw=dict(max_iter=5000))
+    for k in ("u", "F", "v"):
+        e = rel(out[k], ref[k])
+        banner(f"  {k}: rel {e:.2e}")
+        assert e <= tol, k
+    assert out["stats"]["unconverged"] == 0
+
+
+def test_large_mesh_operator_and_setup():
+    NM = 2
+    lv = np.array([91, 128, 256, 100, 200, 65, 128, 91, 16], np.int32)
+    rng = np.random.default_rng(2)
+    a = rng.uniform(-0.3, 0.3, lv.size)
+    th = rng.uniform(0.0, np.pi / 8, lv.size)
+    banner(f"large-mesh operator and set-up levels {lv.tolist()}")
+    ts = oracle_for(NM, lv, a, th, dt=0.005)
+    g = gpu_for(NM, lv, a, th, dt=0.005)
+    try:
+        x = rng.standard_normal(g.n_micro)
+        y = g.apply(x).cpu().numpy()
+        beta, ln, w = (t.cpu().numpy() for t in g.setup())
+    finally:
+        g.close()
+    for i, I in enumerate(ts.inst):
+        sl = slice(ts.offsets[i], ts.offsets[i + 1])
+        assert rel(y[sl], I.S @ x[sl]) <= 1e-14, (i, I.N)
+    assert rel(ln, ts.len) <= 1e-14
+    assert rel(beta, ts.beta) <= 1e-12
+    assert rel(w, np.concatenate([I.w for I in ts.inst])) <= 1e-11
+
+
+def test_gradient_with_large_meshes():
+    NM, steps = 3, 4
+    lv = _levels(NM, [128, 91, 16, 200], [8, 16, 96], 6)
+    rng = np.random.default_rng(9)
+    a = rng.uniform(-0.2, 0.2, lv.size)
+    u0 = W.initial_macro(NM)
+    v0 = np.zeros(int(W.offsets(lv)[-1]))
+    banner(f"adjoint with large meshes levels {lv.tolist()}")
+    ts = oracle_for(NM, lv, a, None, dt=0.01)
+    J_ref, g_ref = adjoint.gradient(ts, u0, v0, steps)
+    g = gpu_for(NM, lv, a, None, dt=0.01, rtol=1e-13, max_iter=5000, checkpoint_every=2)
+    try:
+        g.set_state(u0, v0)
+        J, dJ = g.gradient(steps)
+        dJ = dJ.cpu().numpy()
+    finally:
+        g.close()
+    eJ, eg = abs(J - J_ref) / abs(J_ref), rel(dJ, g_ref)
+    banner(f"  J rel {eJ:.2e} dJ/da rel {eg:.2e}")
+    assert eJ <= 1e-9 and eg <= 1e-9
+
+
+def test_indicator_refuses_large_meshes():
+    from paper_2103_17040_amd import tsm
+    NM = 2
+    lv = np.array([8, 8, 8, 8, 128, 8, 8, 8, 8], np.int32)
+    g = gpu_for(NM, lv, np.zeros(9))
+    try:
+        g.set_state(W.initial_macro(NM), None)
+        with pytest.raises(tsm.TsmError) as e:
+            g.error_indicator()
+        assert e.value.status == tsm.TSM_ESTATE
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("levels", [[91, 128, 16, 64], [128, 256]])
+def test_stationary_large_meshes(levels):
+    from paper_2103_17040_amd import StationarySystem
+    NM = 3
+    n = (NM + 1) ** 2
+    lv = np.asarray([levels[i % len(levels)] for i in range(n)], dtype=np.int32)
+    per, Fc, Fb = W.jacobian_tables(lv, W.stationary_case_jacobian("B"),
+                                    [tuple(x) for x in W.stationary_macro_nodes(NM)])
+    phys = dict(Dv=1.0, Dw=0.1, kappa1=0.5, kappa2=1.0, kappa3=0.25, kappa4=1.0)
+    src = dict(fu=0.3, fv=1.0, fw=-0.2)
+    banner(f"stationary Case B NM={NM} levels={levels}")
+    parts, dirichlet = (0, 0, 1, 2), (0, 0, 1, 0)
+    g = StationarySystem(NM, lv, jacobians=(Fc, Fb), parts=parts, dirichlet=dirichlet, u_dirichlet=1.0,
+                         rtol=1e-14, **src, **phys)
+    try:
+        u, w, v = (t.cpu().numpy() for t in g.solve())
+        stats = g.stats()
+    finally:
+        g.close()
+    prm = st.StationaryParams(macro_cells=NM, parts=parts, dirichlet=tuple(bool(d) for d in dirichlet), **phys)
+    ref = st.solve(prm, lv, per, st.constant_data(u_dirichlet=1.0, **src))
+    eu, ew, ev = rel(u, ref["u"]), rel(w, ref["w"]), rel(v, np.concatenate(ref["v"]))
+    banner(f"  rel u {eu:.2e} w {ew:.2e} v {ev:.2e} micro iters {stats['micro_iters_max']}")
+    assert eu <= TOL_FP64 and ew <= TOL_FP64 and ev <= TOL_FP64

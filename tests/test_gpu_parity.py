@@ -203,7 +203,7 @@ def test_error_paths():
         gpu_for(NM, lv, bad)
     assert e.value.status == tsm.TSM_EINVAL
     with pytest.raises(tsm.TsmError) as e:
-        gpu_for(NM, np.full(9, 65, np.int32), np.zeros(9))
+        gpu_for(NM, np.full(9, 257, np.int32), np.zeros(9))
     assert e.value.status == tsm.TSM_EINVAL
     g = gpu_for(NM, lv, np.full(9, 0.2), max_iter=2)
     try:

@@ -192,3 +192,30 @@ def test_manufactured_data_match_the_printed_normals(x):
     v = x1 + x2 + y0 * y1 * (1 - y1)
     g1 = printed[0][2]
     assert np.max(np.abs(d2.gv(None, x1, x2, t, -one) - g1(y0, y1, v))) > 1e-2
+
+
+def test_manufactured_data_and_errors_in_worker_processes():
+    """The worker-process forms used on the finest convergence rows give the
+    serial results: data bit for bit, error integrals to rounding."""
+    from workloads import manufactured as MF
+    phys = dict(Dv=1.0, Dw=0.5, kappa1=0.5, kappa2=1.0, kappa3=0.25, kappa4=1.0)
+    parts = (0, 0, 1, 2)
+    NM = 3
+    levels = np.array([4, 6, 5, 4] * 4, dtype=np.int32)
+    prm = st.StationaryParams(macro_cells=NM, **phys)
+    serial = MF.data_at_points(manufactured(prm, MF.U_MANU, MF.V_MANU, MF.W_MANU, ZETA_MANU), NM, levels, parts)
+    par = MF.manufactured_data_at_points(phys, parts, NM, levels, workers=2)
+    assert serial.keys() == par.keys()
+    for k in serial:
+        assert np.array_equal(serial[k], par[k]), k
+    rng = np.random.default_rng(4)
+    N = 4
+    v_h = [rng.standard_normal((N + 1) ** 2) for _ in range((NM + 1) ** 2)]
+    u_h, w_h = rng.standard_normal((NM + 1) ** 2), rng.standard_normal((NM + 1) ** 2)
+    e1 = MF.convergence_errors(NM, N, u_h, w_h, v_h, prm, workers=1)
+    e2 = MF.convergence_errors(NM, N, u_h, w_h, v_h, prm, workers=2)
+    assert np.allclose(e1, e2, rtol=1e-13, atol=0.0)
+    # the constant Jacobian of the manufactured map is the one the tables hold
+    F = MF.constant_map_jacobian(ZETA_MANU)
+    assert np.array_equal(F, np.array([[14 / 25, -27 / 125], [-3 / 25, 6 / 25]]))
+    assert MF.constant_map_jacobian((Z1 * Z2, Z2)) is None

@@ -137,6 +137,15 @@ def manufactured(prm, u, v, w, zeta) -> Data:
         gw=lambda x1, x2, n: _bc(dw[0](x1, x2), x1) * n[0] + _bc(dw[1](x1, x2), x1) * n[1])
 
 
+def constant_map_jacobian(zeta):
+    """D_z zeta as a 2 x 2 float array when it is constant (in x and z),
+    else None."""
+    F = map_jacobian(zeta)
+    if any(e.free_symbols for e in F):
+        return None
+    return np.array(F.evalf(), dtype=float)
+
+
 def map_tables(NM, levels, zeta):
     """Jacobian tables of the map zeta(x, z) at every instance (jacobian_tables layout)."""
     Fn = sy.lambdify((X1, X2, Z1, Z2), map_jacobian(zeta), "numpy")
@@ -150,24 +159,90 @@ def map_tables(NM, levels, zeta):
     return jacobian_tables(np.asarray(levels), fn, [tuple(x) for x in stationary_macro_nodes(NM)])
 
 
+def _micro_data(data: Data, xs, parts, ks, levels):
+    """fv at the cell points and gv at the boundary points of instances ks."""
+    fv, gv = [], []
+    for k, N in zip(ks, levels):
+        (c1, c2), (b1, b2) = table_points(int(N))
+        x1, x2 = float(xs[k, 0]), float(xs[k, 1])
+        fv.append(data.fv(x1, x2, c1, c2).ravel())
+        gv.append(np.stack([data.gv(parts[s], x1, x2, b1[s], b2[s]) for s in range(4)]).ravel())
+    return np.concatenate(fv), np.concatenate(gv)
+
+
+def _macro_data(data: Data, NM, xs):
+    (c1, c2), (b1, b2) = table_points(int(NM))     # the macro mesh is [-1,1]^2 as well
+    return {"fu_cell": data.fu(c1, c2).ravel(), "fw_cell": data.fw(c1, c2).ravel(),
+            "gu_bnd": np.stack([data.gu(b1[s], b2[s], SIDE_NORMALS[s]) for s in range(4)]).ravel(),
+            "gw_bnd": np.stack([data.gw(b1[s], b2[s], SIDE_NORMALS[s]) for s in range(4)]).ravel(),
+            "uD": data.uD(xs[:, 0], xs[:, 1]).ravel()}
+
+
 def data_at_points(data: Data, NM, levels, parts):
     """The data at the quadrature points in the layouts of
     tsm_stationary_set_data: fv_cell, gv_bnd, fu_cell, fw_cell, gu_bnd,
     gw_bnd, uD (flat float64 arrays)."""
     xs = stationary_macro_nodes(NM)
-    fv, gv = [], []
-    for k, N in enumerate(np.asarray(levels).tolist()):
-        (c1, c2), (b1, b2) = table_points(int(N))
-        x1, x2 = float(xs[k, 0]), float(xs[k, 1])
-        fv.append(data.fv(x1, x2, c1, c2).ravel())
-        gv.append(np.stack([data.gv(parts[s], x1, x2, b1[s], b2[s]) for s in range(4)]).ravel())
-    (c1, c2), (b1, b2) = table_points(int(NM))     # the macro mesh is [-1,1]^2 as well
-    out = {"fv_cell": np.concatenate(fv), "gv_bnd": np.concatenate(gv),
-           "fu_cell": data.fu(c1, c2).ravel(), "fw_cell": data.fw(c1, c2).ravel(),
-           "gu_bnd": np.stack([data.gu(b1[s], b2[s], SIDE_NORMALS[s]) for s in range(4)]).ravel(),
-           "gw_bnd": np.stack([data.gw(b1[s], b2[s], SIDE_NORMALS[s]) for s in range(4)]).ravel(),
-           "uD": data.uD(xs[:, 0], xs[:, 1]).ravel()}
+    lv = np.asarray(levels).tolist()
+    fv, gv = _micro_data(data, xs, parts, range(len(lv)), lv)
+    out = {"fv_cell": fv, "gv_bnd": gv, **_macro_data(data, NM, xs)}
     return {k: np.array(v, dtype=np.float64) for k, v in out.items()}     # writable copies
+
+
+# ---------------------------------------------------------------------------
+# the same in worker processes (the finest rows of Section 4.2 have 16641
+# instances of 16641 DoFs each): each worker derives the data once from the
+# expressions and takes instances in chunks; results come back in order
+# ---------------------------------------------------------------------------
+
+_WORKER = {}
+
+
+def _chunks(n, size):
+    return [range(k, min(n, k + size)) for k in range(0, n, size)]
+
+
+def _pool(workers, init, args):
+    """Spawned worker processes (a worker that dies raises in the parent
+    instead of leaving it waiting)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    return ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"), initializer=init, initargs=args)
+
+
+def _init_data(phys, parts, exprs, NM):
+    import types
+    prm = types.SimpleNamespace(parts=tuple(parts), **phys)
+    _WORKER["data"] = manufactured(prm, *exprs)
+    _WORKER["xs"] = stationary_macro_nodes(NM)
+    _WORKER["parts"] = tuple(parts)
+
+
+def _data_job(job):
+    ks, levels = job
+    return _micro_data(_WORKER["data"], _WORKER["xs"], _WORKER["parts"], ks, levels)
+
+
+def manufactured_data_at_points(phys, parts, NM, levels, workers=1, u=U_MANU, v=V_MANU, w=W_MANU, zeta=ZETA_MANU):
+    """data_at_points of the manufactured data of (u, v, w, zeta) with the
+    physical parameters phys (Dv, Dw, kappa1..kappa4), the micro part on
+    `workers` processes."""
+    import types
+    prm = types.SimpleNamespace(parts=tuple(parts), **phys)
+    data = manufactured(prm, u, v, w, zeta)
+    xs = stationary_macro_nodes(NM)
+    lv = np.asarray(levels).tolist()
+    if workers <= 1:
+        fv, gv = _micro_data(data, xs, parts, range(len(lv)), lv)
+    else:
+        jobs = [(list(r), [lv[k] for k in r]) for r in _chunks(len(lv), 64)]
+        with _pool(workers, _init_data, (dict(phys), tuple(parts), (u, v, w, zeta), NM)) as pool:
+            parts_out = list(pool.map(_data_job, jobs))
+        fv = np.concatenate([a for a, _ in parts_out])
+        gv = np.concatenate([b for _, b in parts_out])
+        del parts_out
+    out = {"fv_cell": fv, "gv_bnd": gv, **_macro_data(data, NM, xs)}
+    return {k: np.ascontiguousarray(a, dtype=np.float64) for k, a in out.items()}
 
 
 # ---------------------------------------------------------------------------
@@ -209,33 +284,54 @@ def q1_errors(N, nodal, exact, grad_exact, F=None):
     return e0, eg
 
 
-def convergence_errors(NM, N, u_h, w_h, v_h, prm, u=U_MANU, v=V_MANU, w=W_MANU, zeta=ZETA_MANU):
+def convergence_errors(NM, N, u_h, w_h, v_h, prm, u=U_MANU, v=V_MANU, w=W_MANU, zeta=ZETA_MANU, workers=1):
     """(e_uw, e_uw_grad, e_v, e_v_grad) of Section 4.2 for discrete u_h, w_h
     (nodal, (NM+1)^2) and v_h (one array per instance, all N x N) with a map
     whose D_z zeta is constant; the x-integral of the micro errors is taken
-    at the nodes with the weights of the hats (int xi_k)."""
+    at the nodes with the weights of the hats (int xi_k), over `workers`
+    processes."""
     uf, wf = sy.lambdify((X1, X2), u, "numpy"), sy.lambdify((X1, X2), w, "numpy")
     gu = [sy.lambdify((X1, X2), sy.diff(u, s), "numpy") for s in (X1, X2)]
     gw = [sy.lambdify((X1, X2), sy.diff(w, s), "numpy") for s in (X1, X2)]
     a0, a1 = q1_errors(NM, u_h, lambda s, t: _bc(uf(s, t), s), lambda s, t: (_bc(gu[0](s, t), s), _bc(gu[1](s, t), s)))
     b0, b1 = q1_errors(NM, w_h, lambda s, t: _bc(wf(s, t), s), lambda s, t: (_bc(gw[0](s, t), s), _bc(gw[1](s, t), s)))
-    F = np.array(map_jacobian(zeta).evalf(), dtype=float)
-    vy = sy.lambdify((X1, X2, Y1, Y2), v, "numpy")
-    gvy = [sy.lambdify((X1, X2, Y1, Y2), sy.diff(v, s), "numpy") for s in (Y1, Y2)]
-    zm = sy.lambdify((X1, X2, Z1, Z2), zeta, "numpy")
-    xs = stationary_macro_nodes(NM)
+    if workers <= 1:
+        _init_errors(NM, N, v, zeta)
+        v0, v1 = _error_job((list(range(len(v_h))), v_h))
+    else:
+        jobs = [(list(r), [v_h[k] for k in r]) for r in _chunks(len(v_h), 64)]
+        with _pool(workers, _init_errors, (NM, N, v, zeta)) as pool:
+            sums = list(pool.map(_error_job, jobs))
+        v0 = sum(a for a, _ in sums)
+        v1 = sum(b for _, b in sums)
+    return np.sqrt(a0) + np.sqrt(b0), np.sqrt(a1) + np.sqrt(b1), np.sqrt(v0), np.sqrt(v1)
+
+
+def _init_errors(NM, N, v, zeta):
     k1 = np.arange(NM + 1)
     cells = ((k1 > 0).astype(int) + (k1 < NM))
-    L = (0.25 * (2.0 / NM) ** 2) * np.outer(cells, cells).ravel()
+    _WORKER.update(
+        N=N, F=np.array(map_jacobian(zeta).evalf(), dtype=float),
+        vy=sy.lambdify((X1, X2, Y1, Y2), v, "numpy"),
+        gvy=[sy.lambdify((X1, X2, Y1, Y2), sy.diff(v, s), "numpy") for s in (Y1, Y2)],
+        zm=sy.lambdify((X1, X2, Z1, Z2), zeta, "numpy"), xs=stationary_macro_nodes(NM),
+        L=(0.25 * (2.0 / NM) ** 2) * np.outer(cells, cells).ravel())
+
+
+def _error_job(job):
+    """(sum_k L_k int e_k^2, sum_k L_k int |grad e_k|^2) over instances ks."""
+    ks, v_h = job
+    c = _WORKER
+    vy, gvy, zm = c["vy"], c["gvy"], c["zm"]
     v0 = v1 = 0.0
-    for k in range(len(v_h)):
-        x1, x2 = float(xs[k, 0]), float(xs[k, 1])
+    for k, vk in zip(ks, v_h):
+        x1, x2 = float(c["xs"][k, 0]), float(c["xs"][k, 1])
         ex = lambda s, t: _bc(vy(x1, x2, *zm(x1, x2, s, t)), s)
         gex = lambda s, t: tuple(_bc(g(x1, x2, *zm(x1, x2, s, t)), s) for g in gvy)
-        c0, c1 = q1_errors(N, v_h[k], ex, gex, F=F)
-        v0 += L[k] * c0
-        v1 += L[k] * c1
-    return np.sqrt(a0) + np.sqrt(b0), np.sqrt(a1) + np.sqrt(b1), np.sqrt(v0), np.sqrt(v1)
+        c0, c1 = q1_errors(c["N"], vk, ex, gex, F=c["F"])
+        v0 += c["L"][k] * c0
+        v1 += c["L"][k] * c1
+    return v0, v1
 
 
 def orders(dofs, errs):
