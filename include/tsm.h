@@ -81,6 +81,11 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
                                             amplitudes at the start of every solve (Section 3.1:
                                             J and K K^T J at the quadrature points).  Geometry from
                                             Jacobian tables always uses the assembled operator. */
+#define TSM_FLAG_MACRO_PCG  (1ull << 10) /* solve the macro system (forward and adjoint) by PCG with
+                                            the sine-basis solve of A_M's tensor part as
+                                            preconditioner even where the sweep would do (it is
+                                            used anyway where the sweep's contraction bound is
+                                            0.5 or more) */
 #define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
                                             HIP events on the context's stream (see tsm_stats) */
 #define TSM_FLAG_FIXED_POINT (1ull << 5) /* tsm_step couples macro and micro solves by the paper's
@@ -132,7 +137,7 @@ typedef struct {
     double iters_mean;
     int32_t sweeps_max;          /* refinement sweeps of the last step */
     int32_t unconverged;         /* instances that missed rtol in the last step */
-    int32_t macro_sweeps;        /* tensor-preconditioned macro sweeps per solve */
+    int32_t macro_sweeps;        /* tensor-preconditioned macro sweeps per solve (0 under PCG) */
     double macro_contraction;    /* bound on the macro sweep contraction factor */
     double setup_ms;             /* last set_deformation */
     double step_ms;              /* last tsm_step call, between events on the stream */
@@ -146,6 +151,7 @@ typedef struct {
                                     (1 + the inner solves of an instance) */
     int32_t fp_iters_last;       /* TSM_FLAG_FIXED_POINT: coupling iterations of the last step */
     int32_t fp_iters_max;        /* ... and the most over the steps of the last tsm_step call */
+    int32_t macro_pcg_iters;     /* macro PCG iterations per solve when PCG is used, else 0 */
 } tsm_stats;
 
 typedef struct tsm_ctx tsm_ctx;

@@ -96,6 +96,13 @@ struct tsm_ctx {
     double *rhs = nullptr, *R = nullptr, *T1 = nullptr, *T2 = nullptr, *Q = nullptr, *lam = nullptr;
     int macro_sweeps = 2;
     double rho = 0.0;
+    // macro PCG (sine-basis preconditioner): z, p (full grid), q, (r, z);
+    // iteration count from the condition bound (0: A_M not shown SPD)
+    double *mp_z = nullptr, *mp_p = nullptr, *mp_q = nullptr, *mp_s = nullptr;
+    int macro_pcg_iters = 0;
+    bool macro_pcg() const {
+        return macro_pcg_iters > 0 && (rho >= 0.5 || (prm.flags & TSM_FLAG_MACRO_PCG));
+    }
     // alternating (fixed-point) coupling: macro operator with beta = kappa p
     // (eigenvalues lam_fp), full micro state vf, rhs M v^n, previous macro
     // state, per-instance residual norms, the residual sum (2 values)
@@ -169,6 +176,7 @@ struct tsm_ctx {
     }
     void free_macro() {
         dfree(rhs); dfree(R); dfree(T1); dfree(T2); dfree(Q); dfree(lam);
+        dfree(mp_z); dfree(mp_p); dfree(mp_q); dfree(mp_s);
         dfree(lam_fp); dfree(beta_fp); dfree(vf); dfree(rvec); dfree(u_prev); dfree(resn); dfree(fpm);
     }
     void drop_graph() {
@@ -415,7 +423,34 @@ tsm_status enqueue_macro_solve(tsm_ctx* c, double* u, const MacroArgs& m, const 
     return TSM_OK;
 }
 
+// Macro solve of A_M u = rhs in place by PCG with A0^{-1} (sine basis) as
+// preconditioner, a fixed number of iterations (from the condition bound,
+// so the sequence can be captured in a graph).
+tsm_status enqueue_macro_pcg(tsm_ctx* c, double* u) {
+    const MacroArgs m = c->macro_args();
+    const int n = m.n, NM = c->NM;
+    hipStream_t s = c->stream;
+    auto precondition = [&]() -> hipError_t {     // z = A0^{-1} r
+        hipError_t e = launch_gemm(n, c->Q, c->R, c->T1, 0, nullptr, nullptr, NM, s);
+        if (e == hipSuccess) e = launch_gemm(n, c->T1, c->Q, c->T2, 1, c->lam, nullptr, NM, s);
+        if (e == hipSuccess) e = launch_gemm(n, c->Q, c->T2, c->T1, 0, nullptr, nullptr, NM, s);
+        if (e == hipSuccess) e = launch_gemm(n, c->T1, c->Q, c->mp_z, 0, nullptr, nullptr, NM, s);
+        return e;
+    };
+    HIPCHK(launch_macro_residual(m, u, c->rhs, c->R, s));
+    HIPCHK(precondition());
+    HIPCHK(launch_macro_pcg_start(NM, c->R, c->mp_z, c->mp_p, c->mp_s, s));
+    for (int it = 0; it < c->macro_pcg_iters; ++it) {
+        HIPCHK(launch_macro_pcg_step(m, c->mp_p, c->mp_q, c->R, u, c->mp_s, s));
+        if (it + 1 == c->macro_pcg_iters) break;
+        HIPCHK(precondition());
+        HIPCHK(launch_macro_pcg_direction(NM, c->R, c->mp_z, c->mp_p, c->mp_s, s));
+    }
+    return TSM_OK;
+}
+
 tsm_status enqueue_macro_solve(tsm_ctx* c, double* u) {
+    if (c->macro_pcg()) return enqueue_macro_pcg(c, u);
     return enqueue_macro_solve(c, u, c->macro_args(), c->lam, c->macro_sweeps);
 }
 
@@ -719,6 +754,8 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
     HIPALLOC(c->rhs, (size_t)n * n); HIPALLOC(c->R, (size_t)n * n); HIPALLOC(c->T1, (size_t)n * n);
     HIPALLOC(c->T2, (size_t)n * n); HIPALLOC(c->Q, (size_t)n * n); HIPALLOC(c->lam, (size_t)n * n);
     HIPALLOC(c->lam_fp, (size_t)n * n);
+    HIPALLOC(c->mp_z, (size_t)n * n); HIPALLOC(c->mp_q, (size_t)n * n);
+    HIPALLOC(c->mp_p, (size_t)(n + 2) * (n + 2)); HIPALLOC(c->mp_s, 4);
     c->have_mesh = true;
     return TSM_OK;
 }
@@ -859,11 +896,39 @@ tsm_status finish_setup(tsm_ctx* c, std::chrono::steady_clock::time_point t0, Wh
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) Qh[(size_t)i * n + j] = qs * std::sin(M_PI * (double)(i + 1) * (j + 1) / (n + 1));
     c->rho = H * H * 0.5 * (bmax - bmin) / lmin;
-    if (!(c->rho < 0.5))
-        return c->fail(TSM_EINVAL, "macro sweep contraction bound " + std::to_string(c->rho) +
-                                       " >= 0.5: response functionals too heterogeneous for the tensor solver");
+    // PCG bound: with A_M = A(0) + diag(c_k), c_k = -sign H^2 beta_k, and the
+    // preconditioner A(0) + c_ref I, the generalised Rayleigh quotient is
+    // (t + cbar) / (t + c_ref) with t in [tmin, tmax] (the eigenvalues of the
+    // tensor operator A(0)) and cbar in [cmin, cmax]; it is monotone in t, so
+    // its range -- and the condition number -- follow from the end points.
+    {
+        double tmin = 1e300, tmax = -1e300;
+        for (int l2 = 0; l2 < n; ++l2)
+            for (int l1 = 0; l1 < n; ++l1) {
+                const double a0 = lh[(size_t)l2 * n + l1] + sg * bref * H * H;
+                tmin = std::min(tmin, a0);
+                tmax = std::max(tmax, a0);
+            }
+        const double c_lo = std::min(-sg * H * H * bmin, -sg * H * H * bmax);
+        const double c_hi = std::max(-sg * H * H * bmin, -sg * H * H * bmax);
+        const double c_ref = -sg * H * H * bref;
+        c->macro_pcg_iters = 0;
+        if (tmin + c_lo > 0 && tmin + c_ref > 0) {
+            const double lo = std::min((tmin + c_lo) / (tmin + c_ref), (tmax + c_lo) / (tmax + c_ref));
+            const double hi = std::max((tmin + c_hi) / (tmin + c_ref), (tmax + c_hi) / (tmax + c_ref));
+            const double sk = std::sqrt(hi / lo);
+            const double q = (sk - 1.0) / (sk + 1.0);
+            // ||e_k||_A <= 2 q^k ||e_0||_A; a quarter more for finite precision
+            int k = q > 0 ? (int)std::ceil(std::log(0.5e-17) / std::log(q)) : 1;
+            k = std::max(2, k + k / 4 + 2);
+            c->macro_pcg_iters = std::min(k, 400);
+        }
+    }
+    if (!(c->rho < 0.5) && c->macro_pcg_iters == 0)
+        return c->fail(TSM_EINVAL, "macro operator not shown positive definite (sweep contraction bound " +
+                                       std::to_string(c->rho) + ")");
     int sweeps = 2;
-    if (c->rho > 0) sweeps = std::max(2, (int)std::ceil(std::log(1e-17) / std::log(c->rho)));
+    if (c->rho > 0) sweeps = std::max(2, (int)std::ceil(std::log(1e-17) / std::log(std::min(c->rho, 0.5))));
     c->macro_sweeps = std::min(sweeps, 64);
     HIPCHK(hipMemcpy(c->Q, Qh.data(), Qh.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->lam, lh.data(), lh.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -1237,7 +1302,7 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
                                                     TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64)) != 0;
     if (flags & ~(TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_TIMING | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT |
                   TSM_FLAG_FIXED_POINT | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64 |
-                  TSM_FLAG_STORED_OPERATOR))
+                  TSM_FLAG_STORED_OPERATOR | TSM_FLAG_MACRO_PCG))
         return c->fail(TSM_EINVAL, "unknown flag bits");
     HIPCHK(hipStreamSynchronize(c->stream));
     c->prm.flags = flags;
@@ -1356,7 +1421,8 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
     s->n_inst = c->n_inst;
     s->n_micro_dofs = c->total;
     s->steps_taken = c->steps_taken;
-    s->macro_sweeps = c->macro_sweeps;
+    s->macro_sweeps = c->macro_pcg() ? 0 : c->macro_sweeps;
+    s->macro_pcg_iters = c->macro_pcg() ? c->macro_pcg_iters : 0;
     s->macro_contraction = c->rho;
     s->setup_ms = c->setup_ms;
     s->step_ms = c->step_ms;

@@ -212,9 +212,97 @@ __global__ __launch_bounds__(1024) void coupling_residual_kernel(int nR, const d
     }
 }
 
+// ---------------------------------------------------------------------------
+// Preconditioned CG on A_M with A_0^{-1} (the sine-basis solve of the sweep)
+// as preconditioner, for batches whose response functionals are too
+// heterogeneous for the sweep to contract quickly.  Vectors on the interior
+// n x n grid (r, z, q = A_M p) except the search direction p, which is kept on
+// the full (NM+1)^2 grid with a zero boundary so the 9-point stencil reads it
+// directly.  s[0] holds (r, z).  One 1024-lane workgroup per kernel, fixed
+// summation order; a zero (p, A_M p) or (r, z) -- an exactly solved system --
+// gives a zero step instead of 0/0.
+// ---------------------------------------------------------------------------
+constexpr int kPcgThreads = 1024;
+
+// p = z (zero boundary), s[0] = (r, z)
+__global__ __launch_bounds__(kPcgThreads) void macro_pcg_start_kernel(int NM, const double* r, const double* z,
+                                                                      double* p, double* s) {
+    __shared__ double red_s[2][1][kPcgThreads / kWave];
+    BlockReducer<kPcgThreads / kWave, 1, double> red(red_s);
+    const int W = NM + 1, n = NM - 1;
+    double acc[1] = {0.0};
+    for (int k = threadIdx.x; k < W * W; k += kPcgThreads) {
+        const int k1 = k % W, k2 = k / W;
+        const bool inner = k1 > 0 && k1 < NM && k2 > 0 && k2 < NM;
+        const int idx = (k2 - 1) * n + (k1 - 1);
+        p[k] = inner ? z[idx] : 0.0;
+        if (inner) acc[0] += r[idx] * z[idx];
+    }
+    red.sum(acc);
+    if (threadIdx.x == 0) s[0] = acc[0];
+}
+
+// q = A_M p, alpha = (r, z) / (p, q), u += alpha p, r -= alpha q
+__global__ __launch_bounds__(kPcgThreads) void macro_pcg_step_kernel(MacroArgs m, const double* p, double* q,
+                                                                     double* r, double* u, const double* s) {
+    __shared__ double red_s[2][1][kPcgThreads / kWave];
+    BlockReducer<kPcgThreads / kWave, 1, double> red(red_s);
+    const int W = m.NM + 1;
+    const double rz = s[0];
+    double acc[1] = {0.0};
+    for (int idx = threadIdx.x; idx < m.n * m.n; idx += kPcgThreads) {
+        const int k = (idx / m.n + 1) * W + (idx % m.n + 1);
+        const double Ap = m.mass_c * mass9(p, k, W) + m.lap_c * lap9(p, k, W) - m.sig_h2 * m.beta[k] * p[k];
+        q[idx] = Ap;
+        acc[0] += p[k] * Ap;
+    }
+    red.sum(acc);
+    const double alpha = acc[0] > 0.0 ? rz / acc[0] : 0.0;
+    for (int idx = threadIdx.x; idx < m.n * m.n; idx += kPcgThreads) {
+        const int k = (idx / m.n + 1) * W + (idx % m.n + 1);
+        u[k] += alpha * p[k];
+        r[idx] -= alpha * q[idx];
+    }
+}
+
+// beta = (r, z)_new / (r, z), p = z + beta p, s[0] = (r, z)_new
+__global__ __launch_bounds__(kPcgThreads) void macro_pcg_direction_kernel(int NM, const double* r, const double* z,
+                                                                          double* p, double* s) {
+    __shared__ double red_s[2][1][kPcgThreads / kWave];
+    BlockReducer<kPcgThreads / kWave, 1, double> red(red_s);
+    const int W = NM + 1, n = NM - 1;
+    const double rz_old = s[0];
+    double acc[1] = {0.0};
+    for (int idx = threadIdx.x; idx < n * n; idx += kPcgThreads) acc[0] += r[idx] * z[idx];
+    red.sum(acc);      // every lane has read s[0] before the barrier inside
+    const double beta = rz_old > 0.0 ? acc[0] / rz_old : 0.0;
+    for (int idx = threadIdx.x; idx < n * n; idx += kPcgThreads) {
+        const int k = (idx / n + 1) * W + (idx % n + 1);
+        p[k] = z[idx] + beta * p[k];
+    }
+    if (threadIdx.x == 0) s[0] = acc[0];
+}
+
 inline int blocks(int n, int t) { return (n + t - 1) / t; }
 
 }  // namespace
+
+hipError_t launch_macro_pcg_start(int NM, const double* r, const double* z, double* p, double* s, hipStream_t st) {
+    hipLaunchKernelGGL(macro_pcg_start_kernel, dim3(1), dim3(kPcgThreads), 0, st, NM, r, z, p, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_pcg_step(const MacroArgs& m, const double* p, double* q, double* r, double* u,
+                                 const double* s, hipStream_t st) {
+    hipLaunchKernelGGL(macro_pcg_step_kernel, dim3(1), dim3(kPcgThreads), 0, st, m, p, q, r, u, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_pcg_direction(int NM, const double* r, const double* z, double* p, double* s,
+                                      hipStream_t st) {
+    hipLaunchKernelGGL(macro_pcg_direction_kernel, dim3(1), dim3(kPcgThreads), 0, st, NM, r, z, p, s);
+    return hipGetLastError();
+}
 
 hipError_t launch_macro_rhs_forward(const MacroArgs& m, const double* u, const double* bx,
                                     double* rhs, double* alpha, hipStream_t s) {

@@ -320,6 +320,13 @@ hipError_t launch_macro_residual(const MacroArgs& m, const double* u, const doub
 hipError_t launch_gemm(int n, const double* A, const double* B, double* C, int epilogue,
                        const double* lam, double* u, int NM, hipStream_t s);
 hipError_t launch_observable(const MacroArgs& m, const double* u, double* J, hipStream_t s);
+// macro PCG with the sine-basis preconditioner: r, z, q interior (n x n), p
+// full grid (zero boundary), s[0] = (r, z)
+hipError_t launch_macro_pcg_start(int NM, const double* r, const double* z, double* p, double* s, hipStream_t st);
+hipError_t launch_macro_pcg_step(const MacroArgs& m, const double* p, double* q, double* r, double* u,
+                                 const double* s, hipStream_t st);
+hipError_t launch_macro_pcg_direction(int NM, const double* r, const double* z, double* p, double* s,
+                                      hipStream_t st);
 hipError_t launch_adjoint_coef(const MacroArgs& m, const double* mu, double* coef, hipStream_t s);
 
 // Gradient contribution of one adjoint step m (one workgroup per instance):

@@ -31,6 +31,7 @@ TSM_FLAG_GENERIC_16 = 1 << 6
 TSM_FLAG_GENERIC_32 = 1 << 7
 TSM_FLAG_GENERIC_64 = 1 << 8
 TSM_FLAG_STORED_OPERATOR = 1 << 9
+TSM_FLAG_MACRO_PCG = 1 << 10
 TSM_PART_N, TSM_PART_I, TSM_PART_O = 0, 1, 2
 
 STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV",
@@ -64,7 +65,8 @@ class tsm_stats(ctypes.Structure):
                 ("timed_steps", ctypes.c_int32), ("micro_launches", ctypes.c_int32),
                 ("grad_forward_ms", ctypes.c_double), ("grad_backward_ms", ctypes.c_double),
                 ("sweeps_mean", ctypes.c_double),
-                ("fp_iters_last", ctypes.c_int32), ("fp_iters_max", ctypes.c_int32)]
+                ("fp_iters_last", ctypes.c_int32), ("fp_iters_max", ctypes.c_int32),
+                ("macro_pcg_iters", ctypes.c_int32)]
 
 
 class tsm_stationary_params(ctypes.Structure):
