@@ -273,7 +273,7 @@ def _rel(x, ref):
     return float(np.linalg.norm(x - ref) / (den if den > 0 else 1.0))
 
 
-def stationary_leg(reps, parity=True):
+def stationary_leg(reps, parity=True, flags=0):
     """The paper's stationary three-field system (Section 2.1 model) on the
     Case B map with the Table 3 parameters and a unit micro source (the
     Table 3 data alone give the constant state), at the paper's size (81
@@ -287,7 +287,7 @@ def stationary_leg(reps, parity=True):
     res = {}
     for name, NM in (("case_B_81x4225", 8), ("case_B_4225x4225", 64)):
         lv, _, Fc, Fb = W.stationary_case("B", NM, 64)
-        g = StationarySystem(NM, lv, jacobians=(Fc, Fb), fv=1.0)
+        g = StationarySystem(NM, lv, jacobians=(Fc, Fb), fv=1.0, flags=flags)
         try:
             g.solve()
             ms, micro = [], []
@@ -308,6 +308,23 @@ def stationary_leg(reps, parity=True):
                "micro_dof_iterations_per_s": dof_iters / t_micro,
                # a PCG streaming its FP64 vectors: 10 words per DoF and iteration
                "streaming_model_GBs": dof_iters * 80.0 / t_micro / 1e9}
+        if flags == 0:
+            # the multigrid V-cycle on every mesh size (by default only above
+            # 64 cells per side, where it replaces one-workgroup Jacobi CG)
+            from paper_2103_17040_amd import tsm
+            mg = StationarySystem(NM, lv, jacobians=(Fc, Fb), fv=1.0, flags=tsm.TSM_FLAG_MULTIGRID)
+            try:
+                mg.solve()
+                mms = []
+                for _ in range(reps):
+                    mg.solve()
+                    mst = mg.stats()
+                    mms.append(mst["solve_ms"])
+            finally:
+                mg.close()
+            ent["multigrid_all_sizes"] = {"solve_ms": statistics.median(mms),
+                                          "micro_iters_mean": mst["micro_iters_mean"],
+                                          "micro_iters_max": mst["micro_iters_max"]}
         if parity and NM == 8:
             ref = np.load(os.path.join(GOLD, "stationary_caseB.npz"), allow_pickle=False)
             off = W.offsets(lv)
@@ -455,7 +472,7 @@ def _constant_tables(levels, F, device):
     return f.expand(n_cell_pts, 4).contiguous().view(-1), f.expand(n_bnd_pts, 4).contiguous().view(-1)
 
 
-def stationary_convergence_leg(sizes=PAPER_CONVERGENCE_ROWS, workers=None):
+def stationary_convergence_leg(sizes=PAPER_CONVERGENCE_ROWS, workers=None, flags=0):
     """The convergence benchmark of Section 4.2 on the GPU: the paper's
     manufactured solution and map (eq. manu_system; data re-derived), N_M = N
     cells per side on both scales -- the rows of Tables 1-2, 81 to 16641
@@ -486,7 +503,7 @@ def stationary_convergence_leg(sizes=PAPER_CONVERGENCE_ROWS, workers=None):
         pts = MF.manufactured_data_at_points(phys, parts, N, levels, workers)
         t1 = time.perf_counter()
         Fc, Fb = _constant_tables(levels, F, "cuda")
-        g = StationarySystem(N, levels, jacobians=(Fc, Fb), rtol=1e-13, **phys)
+        g = StationarySystem(N, levels, jacobians=(Fc, Fb), rtol=1e-13, flags=flags, **phys)
         del Fc, Fb
         torch.cuda.empty_cache()
         try:

@@ -86,6 +86,16 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
                                             preconditioner even where the sweep would do (it is
                                             used anyway where the sweep's contraction bound is
                                             0.5 or more) */
+#define TSM_FLAG_MULTIGRID  (1ull << 11) /* stationary contexts: the micro solves of every mesh
+                                            with N = c 2^L cells per side (c <= 8, L >= 1) by CG
+                                            preconditioned with one geometric multigrid V-cycle
+                                            (Galerkin coarse operators of the nested meshes, two
+                                            damped Jacobi sweeps before and after, dense coarsest
+                                            solve).  Without it only such meshes above 64 cells
+                                            per side take the V-cycle (the packed Jacobi kernels
+                                            are faster at 64 and below); the other sizes keep
+                                            Jacobi either way. */
+#define TSM_FLAG_NO_MULTIGRID (1ull << 12) /* stationary contexts: Jacobi for every mesh */
 #define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
                                             HIP events on the context's stream (see tsm_stats) */
 #define TSM_FLAG_FIXED_POINT (1ull << 5) /* tsm_step couples macro and micro solves by the paper's

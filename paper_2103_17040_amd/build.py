@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtsm.so")
-SOURCES = ["api.hip", "assemble.hip", "micro.hip", "micro_packed.hip", "macro.hip", "adjoint.hip", "stationary.hip", "refine.hip"]
+SOURCES = ["api.hip", "assemble.hip", "micro.hip", "micro_packed.hip", "macro.hip", "adjoint.hip", "stationary.hip", "refine.hip", "mg.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

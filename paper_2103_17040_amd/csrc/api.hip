@@ -24,6 +24,17 @@ int slots_for(int n) {
     return -1;
 }
 
+// Coarse levels of the multigrid hierarchy of an N-cell mesh: N = c 2^L with
+// c <= kMgCoarsest and L >= 1, else 0 (no hierarchy).
+int mg_levels_for(int N) {
+    int L = 0, c = N;
+    while (c > kMgCoarsest && c % 2 == 0 && L < kMgMaxLevels) {
+        c /= 2;
+        ++L;
+    }
+    return (L >= 1 && c <= kMgCoarsest) ? L : 0;
+}
+
 struct Group {
     int first;      // first task in the order array
     int count;
@@ -85,6 +96,46 @@ struct tsm_ctx {
     // that runs micro solves side by side)
     double* lg_ws = nullptr;
     int lg_sets = 0;
+    // multigrid-preconditioned micro solves (stationary contexts with
+    // TSM_FLAG_MULTIGRID): per-instance coarse levels, Galerkin operators,
+    // coarsest inverses, damping, and per-stream workspaces
+    int32_t* mg_nlev = nullptr;
+    int64_t *mg_coff = nullptr, *mg_ioff = nullptr;
+    double *mg_Ac = nullptr, *mg_inv = nullptr, *mg_omega = nullptr, *mg_ws = nullptr, *mg_cws = nullptr;
+    int64_t mg_ctotal = 0;
+    int mg_sets = 0;
+    bool mg_ready = false;
+    // an N-cell instance of this context is solved on the multigrid path:
+    // by default the meshes above kMaxLevel cells per side (there the
+    // alternative is one-workgroup Jacobi CG, whose iteration count grows
+    // like N), every mesh with a hierarchy under TSM_FLAG_MULTIGRID, none
+    // under TSM_FLAG_NO_MULTIGRID; stationary contexts only
+    bool mg_use(int N) const {
+        if (!stationary || (prm.flags & TSM_FLAG_NO_MULTIGRID) || mg_levels_for(N) == 0) return false;
+        return N > kMaxLevel || (prm.flags & TSM_FLAG_MULTIGRID);
+    }
+    MgArgs mg_args(int set) const {
+        MgArgs G{};
+        G.nlev = mg_nlev;
+        G.coff = mg_coff;
+        G.ioff = mg_ioff;
+        G.Ac = mg_Ac;
+        G.inv = mg_inv;
+        G.omega = mg_omega;
+        G.ws = mg_ws + (int64_t)set * 5 * total;
+        G.ws_stride = total;
+        G.cws = mg_cws + (int64_t)set * 3 * mg_ctotal;
+        G.cws_stride = mg_ctotal;
+        G.nu = 2;
+        return G;
+    }
+    void free_mg() {
+        dfree(mg_nlev); dfree(mg_coff); dfree(mg_ioff); dfree(mg_Ac); dfree(mg_inv); dfree(mg_omega);
+        dfree(mg_ws); dfree(mg_cws);
+        mg_ctotal = 0;
+        mg_sets = 0;
+        mg_ready = false;
+    }
     float *S32 = nullptr, *Slo = nullptr;
     // symmetric upper-half planes [kSym][n] of S, K = S - M/dt, M (FP32), S split in FP32
     double *Ss64 = nullptr, *Ks64 = nullptr;
@@ -162,6 +213,7 @@ struct tsm_ctx {
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(Mw); dfree(v0); dfree(S32); dfree(Slo);
         dfree(bcomp); dfree(lg_ws);
         lg_sets = 0;
+        free_mg();
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
@@ -267,6 +319,12 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
         MicroArgs a = base;
         a.n_tasks = g.count;
         a.order = c->order + g.first;
+        if (g.slots == -2) {
+            if (!c->mg_ready || set >= c->mg_sets) return c->fail(TSM_ESTATE, "multigrid hierarchy not built");
+            MgArgs G = c->mg_args(set);
+            HIPCHK(launch_micro_mg(a, G, st));
+            continue;
+        }
         if (g.slots < 0) {
             if (set >= c->lg_sets) return c->fail(TSM_EINVAL, "no large-mesh workspace for this stream");
             a.ws = c->lg_ws + (int64_t)set * 3 * c->total;
@@ -299,7 +357,7 @@ tsm_status plan_tasks(tsm_ctx* c) {
     };
     auto packable = [&](int32_t i) {
         const int lvl = c->level_h[i];
-        return use_packs && packed_capacity(lvl) > 0 && size_ok(lvl);
+        return use_packs && packed_capacity(lvl) > 0 && size_ok(lvl) && !c->mg_use(lvl);
     };
     c->order_h.resize(n_inst);
     for (int64_t i = 0; i < n_inst; ++i) c->order_h[i] = (int32_t)i;
@@ -335,8 +393,10 @@ tsm_status plan_tasks(tsm_ctx* c) {
     const bool stream_all = (c->prm.flags & TSM_FLAG_STENCIL_STREAM) != 0;
     for (; t < n_inst; ++t) {
         const int lvl = c->level_h[c->order_h[t]];
-        // slots -1: above kMaxLevel, the large-mesh kernel
-        const int sl = lvl > kMaxLevel ? -1 : slots_for((lvl + 1) * (lvl + 1));
+        // slots -2: the multigrid kernel; -1: above kMaxLevel, the large-mesh kernel
+        const int sl = c->mg_use(lvl) ? -2
+                       : lvl > kMaxLevel               ? -1
+                                                       : slots_for((lvl + 1) * (lvl + 1));
         if (c->groups.empty() || c->groups.back().slots != sl) {
             Group g;
             g.first = (int)t;
@@ -812,6 +872,45 @@ AssembleArgs assemble_base(tsm_ctx* c) {
     return as;
 }
 
+// The multigrid hierarchy of a stationary context from its assembled
+// operators: levels, offsets, Galerkin operators, damping, coarsest inverses.
+tsm_status mg_setup(tsm_ctx* c) {
+    c->free_mg();
+    const int64_t ni = c->n_inst;
+    std::vector<int32_t> nl(ni);
+    std::vector<int64_t> co(ni), io(ni);
+    int64_t ct = 0, it = 0;
+    int lmax = 0;
+    for (int64_t i = 0; i < ni; ++i) {
+        const int N = c->level_h[i];
+        const int L = c->mg_use(N) ? mg_levels_for(N) : 0;
+        nl[i] = L;
+        co[i] = ct;
+        io[i] = it;
+        for (int l = 1; l <= L; ++l) ct += (int64_t)((N >> l) + 1) * ((N >> l) + 1);
+        if (L > 0) {
+            const int64_t nc = (int64_t)((N >> L) + 1) * ((N >> L) + 1);
+            it += nc * nc;
+        }
+        lmax = std::max(lmax, L);
+    }
+    if (lmax == 0) return TSM_OK;      // no instance has a hierarchy: nothing runs on this path
+    HIPALLOC(c->mg_nlev, ni); HIPALLOC(c->mg_coff, ni); HIPALLOC(c->mg_ioff, ni);
+    HIPALLOC(c->mg_Ac, (size_t)kStencil * ct); HIPALLOC(c->mg_inv, (size_t)it);
+    HIPALLOC(c->mg_omega, (size_t)ni * (kMgMaxLevels + 1));
+    c->mg_sets = 3;                    // the three micro solves run side by side
+    c->mg_ctotal = ct;
+    HIPALLOC(c->mg_ws, (size_t)c->mg_sets * 5 * c->total); HIPALLOC(c->mg_cws, (size_t)c->mg_sets * 3 * ct);
+    HIPCHK(hipMemcpy(c->mg_nlev, nl.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_coff, co.data(), ni * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_ioff, io.data(), ni * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(c->mg_omega, 0, (size_t)ni * (kMgMaxLevels + 1) * sizeof(double)));
+    HIPCHK(launch_mg_setup(micro_base(c), c->mg_args(0), (int)ni, lmax, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->mg_ready = true;
+    return TSM_OK;
+}
+
 template <class What>
 tsm_status finish_setup(tsm_ctx* c, std::chrono::steady_clock::time_point t0, What what) {
     const int64_t n_inst = c->n_inst;
@@ -827,6 +926,8 @@ tsm_status finish_setup(tsm_ctx* c, std::chrono::steady_clock::time_point t0, Wh
             return c->fail(TSM_EGEOM, buf);
         }
     if (c->stationary) {   // the solves belong to tsm_stationary_solve
+        const tsm_status ms = mg_setup(c);   // (frees a hierarchy of an earlier geometry)
+        if (ms != TSM_OK) return ms;
         c->have_geom = true;
         c->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         return TSM_OK;
@@ -1299,16 +1400,22 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
 tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
     if (!c) return TSM_EINVAL;
     const bool replan = ((flags ^ c->prm.flags) & (TSM_FLAG_STENCIL_STREAM | TSM_FLAG_GENERIC | TSM_FLAG_GENERIC_16 |
-                                                    TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64)) != 0;
+                                                    TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64 |
+                                                    TSM_FLAG_MULTIGRID | TSM_FLAG_NO_MULTIGRID)) != 0;
     if (flags & ~(TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_TIMING | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT |
                   TSM_FLAG_FIXED_POINT | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64 |
-                  TSM_FLAG_STORED_OPERATOR | TSM_FLAG_MACRO_PCG))
+                  TSM_FLAG_STORED_OPERATOR | TSM_FLAG_MACRO_PCG | TSM_FLAG_MULTIGRID | TSM_FLAG_NO_MULTIGRID))
         return c->fail(TSM_EINVAL, "unknown flag bits");
+    const bool mg_changed = ((flags ^ c->prm.flags) & (TSM_FLAG_MULTIGRID | TSM_FLAG_NO_MULTIGRID)) != 0;
     HIPCHK(hipStreamSynchronize(c->stream));
     c->prm.flags = flags;
     if (replan && c->have_mesh) {
         tsm_status st = plan_tasks(c);
         if (st != TSM_OK) return st;
+    }
+    if (c->stationary && c->have_geom && mg_changed) {
+        const tsm_status ms = mg_setup(c);
+        if (ms != TSM_OK) return ms;
     }
     if (c->have_geom && !c->stationary) return build_graph(c);
     return TSM_OK;
@@ -1588,7 +1695,8 @@ tsm_status tsm_stationary_create(const tsm_stationary_params* sp, void* stream, 
         n_dir += sp->dirichlet[s] != 0;
     }
     const uint64_t plan = TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT |
-                          TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64;
+                          TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64 | TSM_FLAG_MULTIGRID |
+                          TSM_FLAG_NO_MULTIGRID;
     const double pos[] = {sp->Dv, sp->Dw, sp->kappa1, sp->kappa2, sp->kappa3, sp->kappa4, sp->rtol, sp->macro_rtol};
     bool ok = sp->macro_cells >= 2 && sp->macro_cells <= 256 && parts_ok && n_in >= 1 && n_out >= 1 && n_dir >= 1 &&
               sp->max_iter >= 1 && sp->macro_max_iter >= 1 && !(sp->flags & ~plan) && std::isfinite(sp->fu) &&

@@ -225,6 +225,31 @@ hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_
 // instances with more than kMaxLevel cells per side: one 1024-lane workgroup
 // per task, vectors in the workspace a.ws (FP64 in either precision mode)
 hipError_t launch_micro_large(const MicroArgs& a, hipStream_t s);
+
+// Multigrid-preconditioned micro solves (mg.hip).  An instance with
+// N = c 2^L cells per side, c <= kMgCoarsest, L >= 1, has coarse levels
+// 1..L (N >> l cells per side), their Galerkin operators in Ac (9
+// coefficient-major planes per level at 9 * (coff + level offset)), the
+// coarsest operator's dense inverse at inv + ioff, and a Jacobi damping per
+// smoothed level.
+constexpr int kMgMaxLevels = 8;
+constexpr int kMgCoarsest = 8;
+struct MgArgs {
+    const int32_t* nlev;   // [n_inst] L (0: not on the multigrid path)
+    const int64_t* coff;   // [n_inst] offset of the instance's coarse levels (vectors; x9 for operators)
+    const int64_t* ioff;   // [n_inst] offset of the coarsest inverse
+    double* Ac;
+    double* inv;
+    double* omega;         // [n_inst][kMgMaxLevels + 1]
+    double* ws;            // fine-level vectors r, z, t, p, q: ws + k * ws_stride + offset
+    int64_t ws_stride;
+    double* cws;           // coarse-level vectors x, r, t: cws + k * cws_stride + coarse offset
+    int64_t cws_stride;
+    int nu;                // smoothing sweeps before and after the coarse correction
+};
+hipError_t launch_micro_mg(const MicroArgs& a, const MgArgs& g, hipStream_t s);
+// Galerkin operators (levels 0 -> max_levels), damping, coarsest inverses
+hipError_t launch_mg_setup(const MicroArgs& a, const MgArgs& g, int n_inst, int max_levels, hipStream_t s);
 // packs of one mesh size (16, 32 or 64); mode 1 FP64, 2 refinement, 3 refinement
 // with the operator evaluated matrix-free from the amplitudes (time-step form only)
 hipError_t launch_packed(const MicroArgs& a, const PackList& p, int level, int mode, int grid, hipStream_t s);

@@ -106,9 +106,12 @@ def test_indicator_refuses_large_meshes():
         g.close()
 
 
+@pytest.mark.parametrize("multigrid", [True, False])
 @pytest.mark.parametrize("levels", [[91, 128, 16, 64], [128, 256]])
-def test_stationary_large_meshes(levels):
-    from paper_2103_17040_amd import StationarySystem
+def test_stationary_large_meshes(levels, multigrid):
+    """128 and 256 take the multigrid V-cycle by default, 91 Jacobi; with
+    TSM_FLAG_NO_MULTIGRID every large mesh runs the Jacobi kernel."""
+    from paper_2103_17040_amd import StationarySystem, tsm
     NM = 3
     n = (NM + 1) ** 2
     lv = np.asarray([levels[i % len(levels)] for i in range(n)], dtype=np.int32)
@@ -116,10 +119,10 @@ def test_stationary_large_meshes(levels):
                                     [tuple(x) for x in W.stationary_macro_nodes(NM)])
     phys = dict(Dv=1.0, Dw=0.1, kappa1=0.5, kappa2=1.0, kappa3=0.25, kappa4=1.0)
     src = dict(fu=0.3, fv=1.0, fw=-0.2)
-    banner(f"stationary Case B NM={NM} levels={levels}")
+    banner(f"stationary Case B NM={NM} levels={levels} multigrid={multigrid}")
     parts, dirichlet = (0, 0, 1, 2), (0, 0, 1, 0)
     g = StationarySystem(NM, lv, jacobians=(Fc, Fb), parts=parts, dirichlet=dirichlet, u_dirichlet=1.0,
-                         rtol=1e-14, **src, **phys)
+                         rtol=1e-14, flags=0 if multigrid else tsm.TSM_FLAG_NO_MULTIGRID, **src, **phys)
     try:
         u, w, v = (t.cpu().numpy() for t in g.solve())
         stats = g.stats()
