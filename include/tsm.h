@@ -190,8 +190,7 @@ tsm_status tsm_create(const tsm_params* p, void* stream, tsm_ctx** out);
  * cells per side of K_h (host pointer, n_inst entries, read during the call;
  * n_inst == (N_M+1)^2, else EINVAL; a size outside 2..256: EINVAL).  Sizes
  * 16, 32 and 64 run the packed kernels; sizes above 64 run one workgroup
- * per instance in FP64 (either precision mode) and are not refined by the
- * indicator calls below.
+ * per instance in FP64 (either precision mode).
  * Allocates the ragged buffers (ENOMEM if that fails).  Invalidates any
  * deformation and state. */
 tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_t n_inst);
@@ -337,9 +336,8 @@ void tsm_destroy(tsm_ctx* c);
  * instance i's reference mesh of (h/12) int_e [[ d (C grad_z v_i) . nu_e ]]^2,
  * the jump of the pulled-back flux (C = K K^T J, Section 3.1) integrated with
  * the 2-point rule.  Needs set_state; ESTATE for a geometry given by Jacobian
- * tables (C is needed at points the tables do not hold), for a
- * stationary context and for meshes above 64 cells per side; EINVAL unless
- * n == n_inst. */
+ * tables (C is needed at points the tables do not hold) and for a
+ * stationary context; EINVAL unless n == n_inst. */
 tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out, int64_t n);
 
 /* Bulk marking over the global functional sum_i eta2[i]: the fewest
@@ -347,14 +345,15 @@ tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out, int64_t n);
  * index first), whose indicators reach theta times the functional get
  * level_new[i] = 2 level[i]; the others keep level[i].  Host pointers, n_inst
  * entries each; *n_marked (may be NULL) receives the count.  EINVAL on
- * theta outside [0, 1], a negative or non-finite eta2 or a bad level
- * (message in tsm_last_error(NULL)). */
+ * theta outside [0, 1], a negative or non-finite eta2 or a level outside
+ * 2..256 (message in tsm_last_error(NULL)); max_level 256 lets every mesh
+ * that tsm_set_reference_mesh accepts after refinement be marked. */
 tsm_status tsm_mark_refine(int64_t n_inst, const double* eta2, const int32_t* level, double theta, int32_t max_level,
                            int32_t* level_new, int64_t* n_marked);
 
 /* Nested Q1 interpolation of a ragged micro field from the meshes level_old
  * to level_new (host pointers, n_inst each; level_new[i] is level_old[i] or
- * 2 level_old[i], at most 64): v_old (ragged by level_old, n_old entries)
+ * 2 level_old[i], at most 256): v_old (ragged by level_old, n_old entries)
  * to v_new (ragged by level_new, n_new entries), device pointers.  A fine
  * node takes the coarse value at a corner, the mean of 2 on an edge
  * midpoint, of 4 at a cell centre.  Runs on `stream` (a hipStream_t, NULL:

@@ -1572,7 +1572,6 @@ tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out, int64_t n) {
     if (c->stationary) return c->fail(TSM_ESTATE, "stationary context: no time-stepped micro state");
     if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
     if (c->geom_tables) return c->fail(TSM_ESTATE, "indicator needs the amplitude geometry (not Jacobian tables)");
-    if (c->lg_sets > 0) return c->fail(TSM_ESTATE, "indicator: meshes above 64 cells per side are not refined");
     IndicatorArgs a{};
     a.n_inst = (int)c->n_inst;
     a.level = c->level;
@@ -1598,8 +1597,8 @@ tsm_status tsm_mark_refine(int64_t n_inst, const double* eta2, const int32_t* le
     for (int64_t i = 0; i < n_inst; ++i) {
         if (!(eta2[i] >= 0.0) || !std::isfinite(eta2[i]))
             return create_failed(nullptr, TSM_EINVAL, "tsm_mark_refine: eta2 negative or not finite");
-        if (level[i] < kMinLevel || level[i] > kMaxLevel)
-            return create_failed(nullptr, TSM_EINVAL, "tsm_mark_refine: level outside 2..64");
+        if (level[i] < kMinLevel || level[i] > kMaxMesh)
+            return create_failed(nullptr, TSM_EINVAL, "tsm_mark_refine: level outside 2..256");
         total += eta2[i];
         if (2 * level[i] <= max_level) cand.push_back(i);
         level_new[i] = level[i];
@@ -1625,9 +1624,9 @@ tsm_status tsm_prolong(int64_t n_inst, const int32_t* lo, const int32_t* ln, con
     if (n_inst < 1 || !lo || !ln || !vo || !vn) return create_failed(nullptr, TSM_EINVAL, "tsm_prolong: bad arguments");
     std::vector<int64_t> oo(n_inst + 1, 0), on(n_inst + 1, 0);
     for (int64_t i = 0; i < n_inst; ++i) {
-        if (lo[i] < kMinLevel || lo[i] > kMaxLevel || !(ln[i] == lo[i] || ln[i] == 2 * lo[i]) || ln[i] > kMaxLevel)
+        if (lo[i] < kMinLevel || lo[i] > kMaxMesh || !(ln[i] == lo[i] || ln[i] == 2 * lo[i]) || ln[i] > kMaxMesh)
             return create_failed(nullptr, TSM_EINVAL,
-                                 "tsm_prolong: level_new[" + std::to_string(i) + "] is neither level_old nor twice it (<= 64)");
+                                 "tsm_prolong: level_new[" + std::to_string(i) + "] is neither level_old nor twice it (<= 256)");
         oo[i + 1] = oo[i] + (int64_t)(lo[i] + 1) * (lo[i] + 1);
         on[i + 1] = on[i] + (int64_t)(ln[i] + 1) * (ln[i] + 1);
     }

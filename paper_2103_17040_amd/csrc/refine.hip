@@ -25,9 +25,11 @@ constexpr int NT = 256;
 
 constexpr int kCoords = 3 * kMaxLevel + 1;   // N+1 node and 2N Gauss coordinates of a side
 
-// one workgroup per instance; the micro state v = v0 + u w is formed once
-// into LDS, and sin/cos of every node and Gauss coordinate of the mesh
-// (the only points the indicator visits) are tabulated there too
+// one workgroup per instance; up to kMaxLevel cells per side the micro state
+// v = v0 + u w is formed once into LDS, and sin/cos of every node and Gauss
+// coordinate of the mesh (the only points the indicator visits) are
+// tabulated there too; larger meshes read v0 and w at every point and
+// evaluate the coordinates where they are used
 __global__ __launch_bounds__(NT) void indicator_kernel(IndicatorArgs A) {
     __shared__ double red_s[2][1][NT / kWave];
     __shared__ double vs[(kMaxLevel + 1) * (kMaxLevel + 1)];
@@ -40,20 +42,32 @@ __global__ __launch_bounds__(NT) void indicator_kernel(IndicatorArgs A) {
     const double* v0 = A.v0 + off;
     const double* w = A.w + off;
     const double h = 2.0 / N;
-    for (int j = threadIdx.x; j < NP * NP; j += NT) vs[j] = v0[j] + u * w[j];
+    const bool big = N > kMaxLevel;      // uniform over the workgroup
     // coordinate k: node k (k <= N), or Gauss point g of cell c at N + 1 + 2c + g
-    for (int k = threadIdx.x; k < 3 * N + 1; k += NT) {
-        const double y = k <= N ? -1.0 + k * h : -1.0 + (((k - NP) >> 1) + gauss_x((k - NP) & 1)) * h;
+    auto coord = [&](int k, double& y, double& sn, double& cs) {
+        y = k <= N ? -1.0 + k * h : -1.0 + (((k - NP) >> 1) + gauss_x((k - NP) & 1)) * h;
         double s, c;
         sincospi(y, &s, &c);
-        ycoord[k] = y;
-        ysin[k] = 0.25 * s;
-        ycos[k] = 0.25 * M_PI * c;
+        sn = 0.25 * s;
+        cs = 0.25 * M_PI * c;
+    };
+    if (!big) {
+        for (int j = threadIdx.x; j < NP * NP; j += NT) vs[j] = v0[j] + u * w[j];
+        for (int k = threadIdx.x; k < 3 * N + 1; k += NT) coord(k, ycoord[k], ysin[k], ycos[k]);
     }
     __syncthreads();
-    auto V = [&](int j1, int j2) { return vs[j2 * NP + j1]; };
+    auto V = [&](int j1, int j2) {
+        const int j = j2 * NP + j1;
+        return big ? v0[j] + u * w[j] : vs[j];
+    };
     // C at (node coordinate kn along one axis, Gauss coordinate kg along the other)
     auto pull = [&](int k1, int k2) {
+        if (big) {
+            double y1, s1, c1, y2, s2, c2;
+            coord(k1, y1, s1, c1);
+            coord(k2, y2, s2, c2);
+            return pullback_at(a, y1, y2, s1, c1, s2, c2);
+        }
         return pullback_at(a, ycoord[k1], ycoord[k2], ysin[k1], ycos[k1], ysin[k2], ycos[k2]);
     };
     // work items: direction x interior line (1..N-1) x segment (0..N-1) x point
@@ -213,9 +227,9 @@ extern "C" tsm_status tsm_prolong_noalloc(int64_t n_inst, const int32_t* lo, con
                                            std::to_string(kNoAllocMaxInst));
     int64_t to = 0, tn = 0;
     for (int64_t i = 0; i < n_inst; ++i) {
-        if (lo[i] < kMinLevel || lo[i] > kMaxLevel || !(ln[i] == lo[i] || ln[i] == 2 * lo[i]) || ln[i] > kMaxLevel)
+        if (lo[i] < kMinLevel || lo[i] > kMaxMesh || !(ln[i] == lo[i] || ln[i] == 2 * lo[i]) || ln[i] > kMaxMesh)
             return call_failed(TSM_EINVAL, "tsm_prolong_noalloc: level_new[" + std::to_string(i) +
-                                               "] is neither level_old nor twice it (<= 64)");
+                                               "] is neither level_old nor twice it (<= 256)");
         to += (int64_t)(lo[i] + 1) * (lo[i] + 1);
         tn += (int64_t)(ln[i] + 1) * (ln[i] + 1);
     }

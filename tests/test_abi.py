@@ -154,14 +154,26 @@ def test_mark_refine_matches_the_oracle(lib_built):
         expect = lv.copy()
         expect[m] *= 2
         assert np.array_equal(new, expect) and nm == len(m), trial
+    # meshes above 64 cells per side refine up to 256
+    for trial in range(10):
+        n = int(rng.integers(1, 100))
+        eta = rng.exponential(size=n)
+        lv = rng.choice(np.array([16, 64, 91, 128, 256], np.int32), n)
+        new, nm = tsm.tsm_mark_refine(eta, lv, 0.6, 256)
+        m = refine.mark(eta, lv, 0.6, 256)
+        expect = lv.copy()
+        expect[m] *= 2
+        assert np.array_equal(new, expect) and nm == len(m) and new.max() <= 256, trial
     for eta, lv, th in (([1.0, -1.0], [8, 8], 0.5), ([1.0, np.nan], [8, 8], 0.5), ([1.0], [8], 1.5),
-                        ([1.0], [1], 0.5)):
+                        ([1.0], [1], 0.5), ([1.0], [257], 0.5)):
         with pytest.raises(tsm.TsmError) as e:
             tsm.tsm_mark_refine(np.array(eta), np.array(lv, np.int32), th)
         assert e.value.status == tsm.TSM_EINVAL
-    with pytest.raises(tsm.TsmError) as e:   # bad levels are refused before any device call
-        tsm.tsm_prolong(np.array([8], np.int32), np.array([12], np.int32), 0, 0, n_old=81, n_new=289)
-    assert e.value.status == tsm.TSM_EINVAL
+    for lo, ln in ((8, 12), (129, 258)):     # bad levels are refused before any device call
+        with pytest.raises(tsm.TsmError) as e:
+            tsm.tsm_prolong(np.array([lo], np.int32), np.array([ln], np.int32), 0, 0, n_old=(lo + 1) ** 2,
+                            n_new=(ln + 1) ** 2)
+        assert e.value.status == tsm.TSM_EINVAL
     # so are vectors whose entry counts do not match the levels (81 and 289
     # here); the pointers are never touched, the counts are checked first
     for n_old, n_new in ((80, 289), (81, 288), (0, 0)):

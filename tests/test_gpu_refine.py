@@ -168,3 +168,79 @@ def test_indicator_state_errors():
         assert e.value.status == tsm.TSM_ESTATE
     finally:
         g.close()
+
+
+def test_indicator_and_interpolation_above_64_cells():
+    """Meshes of 65-256 cells per side: the indicator (read from global
+    memory, coordinates evaluated where used) to 1e-12 and the nested
+    interpolation up to 256 cells bitwise, against the oracle."""
+    from paper_2103_17040_amd import TwoScaleBatch, tsm
+    import torch
+    NM = 2
+    lv = np.array([91, 128, 65, 100, 256, 64, 128, 16, 97], np.int32)
+    a = np.random.default_rng(12).uniform(-0.3, 0.3, lv.size)
+    u, v = W.random_state(lv, NM, seed=13)
+    banner(f"indicator and interpolation, levels {lv.tolist()}")
+    g = TwoScaleBatch(NM, lv, a, d=0.5)
+    try:
+        g.set_state(u, v)
+        eta = g.error_indicator().cpu().numpy()
+    finally:
+        g.close()
+    off = W.offsets(lv)
+    ref = np.array([refine.indicator(int(lv[i]), v[off[i]:off[i + 1]], a[i], d=0.5) for i in range(len(lv))])
+    assert np.max(np.abs(eta - ref) / np.maximum(ref, 1e-300)) <= 1e-12
+    new = np.where(lv <= 128, 2 * lv, lv).astype(np.int32)
+    vo = torch.as_tensor(v, device="cuda:0")
+    vn = torch.empty(int(W.offsets(new)[-1]), dtype=torch.float64, device="cuda:0")
+    tsm.tsm_prolong(lv, new, vo, vn)
+    out = vn.cpu().numpy()
+    on = W.offsets(new)
+    for i in range(len(lv)):
+        x = v[off[i]:off[i + 1]]
+        exp = refine.prolong(int(lv[i]), x) if new[i] != lv[i] else x
+        assert np.array_equal(out[on[i]:on[i + 1]], exp), i
+
+
+def test_refinement_into_large_meshes_steps_like_the_oracle():
+    """Step, refine every interior instance with max_level 256 (64 -> 128,
+    128 -> 256, 100 -> 200 cells per side), step on, against the oracle
+    doing the same."""
+    from paper_2103_17040_amd import TwoScaleBatch
+    NM, dt, k1, k2 = 3, 0.01, 2, 2
+    lv = np.full(16, 16, np.int32)
+    lv[[5, 6, 9, 10]] = [64, 128, 32, 100]      # the interior nodes
+    a = np.random.default_rng(21).uniform(-0.3, 0.3, lv.size)
+    u0 = W.initial_macro(NM)
+    v0 = np.zeros(int(W.offsets(lv)[-1]))
+    banner(f"refine into large meshes, levels {lv.tolist()}")
+    ts = twoscale.TwoScale(twoscale.Params(NM, dt), lv, a)
+    r1 = ts.run(u0, v0, k1)
+    off = W.offsets(lv)
+    eta_ref = np.array([refine.indicator(int(lv[i]), r1["v"][off[i]:off[i + 1]], a[i], d=0.5)
+                        for i in range(len(lv))])
+    m = refine.mark(eta_ref, lv, 0.999, 256)
+    srt = np.sort(eta_ref[lv * 2 <= 256])[::-1]
+    assert len(m) < len(srt) and (srt[len(m) - 1] - srt[len(m)]) > 1e-6 * srt[0]
+    new = lv.copy()
+    new[m] *= 2
+    assert new.max() > 128
+    vn = np.concatenate([refine.prolong(int(lv[i]), r1["v"][off[i]:off[i + 1]]) if new[i] != lv[i]
+                         else r1["v"][off[i]:off[i + 1]] for i in range(len(lv))])
+    r2 = twoscale.TwoScale(twoscale.Params(NM, dt), new, a).run(r1["u"][-1], vn, k2)
+    g = TwoScaleBatch(NM, lv, a, dt=dt, rtol=1e-13, max_iter=5000)
+    try:
+        g.set_state(u0, v0)
+        g.step(k1)
+        g2, levels2, eta = g.refine(0.999, max_level=256)
+    finally:
+        g.close()
+    try:
+        assert np.array_equal(levels2, new)
+        assert rel(eta, eta_ref) <= 1e-8
+        g2.step(k2)
+        u, v = g2.macro().cpu().numpy(), g2.micro().cpu().numpy()
+    finally:
+        g2.close()
+    banner(f"  marked {len(m)} of {len(lv)}; rel u {rel(u, r2['u'][-1]):.2e} v {rel(v, r2['v']):.2e}")
+    assert rel(u, r2["u"][-1]) <= 1e-10 and rel(v, r2["v"]) <= 1e-10
