@@ -329,6 +329,24 @@ struct RegStencil {
     __device__ __forceinline__ TS value(int, int, TS raw) const { return raw; }
 };
 
+// FP64 stencil of the lane's rows with the two lower corner couplings (SW,
+// SE) in LDS slots of the lane ([corner][row][lane]: each lane reads only
+// what it wrote, so no barrier) and the other seven in registers: 12 fewer
+// FP64 values held through the solve.
+template <class L>
+struct RegLdsStencil {
+    static constexpr bool kGlobal = false;
+    using raw_t = double;
+    const double (&S)[L::R][kStencil];
+    const double* cs;
+    __device__ __forceinline__ double load(const Lane&, int i, int k) const {
+        if (k == 0) return cs[i * NTP + threadIdx.x];
+        if (k == 2) return cs[(L::R + i) * NTP + threadIdx.x];
+        return S[i][k];
+    }
+    __device__ __forceinline__ double value(int, int, double raw) const { return raw; }
+};
+
 // Streamed planes are addressed with one VGPR per lane: each load is plane
 // k's base (wave-uniform, SGPRs) + the byte offset of the lane's node in
 // strip row 0 (VGPR) + a compile-time offset for the row and the neighbour
@@ -868,10 +886,10 @@ __device__ __forceinline__ void mf_start(const MicroArgs& A, const Lane& z, doub
 // xs: LDS for the iterate, kFp64Rows slots per lane ([row][lane]): x is only
 // read and written once per iteration, so it waits there instead of holding
 // registers that the resident stencil needs.
-template <class L, class Prefetch>
+template <class L, bool CS = false, class Prefetch>
 __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, double* xs,
                           PackRed<1, double>& red1, PackRed<2, double>& red2, PackRed<3, double>& red3,
-                          Prefetch prefetch) {
+                          Prefetch prefetch, double* cs = nullptr) {
     const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     double x[L::R], r[L::R], p[L::R];
@@ -881,7 +899,8 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
     prefetch();
 #pragma unroll
     for (int i = 0; i < L::R; ++i) xs[i * NTP + threadIdx.x] = x[i];
-    // the FP64 stencil of the lane's rows, resident in registers for the solve
+    // the FP64 stencil of the lane's rows, resident for the solve: in
+    // registers, or (cs given) its corner couplings in LDS
     double Sr[L::R][kStencil];
     {
         SymStencil<L, double> Sg{A.Ss64 + kSym * z.off};
@@ -889,16 +908,23 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
 #pragma unroll
         for (int i = 0; i < L::R; ++i)
 #pragma unroll
-            for (int k = 0; k < kStencil; ++k) Sr[i][k] = (k == 1 && i > 0) ? Sr[i - 1][7] : Sg.load(z, i, k);
+            for (int k = 0; k < kStencil; ++k) {
+                if (CS && (k == 0 || k == 2)) cs[((k >> 1) * L::R + i) * NTP + threadIdx.x] = Sg.load(z, i, k);
+                else Sr[i][k] = (k == 1 && i > 0) ? Sr[i - 1][7] : Sg.load(z, i, k);
+            }
     }
     const RegStencil<L, double> S{Sr};
+    const RegLdsStencil<L> SL{Sr, cs};
     if (A.rhs_vec == nullptr) {
         // ||b|| of the time step from b = S x0 + r with the resident stencil
         // (x0 is still in the grid): no pass over M
         double sb[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) sb[i] = 0.0;
-        if (z.act) strip_apply_lean<L, 1>(S, xg, z, x, sb);
+        if (z.act) {
+            if constexpr (CS) strip_apply_lean<L, 1>(SL, xg, z, x, sb);
+            else strip_apply_lean<L, 1>(S, xg, z, x, sb);
+        }
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
             const double bi = sb[i] + r[i];
@@ -931,7 +957,10 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
         double q[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) q[i] = 0.0;
-        if (z.act) strip_apply_lean<L, 1>(S, xg, z, p, q);
+        if (z.act) {
+            if constexpr (CS) strip_apply_lean<L, 1>(SL, xg, z, p, q);
+            else strip_apply_lean<L, 1>(S, xg, z, p, q);
+        }
         double pq[1] = {0.0};
 #pragma unroll
         for (int i = 0; i < L::R; ++i) pq[0] += p[i] * q[i];
@@ -1242,8 +1271,10 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
         });
     } else {
         __shared__ double xs[L::R * NTP];
+        // the corner couplings of the resident stencil (2 x R doubles a lane)
+        __shared__ double cs[2 * L::R * NTP];
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_fp64<L>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch);
+            pack_fp64<L, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs);
         });
     }
 }
@@ -1276,10 +1307,11 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
         });
     } else {
         __shared__ double xs[kFp64Rows * NTP];
+        __shared__ double cs[2 * kFp64Rows * NTP];
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
-            if (lvl == 64) pack_fp64<L64>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch);
-            else if (lvl == 32) pack_fp64<L32>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch);
-            else pack_fp64<L16>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch);
+            if (lvl == 64) pack_fp64<L64, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs);
+            else if (lvl == 32) pack_fp64<L32, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs);
+            else pack_fp64<L16, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs);
         });
     }
 }

@@ -92,20 +92,6 @@ def test_gradient_with_large_meshes():
     assert eJ <= 1e-9 and eg <= 1e-9
 
 
-def test_indicator_refuses_large_meshes():
-    from paper_2103_17040_amd import tsm
-    NM = 2
-    lv = np.array([8, 8, 8, 8, 128, 8, 8, 8, 8], np.int32)
-    g = gpu_for(NM, lv, np.zeros(9))
-    try:
-        g.set_state(W.initial_macro(NM), None)
-        with pytest.raises(tsm.TsmError) as e:
-            g.error_indicator()
-        assert e.value.status == tsm.TSM_ESTATE
-    finally:
-        g.close()
-
-
 @pytest.mark.parametrize("multigrid", [True, False])
 @pytest.mark.parametrize("levels", [[91, 128, 16, 64], [128, 256]])
 def test_stationary_large_meshes(levels, multigrid):
