@@ -126,7 +126,9 @@ typedef struct {
                                 still needs, but no tighter than 2^-18 */
     double setup_rtol;       /* response solves w_i at setup */
     int32_t max_iter;        /* PCG iterations per solve (per inner solve) */
-    int32_t max_refine;      /* FP64 refinement sweeps (refinement mode) */
+    int32_t max_refine;      /* FP64 refinement sweeps (refinement mode); a packed solve
+                                still above rtol after them is solved again from its initial
+                                guess by FP64 Jacobi PCG (tsm_stats.fp64_fallbacks) */
     int32_t checkpoint_every;/* adjoint checkpoint spacing in steps, >= 1 */
     uint64_t flags;          /* TSM_FLAG_* */
     double fp_rtol;          /* TSM_FLAG_FIXED_POINT: stop when the residual sum changes by
@@ -162,6 +164,11 @@ typedef struct {
     int32_t fp_iters_last;       /* TSM_FLAG_FIXED_POINT: coupling iterations of the last step */
     int32_t fp_iters_max;        /* ... and the most over the steps of the last tsm_step call */
     int32_t macro_pcg_iters;     /* macro PCG iterations per solve when PCG is used, else 0 */
+    int32_t fp64_fallbacks;      /* refinement mode: packed solves that missed rtol after
+                                    max_refine sweeps and were solved again in FP64 (Jacobi PCG
+                                    from the step's initial guess), summed over the steps of the
+                                    last tsm_step call; a solve that misses rtol there too counts
+                                    in unconverged */
 } tsm_stats;
 
 typedef struct tsm_ctx tsm_ctx;

@@ -96,6 +96,11 @@ struct tsm_ctx {
     // that runs micro solves side by side)
     double* lg_ws = nullptr;
     int lg_sets = 0;
+    // FP64 recovery of packed refinement solves that miss rtol: the list
+    // the packed kernels fill, and one workspace slot per workgroup
+    int32_t* fb_list = nullptr;
+    double* fb_ws = nullptr;
+    int64_t fb_slot = 0;
     // multigrid-preconditioned micro solves (stationary contexts with
     // TSM_FLAG_MULTIGRID): per-instance coarse levels, Galerkin operators,
     // coarsest inverses, damping, and per-stream workspaces
@@ -211,8 +216,9 @@ struct tsm_ctx {
         dfree(Ss64); dfree(Ks64); dfree(Ss32); dfree(Sslo);
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(Mw); dfree(v0); dfree(S32); dfree(Slo);
-        dfree(bcomp); dfree(lg_ws);
+        dfree(bcomp); dfree(lg_ws); dfree(fb_list); dfree(fb_ws);
         lg_sets = 0;
+        fb_slot = 0;
         free_mg();
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
@@ -286,6 +292,12 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
     // the packed kernels leave b^T x to one boundary pass over their instances
     MicroArgs pbase = base;
     pbase.bx_out = nullptr;
+    // refinement solves that miss rtol are listed and solved again in FP64
+    const bool fb = refine && c->n_packs > 0 && c->fb_list != nullptr && c->fb_ws != nullptr;
+    if (fb) {
+        pbase.fb_list = c->fb_list;
+        HIPCHK(launch_fill_i32(c->fb_list, 0, 1, st));
+    }
     if ((c->prm.flags & TSM_FLAG_PERSISTENT) && c->n_packs > 0) {
         // one persistent launch over every pack; the queue is reset by a
         // kernel so the sequence can be captured in a graph
@@ -312,6 +324,7 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
             HIPCHK(launch_packed(a, pl, pg[0], pmode, pg[2], st));
         }
     }
+    if (fb) HIPCHK(launch_micro_fallback(pbase, c->fb_ws, c->fb_slot, c->n_cu, c->counters, st));
     if (c->n_packs > 0 && base.bx_out != nullptr)
         HIPCHK(launch_bdot_boundary((int)c->n_packed_tasks, c->order, c->level, c->offsets, c->bcomp, base.X_out,
                                     base.bx_out, st));
@@ -771,6 +784,14 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
         // the three micro solves of a stationary context run side by side
         c->lg_sets = c->stationary ? 3 : 1;
         HIPALLOC(c->lg_ws, (size_t)c->lg_sets * 3 * tot);
+    }
+    if (c->prm.precision == TSM_FP32_REFINE) {
+        int nmax = 0;
+        for (int32_t l : c->level_h)
+            if (l <= kMaxLevel) nmax = std::max(nmax, (l + 1) * (l + 1));
+        c->fb_slot = nmax;
+        HIPALLOC(c->fb_list, ni + 1);
+        if (nmax > 0) HIPALLOC(c->fb_ws, (size_t)c->n_cu * 3 * nmax);
     }
     if (c->stationary) {
         HIPALLOC(c->st_bO, tot); HIPALLOC(c->st_lenO, ni);
@@ -1547,8 +1568,10 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
         HIPCHK(hipStreamSynchronize(c->stream));
         HIPCHK(hipMemcpy(it.data(), c->iters, c->n_inst * sizeof(int32_t), hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(sw.data(), c->sweeps, c->n_inst * sizeof(int32_t), hipMemcpyDeviceToHost));
-        int32_t nc = 0;
-        HIPCHK(hipMemcpy(&nc, c->counters, sizeof(int32_t), hipMemcpyDeviceToHost));
+        int32_t cnt[4] = {0, 0, 0, 0};
+        HIPCHK(hipMemcpy(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost));
+        const int32_t nc = cnt[0];
+        s->fp64_fallbacks = cnt[2];
         s->iters_min = *std::min_element(it.begin(), it.end());
         s->iters_max = *std::max_element(it.begin(), it.end());
         double sum = 0;

@@ -400,20 +400,15 @@ hipError_t launch_mode(const MicroArgs& a, int slots, int grid, size_t lds, hipS
 constexpr int NTL = 1024;
 constexpr int NWL = NTL / kWave;
 
-__global__ __launch_bounds__(NTL) void micro_large_kernel(MicroArgs A) {
-    __shared__ double r1[2][1][NWL];
-    __shared__ double r3[2][3][NWL];
-    BlockReducer<NWL, 1, double> red1(r1);
-    BlockReducer<NWL, 3, double> red3(r3);
-    const int inst = A.order[blockIdx.x];
+// FP64 Jacobi PCG of one instance by the whole workgroup, vectors r, p, q
+// given (instance-sized).
+__device__ void pcg_fp64_instance(const MicroArgs& A, int inst, double* r, double* p, double* q,
+                                  BlockReducer<NWL, 1, double>& red1, BlockReducer<NWL, 3, double>& red3) {
     const Geo g = instance_geo(A, inst);
     const int tid = threadIdx.x;
     const double* __restrict__ S = A.S64 + kStencil * g.off;
     const double* __restrict__ M = A.M64 + kStencil * g.off;
     double* x = A.X_out + g.off;
-    double* r = A.ws + g.off;
-    double* p = A.ws + A.ws_stride + g.off;
-    double* q = A.ws + 2 * A.ws_stride + g.off;
     auto nb = [&](int j, int k) {
         const int jj = j + g.dj[k];
         return jj < 0 ? 0 : (jj >= g.n ? g.n - 1 : jj);
@@ -492,6 +487,35 @@ __global__ __launch_bounds__(NTL) void micro_large_kernel(MicroArgs A) {
         if (A.sweeps_out) A.sweeps_out[inst] = 1;
         if (A.res_out) A.res_out[inst] = sqrt(rr);
         if (!conv) atomicAdd(A.nonconv, 1);
+    }
+}
+
+__global__ __launch_bounds__(NTL) void micro_large_kernel(MicroArgs A) {
+    __shared__ double r1[2][1][NWL];
+    __shared__ double r3[2][3][NWL];
+    BlockReducer<NWL, 1, double> red1(r1);
+    BlockReducer<NWL, 3, double> red3(r3);
+    const int inst = A.order[blockIdx.x];
+    const int64_t off = A.offsets[inst];
+    pcg_fp64_instance(A, inst, A.ws + off, A.ws + A.ws_stride + off, A.ws + 2 * A.ws_stride + off, red1, red3);
+}
+
+// The FP64 recovery of the packed refinement solves: the instances the
+// packed kernels listed (missed rtol after max_refine sweeps; their X0 is
+// untouched) solved again from X0 in FP64, each by one workgroup with its
+// own slot of the workspace.
+__global__ __launch_bounds__(NTL) void micro_fallback_kernel(MicroArgs A, double* ws, int64_t slot,
+                                                             int32_t* counters) {
+    __shared__ double r1[2][1][NWL];
+    __shared__ double r3[2][3][NWL];
+    BlockReducer<NWL, 1, double> red1(r1);
+    BlockReducer<NWL, 3, double> red3(r3);
+    const int cnt = A.fb_list[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && cnt > 0) atomicAdd(counters + 2, cnt);
+    double* r = ws + (int64_t)3 * blockIdx.x * slot;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) {
+        pcg_fp64_instance(A, A.fb_list[1 + t], r, r + slot, r + 2 * slot, red1, red3);
+        __syncthreads();     // every lane is done with the vectors before the next instance
     }
 }
 
@@ -582,6 +606,13 @@ hipError_t launch_micro_large(const MicroArgs& a, hipStream_t s) {
     if (a.n_tasks <= 0) return hipSuccess;
     if (a.ws == nullptr) return hipErrorInvalidValue;
     hipLaunchKernelGGL(micro_large_kernel, dim3(a.n_tasks), dim3(NTL), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_micro_fallback(const MicroArgs& a, double* ws, int64_t slot, int grid, int32_t* counters,
+                                 hipStream_t s) {
+    if (a.fb_list == nullptr || ws == nullptr || grid <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(micro_fallback_kernel, dim3(grid), dim3(NTL), 0, s, a, ws, slot, counters);
     return hipGetLastError();
 }
 

@@ -509,9 +509,14 @@ __device__ __forceinline__ void strip_apply_lean(const ST& S0, const TG* g, cons
 template <class L>
 __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, const double (&x)[L::R],
                                            int iters, int sweeps, bool conv, double rr, PackRed<1, double>& red1) {
+    // an instance that missed rtol goes to the FP64 recovery (when there is
+    // one) with X0 untouched; conv is uniform over the instance's lanes
+    const bool hand_off = !conv && A.fb_list != nullptr;
+    if (!hand_off) {
 #pragma unroll
-    for (int i = 0; i < L::R; ++i)
-        if (row_ok<L>(z, i)) A.X_out[z.off + node_of<L>(z, i)] = x[i];
+        for (int i = 0; i < L::R; ++i)
+            if (row_ok<L>(z, i)) A.X_out[z.off + node_of<L>(z, i)] = x[i];
+    }
     double bx[1] = {0.0};
     if (A.bx_out != nullptr) {
 #pragma unroll
@@ -524,7 +529,8 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
         if (A.iters_out) A.iters_out[z.inst] = iters;
         if (A.sweeps_out) A.sweeps_out[z.inst] = sweeps;
         if (A.res_out) A.res_out[z.inst] = sqrt(rr);
-        if (!conv) atomicAdd(A.nonconv, 1);
+        if (hand_off) A.fb_list[1 + atomicAdd(A.fb_list, 1)] = z.inst;
+        else if (!conv) atomicAdd(A.nonconv, 1);
     }
 }
 

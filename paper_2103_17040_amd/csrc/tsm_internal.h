@@ -169,6 +169,11 @@ struct MicroArgs {
     // vectors (r, p, q), ws_stride doubles apart
     double* ws;
     int64_t ws_stride;
+    // FP64 recovery of the packed refinement solves (may be null): an
+    // instance that misses rtol after max_refine sweeps is not stored but
+    // appended to fb_list ([0] count, then instance indices), and
+    // launch_micro_fallback solves it again in FP64 from X0
+    int32_t* fb_list;
 };
 
 // Packs of instances of one mesh size solved by one kPackThreads-lane workgroup.
@@ -225,6 +230,14 @@ hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_
 // instances with more than kMaxLevel cells per side: one 1024-lane workgroup
 // per task, vectors in the workspace a.ws (FP64 in either precision mode)
 hipError_t launch_micro_large(const MicroArgs& a, hipStream_t s);
+// FP64 Jacobi PCG of the instances in a.fb_list (the same right-hand sides
+// and outputs as the packed kernels, b^T x left to the boundary pass), one
+// 1024-lane workgroup per listed instance, `grid` workgroups looping over
+// the list; vectors r, p, q at ws + (3 blockIdx.x + k) * slot.  Adds the
+// list's count to counters[2]; an instance that misses rtol again counts in
+// a.nonconv.
+hipError_t launch_micro_fallback(const MicroArgs& a, double* ws, int64_t slot, int grid, int32_t* counters,
+                                 hipStream_t s);
 
 // Multigrid-preconditioned micro solves (mg.hip).  An instance with
 // N = c 2^L cells per side, c <= kMgCoarsest, L >= 1, has coarse levels

@@ -68,7 +68,7 @@ class tsm_stats(ctypes.Structure):
                 ("grad_forward_ms", ctypes.c_double), ("grad_backward_ms", ctypes.c_double),
                 ("sweeps_mean", ctypes.c_double),
                 ("fp_iters_last", ctypes.c_int32), ("fp_iters_max", ctypes.c_int32),
-                ("macro_pcg_iters", ctypes.c_int32)]
+                ("macro_pcg_iters", ctypes.c_int32), ("fp64_fallbacks", ctypes.c_int32)]
 
 
 class tsm_stationary_params(ctypes.Structure):

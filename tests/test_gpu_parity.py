@@ -70,6 +70,22 @@ def test_small_workload_refine_parity():
     for k in ("u", "F", "v"):
         assert rel(out[k], ref[k]) <= TOL_REFINE, k
     assert out["stats"]["sweeps_max"] >= 2
+    assert out["stats"]["fp64_fallbacks"] == 0
+
+
+def test_fp64_recovery_of_refinement():
+    """Packed refinement solves that still miss rtol after max_refine sweeps
+    are solved again in FP64 from the step's initial guess: with one sweep
+    allowed at rtol 1e-12 every interior solve falls back, and the steps
+    match the oracle as the FP64 form does."""
+    w, a, th, lv, u0, v0, phys = workload_case("small_fp64")
+    ref, out, _ = run_both(w.macro_cells, lv, a, th, w.dt, 4, u0, v0, precision="fp32_refine",
+                           rtol=1e-12, gpu_kw=dict(max_refine=1), **phys)
+    banner(f"  fallbacks in the last step: {out['stats']['fp64_fallbacks']}")
+    assert out["stats"]["fp64_fallbacks"] >= (w.macro_cells - 1) ** 2
+    assert out["stats"]["unconverged"] == 0
+    for k in ("u", "F", "v"):
+        assert rel(out[k], ref[k]) <= TOL_FP64, k
 
 
 @pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, TOL_FP64), ("fp32_refine", 1e-10, TOL_REFINE)])
