@@ -9,9 +9,23 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "tsm_internal.h"
 
 using namespace tsm;
+
+namespace {
+// A roctx range over a library call, so that a marker trace of a profiler
+// (rocprofv3 --marker-trace) shows set-up, steps, gradients and solves
+// around their kernels.  Without a profiler attached the calls do nothing.
+struct Range {
+    explicit Range(const char* name) { roctxRangePush(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+}  // namespace
 
 namespace {
 
@@ -722,6 +736,7 @@ tsm_status tsm_create(const tsm_params* p, void* stream, tsm_ctx** out) {
 }
 
 tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_t n_inst) {
+    const Range range("tsm_set_reference_mesh");
     if (!c) return TSM_EINVAL;
     if (!micro_cells) return c->fail(TSM_EINVAL, "micro_cells is NULL");
     const int64_t expect = (int64_t)(c->NM + 1) * (c->NM + 1);
@@ -1067,6 +1082,7 @@ tsm_status finish_setup(tsm_ctx* c, std::chrono::steady_clock::time_point t0, Wh
 }  // extern "C++"
 
 tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta, int64_t n_inst) {
+    const Range range("tsm_set_deformation");
     if (!c) return TSM_EINVAL;
     if (!c->have_mesh) return c->fail(TSM_ESTATE, "set_reference_mesh first");
     if (!a) return c->fail(TSM_EINVAL, "a is NULL");
@@ -1093,6 +1109,7 @@ tsm_status tsm_set_deformation(tsm_ctx* c, const double* a, const double* theta,
 }
 
 tsm_status tsm_set_jacobians(tsm_ctx* c, const double* Fcell, int64_t n_cell, const double* Fbnd, int64_t n_bnd) {
+    const Range range("tsm_set_jacobians");
     if (!c) return TSM_EINVAL;
     if (!c->have_mesh) return c->fail(TSM_ESTATE, "set_reference_mesh first");
     if (!Fcell || !Fbnd) return c->fail(TSM_EINVAL, "Jacobian table is NULL");
@@ -1154,6 +1171,7 @@ tsm_status tsm_set_state(tsm_ctx* c, const double* u, int64_t n_u, const double*
 }
 
 tsm_status tsm_step(tsm_ctx* c, int32_t n_steps) {
+    const Range range("tsm_step");
     if (!c) return TSM_EINVAL;
     if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
     if (n_steps < 0) return c->fail(TSM_EINVAL, "n_steps < 0");
@@ -1267,6 +1285,7 @@ tsm_status tsm_apply_operator(tsm_ctx* c, const double* x, double* y, int64_t n)
 }
 
 tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda_out, int64_t n) {
+    const Range range("tsm_gradient");
     if (!c) return TSM_EINVAL;
     if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
     if (n_steps < 1) return c->fail(TSM_EINVAL, "n_steps < 1");
@@ -1443,6 +1462,7 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
 }
 
 tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* flags_out) {
+    const Range range("tsm_autotune");
     if (!c) return TSM_EINVAL;
     if (!c->have_state) return c->fail(TSM_ESTATE, "set_state first");
     if (steps < 1) return c->fail(TSM_EINVAL, "steps < 1");
@@ -1589,6 +1609,7 @@ tsm_status tsm_get_stats(const tsm_ctx* cc, tsm_stats* s) {
 const char* tsm_last_error(const tsm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 tsm_status tsm_error_indicator(tsm_ctx* c, double* eta2_out, int64_t n) {
+    const Range range("tsm_error_indicator");
     if (!c) return TSM_EINVAL;
     if (!eta2_out) return c->fail(TSM_EINVAL, "eta2_out is NULL");
     if (n != c->n_inst) return c->fail(TSM_EINVAL, "eta2_out must hold n_inst = " + std::to_string(c->n_inst) + " entries");
@@ -1752,6 +1773,7 @@ tsm_status tsm_stationary_create(const tsm_stationary_params* sp, void* stream, 
 
 tsm_status tsm_stationary_solve(tsm_ctx* c, double* u_out, double* w_out, int64_t n_inst, double* v_out,
                                 int64_t n_v) {
+    const Range range("tsm_stationary_solve");
     if (!c) return TSM_EINVAL;
     if (!c->stationary) return c->fail(TSM_ESTATE, "not a stationary context (tsm_stationary_create)");
     if (!c->have_geom) return c->fail(TSM_ESTATE, "set_deformation or set_jacobians first");
