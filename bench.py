@@ -263,6 +263,35 @@ def general_map_leg(steps, precision="fp32_refine", rtol=1e-10):
             "micro_dofs": int(W.offsets(lv)[-1]), "iters_mean": st["iters_mean"], "precision": precision}
 
 
+def macro_pcg_leg(steps=5):
+    """The macro solve of a heterogeneous batch: 4225 instances of 16/32
+    cells scaled by s ~ U[0.1, 8] (so the micro responses beta_i spread over
+    a factor of 50), dt = 30, kappa = 10 and D = 1e-6, where the sweep's
+    contraction bound exceeds 0.5 and the library solves A_M by PCG with the
+    sine-basis preconditioner; per-phase times from TSM_FLAG_TIMING."""
+    from paper_2103_17040_amd import TwoScaleBatch, tsm
+    NM = 64
+    n = (NM + 1) ** 2
+    rng = np.random.default_rng(3)
+    lv = rng.choice(np.array([16, 32], np.int32), n)
+    sc = rng.uniform(0.1, 8.0, n)
+    _, Fc, Fb = W.jacobian_tables(lv, W.scaling_map_jacobian, [(x,) for x in sc])
+    g = TwoScaleBatch(NM, lv, jacobians=(Fc, Fb), dt=30.0, D=1e-6, d=0.5, kappa=10.0, p=1.0, precision="fp64",
+                      rtol=1e-10, max_iter=20000, flags=tsm.TSM_FLAG_TIMING)
+    try:
+        g.set_state(W.initial_macro(NM), None)
+        g.step(1)
+        g.step(steps)
+        st = g.stats()
+    finally:
+        g.close()
+    ts = max(st["timed_steps"], 1)
+    return {"workload": f"{n} instances, 16/32 cells, cells scaled by U[0.1, 8], dt 30, kappa 10, D 1e-6",
+            "macro_contraction_bound": st["macro_contraction"], "macro_pcg_iters": st["macro_pcg_iters"],
+            "macro_ms_per_step": st["macro_ms"] / ts, "micro_ms_per_step": st["micro_ms"] / ts,
+            "steps": steps, "unconverged": st["unconverged"]}
+
+
 GOLD = os.path.join(ROOT, "tests", "golden")
 
 
@@ -892,6 +921,8 @@ def main():
                                           W.polynomial_map_params(len(lvu), seed=2)[:16])
             gm["cpu_oracle"] = oracle_rate(wu, lvu[:16], au, thu, jacobians=per)
     if args.gm_steps > 0:
+        _log("heterogeneous macro leg ...")
+        out["general_map"]["heterogeneous_macro_pcg"] = macro_pcg_leg()
         _log("refinement leg ...")
         out["refinement"] = refinement_leg()
         if not args.no_cpu_baseline:

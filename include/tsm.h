@@ -85,7 +85,8 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
                                             the sine-basis solve of A_M's tensor part as
                                             preconditioner even where the sweep would do (it is
                                             used anyway where the sweep's contraction bound is
-                                            0.5 or more) */
+                                            0.5 or more, or where PCG needs fewer operations than
+                                            the sweeps at that bound) */
 #define TSM_FLAG_MULTIGRID  (1ull << 11) /* stationary contexts: the micro solves of every mesh
                                             with N = c 2^L cells per side (c <= 8, L >= 1) by CG
                                             preconditioned with one geometric multigrid V-cycle

@@ -170,8 +170,9 @@ struct tsm_ctx {
     // iteration count from the condition bound (0: A_M not shown SPD)
     double *mp_z = nullptr, *mp_p = nullptr, *mp_q = nullptr, *mp_s = nullptr;
     int macro_pcg_iters = 0;
+    bool macro_pcg_cheaper = false;   // fewer operations than the sweeps at this contraction bound
     bool macro_pcg() const {
-        return macro_pcg_iters > 0 && (rho >= 0.5 || (prm.flags & TSM_FLAG_MACRO_PCG));
+        return macro_pcg_iters > 0 && (rho >= 0.5 || macro_pcg_cheaper || (prm.flags & TSM_FLAG_MACRO_PCG));
     }
     // alternating (fixed-point) coupling: macro operator with beta = kappa p
     // (eigenvalues lam_fp), full micro state vf, rhs M v^n, previous macro
@@ -1067,6 +1068,10 @@ tsm_status finish_setup(tsm_ctx* c, std::chrono::steady_clock::time_point t0, Wh
     int sweeps = 2;
     if (c->rho > 0) sweeps = std::max(2, (int)std::ceil(std::log(1e-17) / std::log(std::min(c->rho, 0.5))));
     c->macro_sweeps = std::min(sweeps, 64);
+    // a PCG iteration costs about 1.2 sweeps (the same four GEMMs, two
+    // one-workgroup kernels instead of the residual kernel)
+    const int sweeps_needed = c->rho > 0 ? (int)std::ceil(std::log(1e-17) / std::log(c->rho)) : 2;
+    c->macro_pcg_cheaper = c->rho < 1.0 && c->macro_pcg_iters > 0 && 6 * c->macro_pcg_iters < 5 * sweeps_needed;
     HIPCHK(hipMemcpy(c->Q, Qh.data(), Qh.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->lam, lh.data(), lh.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->lam_fp, lf.data(), lf.size() * sizeof(double), hipMemcpyHostToDevice));

@@ -12,20 +12,12 @@ from oracle import adjoint, twoscale
 pytestmark = pytest.mark.gpu
 
 
-def _scale_map(y1, y2, s):
-    y1 = np.asarray(y1, dtype=np.float64)
-    M = np.zeros(y1.shape + (2, 2))
-    M[..., 0, 0] = s
-    M[..., 1, 1] = s
-    return M
-
-
 def _heterogeneous(NM, seed):
     n = (NM + 1) ** 2
     rng = np.random.default_rng(seed)
     lv = rng.choice(np.array([8, 16]), n).astype(np.int32)
     s = rng.uniform(0.2, 4.0, n)
-    per, Fc, Fb = W.jacobian_tables(lv, _scale_map, [(x,) for x in s])
+    per, Fc, Fb = W.jacobian_tables(lv, W.scaling_map_jacobian, [(x,) for x in s])
     return lv, per, Fc, Fb
 
 

@@ -222,6 +222,16 @@ def polynomial_map_jacobian(y1, y2, c, d, theta):
     return np.einsum("ij,...jk->...ik", R, M)
 
 
+def scaling_map_jacobian(y1, y2, s):
+    """D zeta of zeta(y) = s y: cells scaled by s, so the micro responses
+    (and the coefficients of the macro system) vary with s."""
+    y1 = np.asarray(y1, dtype=np.float64)
+    M = np.zeros(y1.shape + (2, 2))
+    M[..., 0, 0] = s
+    M[..., 1, 1] = s
+    return M
+
+
 def sinusoidal_map_jacobian(y1, y2, a, theta):
     """D zeta of the workloads' family zeta(y) = R_theta (y + a phi(y)),
     phi = (sin(pi y1) y2, sin(pi y2) y1)/4 (for checking the table layout)."""
