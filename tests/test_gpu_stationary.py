@@ -390,3 +390,28 @@ def test_multigrid_iterations_at_paper_size():
     assert max(mg[3]["micro_iters_max"]) <= 60
     for a, b in zip(jac[:3], mg[:3]):
         assert rel(b, a) <= 1e-10
+
+
+def test_multigrid_flags_switch_on_a_live_context():
+    """tsm_set_flags on a stationary context rebuilds the task plan and the
+    multigrid hierarchy: Jacobi, V-cycle on every size, V-cycle only above
+    64 cells, in turn on one context, all agreeing within the tolerance."""
+    from paper_2103_17040_amd import StationarySystem, tsm
+    NM = 3
+    levels = np.asarray([[16, 128, 32, 64][i % 4] for i in range(16)], dtype=np.int32)
+    _, Fc, Fb = _case_tables("B", NM, levels)
+    banner("stationary multigrid flags on a live context")
+    g = StationarySystem(NM, levels, jacobians=(Fc, Fb), fv=1.0, rtol=1e-14, flags=tsm.TSM_FLAG_NO_MULTIGRID, **PHYS)
+    try:
+        outs, iters = [], []
+        for fl in (tsm.TSM_FLAG_NO_MULTIGRID, tsm.TSM_FLAG_MULTIGRID, 0):
+            g.set_flags(fl)
+            outs.append([t.cpu().numpy() for t in g.solve()])
+            iters.append(g.stats()["micro_iters_max"][0])
+    finally:
+        g.close()
+    banner(f"  micro iterations (max): Jacobi {iters[0]}, V-cycle {iters[1]}, default {iters[2]}")
+    assert iters[1] < iters[0] / 5
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert rel(b, a) <= TOL
