@@ -1,4 +1,4 @@
-// Geometric multigrid as the preconditioner of the micro CG (Section 3.3:
+// Geometric multigrid as the preconditioner of the micro CG (Section 3.5:
 // the micro systems are solved by CG; the preconditioner is this library's
 // choice).  The stationary micro operator S = Dv A + k2 B^I + k4 B^O has no
 // mass term, so the Jacobi-preconditioned CG needs O(N) iterations on an
