@@ -59,6 +59,11 @@ FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 33.0, 43.0   # (refine: S x0 replaces 
 # entries (3 ADD + 1 FMA); K x0 on the 4 corners (16 FMA); the node sums
 # (~10 ADD): 4 * 69 + 50 + 32 + 10 = 368 flops.
 FLOP_OPERATOR_MF = 368.0
+# The extrapolated start of the first inner solve, per DoF: e1 = X0 - hx and
+# the linear extrapolation (3), the guess's residual r - S d0 (9 FMA + 1 ADD)
+# and the two dot products of the guessed and plain residuals (2 x (MUL +
+# FMA)) = 24 flops.
+FLOP_GUESS = 24.0
 # Bytes the instance-resident micro kernel must move per DoF per step
 # (algorithmic: the vectors of the iterations stay on chip; operators are read
 # from their symmetric upper-half planes, 5 coefficients per node):
@@ -73,6 +78,9 @@ FLOP_OPERATOR_MF = 368.0
 #               (40; it also gives ||b|| = ||S x0 + r|| and diag^{-1})
 B_START, B_K, B_END = 16.0, 40.0, 8.0
 B_S64, B_S32, B_SLO = 40.0, 20.0, 20.0
+#   extrapolated start (refinement, assembled operator): the previous X0
+#   and increment read and written in FP32 (8 + 8)
+B_HIST = 16.0
 
 
 PACKED_LEVELS = (16, 32, 64)
@@ -87,9 +95,15 @@ def packed_under(N, flags):
 
 def matrix_free(N, flags, refine):
     """Whether the packed refinement kernel evaluates the operator from the
-    amplitudes (the default of the per-size plan) instead of reading the
-    assembled planes (the stored-operator flag, and the persistent plans)."""
-    return refine and packed_under(N, flags) and not (flags & ((1 << 9) | (1 << 4)))
+    amplitudes (the matrix-free flag on a per-size plan) instead of reading
+    the assembled planes."""
+    return refine and packed_under(N, flags) and bool(flags & (1 << 9)) and not (flags & (1 << 4))
+
+
+def extrapolated(N, flags, refine):
+    """Whether the packed refinement kernel starts its first inner solve from
+    the extrapolated increment (assembled operator, unless switched off)."""
+    return refine and packed_under(N, flags) and not matrix_free(N, flags, refine) and not (flags & (1 << 13))
 
 
 def micro_bytes_per_dof(N, flags, refine, iters, sweeps):
@@ -103,7 +117,8 @@ def micro_bytes_per_dof(N, flags, refine, iters, sweeps):
         if matrix_free(N, flags, refine):
             return B_START + B_END + bdot
         if refine:
-            return B_START + B_K + B_S32 + B_SLO + B_END + bdot
+            hist = B_HIST if extrapolated(N, flags, refine) else 0.0
+            return B_START + B_K + B_S32 + B_SLO + B_END + hist + bdot
         return B_START + B_K + B_S64 + B_END + bdot
     slots = next(s for s in GENERIC_SLOTS if s * 256 >= (N + 1) ** 2)
     if refine:   # FP32 stencil once (resident) or per inner iteration; FP64 rows per residual
@@ -800,8 +815,9 @@ def main():
     dofs_per_launch = n_dofs / max(tst["micro_launches"], 1)
     plan_flags = main_form["plan"]["flags"]
     mf_dofs = sum((N + 1) ** 2 for N in lv.tolist() if matrix_free(int(N), plan_flags, refine))
+    ex_dofs = sum((N + 1) ** 2 for N in lv.tolist() if extrapolated(int(N), plan_flags, refine))
     flops = (dofs_per_launch * (FLOP_ITER * iters + FLOP_SWEEP * sweeps + FLOP_SOLVE)
-             + mf_dofs / max(tst["micro_launches"], 1) * FLOP_OPERATOR_MF)
+             + (mf_dofs * FLOP_OPERATOR_MF + ex_dofs * FLOP_GUESS) / max(tst["micro_launches"], 1))
     step_bytes = sum((N + 1) ** 2 * micro_bytes_per_dof(int(N), plan_flags, refine, iters, sweeps)
                      for N in lv.tolist())
     nbytes = step_bytes / max(tst["micro_launches"], 1)

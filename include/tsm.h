@@ -75,12 +75,16 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
                                             workgroup per compute unit) with a work queue
                                             (largest meshes first), instead of one launch per
                                             mesh size with one workgroup per pack */
-#define TSM_FLAG_STORED_OPERATOR (1ull << 9) /* the packed refinement kernels read the operator
-                                            assembled at setup (FP32 planes and the FP64 K planes)
-                                            instead of evaluating it matrix-free from the
-                                            amplitudes at the start of every solve (Section 3.1:
-                                            J and K K^T J at the quadrature points).  Geometry from
-                                            Jacobian tables always uses the assembled operator. */
+#define TSM_FLAG_MATRIX_FREE (1ull << 9) /* per-size launch plans (not TSM_FLAG_PERSISTENT): the
+                                            packed refinement kernels evaluate the time-step
+                                            operator matrix-free from the amplitudes at the start
+                                            of every solve (Section 3.1: J and K K^T J at the
+                                            quadrature points) instead of reading the operator
+                                            assembled at setup.  Opt-in only: it is slower than
+                                            the assembled operator, tsm_autotune never picks it
+                                            by itself, and it has no extrapolated start.  Geometry
+                                            from Jacobian tables always uses the assembled
+                                            operator. */
 #define TSM_FLAG_MACRO_PCG  (1ull << 10) /* solve the macro system (forward and adjoint) by PCG with
                                             the sine-basis solve of A_M's tensor part as
                                             preconditioner even where the sweep would do (it is
@@ -97,6 +101,19 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
                                             are faster at 64 and below); the other sizes keep
                                             Jacobi either way. */
 #define TSM_FLAG_NO_MULTIGRID (1ull << 12) /* stationary contexts: Jacobi for every mesh */
+#define TSM_FLAG_NO_EXTRAPOLATION (1ull << 13) /* FP32_REFINE time steps: start every first
+                                            inner solve from zero.  By default the packed
+                                            refinement kernels with the assembled operator start
+                                            it from the increment extrapolated linearly from the
+                                            last two steps (two FP32 values of history per micro
+                                            DoF; an instance whose guessed residual is not smaller
+                                            drops the guess).  The FP64 residual of the
+                                            refinement takes the guess in exactly, so results meet
+                                            rtol either way; they differ in rounding only.  The
+                                            history restarts at tsm_set_state, tsm_set_flags and
+                                            every change of the state other than a tsm_step;
+                                            tsm_gradient's forward and recomputed steps do not
+                                            use it. */
 #define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
                                             HIP events on the context's stream (see tsm_stats) */
 #define TSM_FLAG_FIXED_POINT (1ull << 5) /* tsm_step couples macro and micro solves by the paper's
@@ -312,13 +329,15 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags);
  * `steps` steps each (after one warm-up step) from the current state, then,
  * from the faster packed plan, move one packed mesh size at a time to the
  * one-instance-per-workgroup kernel (TSM_FLAG_GENERIC_16/32/64) while that
- * is faster, then (refinement mode, packed plan, amplitude geometry) time the
- * chosen plan with the other form of the operator (TSM_FLAG_STORED_OPERATOR
- * toggled); restore the state after every trial and keep the fastest plan.
+ * is faster, then, if the caller asked for the matrix-free operator
+ * (TSM_FLAG_MATRIX_FREE; refinement mode, packed plan, amplitude geometry),
+ * time the chosen plan with the assembled operator; restore the state after
+ * every trial and keep the fastest plan.  The matrix-free form is never
+ * tried unless asked for.
  * ms_out[5] (host, may be NULL): ms per step of the per-size, persistent and
  * generic plans in the caller's operator form (-1 where a plan does not
- * apply), of the chosen plan, and of the runner-up operator form of the
- * chosen plan (-1 if not tried); *flags_out (host, may be NULL): the chosen
+ * apply), of the chosen plan, and of the chosen plan with the assembled
+ * operator (-1 if not tried); *flags_out (host, may be NULL): the chosen
  * TSM_FLAG_* plan bits.  Needs set_state first. */
 tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* flags_out);
 

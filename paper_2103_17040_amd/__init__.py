@@ -172,7 +172,7 @@ class TwoScaleBatch:
         self._flags = (self._flags & ~tsm.PLAN_BITS) | flags
         res = {"flags": flags, "plan": tsm.plan_name(flags),
                "ms_per_step": {"per_size": ms[0], "persistent": ms[1], "generic": ms[2], "chosen": ms[3],
-                               "other_operator_form": ms[4]}}
+                               "assembled_operator": ms[4]}}
         if cache is not None:
             rec = {}
             if os.path.exists(cache):

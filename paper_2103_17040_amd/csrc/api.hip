@@ -115,6 +115,12 @@ struct tsm_ctx {
     int32_t* fb_list = nullptr;
     double* fb_ws = nullptr;
     int64_t fb_slot = 0;
+    // history of the extrapolated start of the forward refinement solves:
+    // the previous X0 and increment (FP32 per micro DoF) and the number of
+    // steps they cover (device counter, advanced inside the step graph)
+    float* hx = nullptr;
+    float* he = nullptr;
+    int32_t* hn = nullptr;
     // multigrid-preconditioned micro solves (stationary contexts with
     // TSM_FLAG_MULTIGRID): per-instance coarse levels, Galerkin operators,
     // coarsest inverses, damping, and per-stream workspaces
@@ -231,7 +237,7 @@ struct tsm_ctx {
         dfree(Ss64); dfree(Ks64); dfree(Ss32); dfree(Sslo);
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(Mw); dfree(v0); dfree(S32); dfree(Slo);
-        dfree(bcomp); dfree(lg_ws); dfree(fb_list); dfree(fb_ws);
+        dfree(bcomp); dfree(lg_ws); dfree(fb_list); dfree(fb_ws); dfree(hx); dfree(he); dfree(hn);
         lg_sets = 0;
         fb_slot = 0;
         free_mg();
@@ -295,18 +301,25 @@ namespace {
 // or another for launches that run beside it).
 tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st, int32_t* queue, int set = 0) {
     const bool refine = c->prm.precision == TSM_FP32_REFINE && !setup;
-    // the packed refinement kernels evaluate the operator from the
-    // amplitudes (time-step form: right-hand side M x0/dt with M w) unless
-    // the geometry came from tables or the assembled operator is asked for;
-    // the persistent launch plans read the assembled operator (their
-    // matrix-free form is switched off: a run of it faulted the GPU and its
-    // cause is not found)
+    // the packed refinement kernels read the operator assembled at setup;
+    // per-size plans evaluate it from the amplitudes instead when asked
+    // (TSM_FLAG_MATRIX_FREE; time-step form: right-hand side M x0/dt with
+    // M w).  The persistent plans never do: a run of their matrix-free form
+    // faulted the GPU and its cause is not found.
     const bool mf = refine && base.rhs_vec == nullptr && base.Mw != nullptr && !base.zero_init && !c->geom_tables &&
-                    !c->stationary && !(c->prm.flags & (TSM_FLAG_STORED_OPERATOR | TSM_FLAG_PERSISTENT));
+                    !c->stationary && (c->prm.flags & TSM_FLAG_MATRIX_FREE) &&
+                    !(c->prm.flags & TSM_FLAG_PERSISTENT);
     const int pmode = refine ? (mf ? 3 : 2) : 1;
     // the packed kernels leave b^T x to one boundary pass over their instances
     MicroArgs pbase = base;
     pbase.bx_out = nullptr;
+    // the extrapolated start (history of the forward step) belongs to the
+    // stored-operator refinement kernels only
+    if (pmode != 2 || c->n_packs == 0) {
+        pbase.hx = nullptr;
+        pbase.he = nullptr;
+        pbase.hn = nullptr;
+    }
     // refinement solves that miss rtol are listed and solved again in FP64
     const bool fb = refine && c->n_packs > 0 && c->fb_list != nullptr && c->fb_ws != nullptr;
     if (fb) {
@@ -339,6 +352,7 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
             HIPCHK(launch_packed(a, pl, pg[0], pmode, pg[2], st));
         }
     }
+    if (pbase.hx != nullptr) HIPCHK(launch_history_advance(c->hn, st));
     if (fb) HIPCHK(launch_micro_fallback(pbase, c->fb_ws, c->fb_slot, c->n_cu, c->counters, st));
     if (c->n_packs > 0 && base.bx_out != nullptr)
         HIPCHK(launch_bdot_boundary((int)c->n_packed_tasks, c->order, c->level, c->offsets, c->bcomp, base.X_out,
@@ -553,6 +567,11 @@ tsm_status enqueue_step(tsm_ctx* c, const hipEvent_t* ev = nullptr) {
     a.rhs_vec = nullptr;
     a.zero_init = 0;
     a.X_out = c->v0;
+    if (c->hx != nullptr && !(c->prm.flags & TSM_FLAG_NO_EXTRAPOLATION)) {
+        a.hx = c->hx;
+        a.he = c->he;
+        a.hn = c->hn;
+    }
     tsm_status st = enqueue_micro(c, a, false);
     if (st != TSM_OK) return st;
     if (ev) HIPCHK(hipEventRecord(ev[1], c->stream));
@@ -623,6 +642,13 @@ tsm_status step_fixed_point(tsm_ctx* c) {
     HIPCHK(launch_state_split((int)ni, c->offsets, c->u, c->vf, c->w, c->v0, s));       // back to (v0, u)
     c->fp_iters_last = it;
     c->fp_iters_max = std::max(c->fp_iters_max, it);
+    return TSM_OK;
+}
+
+// The history of the extrapolated start no longer follows the state: the
+// next steps start without it (a fill kernel on the context's stream).
+tsm_status reset_history(tsm_ctx* c) {
+    if (c->hn != nullptr) HIPCHK(launch_fill_i32(c->hn, 0, 1, c->stream));
     return TSM_OK;
 }
 
@@ -808,6 +834,10 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
         c->fb_slot = nmax;
         HIPALLOC(c->fb_list, ni + 1);
         if (nmax > 0) HIPALLOC(c->fb_ws, (size_t)c->n_cu * 3 * nmax);
+        if (!c->stationary) {
+            HIPALLOC(c->hx, tot); HIPALLOC(c->he, tot); HIPALLOC(c->hn, 1);
+            HIPCHK(launch_fill_i32(c->hn, 0, 1, c->stream));
+        }
     }
     if (c->stationary) {
         HIPALLOC(c->st_bO, tot); HIPALLOC(c->st_lenO, ni);
@@ -1169,6 +1199,7 @@ tsm_status tsm_set_state(tsm_ctx* c, const double* u, int64_t n_u, const double*
     HIPCHK(hipMemcpy(c->u, uh.data(), c->n_inst * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(launch_state_split((int)c->n_inst, c->offsets, c->u, v, c->w, c->v0, c->stream));
     HIPCHK(hipMemsetAsync(c->F, 0, c->n_inst * sizeof(double), c->stream));
+    if (reset_history(c) != TSM_OK) return TSM_EHIP;
     HIPCHK(hipStreamSynchronize(c->stream));
     c->steps_taken = 0;
     c->have_state = true;
@@ -1205,6 +1236,8 @@ tsm_status tsm_step(tsm_ctx* c, int32_t n_steps) {
         }
     }
     HIPCHK(hipEventRecord(c->ev1, c->stream));
+    // the alternating step moves the state without the history
+    if (fixed_point && n_steps > 0 && reset_history(c) != TSM_OK) return TSM_EHIP;
     int32_t nc = 0;
     HIPCHK(hipMemcpyAsync(&nc, c->counters, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1334,6 +1367,9 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
                 HIPCHK(hipMemcpyAsync(ck_u + (size_t)(n / K) * ni, c->u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
                 HIPCHK(hipMemcpyAsync(ck_v + (size_t)(n / K) * tot, c->v0, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
             }
+            // every step of the tape starts without the extrapolated guess, so
+            // that the recomputed segments repeat it bitwise
+            if (reset_history(c) != TSM_OK) return TSM_EHIP;
             if (c->graph) {
                 HIPCHK(hipGraphLaunch(c->graph, s));
             } else {
@@ -1357,6 +1393,7 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
             HIPCHK(hipMemcpyAsync(c->v0, ck_v + (size_t)sg * tot, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
             HIPCHK(launch_state_join((int)ni, c->offsets, c->u, c->v0, c->w, V, s));
             for (int n = a + 1; n <= e; ++n) {
+                if (reset_history(c) != TSM_OK) return TSM_EHIP;
                 if (c->graph) {
                     HIPCHK(hipGraphLaunch(c->graph, s));
                 } else {
@@ -1409,6 +1446,7 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
         HIPCHK(hipMemcpyAsync(c->u, save_u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
         HIPCHK(hipMemcpyAsync(c->v0, save_v, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
         HIPCHK(hipMemcpyAsync(c->F, save_F, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (reset_history(c) != TSM_OK) return TSM_EHIP;
         int32_t nc = 0;
         HIPCHK(hipMemcpyAsync(&nc, c->counters, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -1449,11 +1487,13 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
                                                     TSM_FLAG_MULTIGRID | TSM_FLAG_NO_MULTIGRID)) != 0;
     if (flags & ~(TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_TIMING | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT |
                   TSM_FLAG_FIXED_POINT | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64 |
-                  TSM_FLAG_STORED_OPERATOR | TSM_FLAG_MACRO_PCG | TSM_FLAG_MULTIGRID | TSM_FLAG_NO_MULTIGRID))
+                  TSM_FLAG_MATRIX_FREE | TSM_FLAG_MACRO_PCG | TSM_FLAG_MULTIGRID | TSM_FLAG_NO_MULTIGRID |
+                  TSM_FLAG_NO_EXTRAPOLATION))
         return c->fail(TSM_EINVAL, "unknown flag bits");
     const bool mg_changed = ((flags ^ c->prm.flags) & (TSM_FLAG_MULTIGRID | TSM_FLAG_NO_MULTIGRID)) != 0;
     HIPCHK(hipStreamSynchronize(c->stream));
     c->prm.flags = flags;
+    if (reset_history(c) != TSM_OK) return TSM_EHIP;
     if (replan && c->have_mesh) {
         tsm_status st = plan_tasks(c);
         if (st != TSM_OK) return st;
@@ -1474,12 +1514,13 @@ tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* fla
     const int64_t ni = c->n_inst, tot = c->total;
     // plans are timed with the whole-step events (TSM_FLAG_TIMING would turn the graph off)
     const uint64_t plan_bits = TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 |
-                               TSM_FLAG_GENERIC_64 | TSM_FLAG_STORED_OPERATOR;
+                               TSM_FLAG_GENERIC_64 | TSM_FLAG_MATRIX_FREE;
     const uint64_t timing = c->prm.flags & TSM_FLAG_TIMING;
     const uint64_t keep = c->prm.flags & ~(plan_bits | TSM_FLAG_TIMING);
     const uint64_t entry_flags = c->prm.flags;
-    // stages 1 and 2 keep the caller's operator form; stage 3 tries the other
-    const uint64_t op_form = c->prm.flags & TSM_FLAG_STORED_OPERATOR;
+    // stages 1 and 2 keep the caller's operator form; stage 3 tries the
+    // assembled one when the caller asked for the matrix-free form
+    const uint64_t op_form = c->prm.flags & TSM_FLAG_MATRIX_FREE;
     double ms[5] = {-1.0, -1.0, -1.0, -1.0, -1.0};
     double *su = nullptr, *sv = nullptr, *sF = nullptr;
     if (dalloc(&su, ni) != hipSuccess || dalloc(&sv, tot) != hipSuccess || dalloc(&sF, ni) != hipSuccess) {
@@ -1538,15 +1579,15 @@ tsm_status tsm_autotune(tsm_ctx* c, int32_t steps, double* ms_out, uint64_t* fla
         }
     }
     if (ms[2] >= 0 && ms[2] < best_ms) { best = TSM_FLAG_GENERIC | op_form; best_ms = ms[2]; }
-    // stage 3: the chosen plan with the other form of the packed refinement
-    // operator (matrix-free from the amplitudes, or assembled at setup)
-    const bool op_choice = packs && !(best & TSM_FLAG_GENERIC) && c->prm.precision == TSM_FP32_REFINE &&
-                           !c->geom_tables;
+    // stage 3 (the caller asked for the matrix-free operator): the chosen
+    // plan with the assembled operator instead
+    const bool op_choice = op_form != 0 && packs && !(best & TSM_FLAG_GENERIC) &&
+                           c->prm.precision == TSM_FP32_REFINE && !c->geom_tables;
     if (op_choice && st == TSM_OK) {
-        trial(best ^ TSM_FLAG_STORED_OPERATOR, ms[4]);
+        trial(best & ~TSM_FLAG_MATRIX_FREE, ms[4]);
         if (ms[4] >= 0 && ms[4] < best_ms) {
             std::swap(best_ms, ms[4]);
-            best ^= TSM_FLAG_STORED_OPERATOR;
+            best &= ~TSM_FLAG_MATRIX_FREE;
         }
     }
     ms[3] = best_ms;

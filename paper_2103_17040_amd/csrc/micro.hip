@@ -589,6 +589,11 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, int n) {
     if (i < n) p[i] = v;
 }
 
+// One more step of history for the extrapolated start (at most two are used).
+__global__ void history_advance_kernel(int32_t* hn) {
+    if (threadIdx.x == 0) hn[0] = hn[0] < 2 ? hn[0] + 1 : 2;
+}
+
 }  // namespace
 
 hipError_t launch_micro(const MicroArgs& a, int slots, int mode, int grid, size_t lds, hipStream_t s) {
@@ -648,6 +653,11 @@ hipError_t launch_bnd_gather(int n_inst, const int32_t* level, const int64_t* of
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_history_advance(int32_t* hn, hipStream_t s) {
+    hipLaunchKernelGGL(history_advance_kernel, dim3(1), dim3(64), 0, s, hn);
     return hipGetLastError();
 }
 

@@ -81,6 +81,18 @@ using L64 = Lvl<64, 768, 6>;
 // Every use orders LDS accesses alone.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Element at a 32-bit byte offset from a wave-uniform base: the load takes
+// the base in scalar registers and one 32-bit offset register per lane
+// (an element index scaled in 64 bits needs a 64-bit address per load).
+template <typename T>
+__device__ __forceinline__ T& at_byte(T* base, uint32_t byte_off) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ const T& at_byte(const T* base, uint32_t byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 // Per-instance sums of NV values (NV <= 4).  Level 1: every wave reduces its
 // lanes into lane 63 (wave_total_last), which writes the NV totals to LDS.
 // Level 2, after the one barrier: lane l < IPP*WPI reads wave l's totals and
@@ -548,33 +560,85 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
 // FP32 planes into LDS (planes_copy_start) once x0 is in the grid, so that it
 // overlaps the operator application; the caller waits for it
 // (planes_copy_wait).
+// hslot (non-null, time-step form with a history, A.hx): the predicted
+// increment of the step (2 e1 - e2, or e1 with one step of history, 0 with
+// none) goes to the lane's slots hslot[i * NTP + lane] (every lane writes
+// all of its slots), and the history moves on (hx = X0, he = e1).  Returns
+// the steps of history used (-1: no history).
 template <class L>
-__device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, double* xg, double (&x)[L::R],
-                                           double (&r)[L::R], double& bb, const float* copy_src = nullptr,
-                                           float* copy_dst = nullptr, int copy_shift = 0) {
+__device__ __forceinline__ int pack_start(const MicroArgs& A, const Lane& z, double* xg, double (&x)[L::R],
+                                          double (&r)[L::R], double& bb, const float* copy_src = nullptr,
+                                          float* copy_dst = nullptr, int copy_shift = 0, float* hslot = nullptr) {
     zero_halo<L, double>(xg, z);
     const double cf = (z.live && A.coef != nullptr) ? A.coef[z.inst] : 0.0;
     // time step with M w: start from X0 alone; the right-hand side keeps
     // coef w through cm[i] = coef (M w)_j / dt
     const bool use_mw = A.rhs_vec == nullptr && A.Mw != nullptr && !A.zero_init;
+    const int hn = (hslot != nullptr && use_mw && A.hx != nullptr) ? *A.hn : -1;
+    // The loads are unconditional -- rows past the mesh and spare lanes read
+    // node 0 of their instance (of instance 0), values discarded -- so that
+    // all of a lane's loads are in flight together: a load under a per-row
+    // branch is waited for at the end of its branch, one round trip per row.
+    // the instance's arrays (wave-uniform bases) and the lane's nodes
+    const bool load_x = !A.zero_init;
+    const double* px = (load_x ? A.X0 : A.b) + z.off;          // A.b: any FP64 array of the layout
+    const double* pm = (use_mw ? A.Mw : (load_x && A.w != nullptr ? A.w : A.b)) + z.off;
+    uint32_t jr[L::R];     // unsigned: a wave-uniform base plus a 32-bit lane offset
+#pragma unroll
+    for (int i = 0; i < L::R; ++i) jr[i] = row_ok<L>(z, i) ? (uint32_t)node_of<L>(z, i) : 0u;
+    double lx[L::R], lm[L::R];
+    float lh[L::R], le[L::R];
+#pragma unroll
+    for (int i = 0; i < L::R; ++i) {
+        lx[i] = at_byte(px, 8u * jr[i]);
+        lm[i] = at_byte(pm, 8u * jr[i]);
+    }
+    if (hn >= 0) {
+        const float* ph = A.hx + z.off;
+        const float* pe = A.he + z.off;
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) {
+            lh[i] = at_byte(ph, 4u * jr[i]);
+            le[i] = at_byte(pe, 4u * jr[i]);
+        }
+    }
+    // every load is issued before the first value is used
+    asm volatile("" ::: "memory");
     double cm[L::R];
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
-        double v = 0.0, m = 0.0;
-        if (row_ok<L>(z, i) && !A.zero_init) {
-            const int j = node_of<L>(z, i);
-            if (use_mw) {
-                v = A.X0[z.off + j];
-                m = cf * A.inv_dt * A.Mw[z.off + j];
-            } else {
-                v = A.X0[z.off + j] + cf * A.w[z.off + j];
-            }
+        const bool ok = row_ok<L>(z, i);
+        x[i] = (ok && load_x) ? (use_mw ? lx[i] : lx[i] + cf * lm[i]) : 0.0;
+        cm[i] = (ok && use_mw) ? cf * A.inv_dt * lm[i] : 0.0;
+    }
+    float hq[L::R];
+    if (hn >= 0) {
+        // e1 = X0 - hx is the last step's increment (hx is X0 rounded to
+        // FP32: ~2^-24 |X0| absolute, far below the increment); hq[i] keeps e1
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) {
+            const bool ok = row_ok<L>(z, i);
+            const float e1 = (ok && hn >= 1) ? (float)(x[i] - (double)lh[i]) : 0.0f;
+            const float pr = hn >= 2 ? 2.0f * e1 - le[i] : e1;
+            hslot[i * NTP + threadIdx.x] = ok ? pr : 0.0f;
+            hq[i] = e1;
         }
-        x[i] = v;
-        cm[i] = m;
     }
     strip_store<L>(xg, z, x);
     __syncthreads();
+    // the history moves on once every load of it has returned (the barrier
+    // above waited for them), so no store overtakes a load of its address
+    if (hn >= 0) {
+        float* ph = A.hx + z.off;
+        float* pe = A.he + z.off;
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) {
+            if (row_ok<L>(z, i)) {
+                at_byte(ph, 4u * jr[i]) = (float)x[i];
+                at_byte(pe, 4u * jr[i]) = hq[i];
+            }
+        }
+    }
     if (copy_src != nullptr && z.live) planes_copy_start<L>(copy_src, copy_dst, z.lt, copy_shift);
     double b[L::R], sx[L::R];
 #pragma unroll
@@ -601,6 +665,7 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
 #pragma unroll
         for (int i = 0; i < L::R; ++i) r[i] = cm[i] - sx[i];
     }
+    return hn;
 }
 
 // ------------------------------------------------------------ matrix-free
@@ -1007,10 +1072,12 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
 // parts Slo, copied while the first inner solve runs, for the FP64 residual
 // updates.  Between the start of a copy and its wait, barriers are
 // lds_barrier() (LDS ordering only) so that the copy stays in flight.
+// hslot: per-lane slots of the predicted increment (extrapolated start of
+// the stored-operator form; null: none).
 template <class L, bool MF, class Prefetch>
 __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, float* planes,
                             MfShared* ms, PackRed<1, double>& red1, PackRed<2, double>& red2,
-                            PackRed<2, float>& rf2, Prefetch prefetch) {
+                            PackRed<2, float>& rf2, Prefetch prefetch, float* hslot) {
     const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     float* pg = reinterpret_cast<float*>(xg);
@@ -1022,6 +1089,7 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
     double x[L::R], r64[L::R];
     double bb = 0.0;
     float S[L::R][kStencil], dinv[L::R];
+    int hn = -1;
     if constexpr (MF) {
         // the operator from the amplitude: FP32 stencil to registers, low
         // parts to the planes buffer, r = -K x0 + coef M w / dt
@@ -1032,7 +1100,7 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
         for (int i = 0; i < L::R; ++i) x[i] = row_ok<L>(z, i) ? xg[cell_of<L>(z, i)] : 0.0;
         prefetch();
     } else {
-        pack_start<L>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift);
+        hn = pack_start<L>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift, hslot);
         planes_copy_wait();
         const LdsPlanes<L> plc(pl, z);
         // coefficient 1 of row i > 0 is coefficient 7 of row i-1; rows past
@@ -1108,6 +1176,38 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
         float gam_prev = 1.0f, alpha_prev = 1.0f;
         bool iconv = !me;
         int k = 0;
+        // Extrapolated start of the first inner solve: d0 = (predicted
+        // increment) / ||r||, r = r/||r|| - S d0.  The inner test stays
+        // relative to the residual without the guess, and an instance whose
+        // guessed residual is not smaller drops the guess (d0 = 0).  The FP64
+        // update below takes the whole d, the guess included, so the outer
+        // residual stays exact.  One operator application and one reduction.
+        const bool guessed = hn >= 1 && sweeps == 1;
+        if (guessed) {
+            const float fs = (float)isc;
+#pragma unroll
+            for (int i = 0; i < L::R; ++i) d[i] = hslot[i * NTP + threadIdx.x] * fs;
+            strip_store<L>(pg, z, d);
+            lds_barrier();
+            float sd[L::R];
+            strip_apply<L, L::R>(SR, pg, z, d, sd);
+            float g2[2] = {0.0f, 0.0f};     // guessed and plain (r, D^-1 r)
+#pragma unroll
+            for (int i = 0; i < L::R; ++i) {
+                sd[i] = r[i] - sd[i];
+                g2[0] += sd[i] * dinv[i] * sd[i];
+                g2[1] += r[i] * dinv[i] * r[i];
+            }
+            rf2.sum<L>(g2, z.w0);     // its barrier also ends the reads of d in the grid
+            const bool keep = g2[0] < g2[1];
+#pragma unroll
+            for (int i = 0; i < L::R; ++i) {
+                r[i] = keep ? sd[i] : r[i];
+                d[i] = keep ? d[i] : 0.0f;
+            }
+            gam0 = g2[1];
+            vthr = (ithr < INFINITY) ? ithr * rf2.tail : ithr;
+        }
         // One iteration, from the direction pair (pi, si) to (po, so): u and
         // w are formed in po and so, which then become the new p and s.  Two
         // iterations per loop trip with the pairs swapped, so the new p and s
@@ -1129,7 +1229,7 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
                 g2[1] += r[i] * po[i];
             }
             rf2.sum<L>(g2, z.w0);
-            if (k == 0) {
+            if (k == 0 && !guessed) {
                 gam0 = g2[1];
                 vthr = (ithr < INFINITY) ? ithr * rf2.tail : ithr;
             }
@@ -1266,14 +1366,15 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
     PackRed<2, float> rf2(sh.f3);
     if constexpr (MODE == 2) {
         __shared__ __attribute__((aligned(16))) float planes[L::PS * L::IPP + 2 * L::NP];
+        __shared__ float hslot[L::R * NTP];
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_refine<L, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch);
+            pack_refine<L, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot);
         });
     } else if constexpr (MODE == 3) {
         __shared__ __attribute__((aligned(16))) float planes[L::PS * L::IPP + 2 * L::NP];
         __shared__ MfShared ms;
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_refine<L, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch);
+            pack_refine<L, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr);
         });
     } else {
         __shared__ double xs[L::R * NTP];
@@ -1298,18 +1399,23 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
     PackRed<2, float> rf2(sh.f3);
     if constexpr (MODE == 2) {
         __shared__ __attribute__((aligned(16))) float planes[kPlaneFloats];
+        __shared__ float hslot[kFp64Rows * NTP];
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
-            if (lvl == 64) pack_refine<L64, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch);
-            else if (lvl == 32) pack_refine<L32, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch);
-            else pack_refine<L16, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch);
+            if (lvl == 64)
+                pack_refine<L64, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot);
+            else if (lvl == 32)
+                pack_refine<L32, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot);
+            else pack_refine<L16, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot);
         });
     } else if constexpr (MODE == 3) {
         __shared__ __attribute__((aligned(16))) float planes[kPlaneFloats];
         __shared__ MfShared ms;
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
-            if (lvl == 64) pack_refine<L64, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch);
-            else if (lvl == 32) pack_refine<L32, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch);
-            else pack_refine<L16, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch);
+            if (lvl == 64)
+                pack_refine<L64, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr);
+            else if (lvl == 32)
+                pack_refine<L32, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr);
+            else pack_refine<L16, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr);
         });
     } else {
         __shared__ double xs[kFp64Rows * NTP];

@@ -174,6 +174,14 @@ struct MicroArgs {
     // appended to fb_list ([0] count, then instance indices), and
     // launch_micro_fallback solves it again in FP64 from X0
     int32_t* fb_list;
+    // extrapolated start of the forward time-step solves (packed refinement
+    // kernels, all null elsewhere): hx holds the X0 of the previous step and
+    // he the increment before it (FP32, ragged like X0), *hn the number of
+    // steps that history covers (0, 1, 2).  The first inner solve starts from
+    // 2 e1 - e2 (e1 = X0 - hx, e2 = he), or e1 when one step is known
+    float* hx;
+    float* he;
+    const int32_t* hn;
 };
 
 // Packs of instances of one mesh size solved by one kPackThreads-lane workgroup.
@@ -274,6 +282,9 @@ size_t packed_lds_bytes(int level);      // dynamic LDS of one pack
 hipError_t launch_apply(int n_inst, const int32_t* level, const int64_t* offsets,
                         const double* S64, const double* x, double* y, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int n, hipStream_t s);
+// *hn = min(*hn + 1, 2): the forward step just taken extends the history of
+// the extrapolated start
+hipError_t launch_history_advance(int32_t* hn, hipStream_t s);
 // out_i = b_i^T x_i for every instance
 hipError_t launch_bdot(int n_inst, const int64_t* offsets, const double* b, const double* x, double* out,
                        hipStream_t s);

@@ -30,10 +30,11 @@ TSM_FLAG_FIXED_POINT = 1 << 5
 TSM_FLAG_GENERIC_16 = 1 << 6
 TSM_FLAG_GENERIC_32 = 1 << 7
 TSM_FLAG_GENERIC_64 = 1 << 8
-TSM_FLAG_STORED_OPERATOR = 1 << 9
+TSM_FLAG_MATRIX_FREE = 1 << 9
 TSM_FLAG_MACRO_PCG = 1 << 10
 TSM_FLAG_MULTIGRID = 1 << 11
 TSM_FLAG_NO_MULTIGRID = 1 << 12
+TSM_FLAG_NO_EXTRAPOLATION = 1 << 13
 TSM_PART_N, TSM_PART_I, TSM_PART_O = 0, 1, 2
 
 STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV",
@@ -247,7 +248,7 @@ def tsm_set_flags(ctx, flags: int) -> None:
 
 
 PLAN_BITS = (TSM_FLAG_PERSISTENT | TSM_FLAG_GENERIC | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32
-             | TSM_FLAG_GENERIC_64 | TSM_FLAG_STORED_OPERATOR)
+             | TSM_FLAG_GENERIC_64 | TSM_FLAG_MATRIX_FREE)
 
 
 def plan_name(flags: int) -> str:
@@ -258,14 +259,15 @@ def plan_name(flags: int) -> str:
     for bit, lvl in ((TSM_FLAG_GENERIC_16, 16), (TSM_FLAG_GENERIC_32, 32), (TSM_FLAG_GENERIC_64, 64)):
         if flags & bit:
             name += f"+generic{lvl}"
-    if flags & TSM_FLAG_STORED_OPERATOR:
-        name += "+stored_operator"
+    if flags & TSM_FLAG_MATRIX_FREE:
+        name += "+matrix_free"
     return name
 
 
 def tsm_autotune(ctx, steps: int):
-    """Returns (ms per step [per-size, persistent, generic, chosen, other operator
-    form of the chosen plan], chosen plan flags)."""
+    """Returns (ms per step [per-size, persistent, generic, chosen, chosen plan
+    with the assembled operator when the matrix-free one was asked for], chosen
+    plan flags)."""
     ms = (ctypes.c_double * 5)()
     fl = ctypes.c_uint64()
     _check(ctx, _lib.tsm_autotune(ctx, int(steps), ms, ctypes.byref(fl)))

@@ -27,12 +27,7 @@ def _case(NM, levels, seed):
     return lv, a, th
 
 
-def _run(NM, lv, a, th, prec, flags, steps, u0, v0, rtol, stored=True):
-    """stored: the refinement kernels read the assembled operator, which
-    the persistent plans always do, so that plans compare bit for bit."""
-    from paper_2103_17040_amd import tsm
-    if prec == "fp32_refine" and stored:
-        flags |= tsm.TSM_FLAG_STORED_OPERATOR
+def _run(NM, lv, a, th, prec, flags, steps, u0, v0, rtol):
     g = gpu_for(NM, lv, a, th, 0.005, precision=prec, rtol=rtol, flags=flags)
     try:
         g.set_state(u0, v0)
@@ -102,7 +97,7 @@ def test_autotune_restores_state_and_keeps_results(tmp_path):
     u0 = W.initial_macro(NM)
     v0 = np.random.default_rng(3).uniform(0, 1, int(W.offsets(lv)[-1]))
     banner("autotune")
-    ref = _run(NM, lv, a, th, "fp32_refine", 0, 4, u0, v0, 1e-10, stored=False)
+    ref = _run(NM, lv, a, th, "fp32_refine", 0, 4, u0, v0, 1e-10)
     g = gpu_for(NM, lv, a, th, 0.005, precision="fp32_refine", rtol=1e-10)
     try:
         g.set_state(u0, v0)
@@ -117,11 +112,10 @@ def test_autotune_restores_state_and_keeps_results(tmp_path):
         assert all(ms[k] > 0 for k in ("per_size", "persistent", "generic", "chosen"))
         assert res["flags"] & ~tsm.PLAN_BITS == 0
         assert res["plan"] == tsm.plan_name(res["flags"])
-        # the chosen plan is at least as fast as every plan timed (the other
-        # operator form of a packed refinement plan is timed too)
+        # the chosen plan is at least as fast as every plan timed; the
+        # matrix-free operator is not tried unless asked for
         assert ms["chosen"] == min(timed.values())
-        if not res["flags"] & tsm.TSM_FLAG_GENERIC:
-            assert ms["other_operator_form"] > 0
+        assert ms["assembled_operator"] < 0 and not res["flags"] & tsm.TSM_FLAG_MATRIX_FREE
         assert g.stats()["steps_taken"] == 0
         g.step(4)
         out = (g.macro().cpu().numpy(), g.micro().cpu().numpy(), g.fluxes().cpu().numpy())
@@ -130,10 +124,10 @@ def test_autotune_restores_state_and_keeps_results(tmp_path):
     finally:
         g.close()
     for x, y in zip(ref, out):
-        # the per-size plan with the matrix-free operator is the reference's
-        # own; any other plan sums in another order or reads the assembled
-        # operator
-        if res["flags"] == 0:
+        # the per-size plan is the reference's own; the persistent plan sums
+        # in the same order, the generic kernels in another
+        generic = tsm.TSM_FLAG_GENERIC | tsm.TSM_FLAG_GENERIC_16 | tsm.TSM_FLAG_GENERIC_32 | tsm.TSM_FLAG_GENERIC_64
+        if not res["flags"] & generic:
             assert np.array_equal(x, y)
         else:
             assert rel(x, y) <= 1e-8
