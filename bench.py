@@ -200,11 +200,20 @@ def run_form(w, a, th, lv, precision, steps, warmup, rtol, adjoint_steps=0, plan
         t = time.perf_counter() - t0
         st = g.stats()
         # roofline pass: the same steps again, direct launches bracketed by
-        # HIP events
+        # HIP events, one call per step so that the inner iterations and
+        # sweeps of every step enter the work model (they fall over the run
+        # as the extrapolated start improves)
         g.set_flags(tsm.TSM_FLAG_TIMING | plan["flags"])
         g.set_state(u_start, v_start)
-        g.step(steps)
-        tst = g.stats()
+        acc = {"micro_ms": 0.0, "macro_ms": 0.0, "iters_mean": 0.0, "sweeps_mean": 0.0}
+        for _ in range(steps):
+            g.step(1)
+            s1 = g.stats()
+            for k in acc:
+                acc[k] += s1[k]
+        tst = dict(s1)
+        tst.update(micro_ms=acc["micro_ms"], macro_ms=acc["macro_ms"], timed_steps=steps,
+                   iters_mean_run=acc["iters_mean"] / steps, sweeps_mean_run=acc["sweeps_mean"] / steps)
         g.set_flags(plan["flags"])
         fp = None
         if fp_steps > 0:
@@ -810,8 +819,9 @@ def main():
     launches = tst["timed_steps"] * tst["micro_launches"]
     micro_ms_per_launch = tst["micro_ms"] / max(launches, 1)
     st = main_form["stats"]
-    iters = st["iters_mean"]
-    sweeps = st["sweeps_mean"] if refine else 0
+    # inner iterations and sweeps per solve, means over the timed steps
+    iters = tst["iters_mean_run"]
+    sweeps = tst["sweeps_mean_run"] if refine else 0
     dofs_per_launch = n_dofs / max(tst["micro_launches"], 1)
     plan_flags = main_form["plan"]["flags"]
     mf_dofs = sum((N + 1) ** 2 for N in lv.tolist() if matrix_free(int(N), plan_flags, refine))
@@ -896,8 +906,8 @@ def main():
         "config": {"workload": w.name, "instances": w.n_inst, "micro_levels": sorted(set(lv.tolist())),
                    "micro_dofs": n_dofs, "dt": w.dt, "rtol": w.rtol, "precision": w.precision,
                    "seed": args.seed},
-        "iters_mean": iters, "iters_max": st["iters_max"], "sweeps_max": st["sweeps_max"],
-        "sweeps_mean": st["sweeps_mean"],
+        "iters_mean": iters, "iters_mean_last_step": st["iters_mean"], "iters_max": st["iters_max"],
+        "sweeps_max": st["sweeps_max"], "sweeps_mean": tst["sweeps_mean_run"] if refine else st["sweeps_mean"],
         "setup_ms": main_form["setup_ms"],
         "macro_ms_per_step": tst["macro_ms"] / max(tst["timed_steps"], 1),
         "launch_plan": main_form["plan"],

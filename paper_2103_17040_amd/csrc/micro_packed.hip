@@ -81,18 +81,6 @@ using L64 = Lvl<64, 768, 6>;
 // Every use orders LDS accesses alone.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Element at a 32-bit byte offset from a wave-uniform base: the load takes
-// the base in scalar registers and one 32-bit offset register per lane
-// (an element index scaled in 64 bits needs a 64-bit address per load).
-template <typename T>
-__device__ __forceinline__ T& at_byte(T* base, uint32_t byte_off) {
-    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
-}
-template <typename T>
-__device__ __forceinline__ const T& at_byte(const T* base, uint32_t byte_off) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-
 // Per-instance sums of NV values (NV <= 4).  Level 1: every wave reduces its
 // lanes into lane 63 (wave_total_last), which writes the NV totals to LDS.
 // Level 2, after the one barrier: lane l < IPP*WPI reads wave l's totals and
@@ -575,52 +563,36 @@ __device__ __forceinline__ int pack_start(const MicroArgs& A, const Lane& z, dou
     // coef w through cm[i] = coef (M w)_j / dt
     const bool use_mw = A.rhs_vec == nullptr && A.Mw != nullptr && !A.zero_init;
     const int hn = (hslot != nullptr && use_mw && A.hx != nullptr) ? *A.hn : -1;
-    // The loads are unconditional -- rows past the mesh and spare lanes read
-    // node 0 of their instance (of instance 0), values discarded -- so that
-    // all of a lane's loads are in flight together: a load under a per-row
-    // branch is waited for at the end of its branch, one round trip per row.
-    // the instance's arrays (wave-uniform bases) and the lane's nodes
-    const bool load_x = !A.zero_init;
-    const double* px = (load_x ? A.X0 : A.b) + z.off;          // A.b: any FP64 array of the layout
-    const double* pm = (use_mw ? A.Mw : (load_x && A.w != nullptr ? A.w : A.b)) + z.off;
-    uint32_t jr[L::R];     // unsigned: a wave-uniform base plus a 32-bit lane offset
-#pragma unroll
-    for (int i = 0; i < L::R; ++i) jr[i] = row_ok<L>(z, i) ? (uint32_t)node_of<L>(z, i) : 0u;
-    double lx[L::R], lm[L::R];
-    float lh[L::R], le[L::R];
-#pragma unroll
-    for (int i = 0; i < L::R; ++i) {
-        lx[i] = at_byte(px, 8u * jr[i]);
-        lm[i] = at_byte(pm, 8u * jr[i]);
-    }
-    if (hn >= 0) {
-        const float* ph = A.hx + z.off;
-        const float* pe = A.he + z.off;
-#pragma unroll
-        for (int i = 0; i < L::R; ++i) {
-            lh[i] = at_byte(ph, 4u * jr[i]);
-            le[i] = at_byte(pe, 4u * jr[i]);
-        }
-    }
-    // every load is issued before the first value is used
-    asm volatile("" ::: "memory");
     double cm[L::R];
+    float hp[L::R], hq[L::R];
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
-        const bool ok = row_ok<L>(z, i);
-        x[i] = (ok && load_x) ? (use_mw ? lx[i] : lx[i] + cf * lm[i]) : 0.0;
-        cm[i] = (ok && use_mw) ? cf * A.inv_dt * lm[i] : 0.0;
+        double v = 0.0, m = 0.0;
+        float xp = 0.0f, ep = 0.0f;
+        if (row_ok<L>(z, i) && !A.zero_init) {
+            const int j = node_of<L>(z, i);
+            if (use_mw) {
+                v = A.X0[z.off + j];
+                m = cf * A.inv_dt * A.Mw[z.off + j];
+                if (hn >= 1) xp = A.hx[z.off + j];
+                if (hn >= 2) ep = A.he[z.off + j];
+            } else {
+                v = A.X0[z.off + j] + cf * A.w[z.off + j];
+            }
+        }
+        x[i] = v;
+        cm[i] = m;
+        hp[i] = xp;
+        hq[i] = ep;
     }
-    float hq[L::R];
     if (hn >= 0) {
         // e1 = X0 - hx is the last step's increment (hx is X0 rounded to
         // FP32: ~2^-24 |X0| absolute, far below the increment); hq[i] keeps e1
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
-            const bool ok = row_ok<L>(z, i);
-            const float e1 = (ok && hn >= 1) ? (float)(x[i] - (double)lh[i]) : 0.0f;
-            const float pr = hn >= 2 ? 2.0f * e1 - le[i] : e1;
-            hslot[i * NTP + threadIdx.x] = ok ? pr : 0.0f;
+            const float e1 = hn >= 1 ? (float)(x[i] - (double)hp[i]) : 0.0f;
+            const float pr = hn >= 2 ? 2.0f * e1 - hq[i] : e1;
+            hslot[i * NTP + threadIdx.x] = row_ok<L>(z, i) ? pr : 0.0f;
             hq[i] = e1;
         }
     }
@@ -629,13 +601,12 @@ __device__ __forceinline__ int pack_start(const MicroArgs& A, const Lane& z, dou
     // the history moves on once every load of it has returned (the barrier
     // above waited for them), so no store overtakes a load of its address
     if (hn >= 0) {
-        float* ph = A.hx + z.off;
-        float* pe = A.he + z.off;
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
             if (row_ok<L>(z, i)) {
-                at_byte(ph, 4u * jr[i]) = (float)x[i];
-                at_byte(pe, 4u * jr[i]) = hq[i];
+                const int j = node_of<L>(z, i);
+                A.hx[z.off + j] = (float)x[i];
+                A.he[z.off + j] = hq[i];
             }
         }
     }
