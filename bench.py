@@ -78,8 +78,8 @@ FLOP_GUESS = 24.0
 #               (40; it also gives ||b|| = ||S x0 + r|| and diag^{-1})
 B_START, B_K, B_END = 16.0, 40.0, 8.0
 B_S64, B_S32, B_SLO = 40.0, 20.0, 20.0
-#   extrapolated start (refinement, assembled operator): the previous X0
-#   and increment read and written in FP32 (8 + 8)
+#   extrapolated start (packed kernels on the assembled operator): the
+#   previous X0 and increment read and written in FP32 (8 + 8)
 B_HIST = 16.0
 
 
@@ -101,9 +101,10 @@ def matrix_free(N, flags, refine):
 
 
 def extrapolated(N, flags, refine):
-    """Whether the packed refinement kernel starts its first inner solve from
-    the extrapolated increment (assembled operator, unless switched off)."""
-    return refine and packed_under(N, flags) and not matrix_free(N, flags, refine) and not (flags & (1 << 13))
+    """Whether the packed kernel starts its solve (refinement: its first inner
+    solve) from the extrapolated increment (assembled operator, unless
+    switched off)."""
+    return packed_under(N, flags) and not matrix_free(N, flags, refine) and not (flags & (1 << 13))
 
 
 def micro_bytes_per_dof(N, flags, refine, iters, sweeps):
@@ -116,10 +117,10 @@ def micro_bytes_per_dof(N, flags, refine, iters, sweeps):
         bdot = 16.0 * 4 * N / (N + 1) ** 2      # the boundary pass for b^T x
         if matrix_free(N, flags, refine):
             return B_START + B_END + bdot
+        hist = B_HIST if extrapolated(N, flags, refine) else 0.0
         if refine:
-            hist = B_HIST if extrapolated(N, flags, refine) else 0.0
             return B_START + B_K + B_S32 + B_SLO + B_END + hist + bdot
-        return B_START + B_K + B_S64 + B_END + bdot
+        return B_START + B_K + B_S64 + B_END + hist + bdot
     slots = next(s for s in GENERIC_SLOTS if s * 256 >= (N + 1) ** 2)
     if refine:   # FP32 stencil once (resident) or per inner iteration; FP64 rows per residual
         return 16 + 72 + 72 * sweeps + (36 if slots <= 9 else 36 * iters) + 16

@@ -101,15 +101,16 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
                                             are faster at 64 and below); the other sizes keep
                                             Jacobi either way. */
 #define TSM_FLAG_NO_MULTIGRID (1ull << 12) /* stationary contexts: Jacobi for every mesh */
-#define TSM_FLAG_NO_EXTRAPOLATION (1ull << 13) /* FP32_REFINE time steps: start every first
-                                            inner solve from zero.  By default the packed
-                                            refinement kernels with the assembled operator start
-                                            it from the increment extrapolated linearly from the
-                                            last two steps (two FP32 values of history per micro
-                                            DoF; an instance whose guessed residual is not smaller
-                                            drops the guess).  The FP64 residual of the
-                                            refinement takes the guess in exactly, so results meet
-                                            rtol either way; they differ in rounding only.  The
+#define TSM_FLAG_NO_EXTRAPOLATION (1ull << 13) /* time steps start every micro solve from
+                                            the previous state.  By default the packed kernels
+                                            with the assembled operator start it from the previous
+                                            state plus the increment extrapolated linearly from
+                                            the last two steps (two FP32 values of history per
+                                            micro DoF; an instance whose guessed residual is not
+                                            smaller drops the guess; in FP32_REFINE the guess
+                                            starts the first inner solve).  The FP64 residual
+                                            takes the guess in exactly, so results meet rtol
+                                            either way; they differ in rounding only.  The
                                             history restarts at tsm_set_state, tsm_set_flags and
                                             every change of the state other than a tsm_step;
                                             tsm_gradient's forward and recomputed steps do not

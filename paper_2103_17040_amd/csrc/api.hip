@@ -314,8 +314,8 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
     MicroArgs pbase = base;
     pbase.bx_out = nullptr;
     // the extrapolated start (history of the forward step) belongs to the
-    // stored-operator refinement kernels only
-    if (pmode != 2 || c->n_packs == 0) {
+    // packed kernels that read the assembled operator (FP64 and refinement)
+    if (pmode == 3 || c->n_packs == 0) {
         pbase.hx = nullptr;
         pbase.he = nullptr;
         pbase.hn = nullptr;
@@ -834,10 +834,10 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
         c->fb_slot = nmax;
         HIPALLOC(c->fb_list, ni + 1);
         if (nmax > 0) HIPALLOC(c->fb_ws, (size_t)c->n_cu * 3 * nmax);
-        if (!c->stationary) {
-            HIPALLOC(c->hx, tot); HIPALLOC(c->he, tot); HIPALLOC(c->hn, 1);
-            HIPCHK(launch_fill_i32(c->hn, 0, 1, c->stream));
-        }
+    }
+    if (!c->stationary) {
+        HIPALLOC(c->hx, tot); HIPALLOC(c->he, tot); HIPALLOC(c->hn, 1);
+        HIPCHK(launch_fill_i32(c->hn, 0, 1, c->stream));
     }
     if (c->stationary) {
         HIPALLOC(c->st_bO, tot); HIPALLOC(c->st_lenO, ni);

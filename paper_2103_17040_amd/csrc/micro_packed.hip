@@ -534,6 +534,57 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
     }
 }
 
+// Steps of history of the extrapolated start for this solve (-1: none; the
+// time-step form with a history only).
+__device__ __forceinline__ int history_steps(const MicroArgs& A) {
+    return (A.rhs_vec == nullptr && A.Mw != nullptr && !A.zero_init && A.hx != nullptr) ? *A.hn : -1;
+}
+
+// Issue the loads of the history of the lane's rows (hx, and he with two
+// steps), all in one block: rows past the mesh read node 0 (discarded).
+template <class L>
+__device__ __forceinline__ void history_load(const MicroArgs& A, const Lane& z, int hn, float (&lh)[L::R],
+                                             float (&le)[L::R]) {
+#pragma unroll
+    for (int i = 0; i < L::R; ++i) {
+        lh[i] = 0.0f;
+        le[i] = 0.0f;
+    }
+    if (hn >= 2) {
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) {
+            const int j = row_ok<L>(z, i) ? node_of<L>(z, i) : 0;
+            lh[i] = A.hx[z.off + j];
+            le[i] = A.he[z.off + j];
+        }
+    } else if (hn == 1) {
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) lh[i] = A.hx[z.off + (row_ok<L>(z, i) ? node_of<L>(z, i) : 0)];
+    }
+}
+
+// From the loaded history and the current X0 (xc): the predicted increment
+// 2 e1 - e2 (e1 alone with one step, 0 with none; e1 = X0 - hx, where hx is
+// X0 rounded to FP32, ~2^-24 |X0| absolute, far below the increment) of the
+// lane's rows into g, then the history moves on (hx = X0, he = e1).  The
+// caller has waited for the loads (vmcnt), so no store overtakes a load of
+// its address.
+template <class L, typename TG>
+__device__ __forceinline__ void history_step(const MicroArgs& A, const Lane& z, int hn, const double (&xc)[L::R],
+                                             const float (&lh)[L::R], const float (&le)[L::R], TG (&g)[L::R]) {
+#pragma unroll
+    for (int i = 0; i < L::R; ++i) {
+        const float e1 = hn >= 1 ? (float)(xc[i] - (double)lh[i]) : 0.0f;
+        const float pr = hn >= 2 ? 2.0f * e1 - le[i] : e1;
+        g[i] = row_ok<L>(z, i) ? (TG)pr : TG(0);
+        if (row_ok<L>(z, i)) {
+            const int j = node_of<L>(z, i);
+            A.hx[z.off + j] = (float)xc[i];
+            A.he[z.off + j] = e1;
+        }
+    }
+}
+
 // x0 into registers and the (double) grid, then the FP64 residual:
 //   given right-hand side:  b = rhs_scale rhs [+ rhs_bscale c_i b_i],  r = b - S x0,
 //                           and the partial ||b||^2 in bb
@@ -548,23 +599,24 @@ __device__ __forceinline__ void pack_store(const MicroArgs& A, const Lane& z, co
 // FP32 planes into LDS (planes_copy_start) once x0 is in the grid, so that it
 // overlaps the operator application; the caller waits for it
 // (planes_copy_wait).
-// hslot (non-null, time-step form with a history, A.hx): the predicted
-// increment of the step (2 e1 - e2, or e1 with one step of history, 0 with
-// none) goes to the lane's slots hslot[i * NTP + lane] (every lane writes
-// all of its slots), and the history moves on (hx = X0, he = e1).  Returns
-// the steps of history used (-1: no history).
+// hslot (non-null) with hist >= 0 (history_steps of the launch): the
+// history of the lane's rows is read with X0, the predicted increment goes
+// to the lane's slots hslot[i * NTP + lane] (history_step; every lane writes
+// all of its slots), and the history moves on after the barrier that waits
+// for those loads.
 template <class L>
-__device__ __forceinline__ int pack_start(const MicroArgs& A, const Lane& z, double* xg, double (&x)[L::R],
-                                          double (&r)[L::R], double& bb, const float* copy_src = nullptr,
-                                          float* copy_dst = nullptr, int copy_shift = 0, float* hslot = nullptr) {
+__device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, double* xg, double (&x)[L::R],
+                                           double (&r)[L::R], double& bb, const float* copy_src = nullptr,
+                                           float* copy_dst = nullptr, int copy_shift = 0, float* hslot = nullptr,
+                                           int hist = -1) {
     zero_halo<L, double>(xg, z);
     const double cf = (z.live && A.coef != nullptr) ? A.coef[z.inst] : 0.0;
     // time step with M w: start from X0 alone; the right-hand side keeps
     // coef w through cm[i] = coef (M w)_j / dt
     const bool use_mw = A.rhs_vec == nullptr && A.Mw != nullptr && !A.zero_init;
-    const int hn = (hslot != nullptr && use_mw && A.hx != nullptr) ? *A.hn : -1;
+    const int hn = hslot != nullptr ? hist : -1;
     double cm[L::R];
-    float hp[L::R], hq[L::R];
+    float lh[L::R], le[L::R];
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
         double v = 0.0, m = 0.0;
@@ -582,33 +634,16 @@ __device__ __forceinline__ int pack_start(const MicroArgs& A, const Lane& z, dou
         }
         x[i] = v;
         cm[i] = m;
-        hp[i] = xp;
-        hq[i] = ep;
-    }
-    if (hn >= 0) {
-        // e1 = X0 - hx is the last step's increment (hx is X0 rounded to
-        // FP32: ~2^-24 |X0| absolute, far below the increment); hq[i] keeps e1
-#pragma unroll
-        for (int i = 0; i < L::R; ++i) {
-            const float e1 = hn >= 1 ? (float)(x[i] - (double)hp[i]) : 0.0f;
-            const float pr = hn >= 2 ? 2.0f * e1 - hq[i] : e1;
-            hslot[i * NTP + threadIdx.x] = row_ok<L>(z, i) ? pr : 0.0f;
-            hq[i] = e1;
-        }
+        lh[i] = xp;
+        le[i] = ep;
     }
     strip_store<L>(xg, z, x);
     __syncthreads();
-    // the history moves on once every load of it has returned (the barrier
-    // above waited for them), so no store overtakes a load of its address
     if (hn >= 0) {
+        float g[L::R];
+        history_step<L>(A, z, hn, x, lh, le, g);
 #pragma unroll
-        for (int i = 0; i < L::R; ++i) {
-            if (row_ok<L>(z, i)) {
-                const int j = node_of<L>(z, i);
-                A.hx[z.off + j] = (float)x[i];
-                A.he[z.off + j] = hq[i];
-            }
-        }
+        for (int i = 0; i < L::R; ++i) hslot[i * NTP + threadIdx.x] = g[i];
     }
     if (copy_src != nullptr && z.live) planes_copy_start<L>(copy_src, copy_dst, z.lt, copy_shift);
     double b[L::R], sx[L::R];
@@ -636,8 +671,8 @@ __device__ __forceinline__ int pack_start(const MicroArgs& A, const Lane& z, dou
 #pragma unroll
         for (int i = 0; i < L::R; ++i) r[i] = cm[i] - sx[i];
     }
-    return hn;
 }
+
 
 // ------------------------------------------------------------ matrix-free
 // The time-step operator S = M/dt + d A + kappa B of a pack's instances,
@@ -931,7 +966,7 @@ __device__ __forceinline__ void mf_start(const MicroArgs& A, const Lane& z, doub
 template <class L, bool CS = false, class Prefetch>
 __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, double* xs,
                           PackRed<1, double>& red1, PackRed<2, double>& red2, PackRed<3, double>& red3,
-                          Prefetch prefetch, double* cs = nullptr) {
+                          Prefetch prefetch, double* cs = nullptr, int hist = -1) {
     const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     double x[L::R], r[L::R], p[L::R];
@@ -971,6 +1006,48 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
         for (int i = 0; i < L::R; ++i) {
             const double bi = sb[i] + r[i];
             bb += row_ok<L>(z, i) ? bi * bi : 0.0;
+        }
+    }
+    // Extrapolated start (time-step form with a history): x0 = X0 + the
+    // predicted increment (2 e1 - e2, or e1), r -= S (that increment) with
+    // the resident FP64 stencil, kept only where it lowers ||r||.  The
+    // history is read here rather than with X0 (the LDS has no room to hold
+    // the prediction until the stencil is resident) and moves on once its
+    // loads have returned.
+    const int hn = hist;
+    if (hn >= 0) {
+        float lh[L::R], le[L::R];
+        history_load<L>(A, z, hn, lh, le);
+        double xc[L::R], g[L::R];
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) xc[i] = xs[i * NTP + threadIdx.x];
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        history_step<L>(A, z, hn, xc, lh, le, g);
+        if (hn >= 1) {
+            __syncthreads();     // the reads of x0 in the grid are done
+            strip_store<L>(xg, z, g);
+            __syncthreads();
+            double sg[L::R];
+#pragma unroll
+            for (int i = 0; i < L::R; ++i) sg[i] = 0.0;
+            if (z.act) {
+                if constexpr (CS) strip_apply_lean<L, 1>(SL, xg, z, g, sg);
+                else strip_apply_lean<L, 1>(S, xg, z, g, sg);
+            }
+            double a2[2] = {0.0, 0.0};     // guessed and plain ||r||^2
+#pragma unroll
+            for (int i = 0; i < L::R; ++i) {
+                sg[i] = r[i] - sg[i];
+                a2[0] += sg[i] * sg[i];
+                a2[1] += r[i] * r[i];
+            }
+            red2.sum<L>(a2, z.w0);     // its barrier also ends the reads of the guess in the grid
+            const bool keep = a2[0] < a2[1];
+#pragma unroll
+            for (int i = 0; i < L::R; ++i) {
+                r[i] = keep ? sg[i] : r[i];
+                xs[i * NTP + threadIdx.x] += keep ? g[i] : 0.0;
+            }
         }
     }
     double acc[3] = {bb, 0.0, 0.0};
@@ -1044,11 +1121,11 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
 // updates.  Between the start of a copy and its wait, barriers are
 // lds_barrier() (LDS ordering only) so that the copy stays in flight.
 // hslot: per-lane slots of the predicted increment (extrapolated start of
-// the stored-operator form; null: none).
+// the stored-operator form; null: none); hist: history_steps of the launch.
 template <class L, bool MF, class Prefetch>
 __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, float* planes,
                             MfShared* ms, PackRed<1, double>& red1, PackRed<2, double>& red2,
-                            PackRed<2, float>& rf2, Prefetch prefetch, float* hslot) {
+                            PackRed<2, float>& rf2, Prefetch prefetch, float* hslot, int hist) {
     const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     float* pg = reinterpret_cast<float*>(xg);
@@ -1071,7 +1148,8 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
         for (int i = 0; i < L::R; ++i) x[i] = row_ok<L>(z, i) ? xg[cell_of<L>(z, i)] : 0.0;
         prefetch();
     } else {
-        hn = pack_start<L>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift, hslot);
+        pack_start<L>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift, hslot, hist);
+        if (hslot != nullptr) hn = hist;
         planes_copy_wait();
         const LdsPlanes<L> plc(pl, z);
         // coefficient 1 of row i > 0 is coefficient 7 of row i-1; rows past
@@ -1282,6 +1360,7 @@ struct PackShared {
     float f3[2][NWP][4];
     int32_t meta[2][kMetaWords];   // this pack's and the next one's
     int task;
+    int hist;                      // steps of history of the extrapolated start (history_steps)
 };
 
 // The work loop of a packed workgroup.  With a queue, packs are popped one
@@ -1302,6 +1381,9 @@ __device__ __forceinline__ void pack_loop(const MicroArgs& A, const PackList& P,
         task = blockIdx.x;
     }
     if (task < P.n_packs && threadIdx.x < kWave) meta_copy_start(P, pack_level, task, sh.meta[0]);
+    // the history count is fixed during the launch: read once, here, so that
+    // no wait for it lands behind a pack's plane copy
+    if (threadIdx.x == 0) sh.hist = history_steps(A);
     planes_copy_wait();
     int buf = 0;
     while (task < P.n_packs) {
@@ -1339,20 +1421,20 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
         __shared__ __attribute__((aligned(16))) float planes[L::PS * L::IPP + 2 * L::NP];
         __shared__ float hslot[L::R * NTP];
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_refine<L, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot);
+            pack_refine<L, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot, sh.hist);
         });
     } else if constexpr (MODE == 3) {
         __shared__ __attribute__((aligned(16))) float planes[L::PS * L::IPP + 2 * L::NP];
         __shared__ MfShared ms;
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_refine<L, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr);
+            pack_refine<L, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr, -1);
         });
     } else {
         __shared__ double xs[L::R * NTP];
         // the corner couplings of the resident stencil (2 x R doubles a lane)
         __shared__ double cs[2 * L::R * NTP];
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_fp64<L, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs);
+            pack_fp64<L, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist);
         });
     }
 }
@@ -1373,28 +1455,28 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
         __shared__ float hslot[kFp64Rows * NTP];
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
             if (lvl == 64)
-                pack_refine<L64, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot);
+                pack_refine<L64, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot, sh.hist);
             else if (lvl == 32)
-                pack_refine<L32, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot);
-            else pack_refine<L16, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot);
+                pack_refine<L32, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot, sh.hist);
+            else pack_refine<L16, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot, sh.hist);
         });
     } else if constexpr (MODE == 3) {
         __shared__ __attribute__((aligned(16))) float planes[kPlaneFloats];
         __shared__ MfShared ms;
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
             if (lvl == 64)
-                pack_refine<L64, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr);
+                pack_refine<L64, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr, -1);
             else if (lvl == 32)
-                pack_refine<L32, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr);
-            else pack_refine<L16, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr);
+                pack_refine<L32, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr, -1);
+            else pack_refine<L16, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr, -1);
         });
     } else {
         __shared__ double xs[kFp64Rows * NTP];
         __shared__ double cs[2 * kFp64Rows * NTP];
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
-            if (lvl == 64) pack_fp64<L64, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs);
-            else if (lvl == 32) pack_fp64<L32, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs);
-            else pack_fp64<L16, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs);
+            if (lvl == 64) pack_fp64<L64, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist);
+            else if (lvl == 32) pack_fp64<L32, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist);
+            else pack_fp64<L16, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist);
         });
     }
 }

@@ -174,11 +174,12 @@ struct MicroArgs {
     // appended to fb_list ([0] count, then instance indices), and
     // launch_micro_fallback solves it again in FP64 from X0
     int32_t* fb_list;
-    // extrapolated start of the forward time-step solves (packed refinement
-    // kernels, all null elsewhere): hx holds the X0 of the previous step and
-    // he the increment before it (FP32, ragged like X0), *hn the number of
-    // steps that history covers (0, 1, 2).  The first inner solve starts from
-    // 2 e1 - e2 (e1 = X0 - hx, e2 = he), or e1 when one step is known
+    // extrapolated start of the forward time-step solves (packed kernels on
+    // the assembled operator, all null elsewhere): hx holds the X0 of the
+    // previous step and he the increment before it (FP32, ragged like X0),
+    // *hn the number of steps that history covers (0, 1, 2).  The solve
+    // starts from X0 + 2 e1 - e2 (e1 = X0 - hx, e2 = he), or X0 + e1 when one
+    // step is known (the refinement form: its first inner solve)
     float* hx;
     float* he;
     const int32_t* hn;

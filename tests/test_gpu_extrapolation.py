@@ -22,8 +22,8 @@ def _case(NM, levels, seed):
     return lv, a, th
 
 
-def _run(NM, lv, a, th, dt, steps, u0, v0, flags):
-    g = gpu_for(NM, lv, a, th, dt=dt, precision="fp32_refine", rtol=1e-10, flags=flags)
+def _run(NM, lv, a, th, dt, steps, u0, v0, flags, precision="fp32_refine", rtol=1e-10):
+    g = gpu_for(NM, lv, a, th, dt=dt, precision=precision, rtol=rtol, flags=flags)
     try:
         g.set_state(u0, v0)
         us, Fs, its = [g.macro().cpu().numpy()], [], []
@@ -37,28 +37,32 @@ def _run(NM, lv, a, th, dt, steps, u0, v0, flags):
         g.close()
 
 
+@pytest.mark.parametrize("precision,rtol,tol", [("fp32_refine", 1e-10, 1e-8), ("fp64", 1e-12, 1e-10)])
 @pytest.mark.parametrize("plan", ["persistent", "per_size"])
-def test_extrapolated_start_matches_oracle_and_saves_iterations(plan):
+def test_extrapolated_start_matches_oracle_and_saves_iterations(plan, precision, rtol, tol):
     from paper_2103_17040_amd import tsm
     NM, dt, steps = 4, 0.0025, 10
     lv, a, th = _case(NM, [16, 32, 64], 71)
     u0 = W.initial_macro(NM)
     v0 = np.zeros(int(W.offsets(lv)[-1]))
     base = tsm.TSM_FLAG_PERSISTENT if plan == "persistent" else 0
-    banner(f"extrapolated start, {plan}, NM={NM} levels 16/32/64, {steps} steps")
+    banner(f"extrapolated start, {plan}, {precision}, NM={NM} levels 16/32/64, {steps} steps")
     ref = oracle_for(NM, lv, a, th, dt).run(u0, v0, steps)
-    on = _run(NM, lv, a, th, dt, steps, u0, v0, base)
-    off = _run(NM, lv, a, th, dt, steps, u0, v0, base | tsm.TSM_FLAG_NO_EXTRAPOLATION)
+    on = _run(NM, lv, a, th, dt, steps, u0, v0, base, precision, rtol)
+    off = _run(NM, lv, a, th, dt, steps, u0, v0, base | tsm.TSM_FLAG_NO_EXTRAPOLATION, precision, rtol)
     for name, out in (("on", on), ("off", off)):
         eu, eF, ev = rel(out["u"], ref["u"]), rel(out["F"], ref["F"]), rel(out["v"], ref["v"])
-        banner(f"  {name}: rel u {eu:.2e} F {eF:.2e} v {ev:.2e}; inner iterations {out['iters'].round(1).tolist()}")
-        assert eu <= 1e-8 and eF <= 1e-8 and ev <= 1e-8, name
+        banner(f"  {name}: rel u {eu:.2e} F {eF:.2e} v {ev:.2e}; iterations {out['iters'].round(1).tolist()}")
+        assert eu <= tol and eF <= tol and ev <= tol, name
     # the two runs differ only by rounding and the solver tolerance
-    assert rel(on["v"], off["v"]) <= 1e-8
+    assert rel(on["v"], off["v"]) <= tol
     # the first step has no history (identical); from the third on the guess
-    # is the linear extrapolation and must save iterations
+    # is the linear extrapolation and must save iterations (refinement: inner
+    # iterations)
     assert on["iters"][0] == off["iters"][0]
-    assert on["iters"][3:].sum() < 0.9 * off["iters"][3:].sum()
+    # (the FP64 solves of these small, mass-dominated systems take ~6
+    # iterations, so the guess saves less of them)
+    assert on["iters"][3:].sum() < (0.9 if precision == "fp32_refine" else 0.95) * off["iters"][3:].sum()
 
 
 def test_history_restarts_with_the_state():
