@@ -112,9 +112,11 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
                                             takes the guess in exactly, so results meet rtol
                                             either way; they differ in rounding only.  The
                                             history restarts at tsm_set_state, tsm_set_flags and
-                                            every change of the state other than a tsm_step;
-                                            tsm_gradient's forward and recomputed steps do not
-                                            use it. */
+                                            every change of the state other than a tsm_step.
+                                            tsm_gradient's tape starts with an empty history and
+                                            keeps it with every checkpoint (its recomputed
+                                            segments repeat the tape bitwise); its adjoint micro
+                                            solves extrapolate from their own history. */
 #define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
                                             HIP events on the context's stream (see tsm_stats) */
 #define TSM_FLAG_FIXED_POINT (1ull << 5) /* tsm_step couples macro and micro solves by the paper's

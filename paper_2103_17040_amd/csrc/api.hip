@@ -189,6 +189,9 @@ struct tsm_ctx {
 
     // adjoint work vectors (first tsm_gradient)
     double *lam0 = nullptr, *mu = nullptr, *coef = nullptr, *grad = nullptr, *Jd = nullptr;
+    // history of the extrapolated start of the adjoint micro solves (lam0)
+    float *lhx = nullptr, *lhe = nullptr;
+    int32_t* lhn = nullptr;
     double grad_fwd_ms = 0.0, grad_bwd_ms = 0.0;
 
     // stationary three-field system (tsm_stationary_create): b holds b_I and
@@ -243,7 +246,7 @@ struct tsm_ctx {
         free_mg();
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
-        dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd);
+        dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd); dfree(lhx); dfree(lhe); dfree(lhn);
         dfree(st_bO); dfree(st_lenO); dfree(st_zI); dfree(st_zO); dfree(st_z0); dfree(st_dots);
         dfree(st_w); dfree(st_work); dfree(st_info); dfree(st_iters); dfree(st_sweeps);
         dfree(st_wcell); dfree(st_wbnd); dfree(st_Fv); dfree(st_GI); dfree(st_GO); dfree(st_Fu); dfree(st_Fw);
@@ -352,7 +355,7 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
             HIPCHK(launch_packed(a, pl, pg[0], pmode, pg[2], st));
         }
     }
-    if (pbase.hx != nullptr) HIPCHK(launch_history_advance(c->hn, st));
+    if (pbase.hx != nullptr) HIPCHK(launch_history_advance(const_cast<int32_t*>(pbase.hn), st));
     if (fb) HIPCHK(launch_micro_fallback(pbase, c->fb_ws, c->fb_slot, c->n_cu, c->counters, st));
     if (c->n_packs > 0 && base.bx_out != nullptr)
         HIPCHK(launch_bdot_boundary((int)c->n_packed_tasks, c->order, c->level, c->offsets, c->bcomp, base.X_out,
@@ -1340,14 +1343,28 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
     if (!c->lam0) {
         HIPALLOC(c->lam0, tot); HIPALLOC(c->mu, ni); HIPALLOC(c->coef, ni); HIPALLOC(c->grad, ni);
         HIPALLOC(c->Jd, 1);
+        if (c->hx != nullptr) {
+            HIPALLOC(c->lhx, tot); HIPALLOC(c->lhe, tot); HIPALLOC(c->lhn, 1);
+        }
     }
+    const bool extrap = c->hx != nullptr && !(c->prm.flags & TSM_FLAG_NO_EXTRAPOLATION);
     // --- work buffers of this call
     double *U = nullptr, *ck_u = nullptr, *ck_v = nullptr, *V = nullptr, *save_u = nullptr, *save_v = nullptr,
            *save_F = nullptr;
-    auto release = [&]() { dfree(U); dfree(ck_u); dfree(ck_v); dfree(V); dfree(save_u); dfree(save_v); dfree(save_F); };
+    // the history of the extrapolated start at every checkpoint, so that a
+    // recomputed segment repeats its steps bitwise
+    float *ck_hx = nullptr, *ck_he = nullptr;
+    int32_t* ck_hn = nullptr;
+    auto release = [&]() {
+        dfree(U); dfree(ck_u); dfree(ck_v); dfree(V); dfree(save_u); dfree(save_v); dfree(save_F);
+        dfree(ck_hx); dfree(ck_he); dfree(ck_hn);
+    };
+    const size_t nh = extrap ? (size_t)nseg : 0;
     if (dalloc(&U, (size_t)(N + 1) * ni) != hipSuccess || dalloc(&ck_u, (size_t)nseg * ni) != hipSuccess ||
         dalloc(&ck_v, (size_t)nseg * tot) != hipSuccess || dalloc(&V, (size_t)(K + 1) * tot) != hipSuccess ||
-        dalloc(&save_u, ni) != hipSuccess || dalloc(&save_v, tot) != hipSuccess || dalloc(&save_F, ni) != hipSuccess) {
+        dalloc(&save_u, ni) != hipSuccess || dalloc(&save_v, tot) != hipSuccess || dalloc(&save_F, ni) != hipSuccess ||
+        dalloc(&ck_hx, nh * tot) != hipSuccess || dalloc(&ck_he, nh * tot) != hipSuccess ||
+        dalloc(&ck_hn, nh) != hipSuccess) {
         (void)hipGetLastError();
         release();
         return c->fail(TSM_ENOMEM, "gradient work buffers");
@@ -1360,16 +1377,22 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
         HIPCHK(hipMemcpyAsync(save_F, c->F, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
         HIPCHK(hipMemsetAsync(c->counters, 0, 4 * sizeof(int32_t), s));
         HIPCHK(hipEventRecord(c->ev0, s));
-        // forward with checkpoints; u of every step kept (n_inst doubles per step)
+        // forward with checkpoints; u of every step kept (n_inst doubles per
+        // step).  The tape's history of the extrapolated start begins empty
+        // and is kept with every checkpoint.
         HIPCHK(hipMemcpyAsync(U, c->u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (reset_history(c) != TSM_OK) return TSM_EHIP;
         for (int n = 0; n < N; ++n) {
             if (n % K == 0) {
-                HIPCHK(hipMemcpyAsync(ck_u + (size_t)(n / K) * ni, c->u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(ck_v + (size_t)(n / K) * tot, c->v0, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+                const size_t q = (size_t)(n / K);
+                HIPCHK(hipMemcpyAsync(ck_u + q * ni, c->u, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(ck_v + q * tot, c->v0, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+                if (extrap) {
+                    HIPCHK(hipMemcpyAsync(ck_hx + q * tot, c->hx, tot * sizeof(float), hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(ck_he + q * tot, c->he, tot * sizeof(float), hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(ck_hn + q, c->hn, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+                }
             }
-            // every step of the tape starts without the extrapolated guess, so
-            // that the recomputed segments repeat it bitwise
-            if (reset_history(c) != TSM_OK) return TSM_EHIP;
             if (c->graph) {
                 HIPCHK(hipGraphLaunch(c->graph, s));
             } else {
@@ -1381,8 +1404,10 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
         const MacroArgs m = c->macro_args();
         HIPCHK(launch_observable(m, U + (size_t)N * ni, c->Jd, s));
         HIPCHK(hipEventRecord(c->ev1, s));
-        // backward: lambda^{N+1} = 0, mu^{N+1} = 0
+        // backward: lambda^{N+1} = 0, mu^{N+1} = 0; the history of the
+        // adjoint solves' extrapolated start begins empty
         HIPCHK(hipMemsetAsync(c->lam0, 0, tot * sizeof(double), s));
+        if (extrap) HIPCHK(launch_fill_i32(c->lhn, 0, 1, s));
         HIPCHK(hipMemsetAsync(c->coef, 0, ni * sizeof(double), s));
         HIPCHK(hipMemsetAsync(c->mu, 0, ni * sizeof(double), s));
         HIPCHK(hipMemsetAsync(c->grad, 0, ni * sizeof(double), s));
@@ -1391,9 +1416,13 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
             // recompute the segment's states v^a .. v^e (same kernels: bitwise equal)
             HIPCHK(hipMemcpyAsync(c->u, ck_u + (size_t)sg * ni, ni * sizeof(double), hipMemcpyDeviceToDevice, s));
             HIPCHK(hipMemcpyAsync(c->v0, ck_v + (size_t)sg * tot, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+            if (extrap) {
+                HIPCHK(hipMemcpyAsync(c->hx, ck_hx + (size_t)sg * tot, tot * sizeof(float), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(c->he, ck_he + (size_t)sg * tot, tot * sizeof(float), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(c->hn, ck_hn + sg, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            }
             HIPCHK(launch_state_join((int)ni, c->offsets, c->u, c->v0, c->w, V, s));
             for (int n = a + 1; n <= e; ++n) {
-                if (reset_history(c) != TSM_OK) return TSM_EHIP;
                 if (c->graph) {
                     HIPCHK(hipGraphLaunch(c->graph, s));
                 } else {
@@ -1411,6 +1440,11 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
                 ma.rhs_vec = nullptr;
                 ma.zero_init = 0;
                 ma.X_out = c->lam0;
+                if (extrap) {
+                    ma.hx = c->lhx;
+                    ma.he = c->lhe;
+                    ma.hn = c->lhn;
+                }
                 tsm_status e3 = enqueue_micro(c, ma, false);
                 if (e3 != TSM_OK) return e3;
                 // macro adjoint: A_M mu^m = M_H mu^{m+1}/dt + kappa p (b^T lam0^m) (+ 2 M_H u^N)
