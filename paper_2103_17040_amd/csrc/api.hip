@@ -535,6 +535,10 @@ tsm_status enqueue_macro_pcg(tsm_ctx* c, double* u) {
     const MacroArgs m = c->macro_args();
     const int n = m.n, NM = c->NM;
     hipStream_t s = c->stream;
+    if (macro_pcg_fused_fits(NM)) {
+        HIPCHK(launch_macro_pcg_fused(m, u, c->rhs, c->Q, c->lam, c->macro_pcg_iters, s));
+        return TSM_OK;
+    }
     auto precondition = [&]() -> hipError_t {     // z = A0^{-1} r
         hipError_t e = launch_gemm(n, c->Q, c->R, c->T1, 0, nullptr, nullptr, NM, s);
         if (e == hipSuccess) e = launch_gemm(n, c->T1, c->Q, c->T2, 1, c->lam, nullptr, NM, s);

@@ -283,6 +283,158 @@ __global__ __launch_bounds__(kPcgThreads) void macro_pcg_direction_kernel(int NM
     if (threadIdx.x == 0) s[0] = acc[0];
 }
 
+// ---------------------------------------------------------------------------
+// The same PCG in ONE launch for interior grids of at most kFN x kFN nodes:
+// one 1024-lane workgroup runs every iteration.  The four n x n products of
+// the preconditioner are 64 x 64 FP64 MFMA products (zero-padded): Q and two
+// work matrices sit in LDS, each of the 16 waves owns one 16 x 16 output tile
+// (v_mfma_f64_16x16x4f64: lane l holds A(l%16, l/16) and B(l/16, l%16) of a
+// 16x4 by 4x16 step and D rows 4(l/16)+q, column l%16, q = 0..3).  A lane's
+// four D positions are also its four nodes of the interior grid, so r, z, q,
+// the iterate and 1/Lambda stay in registers; the search direction sits on
+// the full macro grid in LDS (zero boundary) for the 9-point stencil.  The
+// iteration count and the order of operations are those of the multi-launch
+// form; sums are taken in another order.
+// ---------------------------------------------------------------------------
+constexpr int kFN = 64;            // padded side of the preconditioner's matrices
+constexpr int kFP = kFN + 1;       // LDS row stride (doubles)
+constexpr int kFW = kFN + 2;       // largest macro grid side (NM + 1) of the fused form
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+// The calling wave's 16 x 16 tile (rows 16 tr.., columns 16 tc..) of A B,
+// A and B kFN x kFN in LDS, in the MFMA output layout.
+__device__ __forceinline__ dv4 tile_product(const double (*A)[kFP], const double (*B)[kFP], int tr, int tc) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int i = lane & 15, kk = lane >> 4;
+    dv4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < kFN; k0 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[tr * 16 + i][k0 + kk], B[k0 + kk][tc * 16 + i], acc, 0, 0, 0);
+    return acc;
+}
+
+__global__ __launch_bounds__(kPcgThreads) void macro_pcg_fused_kernel(MacroArgs m, double* u, const double* rhs,
+                                                                      const double* Q, const double* lam, int iters) {
+    __shared__ double Qs[kFN][kFP], Ts[kFN][kFP], Xs[kFN][kFP];
+    __shared__ double Ps[kFW * kFW];
+    __shared__ double red_s[2][1][kPcgThreads / kWave];
+    BlockReducer<kPcgThreads / kWave, 1, double> red(red_s);
+    const int NM = m.NM, W = NM + 1, n = m.n;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int tr = wid >> 2, tc = wid & 3;
+    // the lane's four nodes (row, col of the interior grid)
+    int row[4], col[4], kg[4];
+    bool ok[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        row[q] = tr * 16 + 4 * (lane >> 4) + q;
+        col[q] = tc * 16 + (lane & 15);
+        ok[q] = row[q] < n && col[q] < n;
+        // padding positions point at the first interior node, so that every
+        // stencil read stays on the grid (their results are discarded)
+        kg[q] = ok[q] ? (row[q] + 1) * W + col[q] + 1 : W + 1;
+    }
+    for (int e = threadIdx.x; e < kFN * kFN; e += kPcgThreads) {
+        const int a = e / kFN, b = e % kFN;
+        Qs[a][b] = (a < n && b < n) ? Q[(a < n && b < n) ? a * n + b : 0] : 0.0;
+    }
+    for (int e = threadIdx.x; e < W * W; e += kPcgThreads) Ps[e] = 0.0;
+    double x[4], r[4], z[4], pv[4], bt[4], il[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int idx = ok[q] ? row[q] * n + col[q] : 0;
+        x[q] = ok[q] ? u[kg[q]] : 0.0;
+        r[q] = ok[q] ? rhs[idx] : 0.0;
+        bt[q] = ok[q] ? m.beta[kg[q]] : 0.0;
+        il[q] = ok[q] ? 1.0 / lam[idx] : 0.0;
+    }
+    __syncthreads();
+    // y = A_M v at the lane's nodes, v on the grid Ps
+    auto apply = [&](const double (&v)[4], double (&y)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = kg[q];
+            y[q] = ok[q] ? m.mass_c * mass9(Ps, k, W) + m.lap_c * lap9(Ps, k, W) - m.sig_h2 * bt[q] * v[q] : 0.0;
+        }
+    };
+    // z = A_0^{-1} r: Q R Q, divided by Lambda, then Q (.) Q
+    auto precondition = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xs[row[q]][col[q]] = r[q];
+        __syncthreads();
+        dv4 t = tile_product(Qs, Xs, tr, tc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ts[row[q]][col[q]] = t[q];
+        __syncthreads();
+        t = tile_product(Ts, Qs, tr, tc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xs[row[q]][col[q]] = t[q] * il[q];
+        __syncthreads();
+        t = tile_product(Qs, Xs, tr, tc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ts[row[q]][col[q]] = t[q];
+        __syncthreads();
+        t = tile_product(Ts, Qs, tr, tc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) z[q] = ok[q] ? t[q] : 0.0;
+    };
+    // r = rhs - A_M u
+    {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (ok[q]) Ps[kg[q]] = x[q];
+        __syncthreads();
+        double au[4];
+        apply(x, au);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r[q] -= au[q];
+    }
+    precondition();
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        pv[q] = z[q];
+        acc[0] += r[q] * z[q];
+    }
+    red.sum(acc);      // its barrier also ends the reads of u on the grid
+    double rz = acc[0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (ok[q]) Ps[kg[q]] = pv[q];
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+        double aq[4];
+        apply(pv, aq);
+        acc[0] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[0] += pv[q] * aq[q];
+        red.sum(acc);
+        const double alpha = acc[0] > 0.0 ? rz / acc[0] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            x[q] += alpha * pv[q];
+            r[q] -= alpha * aq[q];
+        }
+        if (it + 1 == iters) break;
+        precondition();
+        acc[0] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[0] += r[q] * z[q];
+        red.sum(acc);
+        const double beta = rz > 0.0 ? acc[0] / rz : 0.0;
+        rz = acc[0];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pv[q] = z[q] + beta * pv[q];
+            if (ok[q]) Ps[kg[q]] = pv[q];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (ok[q]) u[kg[q]] = x[q];
+}
+
 inline int blocks(int n, int t) { return (n + t - 1) / t; }
 
 }  // namespace
@@ -295,6 +447,15 @@ hipError_t launch_macro_pcg_start(int NM, const double* r, const double* z, doub
 hipError_t launch_macro_pcg_step(const MacroArgs& m, const double* p, double* q, double* r, double* u,
                                  const double* s, hipStream_t st) {
     hipLaunchKernelGGL(macro_pcg_step_kernel, dim3(1), dim3(kPcgThreads), 0, st, m, p, q, r, u, s);
+    return hipGetLastError();
+}
+
+bool macro_pcg_fused_fits(int NM) { return NM - 1 <= kFN && NM + 1 <= kFW; }
+
+hipError_t launch_macro_pcg_fused(const MacroArgs& m, double* u, const double* rhs, const double* Q,
+                                  const double* lam, int iters, hipStream_t st) {
+    if (!macro_pcg_fused_fits(m.NM) || m.n != m.NM - 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(macro_pcg_fused_kernel, dim3(1), dim3(kPcgThreads), 0, st, m, u, rhs, Q, lam, iters);
     return hipGetLastError();
 }
 

@@ -373,6 +373,12 @@ hipError_t launch_observable(const MacroArgs& m, const double* u, double* J, hip
 // macro PCG with the sine-basis preconditioner: r, z, q interior (n x n), p
 // full grid (zero boundary), s[0] = (r, z)
 hipError_t launch_macro_pcg_start(int NM, const double* r, const double* z, double* p, double* s, hipStream_t st);
+// The whole macro PCG (residual, preconditioner, iters steps) in one
+// single-workgroup launch for NM - 1 <= 64 interior nodes per side
+// (macro_pcg_fused_fits); u (full grid, zero boundary) in place.
+bool macro_pcg_fused_fits(int NM);
+hipError_t launch_macro_pcg_fused(const MacroArgs& m, double* u, const double* rhs, const double* Q,
+                                  const double* lam, int iters, hipStream_t st);
 hipError_t launch_macro_pcg_step(const MacroArgs& m, const double* p, double* q, double* r, double* u,
                                  const double* s, hipStream_t st);
 hipError_t launch_macro_pcg_direction(int NM, const double* r, const double* z, double* p, double* s,
