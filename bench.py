@@ -274,6 +274,7 @@ def general_map_leg(steps, precision="fp32_refine", rtol=1e-10):
         setup_tables = g.stats()["setup_ms"]
         g.set_state(u0, None)
         g.step(1)
+        plan = g.autotune(steps=2)      # the launch plan a user's autotune call picks (state restored)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g.step(steps)
@@ -284,7 +285,7 @@ def general_map_leg(steps, precision="fp32_refine", rtol=1e-10):
         g.close()
     return {"workload": f"{len(lv)} instances, 16/32/64 cells (uneven batch), polynomial map from Jacobian tables",
             "table_bytes": 8 * (Fc.size + Fb.size), "setup_ms_tables": setup_tables,
-            "setup_ms_analytic": setup_analytic, "steps": steps, "ms_per_step": t * 1e3,
+            "setup_ms_analytic": setup_analytic, "steps": steps, "ms_per_step": t * 1e3, "plan": plan["plan"],
             "micro_dofs": int(W.offsets(lv)[-1]), "iters_mean": st["iters_mean"], "precision": precision}
 
 
@@ -456,8 +457,11 @@ def refinement_leg(steps=5, theta=0.3):
             ts.append((time.perf_counter() - t0) * 1e3)
         return statistics.median(ts), out
 
+    plans = []
+
     def step_ms(b):
         b.step(1)
+        plans.append(b.autotune(steps=2)["plan"])     # state restored
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.step(steps)
@@ -491,7 +495,7 @@ def refinement_leg(steps=5, theta=0.3):
             "micro_dofs_before": int(W.offsets(lv)[-1]), "micro_dofs_after": int(W.offsets(new2)[-1]),
             "indicator_ms": ms_ind, "marking_ms": ms_mark, "prolong_ms": ms_pro,
             "refine_total_ms": t_refine, "setup_ms_refined": setup2,
-            "ms_per_step_before": before, "ms_per_step_after": after}
+            "ms_per_step_before": before, "ms_per_step_after": after, "plans": plans}
 
 
 def _paper_table_rows():
