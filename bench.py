@@ -64,10 +64,17 @@ FLOP_OPERATOR_MF = 368.0
 # and the two dot products of the guessed and plain residuals (2 x (MUL +
 # FMA)) = 24 flops.
 FLOP_GUESS = 24.0
+# The separable mass of the start residual (default for the analytic family),
+# per DoF: the column pass along R+2 rows for R nodes (5 x 3 FMA a row, ~20
+# FMA a node at R = 6), the row pass (15 FMA) and the 1/dt scale (1 FMA) = 72
+# flops in place of K x0 (18); the refinement adds the low part Slo x0 at
+# its first update (9 FMA = 18 flops).
+FLOP_MASS, FLOP_LOW0 = 72.0 - 18.0, 18.0
 # Bytes the instance-resident micro kernel must move per DoF per step
 # (algorithmic: the vectors of the iterations stay on chip; operators are read
 # from their symmetric upper-half planes, 5 coefficients per node):
-#   both forms: x0 = v0 + u w (read v0, w: 16), r = -K x0 (FP64 K, 40),
+#   both forms: x0 = v0 + u w (read v0, w: 16), r = -K x0 (FP64 K, 40; none
+#               with the separable mass, which comes from per-level tables),
 #               write x (8); b^T x for the flux average is a separate pass
 #               over the 4N boundary nodes (b and x: 16 B each, below 1 B
 #               per node of the mesh)
@@ -107,6 +114,13 @@ def extrapolated(N, flags, refine):
     return packed_under(N, flags) and not matrix_free(N, flags, refine) and not (flags & (1 << 13))
 
 
+def mass_free(N, flags, refine):
+    """Whether the packed kernel on the assembled operator forms its start
+    residual with the separable mass instead of reading K (analytic family;
+    unless the assembled-start flag is set)."""
+    return packed_under(N, flags) and not matrix_free(N, flags, refine) and not (flags & (1 << 14))
+
+
 def micro_bytes_per_dof(N, flags, refine, iters, sweeps):
     """Algorithmic HBM bytes per DoF-update of the micro kernel that solves an
     N x N instance under the launch plan `flags` (packed kernels: symmetric
@@ -118,9 +132,10 @@ def micro_bytes_per_dof(N, flags, refine, iters, sweeps):
         if matrix_free(N, flags, refine):
             return B_START + B_END + bdot
         hist = B_HIST if extrapolated(N, flags, refine) else 0.0
+        kb = 0.0 if mass_free(N, flags, refine) else B_K
         if refine:
-            return B_START + B_K + B_S32 + B_SLO + B_END + hist + bdot
-        return B_START + B_K + B_S64 + B_END + hist + bdot
+            return B_START + kb + B_S32 + B_SLO + B_END + hist + bdot
+        return B_START + kb + B_S64 + B_END + hist + bdot
     slots = next(s for s in GENERIC_SLOTS if s * 256 >= (N + 1) ** 2)
     if refine:   # FP32 stencil once (resident) or per inner iteration; FP64 rows per residual
         return 16 + 72 + 72 * sweeps + (36 if slots <= 9 else 36 * iters) + 16
@@ -141,12 +156,22 @@ KERNEL_SOURCES = ("micro_packed.hip", "device_common.h", "tsm_internal.h")
 COUNTERS = os.path.join(ROOT, "profiles", "micro_kernel_counters.json")
 
 
+def code_text(src):
+    """C++ source without its comments and blank lines (what the counters
+    depend on)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
 def kernel_source_hash():
+    """sha256 of the micro kernels' code (comments excluded)."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2103_17040_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2103_17040_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()
 
 
@@ -831,8 +856,11 @@ def main():
     plan_flags = main_form["plan"]["flags"]
     mf_dofs = sum((N + 1) ** 2 for N in lv.tolist() if matrix_free(int(N), plan_flags, refine))
     ex_dofs = sum((N + 1) ** 2 for N in lv.tolist() if extrapolated(int(N), plan_flags, refine))
+    sm_dofs = sum((N + 1) ** 2 for N in lv.tolist() if mass_free(int(N), plan_flags, refine))
+    flop_sm = FLOP_MASS + (FLOP_LOW0 if refine else 0.0)
     flops = (dofs_per_launch * (FLOP_ITER * iters + FLOP_SWEEP * sweeps + FLOP_SOLVE)
-             + (mf_dofs * FLOP_OPERATOR_MF + ex_dofs * FLOP_GUESS) / max(tst["micro_launches"], 1))
+             + (mf_dofs * FLOP_OPERATOR_MF + ex_dofs * FLOP_GUESS + sm_dofs * flop_sm)
+             / max(tst["micro_launches"], 1))
     step_bytes = sum((N + 1) ** 2 * micro_bytes_per_dof(int(N), plan_flags, refine, iters, sweeps)
                      for N in lv.tolist())
     nbytes = step_bytes / max(tst["micro_launches"], 1)
@@ -883,7 +911,7 @@ def main():
         "hbm_algorithmic_bytes_per_unit": alg_bytes / max(floor_units, 1),
         "hbm_algorithmic_GBs": hbm_alg, "hbm_frac": hbm_frac,
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated); "
-                        "null when the kernel sources changed since the counters were taken",
+                        "null when the kernel code (comments aside) changed since the counters were taken",
         "traffic_over_algorithmic": (traffic / alg_bytes) if traffic else None,
         "traffic_frac_of_hbm_peak": (traffic / t_launch / 1e9 / PEAK_HBM_GBS) if traffic else None,
         "resident_model_bytes_per_unit": nbytes / max(dofs_per_launch, 1),

@@ -117,6 +117,20 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
                                             keeps it with every checkpoint (its recomputed
                                             segments repeat the tape bitwise); its adjoint micro
                                             solves extrapolate from their own history. */
+#define TSM_FLAG_ASSEMBLED_START (1ull << 14) /* time steps form the start residual
+                                            -K x0 + coef M w/dt of the packed solves on the
+                                            assembled operator from the assembled planes of
+                                            K = S - M/dt (one more FP64 operator read per solve).
+                                            By default, for the analytic deformation family, it is
+                                            formed as coef M w/dt + M x0/dt - S x0: M x0 from
+                                            per-level tables (J = det(I + aG) is a sum of five
+                                            products f(y1) g(y2), so with the tensor 2x2 Gauss rule
+                                            M is a sum of five Kronecker products of 1D weighted
+                                            masses; Sections 3.1 and 3.4), S x0 with the stencil
+                                            the solve holds.  FP32_REFINE adds the low part of
+                                            S x0 at its first FP64 residual update.  Results
+                                            differ in rounding only.  Jacobian tables and the
+                                            stationary system always read K. */
 #define TSM_FLAG_TIMING     (1ull << 2)  /* tsm_step launches directly and times each phase with
                                             HIP events on the context's stream (see tsm_stats) */
 #define TSM_FLAG_FIXED_POINT (1ull << 5) /* tsm_step couples macro and micro solves by the paper's

@@ -168,6 +168,7 @@ struct tsm_ctx {
     // tables
     int32_t* tab_off = nullptr;
     double *tab_y = nullptr, *tab_s = nullptr, *tab_c = nullptr;
+    double* tab_m = nullptr;        // separable mass tables (MicroArgs::mass1d)
     // macro solver
     double *rhs = nullptr, *R = nullptr, *T1 = nullptr, *T2 = nullptr, *Q = nullptr, *lam = nullptr;
     int macro_sweeps = 2;
@@ -244,7 +245,7 @@ struct tsm_ctx {
         lg_sets = 0;
         fb_slot = 0;
         free_mg();
-        dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c);
+        dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c); dfree(tab_m);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
         dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd); dfree(lhx); dfree(lhe); dfree(lhn);
         dfree(st_bO); dfree(st_lenO); dfree(st_zI); dfree(st_zO); dfree(st_z0); dfree(st_dots);
@@ -323,6 +324,12 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
         pbase.he = nullptr;
         pbase.hn = nullptr;
     }
+    // the start residual of the packed kernels on the assembled operator
+    // takes M x0 from the separable mass tables where the geometry is the
+    // analytic family (not for Jacobian tables or the stationary system)
+    pbase.mass1d = (pmode != 3 && !c->geom_tables && !c->stationary && !(c->prm.flags & TSM_FLAG_ASSEMBLED_START))
+                       ? c->tab_m
+                       : nullptr;
     // refinement solves that miss rtol are listed and solved again in FP64
     const bool fb = refine && c->n_packs > 0 && c->fb_list != nullptr && c->fb_ws != nullptr;
     if (fb) {
@@ -808,6 +815,34 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
             tc.push_back(0.25 * M_PI * std::cos(M_PI * y));
         }
     }
+    // separable mass tables (MicroArgs::mass1d), 16 (N+1) = 8 (2N+2) doubles
+    // a level, so level N starts at 8 tab_off[N]: for each weight function f
+    // (1, c, y, c y, s of the Gauss abscissa) the 1D Q1 mass
+    // m_jk = (h/2) sum_g f(y_g) phi_j(y_g) phi_k(y_g) over the cells, stored
+    // per node j as the planes (3 f + d + 1) of k = j + d
+    std::vector<double> tm(8 * ty.size(), 0.0);
+    for (int N = kMinLevel; N <= kMaxMesh; ++N) {
+        if (!present[N]) continue;
+        const int NP = N + 1, t0 = toff[N];
+        double* m = tm.data() + 8 * (size_t)t0;
+        const double wh = 1.0 / N;     // h / 2
+        for (int f = 0; f < 5; ++f)
+            for (int e = 0; e < N; ++e) {
+                double m00 = 0.0, m01 = 0.0, m11 = 0.0;
+                for (int g = 0; g < 2; ++g) {
+                    const int t = t0 + 2 * e + g;
+                    const double y = ty[t], fv = f == 0 ? 1.0 : f == 1 ? tc[t] : f == 2 ? y : f == 3 ? tc[t] * y : ts[t];
+                    const double p1 = g ? g1 : g0, p0 = 1.0 - p1;
+                    m00 += wh * fv * p0 * p0;
+                    m01 += wh * fv * p0 * p1;
+                    m11 += wh * fv * p1 * p1;
+                }
+                m[(3 * f + 1) * NP + e] += m00;
+                m[(3 * f + 2) * NP + e] = m01;
+                m[(3 * f + 0) * NP + e + 1] = m01;
+                m[(3 * f + 1) * NP + e + 1] += m11;
+            }
+    }
 
     const int64_t ni = n_inst, tot = c->total;
     HIPALLOC(c->level, ni); HIPALLOC(c->iters, ni); HIPALLOC(c->sweeps, ni);
@@ -869,13 +904,14 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
         HIPALLOC(c->st_Fu, ni); HIPALLOC(c->st_Fw, ni); HIPALLOC(c->st_uDn, ni);
     }
     HIPALLOC(c->tab_off, kMaxMesh + 1); HIPALLOC(c->tab_y, ty.size()); HIPALLOC(c->tab_s, ts.size());
-    HIPALLOC(c->tab_c, tc.size());
+    HIPALLOC(c->tab_c, tc.size()); HIPALLOC(c->tab_m, tm.size());
     HIPCHK(hipMemcpy(c->level, c->level_h.data(), ni * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->offsets, c->off_h.data(), (ni + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->tab_off, toff.data(), toff.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->tab_y, ty.data(), ty.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->tab_s, ts.data(), ts.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->tab_c, tc.data(), tc.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->tab_m, tm.data(), tm.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemset(c->u, 0, ni * sizeof(double)));
     HIPCHK(hipMemset(c->F, 0, ni * sizeof(double)));
     HIPCHK(hipMemset(c->v0, 0, tot * sizeof(double)));
@@ -1526,7 +1562,7 @@ tsm_status tsm_set_flags(tsm_ctx* c, uint64_t flags) {
     if (flags & ~(TSM_FLAG_NO_GRAPH | TSM_FLAG_STENCIL_STREAM | TSM_FLAG_TIMING | TSM_FLAG_GENERIC | TSM_FLAG_PERSISTENT |
                   TSM_FLAG_FIXED_POINT | TSM_FLAG_GENERIC_16 | TSM_FLAG_GENERIC_32 | TSM_FLAG_GENERIC_64 |
                   TSM_FLAG_MATRIX_FREE | TSM_FLAG_MACRO_PCG | TSM_FLAG_MULTIGRID | TSM_FLAG_NO_MULTIGRID |
-                  TSM_FLAG_NO_EXTRAPOLATION))
+                  TSM_FLAG_NO_EXTRAPOLATION | TSM_FLAG_ASSEMBLED_START))
         return c->fail(TSM_EINVAL, "unknown flag bits");
     const bool mg_changed = ((flags ^ c->prm.flags) & (TSM_FLAG_MULTIGRID | TSM_FLAG_NO_MULTIGRID)) != 0;
     HIPCHK(hipStreamSynchronize(c->stream));

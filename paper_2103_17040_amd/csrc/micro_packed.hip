@@ -19,8 +19,10 @@
 // coefficients per node instead of 9, so each operator read costs 40 (FP64)
 // or 20 (FP32) bytes per node; the lower coefficients are loaded from the
 // neighbours' planes (same cache lines as the neighbours' own loads).  Every
-// operator is read once per solve: the start residual from K, the solver's
-// stencil into registers (FP32 planes through an asynchronous LDS copy).
+// operator is read once per solve: the solver's stencil into registers (FP32
+// planes through an asynchronous LDS copy), and for the start residual
+// either K or, for the analytic deformation family, nothing: its mass term
+// comes from per-level 1D tables (mass_apply) and S x0 from the stencil.
 //
 // Register budget (768 lanes: 168 VGPRs per lane) decides the data flow:
 //   FP64 form     the FP64 stencil rows resident in registers for the whole
@@ -28,8 +30,9 @@
 //                 FP32 (the preconditioner need not be exact).
 //   REFINE form   FP32 stencil and diag^{-1} resident in registers for the
 //                 whole solve; FP32 PCG on S d = r/||r||; the FP64 residual
-//                 is formed once as r = -K x0 (K = S - M/dt, the right-hand
-//                 side M x0/dt enters only through its norm), then updated
+//                 is formed once as r = -K x0 (K = S - M/dt), or as
+//                 M x0/dt - S32 x0 with the separable mass (the low part
+//                 -Slo x0 joins at the first update), then updated
 //                 as r <- r - ||r|| S d with the FP64 stencil (FP32 part in
 //                 registers plus the FP32 low part from LDS), x <- x + ||r|| d,
 //                 until ||r|| <= rtol ||b||.
@@ -397,6 +400,16 @@ struct SplitStencil {
     __device__ __forceinline__ double value(int i, int k, float raw) const { return (double)S[i][k] + (double)raw; }
 };
 
+// The low parts alone (the LDS planes of SplitStencil), applied in FP64.
+template <class L>
+struct LowStencil {
+    static constexpr bool kGlobal = false;
+    using raw_t = float;
+    LdsPlanes<L> planes;
+    __device__ __forceinline__ float load(const Lane& z, int i, int k) const { return planes.at(z, i, k); }
+    __device__ __forceinline__ double value(int, int, float raw) const { return (double)raw; }
+};
+
 // y_i = sum_k S_ik g(row r0+i + dr, col + dc) in k order 0..8, one product
 // at a time; own-column values come from mine[].  Streamed coefficients are
 // loaded B rows at a time, all loads of a batch in flight before the first
@@ -585,6 +598,83 @@ __device__ __forceinline__ void history_step(const MicroArgs& A, const Lane& z, 
     }
 }
 
+// Time-step solve whose start residual takes M x0 from the separable mass
+// tables (MicroArgs::mass1d) instead of K x0 from the assembled planes.
+__device__ __forceinline__ bool mass_free(const MicroArgs& A) {
+    return A.mass1d != nullptr && A.rhs_vec == nullptr && A.Mw != nullptr && !A.zero_init;
+}
+
+// Separable mass of the analytic family.  J = det(I + a G) at the point
+// (y1, y2) is 1 + a (c(y1) y2 + y1 c(y2)) + a^2 (c(y1) y1 c(y2) y2 -
+// s(y1) s(y2)): five terms f_T(y1) g_T(y2), and the 2x2 Gauss rule is the
+// tensor product of the 1D rule, so the J-weighted Q1 mass (Section 3.1) is
+//   M = sum_T kappa_T  M1[g_T] (x) M1[f_T],   kappa = (1, a, a, a^2, -a^2),
+//   (f_T, g_T) = (1, 1), (c, y), (y, c), (c y, c y), (s, s),
+// with M1[f] the 1D Q1 mass weighted by f at the Gauss points (table planes
+// per level; Section 3.4 caches J per quadrature point, here its factors
+// per level).  The lane applies M1[f_T] of its column along the rows r0-1 ..
+// r0+R (three grid reads a row), then M1[g_T] of each of its rows across
+// three consecutive such rows: 35 FP64 FMAs per node.  mt: the level's
+// table in LDS (mass_table_copy); x0 in the grid (zero halo); active lanes
+// only; rows past the mesh give 0.
+constexpr int kMassF = 5;
+constexpr int kMassG[kMassF] = {0, 2, 1, 3, 4};     // g_T as a function index
+// Asynchronous copy of the level's table (16 planes of N+1 doubles, the
+// last one padding) into LDS at dst, 16 bytes a lane, without registers; it
+// has landed once the wave has waited for its loads.
+template <class L>
+__device__ __forceinline__ void mass_table_copy(const MicroArgs& A, double* dst) {
+    using gptr = __attribute__((address_space(1))) void*;
+    using lptr = __attribute__((address_space(3))) void*;
+    constexpr int pieces = 8 * L::NP;
+    const double* src = A.mass1d + 8 * A.tab.off[L::N];
+    const int lane = threadIdx.x & (kWave - 1), w0 = threadIdx.x - lane;
+    if (w0 + lane < pieces) __builtin_amdgcn_global_load_lds((gptr)(src + 2 * (w0 + lane)), (lptr)(dst + 2 * w0), 16, 0, 0);
+}
+
+template <class L>
+__device__ __forceinline__ void mass_apply(const double* mt, const Lane& z, const double* xg, double a,
+                                           double (&mx)[L::R]) {
+    constexpr int NP = L::NP, W2 = L::W2;
+    const double a2 = a * a;
+    const double kap[kMassF] = {1.0, a, a, a2, -a2};
+    double fk[kMassF][3];     // kappa_T M1[f_T] of the lane's column
+#pragma unroll
+    for (int t = 0; t < kMassF; ++t)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fk[t][d] = kap[t] * mt[(3 * t + d) * NP + z.col];
+    auto across = [&](int rho, double (&v)[kMassF]) {
+        const int cb = (rho + 1) * W2 + z.col + 1;
+        const double xl = xg[cb - 1], xm = xg[cb], xr = xg[cb + 1];
+#pragma unroll
+        for (int t = 0; t < kMassF; ++t) v[t] = fk[t][0] * xl + fk[t][1] * xm + fk[t][2] * xr;
+    };
+    double vm[kMassF], v0[kMassF], vp[kMassF];
+    across(z.r0 - 1, vm);
+    across(z.r0, v0);
+    // one row's coefficients in flight at a time (hoisting all of them
+    // would spill)
+#pragma unroll
+    for (int i = 0; i < L::R; ++i) {
+        __builtin_amdgcn_sched_barrier(0);
+        const int rho = z.r0 + i;
+        across(rho + 1, vp);
+        const double* gp = mt + (rho < NP ? rho : NP - 1);
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < kMassF; ++t) {
+            const double* gt = gp + 3 * kMassG[t] * NP;
+            s += gt[0] * vm[t] + gt[NP] * v0[t] + gt[2 * NP] * vp[t];
+        }
+        mx[i] = rho < NP ? s : 0.0;
+#pragma unroll
+        for (int t = 0; t < kMassF; ++t) {
+            vm[t] = v0[t];
+            v0[t] = vp[t];
+        }
+    }
+}
+
 // x0 into registers and the (double) grid, then the FP64 residual:
 //   given right-hand side:  b = rhs_scale rhs [+ rhs_bscale c_i b_i],  r = b - S x0,
 //                           and the partial ||b||^2 in bb
@@ -599,6 +689,9 @@ __device__ __forceinline__ void history_step(const MicroArgs& A, const Lane& z, 
 // FP32 planes into LDS (planes_copy_start) once x0 is in the grid, so that it
 // overlaps the operator application; the caller waits for it
 // (planes_copy_wait).
+// mtab (non-null, LDS for the level's table) with mass_free: the separable
+// mass; r leaves with coef M w/dt + M x0/dt, the right-hand side b itself,
+// and the caller subtracts S x0.
 // hslot (non-null) with hist >= 0 (history_steps of the launch): the
 // history of the lane's rows is read with X0, the predicted increment goes
 // to the lane's slots hslot[i * NTP + lane] (history_step; every lane writes
@@ -608,7 +701,9 @@ template <class L>
 __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, double* xg, double (&x)[L::R],
                                            double (&r)[L::R], double& bb, const float* copy_src = nullptr,
                                            float* copy_dst = nullptr, int copy_shift = 0, float* hslot = nullptr,
-                                           int hist = -1) {
+                                           int hist = -1, double* mtab = nullptr) {
+    const bool sep = mtab != nullptr && mass_free(A);
+    if (sep) mass_table_copy<L>(A, mtab);
     zero_halo<L, double>(xg, z);
     const double cf = (z.live && A.coef != nullptr) ? A.coef[z.inst] : 0.0;
     // time step with M w: start from X0 alone; the right-hand side keeps
@@ -638,6 +733,8 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
         le[i] = ep;
     }
     strip_store<L>(xg, z, x);
+    // (the mass table copy has landed in every wave past this barrier)
+    if (sep) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (hn >= 0) {
         float g[L::R];
@@ -666,6 +763,10 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
             r[i] = b[i] - sx[i];
             bb += b[i] * b[i];
         }
+    } else if (sep) {
+        if (z.act) mass_apply<L>(mtab, z, xg, A.amp[z.inst], sx);
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) r[i] = cm[i] + A.inv_dt * sx[i];
     } else {
         if (z.act) strip_apply_lean<L, L::R>(SymStencil<L, double>{A.Ks64 + kSym * z.off}, xg, z, x, sx);
 #pragma unroll
@@ -966,13 +1067,13 @@ __device__ __forceinline__ void mf_start(const MicroArgs& A, const Lane& z, doub
 template <class L, bool CS = false, class Prefetch>
 __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, double* xs,
                           PackRed<1, double>& red1, PackRed<2, double>& red2, PackRed<3, double>& red3,
-                          Prefetch prefetch, double* cs = nullptr, int hist = -1) {
+                          Prefetch prefetch, double* cs = nullptr, int hist = -1, double* mtab = nullptr) {
     const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     double x[L::R], r[L::R], p[L::R];
     float dinv[L::R];
     double bb;
-    pack_start<L>(A, z, xg, x, r, bb);
+    pack_start<L>(A, z, xg, x, r, bb, nullptr, nullptr, 0, nullptr, -1, mtab);
     prefetch();
 #pragma unroll
     for (int i = 0; i < L::R; ++i) xs[i * NTP + threadIdx.x] = x[i];
@@ -1002,9 +1103,12 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
             if constexpr (CS) strip_apply_lean<L, 1>(SL, xg, z, x, sb);
             else strip_apply_lean<L, 1>(S, xg, z, x, sb);
         }
+        // (separable mass: r holds b, and r = b - S x0 from here on)
+        const bool mfree = mtab != nullptr && mass_free(A);
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
-            const double bi = sb[i] + r[i];
+            const double bi = mfree ? r[i] : sb[i] + r[i];
+            if (mfree) r[i] -= sb[i];
             bb += row_ok<L>(z, i) ? bi * bi : 0.0;
         }
     }
@@ -1124,8 +1228,9 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
 // the stored-operator form; null: none); hist: history_steps of the launch.
 template <class L, bool MF, class Prefetch>
 __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, double* lds, float* planes,
-                            MfShared* ms, PackRed<1, double>& red1, PackRed<2, double>& red2,
-                            PackRed<2, float>& rf2, Prefetch prefetch, float* hslot, int hist) {
+                            MfShared* ms, PackRed<1, double>& red1, PackRed<3, double>& red3,
+                            PackRed<2, float>& rf2, Prefetch prefetch, float* hslot, int hist,
+                            double* mtab = nullptr) {
     const Lane z = lane_of<L>(meta, cnt);
     double* xg = lds + (z.sub < L::IPP ? z.sub : 0) * L::GRID;
     float* pg = reinterpret_cast<float*>(xg);
@@ -1148,7 +1253,7 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
         for (int i = 0; i < L::R; ++i) x[i] = row_ok<L>(z, i) ? xg[cell_of<L>(z, i)] : 0.0;
         prefetch();
     } else {
-        pack_start<L>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift, hslot, hist);
+        pack_start<L>(A, z, xg, x, r64, bb, A.Ss32 + kSym * z.off, region, shift, hslot, hist, mtab);
         if (hslot != nullptr) hn = hist;
         planes_copy_wait();
         const LdsPlanes<L> plc(pl, z);
@@ -1169,6 +1274,10 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
     const LdsPlanes<L> plv(pl, z);
     const RegStencil<L, float> SR{S};
     const SplitStencil<L> S64{S, plv};
+    // separable mass (stored-operator form): r64 holds b = coef M w/dt +
+    // M x0/dt and becomes b - S32 x0 here; the low part -Slo x0 joins at the
+    // first FP64 update (the low parts arrive during the first inner solve)
+    const bool mfree = !MF && mtab != nullptr && mass_free(A);
     if (A.rhs_vec == nullptr) {
         // ||b|| of the time step from b = S x0 + r (S in FP32: the norm only
         // sizes the tolerance, ~1e-7 relative is plenty); x0 is in the grid
@@ -1178,25 +1287,37 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
         if (z.act) strip_apply<L, L::R>(SR, xg, z, x, sb);
 #pragma unroll
         for (int i = 0; i < L::R; ++i) {
-            const double bi = sb[i] + r64[i];
+            const double bi = mfree ? r64[i] : sb[i] + r64[i];
+            if (mfree) r64[i] -= sb[i];
             bb += row_ok<L>(z, i) ? bi * bi : 0.0;
         }
     }
-    double acc[2] = {bb, 0.0};     // ||b||^2, ||r||^2
+    // ||b||^2, ||r||^2 and the residual of the start test: without the low
+    // part, r64 is exact only where x0 = 0, so an instance with x0 != 0
+    // takes at least one sweep (its test value is huge)
+    bool nz = false;
+#pragma unroll
+    for (int i = 0; i < L::R; ++i) nz = nz || x[i] != 0.0;
+    double acc[3] = {bb, 0.0, (mfree && nz) ? 1e300 : 0.0};
 #pragma unroll
     for (int i = 0; i < L::R; ++i) acc[1] += r64[i] * r64[i];
-    red2.sum<L>(acc, z.w0);
+    acc[2] += acc[1];
+    red3.sum<L>(acc, z.w0);
     __shared__ double otol_s[L::IPP];
     __shared__ float itol_s[L::IPP];
     const double tol2 = A.rtol * A.rtol * acc[0];
     if (z.live && z.lt == 0) otol_s[z.sub] = tol2;
     double rr = acc[1];
-    bool conv = rr <= tol2;
+    bool conv = acc[2] <= tol2;
     int sweeps = 1, iters = 0;
     zero_halo<L, float>(pg, z);     // the float view of the grid from here on
+    // second float grid (the upper half of the double one): x0 in FP32 for
+    // the low-part term of the first update
+    float* pg2 = pg + L::GRID;
+    if (mfree) zero_halo<L, float>(pg2, z);
     lds_barrier();
     const double othr = lane_threshold<L>(otol_s, cnt);
-    bool ogo = red2.any_above(othr);
+    bool ogo = red3.any_above(othr);
     while (ogo && sweeps <= A.max_refine) {
         // Inner FP32 solve of S d = r / ||r|| by the Chronopoulos-Gear form of
         // PCG: s = S p is carried by a recurrence, so each iteration needs one
@@ -1310,10 +1431,31 @@ __device__ void pack_refine(const MicroArgs& A, const int32_t* meta, int cnt, do
         }
         // x += ||r|| d;  r64 -= ||r|| S d  (FP64 stencil, d exact in FP64)
         const double sc = me ? rn : 0.0;
+        // separable mass, first update: also r64 -= Slo x0 (x0 in FP32 in the
+        // second grid: the low parts are ~2^-24 of S, so this rounding is
+        // ~2^-48 of S x0, the size of the split's own)
+        const bool low0 = mfree && sweeps == 1;
+        if (low0) {
+            float x0f[L::R];
+#pragma unroll
+            for (int i = 0; i < L::R; ++i) x0f[i] = (float)x[i];
+            strip_store<L>(pg2, z, x0f);
+        }
 #pragma unroll
         for (int i = 0; i < L::R; ++i) x[i] += sc * (double)d[i];
         strip_store<L>(pg, z, d);
         planes_copy_wait();     // the low parts are in LDS from here on
+        if (low0 && z.act) {
+            float x0f[L::R];
+#pragma unroll
+            for (int i = 0; i < L::R; ++i) x0f[i] = pg2[cell_of<L>(z, i)];
+            double s0[L::R];
+#pragma unroll
+            for (int i = 0; i < L::R; ++i) s0[i] = 0.0;
+            strip_apply_lean<L, 1>(LowStencil<L>{plv}, pg2, z, x0f, s0);
+#pragma unroll
+            for (int i = 0; i < L::R; ++i) r64[i] -= s0[i];
+        }
         double sd[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) sd[i] = 0.0;
@@ -1420,21 +1562,24 @@ __global__ __launch_bounds__(NTP) void packed_kernel(MicroArgs A, PackList P) {
     if constexpr (MODE == 2) {
         __shared__ __attribute__((aligned(16))) float planes[L::PS * L::IPP + 2 * L::NP];
         __shared__ float hslot[L::R * NTP];
+        __shared__ __attribute__((aligned(16))) double mtab[16 * L::NP];
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_refine<L, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot, sh.hist);
+            pack_refine<L, false>(A, meta, cnt, lds, planes, nullptr, red1, red3, rf2, prefetch, hslot, sh.hist,
+                                  mtab);
         });
     } else if constexpr (MODE == 3) {
         __shared__ __attribute__((aligned(16))) float planes[L::PS * L::IPP + 2 * L::NP];
         __shared__ MfShared ms;
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_refine<L, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr, -1);
+            pack_refine<L, true>(A, meta, cnt, lds, planes, &ms, red1, red3, rf2, prefetch, nullptr, -1);
         });
     } else {
         __shared__ double xs[L::R * NTP];
         // the corner couplings of the resident stencil (2 x R doubles a lane)
         __shared__ double cs[2 * L::R * NTP];
+        __shared__ __attribute__((aligned(16))) double mtab[16 * L::NP];
         pack_loop(A, P, nullptr, sh, [&](const int32_t* meta, int cnt, int, auto prefetch) {
-            pack_fp64<L, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist);
+            pack_fp64<L, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist, mtab);
         });
     }
 }
@@ -1453,30 +1598,36 @@ __global__ __launch_bounds__(NTP) void packed_mixed_kernel(MicroArgs A, PackList
     if constexpr (MODE == 2) {
         __shared__ __attribute__((aligned(16))) float planes[kPlaneFloats];
         __shared__ float hslot[kFp64Rows * NTP];
+        __shared__ __attribute__((aligned(16))) double mtab[16 * (kMaxLevel + 1)];
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
             if (lvl == 64)
-                pack_refine<L64, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot, sh.hist);
+                pack_refine<L64, false>(A, meta, cnt, lds, planes, nullptr, red1, red3, rf2, prefetch, hslot, sh.hist,
+                                        mtab);
             else if (lvl == 32)
-                pack_refine<L32, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot, sh.hist);
-            else pack_refine<L16, false>(A, meta, cnt, lds, planes, nullptr, red1, red2, rf2, prefetch, hslot, sh.hist);
+                pack_refine<L32, false>(A, meta, cnt, lds, planes, nullptr, red1, red3, rf2, prefetch, hslot, sh.hist,
+                                        mtab);
+            else pack_refine<L16, false>(A, meta, cnt, lds, planes, nullptr, red1, red3, rf2, prefetch, hslot, sh.hist,
+                                         mtab);
         });
     } else if constexpr (MODE == 3) {
         __shared__ __attribute__((aligned(16))) float planes[kPlaneFloats];
         __shared__ MfShared ms;
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
             if (lvl == 64)
-                pack_refine<L64, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr, -1);
+                pack_refine<L64, true>(A, meta, cnt, lds, planes, &ms, red1, red3, rf2, prefetch, nullptr, -1);
             else if (lvl == 32)
-                pack_refine<L32, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr, -1);
-            else pack_refine<L16, true>(A, meta, cnt, lds, planes, &ms, red1, red2, rf2, prefetch, nullptr, -1);
+                pack_refine<L32, true>(A, meta, cnt, lds, planes, &ms, red1, red3, rf2, prefetch, nullptr, -1);
+            else pack_refine<L16, true>(A, meta, cnt, lds, planes, &ms, red1, red3, rf2, prefetch, nullptr, -1);
         });
     } else {
         __shared__ double xs[kFp64Rows * NTP];
         __shared__ double cs[2 * kFp64Rows * NTP];
+        __shared__ __attribute__((aligned(16))) double mtab[16 * (kMaxLevel + 1)];
         pack_loop(A, P, pack_level, sh, [&](const int32_t* meta, int cnt, int lvl, auto prefetch) {
-            if (lvl == 64) pack_fp64<L64, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist);
-            else if (lvl == 32) pack_fp64<L32, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist);
-            else pack_fp64<L16, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist);
+            if (lvl == 64) pack_fp64<L64, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist, mtab);
+            else if (lvl == 32)
+                pack_fp64<L32, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist, mtab);
+            else pack_fp64<L16, true>(A, meta, cnt, lds, xs, red1, red2, red3, prefetch, cs, sh.hist, mtab);
         });
     }
 }

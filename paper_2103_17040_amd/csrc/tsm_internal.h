@@ -183,6 +183,15 @@ struct MicroArgs {
     float* hx;
     float* he;
     const int32_t* hn;
+    // separable mass of the analytic deformation family (packed kernels on
+    // the assembled operator, time-step form; null: none).  For level N the
+    // table starts at mass1d + 8 tab.off[N]: 15 planes of N+1 doubles, plane
+    // 3 f + d + 1 the 1D Q1 mass weighted at the Gauss points by function f
+    // (1, c, y, c y, s) between node j and node j + d (d = -1, 0, +1; zero
+    // past the ends).  With it the start residual is coef M w/dt + M x0/dt
+    // - S x0 (S from the stencil the solve holds) instead of -K x0 + coef
+    // M w/dt with K read from the assembled planes.
+    const double* mass1d;
 };
 
 // Packs of instances of one mesh size solved by one kPackThreads-lane workgroup.

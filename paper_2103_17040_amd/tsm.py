@@ -35,6 +35,7 @@ TSM_FLAG_MACRO_PCG = 1 << 10
 TSM_FLAG_MULTIGRID = 1 << 11
 TSM_FLAG_NO_MULTIGRID = 1 << 12
 TSM_FLAG_NO_EXTRAPOLATION = 1 << 13
+TSM_FLAG_ASSEMBLED_START = 1 << 14
 TSM_PART_N, TSM_PART_I, TSM_PART_O = 0, 1, 2
 
 STATUS_NAMES = {0: "TSM_OK", -1: "TSM_EINVAL", -2: "TSM_EGEOM", -3: "TSM_ENOCONV",

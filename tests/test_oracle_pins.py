@@ -133,6 +133,36 @@ def test_micro_operator_structure(a, theta):
         assert abs(b.sum() - 8.0) < 1e-14 and abs(one @ (M @ one) - 4.0) < 1e-14
 
 
+@pytest.mark.parametrize("N,a,theta", [(3, 0.0, 0.0), (5, 0.27, 0.4), (8, -0.3, 1.1)])
+def test_mass_is_a_sum_of_kronecker_products(N, a, theta):
+    """For the map family, J = det(I + aG) = 1 + a(c(y1) y2 + y1 c(y2))
+    + a^2 (c(y1) y1 c(y2) y2 - s(y1) s(y2)) with s = sin(pi y)/4 and
+    c = pi cos(pi y)/4, each term a product f(y1) g(y2); the 2x2 Gauss rule
+    is a tensor rule, so the J-weighted Q1 mass is sum_T kappa_T (M1[g_T] x
+    M1[f_T]) with 1D masses weighted at the 1D Gauss points (node order
+    j = j2 (N+1) + j1).  Built here from the 1D rule alone and compared with
+    the oracle's 2D assembly (R_theta leaves J unchanged)."""
+    h = 2.0 / N
+    gx = np.array([0.5 - 0.5 / math.sqrt(3.0), 0.5 + 0.5 / math.sqrt(3.0)])
+
+    def m1(f):
+        m = np.zeros((N + 1, N + 1))
+        for e in range(N):
+            for t in gx:
+                y = -1.0 + (e + t) * h
+                phi = np.array([1.0 - t, t])
+                m[e:e + 2, e:e + 2] += 0.5 * h * f(y) * np.outer(phi, phi)
+        return m
+
+    s = lambda y: math.sin(math.pi * y) / 4
+    c = lambda y: math.pi * math.cos(math.pi * y) / 4
+    terms = [(1.0, lambda y: 1.0, lambda y: 1.0), (a, c, lambda y: y), (a, lambda y: y, c),
+             (a * a, lambda y: c(y) * y, lambda y: c(y) * y), (-a * a, s, s)]
+    Ms = sum(k * np.kron(m1(g), m1(f)) for k, f, g in terms)
+    M = fem.micro_matrices(N, a, theta)[0].toarray()
+    assert np.abs(M - Ms).max() <= 1e-14 * np.abs(M).max()
+
+
 def test_geometry_totals_equal_square():
     """Y_x = Y = [-1,1]^2 for every amplitude, so the discrete volume
     1^T M 1 and boundary length 1^T B 1 equal 4 and 8.  The amplitude-linear
