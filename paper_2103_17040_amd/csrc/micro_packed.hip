@@ -712,25 +712,41 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
     const int hn = hslot != nullptr ? hist : -1;
     double cm[L::R];
     float lh[L::R], le[L::R];
+    // the rows' loads: no arithmetic and no uniform branch inside a row's
+    // branch, so that every row's loads are in flight before the first wait
+    // (M w, or w, in wv)
+    double wv[L::R];
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
-        double v = 0.0, m = 0.0;
-        float xp = 0.0f, ep = 0.0f;
-        if (row_ok<L>(z, i) && !A.zero_init) {
-            const int j = node_of<L>(z, i);
-            if (use_mw) {
-                v = A.X0[z.off + j];
-                m = cf * A.inv_dt * A.Mw[z.off + j];
-                if (hn >= 1) xp = A.hx[z.off + j];
-                if (hn >= 2) ep = A.he[z.off + j];
-            } else {
-                v = A.X0[z.off + j] + cf * A.w[z.off + j];
+        x[i] = 0.0;
+        wv[i] = 0.0;
+        lh[i] = 0.0f;
+        le[i] = 0.0f;
+    }
+    if (!A.zero_init) {
+        const double* ws = use_mw ? A.Mw : A.w;
+#pragma unroll
+        for (int i = 0; i < L::R; ++i)
+            if (row_ok<L>(z, i)) {
+                x[i] = A.X0[z.off + node_of<L>(z, i)];
+                wv[i] = ws[z.off + node_of<L>(z, i)];
             }
+        if (hn >= 1) {
+#pragma unroll
+            for (int i = 0; i < L::R; ++i)
+                if (row_ok<L>(z, i)) lh[i] = A.hx[z.off + node_of<L>(z, i)];
         }
-        x[i] = v;
-        cm[i] = m;
-        lh[i] = xp;
-        le[i] = ep;
+        if (hn >= 2) {
+#pragma unroll
+            for (int i = 0; i < L::R; ++i)
+                if (row_ok<L>(z, i)) le[i] = A.he[z.off + node_of<L>(z, i)];
+        }
+    }
+    const double cmf = use_mw ? cf * A.inv_dt : 0.0, cw = use_mw ? 0.0 : cf;
+#pragma unroll
+    for (int i = 0; i < L::R; ++i) {
+        cm[i] = cmf * wv[i];
+        x[i] += cw * wv[i];
     }
     strip_store<L>(xg, z, x);
     // (the mass table copy has landed in every wave past this barrier)
