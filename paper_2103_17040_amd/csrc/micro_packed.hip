@@ -706,6 +706,9 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
     if (sep) mass_table_copy<L>(A, mtab);
     zero_halo<L, double>(xg, z);
     const double cf = (z.live && A.coef != nullptr) ? A.coef[z.inst] : 0.0;
+    // the amplitude of the separable mass, loaded with the rows (no load
+    // can pass the barrier that follows them)
+    const double am = (sep && z.live) ? A.amp[z.inst] : 0.0;
     // time step with M w: start from X0 alone; the right-hand side keeps
     // coef w through cm[i] = coef (M w)_j / dt
     const bool use_mw = A.rhs_vec == nullptr && A.Mw != nullptr && !A.zero_init;
@@ -780,7 +783,7 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
             bb += b[i] * b[i];
         }
     } else if (sep) {
-        if (z.act) mass_apply<L>(mtab, z, xg, A.amp[z.inst], sx);
+        if (z.act) mass_apply<L>(mtab, z, xg, am, sx);
 #pragma unroll
         for (int i = 0; i < L::R; ++i) r[i] = cm[i] + A.inv_dt * sx[i];
     } else {
