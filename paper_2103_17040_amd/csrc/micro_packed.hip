@@ -682,7 +682,9 @@ __device__ __forceinline__ void mass_apply(const double* mt, const Lane& z, cons
 //   time step with Mw:      the iterate starts from y0 = X0 (x0 = y0 + coef w)
 //                           and r = b - S y0 = -K y0 + coef M w / dt
 // (K = S - M/dt is stored on its own, so the residual carries no
-// cancellation).  The time-step forms leave ||b||^2 to the caller (bb = 0),
+// cancellation; the separable-mass start below forms b - S y0 instead, a
+// difference of two terms of size ||b|| that is exact to ~1e-16 ||b||, far
+// below rtol ||b||).  The time-step forms leave ||b||^2 to the caller (bb = 0),
 // which forms b = S y0 + r from its register stencil (y0 stays in the
 // double grid) instead of reading M.
 // copy_src/copy_dst (non-null): start the asynchronous copy of the instance's
