@@ -60,9 +60,9 @@ FLOP_ITER, FLOP_SWEEP, FLOP_SOLVE = 31.0, 33.0, 43.0   # (refine: S x0 replaces 
 # (~10 ADD): 4 * 69 + 50 + 32 + 10 = 368 flops.
 FLOP_OPERATOR_MF = 368.0
 # The extrapolated start of the first inner solve, per DoF: e1 = X0 - hx and
-# the linear extrapolation (3), the guess's residual r - S d0 (9 FMA + 1 ADD)
-# and the two dot products of the guessed and plain residuals (2 x (MUL +
-# FMA)) = 24 flops.
+# the extrapolation 3 (e1 - e2) + e3 (3), the guess's residual r - S d0 (9 FMA
+# + 1 ADD) and the two dot products of the guessed and plain residuals (2 x
+# (MUL + FMA)) = 24 flops.
 FLOP_GUESS = 24.0
 # The separable mass of the start residual (default for the analytic family),
 # per DoF: the column pass along R+2 rows for R nodes (5 x 3 FMA a row, ~20
@@ -86,8 +86,9 @@ FLOP_MASS, FLOP_LOW0 = 72.0 - 18.0, 18.0
 B_START, B_K, B_END = 16.0, 40.0, 8.0
 B_S64, B_S32, B_SLO = 40.0, 20.0, 20.0
 #   extrapolated start (packed kernels on the assembled operator): the
-#   previous X0 and increment read and written in FP32 (8 + 8)
-B_HIST = 16.0
+#   previous X0 and the two increments before it read and written in FP32
+#   (12 + 12)
+B_HIST = 24.0
 
 
 PACKED_LEVELS = (16, 32, 64)

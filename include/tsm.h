@@ -104,8 +104,9 @@ enum { TSM_FP64 = 0, TSM_FP32_REFINE = 1 };
 #define TSM_FLAG_NO_EXTRAPOLATION (1ull << 13) /* time steps start every micro solve from
                                             the previous state.  By default the packed kernels
                                             with the assembled operator start it from the previous
-                                            state plus the increment extrapolated linearly from
-                                            the last two steps (two FP32 values of history per
+                                            state plus the increment extrapolated quadratically
+                                            from the last three steps, 3 e1 - 3 e2 + e3 (linearly,
+                                            2 e1 - e2, after two; three FP32 values of history per
                                             micro DoF; an instance whose guessed residual is not
                                             smaller drops the guess; in FP32_REFINE the guess
                                             starts the first inner solve).  The FP64 residual

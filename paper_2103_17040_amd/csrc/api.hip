@@ -116,10 +116,12 @@ struct tsm_ctx {
     double* fb_ws = nullptr;
     int64_t fb_slot = 0;
     // history of the extrapolated start of the forward refinement solves:
-    // the previous X0 and increment (FP32 per micro DoF) and the number of
-    // steps they cover (device counter, advanced inside the step graph)
+    // the previous X0 and the two increments before it (FP32 per micro DoF)
+    // and the number of steps they cover (device counter, advanced inside
+    // the step graph)
     float* hx = nullptr;
     float* he = nullptr;
+    float* he2 = nullptr;
     int32_t* hn = nullptr;
     // multigrid-preconditioned micro solves (stationary contexts with
     // TSM_FLAG_MULTIGRID): per-instance coarse levels, Galerkin operators,
@@ -191,7 +193,7 @@ struct tsm_ctx {
     // adjoint work vectors (first tsm_gradient)
     double *lam0 = nullptr, *mu = nullptr, *coef = nullptr, *grad = nullptr, *Jd = nullptr;
     // history of the extrapolated start of the adjoint micro solves (lam0)
-    float *lhx = nullptr, *lhe = nullptr;
+    float *lhx = nullptr, *lhe = nullptr, *lhe2 = nullptr;
     int32_t* lhn = nullptr;
     double grad_fwd_ms = 0.0, grad_bwd_ms = 0.0;
 
@@ -241,13 +243,13 @@ struct tsm_ctx {
         dfree(Ss64); dfree(Ks64); dfree(Ss32); dfree(Sslo);
         dfree(amp); dfree(beta); dfree(len); dfree(jmin); dfree(bx); dfree(alpha); dfree(F); dfree(u);
         dfree(S64); dfree(M64); dfree(b); dfree(w); dfree(Mw); dfree(v0); dfree(S32); dfree(Slo);
-        dfree(bcomp); dfree(lg_ws); dfree(fb_list); dfree(fb_ws); dfree(hx); dfree(he); dfree(hn);
+        dfree(bcomp); dfree(lg_ws); dfree(fb_list); dfree(fb_ws); dfree(hx); dfree(he); dfree(he2); dfree(hn);
         lg_sets = 0;
         fb_slot = 0;
         free_mg();
         dfree(tab_off); dfree(tab_y); dfree(tab_s); dfree(tab_c); dfree(tab_m);
         dfree(pk_first); dfree(pk_count); dfree(pk_level); dfree(pk_slot_inst); dfree(pk_slot_off);
-        dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd); dfree(lhx); dfree(lhe); dfree(lhn);
+        dfree(lam0); dfree(mu); dfree(coef); dfree(grad); dfree(Jd); dfree(lhx); dfree(lhe); dfree(lhe2); dfree(lhn);
         dfree(st_bO); dfree(st_lenO); dfree(st_zI); dfree(st_zO); dfree(st_z0); dfree(st_dots);
         dfree(st_w); dfree(st_work); dfree(st_info); dfree(st_iters); dfree(st_sweeps);
         dfree(st_wcell); dfree(st_wbnd); dfree(st_Fv); dfree(st_GI); dfree(st_GO); dfree(st_Fu); dfree(st_Fw);
@@ -322,6 +324,7 @@ tsm_status enqueue_micro(tsm_ctx* c, MicroArgs base, bool setup, hipStream_t st,
     if (pmode == 3 || c->n_packs == 0) {
         pbase.hx = nullptr;
         pbase.he = nullptr;
+        pbase.he2 = nullptr;
         pbase.hn = nullptr;
     }
     // the start residual of the packed kernels on the assembled operator
@@ -584,6 +587,7 @@ tsm_status enqueue_step(tsm_ctx* c, const hipEvent_t* ev = nullptr) {
     if (c->hx != nullptr && !(c->prm.flags & TSM_FLAG_NO_EXTRAPOLATION)) {
         a.hx = c->hx;
         a.he = c->he;
+        a.he2 = c->he2;
         a.hn = c->hn;
     }
     tsm_status st = enqueue_micro(c, a, false);
@@ -878,7 +882,7 @@ tsm_status tsm_set_reference_mesh(tsm_ctx* c, const int32_t* micro_cells, int64_
         if (nmax > 0) HIPALLOC(c->fb_ws, (size_t)c->n_cu * 3 * nmax);
     }
     if (!c->stationary) {
-        HIPALLOC(c->hx, tot); HIPALLOC(c->he, tot); HIPALLOC(c->hn, 1);
+        HIPALLOC(c->hx, tot); HIPALLOC(c->he, tot); HIPALLOC(c->he2, tot); HIPALLOC(c->hn, 1);
         HIPCHK(launch_fill_i32(c->hn, 0, 1, c->stream));
     }
     if (c->stationary) {
@@ -1384,7 +1388,7 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
         HIPALLOC(c->lam0, tot); HIPALLOC(c->mu, ni); HIPALLOC(c->coef, ni); HIPALLOC(c->grad, ni);
         HIPALLOC(c->Jd, 1);
         if (c->hx != nullptr) {
-            HIPALLOC(c->lhx, tot); HIPALLOC(c->lhe, tot); HIPALLOC(c->lhn, 1);
+            HIPALLOC(c->lhx, tot); HIPALLOC(c->lhe, tot); HIPALLOC(c->lhe2, tot); HIPALLOC(c->lhn, 1);
         }
     }
     const bool extrap = c->hx != nullptr && !(c->prm.flags & TSM_FLAG_NO_EXTRAPOLATION);
@@ -1393,17 +1397,18 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
            *save_F = nullptr;
     // the history of the extrapolated start at every checkpoint, so that a
     // recomputed segment repeats its steps bitwise
-    float *ck_hx = nullptr, *ck_he = nullptr;
+    float *ck_hx = nullptr, *ck_he = nullptr, *ck_he2 = nullptr;
     int32_t* ck_hn = nullptr;
     auto release = [&]() {
         dfree(U); dfree(ck_u); dfree(ck_v); dfree(V); dfree(save_u); dfree(save_v); dfree(save_F);
-        dfree(ck_hx); dfree(ck_he); dfree(ck_hn);
+        dfree(ck_hx); dfree(ck_he); dfree(ck_he2); dfree(ck_hn);
     };
     const size_t nh = extrap ? (size_t)nseg : 0;
     if (dalloc(&U, (size_t)(N + 1) * ni) != hipSuccess || dalloc(&ck_u, (size_t)nseg * ni) != hipSuccess ||
         dalloc(&ck_v, (size_t)nseg * tot) != hipSuccess || dalloc(&V, (size_t)(K + 1) * tot) != hipSuccess ||
         dalloc(&save_u, ni) != hipSuccess || dalloc(&save_v, tot) != hipSuccess || dalloc(&save_F, ni) != hipSuccess ||
         dalloc(&ck_hx, nh * tot) != hipSuccess || dalloc(&ck_he, nh * tot) != hipSuccess ||
+        dalloc(&ck_he2, nh * tot) != hipSuccess ||
         dalloc(&ck_hn, nh) != hipSuccess) {
         (void)hipGetLastError();
         release();
@@ -1430,6 +1435,7 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
                 if (extrap) {
                     HIPCHK(hipMemcpyAsync(ck_hx + q * tot, c->hx, tot * sizeof(float), hipMemcpyDeviceToDevice, s));
                     HIPCHK(hipMemcpyAsync(ck_he + q * tot, c->he, tot * sizeof(float), hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(ck_he2 + q * tot, c->he2, tot * sizeof(float), hipMemcpyDeviceToDevice, s));
                     HIPCHK(hipMemcpyAsync(ck_hn + q, c->hn, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
                 }
             }
@@ -1459,6 +1465,7 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
             if (extrap) {
                 HIPCHK(hipMemcpyAsync(c->hx, ck_hx + (size_t)sg * tot, tot * sizeof(float), hipMemcpyDeviceToDevice, s));
                 HIPCHK(hipMemcpyAsync(c->he, ck_he + (size_t)sg * tot, tot * sizeof(float), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(c->he2, ck_he2 + (size_t)sg * tot, tot * sizeof(float), hipMemcpyDeviceToDevice, s));
                 HIPCHK(hipMemcpyAsync(c->hn, ck_hn + sg, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
             }
             HIPCHK(launch_state_join((int)ni, c->offsets, c->u, c->v0, c->w, V, s));
@@ -1483,6 +1490,7 @@ tsm_status tsm_gradient(tsm_ctx* c, int32_t n_steps, double* J_out, double* dJda
                 if (extrap) {
                     ma.hx = c->lhx;
                     ma.he = c->lhe;
+                    ma.he2 = c->lhe2;
                     ma.hn = c->lhn;
                 }
                 tsm_status e3 = enqueue_micro(c, ma, false);

@@ -591,7 +591,7 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, int n) {
 
 // One more step of history for the extrapolated start (at most two are used).
 __global__ void history_advance_kernel(int32_t* hn) {
-    if (threadIdx.x == 0) hn[0] = hn[0] < 2 ? hn[0] + 1 : 2;
+    if (threadIdx.x == 0) hn[0] = hn[0] < 3 ? hn[0] + 1 : 3;
 }
 
 }  // namespace

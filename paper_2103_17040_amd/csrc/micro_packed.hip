@@ -553,47 +553,53 @@ __device__ __forceinline__ int history_steps(const MicroArgs& A) {
     return (A.rhs_vec == nullptr && A.Mw != nullptr && !A.zero_init && A.hx != nullptr) ? *A.hn : -1;
 }
 
-// Issue the loads of the history of the lane's rows (hx, and he with two
-// steps), all in one block: rows past the mesh read node 0 (discarded).
+// Issue the loads of the history of the lane's rows (hx; he with two steps;
+// he2 with three), all in one block: rows past the mesh read node 0
+// (discarded).
 template <class L>
 __device__ __forceinline__ void history_load(const MicroArgs& A, const Lane& z, int hn, float (&lh)[L::R],
-                                             float (&le)[L::R]) {
+                                             float (&le)[L::R], float (&le2)[L::R]) {
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
         lh[i] = 0.0f;
         le[i] = 0.0f;
+        le2[i] = 0.0f;
+    }
+    if (hn >= 1) {
+#pragma unroll
+        for (int i = 0; i < L::R; ++i) lh[i] = A.hx[z.off + (row_ok<L>(z, i) ? node_of<L>(z, i) : 0)];
     }
     if (hn >= 2) {
 #pragma unroll
-        for (int i = 0; i < L::R; ++i) {
-            const int j = row_ok<L>(z, i) ? node_of<L>(z, i) : 0;
-            lh[i] = A.hx[z.off + j];
-            le[i] = A.he[z.off + j];
-        }
-    } else if (hn == 1) {
+        for (int i = 0; i < L::R; ++i) le[i] = A.he[z.off + (row_ok<L>(z, i) ? node_of<L>(z, i) : 0)];
+    }
+    if (hn >= 3) {
 #pragma unroll
-        for (int i = 0; i < L::R; ++i) lh[i] = A.hx[z.off + (row_ok<L>(z, i) ? node_of<L>(z, i) : 0)];
+        for (int i = 0; i < L::R; ++i) le2[i] = A.he2[z.off + (row_ok<L>(z, i) ? node_of<L>(z, i) : 0)];
     }
 }
 
 // From the loaded history and the current X0 (xc): the predicted increment
-// 2 e1 - e2 (e1 alone with one step, 0 with none; e1 = X0 - hx, where hx is
-// X0 rounded to FP32, ~2^-24 |X0| absolute, far below the increment) of the
-// lane's rows into g, then the history moves on (hx = X0, he = e1).  The
-// caller has waited for the loads (vmcnt), so no store overtakes a load of
-// its address.
+// of the lane's rows into g -- 3 e1 - 3 e2 + e3 with three steps of history
+// (the increments extrapolated quadratically), 2 e1 - e2 with two, e1 with
+// one, 0 with none (e1 = X0 - hx, where hx is X0 rounded to FP32, ~2^-24
+// |X0| absolute, far below the increment) -- then the history moves on
+// (hx = X0, he = e1, he2 = the previous he).  The caller has waited for the
+// loads (vmcnt), so no store overtakes a load of its address.
 template <class L, typename TG>
 __device__ __forceinline__ void history_step(const MicroArgs& A, const Lane& z, int hn, const double (&xc)[L::R],
-                                             const float (&lh)[L::R], const float (&le)[L::R], TG (&g)[L::R]) {
+                                             const float (&lh)[L::R], const float (&le)[L::R],
+                                             const float (&le2)[L::R], TG (&g)[L::R]) {
 #pragma unroll
     for (int i = 0; i < L::R; ++i) {
         const float e1 = hn >= 1 ? (float)(xc[i] - (double)lh[i]) : 0.0f;
-        const float pr = hn >= 2 ? 2.0f * e1 - le[i] : e1;
+        const float pr = hn >= 3 ? 3.0f * (e1 - le[i]) + le2[i] : hn >= 2 ? 2.0f * e1 - le[i] : e1;
         g[i] = row_ok<L>(z, i) ? (TG)pr : TG(0);
         if (row_ok<L>(z, i)) {
             const int j = node_of<L>(z, i);
             A.hx[z.off + j] = (float)xc[i];
             A.he[z.off + j] = e1;
+            A.he2[z.off + j] = le[i];
         }
     }
 }
@@ -716,7 +722,7 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
     const bool use_mw = A.rhs_vec == nullptr && A.Mw != nullptr && !A.zero_init;
     const int hn = hslot != nullptr ? hist : -1;
     double cm[L::R];
-    float lh[L::R], le[L::R];
+    float lh[L::R], le[L::R], le2[L::R];
     // the rows' loads: no arithmetic and no uniform branch inside a row's
     // branch, so that every row's loads are in flight before the first wait
     // (M w, or w, in wv)
@@ -727,6 +733,7 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
         wv[i] = 0.0;
         lh[i] = 0.0f;
         le[i] = 0.0f;
+        le2[i] = 0.0f;
     }
     if (!A.zero_init) {
         const double* ws = use_mw ? A.Mw : A.w;
@@ -746,6 +753,11 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
             for (int i = 0; i < L::R; ++i)
                 if (row_ok<L>(z, i)) le[i] = A.he[z.off + node_of<L>(z, i)];
         }
+        if (hn >= 3) {
+#pragma unroll
+            for (int i = 0; i < L::R; ++i)
+                if (row_ok<L>(z, i)) le2[i] = A.he2[z.off + node_of<L>(z, i)];
+        }
     }
     const double cmf = use_mw ? cf * A.inv_dt : 0.0, cw = use_mw ? 0.0 : cf;
 #pragma unroll
@@ -759,7 +771,7 @@ __device__ __forceinline__ void pack_start(const MicroArgs& A, const Lane& z, do
     __syncthreads();
     if (hn >= 0) {
         float g[L::R];
-        history_step<L>(A, z, hn, x, lh, le, g);
+        history_step<L>(A, z, hn, x, lh, le, le2, g);
 #pragma unroll
         for (int i = 0; i < L::R; ++i) hslot[i * NTP + threadIdx.x] = g[i];
     }
@@ -1134,20 +1146,20 @@ __device__ void pack_fp64(const MicroArgs& A, const int32_t* meta, int cnt, doub
         }
     }
     // Extrapolated start (time-step form with a history): x0 = X0 + the
-    // predicted increment (2 e1 - e2, or e1), r -= S (that increment) with
+    // predicted increment (3 e1 - 3 e2 + e3, 2 e1 - e2 or e1), r -= S (that increment) with
     // the resident FP64 stencil, kept only where it lowers ||r||.  The
     // history is read here rather than with X0 (the LDS has no room to hold
     // the prediction until the stencil is resident) and moves on once its
     // loads have returned.
     const int hn = hist;
     if (hn >= 0) {
-        float lh[L::R], le[L::R];
-        history_load<L>(A, z, hn, lh, le);
+        float lh[L::R], le[L::R], le2[L::R];
+        history_load<L>(A, z, hn, lh, le, le2);
         double xc[L::R], g[L::R];
 #pragma unroll
         for (int i = 0; i < L::R; ++i) xc[i] = xs[i * NTP + threadIdx.x];
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        history_step<L>(A, z, hn, xc, lh, le, g);
+        history_step<L>(A, z, hn, xc, lh, le, le2, g);
         if (hn >= 1) {
             __syncthreads();     // the reads of x0 in the grid are done
             strip_store<L>(xg, z, g);

@@ -176,12 +176,14 @@ struct MicroArgs {
     int32_t* fb_list;
     // extrapolated start of the forward time-step solves (packed kernels on
     // the assembled operator, all null elsewhere): hx holds the X0 of the
-    // previous step and he the increment before it (FP32, ragged like X0),
-    // *hn the number of steps that history covers (0, 1, 2).  The solve
-    // starts from X0 + 2 e1 - e2 (e1 = X0 - hx, e2 = he), or X0 + e1 when one
-    // step is known (the refinement form: its first inner solve)
+    // previous step, he the increment before it and he2 the one before that
+    // (FP32, ragged like X0), *hn the number of steps that history covers
+    // (0 .. 3).  The solve starts from X0 + 3 e1 - 3 e2 + e3 (e1 = X0 - hx,
+    // e2 = he, e3 = he2), X0 + 2 e1 - e2 with two steps known, X0 + e1 with
+    // one (the refinement form: its first inner solve)
     float* hx;
     float* he;
+    float* he2;
     const int32_t* hn;
     // separable mass of the analytic deformation family (packed kernels on
     // the assembled operator, time-step form; null: none).  For level N the
