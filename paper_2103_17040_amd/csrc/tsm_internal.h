@@ -40,12 +40,13 @@ __host__ __device__ inline int bnd_node(int N, int k) {
     return (k - 2 * NP - N + 2) * NP + N;
 }
 
-// Tightest relative tolerance asked of an FP32 inner solve (2^-18, 32 FP32
+// Tightest relative tolerance asked of an FP32 inner solve (2^-17, 64 FP32
 // ulps).  The correction of an FP32 solve is accurate to about cond(S)
 // FP32 ulps whatever its own residual says, so iterating further only
-// costs iterations (measured on 64x64 instances: 2^-20 -> 2^-18 saves two
-// of 24 iterations per step and no refinement sweep is added).
-constexpr double kInnerFloor = 3.814697265625e-06;
+// costs iterations (measured on 64x64 instances: 2^-20 -> 2^-18 saved two
+// of 24 iterations per step, and with the extrapolated start 2^-18 ->
+// 2^-17 saves 0.4 of 12.1, no refinement sweep added either time).
+constexpr double kInnerFloor = 7.62939453125e-06;
 
 // Squared relative tolerance of one FP32 inner solve in the refinement: half
 // of what the outer test still needs (tol2 = rtol^2 ||b||^2 against the
